@@ -1,0 +1,196 @@
+/*
+ * unimgs.h -- C ABI of the MI355X (gfx950) mixed Gaussian/triangle rasterizer.
+ *
+ * The library renders 3D Gaussian splats and anti-aliased triangles in one
+ * rasterization pass (the paper's Section 3.2, Eq. 1-11) after moving bound
+ * Gaussians with a deformed proxy mesh (Section 3.3.2, Eq. 12-13).  Every
+ * step runs in hand-written HIP kernels on the stream given to umgs_create.
+ *
+ * Conventions shared by all entry points
+ *   - Arrays marked [device] are device pointers, FP32 (or int32) row-major
+ *     and contiguous unless stated; [host] marks host memory.  The library
+ *     never frees caller memory and never keeps caller pointers after a call
+ *     returns.  Internal work buffers belong to the context.
+ *   - Calls are asynchronous on the context's stream unless stated.  One
+ *     context per stream; a context is not thread-safe.
+ *   - Every call validates its arguments before enqueueing anything; on any
+ *     error nothing has been enqueued by that call and umgs_last_error()
+ *     describes it.  No C++ exception crosses the ABI.
+ *   - Camera: world->camera rotation R (row-major 3x3) and translation t,
+ *     OpenCV axes (x right, y down, z forward).  Pixel (i, j) covers
+ *     [i, i+1) x [j, j+1); a point projects to u = fx x/z + cx,
+ *     v = fy y/z + cy.
+ *   - Gaussians: means (N,3); scales (N,3) linear; quats (N,4) (w,x,y,z),
+ *     normalised inside; opacity (N,) in (0,1); sh (N,(deg+1)^2,3) real SH
+ *     coefficients (degree-0 colour = sh0 * 0.28209479 + 0.5, clamped >= 0);
+ *     cov3d (N,6) optional packed world covariance (xx,xy,xz,yy,yz,zz).
+ *   - Triangles: tri_xyz (T,3,3) world vertices, tri_rgb (T,3,3) per-vertex
+ *     colour, tri_alpha (T,) opacity.  Global fragment ids: Gaussians
+ *     0..N-1, triangles N..N+T-1; equal depth keys order by ascending id.
+ *   - Per-view outputs are packed view after view: image (3,H,W) per view
+ *     (planar RGB), per-pixel arrays (H,W) per view.
+ */
+#ifndef UNIMGS_H
+#define UNIMGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  UMGS_OK = 0,
+  UMGS_ERR_INVALID_ARG = -1,  /* bad pointer, size, option or shape        */
+  UMGS_ERR_CAPACITY = -2,     /* a size exceeds what the library supports   */
+  UMGS_ERR_HIP = -3,          /* a HIP runtime call or launch failed        */
+  UMGS_ERR_STATE = -4,        /* call out of order (e.g. blend before sort) */
+  UMGS_ERR_UNSUPPORTED = -5
+} umgs_status;
+
+typedef struct umgs_ctx umgs_ctx;
+
+typedef struct {
+  float R[9];       /* world -> camera rotation, row-major                 */
+  float t[3];       /* world -> camera translation                         */
+  float fx, fy;     /* focal lengths in pixels                             */
+  float cx, cy;     /* principal point in pixels                           */
+  int32_t width, height;  /* 1 .. 16384                                    */
+} umgs_camera;
+
+typedef struct {
+  int32_t tile_w, tile_h;  /* 8x8, 16x16 or 32x8                               */
+  int32_t frag_batch;      /* fragments staged in LDS per batch: 32,64,128,256 */
+  int32_t sh_degree;       /* 0..3                                             */
+  int32_t k_bind;          /* bindings per Gaussian: 1 (centre) or 8 (corners) */
+  int32_t mode;            /* compositing rule, UMGS_MODE_*                    */
+  float bg[3];             /* opaque background colour                         */
+} umgs_options;
+
+/* Compositing rules (Section 3.2, Fig. 3).  UMGS_MODE_UNIMGS is the paper's
+ * method; the others are its ablations. */
+enum {
+  UMGS_MODE_UNIMGS = 0,      /* depth-adjacent triangles form one entity (Fig. 3d)   */
+  UMGS_MODE_DIRECT = 1,      /* triangles alpha-blended like Gaussians (Fig. 3a)     */
+  UMGS_MODE_ONE_ENTITY = 2,  /* all triangles of a pixel one entity (Fig. 3b/c)      */
+  UMGS_MODE_LITERAL_T = 3    /* entity with pixel T updated per Eq. 6 with Eq. 8's O */
+};
+
+/* Default options: 16x16 tiles, batch 128, SH degree 0, K = 8, UniMGS mode,
+ * black background. */
+void umgs_default_options(umgs_options *opt);
+
+/* Create a context bound to a HIP stream (hipStream_t passed as void*, NULL =
+ * the null stream).  *out receives the context.  Errors: INVALID_ARG for a
+ * NULL out/opt or options outside the ranges above; HIP if the device cannot
+ * be queried. */
+umgs_status umgs_create(umgs_ctx **out, const umgs_options *opt, void *hip_stream);
+void umgs_destroy(umgs_ctx *ctx);
+/* Text of the last error on this context ("" if none).  Owned by ctx. */
+const char *umgs_last_error(const umgs_ctx *ctx);
+/* Replace the options; takes effect at the next umgs_project. */
+umgs_status umgs_set_options(umgs_ctx *ctx, const umgs_options *opt);
+
+/* ---- deformation transfer (Section 3.3.2, Eq. 12-13) ------------------- */
+
+/* Upload the rest proxy mesh (setup, once): V_rest [host] (nV,3), faces
+ * [host] (nF,3) int32, outward oriented.  Builds the vertex->face adjacency.
+ * Synchronous.  Errors: INVALID_ARG (NULL, nV < 3, nF < 1, face index out of
+ * range, a vertex without faces). */
+umgs_status umgs_set_proxy(umgs_ctx *ctx, int32_t nV, const float *V_rest, int32_t nF,
+                           const int32_t *faces);
+
+/* Move N bound Gaussians with the deformed proxy V_def [device] (nV,3).
+ * Per vertex: offset, cotangent-weighted 1-ring deformation gradient (with a
+ * normal pair), polar decomposition and rotation log; per Gaussian: Eq. 12
+ * over its K = k_bind bindings bind_face [device] (N,K) int32 and bind_bary
+ * [device] (N,K,2) = (u,v) with w = 1-u-v, then Eq. 13.
+ * Outputs [device]: means_out (N,3), quats_out (N,4) = quat(R') * q,
+ * cov3d_out (N,6) = A Sigma A^T packed, xform_out (N,9) = A = R'S' row-major;
+ * vertex_out (nV,12) = (Delta 3, log R 3, S xx,xy,xz,yy,yz,zz) may be NULL.
+ * means_out follows a fixed FP32 operation order (the deformed mean orders
+ * the Gaussians): Delta = V'-V; w = (1-u)-v; Delta_i = (u Da + v Db) + w Dc;
+ * s = ((Delta_1 + Delta_2) + ...) + Delta_K; mu' = mu + s * (1/K).
+ * Errors: STATE without umgs_set_proxy; INVALID_ARG for NULL inputs or
+ * N < 0.  Face indices are not range-checked on the device (caller's
+ * responsibility: 0 <= face < nF). */
+umgs_status umgs_bind_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
+                               const int32_t *bind_face, const float *bind_bary,
+                               const float *means, const float *quats, const float *scales,
+                               float *means_out, float *quats_out, float *cov3d_out,
+                               float *xform_out, float *vertex_out);
+
+/* ---- forward rasterization (Section 3.2) ---------------------------------- */
+
+/* Project N Gaussians (EWA splatting: 2D covariance J W Sigma W^T J^T + 0.3 I,
+ * conic, SH colour; the inputs to Eq. 1-2) and set up T triangles (4x
+ * rotated-grid sub-sample coverage with 1/256-px fixed-point vertices: the
+ * o_i^j of Eq. 4/7) for V views cams [host] (V entries).  cov3d may be NULL,
+ * then scales and quats are used (else they may be NULL).  N or T may be 0
+ * (their pointers may then be NULL).  Records stay in the context until the
+ * next umgs_project.  Errors: INVALID_ARG (NULL where required, sizes < 0,
+ * V < 1, bad camera size); CAPACITY if V*(N+T) >= 2^31. */
+umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int32_t N,
+                         const float *means, const float *cov3d, const float *scales,
+                         const float *quats, const float *opacity, const float *sh,
+                         int32_t T, const float *tri_xyz, const float *tri_rgb,
+                         const float *tri_alpha);
+
+/* Bin: duplicate every projected primitive into each screen tile its support
+ * touches, with key (global tile << 32 | depth bits) and value = record id.
+ * Synchronizes the stream once to size the key buffers.  Errors: STATE before
+ * umgs_project; CAPACITY if the duplicate count reaches 2^32 - 1. */
+umgs_status umgs_bin(umgs_ctx *ctx);
+
+/* Sort the duplicates by key (device LSD radix sort; equal keys keep the
+ * ascending-id emission order) and find every tile's [start, end) range.
+ * This is the single mixed depth sort of Section 3.2.  Errors: STATE. */
+umgs_status umgs_sort(umgs_ctx *ctx);
+
+/* Blend every tile front to back (Eq. 1-2 for Gaussians, Eq. 7-9 for
+ * triangle entities, Eq. 10-11 background) with early termination.
+ * Outputs [device], packed per view: image (3,H,W) FP32, T_final (H,W),
+ * n_contrib (H,W) int32 = 1 + position in the tile's sorted list of the last
+ * blended fragment (0 if none), T_entity_in (H,W) = transmittance in front of
+ * the last blended unit -- a Gaussian, or a whole triangle entity (a single
+ * triangle in UMGS_MODE_DIRECT) -- (1 if none); the backward pass needs it
+ * when that unit is opaque.  T_final, n_contrib and
+ * T_entity_in may be NULL.  Errors: STATE before umgs_sort. */
+umgs_status umgs_blend(umgs_ctx *ctx, float *image, float *T_final, int32_t *n_contrib,
+                       float *T_entity_in);
+
+/* Sizes of the current frame: n_dup (duplicates), n_tiles (all views), and
+ * the record count V*(N+T).  Any pointer may be NULL.  Synchronous. */
+umgs_status umgs_query(umgs_ctx *ctx, int64_t *n_dup, int64_t *n_tiles, int64_t *n_records);
+
+/* Copy internal per-frame state into caller memory [device] (for tests):
+ *   UMGS_STATE_KEYS    n_records uint32 depth-key bits (0xFFFFFFFF = culled)
+ *   UMGS_STATE_SORTED_KEYS  n_dup uint64 sorted keys
+ *   UMGS_STATE_SORTED_VALS  n_dup uint32 record ids in sorted order
+ *   UMGS_STATE_RANGES  n_tiles x 2 uint32 [start, end) per global tile
+ *   UMGS_STATE_TRI_FIXED  V*T x 6 int32 snapped vertices (X0,X1,X2,Y0,Y1,Y2)
+ *                         after orientation normalisation (0 when culled)
+ * cap_bytes must hold the whole array.  Errors: INVALID_ARG, STATE. */
+enum { UMGS_STATE_KEYS = 0, UMGS_STATE_SORTED_KEYS = 1, UMGS_STATE_SORTED_VALS = 2,
+       UMGS_STATE_RANGES = 3, UMGS_STATE_TRI_FIXED = 4 };
+umgs_status umgs_copy_state(umgs_ctx *ctx, int32_t which, void *dst, int64_t cap_bytes);
+
+/* ---- kernel timing -------------------------------------------------------- */
+
+/* Per-kernel timing with HIP events recorded on the context stream around
+ * each launch (UMGS_K_* ids).  umgs_set_profiling enables or disables it and
+ * clears the totals; umgs_profile_read synchronizes the stream and returns
+ * the number of timed launches and their total duration.  Keep profiling off
+ * while a stream is being captured into a graph. */
+enum { UMGS_K_VERTEX_FRAMES = 0, UMGS_K_TRANSFER = 1, UMGS_K_PROJECT = 2, UMGS_K_TRIANGLES = 3,
+       UMGS_K_SCAN = 4, UMGS_K_EMIT = 5, UMGS_K_SORT_UPSWEEP = 6, UMGS_K_SORT_SCAN = 7,
+       UMGS_K_SORT_DOWNSWEEP = 8, UMGS_K_RANGES = 9, UMGS_K_BLEND = 10, UMGS_K_BLEND_BWD = 11,
+       UMGS_K_PROJECT_BWD = 12, UMGS_K_COUNT = 13 };
+umgs_status umgs_set_profiling(umgs_ctx *ctx, int32_t enable);
+umgs_status umgs_profile_read(umgs_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UNIMGS_H */

@@ -27,6 +27,10 @@ tiles), sorts them by (depth key, global id) and blends front to back:
   blending a triangle that leaves T < 1e-4.
 * Background (Eq. 10-11 with an opaque background): C += T C_bg.
 
+Besides C and T the oracle reports, per pixel, the transmittance in front of
+the last blended unit (a Gaussian, or a whole triangle entity), which the
+backward pass needs when that unit is opaque.
+
 Global ids: Gaussians 0..N-1, triangles N..N+T-1.  Equal depth keys are
 ordered by ascending id.
 
@@ -135,7 +139,8 @@ def project_gaussians(cam, means, opacity, sh, sh_degree, scales=None, quats=Non
     cov3d, if given, is the packed (xx, xy, xz, yy, yz, zz) world covariance
     (e.g. after deformation transfer); otherwise Sigma = R(q) diag(s^2) R(q)^T.
     """
-    means = np.asarray(means, F32)
+    means64 = np.asarray(means, np.float64)      # continuous path (FP64 inputs allowed)
+    means = np.asarray(means, F32)                # the depth key is pinned in FP32
     n = means.shape[0]
     R32, t32, fx32, fy32, cx32, cy32 = _cam32(cam)
     z32 = view_row_f32(R32, t32, means, 2)
@@ -145,7 +150,7 @@ def project_gaussians(cam, means, opacity, sh, sh_degree, scales=None, quats=Non
     tv = t32.astype(np.float64)
     fx, fy = float(fx32), float(fy32)
     cx, cy = float(cx32), float(cy32)
-    p = means.astype(np.float64) @ W.T + tv
+    p = means64 @ W.T + tv
     x, y, z = p[:, 0], p[:, 1], p[:, 2]
     zs = np.where(valid, z, 1.0)
     Sigma = cov3d_from_packed(cov3d) if cov3d is not None else cov3d_from_scale_rot(scales, quats)
@@ -172,7 +177,7 @@ def project_gaussians(cam, means, opacity, sh, sh_degree, scales=None, quats=Non
     mean2d = np.stack([fx * x / zs + cx, fy * y / zs + cy], -1)
 
     cam_c = -(W.T @ tv)
-    d = means.astype(np.float64) - cam_c[None, :]
+    d = means64 - cam_c[None, :]
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     rgb = _sh.colour(np.asarray(sh), d, sh_degree)
     return GaussProj(valid=valid, key=z32, mean2d=mean2d, cov2d=np.stack([a, b, c], -1),
@@ -302,7 +307,8 @@ class PixelResult:
     T: float                      # final transmittance (before background)
     n_blended: int                # fragments blended
     last_id: int                  # global id of the last blended fragment, -1 if none
-    T_entity_in: float            # T_in of the last opened triangle entity (1 if none)
+    T_entity_in: float            # T before the last blended unit (a Gaussian, or a whole
+                                  # triangle entity; a triangle in direct mode), 1 if none
     order: List[int]              # global ids of the blended fragments, in order
     contributors: List[int]       # all contributors in (key, id) order
     margin: float                 # smallest relative decision margin met
@@ -422,6 +428,7 @@ class Frame:
                     stop = not stop
                 if stop:
                     break
+                T_ent = T
                 C += T * a * self.g.rgb[gid]
                 T = test_T
                 blended.append(gid)
@@ -433,18 +440,19 @@ class Frame:
                 al = self.t.alpha[ti]
                 col = tri_col[gid]
                 if mode == MODE_DIRECT:
-                    test_T = T * (1.0 - al)
-                    rel = abs(test_T - T_STOP) / T_STOP
+                    # like a Gaussian, but blended before the stop test (an
+                    # opaque triangle must still show its colour)
+                    T_ent = T
+                    C += T * al * col
+                    T = T * (1.0 - al)
+                    blended.append(gid)
+                    trace.append(T)
+                    rel = abs(T - T_STOP) / T_STOP
                     margin = min(margin, rel)
                     if rel < margin_rel:
                         ambiguous.append(("s", gid))
-                    stop = (test_T < T_STOP) != (("s", gid) in flips)
-                    if stop:
+                    if (T < T_STOP) != (("s", gid) in flips):
                         break
-                    C += T * al * col
-                    T = test_T
-                    blended.append(gid)
-                    trace.append(T)
                     continue
                 o = tri_cov[gid].astype(np.float64)
                 if not in_entity:

@@ -1,0 +1,438 @@
+// Host side of the C ABI: contexts, argument validation, work buffers and
+// the entry points declared in unimgs.h.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <new>
+
+#include "internal.h"
+
+namespace umgs {
+
+umgs_status fail(Ctx *c, umgs_status s, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return s;
+}
+
+umgs_status hip_check(Ctx *c, hipError_t e, const char *what) {
+  if (e == hipSuccess) return UMGS_OK;
+  return fail(c, UMGS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+umgs_status ensure(Ctx *c, DevBuf &b, size_t bytes, const char *what) {
+  if (bytes <= b.cap) return UMGS_OK;
+  if (b.p) {
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_check(c, e, "stream sync before reallocation");
+    (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+  }
+  size_t cap = bytes + bytes / 8 + 256;
+  hipError_t e = hipMalloc(&b.p, cap);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(c, UMGS_ERR_CAPACITY, "allocation of %zu bytes for %s failed: %s", cap, what,
+                hipGetErrorString(e));
+  }
+  b.cap = cap;
+  return UMGS_OK;
+}
+
+static void free_buf(DevBuf &b) {
+  if (b.p) (void)hipFree(b.p);
+  b.p = nullptr;
+  b.cap = 0;
+}
+
+static bool valid_options(const umgs_options *o, std::string &why) {
+  const bool tile_ok = (o->tile_w == 16 && o->tile_h == 16) || (o->tile_w == 8 && o->tile_h == 8) ||
+                       (o->tile_w == 32 && o->tile_h == 8);
+  if (!tile_ok) { why = "tile shape must be 8x8, 16x16 or 32x8"; return false; }
+  const int b = o->frag_batch;
+  if (!(b == 32 || b == 64 || b == 128 || b == 256)) { why = "frag_batch must be 32, 64, 128 or 256"; return false; }
+  if (o->sh_degree < 0 || o->sh_degree > 3) { why = "sh_degree must be 0..3"; return false; }
+  if (!(o->k_bind == 1 || o->k_bind == 8)) { why = "k_bind must be 1 or 8"; return false; }
+  if (o->mode < UMGS_MODE_UNIMGS || o->mode > UMGS_MODE_LITERAL_T) { why = "unknown mode"; return false; }
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(o->bg[k])) { why = "background must be finite"; return false; }
+  return true;
+}
+
+static hipEvent_t get_event(Ctx *c) {
+  if (!c->prof.pool.empty()) {
+    hipEvent_t e = c->prof.pool.back();
+    c->prof.pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+ScopedTimer::ScopedTimer(Ctx *ctx, int kid) : c(ctx), id(kid) {
+  if (!c->prof.on) return;
+  a = get_event(c);
+  b = get_event(c);
+  if (a && b) (void)hipEventRecord(a, c->stream);
+}
+
+ScopedTimer::~ScopedTimer() {
+  if (!c->prof.on || !a || !b) return;
+  (void)hipEventRecord(b, c->stream);
+  c->prof.pending.push_back({id, a, b});
+}
+
+static umgs_status drain_profile(Ctx *c) {
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "profiler sync");
+  for (auto &p : c->prof.pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      c->prof.ms[p.id] += ms;
+      c->prof.n[p.id] += 1;
+    }
+    c->prof.pool.push_back(p.a);
+    c->prof.pool.push_back(p.b);
+  }
+  c->prof.pending.clear();
+  return UMGS_OK;
+}
+
+hipError_t launch_exclusive_scan_u64(Ctx *c, uint64_t *data, int64_t n, uint64_t *tmp);
+hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v);
+
+}  // namespace umgs
+
+using namespace umgs;
+
+extern "C" {
+
+void umgs_default_options(umgs_options *opt) {
+  if (!opt) return;
+  opt->tile_w = 16;
+  opt->tile_h = 16;
+  opt->frag_batch = 128;
+  opt->sh_degree = 0;
+  opt->k_bind = 8;
+  opt->mode = UMGS_MODE_UNIMGS;
+  opt->bg[0] = opt->bg[1] = opt->bg[2] = 0.0f;
+}
+
+umgs_status umgs_create(umgs_ctx **out, const umgs_options *opt, void *hip_stream) {
+  if (!out || !opt) return UMGS_ERR_INVALID_ARG;
+  *out = nullptr;
+  std::string why;
+  if (!valid_options(opt, why)) return UMGS_ERR_INVALID_ARG;
+  umgs_ctx *h = new (std::nothrow) umgs_ctx();
+  if (!h) return UMGS_ERR_CAPACITY;
+  Ctx *c = &h->c;
+  c->opt = *opt;
+  c->stream = (hipStream_t)hip_stream;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete h;
+    return UMGS_ERR_HIP;
+  }
+  int ncu = 0;
+  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess)
+    c->num_cu = ncu;
+  *out = h;
+  return UMGS_OK;
+}
+
+void umgs_destroy(umgs_ctx *ctx) {
+  if (!ctx) return;
+  Ctx *c = &ctx->c;
+  (void)hipStreamSynchronize(c->stream);
+  DevBuf *bufs[] = {&c->V_rest, &c->faces, &c->vf_ptr, &c->vf_idx, &c->vtab, &c->d_views,
+                    &c->keys, &c->rects, &c->counts, &c->grec, &c->trec, &c->scan_tmp,
+                    &c->k0, &c->k1, &c->v0, &c->v1, &c->hist, &c->ranges};
+  for (DevBuf *b : bufs) free_buf(*b);
+  for (auto &p : c->prof.pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+  if (c->host_pinned.p) (void)hipHostFree(c->host_pinned.p);
+  delete ctx;
+}
+
+const char *umgs_last_error(const umgs_ctx *ctx) { return ctx ? ctx->c.err.c_str() : ""; }
+
+umgs_status umgs_set_options(umgs_ctx *ctx, const umgs_options *opt) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (!opt) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_set_options: NULL options");
+  std::string why;
+  if (!valid_options(opt, why)) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_set_options: %s", why.c_str());
+  c->opt = *opt;
+  return UMGS_OK;
+}
+
+umgs_status umgs_set_proxy(umgs_ctx *ctx, int32_t nV, const float *V_rest, int32_t nF,
+                           const int32_t *faces) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (!V_rest || !faces) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_set_proxy: NULL array");
+  if (nV < 3 || nF < 1) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_set_proxy: nV=%d nF=%d", nV, nF);
+  std::vector<int32_t> ptr(nV + 1, 0);
+  for (int64_t k = 0; k < 3LL * nF; ++k) {
+    const int32_t v = faces[k];
+    if (v < 0 || v >= nV)
+      return fail(c, UMGS_ERR_INVALID_ARG, "umgs_set_proxy: face %lld references vertex %d",
+                  (long long)(k / 3), v);
+    ptr[v + 1]++;
+  }
+  for (int f = 0; f < nF; ++f)
+    if (faces[3 * f] == faces[3 * f + 1] || faces[3 * f] == faces[3 * f + 2] ||
+        faces[3 * f + 1] == faces[3 * f + 2])
+      return fail(c, UMGS_ERR_INVALID_ARG, "umgs_set_proxy: face %d is degenerate", f);
+  for (int v = 0; v < nV; ++v) {
+    if (ptr[v + 1] == 0) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_set_proxy: vertex %d has no face", v);
+    ptr[v + 1] += ptr[v];
+  }
+  std::vector<int32_t> idx(ptr[nV]);
+  std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+  for (int f = 0; f < nF; ++f)
+    for (int k = 0; k < 3; ++k) idx[fill[faces[3 * f + k]]++] = f;
+  umgs_status s;
+  if ((s = ensure(c, c->V_rest, sizeof(float) * 3 * nV, "proxy vertices")) ||
+      (s = ensure(c, c->faces, sizeof(int32_t) * 3 * nF, "proxy faces")) ||
+      (s = ensure(c, c->vf_ptr, sizeof(int32_t) * (nV + 1), "vertex-face offsets")) ||
+      (s = ensure(c, c->vf_idx, sizeof(int32_t) * idx.size(), "vertex-face lists")) ||
+      (s = ensure(c, c->vtab, sizeof(float) * 12 * nV, "vertex transforms")))
+    return s;
+  hipError_t e;
+  if ((e = hipMemcpy(c->V_rest.p, V_rest, sizeof(float) * 3 * nV, hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(c->faces.p, faces, sizeof(int32_t) * 3 * nF, hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(c->vf_ptr.p, ptr.data(), sizeof(int32_t) * (nV + 1), hipMemcpyHostToDevice)) ||
+      (e = hipMemcpy(c->vf_idx.p, idx.data(), sizeof(int32_t) * idx.size(), hipMemcpyHostToDevice)))
+    return hip_check(c, e, "umgs_set_proxy upload");
+  c->nV = nV;
+  c->nF = nF;
+  return UMGS_OK;
+}
+
+umgs_status umgs_bind_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
+                               const int32_t *bind_face, const float *bind_bary,
+                               const float *means, const float *quats, const float *scales,
+                               float *means_out, float *quats_out, float *cov3d_out,
+                               float *xform_out, float *vertex_out) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->nV == 0) return fail(c, UMGS_ERR_STATE, "umgs_bind_transfer: no proxy (call umgs_set_proxy)");
+  if (N < 0) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_bind_transfer: N=%d", N);
+  if (!V_def) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_bind_transfer: NULL V_def");
+  if (N > 0 && (!bind_face || !bind_bary || !means || !quats || !scales || !means_out ||
+                !cov3d_out))
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_bind_transfer: NULL Gaussian array");
+  return hip_check(c, launch_transfer(c, V_def, N, bind_face, bind_bary, means, quats, scales,
+                                      means_out, quats_out, cov3d_out, xform_out, vertex_out),
+                   "transfer launch");
+}
+
+umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int32_t N,
+                         const float *means, const float *cov3d, const float *scales,
+                         const float *quats, const float *opacity, const float *sh,
+                         int32_t T, const float *tri_xyz, const float *tri_rgb,
+                         const float *tri_alpha) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (V < 1 || !cams) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_project: V=%d cams=%p", V, (const void *)cams);
+  if (N < 0 || T < 0) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_project: N=%d T=%d", N, T);
+  if (N > 0 && (!means || !opacity || !sh || (!cov3d && (!scales || !quats))))
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_project: NULL Gaussian array");
+  if (T > 0 && (!tri_xyz || !tri_rgb || !tri_alpha))
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_project: NULL triangle array");
+  if ((int64_t)V * ((int64_t)N + T) >= (1LL << 31))
+    return fail(c, UMGS_ERR_CAPACITY, "umgs_project: V*(N+T) = %lld records", (long long)V * (N + T));
+  const umgs_options &o = c->opt;
+  std::vector<ViewParams> vps(V);
+  int64_t tiles = 0, pix = 0;
+  for (int v = 0; v < V; ++v) {
+    const umgs_camera &cm = cams[v];
+    if (cm.width < 1 || cm.height < 1 || cm.width > 16384 || cm.height > 16384)
+      return fail(c, UMGS_ERR_INVALID_ARG, "umgs_project: view %d size %dx%d", v, cm.width, cm.height);
+    if (!(cm.fx > 0) || !(cm.fy > 0) || !std::isfinite(cm.cx) || !std::isfinite(cm.cy))
+      return fail(c, UMGS_ERR_INVALID_ARG, "umgs_project: view %d intrinsics", v);
+    ViewParams &p = vps[v];
+    memcpy(p.R, cm.R, sizeof p.R);
+    memcpy(p.t, cm.t, sizeof p.t);
+    p.fx = cm.fx; p.fy = cm.fy; p.cx = cm.cx; p.cy = cm.cy;
+    p.tanx = (float)cm.width / (2.0f * cm.fx);
+    p.tany = (float)cm.height / (2.0f * cm.fy);
+    p.W = cm.width; p.H = cm.height;
+    p.ntx = (cm.width + o.tile_w - 1) / o.tile_w;
+    p.nty = (cm.height + o.tile_h - 1) / o.tile_h;
+    p.tile_base = (uint32_t)tiles;
+    p.pad0 = 0;
+    p.pix_base = pix;
+    tiles += (int64_t)p.ntx * p.nty;
+    pix += (int64_t)cm.width * cm.height;
+  }
+  if (tiles >= (1LL << 31)) return fail(c, UMGS_ERR_CAPACITY, "umgs_project: %lld tiles", (long long)tiles);
+  const int64_t nrec = (int64_t)V * (N + T);
+  umgs_status s;
+  if ((s = ensure(c, c->d_views, sizeof(ViewParams) * V, "view table")) ||
+      (s = ensure(c, c->keys, sizeof(uint32_t) * std::max<int64_t>(nrec, 1), "depth keys")) ||
+      (s = ensure(c, c->rects, sizeof(uint2) * std::max<int64_t>(nrec, 1), "tile rects")) ||
+      (s = ensure(c, c->counts, sizeof(uint64_t) * (nrec + 1), "tile counts")) ||
+      (s = ensure(c, c->grec, sizeof(GaussRec) * std::max<int64_t>((int64_t)V * N, 1), "Gaussian records")) ||
+      (s = ensure(c, c->trec, sizeof(TriRec) * std::max<int64_t>((int64_t)V * T, 1), "triangle records")) ||
+      (s = ensure(c, c->scan_tmp, scan_tmp_bytes(std::max<int64_t>(nrec + 1, 1 << 20)), "scan scratch")) ||
+      (s = ensure(c, c->ranges, sizeof(uint2) * tiles, "tile ranges")))
+    return s;
+  c->views = vps;
+  c->V = V; c->N = N; c->T = T;
+  c->tile_w = o.tile_w; c->tile_h = o.tile_h; c->frag_batch = o.frag_batch;
+  c->mode = o.mode; c->sh_degree = o.sh_degree;
+  c->bg[0] = o.bg[0]; c->bg[1] = o.bg[1]; c->bg[2] = o.bg[2];
+  c->n_records = nrec;
+  c->n_tiles = tiles;
+  c->n_pixels = pix;
+  c->n_dup = 0;
+  int bits = 1;
+  while (bits < 31 && (1LL << bits) < tiles) ++bits;
+  c->tile_bits = bits;
+  c->stage = 0;
+  hipError_t e = hipMemcpyAsync(c->d_views.p, vps.data(), sizeof(ViewParams) * V,
+                                hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "view upload");
+  // the scan's total lands in counts[nrec]
+  e = launch_fill_u32(c, (uint32_t *)((uint64_t *)c->counts.p + nrec), 2, 0u);
+  if (e != hipSuccess) return hip_check(c, e, "count reset");
+  if ((e = launch_project_gaussians(c, means, cov3d, scales, quats, opacity, sh)) != hipSuccess)
+    return hip_check(c, e, "project_gaussians launch");
+  if ((e = launch_setup_triangles(c, tri_xyz, tri_rgb, tri_alpha)) != hipSuccess)
+    return hip_check(c, e, "setup_triangles launch");
+  c->stage = 1;
+  return UMGS_OK;
+}
+
+umgs_status umgs_bin(umgs_ctx *ctx) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->stage < 1) return fail(c, UMGS_ERR_STATE, "umgs_bin: no projected frame");
+  hipError_t e = launch_exclusive_scan_u64(c, (uint64_t *)c->counts.p, c->n_records + 1,
+                                           (uint64_t *)c->scan_tmp.p);
+  if (e != hipSuccess) return hip_check(c, e, "count scan");
+  if (!c->host_pinned.p) {
+    if ((e = hipHostMalloc(&c->host_pinned.p, 256, hipHostMallocDefault)) != hipSuccess)
+      return hip_check(c, e, "pinned scratch");
+    c->host_pinned.cap = 256;
+  }
+  uint64_t *h = (uint64_t *)c->host_pinned.p;
+  if ((e = hipMemcpyAsync(h, (uint64_t *)c->counts.p + c->n_records, sizeof(uint64_t),
+                          hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+    return hip_check(c, e, "duplicate count readback");
+  const uint64_t nd = h[0];
+  if (nd >= 0xFFFF0000ull)
+    return fail(c, UMGS_ERR_CAPACITY, "umgs_bin: %llu duplicates exceed 2^32", (unsigned long long)nd);
+  umgs_status s;
+  const size_t n = std::max<uint64_t>(nd, 1);
+  if ((s = ensure(c, c->k0, 8 * n, "keys")) || (s = ensure(c, c->k1, 8 * n, "keys")) ||
+      (s = ensure(c, c->v0, 4 * n, "values")) || (s = ensure(c, c->v1, 4 * n, "values")) ||
+      (s = ensure(c, c->hist, radix_hist_bytes(n), "radix histograms")) ||
+      (s = ensure(c, c->scan_tmp, scan_tmp_bytes(std::max<int64_t>(radix_hist_bytes(n) / 4, c->n_records + 1)), "scan scratch")))
+    return s;
+  c->n_dup = nd;
+  if ((e = launch_emit_keys(c)) != hipSuccess) return hip_check(c, e, "emit_keys launch");
+  c->stage = 2;
+  return UMGS_OK;
+}
+
+umgs_status umgs_sort(umgs_ctx *ctx) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->stage < 2) return fail(c, UMGS_ERR_STATE, "umgs_sort: frame not binned");
+  hipError_t e = launch_radix_sort(c);
+  if (e != hipSuccess) return hip_check(c, e, "radix sort launch");
+  if ((e = launch_tile_ranges(c)) != hipSuccess) return hip_check(c, e, "tile ranges launch");
+  c->stage = 3;
+  return UMGS_OK;
+}
+
+umgs_status umgs_blend(umgs_ctx *ctx, float *image, float *T_final, int32_t *n_contrib,
+                       float *T_entity_in) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->stage < 3) return fail(c, UMGS_ERR_STATE, "umgs_blend: frame not sorted");
+  if (!image) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_blend: NULL image");
+  return hip_check(c, launch_blend(c, image, T_final, n_contrib, T_entity_in), "blend launch");
+}
+
+umgs_status umgs_query(umgs_ctx *ctx, int64_t *n_dup, int64_t *n_tiles, int64_t *n_records) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "umgs_query sync");
+  if (n_dup) *n_dup = (int64_t)c->n_dup;
+  if (n_tiles) *n_tiles = c->n_tiles;
+  if (n_records) *n_records = c->n_records;
+  return UMGS_OK;
+}
+
+umgs_status umgs_copy_state(umgs_ctx *ctx, int32_t which, void *dst, int64_t cap_bytes) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (!dst) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_copy_state: NULL destination");
+  const void *src = nullptr;
+  int64_t bytes = 0;
+  int need = 1;
+  switch (which) {
+    case UMGS_STATE_KEYS: src = c->keys.p; bytes = 4 * c->n_records; need = 1; break;
+    case UMGS_STATE_SORTED_KEYS: src = c->sorted_in ? c->k1.p : c->k0.p; bytes = 8 * (int64_t)c->n_dup; need = 3; break;
+    case UMGS_STATE_SORTED_VALS: src = c->sorted_in ? c->v1.p : c->v0.p; bytes = 4 * (int64_t)c->n_dup; need = 3; break;
+    case UMGS_STATE_RANGES: src = c->ranges.p; bytes = 8 * c->n_tiles; need = 3; break;
+    case UMGS_STATE_TRI_FIXED: src = c->trec.p; bytes = 24 * (int64_t)c->V * c->T; need = 1; break;
+    default: return fail(c, UMGS_ERR_INVALID_ARG, "umgs_copy_state: unknown state %d", which);
+  }
+  if (c->stage < need) return fail(c, UMGS_ERR_STATE, "umgs_copy_state: state %d not computed", which);
+  if (cap_bytes < bytes) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_copy_state: need %lld bytes", (long long)bytes);
+  if (bytes == 0) return UMGS_OK;
+  hipError_t e;
+  if (which == UMGS_STATE_TRI_FIXED) {
+    // 2D copy: the first 24 bytes of every 80-byte record
+    e = hipMemcpy2DAsync(dst, 24, src, sizeof(TriRec), 24, (size_t)c->V * c->T,
+                         hipMemcpyDeviceToDevice, c->stream);
+  } else {
+    e = hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, c->stream);
+  }
+  return hip_check(c, e, "umgs_copy_state copy");
+}
+
+umgs_status umgs_set_profiling(umgs_ctx *ctx, int32_t enable) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  umgs_status s = drain_profile(c);
+  if (s != UMGS_OK) return s;
+  for (int k = 0; k < K_COUNT; ++k) {
+    c->prof.ms[k] = 0.0;
+    c->prof.n[k] = 0;
+  }
+  c->prof.on = enable != 0;
+  return UMGS_OK;
+}
+
+umgs_status umgs_profile_read(umgs_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (kernel < 0 || kernel >= K_COUNT) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_profile_read: kernel %d", kernel);
+  umgs_status s = drain_profile(c);
+  if (s != UMGS_OK) return s;
+  if (launches) *launches = c->prof.n[kernel];
+  if (total_ms) *total_ms = c->prof.ms[kernel];
+  return UMGS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// Internal declarations of the unimgs HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/unimgs.h"
+
+namespace umgs {
+
+// 3DGS constants that the rasterizer follows (Section 3.2 builds on them).
+constexpr float kAlphaMin = 1.0f / 255.0f;   // a fragment contributes iff alpha >= this
+constexpr float kAlphaMax = 0.99f;           // alpha clamp
+constexpr float kTStop = 1e-4f;              // early termination threshold
+constexpr float kNear = 0.2f;                // near plane (view z)
+constexpr float kDilation = 0.3f;            // EWA low-pass, px^2
+constexpr float kFrustumClamp = 1.3f;        // J evaluated at x/z clamped to 1.3 tan(fov/2)
+constexpr int kSubpx = 256;                  // fixed-point vertex resolution: 1/256 px
+constexpr int kCoordLimit = 1 << 24;         // |snapped coordinate| bound (1/256 px)
+constexpr uint32_t kCulled = 0xFFFFFFFFu;    // depth key of a culled primitive
+
+// Per-view parameters in device memory.
+struct ViewParams {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  float tanx, tany;      // W/(2 fx), H/(2 fy)
+  int32_t W, H;
+  int32_t ntx, nty;      // tile grid
+  uint32_t tile_base;    // first global tile id of this view
+  int32_t pad0;
+  int64_t pix_base;      // first pixel of this view in the packed per-pixel arrays
+};
+
+// Projected Gaussian as the blend stage reads it (48 B, 16-B aligned).
+struct __align__(16) GaussRec {
+  float mx, my;          // mean in pixels
+  float qa, qb, qc;      // power = qa dx^2 + qb dx dy + qc dy^2 (= -conic/2 form)
+  float opacity;
+  float r, g, b;
+  float pad[3];
+};
+
+// Set-up triangle (80 B): snapped vertices after orientation normalisation,
+// per-vertex 1/z and colour/z for perspective-correct colour, alpha, and the
+// edge ownership bits of the tie rule.
+struct __align__(16) TriRec {
+  int32_t X[3], Y[3];
+  float iz[3];
+  float ciz[9];
+  float alpha;
+  uint32_t owned;        // bit k: edge k owns samples exactly on it
+};
+
+// Kernel ids for the event-based profiler (same order as UMGS_K_* in unimgs.h).
+enum KernelId {
+  K_VERTEX_FRAMES = 0, K_TRANSFER, K_PROJECT, K_TRIANGLES, K_SCAN, K_EMIT, K_SORT_UPSWEEP,
+  K_SORT_SCAN, K_SORT_DOWNSWEEP, K_RANGES, K_BLEND, K_BLEND_BWD, K_PROJECT_BWD, K_COUNT
+};
+
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  struct Pending { int id; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  double ms[K_COUNT] = {};
+  int64_t n[K_COUNT] = {};
+};
+
+// Device buffer that only grows.
+struct DevBuf {
+  void *p = nullptr;
+  size_t cap = 0;
+};
+
+struct Ctx {
+  umgs_options opt;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int num_cu = 256;
+  std::string err;
+
+  // proxy mesh
+  int32_t nV = 0, nF = 0;
+  DevBuf V_rest, faces, vf_ptr, vf_idx, vtab;
+
+  // per-frame state
+  int stage = 0;         // 0 none, 1 projected, 2 binned, 3 sorted
+  int32_t V = 0, N = 0, T = 0;
+  int32_t tile_w = 16, tile_h = 16, frag_batch = 128, mode = 0, sh_degree = 0;
+  float bg[3] = {0, 0, 0};
+  int64_t n_records = 0;   // V * (N + T)
+  int64_t n_tiles = 0;
+  int64_t n_pixels = 0;
+  uint64_t n_dup = 0;
+  int tile_bits = 1;
+  std::vector<ViewParams> views;
+  std::vector<int32_t> view_first_tile_x;  // host copy helpers
+  DevBuf d_views;
+  DevBuf keys;         // n_records uint32 depth bits
+  DevBuf rects;        // n_records uint2: (tx0 | ty0 << 16, tx1 | ty1 << 16) inclusive-exclusive
+  DevBuf counts;       // n_records + 1 uint64 (scanned in place to offsets)
+  DevBuf grec;         // V*N GaussRec
+  DevBuf trec;         // V*T TriRec
+  DevBuf scan_tmp;
+  DevBuf k0, k1;       // n_dup uint64 keys (ping-pong)
+  DevBuf v0, v1;       // n_dup uint32 values
+  DevBuf hist;         // radix per-block histograms
+  DevBuf ranges;       // n_tiles uint2
+  DevBuf host_pinned;  // not a device buffer: pinned host scratch for small readbacks
+  int sorted_in = 0;   // which ping-pong buffer holds the sorted result
+  Prof prof;
+};
+
+// Records a HIP event pair around the kernels launched in its scope when the
+// context's profiler is on.
+struct ScopedTimer {
+  Ctx *c;
+  int id;
+  hipEvent_t a = nullptr, b = nullptr;
+  ScopedTimer(Ctx *ctx, int kid);
+  ~ScopedTimer();
+};
+
+// error helpers
+umgs_status fail(Ctx *c, umgs_status s, const char *fmt, ...);
+umgs_status hip_check(Ctx *c, hipError_t e, const char *what);
+umgs_status ensure(Ctx *c, DevBuf &b, size_t bytes, const char *what);
+
+// launchers (each returns the launch status)
+hipError_t launch_project_gaussians(Ctx *c, const float *means, const float *cov3d,
+                                    const float *scales, const float *quats,
+                                    const float *opacity, const float *sh);
+hipError_t launch_setup_triangles(Ctx *c, const float *tri_xyz, const float *tri_rgb,
+                                  const float *tri_alpha);
+hipError_t launch_exclusive_scan_u32(Ctx *c, uint32_t *data, int64_t n, uint32_t *tmp);
+size_t scan_tmp_bytes(int64_t n);
+hipError_t launch_emit_keys(Ctx *c);
+hipError_t launch_radix_sort(Ctx *c);
+size_t radix_hist_bytes(uint64_t n);
+hipError_t launch_tile_ranges(Ctx *c);
+hipError_t launch_blend(Ctx *c, float *image, float *T_final, int32_t *n_contrib,
+                        float *T_entity_in);
+hipError_t launch_transfer(Ctx *c, const float *V_def, int32_t N, const int32_t *bind_face,
+                           const float *bind_bary, const float *means, const float *quats,
+                           const float *scales, float *means_out, float *quats_out,
+                           float *cov3d_out, float *xform_out, float *vertex_out);
+
+inline unsigned ceil_div(uint64_t a, uint64_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace umgs
+
+struct umgs_ctx {
+  umgs::Ctx c;
+};

@@ -1,0 +1,366 @@
+// Deformation transfer from a proxy mesh to bound Gaussians.
+//
+// vertex_frames_kernel (one thread per proxy vertex, FP64):
+//   Delta_v = V'_v - V_v (FP32 subtraction: it feeds the pinned mean);
+//   D_v = (sum c e' e^T + w n' n^T)(sum c e e^T + w n n^T)^-1 over the rest
+//   1-ring, c = (cot a + cot b)/2 accumulated face by face, n / n' the rest /
+//   deformed area-weighted normals scaled by the mean 1-ring edge length of
+//   their mesh, w the mean cotangent weight;
+//   polar D = R S with R = [u1 u2 u1 x u2][v1 v2 v3]^T from the eigenvectors
+//   of D^T D (a proper rotation; the nearest one to D);
+//   r_v = log R (axis-angle), written with S as a 12-float row.
+// transfer_kernel (one thread per Gaussian, FP32): Eq. 12 at each of the K
+//   bound points, Eq. 13 averages: R' = exp(mean r_i), S' = mean S_i,
+//   A = R'S', Sigma' = A Sigma A^T, mu' = mu + mean Delta_i (pinned order),
+//   q' = quat(R') * q.
+#include "internal.h"
+
+namespace umgs {
+
+namespace {
+
+__device__ __forceinline__ void cross3(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ __forceinline__ double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+__device__ __forceinline__ double norm3(const double a[3]) { return sqrt(dot3(a, a)); }
+
+// cot of the angle at p between p->q and p->r
+__device__ __forceinline__ double cot_at(const double p[3], const double q[3], const double r[3]) {
+  double u1[3] = {q[0] - p[0], q[1] - p[1], q[2] - p[2]};
+  double u2[3] = {r[0] - p[0], r[1] - p[1], r[2] - p[2]};
+  double c[3];
+  cross3(u1, u2, c);
+  return dot3(u1, u2) / norm3(c);
+}
+
+__device__ void inv3(const double M[9], double I[9]) {
+  const double c00 = M[4] * M[8] - M[5] * M[7];
+  const double c01 = M[5] * M[6] - M[3] * M[8];
+  const double c02 = M[3] * M[7] - M[4] * M[6];
+  const double det = M[0] * c00 + M[1] * c01 + M[2] * c02;
+  const double id = 1.0 / det;
+  I[0] = c00 * id;
+  I[1] = (M[2] * M[7] - M[1] * M[8]) * id;
+  I[2] = (M[1] * M[5] - M[2] * M[4]) * id;
+  I[3] = c01 * id;
+  I[4] = (M[0] * M[8] - M[2] * M[6]) * id;
+  I[5] = (M[2] * M[3] - M[0] * M[5]) * id;
+  I[6] = c02 * id;
+  I[7] = (M[1] * M[6] - M[0] * M[7]) * id;
+  I[8] = (M[0] * M[4] - M[1] * M[3]) * id;
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric 3x3 matrix A (row-major).
+// On return A's diagonal holds eigenvalues and V's columns the eigenvectors.
+__device__ void jacobi3(double A[9], double V[9]) {
+  for (int k = 0; k < 9; ++k) V[k] = (k % 4 == 0) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    const double off = A[1] * A[1] + A[2] * A[2] + A[5] * A[5];
+    const double scale = A[0] * A[0] + A[4] * A[4] + A[8] * A[8];
+    if (off <= 1e-30 * scale || off == 0.0) break;
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0;
+      const int q = pq == 0 ? 1 : 2;
+      const double apq = A[3 * p + q];
+      if (apq == 0.0) continue;
+      const double app = A[3 * p + p], aqq = A[3 * q + q];
+      const double theta = (aqq - app) / (2.0 * apq);
+      const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+      const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+      // A <- J^T A J with J the rotation in the (p,q) plane
+      for (int k = 0; k < 3; ++k) {
+        const double akp = A[3 * k + p], akq = A[3 * k + q];
+        A[3 * k + p] = c * akp - s * akq;
+        A[3 * k + q] = s * akp + c * akq;
+      }
+      for (int k = 0; k < 3; ++k) {
+        const double apk = A[3 * p + k], aqk = A[3 * q + k];
+        A[3 * p + k] = c * apk - s * aqk;
+        A[3 * q + k] = s * apk + c * aqk;
+      }
+      for (int k = 0; k < 3; ++k) {
+        const double vkp = V[3 * k + p], vkq = V[3 * k + q];
+        V[3 * k + p] = c * vkp - s * vkq;
+        V[3 * k + q] = s * vkp + c * vkq;
+      }
+    }
+  }
+}
+
+__global__ void vertex_frames_kernel(int nV, const float *__restrict__ Vr,
+                                     const float *__restrict__ Vd,
+                                     const int32_t *__restrict__ faces,
+                                     const int32_t *__restrict__ vf_ptr,
+                                     const int32_t *__restrict__ vf_idx,
+                                     float *__restrict__ vtab) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nV) return;
+  double P[9] = {0}, Q[9] = {0};
+  double nrm[3] = {0, 0, 0}, nrmd[3] = {0, 0, 0};
+  double wsum = 0.0, ls = 0.0, lsd = 0.0;
+  const double pv[3] = {Vr[3 * v], Vr[3 * v + 1], Vr[3 * v + 2]};
+  const double qv[3] = {Vd[3 * v], Vd[3 * v + 1], Vd[3 * v + 2]};
+  const int f0 = vf_ptr[v], f1 = vf_ptr[v + 1];
+  for (int k = f0; k < f1; ++k) {
+    const int f = vf_idx[k];
+    const int a0 = faces[3 * f], a1 = faces[3 * f + 1], a2 = faces[3 * f + 2];
+    const int ia = (a0 == v) ? a1 : (a1 == v) ? a2 : a0;
+    const int ib = (a0 == v) ? a2 : (a1 == v) ? a0 : a1;
+    const double pa[3] = {Vr[3 * ia], Vr[3 * ia + 1], Vr[3 * ia + 2]};
+    const double pb[3] = {Vr[3 * ib], Vr[3 * ib + 1], Vr[3 * ib + 2]};
+    const double qa[3] = {Vd[3 * ia], Vd[3 * ia + 1], Vd[3 * ia + 2]};
+    const double qb[3] = {Vd[3 * ib], Vd[3 * ib + 1], Vd[3 * ib + 2]};
+    const double cb = cot_at(pb, pv, pa), ca = cot_at(pa, pv, pb);
+    double ea[3], eb[3], fa[3], fb[3];
+    for (int i = 0; i < 3; ++i) {
+      ea[i] = pa[i] - pv[i]; eb[i] = pb[i] - pv[i];
+      fa[i] = qa[i] - qv[i]; fb[i] = qb[i] - qv[i];
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        P[3 * i + j] += 0.5 * cb * fa[i] * ea[j] + 0.5 * ca * fb[i] * eb[j];
+        Q[3 * i + j] += 0.5 * cb * ea[i] * ea[j] + 0.5 * ca * eb[i] * eb[j];
+      }
+    wsum += 0.5 * (ca + cb);
+    double c[3];
+    cross3(ea, eb, c);
+    for (int i = 0; i < 3; ++i) nrm[i] += c[i];
+    cross3(fa, fb, c);
+    for (int i = 0; i < 3; ++i) nrmd[i] += c[i];
+    ls += norm3(ea) + norm3(eb);
+    lsd += norm3(fa) + norm3(fb);
+  }
+  const double nf = (double)(f1 - f0);
+  const double sn = ls / (2.0 * nf) / norm3(nrm), snd = lsd / (2.0 * nf) / norm3(nrmd);
+  const double w = wsum / nf;
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      P[3 * i + j] += w * (nrmd[i] * snd) * (nrm[j] * sn);
+      Q[3 * i + j] += w * (nrm[i] * sn) * (nrm[j] * sn);
+    }
+  double Qi[9], D[9];
+  inv3(Q, Qi);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      D[3 * i + j] = P[3 * i] * Qi[j] + P[3 * i + 1] * Qi[3 + j] + P[3 * i + 2] * Qi[6 + j];
+
+  // polar decomposition through the eigenvectors of D^T D
+  double M[9], E[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      M[3 * i + j] = D[i] * D[j] + D[3 + i] * D[3 + j] + D[6 + i] * D[6 + j];
+  jacobi3(M, E);
+  int o0 = 0, o1 = 1, o2 = 2;   // order eigenvalues descending
+  double l[3] = {M[0], M[4], M[8]};
+  if (l[o0] < l[o1]) { int t = o0; o0 = o1; o1 = t; }
+  if (l[o1] < l[o2]) { int t = o1; o1 = o2; o2 = t; }
+  if (l[o0] < l[o1]) { int t = o0; o0 = o1; o1 = t; }
+  double v1[3] = {E[o0], E[3 + o0], E[6 + o0]};
+  double v2[3] = {E[o1], E[3 + o1], E[6 + o1]};
+  double v3[3];
+  cross3(v1, v2, v3);   // proper eigenvector frame
+  double u1[3], u2[3], u3[3];
+  for (int i = 0; i < 3; ++i) {
+    u1[i] = D[3 * i] * v1[0] + D[3 * i + 1] * v1[1] + D[3 * i + 2] * v1[2];
+    u2[i] = D[3 * i] * v2[0] + D[3 * i + 1] * v2[1] + D[3 * i + 2] * v2[2];
+  }
+  const double n1 = norm3(u1);
+  for (int i = 0; i < 3; ++i) u1[i] /= n1;
+  const double pr = dot3(u1, u2);
+  for (int i = 0; i < 3; ++i) u2[i] -= pr * u1[i];
+  const double n2 = norm3(u2);
+  for (int i = 0; i < 3; ++i) u2[i] /= n2;
+  cross3(u1, u2, u3);
+  double R[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) R[3 * i + j] = u1[i] * v1[j] + u2[i] * v2[j] + u3[i] * v3[j];
+  double S[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j)
+      S[3 * i + j] = R[i] * D[j] + R[3 + i] * D[3 + j] + R[6 + i] * D[6 + j];
+  // principal rotation log
+  const double ct = fmin(1.0, fmax(-1.0, 0.5 * (R[0] + R[4] + R[8] - 1.0)));
+  const double th = acos(ct);
+  const double fth = th < 1e-4 ? 0.5 * (1.0 + th * th / 6.0) : th / (2.0 * sin(th));
+  float *out = vtab + 12 * (int64_t)v;
+  out[0] = Vd[3 * v] - Vr[3 * v];
+  out[1] = Vd[3 * v + 1] - Vr[3 * v + 1];
+  out[2] = Vd[3 * v + 2] - Vr[3 * v + 2];
+  out[3] = (float)(fth * (R[7] - R[5]));
+  out[4] = (float)(fth * (R[2] - R[6]));
+  out[5] = (float)(fth * (R[3] - R[1]));
+  out[6] = (float)S[0];
+  out[7] = (float)(0.5 * (S[1] + S[3]));
+  out[8] = (float)(0.5 * (S[2] + S[6]));
+  out[9] = (float)S[4];
+  out[10] = (float)(0.5 * (S[5] + S[7]));
+  out[11] = (float)S[8];
+}
+
+__device__ __forceinline__ float3 interp_delta(float u, float v, float w, const float4 &a,
+                                               const float4 &b, const float4 &c) {
+#pragma clang fp contract(off)
+  float3 d;
+  d.x = (u * a.x + v * b.x) + w * c.x;
+  d.y = (u * a.y + v * b.y) + w * c.y;
+  d.z = (u * a.z + v * b.z) + w * c.z;
+  return d;
+}
+
+__device__ __forceinline__ float3 add3(float3 a, float3 b) {
+#pragma clang fp contract(off)
+  return make_float3(a.x + b.x, a.y + b.y, a.z + b.z);
+}
+
+__device__ __forceinline__ float pinned_w(float u, float v) {
+#pragma clang fp contract(off)
+  return (1.0f - u) - v;
+}
+
+__device__ __forceinline__ float pinned_mean(float m, float s, float invk) {
+#pragma clang fp contract(off)
+  return m + s * invk;
+}
+
+template <int K>
+__global__ void transfer_kernel(int N, const float4 *__restrict__ vtab,
+                                const int32_t *__restrict__ faces,
+                                const int32_t *__restrict__ bind_face,
+                                const float *__restrict__ bind_bary,
+                                const float *__restrict__ means, const float *__restrict__ quats,
+                                const float *__restrict__ scales, float *__restrict__ means_out,
+                                float *__restrict__ quats_out, float *__restrict__ cov3d_out,
+                                float *__restrict__ xform_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  float3 dsum = make_float3(0.f, 0.f, 0.f);
+  float rs[3] = {0.f, 0.f, 0.f};
+  float Ss[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = bind_face[(int64_t)K * i + k];
+    const float u = bind_bary[2 * ((int64_t)K * i + k)];
+    const float v = bind_bary[2 * ((int64_t)K * i + k) + 1];
+    const float w = pinned_w(u, v);
+    const int va = faces[3 * f], vb = faces[3 * f + 1], vc = faces[3 * f + 2];
+    const float4 a0 = vtab[3 * va], a1 = vtab[3 * va + 1], a2 = vtab[3 * va + 2];
+    const float4 b0 = vtab[3 * vb], b1 = vtab[3 * vb + 1], b2 = vtab[3 * vb + 2];
+    const float4 c0 = vtab[3 * vc], c1 = vtab[3 * vc + 1], c2 = vtab[3 * vc + 2];
+    const float3 di = interp_delta(u, v, w, a0, b0, c0);
+    dsum = (k == 0) ? di : add3(dsum, di);
+    // Eq. 12: log-rotation and shear interpolated with the same barycentrics
+    rs[0] += u * a0.w + v * b0.w + w * c0.w;
+    rs[1] += u * a1.x + v * b1.x + w * c1.x;
+    rs[2] += u * a1.y + v * b1.y + w * c1.y;
+    Ss[0] += u * a1.z + v * b1.z + w * c1.z;
+    Ss[1] += u * a1.w + v * b1.w + w * c1.w;
+    Ss[2] += u * a2.x + v * b2.x + w * c2.x;
+    Ss[3] += u * a2.y + v * b2.y + w * c2.y;
+    Ss[4] += u * a2.z + v * b2.z + w * c2.z;
+    Ss[5] += u * a2.w + v * b2.w + w * c2.w;
+  }
+  const float invk = 1.0f / (float)K;
+  means_out[3 * i] = pinned_mean(means[3 * i], dsum.x, invk);
+  means_out[3 * i + 1] = pinned_mean(means[3 * i + 1], dsum.y, invk);
+  means_out[3 * i + 2] = pinned_mean(means[3 * i + 2], dsum.z, invk);
+
+  // Eq. 13: R' = exp(mean r), S' = mean S, A = R'S'
+  const float r0 = rs[0] * invk, r1 = rs[1] * invk, r2 = rs[2] * invk;
+  const float th2 = r0 * r0 + r1 * r1 + r2 * r2;
+  const float th = sqrtf(th2);
+  float sa, hb, sh_over;   // sin(th)/th, (1-cos th)/th^2, sin(th/2)/th
+  if (th < 1e-2f) {
+    sa = 1.0f - th2 * (1.0f / 6.0f);
+    hb = 0.5f - th2 * (1.0f / 24.0f);
+    sh_over = 0.5f - th2 * (1.0f / 48.0f);
+  } else {
+    const float s = sinf(th), h = sinf(0.5f * th);
+    sa = s / th;
+    const float q = h / (0.5f * th);
+    hb = 0.5f * q * q;
+    sh_over = h / th;
+  }
+  // R' = I + sa K + hb K^2, K = [r]_x
+  const float Rp[9] = {1.f - hb * (r1 * r1 + r2 * r2), -sa * r2 + hb * r0 * r1, sa * r1 + hb * r0 * r2,
+                       sa * r2 + hb * r0 * r1, 1.f - hb * (r0 * r0 + r2 * r2), -sa * r0 + hb * r1 * r2,
+                       -sa * r1 + hb * r0 * r2, sa * r0 + hb * r1 * r2, 1.f - hb * (r0 * r0 + r1 * r1)};
+  const float Sm[9] = {Ss[0] * invk, Ss[1] * invk, Ss[2] * invk, Ss[1] * invk, Ss[3] * invk,
+                       Ss[4] * invk, Ss[2] * invk, Ss[4] * invk, Ss[5] * invk};
+  float A[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      A[3 * r + c] = Rp[3 * r] * Sm[c] + Rp[3 * r + 1] * Sm[3 + c] + Rp[3 * r + 2] * Sm[6 + c];
+
+  float qw = quats[4 * i], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
+  const float qn = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  qw *= qn; qx *= qn; qy *= qn; qz *= qn;
+  const float Rq[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
+                       2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
+                       2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
+  const float s0 = scales[3 * i], s1 = scales[3 * i + 1], s2 = scales[3 * i + 2];
+  // B = A R(q) diag(s); Sigma' = B B^T
+  float B[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    B[3 * r] = (A[3 * r] * Rq[0] + A[3 * r + 1] * Rq[3] + A[3 * r + 2] * Rq[6]) * s0;
+    B[3 * r + 1] = (A[3 * r] * Rq[1] + A[3 * r + 1] * Rq[4] + A[3 * r + 2] * Rq[7]) * s1;
+    B[3 * r + 2] = (A[3 * r] * Rq[2] + A[3 * r + 1] * Rq[5] + A[3 * r + 2] * Rq[8]) * s2;
+  }
+  float *cv = cov3d_out + 6 * (int64_t)i;
+  cv[0] = B[0] * B[0] + B[1] * B[1] + B[2] * B[2];
+  cv[1] = B[0] * B[3] + B[1] * B[4] + B[2] * B[5];
+  cv[2] = B[0] * B[6] + B[1] * B[7] + B[2] * B[8];
+  cv[3] = B[3] * B[3] + B[4] * B[4] + B[5] * B[5];
+  cv[4] = B[3] * B[6] + B[4] * B[7] + B[5] * B[8];
+  cv[5] = B[6] * B[6] + B[7] * B[7] + B[8] * B[8];
+  if (xform_out) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) xform_out[9 * (int64_t)i + k] = A[k];
+  }
+  if (quats_out) {
+    const float pw = cosf(0.5f * th), px = sh_over * r0, py = sh_over * r1, pz = sh_over * r2;
+    float *qo = quats_out + 4 * (int64_t)i;
+    qo[0] = pw * qw - px * qx - py * qy - pz * qz;
+    qo[1] = pw * qx + px * qw + py * qz - pz * qy;
+    qo[2] = pw * qy - px * qz + py * qw + pz * qx;
+    qo[3] = pw * qz + px * qy - py * qx + pz * qw;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_transfer(Ctx *c, const float *V_def, int32_t N, const int32_t *bind_face,
+                           const float *bind_bary, const float *means, const float *quats,
+                           const float *scales, float *means_out, float *quats_out,
+                           float *cov3d_out, float *xform_out, float *vertex_out) {
+  float *vtab = vertex_out ? vertex_out : (float *)c->vtab.p;
+  hipError_t e;
+  {
+    ScopedTimer t(c, K_VERTEX_FRAMES);
+    hipLaunchKernelGGL(vertex_frames_kernel, dim3(ceil_div(c->nV, 128)), dim3(128), 0, c->stream,
+                       c->nV, (const float *)c->V_rest.p, V_def, (const int32_t *)c->faces.p,
+                       (const int32_t *)c->vf_ptr.p, (const int32_t *)c->vf_idx.p, vtab);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess || N == 0) return e;
+  ScopedTimer tt(c, K_TRANSFER);
+  if (c->opt.k_bind == 8)
+    hipLaunchKernelGGL(transfer_kernel<8>, dim3(ceil_div(N, 256)), dim3(256), 0, c->stream, N,
+                       (const float4 *)vtab, (const int32_t *)c->faces.p, bind_face, bind_bary,
+                       means, quats, scales, means_out, quats_out, cov3d_out, xform_out);
+  else
+    hipLaunchKernelGGL(transfer_kernel<1>, dim3(ceil_div(N, 256)), dim3(256), 0, c->stream, N,
+                       (const float4 *)vtab, (const int32_t *)c->faces.p, bind_face, bind_bary,
+                       means, quats, scales, means_out, quats_out, cov3d_out, xform_out);
+  return hipGetLastError();
+}
+
+}  // namespace umgs

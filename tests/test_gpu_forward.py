@@ -1,0 +1,261 @@
+"""GPU forward path vs the CPU FP64 oracle (through the C ABI).
+
+Bit-exact: depth keys, snapped triangle vertices, sorted (tile, depth, id)
+order, the last blended fragment of every pixel.  Within 1e-4 per channel:
+image and final transmittance.  Pixels whose oracle decisions sit within
+1e-4 (relative) of a threshold may match an outcome with that decision
+inverted (both are valid).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import render as OR
+from paper_2601_19233_amd import scenes
+from tests import _parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev(gpu):
+    import torch
+    return torch
+
+
+def rast(**opts):
+    from paper_2601_19233_amd.render import Rasterizer
+    return Rasterizer("cuda:0", **opts)
+
+
+def run(scene, cams=None, cov3d=None, means=None, **opts):
+    from paper_2601_19233_amd.render import scene_inputs
+    r = rast(sh_degree=scene.sh_degree, **opts)
+    cams = scene.cams if cams is None else cams
+    out = r.render(cams, **scene_inputs(scene, cov3d=cov3d, means=means))
+    return r, out
+
+
+def to_np(t):
+    return t.detach().cpu().numpy()
+
+
+def view_arrays(r, out, v=0):
+    img = to_np(r.split_views(out["image"], 3)[v])
+    Tf = to_np(r.split_views(out["T_final"], 1)[v])
+    nc = to_np(r.split_views(out["n_contrib"], 1)[v])
+    return img, Tf, nc
+
+
+def entity_T(r, out, v=0):
+    return to_np(r.split_views(out["T_entity_in"], 1)[v])
+
+
+def last_gids(r, nc, v=0):
+    from paper_2601_19233_amd import _lib as L
+    ranges = to_np(r.copy_state(L.STATE_RANGES)).astype(np.int64)
+    vals = to_np(r.copy_state(L.STATE_SORTED_VALS)).astype(np.uint32)
+    W, H = r.views[v]
+    tw, th = r.opts.tile_w, r.opts.tile_h
+    ntx = (W + tw - 1) // tw
+    base = sum(((w + tw - 1) // tw) * ((h + th - 1) // th) for w, h in r.views[:v])
+    return PT.gpu_last_gid(nc, ranges, vals, base, ntx, tw, th, W, H, r.N + r.T, v)
+
+
+# ---------------------------------------------------------------- decision values
+
+def test_keys_and_snapped_vertices_bit_exact(torch_dev):
+    from paper_2601_19233_amd import _lib as L
+    s = scenes.make_config(0)
+    note("keys cfg0")
+    r, _ = run(s)
+    keys = to_np(r.copy_state(L.STATE_KEYS)).view(np.uint32)
+    fr = PT.oracle_frame(s, s.cams[0])
+    gk = np.where(fr.g.valid, fr.g.key.view(np.uint32), np.uint32(0xFFFFFFFF))
+    tk = np.where(fr.t.valid, fr.t.key.view(np.uint32), np.uint32(0xFFFFFFFF))
+    # Gaussians that cannot reach 1/255 anywhere are also culled on the GPU
+    live = s.opacity.astype(np.float32) * np.float32(255) > 1
+    gk = np.where(live, gk, np.uint32(0xFFFFFFFF))
+    assert np.array_equal(keys[: s.N], gk)
+    assert np.array_equal(keys[s.N:], tk)
+    fx = to_np(r.copy_state(L.STATE_TRI_FIXED))
+    v = fr.t.valid
+    assert np.array_equal(fx[v, :3], fr.t.X[v])
+    assert np.array_equal(fx[v, 3:], fr.t.Y[v])
+
+
+def test_sorted_order_is_stable_key_order(torch_dev):
+    from paper_2601_19233_amd import _lib as L
+    s = scenes.make_config(0)
+    note("sort order cfg0")
+    r, _ = run(s, tile=(8, 8))
+    k = to_np(r.copy_state(L.STATE_SORTED_KEYS)).view(np.uint64)
+    vals = to_np(r.copy_state(L.STATE_SORTED_VALS)).view(np.uint32)
+    assert k.size > 0
+    assert np.all(k[1:] >= k[:-1])
+    eq = k[1:] == k[:-1]
+    assert np.all(vals[1:][eq] > vals[:-1][eq])
+    # the depth part of each key is that primitive's key
+    keys = to_np(r.copy_state(L.STATE_KEYS)).view(np.uint32)
+    assert np.array_equal((k & 0xFFFFFFFF).astype(np.uint32), keys[vals])
+    # the pair multiset is a permutation of what numpy's stable sort gives
+    order = np.lexsort((vals, k))
+    assert np.array_equal(order, np.arange(k.size))
+    # ranges partition the list
+    rg = to_np(r.copy_state(L.STATE_RANGES)).astype(np.int64)
+    nonempty = rg[:, 1] > rg[:, 0]
+    assert rg[nonempty, 1].max() == k.size
+    tiles = (k >> np.uint64(32)).astype(np.int64)
+    for t in np.flatnonzero(nonempty)[::7]:
+        assert np.all(tiles[rg[t, 0]:rg[t, 1]] == t)
+
+
+# ---------------------------------------------------------------- images
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8)])
+def test_cfg0_full_frame_parity(torch_dev, tile):
+    s = scenes.make_config(0)
+    note(f"cfg0 full frame tile={tile}")
+    r, out = run(s, tile=tile)
+    img, Tf, nc = view_arrays(r, out)
+    lg = last_gids(r, nc)
+    fr = PT.oracle_frame(s, s.cams[0])
+    px = [(x, y) for y in range(64) for x in range(64)]
+    res = PT.compare_pixels(fr, img, Tf, lg, px, Tent=entity_T(r, out))
+    note(f"cfg0 {tile}: {res}")
+    assert res["ambiguous"] < 0.01 * len(px)
+
+
+def test_tile_shape_invariance_bit_identical(torch_dev):
+    s = scenes.make_config(0)
+    note("tile invariance")
+    imgs = []
+    for tile in [(16, 16), (8, 8), (32, 8)]:
+        r, out = run(s, tile=tile)
+        imgs.append(to_np(out["image"]))
+    assert np.array_equal(imgs[0], imgs[1]) and np.array_equal(imgs[0], imgs[2])
+
+
+def test_batch_size_invariance(torch_dev):
+    s = scenes.make_config(0)
+    note("batch invariance")
+    ref = None
+    for b in (32, 64, 128, 256):
+        r, out = run(s, frag_batch=b)
+        im = to_np(out["image"])
+        if ref is None:
+            ref = im
+        assert np.array_equal(im, ref)
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_ablation_modes_parity(torch_dev, mode):
+    s = scenes.make_config(0, seed=5, res_scale=0.75)
+    note(f"mode {mode}")
+    r, out = run(s, mode=mode)
+    img, Tf, nc = view_arrays(r, out)
+    fr = PT.oracle_frame(s, s.cams[0], mode=mode)
+    W, H = s.cams[0].width, s.cams[0].height
+    px = [(x, y) for y in range(H) for x in range(W)]
+    PT.compare_pixels(fr, img, Tf, last_gids(r, nc), px, Tent=entity_T(r, out))
+
+
+def test_background_and_ragged_size(torch_dev):
+    s = scenes.make_config(0, seed=7, scale=0.5)
+    cam = scenes.look_at((0.3, 0.2, 2.6), 53, 37)
+    bg = (0.2, 0.5, 0.9)
+    note("ragged 53x37 with background")
+    r, out = run(s, cams=[cam], bg=bg, tile=(16, 16))
+    img, Tf, nc = view_arrays(r, out)
+    fr = PT.oracle_frame(s, cam, bg=bg)
+    px = [(x, y) for y in range(37) for x in range(53)]
+    PT.compare_pixels(fr, img, Tf, last_gids(r, nc), px)
+
+
+def test_empty_and_degenerate_scenes(torch_dev):
+    import torch
+    from paper_2601_19233_amd.render import Rasterizer
+    note("empty scene")
+    cam = scenes.look_at((0, 0, 3), 20, 12)
+    r = Rasterizer("cuda:0", bg=(0.1, 0.2, 0.3))
+    out = r.render([cam])
+    img = to_np(out["image"]).reshape(3, 12, 20)
+    assert np.allclose(img[0], 0.1) and np.allclose(img[1], 0.2) and np.allclose(img[2], 0.3)
+    assert np.all(to_np(out["T_final"]) == 1.0)
+    # everything behind the camera or degenerate: still background
+    note("culled scene")
+    means = np.array([[0, 0, 5.0], [0, 0, 3.1]], np.float32)     # behind / inside near plane
+    tri = np.array([[[0, 0, 4.0], [1, 0, 4.0], [0, 1, 4.0]],      # behind the camera
+                    [[0, 0, 0], [0.5, 0.5, 0], [1, 1, 0]]], np.float32)   # zero area
+    out = r.render([cam], means=means, opacity=np.full(2, 0.9, np.float32),
+                   sh=np.zeros((2, 3), np.float32), scales=np.full((2, 3), 0.1, np.float32),
+                   quats=np.tile(np.float32([1, 0, 0, 0]), (2, 1)), tri_xyz=tri.reshape(2, 9),
+                   tri_rgb=np.ones((2, 9), np.float32), tri_alpha=np.ones(2, np.float32))
+    assert np.all(to_np(out["T_final"]) == 1.0)
+    # 1x1 image
+    note("1x1 image")
+    s = scenes.make_config(0)
+    cam1 = scenes.look_at((0, 0, 3), 1, 1)
+    r2, out = run(s, cams=[cam1])
+    fr = PT.oracle_frame(s, cam1)
+    img, Tf, nc = view_arrays(r2, out)
+    PT.compare_pixels(fr, img, Tf, None, [(0, 0)])
+
+
+def test_deformed_scene_parity(torch_dev):
+    """Scaled deformed workload: GPU transfer then GPU render, against the
+    oracle transfer then oracle render, on every pixel of a small view."""
+    import torch
+    from oracle import transfer as OT
+    from paper_2601_19233_amd.render import Rasterizer, scene_inputs
+    s = scenes.make_config(1, scale=0.004, res_scale=0.06)
+    note(f"deformed N={s.N} T={s.T} view={s.cams[0].width}x{s.cams[0].height}")
+    r = Rasterizer("cuda:0")
+    r.set_proxy(s.proxy.V_rest, s.proxy.faces)
+    dt = r.bind_transfer(s.proxy.V_def, s.bind_face, s.bind_bary, s.means, s.quats, s.scales)
+    ot = OT.transfer(s.proxy.V_rest, s.proxy.faces, s.proxy.V_def, s.means, s.quats, s.scales,
+                     s.bind_face, s.bind_bary)
+    gm = to_np(dt["means"])
+    assert np.array_equal(gm, ot["means"])            # pinned FP32 mean
+    np.testing.assert_allclose(to_np(dt["cov3d"]), ot["cov3d"], rtol=2e-4,
+                               atol=1e-5 * np.abs(ot["cov3d"]).max())
+    out = r.render(s.cams, **scene_inputs(s, cov3d=dt["cov3d"], means=dt["means"]))
+    img, Tf, nc = view_arrays(r, out)
+    fr = PT.oracle_frame(s, s.cams[0], cov3d=ot["cov3d"], means=ot["means"])
+    W, H = s.cams[0].width, s.cams[0].height
+    px = [(x, y) for y in range(H) for x in range(W)]
+    PT.compare_pixels(fr, img, Tf, last_gids(r, nc), px)
+
+
+def test_sh3_parity(torch_dev):
+    s = scenes.make_config(2, scale=0.01, res_scale=0.1)
+    note(f"sh3 N={s.N} T={s.T}")
+    r, out = run(s)
+    img, Tf, nc = view_arrays(r, out)
+    fr = PT.oracle_frame(s, s.cams[0])
+    W, H = s.cams[0].width, s.cams[0].height
+    px = [(x, y) for y in range(H) for x in range(W)]
+    PT.compare_pixels(fr, img, Tf, last_gids(r, nc), px)
+
+
+def test_multi_view_matches_single_views(torch_dev):
+    s = scenes.make_config(3, scale=0.004, res_scale=0.08, n_views=5)
+    note(f"multi-view {[(c.width, c.height) for c in s.cams]}")
+    r, out = run(s)
+    imgs = r.split_views(out["image"], 3)
+    for v, cam in enumerate(s.cams):
+        r1, o1 = run(s, cams=[cam])
+        assert np.array_equal(to_np(imgs[v]), to_np(o1["image"]).reshape(3, cam.height, cam.width))
+    # and one view against the oracle
+    img, Tf, nc = view_arrays(r, out, v=2)
+    fr = PT.oracle_frame(s, s.cams[2])
+    W, H = s.cams[2].width, s.cams[2].height
+    px = [(x, y) for y in range(0, H, 2) for x in range(0, W, 2)]
+    PT.compare_pixels(fr, img, Tf, last_gids(r, nc, v=2), px)
