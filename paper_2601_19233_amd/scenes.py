@@ -30,6 +30,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import os
 from typing import List, Optional
 
 import numpy as np
@@ -436,8 +437,56 @@ def make_config(index: int, seed: Optional[int] = None, scale: float = 1.0,
     ``scale`` multiplies the Gaussian count and the mesh subdivision density
     (triangle counts scale with it); ``res_scale`` multiplies image width and
     height; ``n_views`` overrides the number of views of workloads 3 and 4.
-    The full-size workloads are ``scale = res_scale = 1``.
+    The full-size workloads are ``scale = res_scale = 1``.  If the
+    environment variable UMGS_SCENE_CACHE names a directory, generated scenes
+    are stored there (pickle-free .npz) and reused.
     """
+    cache = os.environ.get("UMGS_SCENE_CACHE")
+    if cache:
+        key = f"cfg{index}_s{seed}_x{scale}_r{res_scale}_v{n_views}_k{K}.npz"
+        path = os.path.join(cache, key)
+        if os.path.exists(path):
+            return _load_scene(path)
+        sc = _make_config(index, seed, scale, res_scale, n_views, K)
+        os.makedirs(cache, exist_ok=True)
+        _save_scene(sc, path)
+        return sc
+    return _make_config(index, seed, scale, res_scale, n_views, K)
+
+
+_CAM_FIELDS = ("fx", "fy", "cx", "cy", "width", "height")
+
+
+def _save_scene(sc: Scene, path: str):
+    d = dict(name=np.array(sc.name), means=sc.means, scales=sc.scales, quats=sc.quats,
+             opacity=sc.opacity, sh=sc.sh, sh_degree=np.array(sc.sh_degree), tri_xyz=sc.tri_xyz,
+             tri_rgb=sc.tri_rgb, tri_alpha=sc.tri_alpha, bg=np.array(sc.bg, np.float64),
+             cam_R=np.stack([c.R for c in sc.cams]), cam_t=np.stack([c.t for c in sc.cams]),
+             cam_k=np.array([[getattr(c, f) for f in _CAM_FIELDS] for c in sc.cams], np.float64))
+    if sc.proxy is not None:
+        d.update(V_rest=sc.proxy.V_rest, faces=sc.proxy.faces, V_def=sc.proxy.V_def,
+                 bind_face=sc.bind_face, bind_bary=sc.bind_bary)
+    tmp = path + ".tmp.npz"
+    np.savez(tmp, **d)
+    os.replace(tmp, path)
+
+
+def _load_scene(path: str) -> Scene:
+    z = np.load(path)          # allow_pickle stays False
+    cams = [Camera(R=z["cam_R"][i], t=z["cam_t"][i], fx=float(k[0]), fy=float(k[1]), cx=float(k[2]),
+                   cy=float(k[3]), width=int(k[4]), height=int(k[5]))
+            for i, k in enumerate(z["cam_k"])]
+    proxy = None
+    bf = bb = None
+    if "V_rest" in z:
+        proxy = Proxy(z["V_rest"], z["faces"], z["V_def"])
+        bf, bb = z["bind_face"], z["bind_bary"]
+    return Scene(str(z["name"]), z["means"], z["scales"], z["quats"], z["opacity"], z["sh"],
+                 int(z["sh_degree"]), z["tri_xyz"], z["tri_rgb"], z["tri_alpha"], cams, proxy=proxy,
+                 bind_face=bf, bind_bary=bb, bg=tuple(z["bg"].tolist()))
+
+
+def _make_config(index, seed, scale, res_scale, n_views, K) -> Scene:
     seed = index if seed is None else seed
     rng = np.random.default_rng(seed)
 

@@ -1,0 +1,150 @@
+"""Pins of the gradient oracle.
+
+1. Its PyTorch re-evaluation reproduces the pinned NumPy forward oracle.
+2. Its autograd gradients agree with central finite differences of the NumPy
+   forward oracle in FP64 (parameters whose +-h perturbation changes any
+   pixel's discrete decisions are skipped).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import grad as OG
+from oracle import render as OR
+from paper_2601_19233_amd import scenes
+
+F32 = np.float32
+
+
+def mixed_scene(seed, n=14, W=16, H=16, degree=0):
+    rng = np.random.default_rng(seed)
+    cam = scenes.look_at((0.1, -0.1, 2.2), W, H)
+    means = rng.uniform(-0.35, 0.35, size=(n, 3))
+    scales = np.exp(rng.normal(-2.4, 0.3, size=(n, 3)))
+    quats = rng.normal(size=(n, 4))
+    opac = rng.uniform(0.2, 0.9, size=n)
+    nc = (degree + 1) ** 2
+    sh = rng.normal(0, 0.3, size=(n, nc, 3))
+    sh[:, 0, :] = (rng.uniform(0, 1, size=(n, 3)) - 0.5) * 2 * math.sqrt(math.pi)
+    # a semi-transparent quad split into two triangles, and an opaque small sphere
+    qv = np.array([[-0.6, -0.6, 0.05], [0.6, -0.55, 0.1], [0.55, 0.6, 0.0], [-0.6, 0.6, -0.05]])
+    V, F = scenes.icosphere(2, 0.15, (0.1, 0.05, -0.2))
+    xyz = np.concatenate([qv[[[0, 1, 2], [0, 2, 3]]], V[F]]).astype(F32)
+    rgb = rng.uniform(0, 1, size=(xyz.shape[0], 3, 3)).astype(F32)
+    al = np.concatenate([[0.45, 0.45], np.ones(F.shape[0])]).astype(F32)
+    return cam, means, scales, quats, opac, sh, xyz, rgb, al
+
+
+def frame_of(cam, means, scales, quats, opac, sh, deg, xyz, rgb, al, mode=0, bg=(0.1, 0.2, 0.3)):
+    return OR.Frame(cam, means, opac, sh, deg, xyz, rgb, al, scales=scales, quats=quats, bg=bg, mode=mode)
+
+
+def all_pixels(cam):
+    return [(x, y) for y in range(cam.height) for x in range(cam.width)]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_torch_forward_reproduces_oracle(mode):
+    import torch
+    cam, means, scales, quats, opac, sh, xyz, rgb, al = mixed_scene(1)
+    fr = frame_of(cam, means, scales, quats, opac, sh, 0, xyz, rgb, al, mode)
+    px = all_pixels(cam)
+    t = lambda a: torch.tensor(np.asarray(a, np.float64))
+    C, T = OG.render_pixels(fr, px, t(means), t(scales), t(quats), t(opac), t(sh), 0)
+    ref = [fr.pixel(x, y) for x, y in px]
+    np.testing.assert_allclose(C.numpy(), np.stack([r.C for r in ref]), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(T.numpy(), np.array([r.T for r in ref]), rtol=0, atol=1e-12)
+    assert any(len(r.order) > 3 for r in ref)
+
+
+def signature(fr, px):
+    return [tuple(fr.pixel(x, y).order) for x, y in px]
+
+
+def loss(cam, px, w, means, scales, quats, opac, sh, deg, xyz, rgb, al, mode, xform=None, off=None):
+    if xform is not None:
+        Sig = OR.cov3d_from_scale_rot(scales, quats)
+        Sp = xform @ Sig @ np.transpose(xform, (0, 2, 1))
+        cov = np.stack([Sp[:, 0, 0], Sp[:, 0, 1], Sp[:, 0, 2], Sp[:, 1, 1], Sp[:, 1, 2], Sp[:, 2, 2]], 1)
+        fr = OR.Frame(cam, means + off, opac, sh, deg, xyz, rgb, al, cov3d=cov, bg=(0.1, 0.2, 0.3), mode=mode)
+    else:
+        fr = frame_of(cam, means, scales, quats, opac, sh, deg, xyz, rgb, al, mode)
+    C = np.stack([fr.pixel(x, y).C for x, y in px])
+    return float((C * w).sum()), signature(fr, px)
+
+
+def check_fd(cam, params, deg, xyz, rgb, al, mode, gids, xform=None, off=None, rtol=2e-5):
+    means, scales, quats, opac, sh = params
+    px = all_pixels(cam)
+    rng = np.random.default_rng(7)
+    w = rng.normal(size=(len(px), 3))
+    g = OG.gradients(cam, px, w, means, scales, quats, opac, sh, deg, xyz, rgb, al,
+                     bg=(0.1, 0.2, 0.3), mode=mode, xform=xform, mean_offset=off)
+    _, sig0 = loss(cam, px, w, *params, deg, xyz, rgb, al, mode, xform, off)
+    names = ["means", "scales", "quats", "opacity", "sh"]
+    checked = skipped = 0
+    gmax = max(np.abs(g[n]).max() for n in names)
+    for gi in gids:
+        for pi, name in enumerate(names):
+            arr = params[pi]
+            for comp in np.ndindex(arr.shape[1:]):
+                idx = (gi,) + comp
+                th = arr[idx]
+                h = 1e-6 * max(1.0, abs(th))
+                vals = []
+                sigs = []
+                for s in (+1, -1):
+                    pp = [p.copy() for p in params]
+                    pp[pi][idx] = th + s * h
+                    L, sig = loss(cam, px, w, *pp, deg, xyz, rgb, al, mode, xform, off)
+                    vals.append(L)
+                    sigs.append(sig)
+                if sigs[0] != sig0 or sigs[1] != sig0:
+                    skipped += 1
+                    continue
+                fd = (vals[0] - vals[1]) / (2 * h)
+                an = g[name][idx]
+                assert abs(fd - an) <= rtol * max(abs(fd), abs(an)) + 1e-7 * gmax, (name, idx, fd, an)
+                checked += 1
+    return checked, skipped
+
+
+def contributing(cam, params, deg, xyz, rgb, al, mode, k=3):
+    fr = frame_of(cam, *params, deg, xyz, rgb, al, mode)
+    counts = {}
+    for x, y in all_pixels(cam):
+        for gid in fr.pixel(x, y).order:
+            if gid < len(params[0]):
+                counts[gid] = counts.get(gid, 0) + 1
+    return [g for g, _ in sorted(counts.items(), key=lambda t: -t[1])[:k]]
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_gradients_match_finite_differences(mode):
+    cam, means, scales, quats, opac, sh, xyz, rgb, al = mixed_scene(2)
+    params = [means, scales, quats, opac, sh]
+    gids = contributing(cam, params, 0, xyz, rgb, al, mode)
+    checked, skipped = check_fd(cam, params, 0, xyz, rgb, al, mode, gids)
+    assert checked >= 30 and skipped <= checked // 4
+
+
+def test_gradients_sh3_match_finite_differences():
+    cam, means, scales, quats, opac, sh, xyz, rgb, al = mixed_scene(3, degree=3)
+    params = [means, scales, quats, opac, sh]
+    gids = contributing(cam, params, 3, xyz, rgb, al, 0, k=2)
+    checked, skipped = check_fd(cam, params, 3, xyz, rgb, al, 0, gids)
+    assert checked >= 80
+
+
+def test_gradients_deformed_match_finite_differences():
+    """With the transfer's A and mean offset held fixed (Eq. 13 outputs)."""
+    cam, means, scales, quats, opac, sh, xyz, rgb, al = mixed_scene(4)
+    rng = np.random.default_rng(5)
+    n = means.shape[0]
+    A = np.eye(3)[None] + rng.normal(0, 0.15, size=(n, 3, 3))
+    off = rng.normal(0, 0.03, size=(n, 3))
+    params = [means, scales, quats, opac, sh]
+    gids = [0, 3, 5]
+    checked, skipped = check_fd(cam, params, 0, xyz, rgb, al, 0, gids, xform=A, off=off)
+    assert checked >= 20
