@@ -159,6 +159,31 @@ umgs_status umgs_sort(umgs_ctx *ctx);
 umgs_status umgs_blend(umgs_ctx *ctx, float *image, float *T_final, int32_t *n_contrib,
                        float *T_entity_in);
 
+/* ---- backward (gradients through the blend of Section 3.2) ----------------- */
+
+/* Gradients of a loss L with respect to the Gaussians of the last blended
+ * frame on this context, given dL_dimage [device] (same layout as image).
+ * T_final, n_contrib and T_entity_in are the per-pixel outputs of that
+ * umgs_blend call (the backward recovers the transmittance in front of every
+ * fragment from them instead of storing per-fragment state).  means are the
+ * means that were projected; the projected covariance must have been
+ * A Sigma(scales, quats) A^T with A = xform [device] (N,9) row-major, or
+ * Sigma(scales, quats) when xform is NULL (deformed scenes pass the A
+ * written by umgs_bind_transfer; the mean offset is constant, so the
+ * gradient of the rest mean equals that of the deformed mean).
+ * Outputs [device], written (not accumulated): dL_dmeans (N,3),
+ * dL_dscales (N,3) w.r.t. linear scales, dL_dquats (N,4) w.r.t. the raw
+ * quaternion before normalisation, dL_dopacity (N,), dL_dsh (N,(deg+1)^2,3).
+ * Triangles receive no gradients.  Float atomics make the summation order,
+ * hence the last bits, run-dependent.  Errors: STATE without a blended
+ * frame; UNSUPPORTED for UMGS_MODE_ONE_ENTITY and UMGS_MODE_LITERAL_T;
+ * INVALID_ARG for NULL arrays. */
+umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_final,
+                          const int32_t *n_contrib, const float *T_entity_in, const float *means,
+                          const float *scales, const float *quats, const float *xform,
+                          const float *sh, float *dL_dmeans, float *dL_dscales, float *dL_dquats,
+                          float *dL_dopacity, float *dL_dsh);
+
 /* Sizes of the current frame: n_dup (duplicates), n_tiles (all views), and
  * the record count V*(N+T).  Any pointer may be NULL.  Synchronous. */
 umgs_status umgs_query(umgs_ctx *ctx, int64_t *n_dup, int64_t *n_tiles, int64_t *n_records);
@@ -170,9 +195,12 @@ umgs_status umgs_query(umgs_ctx *ctx, int64_t *n_dup, int64_t *n_tiles, int64_t 
  *   UMGS_STATE_RANGES  n_tiles x 2 uint32 [start, end) per global tile
  *   UMGS_STATE_TRI_FIXED  V*T x 6 int32 snapped vertices (X0,X1,X2,Y0,Y1,Y2)
  *                         after orientation normalisation (0 when culled)
+ *   UMGS_STATE_GRAD2D  V*N x 9 float gradients of the last umgs_backward with
+ *                      respect to each projected Gaussian: mean (2), power
+ *                      coefficients of dx^2, dx dy, dy^2 (3), opacity, rgb (3)
  * cap_bytes must hold the whole array.  Errors: INVALID_ARG, STATE. */
 enum { UMGS_STATE_KEYS = 0, UMGS_STATE_SORTED_KEYS = 1, UMGS_STATE_SORTED_VALS = 2,
-       UMGS_STATE_RANGES = 3, UMGS_STATE_TRI_FIXED = 4 };
+       UMGS_STATE_RANGES = 3, UMGS_STATE_TRI_FIXED = 4, UMGS_STATE_GRAD2D = 5 };
 umgs_status umgs_copy_state(umgs_ctx *ctx, int32_t which, void *dst, int64_t cap_bytes);
 
 /* ---- kernel timing -------------------------------------------------------- */

@@ -15,7 +15,7 @@ UMGS_OK = 0
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "CAPACITY", -3: "HIP", -4: "STATE", -5: "UNSUPPORTED"}
 
 MODE_UNIMGS, MODE_DIRECT, MODE_ONE_ENTITY, MODE_LITERAL_T = 0, 1, 2, 3
-STATE_KEYS, STATE_SORTED_KEYS, STATE_SORTED_VALS, STATE_RANGES, STATE_TRI_FIXED = 0, 1, 2, 3, 4
+STATE_KEYS, STATE_SORTED_KEYS, STATE_SORTED_VALS, STATE_RANGES, STATE_TRI_FIXED, STATE_GRAD2D = 0, 1, 2, 3, 4, 5
 
 
 class Camera(C.Structure):
@@ -47,6 +47,7 @@ PROTOTYPES = {
     "umgs_blend": (C.c_int, [P, P, P, P, P]),
     "umgs_query": (C.c_int, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]),
     "umgs_copy_state": (C.c_int, [P, I32, P, I64]),
+    "umgs_backward": (C.c_int, [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]),
     "umgs_set_profiling": (C.c_int, [P, I32]),
     "umgs_profile_read": (C.c_int, [P, I32, C.POINTER(I64), C.POINTER(C.c_double)]),
 }

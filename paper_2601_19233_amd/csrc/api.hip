@@ -155,7 +155,7 @@ void umgs_destroy(umgs_ctx *ctx) {
   (void)hipStreamSynchronize(c->stream);
   DevBuf *bufs[] = {&c->V_rest, &c->faces, &c->vf_ptr, &c->vf_idx, &c->vtab, &c->d_views,
                     &c->keys, &c->rects, &c->counts, &c->grec, &c->trec, &c->scan_tmp,
-                    &c->k0, &c->k1, &c->v0, &c->v1, &c->hist, &c->ranges};
+                    &c->k0, &c->k1, &c->v0, &c->v1, &c->hist, &c->ranges, &c->g2d};
   for (DevBuf *b : bufs) free_buf(*b);
   for (auto &p : c->prof.pending) {
     (void)hipEventDestroy(p.a);
@@ -368,7 +368,33 @@ umgs_status umgs_blend(umgs_ctx *ctx, float *image, float *T_final, int32_t *n_c
   Ctx *c = &ctx->c;
   if (c->stage < 3) return fail(c, UMGS_ERR_STATE, "umgs_blend: frame not sorted");
   if (!image) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_blend: NULL image");
-  return hip_check(c, launch_blend(c, image, T_final, n_contrib, T_entity_in), "blend launch");
+  umgs_status s = hip_check(c, launch_blend(c, image, T_final, n_contrib, T_entity_in), "blend launch");
+  if (s == UMGS_OK) c->stage = 4;
+  return s;
+}
+
+umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_final,
+                          const int32_t *n_contrib, const float *T_entity_in, const float *means,
+                          const float *scales, const float *quats, const float *xform,
+                          const float *sh, float *dL_dmeans, float *dL_dscales, float *dL_dquats,
+                          float *dL_dopacity, float *dL_dsh) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->stage < 4) return fail(c, UMGS_ERR_STATE, "umgs_backward: no blended frame on this context");
+  if (c->mode != UMGS_MODE_UNIMGS && c->mode != UMGS_MODE_DIRECT)
+    return fail(c, UMGS_ERR_UNSUPPORTED, "umgs_backward: mode %d has no backward", c->mode);
+  if (!dL_dimage || !T_final || !n_contrib || !T_entity_in)
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_backward: NULL per-pixel array");
+  if (c->N > 0 && (!means || !scales || !quats || !sh || !dL_dmeans || !dL_dscales || !dL_dquats ||
+                   !dL_dopacity || !dL_dsh))
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_backward: NULL Gaussian array");
+  umgs_status s = ensure(c, c->g2d, sizeof(float) * 9 * std::max<int64_t>((int64_t)c->V * c->N, 1),
+                         "2D gradients");
+  if (s != UMGS_OK) return s;
+  return hip_check(c, launch_backward(c, dL_dimage, T_final, n_contrib, T_entity_in, means, scales,
+                                      quats, xform, sh, dL_dmeans, dL_dscales, dL_dquats,
+                                      dL_dopacity, dL_dsh),
+                   "backward launch");
 }
 
 umgs_status umgs_query(umgs_ctx *ctx, int64_t *n_dup, int64_t *n_tiles, int64_t *n_records) {
@@ -392,6 +418,7 @@ umgs_status umgs_copy_state(umgs_ctx *ctx, int32_t which, void *dst, int64_t cap
   switch (which) {
     case UMGS_STATE_KEYS: src = c->keys.p; bytes = 4 * c->n_records; need = 1; break;
     case UMGS_STATE_SORTED_KEYS: src = c->sorted_in ? c->k1.p : c->k0.p; bytes = 8 * (int64_t)c->n_dup; need = 3; break;
+    case UMGS_STATE_GRAD2D: src = c->g2d.p; bytes = 36 * (int64_t)c->V * c->N; need = 4; break;
     case UMGS_STATE_SORTED_VALS: src = c->sorted_in ? c->v1.p : c->v0.p; bytes = 4 * (int64_t)c->n_dup; need = 3; break;
     case UMGS_STATE_RANGES: src = c->ranges.p; bytes = 8 * c->n_tiles; need = 3; break;
     case UMGS_STATE_TRI_FIXED: src = c->trec.p; bytes = 24 * (int64_t)c->V * c->T; need = 1; break;

@@ -1,0 +1,502 @@
+// Backward pass of the single-pass rasterizer.
+//
+// blend_backward_kernel: one workgroup per tile, one thread per pixel,
+// walking the tile's sorted list from the pixel's last blended fragment
+// back to the front.  Every unit (a Gaussian, or a whole triangle entity)
+// acts on the pixel as C += T_before x contribution, T_after = T_before x m,
+// so going backwards the pixel keeps
+//   B  -- the colour behind the current unit, normalised by the
+//         transmittance in front of it (starts at the background);
+//   T  -- the transmittance in front of the current unit, recovered as
+//         T / (1 - alpha) for a Gaussian and T / tau for an entity, except
+//         for the last blended unit, whose front transmittance the forward
+//         stored (it may be opaque).
+// Gaussian k: dC/dc = T a, dC/da = T (c - B); then B = a c + (1 - a) B.
+// Triangle entity (Eq. 7-9), per sub-sample j in reverse:
+//   s^j = o^j a c + (1 - o^j a) s^j   (starting from B),
+//   p^j = (1 - o^j a) p^j             (starting from 1),
+// and when the entity closes B = mean_j s^j, tau = mean_j p^j.  Triangles
+// are fixed occluders: they pass gradients through T but receive none.
+// Per fragment the 9 gradient terms (mean 2D, the 3 power coefficients,
+// opacity, colour) are summed over the wave with shuffles, over the
+// workgroup's waves in LDS, then added once per tile with float atomics.
+//
+// project_backward_kernel: one thread per Gaussian, looping over views:
+// the chain rule back through the conic inverse, the EWA Jacobian (with the
+// frustum clamp), the pinhole projection, the SH colour and its view
+// direction, Sigma' = A Sigma A^T (when deformed) and Sigma = R S S R^T.
+#include "blend_common.h"
+
+namespace umgs {
+
+namespace {
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
+    const ViewParams *__restrict__ views, int V, int N, int T, int mode, int batch,
+    float bg0, float bg1, float bg2, const uint2 *__restrict__ ranges,
+    const uint32_t *__restrict__ vals, const GaussRec *__restrict__ grec,
+    const TriRec *__restrict__ trec, const float *__restrict__ dLdimg,
+    const float *__restrict__ Tfin, const int32_t *__restrict__ ncontrib,
+    const float *__restrict__ Tent, float *__restrict__ g2d) {
+  constexpr int NT = TW * TH;
+  extern __shared__ uint32_t smem[];
+  uint32_t *slots = smem;                                 // batch * kSlotWords
+  float *gl = (float *)(smem + batch * kSlotWords);       // batch * 9
+  __shared__ int smax;
+
+  const uint32_t tile = blockIdx.x;
+  const int v = find_view(views, V, tile);
+  const ViewParams &vp = views[v];
+  const uint32_t lt = tile - vp.tile_base;
+  const int tx = (int)(lt % (uint32_t)vp.ntx), ty = (int)(lt / (uint32_t)vp.ntx);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int lx = tid % TW, ly = tid / TW;
+  const int px = tx * TW + lx, py = ty * TH + ly;
+  const bool inside = px < vp.W && py < vp.H;
+  const float pcx = (float)px + 0.5f, pcy = (float)py + 0.5f;
+  const int64_t P0x = (int64_t)(tx * TW) * kSubpx + kSubpx / 2;
+  const int64_t P0y = (int64_t)(ty * TH) * kSubpx + kSubpx / 2;
+  const double rlx = (double)(lx * kSubpx), rly = (double)(ly * kSubpx);
+  const bool direct = mode == UMGS_MODE_DIRECT;
+  const uint2 rg = ranges[tile];
+  const int64_t rbase = (int64_t)v * (N + T);
+
+  const int64_t HW = (int64_t)vp.W * vp.H;
+  const int64_t pix = (int64_t)py * vp.W + px;
+  int last = 0;
+  float Tr = 1.0f, Tterm = 1.0f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
+  if (inside) {
+    last = ncontrib[vp.pix_base + pix];
+    Tr = Tfin[vp.pix_base + pix];
+    Tterm = Tent[vp.pix_base + pix];
+    const float *d = dLdimg + 3 * vp.pix_base;
+    dC0 = d[pix];
+    dC1 = d[HW + pix];
+    dC2 = d[2 * HW + pix];
+  }
+  if (tid == 0) smax = 0;
+  __syncthreads();
+  atomicMax(&smax, last);
+  __syncthreads();
+  const int max_last = smax;
+
+  float B0 = bg0, B1 = bg1, B2 = bg2;
+  bool in_ent = false, term_ent = false;
+  float s0[3], s1[3], s2[3], s3[3];
+  float p0 = 1.f, p1 = 1.f, p2 = 1.f, p3 = 1.f;
+
+  for (int bend = max_last; bend > 0; bend -= batch) {
+    const int bstart = max(0, bend - batch);
+    const int bn = bend - bstart;
+    for (int f = tid; f < bn; f += NT) {
+      uint32_t *s = slots + f * kSlotWords;
+      const int64_t local = (int64_t)vals[rg.x + bstart + f] - rbase;
+      if (local < N) {
+        const uint32_t rec = (uint32_t)((int64_t)v * N + local);
+        stage_gauss(s, grec[rec], rec);
+      } else {
+        stage_tri(s, trec[(int64_t)v * T + (local - N)], P0x, P0y);
+      }
+#pragma unroll
+      for (int k = 0; k < 9; ++k) gl[f * 9 + k] = 0.0f;
+    }
+    __syncthreads();
+
+    for (int f = bn - 1; f >= 0; --f) {
+      const uint32_t *s = slots + f * kSlotWords;
+      const int pos = bstart + f;
+      const bool mine = pos < last;
+      if (!__any(mine)) continue;
+      if ((s[31] & 1u) == 0u) {
+        float alpha = 0.f, G = 0.f, dx = 0.f, dy = 0.f;
+        const bool contrib = mine && gauss_eval(s, pcx, pcy, alpha, G, dx, dy);
+        float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (contrib) {
+          if (in_ent) {
+            B0 = 0.25f * ((s0[0] + s1[0]) + (s2[0] + s3[0]));
+            B1 = 0.25f * ((s0[1] + s1[1]) + (s2[1] + s3[1]));
+            B2 = 0.25f * ((s0[2] + s1[2]) + (s2[2] + s3[2]));
+            Tr = term_ent ? Tterm : Tr / (0.25f * ((p0 + p1) + (p2 + p3)));
+            in_ent = false;
+          }
+          const float Tb = (pos == last - 1) ? Tterm : Tr / (1.0f - alpha);
+          const float c0 = __uint_as_float(s[6]), c1 = __uint_as_float(s[7]), c2 = __uint_as_float(s[8]);
+          const float w = Tb * alpha;
+          g[6] = w * dC0;
+          g[7] = w * dC1;
+          g[8] = w * dC2;
+          const float dLda = Tb * ((c0 - B0) * dC0 + (c1 - B1) * dC1 + (c2 - B2) * dC2);
+          B0 = fmaf(alpha, c0 - B0, B0);
+          B1 = fmaf(alpha, c1 - B1, B1);
+          B2 = fmaf(alpha, c2 - B2, B2);
+          Tr = Tb;
+          const float op = __uint_as_float(s[5]);
+          if (op * G < kAlphaMax) {
+            const float qa = __uint_as_float(s[2]), qb = __uint_as_float(s[3]), qc = __uint_as_float(s[4]);
+            g[5] = G * dLda;
+            const float dp = alpha * dLda;     // d alpha / d power = o G = alpha
+            g[0] = dp * (2.0f * qa * dx + qb * dy);
+            g[1] = dp * (qb * dx + 2.0f * qc * dy);
+            g[2] = dp * dx * dx;
+            g[3] = dp * dx * dy;
+            g[4] = dp * dy * dy;
+          }
+        }
+        if (__any(contrib)) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) {
+            const float r = wave_sum(g[k]);
+            if (lane == 0 && r != 0.0f) atomicAdd(&gl[f * 9 + k], r);
+          }
+        }
+      } else {
+        double e[3];
+        float o[4];
+        const bool contrib = mine && tri_eval(s, rlx, rly, direct, e, o) > 0;
+        if (contrib) {
+          float cr, cg, cbl;
+          tri_colour(s, e, cr, cg, cbl);
+          const float alpha = __uint_as_float(s[30]);
+          if (direct) {
+            Tr = (pos == last - 1) ? Tterm : Tr / (1.0f - alpha);
+            B0 = fmaf(alpha, cr - B0, B0);
+            B1 = fmaf(alpha, cg - B1, B1);
+            B2 = fmaf(alpha, cbl - B2, B2);
+          } else {
+            if (!in_ent) {
+              in_ent = true;
+              term_ent = (pos == last - 1);
+              s0[0] = s1[0] = s2[0] = s3[0] = B0;
+              s0[1] = s1[1] = s2[1] = s3[1] = B1;
+              s0[2] = s1[2] = s2[2] = s3[2] = B2;
+              p0 = p1 = p2 = p3 = 1.0f;
+            }
+            const float a0 = o[0] * alpha, a1 = o[1] * alpha, a2 = o[2] * alpha, a3 = o[3] * alpha;
+            s0[0] = fmaf(a0, cr - s0[0], s0[0]); s0[1] = fmaf(a0, cg - s0[1], s0[1]); s0[2] = fmaf(a0, cbl - s0[2], s0[2]);
+            s1[0] = fmaf(a1, cr - s1[0], s1[0]); s1[1] = fmaf(a1, cg - s1[1], s1[1]); s1[2] = fmaf(a1, cbl - s1[2], s1[2]);
+            s2[0] = fmaf(a2, cr - s2[0], s2[0]); s2[1] = fmaf(a2, cg - s2[1], s2[1]); s2[2] = fmaf(a2, cbl - s2[2], s2[2]);
+            s3[0] = fmaf(a3, cr - s3[0], s3[0]); s3[1] = fmaf(a3, cg - s3[1], s3[1]); s3[2] = fmaf(a3, cbl - s3[2], s3[2]);
+            p0 *= 1.0f - a0; p1 *= 1.0f - a1; p2 *= 1.0f - a2; p3 *= 1.0f - a3;
+          }
+        }
+      }
+    }
+    __syncthreads();
+    for (int f = tid; f < bn; f += NT) {
+      const uint32_t *s = slots + f * kSlotWords;
+      if ((s[31] & 1u) != 0u) continue;
+      float *dst = g2d + 9 * (int64_t)s[9];
+#pragma unroll
+      for (int k = 0; k < 9; ++k) {
+        const float r = gl[f * 9 + k];
+        if (r != 0.0f) unsafeAtomicAdd(dst + k, r);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float view_row_c(const float *Rr, float t, float x, float y, float z) {
+#pragma clang fp contract(off)
+  return ((Rr[0] * x + Rr[1] * y) + Rr[2] * z) + t;
+}
+
+// Real SH basis values and gradients (w.r.t. the direction components) for
+// degree <= 3, same sign convention as the forward.
+__device__ void sh_basis_grad(int deg, float x, float y, float z, float *Bv, float *Bx, float *By, float *Bz) {
+  const float C0 = 0.28209479177387814f, C1 = 0.4886025119029199f;
+  Bv[0] = C0; Bx[0] = By[0] = Bz[0] = 0.f;
+  if (deg < 1) return;
+  Bv[1] = -C1 * y; Bx[1] = 0.f; By[1] = -C1; Bz[1] = 0.f;
+  Bv[2] = C1 * z; Bx[2] = 0.f; By[2] = 0.f; Bz[2] = C1;
+  Bv[3] = -C1 * x; Bx[3] = -C1; By[3] = 0.f; Bz[3] = 0.f;
+  if (deg < 2) return;
+  const float xx = x * x, yy = y * y, zz = z * z;
+  const float a0 = 1.0925484305920792f, a1 = -1.0925484305920792f, a2 = 0.31539156525252005f,
+              a3 = -1.0925484305920792f, a4 = 0.5462742152960396f;
+  Bv[4] = a0 * x * y; Bx[4] = a0 * y; By[4] = a0 * x; Bz[4] = 0.f;
+  Bv[5] = a1 * y * z; Bx[5] = 0.f; By[5] = a1 * z; Bz[5] = a1 * y;
+  Bv[6] = a2 * (2.f * zz - xx - yy); Bx[6] = -2.f * a2 * x; By[6] = -2.f * a2 * y; Bz[6] = 4.f * a2 * z;
+  Bv[7] = a3 * x * z; Bx[7] = a3 * z; By[7] = 0.f; Bz[7] = a3 * x;
+  Bv[8] = a4 * (xx - yy); Bx[8] = 2.f * a4 * x; By[8] = -2.f * a4 * y; Bz[8] = 0.f;
+  if (deg < 3) return;
+  const float b0 = -0.5900435899266435f, b1 = 2.890611442640554f, b2 = -0.4570457994644658f,
+              b3 = 0.3731763325901154f, b4 = -0.4570457994644658f, b5 = 1.445305721320277f,
+              b6 = -0.5900435899266435f;
+  Bv[9] = b0 * y * (3.f * xx - yy); Bx[9] = b0 * 6.f * x * y; By[9] = b0 * (3.f * xx - 3.f * yy); Bz[9] = 0.f;
+  Bv[10] = b1 * x * y * z; Bx[10] = b1 * y * z; By[10] = b1 * x * z; Bz[10] = b1 * x * y;
+  Bv[11] = b2 * y * (4.f * zz - xx - yy); Bx[11] = b2 * (-2.f * x * y);
+  By[11] = b2 * (4.f * zz - xx - 3.f * yy); Bz[11] = b2 * 8.f * y * z;
+  Bv[12] = b3 * z * (2.f * zz - 3.f * xx - 3.f * yy); Bx[12] = b3 * (-6.f * x * z);
+  By[12] = b3 * (-6.f * y * z); Bz[12] = b3 * (6.f * zz - 3.f * xx - 3.f * yy);
+  Bv[13] = b4 * x * (4.f * zz - xx - yy); Bx[13] = b4 * (4.f * zz - 3.f * xx - yy);
+  By[13] = b4 * (-2.f * x * y); Bz[13] = b4 * 8.f * x * z;
+  Bv[14] = b5 * z * (xx - yy); Bx[14] = b5 * 2.f * x * z; By[14] = b5 * (-2.f * y * z); Bz[14] = b5 * (xx - yy);
+  Bv[15] = b6 * x * (xx - 3.f * yy); Bx[15] = b6 * (3.f * xx - 3.f * yy); By[15] = b6 * (-6.f * x * y); Bz[15] = 0.f;
+}
+
+__global__ void project_backward_kernel(const ViewParams *__restrict__ views, int V, int N,
+                                        int sh_deg, const float *__restrict__ means,
+                                        const float *__restrict__ scales,
+                                        const float *__restrict__ quats,
+                                        const float *__restrict__ xform,
+                                        const float *__restrict__ sh,
+                                        const float *__restrict__ g2d,
+                                        float *__restrict__ d_means, float *__restrict__ d_scales,
+                                        float *__restrict__ d_quats, float *__restrict__ d_opac,
+                                        float *__restrict__ d_sh) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const int nc = (sh_deg + 1) * (sh_deg + 1);
+  const float mx_w = means[3 * i], my_w = means[3 * i + 1], mz_w = means[3 * i + 2];
+  // Sigma = M M^T, M = R(q) diag(s); deformed: Sigma' = A Sigma A^T
+  float qw = quats[4 * i], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
+  const float qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+  const float iq = 1.0f / qn;
+  qw *= iq; qx *= iq; qy *= iq; qz *= iq;
+  const float Rq[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
+                       2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
+                       2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
+  const float sc[3] = {scales[3 * i], scales[3 * i + 1], scales[3 * i + 2]};
+  float M[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) M[3 * r + c] = Rq[3 * r + c] * sc[c];
+  float Sg[9];   // Sigma (full 3x3)
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Sg[3 * r + c] = M[3 * r] * M[3 * c] + M[3 * r + 1] * M[3 * c + 1] + M[3 * r + 2] * M[3 * c + 2];
+  float A[9];
+  float Sp[9];   // Sigma' used by the projection
+  if (xform) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) A[k] = xform[9 * (int64_t)i + k];
+    float AS[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) AS[3 * r + c] = A[3 * r] * Sg[c] + A[3 * r + 1] * Sg[3 + c] + A[3 * r + 2] * Sg[6 + c];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Sp[3 * r + c] = AS[3 * r] * A[3 * c] + AS[3 * r + 1] * A[3 * c + 1] + AS[3 * r + 2] * A[3 * c + 2];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Sp[k] = Sg[k];
+  }
+
+  float dmu[3] = {0.f, 0.f, 0.f};
+  float dSp[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float dop = 0.f;
+  float dshv[16 * 3];
+  for (int k = 0; k < nc * 3; ++k) dshv[k] = 0.f;
+  const float *shi = sh + (int64_t)i * nc * 3;
+
+  for (int v = 0; v < V; ++v) {
+    const float *g = g2d + 9 * ((int64_t)v * N + i);
+    float gg[9];
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) { gg[k] = g[k]; any = any || gg[k] != 0.0f; }
+    if (!any) continue;
+    const ViewParams &vp = views[v];
+    const float *W = vp.R;
+    const float x = view_row_c(W, vp.t[0], mx_w, my_w, mz_w);
+    const float y = view_row_c(W + 3, vp.t[1], mx_w, my_w, mz_w);
+    const float z = view_row_c(W + 6, vp.t[2], mx_w, my_w, mz_w);
+    const float iz = 1.0f / z, iz2 = iz * iz;
+    const float limx = kFrustumClamp * vp.tanx, limy = kFrustumClamp * vp.tany;
+    const float xz = x * iz, yz = y * iz;
+    const bool clx = xz < -limx || xz > limx, cly = yz < -limy || yz > limy;
+    const float txz = fminf(limx, fmaxf(-limx, xz)), tyz = fminf(limy, fmaxf(-limy, yz));
+    const float J00 = vp.fx * iz, J02 = -vp.fx * txz * iz, J11 = vp.fy * iz, J12 = -vp.fy * tyz * iz;
+    float Tm[6];   // T = J W (2x3)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Tm[k] = J00 * W[k] + J02 * W[6 + k];
+      Tm[3 + k] = J11 * W[3 + k] + J12 * W[6 + k];
+    }
+    float TS[6];   // T Sigma'
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) TS[3 * r + c] = Tm[3 * r] * Sp[c] + Tm[3 * r + 1] * Sp[3 + c] + Tm[3 * r + 2] * Sp[6 + c];
+    const float a = TS[0] * Tm[0] + TS[1] * Tm[1] + TS[2] * Tm[2] + kDilation;
+    const float b = TS[0] * Tm[3] + TS[1] * Tm[4] + TS[2] * Tm[5];
+    const float c = TS[3] * Tm[3] + TS[4] * Tm[4] + TS[5] * Tm[5] + kDilation;
+    const float idet = 1.0f / (a * c - b * b);
+    const float KA = c * idet, KB = -b * idet, KC = a * idet;   // conic
+    // dL/dconic (the power coefficients are -A/2, -B, -C/2)
+    const float gA = -0.5f * gg[2], gB = -gg[3], gC = -0.5f * gg[4];
+    // S = -K G K with G = [[gA, gB/2], [gB/2, gC]]
+    const float G01 = 0.5f * gB;
+    const float KG00 = KA * gA + KB * G01, KG01 = KA * G01 + KB * gC;
+    const float KG10 = KB * gA + KC * G01, KG11 = KB * G01 + KC * gC;
+    const float S00 = -(KG00 * KA + KG01 * KB);
+    const float S01 = -(KG00 * KB + KG01 * KC);
+    const float S11 = -(KG10 * KB + KG11 * KC);
+    // dL/dSigma' += T^T S T
+    float ST[6];   // S T (2x3)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      ST[k] = S00 * Tm[k] + S01 * Tm[3 + k];
+      ST[3 + k] = S01 * Tm[k] + S11 * Tm[3 + k];
+    }
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc) dSp[3 * r + cc] += Tm[r] * ST[cc] + Tm[3 + r] * ST[3 + cc];
+    // dL/dT = 2 S T Sigma'
+    float dT[6];
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+#pragma unroll
+      for (int cc = 0; cc < 3; ++cc)
+        dT[3 * r + cc] = 2.0f * (ST[3 * r] * Sp[cc] + ST[3 * r + 1] * Sp[3 + cc] + ST[3 * r + 2] * Sp[6 + cc]);
+    // dL/dJ = dL/dT W^T (only the non-constant entries)
+    const float dJ00 = dT[0] * W[0] + dT[1] * W[1] + dT[2] * W[2];
+    const float dJ02 = dT[0] * W[6] + dT[1] * W[7] + dT[2] * W[8];
+    const float dJ11 = dT[3] * W[3] + dT[4] * W[4] + dT[5] * W[5];
+    const float dJ12 = dT[3] * W[6] + dT[4] * W[7] + dT[5] * W[8];
+    float dpx = gg[0] * vp.fx * iz;
+    float dpy = gg[1] * vp.fy * iz;
+    float dpz = -gg[0] * vp.fx * x * iz2 - gg[1] * vp.fy * y * iz2;
+    dpz += -dJ00 * vp.fx * iz2 - dJ11 * vp.fy * iz2;
+    if (!clx) { dpx += -dJ02 * vp.fx * iz2; dpz += dJ02 * 2.0f * vp.fx * x * iz2 * iz; }
+    else { dpz += dJ02 * vp.fx * txz * iz2; }
+    if (!cly) { dpy += -dJ12 * vp.fy * iz2; dpz += dJ12 * 2.0f * vp.fy * y * iz2 * iz; }
+    else { dpz += dJ12 * vp.fy * tyz * iz2; }
+    dmu[0] += W[0] * dpx + W[3] * dpy + W[6] * dpz;
+    dmu[1] += W[1] * dpx + W[4] * dpy + W[7] * dpz;
+    dmu[2] += W[2] * dpx + W[5] * dpy + W[8] * dpz;
+    dop += gg[5];
+    // colour: rgb = max(0, sum_k B_k(d) sh_k + 0.5), d = (mu - camera centre) / |.|
+    const float ccx = -(W[0] * vp.t[0] + W[3] * vp.t[1] + W[6] * vp.t[2]);
+    const float ccy = -(W[1] * vp.t[0] + W[4] * vp.t[1] + W[7] * vp.t[2]);
+    const float ccz = -(W[2] * vp.t[0] + W[5] * vp.t[1] + W[8] * vp.t[2]);
+    float ddx = mx_w - ccx, ddy = my_w - ccy, ddz = mz_w - ccz;
+    const float dl = sqrtf(ddx * ddx + ddy * ddy + ddz * ddz), idl = 1.0f / dl;
+    ddx *= idl; ddy *= idl; ddz *= idl;
+    float Bv[16], Bx[16], By[16], Bz[16];
+    sh_basis_grad(sh_deg, ddx, ddy, ddz, Bv, Bx, By, Bz);
+    float gdx = 0.f, gdy = 0.f, gdz = 0.f;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      float raw = 0.5f;
+      for (int k = 0; k < nc; ++k) raw += Bv[k] * shi[3 * k + ch];
+      if (!(raw > 0.0f)) continue;
+      const float gc = gg[6 + ch];
+      for (int k = 0; k < nc; ++k) {
+        dshv[3 * k + ch] += Bv[k] * gc;
+        const float sk = shi[3 * k + ch] * gc;
+        gdx += Bx[k] * sk; gdy += By[k] * sk; gdz += Bz[k] * sk;
+      }
+    }
+    const float dd = ddx * gdx + ddy * gdy + ddz * gdz;
+    dmu[0] += (gdx - ddx * dd) * idl;
+    dmu[1] += (gdy - ddy * dd) * idl;
+    dmu[2] += (gdz - ddz * dd) * idl;
+  }
+
+  // Sigma' -> Sigma
+  float dS[9];
+  if (xform) {
+    float AtG[9];   // A^T dSp
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) AtG[3 * r + c] = A[r] * dSp[c] + A[3 + r] * dSp[3 + c] + A[6 + r] * dSp[6 + c];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) dS[3 * r + c] = AtG[3 * r] * A[c] + AtG[3 * r + 1] * A[3 + c] + AtG[3 * r + 2] * A[6 + c];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) dS[k] = dSp[k];
+  }
+  // Sigma = M M^T: dL/dM = (dS + dS^T) M
+  float dM[9];
+#pragma unroll
+  for (int r = 0; r < 3; ++r)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      float acc = 0.f;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) acc += (dS[3 * r + k] + dS[3 * k + r]) * M[3 * k + c];
+      dM[3 * r + c] = acc;
+    }
+  float gR[9];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    d_scales[3 * (int64_t)i + c] = dM[c] * Rq[c] + dM[3 + c] * Rq[3 + c] + dM[6 + c] * Rq[6 + c];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) gR[3 * r + c] = dM[3 * r + c] * sc[c];
+  }
+  float gw = 2.f * (-qz * gR[1] + qy * gR[2] + qz * gR[3] - qx * gR[5] - qy * gR[6] + qx * gR[7]);
+  float gx = 2.f * (qy * gR[1] + qz * gR[2] + qy * gR[3] - 2.f * qx * gR[4] - qw * gR[5] + qz * gR[6] + qw * gR[7] - 2.f * qx * gR[8]);
+  float gy = 2.f * (-2.f * qy * gR[0] + qx * gR[1] + qw * gR[2] + qx * gR[3] + qz * gR[5] - qw * gR[6] + qz * gR[7] - 2.f * qy * gR[8]);
+  float gz = 2.f * (-2.f * qz * gR[0] - qw * gR[1] + qx * gR[2] + qw * gR[3] - 2.f * qz * gR[4] + qy * gR[5] + qx * gR[6] + qy * gR[7]);
+  // through the normalisation q_hat = q / |q|
+  const float pr = qw * gw + qx * gx + qy * gy + qz * gz;
+  d_quats[4 * (int64_t)i] = (gw - qw * pr) * iq;
+  d_quats[4 * (int64_t)i + 1] = (gx - qx * pr) * iq;
+  d_quats[4 * (int64_t)i + 2] = (gy - qy * pr) * iq;
+  d_quats[4 * (int64_t)i + 3] = (gz - qz * pr) * iq;
+  d_means[3 * (int64_t)i] = dmu[0];
+  d_means[3 * (int64_t)i + 1] = dmu[1];
+  d_means[3 * (int64_t)i + 2] = dmu[2];
+  d_opac[i] = dop;
+  for (int k = 0; k < nc * 3; ++k) d_sh[(int64_t)i * nc * 3 + k] = dshv[k];
+}
+
+template <int TW, int TH>
+hipError_t launch_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int32_t *nc, const float *Te) {
+  const size_t lds = (size_t)c->frag_batch * (kSlotWords + 9) * sizeof(uint32_t);
+  const uint32_t *vals = (const uint32_t *)(c->sorted_in ? c->v1.p : c->v0.p);
+  ScopedTimer t(c, K_BLEND_BWD);
+  hipLaunchKernelGGL((blend_backward_kernel<TW, TH>), dim3((unsigned)c->n_tiles), dim3(TW * TH), lds,
+                     c->stream, (const ViewParams *)c->d_views.p, c->V, c->N, c->T, c->mode,
+                     c->frag_batch, c->bg[0], c->bg[1], c->bg[2], (const uint2 *)c->ranges.p, vals,
+                     (const GaussRec *)c->grec.p, (const TriRec *)c->trec.p, dL, Tf, nc, Te,
+                     (float *)c->g2d.p);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v);
+
+hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32_t *nc,
+                           const float *Te, const float *means, const float *scales,
+                           const float *quats, const float *xform, const float *sh,
+                           float *d_means, float *d_scales, float *d_quats, float *d_opac,
+                           float *d_sh) {
+  hipError_t e = launch_fill_u32(c, (uint32_t *)c->g2d.p, 9 * (int64_t)c->V * c->N, 0u);
+  if (e != hipSuccess) return e;
+  if (c->n_tiles > 0) {
+    if (c->tile_w == 16 && c->tile_h == 16) e = launch_bwd_tw<16, 16>(c, dL, Tf, nc, Te);
+    else if (c->tile_w == 8 && c->tile_h == 8) e = launch_bwd_tw<8, 8>(c, dL, Tf, nc, Te);
+    else e = launch_bwd_tw<32, 8>(c, dL, Tf, nc, Te);
+    if (e != hipSuccess) return e;
+  }
+  if (c->N == 0) return hipSuccess;
+  ScopedTimer t(c, K_PROJECT_BWD);
+  hipLaunchKernelGGL(project_backward_kernel, dim3(ceil_div(c->N, 128)), dim3(128), 0, c->stream,
+                     (const ViewParams *)c->d_views.p, c->V, c->N, c->sh_degree, means, scales,
+                     quats, xform, sh, (const float *)c->g2d.p, d_means, d_scales, d_quats, d_opac,
+                     d_sh);
+  return hipGetLastError();
+}
+
+}  // namespace umgs

@@ -17,26 +17,11 @@
 // Edge functions E = dx (Py - Ya) - dy (Px - Xa) are integers in 1/256-px
 // units below 2^52 in magnitude; they are evaluated in FP64, which holds
 // them exactly (CDNA executes FP64 FMA at full vector rate).
-#include "internal.h"
+#include "blend_common.h"
 
 namespace umgs {
 
 namespace {
-
-constexpr int kSlotWords = 32;   // 128 B per staged fragment
-
-// rotated-grid sample offsets from the pixel centre, 1/256 px
-__constant__ int kSampleOX[4] = {-32, 96, -96, 32};
-__constant__ int kSampleOY[4] = {-96, -32, 32, 96};
-
-__device__ __forceinline__ int find_view(const ViewParams *views, int V, uint32_t tile) {
-  int lo = 0, hi = V - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (views[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
 
 template <int TW, int TH>
 __global__ __launch_bounds__(TW *TH) void blend_kernel(
@@ -62,10 +47,10 @@ __global__ __launch_bounds__(TW *TH) void blend_kernel(
   const int64_t P0x = (int64_t)(tx * TW) * kSubpx + kSubpx / 2;
   const int64_t P0y = (int64_t)(ty * TH) * kSubpx + kSubpx / 2;
   const double rlx = (double)(lx * kSubpx), rly = (double)(ly * kSubpx);
+  const bool direct = mode == UMGS_MODE_DIRECT;
 
   const uint2 rg = ranges[tile];
-  const int per_view = N + T;
-  const int64_t rbase = (int64_t)v * per_view;
+  const int64_t rbase = (int64_t)v * (N + T);
 
   float C0 = 0.f, C1 = 0.f, C2 = 0.f;
   float Tr = 1.0f, Tin = 1.0f, Tent = 1.0f;
@@ -81,32 +66,10 @@ __global__ __launch_bounds__(TW *TH) void blend_kernel(
       uint32_t *s = slots + f * kSlotWords;
       const int64_t local = (int64_t)vals[bstart + f] - rbase;
       if (local < N) {
-        const GaussRec g = grec[(int64_t)v * N + local];
-        const float4 a = make_float4(g.mx, g.my, g.qa, g.qb);
-        const float4 b = make_float4(g.qc, g.opacity, g.r, g.g);
-        *(float4 *)(s + 0) = a;
-        *(float4 *)(s + 4) = b;
-        s[8] = __float_as_uint(g.b);
-        s[31] = 0u;
+        const uint32_t rec = (uint32_t)((int64_t)v * N + local);
+        stage_gauss(s, grec[rec], rec);
       } else {
-        const TriRec tr = trec[(int64_t)v * T + (local - N)];
-        const int ea[3] = {1, 2, 0}, eb[3] = {2, 0, 1};
-        double *dv = (double *)s;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const int64_t dx = (int64_t)tr.X[eb[k]] - tr.X[ea[k]];
-          const int64_t dy = (int64_t)tr.Y[eb[k]] - tr.Y[ea[k]];
-          const int64_t E0 = dx * (P0y - tr.Y[ea[k]]) - dy * (P0x - tr.X[ea[k]]);
-          dv[k] = (double)E0;
-          dv[3 + k] = 96.0 * (double)((dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy));
-          s[12 + k] = (uint32_t)(int32_t)dx;
-          s[15 + k] = (uint32_t)(int32_t)dy;
-          s[18 + k] = __float_as_uint(tr.iz[k]);
-        }
-#pragma unroll
-        for (int k = 0; k < 9; ++k) s[21 + k] = __float_as_uint(tr.ciz[k]);
-        s[30] = __float_as_uint(tr.alpha);
-        s[31] = 1u | (tr.owned << 8);
+        stage_tri(s, trec[(int64_t)v * T + (local - N)], P0x, P0y);
       }
     }
     __syncthreads();
@@ -118,82 +81,30 @@ __global__ __launch_bounds__(TW *TH) void blend_kernel(
         const uint32_t *s = slots + f * kSlotWords;
         const uint32_t tag = s[31];
         if (done) continue;
+        const int32_t pos = (int32_t)(bstart - rg.x + f + 1);
         if ((tag & 1u) == 0u) {
-          const float4 a = *(const float4 *)(s + 0);
-          const float4 b = *(const float4 *)(s + 4);
-          const float dx = a.x - pcx, dy = a.y - pcy;
-          const float power = a.z * dx * dx + a.w * dx * dy + b.x * dy * dy;
-          if (power > 0.0f) continue;
-          const float alpha = fminf(kAlphaMax, b.y * __expf(power));
-          if (alpha < kAlphaMin) continue;
+          float alpha, G, dx, dy;
+          if (!gauss_eval(s, pcx, pcy, alpha, G, dx, dy)) continue;
           const float test_T = Tr * (1.0f - alpha);
           if (test_T < kTStop) { done = true; continue; }
           const float w = Tr * alpha;
-          C0 += w * b.z;
-          C1 += w * b.w;
-          C2 += w * __uint_as_float(s[8]);
+          C0 = fmaf(w, __uint_as_float(s[6]), C0);
+          C1 = fmaf(w, __uint_as_float(s[7]), C1);
+          C2 = fmaf(w, __uint_as_float(s[8]), C2);
           Tent = Tr;
           Tr = test_T;
           if (mode != UMGS_MODE_ONE_ENTITY) in_entity = false;
-          last = (int32_t)(bstart - rg.x + f + 1);
+          last = pos;
         } else {
-          const double *dv = (const double *)s;
-          const uint32_t owned = tag >> 8;
           double e[3];
-          bool any = true;
-          bool full = true;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const double dxk = (double)(int32_t)s[12 + k];
-            const double dyk = (double)(int32_t)s[15 + k];
-            e[k] = fma(dxk, rly, fma(-dyk, rlx, dv[k]));
-            const double own = (double)((owned >> k) & 1u);
-            any = any && (e[k] + dv[3 + k] + own > 0.0);
-            full = full && (e[k] - dv[3 + k] > 0.0);
-          }
-          if (!any) continue;
           float o[4];
-          if (mode == UMGS_MODE_DIRECT) {
-            bool c = true;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) c = c && (e[k] + (double)((owned >> k) & 1u) > 0.0);
-            if (!c) continue;
-          } else if (full) {
-            o[0] = o[1] = o[2] = o[3] = 1.0f;
-          } else {
-            bool anyc = false;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              bool c = true;
-#pragma unroll
-              for (int k = 0; k < 3; ++k) {
-                const double dxk = (double)(int32_t)s[12 + k];
-                const double dyk = (double)(int32_t)s[15 + k];
-                const double ej = fma(dxk, (double)kSampleOY[j], fma(-dyk, (double)kSampleOX[j], e[k]));
-                c = c && (ej + (double)((owned >> k) & 1u) > 0.0);
-              }
-              o[j] = c ? 1.0f : 0.0f;
-              anyc = anyc || c;
-            }
-            if (!anyc) continue;
-          }
-          // perspective-correct colour at the pixel centre (clamped barycentrics)
-          const float b0 = fmaxf((float)e[0], 0.0f), b1 = fmaxf((float)e[1], 0.0f),
-                      b2 = fmaxf((float)e[2], 0.0f);
-          const float iz0 = __uint_as_float(s[18]), iz1 = __uint_as_float(s[19]),
-                      iz2 = __uint_as_float(s[20]);
-          const float den = 1.0f / (b0 * iz0 + b1 * iz1 + b2 * iz2);
-          const float cr = (b0 * __uint_as_float(s[21]) + b1 * __uint_as_float(s[24]) +
-                            b2 * __uint_as_float(s[27])) * den;
-          const float cg = (b0 * __uint_as_float(s[22]) + b1 * __uint_as_float(s[25]) +
-                            b2 * __uint_as_float(s[28])) * den;
-          const float cbl = (b0 * __uint_as_float(s[23]) + b1 * __uint_as_float(s[26]) +
-                             b2 * __uint_as_float(s[29])) * den;
+          if (tri_eval(s, rlx, rly, direct, e, o) == 0) continue;
+          float cr, cg, cbl;
+          tri_colour(s, e, cr, cg, cbl);
           const float alpha = __uint_as_float(s[30]);
-          const int32_t pos = (int32_t)(bstart - rg.x + f + 1);
-          if (mode == UMGS_MODE_DIRECT) {
+          if (direct) {
             const float w = Tr * alpha;
-            C0 += w * cr; C1 += w * cg; C2 += w * cbl;
+            C0 = fmaf(w, cr, C0); C1 = fmaf(w, cg, C1); C2 = fmaf(w, cbl, C2);
             Tent = Tr;
             Tr = Tr * (1.0f - alpha);
             last = pos;
@@ -208,7 +119,7 @@ __global__ __launch_bounds__(TW *TH) void blend_kernel(
           }
           const float O = 0.25f * (o[0] * t0 + o[1] * t1 + o[2] * t2 + o[3] * t3);
           const float w = Tin * O * alpha;
-          C0 += w * cr; C1 += w * cg; C2 += w * cbl;
+          C0 = fmaf(w, cr, C0); C1 = fmaf(w, cg, C1); C2 = fmaf(w, cbl, C2);
           if (mode == UMGS_MODE_LITERAL_T) Tr = Tr * (1.0f - O * alpha);
           t0 *= 1.0f - o[0] * alpha;
           t1 *= 1.0f - o[1] * alpha;

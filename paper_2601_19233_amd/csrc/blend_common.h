@@ -1,0 +1,136 @@
+// Per-fragment evaluation shared by the forward and backward blend kernels.
+// Both kernels must take identical discrete decisions (contributes or not,
+// sub-sample coverage), so the arithmetic is written with explicit fmaf and
+// lives in one place.
+#pragma once
+
+#include "internal.h"
+
+namespace umgs {
+
+constexpr int kSlotWords = 32;   // one staged fragment: 128 B of LDS
+
+// Slot layout (32-bit words)
+//   Gaussian: 0 mx, 1 my, 2 qa, 3 qb, 4 qc, 5 opacity, 6 r, 7 g, 8 b,
+//             9 record index (view * N + i), 31 tag = 0
+//   triangle: 0-5 E0[3] (FP64 edge functions at the tile's first pixel
+//             centre), 6-11 dmax[3] (FP64, max |offset term| over samples),
+//             12-14 dx[3], 15-17 dy[3] (int32), 18-20 1/z, 21-29 colour/z,
+//             30 alpha, 31 tag = 1 | owned << 8
+
+// rotated-grid sample offsets from the pixel centre, 1/256 px
+__device__ __forceinline__ int sample_ox(int j) { return j == 0 ? -32 : j == 1 ? 96 : j == 2 ? -96 : 32; }
+__device__ __forceinline__ int sample_oy(int j) { return j == 0 ? -96 : j == 1 ? -32 : j == 2 ? 32 : 96; }
+
+__device__ __forceinline__ void stage_gauss(uint32_t *s, const GaussRec &g, uint32_t rec) {
+  *(float4 *)(s + 0) = make_float4(g.mx, g.my, g.qa, g.qb);
+  *(float4 *)(s + 4) = make_float4(g.qc, g.opacity, g.r, g.g);
+  s[8] = __float_as_uint(g.b);
+  s[9] = rec;
+  s[31] = 0u;
+}
+
+__device__ __forceinline__ void stage_tri(uint32_t *s, const TriRec &tr, int64_t P0x, int64_t P0y) {
+  const int ea[3] = {1, 2, 0}, eb[3] = {2, 0, 1};
+  double *dv = (double *)s;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int64_t dx = (int64_t)tr.X[eb[k]] - tr.X[ea[k]];
+    const int64_t dy = (int64_t)tr.Y[eb[k]] - tr.Y[ea[k]];
+    const int64_t E0 = dx * (P0y - tr.Y[ea[k]]) - dy * (P0x - tr.X[ea[k]]);
+    dv[k] = (double)E0;
+    dv[3 + k] = 96.0 * (double)((dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy));
+    s[12 + k] = (uint32_t)(int32_t)dx;
+    s[15 + k] = (uint32_t)(int32_t)dy;
+    s[18 + k] = __float_as_uint(tr.iz[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < 9; ++k) s[21 + k] = __float_as_uint(tr.ciz[k]);
+  s[30] = __float_as_uint(tr.alpha);
+  s[31] = 1u | (tr.owned << 8);
+}
+
+// Gaussian: power and alpha at the pixel centre.  Returns whether the
+// fragment contributes (power <= 0 and alpha >= 1/255).
+__device__ __forceinline__ bool gauss_eval(const uint32_t *s, float pcx, float pcy, float &alpha,
+                                           float &G, float &dx, float &dy) {
+  const float4 a = *(const float4 *)(s + 0);
+  const float4 b = *(const float4 *)(s + 4);
+  dx = a.x - pcx;
+  dy = a.y - pcy;
+  const float power = fmaf(a.z, dx * dx, fmaf(a.w, dx * dy, b.x * (dy * dy)));
+  if (power > 0.0f) return false;
+  G = __expf(power);
+  alpha = fminf(kAlphaMax, b.y * G);
+  return alpha >= kAlphaMin;
+}
+
+// Triangle: edge functions at the pixel centre (exact) and sub-sample
+// coverage.  Returns the number of covered samples (0: not a fragment of
+// this pixel).  In direct mode only the pixel centre is tested and o[] is 1.
+__device__ __forceinline__ int tri_eval(const uint32_t *s, double rlx, double rly, bool direct,
+                                        double e[3], float o[4]) {
+  const double *dv = (const double *)s;
+  const uint32_t owned = s[31] >> 8;
+  bool any = true, full = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double dxk = (double)(int32_t)s[12 + k];
+    const double dyk = (double)(int32_t)s[15 + k];
+    e[k] = fma(dxk, rly, fma(-dyk, rlx, dv[k]));
+    const double own = (double)((owned >> k) & 1u);
+    any = any && (e[k] + dv[3 + k] + own > 0.0);
+    full = full && (e[k] - dv[3 + k] > 0.0);
+  }
+  if (!any) return 0;
+  if (direct) {
+    bool c = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) c = c && (e[k] + (double)((owned >> k) & 1u) > 0.0);
+    o[0] = o[1] = o[2] = o[3] = 1.0f;
+    return c ? 4 : 0;
+  }
+  if (full) {
+    o[0] = o[1] = o[2] = o[3] = 1.0f;
+    return 4;
+  }
+  int n = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    bool c = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double dxk = (double)(int32_t)s[12 + k];
+      const double dyk = (double)(int32_t)s[15 + k];
+      const double ej = fma(dxk, (double)sample_oy(j), fma(-dyk, (double)sample_ox(j), e[k]));
+      c = c && (ej + (double)((owned >> k) & 1u) > 0.0);
+    }
+    o[j] = c ? 1.0f : 0.0f;
+    n += c;
+  }
+  return n;
+}
+
+// Perspective-correct colour at the pixel centre from the (clamped)
+// barycentric edge functions.
+__device__ __forceinline__ void tri_colour(const uint32_t *s, const double e[3], float &cr,
+                                           float &cg, float &cb) {
+  const float b0 = fmaxf((float)e[0], 0.0f), b1 = fmaxf((float)e[1], 0.0f),
+              b2 = fmaxf((float)e[2], 0.0f);
+  const float iz0 = __uint_as_float(s[18]), iz1 = __uint_as_float(s[19]), iz2 = __uint_as_float(s[20]);
+  const float den = 1.0f / (b0 * iz0 + b1 * iz1 + b2 * iz2);
+  cr = (b0 * __uint_as_float(s[21]) + b1 * __uint_as_float(s[24]) + b2 * __uint_as_float(s[27])) * den;
+  cg = (b0 * __uint_as_float(s[22]) + b1 * __uint_as_float(s[25]) + b2 * __uint_as_float(s[28])) * den;
+  cb = (b0 * __uint_as_float(s[23]) + b1 * __uint_as_float(s[26]) + b2 * __uint_as_float(s[29])) * den;
+}
+
+__device__ __forceinline__ int find_view(const ViewParams *views, int V, uint32_t tile) {
+  int lo = 0, hi = V - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (views[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+}  // namespace umgs

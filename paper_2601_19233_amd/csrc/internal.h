@@ -88,7 +88,7 @@ struct Ctx {
   DevBuf V_rest, faces, vf_ptr, vf_idx, vtab;
 
   // per-frame state
-  int stage = 0;         // 0 none, 1 projected, 2 binned, 3 sorted
+  int stage = 0;         // 0 none, 1 projected, 2 binned, 3 sorted, 4 blended
   int32_t V = 0, N = 0, T = 0;
   int32_t tile_w = 16, tile_h = 16, frag_batch = 128, mode = 0, sh_degree = 0;
   float bg[3] = {0, 0, 0};
@@ -110,6 +110,7 @@ struct Ctx {
   DevBuf v0, v1;       // n_dup uint32 values
   DevBuf hist;         // radix per-block histograms
   DevBuf ranges;       // n_tiles uint2
+  DevBuf g2d;          // V*N x 9 per-view 2D gradients (backward)
   DevBuf host_pinned;  // not a device buffer: pinned host scratch for small readbacks
   int sorted_in = 0;   // which ping-pong buffer holds the sorted result
   Prof prof;
@@ -144,6 +145,11 @@ size_t radix_hist_bytes(uint64_t n);
 hipError_t launch_tile_ranges(Ctx *c);
 hipError_t launch_blend(Ctx *c, float *image, float *T_final, int32_t *n_contrib,
                         float *T_entity_in);
+hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32_t *nc,
+                           const float *Te, const float *means, const float *scales,
+                           const float *quats, const float *xform, const float *sh,
+                           float *d_means, float *d_scales, float *d_quats, float *d_opac,
+                           float *d_sh);
 hipError_t launch_transfer(Ctx *c, const float *V_def, int32_t N, const int32_t *bind_face,
                            const float *bind_bary, const float *means, const float *quats,
                            const float *scales, float *means_out, float *quats_out,
