@@ -8,6 +8,11 @@ per-vertex proxy transforms and per-Gaussian deformation transfer, Gaussian
 projection and triangle set-up, binning, the (tile, depth) radix sort and the
 front-to-back blend.  Inputs are resident in device memory before timing.
 
+Also measured on the same scene: the forward+backward step (gradients to
+every Gaussian parameter through the deformation), and the batched form --
+16 orbit views at 1920x1080 in one captured graph per step, blend launch
+autotuned -- against rendering the same 16 views one by one.
+
 Prints ONE JSON line (metric, value = forward Mpixels/s, roofline of the
 dominant kernel measured live with HIP events, CPU-oracle baseline).
 """
@@ -30,6 +35,13 @@ HBM_PEAK_GBS = 8000.0
 # VALU lane-instructions per second with packed FP32 disabled:
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
+# VALU lane-operations per evaluated (pixel, fragment) pair of the blend:
+# a Gaussian costs 14 to evaluate alpha (2 sub, 4 mul, 2 fma, exp with its
+# scale, min, 2 compares) and 7 more when it is blended; a triangle about 60
+# (FP64 edge functions with the quick reject/accept tests, the per-sample
+# tests when the pixel straddles an edge, colour and the entity update).
+OPS_PER_GAUSS_PAIR = 20
+OPS_PER_TRI_PAIR = 60
 
 
 def log(msg):
@@ -64,6 +76,83 @@ def cpu_baseline(scene, budget_pixels=400, seed=0):
                       f"extrapolated to {cam.width}x{cam.height}: {full:.0f} s per frame"}
 
 
+def run_batched(scene, args, deform, sc):
+    """16 orbit views at 1080p of the same scene: one captured graph per step
+    (autotuned blend launch) vs rendering the views one by one (eager)."""
+    import torch
+    from paper_2601_19233_amd import autotune, scenes
+    from paper_2601_19233_amd.batched import BatchedStep
+    from paper_2601_19233_amd.render import Rasterizer
+    V = args.batched_views
+    W = max(1, int(round(1920 * args.res_scale)))
+    H = max(1, int(round(1080 * args.res_scale)))
+    cams = scenes.orbit_cameras(np.random.default_rng(101), V, [(W, H)] * V)
+    k_bind = int(scene.bind_face.shape[1])
+    # deformed inputs once (the autotuner times the rasterizer on them)
+    r0 = Rasterizer("cuda:0", sh_degree=scene.sh_degree, k_bind=k_bind)
+    r0.set_proxy(scene.proxy.V_rest, scene.proxy.faces)
+    dt = r0.bind_transfer(deform["V_def"], deform["bind_face"], deform["bind_bary"], sc["means"],
+                          sc["quats"], sc["scales"])
+    tsc = dict(means=dt["means"], cov3d=dt["cov3d"], opacity=sc["opacity"], sh=sc["sh"],
+               tri_xyz=sc["tri_xyz"], tri_rgb=sc["tri_rgb"], tri_alpha=sc["tri_alpha"])
+    t0 = time.time()
+    best = autotune.tune(cams, tsc, sh_degree=scene.sh_degree, k_bind=k_bind, reps=2,
+                         batches=(64, 128, 256), use_cache=False)
+    log(f"autotune {best['tile']} batch {best['frag_batch']} schedule {best['schedule']} "
+        f"in {time.time() - t0:.1f} s")
+    # plain: the same views one at a time
+    rp = Rasterizer("cuda:0", sh_degree=scene.sh_degree, k_bind=k_bind)
+    rp.set_proxy(scene.proxy.V_rest, scene.proxy.faces)
+
+    def plain_views():
+        d = rp.bind_transfer(deform["V_def"], deform["bind_face"], deform["bind_bary"], sc["means"],
+                             sc["quats"], sc["scales"])
+        for c in cams:
+            rp.project([c], means=d["means"], cov3d=d["cov3d"], opacity=sc["opacity"], sh=sc["sh"],
+                       tri_xyz=sc["tri_xyz"], tri_rgb=sc["tri_rgb"], tri_alpha=sc["tri_alpha"])
+            rp.bin()
+            rp.sort()
+            rp.blend(want_state=False)
+
+    def timed(fn, steps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    steps = max(2, min(args.steps, 5))
+    ms_plain = timed(plain_views, steps)
+    del rp
+    res = {"views": V, "width": W, "height": H, "tile": "%dx%d" % best["tile"],
+           "frag_batch": best["frag_batch"], "schedule": ["tile_grid", "persistent"][best["schedule"]],
+           "plain_fwd_views_s": round(V / (ms_plain * 1e-3), 2)}
+    for bwd in (False, True):
+        rb = Rasterizer("cuda:0", sh_degree=scene.sh_degree, k_bind=k_bind, tile=best["tile"],
+                        frag_batch=best["frag_batch"], schedule=best["schedule"], own_stream=True)
+        rb.set_proxy(scene.proxy.V_rest, scene.proxy.faces)
+        step = BatchedStep(rb, cams, sc, deform=deform, backward=bwd)
+        step.prepare()
+        if bwd:
+            step.set_loss_gradient(torch.ones_like(step.out["image"]))
+        ms = timed(step, steps)
+        if rb.overflowed():
+            raise RuntimeError("batched step overflowed its reserved key capacity")
+        key = "fwd_bwd" if bwd else "fwd"
+        res[f"{key}_views_s"] = round(V / (ms * 1e-3), 2)
+        res[f"{key}_mpix_s"] = round(V * W * H / (ms * 1e-3) / 1e6, 2)
+        res[f"{key}_ms_per_step"] = round(ms, 3)
+        res["n_dup"] = int(step.n_dup_seen)
+        log(f"batched {key}: {ms:.2f} ms per {V}-view step")
+        del step, rb
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +163,8 @@ def main():
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-views", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -139,6 +230,8 @@ def main():
     stages = {k: round(v[1] / args.steps, 4) for k, v in prof.items()}
     per_launch = {k: v[1] / v[0] for k, v in prof.items()}
     dominant = max(prof, key=lambda k: prof[k][1])
+    g_pairs, t_pairs = r.blend_pairs()
+    log(f"blend pairs: {g_pairs} Gaussian, {t_pairs} triangle")
     # algorithmic HBM bytes per launch of the bandwidth-bound kernels
     algo_bytes = {
         "sort_downsweep": 24.0 * n_dup,          # read key+value, write key+value
@@ -148,16 +241,57 @@ def main():
         "transfer": scene.N * (40.0 + 12.0 * scene.bind_face.shape[1] + 88.0),
         "project_gaussians": scene.N * (12 + 24 + 4 + 12 + 4 + 8 + 8 + 48.0),
     }
-    roof = None
-    if dominant in algo_bytes:
-        ach = algo_bytes[dominant] / (per_launch[dominant] * 1e-3) / 1e9
-        roof = {"kernel": dominant, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "ms_per_launch": round(per_launch[dominant], 4)}
-    else:
-        roof = {"kernel": dominant, "bound": "alu", "achieved": None, "peak": VALU_PEAK_GOPS,
-                "unit": "Gop/s", "frac": None, "traffic": None,
-                "ms_per_launch": round(per_launch[dominant], 4)}
+    def roofline(k):
+        if k in algo_bytes:
+            ach = algo_bytes[k] / (per_launch[k] * 1e-3) / 1e9
+            return {"kernel": k, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                    "ms_per_launch": round(per_launch[k], 4)}
+        if k == "blend":
+            ops = OPS_PER_GAUSS_PAIR * g_pairs + OPS_PER_TRI_PAIR * t_pairs
+            ach = ops / (per_launch[k] * 1e-3) / 1e9
+            return {"kernel": k, "bound": "alu", "achieved": round(ach, 1), "peak": VALU_PEAK_GOPS,
+                    "unit": "Gop/s", "frac": round(ach / VALU_PEAK_GOPS, 4), "traffic": None,
+                    "ms_per_launch": round(per_launch[k], 4), "gauss_pairs": g_pairs,
+                    "tri_pairs": t_pairs}
+        return None
+
+    roof = roofline(dominant)
+    rooflines = {k: roofline(k) for k in ("sort_downsweep", "sort_upsweep", "emit_keys", "blend",
+                                          "transfer") if k in prof}
+
+    # ---- forward + backward (plain, eager) ---------------------------------
+    g = torch.Generator(device="cpu").manual_seed(0)
+    dL = torch.randn(3 * npix, generator=g).to(dev)
+    fwd_state = {}
+
+    def step_fb():
+        dt = r.bind_transfer(V_def, bface, bbary, means, quats, scales)
+        r.project([cam], means=dt["means"], cov3d=dt["cov3d"], opacity=opac, sh=sh,
+                  tri_xyz=txyz, tri_rgb=trgb, tri_alpha=tal)
+        r.bin()
+        r.sort()
+        o = r.blend(want_state=True)
+        return r.backward(dL, o, dt["means"], scales, quats, sh, dt["xform"])
+
+    for _ in range(args.warmup):
+        step_fb()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        step_fb()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_fb = e0.elapsed_time(e1) / args.steps
+    fwd_bwd = {"mpix_s": round(npix / (ms_fb * 1e-3) / 1e6, 2), "ms_per_step": round(ms_fb, 4),
+               "path": "plain forward + backward (eager), gradients to means/scales/quats/opacity/SH"}
+    log(f"fwd+bwd {ms_fb:.3f} ms/step")
+
+    batched = None
+    if not args.no_batched:
+        batched = run_batched(scene, args, dict(V_def=V_def, bind_face=bface, bind_bary=bbary),
+                              dict(means=means, scales=scales, quats=quats, opacity=opac, sh=sh,
+                                   tri_xyz=txyz, tri_rgb=trgb, tri_alpha=tal))
 
     out = {
         "metric": METRIC, "value": round(fwd_mpix, 2), "unit": "Mpixels/s", "n_gpus": 1,
@@ -167,7 +301,9 @@ def main():
         "config": {"workload": scene.name, "width": cam.width, "height": cam.height,
                    "gaussians": scene.N, "triangles": scene.T, "k_bind": int(scene.bind_face.shape[1]),
                    "tile": args.tile, "frag_batch": args.batch, "path": "plain forward"},
-        "n_dup": n_dup, "stages_ms": stages, "roofline": roof, "wall_s": round(wall, 3),
+        "n_dup": n_dup, "stages_ms": stages, "roofline": roof, "rooflines": rooflines,
+        "wall_s": round(wall, 3),
+        "fwd_bwd": fwd_bwd, "batched": batched,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

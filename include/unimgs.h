@@ -64,8 +64,14 @@ typedef struct {
   int32_t sh_degree;       /* 0..3                                             */
   int32_t k_bind;          /* bindings per Gaussian: 1 (centre) or 8 (corners) */
   int32_t mode;            /* compositing rule, UMGS_MODE_*                    */
+  int32_t schedule;        /* blend schedule, UMGS_SCHEDULE_*                  */
   float bg[3];             /* opaque background colour                         */
 } umgs_options;
+
+/* Blend schedules: one workgroup per screen tile, or a persistent grid that
+ * takes tiles from a queue ordered by fragment-list length, longest first
+ * (evens out many views of uneven size and cost). */
+enum { UMGS_SCHEDULE_TILE_GRID = 0, UMGS_SCHEDULE_PERSISTENT = 1 };
 
 /* Compositing rules (Section 3.2, Fig. 3).  UMGS_MODE_UNIMGS is the paper's
  * method; the others are its ablations. */
@@ -77,7 +83,7 @@ enum {
 };
 
 /* Default options: 16x16 tiles, batch 128, SH degree 0, K = 8, UniMGS mode,
- * black background. */
+ * one workgroup per tile, black background. */
 void umgs_default_options(umgs_options *opt);
 
 /* Create a context bound to a HIP stream (hipStream_t passed as void*, NULL =
@@ -137,9 +143,12 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
                          const float *tri_alpha);
 
 /* Bin: duplicate every projected primitive into each screen tile its support
- * touches, with key (global tile << 32 | depth bits) and value = record id.
- * Synchronizes the stream once to size the key buffers.  Errors: STATE before
- * umgs_project; CAPACITY if the duplicate count reaches 2^32 - 1. */
+ * touches, with a key ordering (global tile, depth) and value = record id.
+ * Without a reservation it synchronizes the stream once to size the key
+ * buffers; after umgs_reserve it does not synchronize, and duplicates beyond
+ * the reserved capacity are dropped and flagged (see umgs_query).  Errors:
+ * STATE before umgs_project; CAPACITY if the duplicate count reaches
+ * 2^32 - 2^16 or a buffer cannot be allocated. */
 umgs_status umgs_bin(umgs_ctx *ctx);
 
 /* Sort the duplicates by key (device LSD radix sort; equal keys keep the
@@ -184,9 +193,42 @@ umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_
                           const float *sh, float *dL_dmeans, float *dL_dscales, float *dL_dquats,
                           float *dL_dopacity, float *dL_dsh);
 
-/* Sizes of the current frame: n_dup (duplicates), n_tiles (all views), and
- * the record count V*(N+T).  Any pointer may be NULL.  Synchronous. */
-umgs_status umgs_query(umgs_ctx *ctx, int64_t *n_dup, int64_t *n_tiles, int64_t *n_records);
+/* ---- graphs: capture one step, replay it ----------------------------------- */
+
+/* Reserve key buffers for max_dup duplicates and stop synchronizing in
+ * umgs_bin (the sort stages then read the frame's sizes on the device); 0
+ * returns to the synchronizing mode.  Call it after one eager frame of the
+ * same shape (which sizes every other buffer).  Errors: CAPACITY. */
+umgs_status umgs_reserve(umgs_ctx *ctx, int64_t max_dup);
+/* Begin capturing the context stream into a graph: the entry points called
+ * until umgs_graph_end are recorded, not run.  Requires a reservation,
+ * profiling off, and umgs_project with the cameras of the last eager frame
+ * (update them between replays with umgs_update_views).  Any entry point
+ * that would allocate or synchronize while capturing fails with STATE or
+ * CAPACITY.  Errors: STATE, HIP. */
+umgs_status umgs_graph_begin(umgs_ctx *ctx);
+/* End the capture and instantiate the graph (replacing any previous one). */
+umgs_status umgs_graph_end(umgs_ctx *ctx);
+/* Launch the instantiated graph on the context stream (asynchronous). */
+umgs_status umgs_graph_launch(umgs_ctx *ctx);
+/* Upload new cameras [host] for the next replays; V and every view's width
+ * and height must equal those of the captured frame.  Asynchronous on the
+ * stream.  Errors: INVALID_ARG, STATE. */
+umgs_status umgs_update_views(umgs_ctx *ctx, int32_t V, const umgs_camera *cams);
+
+/* Measurement: blend the sorted frame again into image [device] while
+ * counting, over all pixels, the fragments each pixel evaluates before it is
+ * done; pairs [host] receives {Gaussian pairs, triangle pairs}.  The
+ * algorithmic work of the blend is these counts times the per-pair
+ * operation counts.  Synchronous.  Errors: STATE before umgs_sort. */
+umgs_status umgs_blend_pairs(umgs_ctx *ctx, float *image, int64_t *pairs);
+
+/* Sizes of the current frame: n_dup (duplicates sorted, at most the
+ * reserved capacity), n_tiles (all views), the record count V*(N+T) and
+ * overflow (1 if duplicates were dropped since the flag was last read; the
+ * flag is cleared by reading it).  Any pointer may be NULL.  Synchronous. */
+umgs_status umgs_query(umgs_ctx *ctx, int64_t *n_dup, int64_t *n_tiles, int64_t *n_records,
+                       int32_t *overflow);
 
 /* Copy internal per-frame state into caller memory [device] (for tests):
  *   UMGS_STATE_KEYS    n_records uint32 depth-key bits (0xFFFFFFFF = culled)

@@ -15,6 +15,7 @@ UMGS_OK = 0
 STATUS_NAMES = {0: "OK", -1: "INVALID_ARG", -2: "CAPACITY", -3: "HIP", -4: "STATE", -5: "UNSUPPORTED"}
 
 MODE_UNIMGS, MODE_DIRECT, MODE_ONE_ENTITY, MODE_LITERAL_T = 0, 1, 2, 3
+SCHEDULE_TILE_GRID, SCHEDULE_PERSISTENT = 0, 1
 STATE_KEYS, STATE_SORTED_KEYS, STATE_SORTED_VALS, STATE_RANGES, STATE_TRI_FIXED, STATE_GRAD2D = 0, 1, 2, 3, 4, 5
 
 
@@ -26,7 +27,7 @@ class Camera(C.Structure):
 class Options(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("frag_batch", C.c_int32),
                 ("sh_degree", C.c_int32), ("k_bind", C.c_int32), ("mode", C.c_int32),
-                ("bg", C.c_float * 3)]
+                ("schedule", C.c_int32), ("bg", C.c_float * 3)]
 
 
 P = C.c_void_p
@@ -45,7 +46,13 @@ PROTOTYPES = {
     "umgs_bin": (C.c_int, [P]),
     "umgs_sort": (C.c_int, [P]),
     "umgs_blend": (C.c_int, [P, P, P, P, P]),
-    "umgs_query": (C.c_int, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64)]),
+    "umgs_query": (C.c_int, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I32)]),
+    "umgs_reserve": (C.c_int, [P, I64]),
+    "umgs_blend_pairs": (C.c_int, [P, P, C.POINTER(I64)]),
+    "umgs_graph_begin": (C.c_int, [P]),
+    "umgs_graph_end": (C.c_int, [P]),
+    "umgs_graph_launch": (C.c_int, [P]),
+    "umgs_update_views": (C.c_int, [P, I32, C.POINTER(Camera)]),
     "umgs_copy_state": (C.c_int, [P, I32, P, I64]),
     "umgs_backward": (C.c_int, [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]),
     "umgs_set_profiling": (C.c_int, [P, I32]),

@@ -1,6 +1,7 @@
 // Host side of the C ABI: contexts, argument validation, work buffers and
 // the entry points declared in unimgs.h.
 #include <stdarg.h>
+#include <stddef.h>
 #include <stdio.h>
 #include <string.h>
 
@@ -29,6 +30,9 @@ umgs_status hip_check(Ctx *c, hipError_t e, const char *what) {
 
 umgs_status ensure(Ctx *c, DevBuf &b, size_t bytes, const char *what) {
   if (bytes <= b.cap) return UMGS_OK;
+  if (c->capturing)
+    return fail(c, UMGS_ERR_CAPACITY, "%s: %zu bytes needed while capturing (reserve or render "
+                "an eager frame of this size first)", what, bytes);
   if (b.p) {
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_check(c, e, "stream sync before reallocation");
@@ -63,6 +67,7 @@ static bool valid_options(const umgs_options *o, std::string &why) {
   if (o->sh_degree < 0 || o->sh_degree > 3) { why = "sh_degree must be 0..3"; return false; }
   if (!(o->k_bind == 1 || o->k_bind == 8)) { why = "k_bind must be 1 or 8"; return false; }
   if (o->mode < UMGS_MODE_UNIMGS || o->mode > UMGS_MODE_LITERAL_T) { why = "unknown mode"; return false; }
+  if (o->schedule != UMGS_SCHEDULE_TILE_GRID && o->schedule != UMGS_SCHEDULE_PERSISTENT) { why = "unknown schedule"; return false; }
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(o->bg[k])) { why = "background must be finite"; return false; }
   return true;
@@ -110,6 +115,7 @@ static umgs_status drain_profile(Ctx *c) {
 
 hipError_t launch_exclusive_scan_u64(Ctx *c, uint64_t *data, int64_t n, uint64_t *tmp);
 hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v);
+hipError_t launch_expand_keys(Ctx *c, uint64_t *dst);
 
 }  // namespace umgs
 
@@ -125,6 +131,7 @@ void umgs_default_options(umgs_options *opt) {
   opt->sh_degree = 0;
   opt->k_bind = 8;
   opt->mode = UMGS_MODE_UNIMGS;
+  opt->schedule = UMGS_SCHEDULE_TILE_GRID;
   opt->bg[0] = opt->bg[1] = opt->bg[2] = 0.0f;
 }
 
@@ -152,10 +159,18 @@ umgs_status umgs_create(umgs_ctx **out, const umgs_options *opt, void *hip_strea
 void umgs_destroy(umgs_ctx *ctx) {
   if (!ctx) return;
   Ctx *c = &ctx->c;
+  if (c->capturing) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(c->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+  }
   (void)hipStreamSynchronize(c->stream);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   DevBuf *bufs[] = {&c->V_rest, &c->faces, &c->vf_ptr, &c->vf_idx, &c->vtab, &c->d_views,
                     &c->keys, &c->rects, &c->counts, &c->grec, &c->trec, &c->scan_tmp,
-                    &c->k0, &c->k1, &c->v0, &c->v1, &c->hist, &c->ranges, &c->g2d};
+                    &c->k0, &c->k1, &c->v0, &c->v1, &c->hist, &c->ranges, &c->g2d,
+                    &c->minmax, &c->finfo, &c->tile_order, &c->pair_count};
   for (DevBuf *b : bufs) free_buf(*b);
   for (auto &p : c->prof.pending) {
     (void)hipEventDestroy(p.a);
@@ -240,6 +255,39 @@ umgs_status umgs_bind_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
                    "transfer launch");
 }
 
+static umgs_status build_views(Ctx *c, int32_t V, const umgs_camera *cams,
+                               std::vector<ViewParams> &vps, int64_t &tiles, int64_t &pix) {
+  const umgs_options &o = c->opt;
+  vps.assign(V, ViewParams());
+  tiles = 0;
+  pix = 0;
+  for (int v = 0; v < V; ++v) {
+    const umgs_camera &cm = cams[v];
+    if (cm.width < 1 || cm.height < 1 || cm.width > 16384 || cm.height > 16384)
+      return fail(c, UMGS_ERR_INVALID_ARG, "view %d size %dx%d", v, cm.width, cm.height);
+    if (!(cm.fx > 0) || !(cm.fy > 0) || !std::isfinite(cm.cx) || !std::isfinite(cm.cy))
+      return fail(c, UMGS_ERR_INVALID_ARG, "view %d intrinsics", v);
+    ViewParams &p = vps[v];
+    memcpy(p.R, cm.R, sizeof p.R);
+    memcpy(p.t, cm.t, sizeof p.t);
+    p.fx = cm.fx; p.fy = cm.fy; p.cx = cm.cx; p.cy = cm.cy;
+    p.tanx = (float)cm.width / (2.0f * cm.fx);
+    p.tany = (float)cm.height / (2.0f * cm.fy);
+    p.W = cm.width; p.H = cm.height;
+    p.ntx = (cm.width + o.tile_w - 1) / o.tile_w;
+    p.nty = (cm.height + o.tile_h - 1) / o.tile_h;
+    p.tile_base = (uint32_t)tiles;
+    p.pad0 = 0;
+    p.pix_base = pix;
+    tiles += (int64_t)p.ntx * p.nty;
+    pix += (int64_t)cm.width * cm.height;
+  }
+  if (tiles >= (1LL << 31)) return fail(c, UMGS_ERR_CAPACITY, "%lld tiles", (long long)tiles);
+  return UMGS_OK;
+}
+
+static int sort_passes_for(int total_bits) { return (total_bits + 7) / 8; }
+
 umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int32_t N,
                          const float *means, const float *cov3d, const float *scales,
                          const float *quats, const float *opacity, const float *sh,
@@ -256,32 +304,20 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
   if ((int64_t)V * ((int64_t)N + T) >= (1LL << 31))
     return fail(c, UMGS_ERR_CAPACITY, "umgs_project: V*(N+T) = %lld records", (long long)V * (N + T));
   const umgs_options &o = c->opt;
-  std::vector<ViewParams> vps(V);
+  std::vector<ViewParams> vps;
   int64_t tiles = 0, pix = 0;
-  for (int v = 0; v < V; ++v) {
-    const umgs_camera &cm = cams[v];
-    if (cm.width < 1 || cm.height < 1 || cm.width > 16384 || cm.height > 16384)
-      return fail(c, UMGS_ERR_INVALID_ARG, "umgs_project: view %d size %dx%d", v, cm.width, cm.height);
-    if (!(cm.fx > 0) || !(cm.fy > 0) || !std::isfinite(cm.cx) || !std::isfinite(cm.cy))
-      return fail(c, UMGS_ERR_INVALID_ARG, "umgs_project: view %d intrinsics", v);
-    ViewParams &p = vps[v];
-    memcpy(p.R, cm.R, sizeof p.R);
-    memcpy(p.t, cm.t, sizeof p.t);
-    p.fx = cm.fx; p.fy = cm.fy; p.cx = cm.cx; p.cy = cm.cy;
-    p.tanx = (float)cm.width / (2.0f * cm.fx);
-    p.tany = (float)cm.height / (2.0f * cm.fy);
-    p.W = cm.width; p.H = cm.height;
-    p.ntx = (cm.width + o.tile_w - 1) / o.tile_w;
-    p.nty = (cm.height + o.tile_h - 1) / o.tile_h;
-    p.tile_base = (uint32_t)tiles;
-    p.pad0 = 0;
-    p.pix_base = pix;
-    tiles += (int64_t)p.ntx * p.nty;
-    pix += (int64_t)cm.width * cm.height;
+  umgs_status s = build_views(c, V, cams, vps, tiles, pix);
+  if (s != UMGS_OK) return s;
+  if (c->capturing) {
+    // a capture replays the device view table: it must describe this frame
+    bool same = (int)c->views.size() == V && V == c->V && N == c->N && T == c->T &&
+                o.tile_w == c->tile_w && o.tile_h == c->tile_h;
+    for (int v = 0; same && v < V; ++v) same = memcmp(&vps[v], &c->views[v], sizeof(ViewParams)) == 0;
+    if (!same)
+      return fail(c, UMGS_ERR_STATE, "umgs_project: while capturing, the cameras and sizes must be "
+                                     "those of the last eager frame");
   }
-  if (tiles >= (1LL << 31)) return fail(c, UMGS_ERR_CAPACITY, "umgs_project: %lld tiles", (long long)tiles);
   const int64_t nrec = (int64_t)V * (N + T);
-  umgs_status s;
   if ((s = ensure(c, c->d_views, sizeof(ViewParams) * V, "view table")) ||
       (s = ensure(c, c->keys, sizeof(uint32_t) * std::max<int64_t>(nrec, 1), "depth keys")) ||
       (s = ensure(c, c->rects, sizeof(uint2) * std::max<int64_t>(nrec, 1), "tile rects")) ||
@@ -289,8 +325,12 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
       (s = ensure(c, c->grec, sizeof(GaussRec) * std::max<int64_t>((int64_t)V * N, 1), "Gaussian records")) ||
       (s = ensure(c, c->trec, sizeof(TriRec) * std::max<int64_t>((int64_t)V * T, 1), "triangle records")) ||
       (s = ensure(c, c->scan_tmp, scan_tmp_bytes(std::max<int64_t>(nrec + 1, 1 << 20)), "scan scratch")) ||
-      (s = ensure(c, c->ranges, sizeof(uint2) * tiles, "tile ranges")))
+      (s = ensure(c, c->ranges, sizeof(uint2) * tiles, "tile ranges")) ||
+      (s = ensure(c, c->minmax, 2 * sizeof(uint32_t), "depth range")) ||
+      (s = ensure(c, c->finfo, sizeof(FrameInfo), "frame info")) ||
+      (s = ensure(c, c->tile_order, sizeof(uint32_t) * (64 + tiles), "tile order")))
     return s;
+  const bool fresh_info = c->finfo.cap && c->views.empty();
   c->views = vps;
   c->V = V; c->N = N; c->T = T;
   c->tile_w = o.tile_w; c->tile_h = o.tile_h; c->frag_batch = o.frag_batch;
@@ -299,22 +339,40 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
   c->n_records = nrec;
   c->n_tiles = tiles;
   c->n_pixels = pix;
-  c->n_dup = 0;
   int bits = 1;
   while (bits < 31 && (1LL << bits) < tiles) ++bits;
   c->tile_bits = bits;
   c->stage = 0;
-  hipError_t e = hipMemcpyAsync(c->d_views.p, vps.data(), sizeof(ViewParams) * V,
-                                hipMemcpyHostToDevice, c->stream);
+  hipError_t e = hipSuccess;
+  if (fresh_info) e = launch_fill_u32(c, (uint32_t *)c->finfo.p, sizeof(FrameInfo) / 4, 0u);
+  if (e == hipSuccess && !c->capturing)
+    e = hipMemcpyAsync(c->d_views.p, vps.data(), sizeof(ViewParams) * V, hipMemcpyHostToDevice,
+                       c->stream);
   if (e != hipSuccess) return hip_check(c, e, "view upload");
   // the scan's total lands in counts[nrec]
   e = launch_fill_u32(c, (uint32_t *)((uint64_t *)c->counts.p + nrec), 2, 0u);
   if (e != hipSuccess) return hip_check(c, e, "count reset");
+  e = launch_fill_u32(c, (uint32_t *)c->minmax.p, 1, kCulled);
+  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t *)c->minmax.p + 1, 1, 0u);
+  if (e != hipSuccess) return hip_check(c, e, "depth range reset");
   if ((e = launch_project_gaussians(c, means, cov3d, scales, quats, opacity, sh)) != hipSuccess)
     return hip_check(c, e, "project_gaussians launch");
   if ((e = launch_setup_triangles(c, tri_xyz, tri_rgb, tri_alpha)) != hipSuccess)
     return hip_check(c, e, "setup_triangles launch");
   c->stage = 1;
+  return UMGS_OK;
+}
+
+static umgs_status ensure_keys(Ctx *c, uint64_t n) {
+  umgs_status s;
+  n = std::max<uint64_t>(n, 1);
+  if ((s = ensure(c, c->k0, 8 * n, "keys")) || (s = ensure(c, c->k1, 8 * n, "keys")) ||
+      (s = ensure(c, c->v0, 4 * n, "values")) || (s = ensure(c, c->v1, 4 * n, "values")) ||
+      (s = ensure(c, c->hist, radix_hist_bytes(n), "radix histograms")) ||
+      (s = ensure(c, c->scan_tmp,
+                  scan_tmp_bytes(std::max<int64_t>(radix_hist_bytes(n) / 4, c->n_records + 1)),
+                  "scan scratch")))
+    return s;
   return UMGS_OK;
 }
 
@@ -325,27 +383,38 @@ umgs_status umgs_bin(umgs_ctx *ctx) {
   hipError_t e = launch_exclusive_scan_u64(c, (uint64_t *)c->counts.p, c->n_records + 1,
                                            (uint64_t *)c->scan_tmp.p);
   if (e != hipSuccess) return hip_check(c, e, "count scan");
-  if (!c->host_pinned.p) {
-    if ((e = hipHostMalloc(&c->host_pinned.p, 256, hipHostMallocDefault)) != hipSuccess)
-      return hip_check(c, e, "pinned scratch");
-    c->host_pinned.cap = 256;
+  if (c->fixed_cap) {
+    // sizes stay on the device; every sort-stage grid covers the capacity
+    if (ensure_keys(c, c->key_cap) != UMGS_OK) return UMGS_ERR_CAPACITY;
+    c->n_launch = c->key_cap;
+    c->sort_passes = sort_passes_for(32 + c->tile_bits);
+  } else {
+    if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_bin: capturing without a reservation");
+    if (!c->host_pinned.p) {
+      if ((e = hipHostMalloc(&c->host_pinned.p, 256, hipHostMallocDefault)) != hipSuccess)
+        return hip_check(c, e, "pinned scratch");
+      c->host_pinned.cap = 256;
+    }
+    uint64_t *h = (uint64_t *)c->host_pinned.p;
+    if ((e = hipMemcpyAsync(h, (uint64_t *)c->counts.p + c->n_records, sizeof(uint64_t),
+                            hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(h + 1, c->minmax.p, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                            c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+      return hip_check(c, e, "duplicate count readback");
+    const uint64_t nd = h[0];
+    if (nd >= 0xFFFF0000ull)
+      return fail(c, UMGS_ERR_CAPACITY, "umgs_bin: %llu duplicates exceed 2^32", (unsigned long long)nd);
+    const uint32_t dmin = ((uint32_t *)(h + 1))[0], dmax = ((uint32_t *)(h + 1))[1];
+    int db = 1;
+    while (dmin <= dmax && db < 32 && (uint64_t)(dmax - dmin) >= (1ull << db)) ++db;
+    umgs_status s = ensure_keys(c, nd);
+    if (s != UMGS_OK) return s;
+    c->key_cap = std::max<uint64_t>(nd, 1);
+    c->n_dup = nd;
+    c->n_launch = nd;
+    c->sort_passes = sort_passes_for(db + c->tile_bits);
   }
-  uint64_t *h = (uint64_t *)c->host_pinned.p;
-  if ((e = hipMemcpyAsync(h, (uint64_t *)c->counts.p + c->n_records, sizeof(uint64_t),
-                          hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
-      (e = hipStreamSynchronize(c->stream)) != hipSuccess)
-    return hip_check(c, e, "duplicate count readback");
-  const uint64_t nd = h[0];
-  if (nd >= 0xFFFF0000ull)
-    return fail(c, UMGS_ERR_CAPACITY, "umgs_bin: %llu duplicates exceed 2^32", (unsigned long long)nd);
-  umgs_status s;
-  const size_t n = std::max<uint64_t>(nd, 1);
-  if ((s = ensure(c, c->k0, 8 * n, "keys")) || (s = ensure(c, c->k1, 8 * n, "keys")) ||
-      (s = ensure(c, c->v0, 4 * n, "values")) || (s = ensure(c, c->v1, 4 * n, "values")) ||
-      (s = ensure(c, c->hist, radix_hist_bytes(n), "radix histograms")) ||
-      (s = ensure(c, c->scan_tmp, scan_tmp_bytes(std::max<int64_t>(radix_hist_bytes(n) / 4, c->n_records + 1)), "scan scratch")))
-    return s;
-  c->n_dup = nd;
   if ((e = launch_emit_keys(c)) != hipSuccess) return hip_check(c, e, "emit_keys launch");
   c->stage = 2;
   return UMGS_OK;
@@ -397,14 +466,35 @@ umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_
                    "backward launch");
 }
 
-umgs_status umgs_query(umgs_ctx *ctx, int64_t *n_dup, int64_t *n_tiles, int64_t *n_records) {
+// Reads the device frame info into the host copies (synchronizes).
+static umgs_status read_frame_info(Ctx *c, FrameInfo *out) {
+  memset(out, 0, sizeof *out);
+  if (!c->finfo.p) return UMGS_OK;
+  hipError_t e = hipMemcpyAsync(out, c->finfo.p, sizeof *out, hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "frame info readback");
+  if (c->stage >= 2) c->n_dup = out->n_dup;
+  return UMGS_OK;
+}
+
+umgs_status umgs_query(umgs_ctx *ctx, int64_t *n_dup, int64_t *n_tiles, int64_t *n_records,
+                       int32_t *overflow) {
   if (!ctx) return UMGS_ERR_INVALID_ARG;
   Ctx *c = &ctx->c;
-  hipError_t e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return hip_check(c, e, "umgs_query sync");
+  if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_query: the stream is being captured");
+  FrameInfo fi;
+  umgs_status s = read_frame_info(c, &fi);
+  if (s != UMGS_OK) return s;
   if (n_dup) *n_dup = (int64_t)c->n_dup;
   if (n_tiles) *n_tiles = c->n_tiles;
   if (n_records) *n_records = c->n_records;
+  if (overflow) {
+    *overflow = fi.overflow ? 1 : 0;
+    if (fi.overflow) {
+      hipError_t e = launch_fill_u32(c, (uint32_t *)c->finfo.p + offsetof(FrameInfo, overflow) / 4, 1, 0u);
+      if (e != hipSuccess) return hip_check(c, e, "overflow reset");
+    }
+  }
   return UMGS_OK;
 }
 
@@ -412,14 +502,18 @@ umgs_status umgs_copy_state(umgs_ctx *ctx, int32_t which, void *dst, int64_t cap
   if (!ctx) return UMGS_ERR_INVALID_ARG;
   Ctx *c = &ctx->c;
   if (!dst) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_copy_state: NULL destination");
+  if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_copy_state: the stream is being captured");
+  FrameInfo fi;
+  umgs_status st = read_frame_info(c, &fi);
+  if (st != UMGS_OK) return st;
   const void *src = nullptr;
   int64_t bytes = 0;
   int need = 1;
   switch (which) {
     case UMGS_STATE_KEYS: src = c->keys.p; bytes = 4 * c->n_records; need = 1; break;
-    case UMGS_STATE_SORTED_KEYS: src = c->sorted_in ? c->k1.p : c->k0.p; bytes = 8 * (int64_t)c->n_dup; need = 3; break;
+    case UMGS_STATE_SORTED_KEYS: src = nullptr; bytes = 8 * (int64_t)c->n_dup; need = 3; break;
     case UMGS_STATE_GRAD2D: src = c->g2d.p; bytes = 36 * (int64_t)c->V * c->N; need = 4; break;
-    case UMGS_STATE_SORTED_VALS: src = c->sorted_in ? c->v1.p : c->v0.p; bytes = 4 * (int64_t)c->n_dup; need = 3; break;
+    case UMGS_STATE_SORTED_VALS: src = fi.sorted_in ? c->v1.p : c->v0.p; bytes = 4 * (int64_t)c->n_dup; need = 3; break;
     case UMGS_STATE_RANGES: src = c->ranges.p; bytes = 8 * c->n_tiles; need = 3; break;
     case UMGS_STATE_TRI_FIXED: src = c->trec.p; bytes = 24 * (int64_t)c->V * c->T; need = 1; break;
     default: return fail(c, UMGS_ERR_INVALID_ARG, "umgs_copy_state: unknown state %d", which);
@@ -428,7 +522,9 @@ umgs_status umgs_copy_state(umgs_ctx *ctx, int32_t which, void *dst, int64_t cap
   if (cap_bytes < bytes) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_copy_state: need %lld bytes", (long long)bytes);
   if (bytes == 0) return UMGS_OK;
   hipError_t e;
-  if (which == UMGS_STATE_TRI_FIXED) {
+  if (which == UMGS_STATE_SORTED_KEYS) {
+    e = launch_expand_keys(c, (uint64_t *)dst);
+  } else if (which == UMGS_STATE_TRI_FIXED) {
     // 2D copy: the first 24 bytes of every 80-byte record
     e = hipMemcpy2DAsync(dst, 24, src, sizeof(TriRec), 24, (size_t)c->V * c->T,
                          hipMemcpyDeviceToDevice, c->stream);
@@ -436,6 +532,98 @@ umgs_status umgs_copy_state(umgs_ctx *ctx, int32_t which, void *dst, int64_t cap
     e = hipMemcpyAsync(dst, src, (size_t)bytes, hipMemcpyDeviceToDevice, c->stream);
   }
   return hip_check(c, e, "umgs_copy_state copy");
+}
+
+umgs_status umgs_blend_pairs(umgs_ctx *ctx, float *image, int64_t *pairs) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->stage < 3) return fail(c, UMGS_ERR_STATE, "umgs_blend_pairs: frame not sorted");
+  if (!image || !pairs) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_blend_pairs: NULL argument");
+  if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_blend_pairs: capturing");
+  umgs_status s = ensure(c, c->pair_count, 2 * sizeof(uint64_t), "pair counters");
+  if (s != UMGS_OK) return s;
+  hipError_t e = launch_fill_u32(c, (uint32_t *)c->pair_count.p, 4, 0u);
+  if (e == hipSuccess)
+    e = launch_blend(c, image, nullptr, nullptr, nullptr, (unsigned long long *)c->pair_count.p);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(pairs, c->pair_count.p, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  return hip_check(c, e, "umgs_blend_pairs");
+}
+
+umgs_status umgs_reserve(umgs_ctx *ctx, int64_t max_dup) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_reserve: the stream is being captured");
+  if (max_dup < 0 || (uint64_t)max_dup >= 0xFFFF0000ull)
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_reserve: max_dup=%lld", (long long)max_dup);
+  if (max_dup == 0) {
+    c->fixed_cap = false;
+    return UMGS_OK;
+  }
+  umgs_status s = ensure_keys(c, (uint64_t)max_dup);
+  if (s != UMGS_OK) return s;
+  c->key_cap = (uint64_t)max_dup;
+  c->fixed_cap = true;
+  return UMGS_OK;
+}
+
+umgs_status umgs_graph_begin(umgs_ctx *ctx) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_graph_begin: already capturing");
+  if (!c->fixed_cap) return fail(c, UMGS_ERR_STATE, "umgs_graph_begin: call umgs_reserve first");
+  if (c->prof.on) return fail(c, UMGS_ERR_STATE, "umgs_graph_begin: profiling is on");
+  if (c->views.empty()) return fail(c, UMGS_ERR_STATE, "umgs_graph_begin: render one eager frame first");
+  if (!c->stream) return fail(c, UMGS_ERR_STATE, "umgs_graph_begin: the null stream cannot be captured");
+  hipError_t e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess) e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) return hip_check(c, e, "hipStreamBeginCapture");
+  c->capturing = true;
+  return UMGS_OK;
+}
+
+umgs_status umgs_graph_end(umgs_ctx *ctx) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (!c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_graph_end: not capturing");
+  c->capturing = false;
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  if (e != hipSuccess) return hip_check(c, e, "hipStreamEndCapture");
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph = g;
+  c->graph_exec = nullptr;
+  e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+  return hip_check(c, e, "hipGraphInstantiate");
+}
+
+umgs_status umgs_graph_launch(umgs_ctx *ctx) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (!c->graph_exec) return fail(c, UMGS_ERR_STATE, "umgs_graph_launch: no graph");
+  if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_graph_launch: capturing");
+  return hip_check(c, hipGraphLaunch(c->graph_exec, c->stream), "hipGraphLaunch");
+}
+
+umgs_status umgs_update_views(umgs_ctx *ctx, int32_t V, const umgs_camera *cams) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_update_views: capturing");
+  if (!cams || V != c->V || c->views.empty())
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_update_views: need the captured frame's %d views", c->V);
+  std::vector<ViewParams> vps;
+  int64_t tiles = 0, pix = 0;
+  umgs_status s = build_views(c, V, cams, vps, tiles, pix);
+  if (s != UMGS_OK) return s;
+  for (int v = 0; v < V; ++v)
+    if (vps[v].W != c->views[v].W || vps[v].H != c->views[v].H)
+      return fail(c, UMGS_ERR_INVALID_ARG, "umgs_update_views: view %d changed size", v);
+  c->views = vps;
+  return hip_check(c, hipMemcpyAsync(c->d_views.p, vps.data(), sizeof(ViewParams) * V,
+                                     hipMemcpyHostToDevice, c->stream),
+                   "view upload");
 }
 
 umgs_status umgs_set_profiling(umgs_ctx *ctx, int32_t enable) {

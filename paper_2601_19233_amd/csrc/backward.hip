@@ -41,7 +41,8 @@ template <int TW, int TH>
 __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
     const ViewParams *__restrict__ views, int V, int N, int T, int mode, int batch,
     float bg0, float bg1, float bg2, const uint2 *__restrict__ ranges,
-    const uint32_t *__restrict__ vals, const GaussRec *__restrict__ grec,
+    const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1,
+    const FrameInfo *__restrict__ fi, const GaussRec *__restrict__ grec,
     const TriRec *__restrict__ trec, const float *__restrict__ dLdimg,
     const float *__restrict__ Tfin, const int32_t *__restrict__ ncontrib,
     const float *__restrict__ Tent, float *__restrict__ g2d) {
@@ -50,6 +51,7 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
   uint32_t *slots = smem;                                 // batch * kSlotWords
   float *gl = (float *)(smem + batch * kSlotWords);       // batch * 9
   __shared__ int smax;
+  const uint32_t *vals = fi->sorted_in ? v1 : v0;
 
   const uint32_t tile = blockIdx.x;
   const int v = find_view(views, V, tile);
@@ -72,8 +74,11 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
   const int64_t pix = (int64_t)py * vp.W + px;
   int last = 0;
   float Tr = 1.0f, Tterm = 1.0f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
+  const int count = (int)(rg.y - rg.x);
   if (inside) {
-    last = ncontrib[vp.pix_base + pix];
+    // positions are 1-based within this tile's list; clamp so a per-pixel
+    // array from another frame can never index past the tile's range
+    last = min(max(ncontrib[vp.pix_base + pix], 0), count);
     Tr = Tfin[vp.pix_base + pix];
     Tterm = Tent[vp.pix_base + pix];
     const float *d = dLdimg + 3 * vp.pix_base;
@@ -463,12 +468,12 @@ __global__ void project_backward_kernel(const ViewParams *__restrict__ views, in
 template <int TW, int TH>
 hipError_t launch_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int32_t *nc, const float *Te) {
   const size_t lds = (size_t)c->frag_batch * (kSlotWords + 9) * sizeof(uint32_t);
-  const uint32_t *vals = (const uint32_t *)(c->sorted_in ? c->v1.p : c->v0.p);
   ScopedTimer t(c, K_BLEND_BWD);
   hipLaunchKernelGGL((blend_backward_kernel<TW, TH>), dim3((unsigned)c->n_tiles), dim3(TW * TH), lds,
                      c->stream, (const ViewParams *)c->d_views.p, c->V, c->N, c->T, c->mode,
-                     c->frag_batch, c->bg[0], c->bg[1], c->bg[2], (const uint2 *)c->ranges.p, vals,
-                     (const GaussRec *)c->grec.p, (const TriRec *)c->trec.p, dL, Tf, nc, Te,
+                     c->frag_batch, c->bg[0], c->bg[1], c->bg[2], (const uint2 *)c->ranges.p,
+                     (const uint32_t *)c->v0.p, (const uint32_t *)c->v1.p,
+                     (const FrameInfo *)c->finfo.p, (const GaussRec *)c->grec.p, (const TriRec *)c->trec.p, dL, Tf, nc, Te,
                      (float *)c->g2d.p);
   return hipGetLastError();
 }

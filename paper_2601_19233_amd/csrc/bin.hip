@@ -98,29 +98,123 @@ hipError_t excl_scan(hipStream_t s, T *data, int64_t n, T *tmp) {
   return hipGetLastError();
 }
 
-// One thread per record: write one key/value pair per overlapped tile.
+// One thread per record: write one key/value pair per overlapped tile.  The
+// key is (global tile << depth_bits) | (depth key - depth_base): the order of
+// (tile, depth) with the depth range of the frame in as few bits as it needs.
 __global__ void emit_keys_kernel(const ViewParams *__restrict__ views, int V, int per_view,
                                  int64_t n_records, const uint32_t *__restrict__ depth,
                                  const uint2 *__restrict__ rects,
                                  const uint64_t *__restrict__ offs,
+                                 const FrameInfo *__restrict__ fi,
                                  uint64_t *__restrict__ keys_out,
                                  uint32_t *__restrict__ vals_out) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n_records) return;
   const uint64_t o0 = offs[r], o1 = offs[r + 1];
-  if (o0 == o1) return;
+  const uint64_t cap = fi->n_dup;          // pairs beyond the key capacity are dropped
+  if (o0 == o1 || o0 >= cap) return;
+  const uint32_t depth_base = fi->depth_base;
+  const int depth_bits = fi->depth_bits;
   const int v = (int)(r / per_view);
   const ViewParams &vp = views[v];
   const uint2 rc = rects[r];
   const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
-  const uint64_t d = depth[r];
+  const uint64_t d = depth[r] - depth_base;
   uint64_t o = o0;
   for (int ty = ty0; ty < ty1; ++ty) {
     const uint64_t row = (uint64_t)vp.tile_base + (uint64_t)ty * vp.ntx;
-    for (int tx = tx0; tx < tx1; ++tx) {
-      keys_out[o] = ((row + tx) << 32) | d;
+    for (int tx = tx0; tx < tx1 && o < cap; ++tx) {
+      keys_out[o] = ((row + tx) << depth_bits) | d;
       vals_out[o] = (uint32_t)r;
       ++o;
+    }
+  }
+}
+
+// Load-balanced emission: each block owns kEmitSpan consecutive output
+// positions and writes them with consecutive lanes on consecutive addresses.
+// The records covering the block's range are found by binary search in the
+// scanned offsets and staged in LDS; every lane then finds its position's
+// record by binary search in LDS and derives the tile from the position's
+// rank inside the record's tile rectangle (row-major, as the scan counted).
+constexpr int kEmitThreads = 256;
+constexpr int kEmitPer = 8;
+constexpr int kEmitSpan = kEmitThreads * kEmitPer;
+constexpr int kEmitRecCap = 1024;
+
+// last r in [lo, hi] with offs[r] <= d (offs is non-decreasing)
+__device__ __forceinline__ int64_t last_record_at(const uint64_t *__restrict__ offs, int64_t lo,
+                                                  int64_t hi, uint64_t d) {
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (offs[mid] <= d) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ uint64_t tile_key(const ViewParams *__restrict__ views, int v, uint2 rc,
+                                             uint64_t j, uint32_t dep, int bits) {
+  const uint32_t tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF;
+  const uint32_t w = tx1 - tx0;
+  const uint32_t jj = (uint32_t)j;
+  const uint32_t ty = ty0 + jj / w, tx = tx0 + jj % w;
+  const uint64_t tile = (uint64_t)views[v].tile_base + (uint64_t)ty * views[v].ntx + tx;
+  return (tile << bits) | dep;
+}
+
+__global__ __launch_bounds__(kEmitThreads) void emit_balanced_kernel(
+    const ViewParams *__restrict__ views, int per_view, int64_t n_records,
+    const uint32_t *__restrict__ depth, const uint2 *__restrict__ rects,
+    const uint64_t *__restrict__ offs, const FrameInfo *__restrict__ fi,
+    uint64_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out) {
+  __shared__ uint64_t s_off[kEmitRecCap];
+  __shared__ uint2 s_rect[kEmitRecCap];
+  __shared__ uint32_t s_dep[kEmitRecCap];
+  __shared__ int32_t s_view[kEmitRecCap];
+  __shared__ int64_t s_lo, s_hi;
+  const uint64_t n = fi->n_dup;
+  const uint64_t d0 = (uint64_t)blockIdx.x * kEmitSpan;
+  if (d0 >= n) return;
+  const uint64_t d1 = min(d0 + (uint64_t)kEmitSpan, n);
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_lo = last_record_at(offs, 0, n_records, d0);
+    s_hi = last_record_at(offs, s_lo, n_records, d1 - 1);
+  }
+  __syncthreads();
+  const int64_t rlo = s_lo, rhi = s_hi;
+  const int64_t nr = rhi - rlo + 1;
+  const uint32_t base = fi->depth_base;
+  const int bits = fi->depth_bits;
+  if (nr <= kEmitRecCap) {
+    for (int64_t i = tid; i < nr; i += kEmitThreads) {
+      const int64_t r = rlo + i;
+      s_off[i] = offs[r];
+      s_rect[i] = rects[r];
+      s_dep[i] = depth[r] - base;
+      s_view[i] = (int32_t)(r / per_view);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kEmitPer; ++k) {
+      const uint64_t d = d0 + (uint64_t)k * kEmitThreads + tid;
+      if (d >= d1) break;
+      int lo = 0, hi = (int)nr - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_off[mid] <= d) lo = mid; else hi = mid - 1;
+      }
+      keys_out[d] = tile_key(views, s_view[lo], s_rect[lo], d - s_off[lo], s_dep[lo], bits);
+      vals_out[d] = (uint32_t)(rlo + lo);
+    }
+  } else {
+    // many empty records inside the range: search the offsets in memory
+    for (int k = 0; k < kEmitPer; ++k) {
+      const uint64_t d = d0 + (uint64_t)k * kEmitThreads + tid;
+      if (d >= d1) break;
+      const int64_t r = last_record_at(offs, rlo, rhi, d);
+      keys_out[d] = tile_key(views, (int)(r / per_view), rects[r], d - offs[r], depth[r] - base, bits);
+      vals_out[d] = (uint32_t)r;
     }
   }
 }
@@ -130,13 +224,46 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
-__global__ void tile_ranges_kernel(const uint64_t *__restrict__ keys, uint64_t n,
-                                   uint2 *__restrict__ ranges) {
+// Turns the scanned total and the depth range into the frame's sizes.
+__global__ void frame_info_kernel(const uint64_t *__restrict__ total,
+                                  const uint32_t *__restrict__ minmax, uint64_t cap,
+                                  int tile_bits, FrameInfo *__restrict__ fi) {
+  const uint64_t raw = *total;
+  fi->n_dup = (uint32_t)(raw < cap ? raw : cap);
+  if (raw > cap) fi->overflow = 1u;
+  const uint32_t lo = minmax[0], hi = minmax[1];
+  const bool any = lo <= hi;
+  fi->depth_base = any ? lo : 0u;
+  int db = 1;
+  while (any && db < 32 && (uint64_t)(hi - lo) >= (1ull << db)) ++db;
+  fi->depth_bits = db;
+  fi->total_bits = db + tile_bits;
+  fi->sorted_in = ((db + tile_bits + 7) / 8) & 1;
+  fi->queue = 0u;
+}
+
+__global__ void tile_ranges_kernel(const uint64_t *__restrict__ k0, const uint64_t *__restrict__ k1,
+                                   const FrameInfo *__restrict__ fi, uint2 *__restrict__ ranges) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t n = fi->n_dup;
   if (i >= n) return;
-  const uint32_t t = (uint32_t)(keys[i] >> 32);
-  if (i == 0 || (uint32_t)(keys[i - 1] >> 32) != t) ranges[t].x = (uint32_t)i;
-  if (i == n - 1 || (uint32_t)(keys[i + 1] >> 32) != t) ranges[t].y = (uint32_t)(i + 1);
+  const int shift = fi->depth_bits;
+  const uint64_t *keys = fi->sorted_in ? k1 : k0;
+  const uint32_t t = (uint32_t)(keys[i] >> shift);
+  if (i == 0 || (uint32_t)(keys[i - 1] >> shift) != t) ranges[t].x = (uint32_t)i;
+  if (i == n - 1 || (uint32_t)(keys[i + 1] >> shift) != t) ranges[t].y = (uint32_t)(i + 1);
+}
+
+// Sorted keys back in the exported (tile << 32 | depth key bits) form.
+__global__ void expand_keys_kernel(const uint64_t *__restrict__ k0, const uint64_t *__restrict__ k1,
+                                   const FrameInfo *__restrict__ fi, uint64_t *__restrict__ out) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= fi->n_dup) return;
+  const int shift = fi->depth_bits;
+  const uint32_t base = fi->depth_base;
+  const uint64_t k = (fi->sorted_in ? k1 : k0)[i];
+  const uint64_t mask = shift >= 64 ? ~0ull : ((1ull << shift) - 1ull);
+  out[i] = ((k >> shift) << 32) | (uint64_t)((uint32_t)(k & mask) + base);
 }
 
 }  // namespace
@@ -162,12 +289,18 @@ hipError_t launch_exclusive_scan_u32(Ctx *c, uint32_t *data, int64_t n, uint32_t
 }
 
 hipError_t launch_emit_keys(Ctx *c) {
-  if (c->n_dup == 0) return hipSuccess;
+  hipLaunchKernelGGL(frame_info_kernel, dim3(1), dim3(1), 0, c->stream,
+                     (const uint64_t *)c->counts.p + c->n_records, (const uint32_t *)c->minmax.p,
+                     (uint64_t)c->key_cap, c->tile_bits, (FrameInfo *)c->finfo.p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || c->n_records == 0) return e;
+  if (c->n_launch == 0) return hipSuccess;
   ScopedTimer t(c, K_EMIT);
-  hipLaunchKernelGGL(emit_keys_kernel, dim3(ceil_div(c->n_records, 256)), dim3(256), 0,
-                     c->stream, (const ViewParams *)c->d_views.p, c->V, c->N + c->T,
-                     c->n_records, (const uint32_t *)c->keys.p, (const uint2 *)c->rects.p,
-                     (const uint64_t *)c->counts.p, (uint64_t *)c->k0.p, (uint32_t *)c->v0.p);
+  hipLaunchKernelGGL(emit_balanced_kernel, dim3(ceil_div(c->n_launch, kEmitSpan)),
+                     dim3(kEmitThreads), 0, c->stream, (const ViewParams *)c->d_views.p,
+                     c->N + c->T, c->n_records, (const uint32_t *)c->keys.p,
+                     (const uint2 *)c->rects.p, (const uint64_t *)c->counts.p,
+                     (const FrameInfo *)c->finfo.p, (uint64_t *)c->k0.p, (uint32_t *)c->v0.p);
   return hipGetLastError();
 }
 
@@ -180,10 +313,18 @@ hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v) {
 hipError_t launch_tile_ranges(Ctx *c) {
   ScopedTimer t(c, K_RANGES);
   hipError_t e = launch_fill_u32(c, (uint32_t *)c->ranges.p, 2 * c->n_tiles, 0u);
-  if (e != hipSuccess || c->n_dup == 0) return e;
-  const uint64_t *k = (const uint64_t *)(c->sorted_in ? c->k1.p : c->k0.p);
-  hipLaunchKernelGGL(tile_ranges_kernel, dim3(ceil_div(c->n_dup, 256)), dim3(256), 0, c->stream,
-                     k, c->n_dup, (uint2 *)c->ranges.p);
+  if (e != hipSuccess || c->n_launch == 0) return e;
+  hipLaunchKernelGGL(tile_ranges_kernel, dim3(ceil_div(c->n_launch, 256)), dim3(256), 0, c->stream,
+                     (const uint64_t *)c->k0.p, (const uint64_t *)c->k1.p,
+                     (const FrameInfo *)c->finfo.p, (uint2 *)c->ranges.p);
+  return hipGetLastError();
+}
+
+hipError_t launch_expand_keys(Ctx *c, uint64_t *dst) {
+  if (c->n_launch == 0) return hipSuccess;
+  hipLaunchKernelGGL(expand_keys_kernel, dim3(ceil_div(c->n_launch, 256)), dim3(256), 0, c->stream,
+                     (const uint64_t *)c->k0.p, (const uint64_t *)c->k1.p,
+                     (const FrameInfo *)c->finfo.p, dst);
   return hipGetLastError();
 }
 

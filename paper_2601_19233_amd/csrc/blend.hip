@@ -14,6 +14,10 @@
 // background).  A wave skips the rest of a batch once all its pixels are
 // done; the workgroup stops loading batches once every pixel is done.
 //
+// Two schedules: one workgroup per tile, or a persistent grid (a few
+// workgroups per CU) pulling tiles from a queue ordered by list length,
+// longest first, which evens out views and tiles of very different cost.
+//
 // Edge functions E = dx (Py - Ya) - dy (Px - Xa) are integers in 1/256-px
 // units below 2^52 in magnitude; they are evaluated in FP64, which holds
 // them exactly (CDNA executes FP64 FMA at full vector rate).
@@ -23,17 +27,18 @@ namespace umgs {
 
 namespace {
 
-template <int TW, int TH>
-__global__ __launch_bounds__(TW *TH) void blend_kernel(
-    const ViewParams *__restrict__ views, int V, int N, int T, int mode, int batch,
-    float bg0, float bg1, float bg2, const uint2 *__restrict__ ranges,
-    const uint32_t *__restrict__ vals, const GaussRec *__restrict__ grec,
-    const TriRec *__restrict__ trec, float *__restrict__ image, float *__restrict__ Tout,
-    int32_t *__restrict__ ncontrib, float *__restrict__ Tent_out) {
+// COUNT instantiations also count the (pixel, fragment) pairs each pixel
+// evaluates before it is done (Gaussian, triangle) into pairs[0..1].
+template <int TW, int TH, bool COUNT = false>
+__device__ __forceinline__ void blend_tile(
+    uint32_t tile, uint32_t *__restrict__ slots, const ViewParams *__restrict__ views, int V,
+    int N, int T, int mode, int batch, float bg0, float bg1, float bg2,
+    const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
+    const GaussRec *__restrict__ grec, const TriRec *__restrict__ trec,
+    float *__restrict__ image, float *__restrict__ Tout, int32_t *__restrict__ ncontrib,
+    float *__restrict__ Tent_out, unsigned long long *__restrict__ pairs = nullptr) {
+  uint32_t n_gp = 0, n_tp = 0;
   constexpr int NT = TW * TH;
-  extern __shared__ uint32_t slots[];   // batch * kSlotWords
-
-  const uint32_t tile = blockIdx.x;
   const int v = find_view(views, V, tile);
   const ViewParams &vp = views[v];
   const uint32_t lt = tile - vp.tile_base;
@@ -82,6 +87,9 @@ __global__ __launch_bounds__(TW *TH) void blend_kernel(
         const uint32_t tag = s[31];
         if (done) continue;
         const int32_t pos = (int32_t)(bstart - rg.x + f + 1);
+        if (COUNT) {
+          if ((tag & 1u) == 0u) ++n_gp; else ++n_tp;
+        }
         if ((tag & 1u) == 0u) {
           float alpha, G, dx, dy;
           if (!gauss_eval(s, pcx, pcy, alpha, G, dx, dy)) continue;
@@ -145,29 +153,181 @@ __global__ __launch_bounds__(TW *TH) void blend_kernel(
     if (ncontrib) ncontrib[vp.pix_base + pix] = last;
     if (Tent_out) Tent_out[vp.pix_base + pix] = Tent;
   }
+  if (COUNT) {
+    unsigned long long g = n_gp, t = n_tp;
+    for (int o = 32; o >= 1; o >>= 1) {
+      g += __shfl_xor(g, o, 64);
+      t += __shfl_xor(t, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      atomicAdd(pairs, g);
+      atomicAdd(pairs + 1, t);
+    }
+  }
+}
+
+struct BlendArgs {
+  const ViewParams *views;
+  int V, N, T, mode, batch;
+  float bg0, bg1, bg2;
+  const uint2 *ranges;
+  const uint32_t *v0, *v1;
+  const GaussRec *grec;
+  const TriRec *trec;
+  FrameInfo *fi;
+  const uint32_t *order;
+  uint32_t n_tiles;
+  float *image, *Tout;
+  int32_t *ncontrib;
+  float *Tent;
+};
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void blend_kernel(BlendArgs a) {
+  extern __shared__ uint32_t slots[];   // batch * kSlotWords
+  const uint32_t *vals = a.fi->sorted_in ? a.v1 : a.v0;
+  blend_tile<TW, TH>(blockIdx.x, slots, a.views, a.V, a.N, a.T, a.mode, a.batch, a.bg0, a.bg1,
+                     a.bg2, a.ranges, vals, a.grec, a.trec, a.image, a.Tout, a.ncontrib, a.Tent);
 }
 
 template <int TW, int TH>
-hipError_t launch_tw(Ctx *c, float *image, float *T_final, int32_t *n_contrib, float *T_ent) {
+__global__ __launch_bounds__(TW *TH) void blend_count_kernel(BlendArgs a,
+                                                             unsigned long long *pairs) {
+  extern __shared__ uint32_t slots[];
+  const uint32_t *vals = a.fi->sorted_in ? a.v1 : a.v0;
+  blend_tile<TW, TH, true>(blockIdx.x, slots, a.views, a.V, a.N, a.T, a.mode, a.batch, a.bg0,
+                           a.bg1, a.bg2, a.ranges, vals, a.grec, a.trec, a.image, a.Tout,
+                           a.ncontrib, a.Tent, pairs);
+}
+
+// Persistent schedule: every workgroup takes the next tile of the
+// longest-first order until the queue is exhausted (each wave reaches the
+// exit once the counter passes the tile count).
+template <int TW, int TH>
+__global__ __launch_bounds__(TW *TH) void blend_persistent_kernel(BlendArgs a) {
+  extern __shared__ uint32_t slots[];
+  __shared__ uint32_t item;
+  const uint32_t *vals = a.fi->sorted_in ? a.v1 : a.v0;
+  for (;;) {
+    if (threadIdx.x == 0) item = atomicAdd(&a.fi->queue, 1u);
+    __syncthreads();
+    const uint32_t it = item;
+    __syncthreads();
+    if (it >= a.n_tiles) break;
+    blend_tile<TW, TH>(a.order[it], slots, a.views, a.V, a.N, a.T, a.mode, a.batch, a.bg0, a.bg1,
+                       a.bg2, a.ranges, vals, a.grec, a.trec, a.image, a.Tout, a.ncontrib, a.Tent);
+  }
+}
+
+// ---- longest-first tile order: bucket tiles by floor(log2(list length)) ----
+constexpr int kBuckets = 34;
+
+__device__ __forceinline__ int length_bucket(uint2 r) {
+  const uint32_t len = r.y - r.x;
+  return len == 0 ? 0 : 33 - __clz(len);      // 1..33, larger = longer
+}
+
+__global__ void order_count_kernel(const uint2 *__restrict__ ranges, uint32_t n,
+                                   uint32_t *__restrict__ cnt) {
+  __shared__ uint32_t h[kBuckets];
+  if (threadIdx.x < kBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) atomicAdd(&h[length_bucket(ranges[t])], 1u);
+  __syncthreads();
+  if (threadIdx.x < kBuckets && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
+}
+
+// cursors: descending bucket order, longest lists first
+__global__ void order_scan_kernel(uint32_t *__restrict__ cnt) {
+  if (threadIdx.x != 0) return;
+  uint32_t run = 0;
+  for (int b = kBuckets - 1; b >= 0; --b) {
+    const uint32_t c = cnt[b];
+    cnt[b] = run;
+    run += c;
+  }
+}
+
+__global__ void order_scatter_kernel(const uint2 *__restrict__ ranges, uint32_t n,
+                                     uint32_t *__restrict__ cursor, uint32_t *__restrict__ order) {
+  __shared__ uint32_t h[kBuckets], base[kBuckets];
+  if (threadIdx.x < kBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  int b = 0;
+  uint32_t local = 0;
+  if (t < n) {
+    b = length_bucket(ranges[t]);
+    local = atomicAdd(&h[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kBuckets && h[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]);
+  __syncthreads();
+  if (t < n) order[base[b] + local] = t;
+}
+
+template <int TW, int TH>
+hipError_t launch_tw(Ctx *c, BlendArgs a, bool persistent, unsigned long long *pairs) {
   const size_t lds = (size_t)c->frag_batch * kSlotWords * sizeof(uint32_t);
-  const uint32_t *vals = (const uint32_t *)(c->sorted_in ? c->v1.p : c->v0.p);
+  if (pairs) {
+    hipLaunchKernelGGL((blend_count_kernel<TW, TH>), dim3((unsigned)c->n_tiles), dim3(TW * TH),
+                       lds, c->stream, a, pairs);
+    return hipGetLastError();
+  }
   ScopedTimer t(c, K_BLEND);
-  hipLaunchKernelGGL((blend_kernel<TW, TH>), dim3((unsigned)c->n_tiles), dim3(TW * TH), lds,
-                     c->stream, (const ViewParams *)c->d_views.p, c->V, c->N, c->T, c->mode,
-                     c->frag_batch, c->bg[0], c->bg[1], c->bg[2], (const uint2 *)c->ranges.p,
-                     vals, (const GaussRec *)c->grec.p, (const TriRec *)c->trec.p, image,
-                     T_final, n_contrib, T_ent);
+  if (persistent) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, blend_persistent_kernel<TW, TH>,
+                                                     TW * TH, lds) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    const uint64_t grid = std::min<uint64_t>((uint64_t)c->num_cu * per_cu, (uint64_t)c->n_tiles);
+    hipLaunchKernelGGL((blend_persistent_kernel<TW, TH>), dim3((unsigned)grid), dim3(TW * TH), lds,
+                       c->stream, a);
+  } else {
+    hipLaunchKernelGGL((blend_kernel<TW, TH>), dim3((unsigned)c->n_tiles), dim3(TW * TH), lds,
+                       c->stream, a);
+  }
   return hipGetLastError();
 }
 
 }  // namespace
 
+hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v);
+
 hipError_t launch_blend(Ctx *c, float *image, float *T_final, int32_t *n_contrib,
-                        float *T_entity_in) {
+                        float *T_entity_in, unsigned long long *pairs) {
   if (c->n_tiles == 0) return hipSuccess;
-  if (c->tile_w == 16 && c->tile_h == 16) return launch_tw<16, 16>(c, image, T_final, n_contrib, T_entity_in);
-  if (c->tile_w == 8 && c->tile_h == 8) return launch_tw<8, 8>(c, image, T_final, n_contrib, T_entity_in);
-  if (c->tile_w == 32 && c->tile_h == 8) return launch_tw<32, 8>(c, image, T_final, n_contrib, T_entity_in);
+  const bool persistent = !pairs && c->opt.schedule == UMGS_SCHEDULE_PERSISTENT;
+  uint32_t *cnt = (uint32_t *)c->tile_order.p;
+  uint32_t *order = cnt + 64;
+  if (persistent) {
+    hipError_t e = launch_fill_u32(c, cnt, kBuckets, 0u);
+    if (e != hipSuccess) return e;
+    const unsigned g = ceil_div(c->n_tiles, 256);
+    hipLaunchKernelGGL(order_count_kernel, dim3(g), dim3(256), 0, c->stream,
+                       (const uint2 *)c->ranges.p, (uint32_t)c->n_tiles, cnt);
+    hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(64), 0, c->stream, cnt);
+    hipLaunchKernelGGL(order_scatter_kernel, dim3(g), dim3(256), 0, c->stream,
+                       (const uint2 *)c->ranges.p, (uint32_t)c->n_tiles, cnt, order);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  BlendArgs a;
+  a.views = (const ViewParams *)c->d_views.p;
+  a.V = c->V; a.N = c->N; a.T = c->T; a.mode = c->mode; a.batch = c->frag_batch;
+  a.bg0 = c->bg[0]; a.bg1 = c->bg[1]; a.bg2 = c->bg[2];
+  a.ranges = (const uint2 *)c->ranges.p;
+  a.v0 = (const uint32_t *)c->v0.p;
+  a.v1 = (const uint32_t *)c->v1.p;
+  a.grec = (const GaussRec *)c->grec.p;
+  a.trec = (const TriRec *)c->trec.p;
+  a.fi = (FrameInfo *)c->finfo.p;
+  a.order = order;
+  a.n_tiles = (uint32_t)c->n_tiles;
+  a.image = image; a.Tout = T_final; a.ncontrib = n_contrib; a.Tent = T_entity_in;
+  if (c->tile_w == 16 && c->tile_h == 16) return launch_tw<16, 16>(c, a, persistent, pairs);
+  if (c->tile_w == 8 && c->tile_h == 8) return launch_tw<8, 8>(c, a, persistent, pairs);
+  if (c->tile_w == 32 && c->tile_h == 8) return launch_tw<32, 8>(c, a, persistent, pairs);
   return hipErrorInvalidValue;
 }
 

@@ -70,6 +70,19 @@ struct Prof {
   int64_t n[K_COUNT] = {};
 };
 
+// Per-frame sizes that the kernels after the count scan read on the device,
+// so a captured graph needs no host synchronisation.
+struct FrameInfo {
+  uint32_t n_dup;        // duplicates in the sort (clamped to the key capacity)
+  uint32_t depth_base;   // smallest depth-key bits of the frame
+  int32_t depth_bits;    // bits of (depth key - depth_base) in a sort key
+  int32_t total_bits;    // depth_bits + tile bits
+  int32_t sorted_in;     // 0: sorted pairs in k0/v0, 1: in k1/v1
+  uint32_t overflow;     // sticky: the duplicates exceeded the key capacity
+  uint32_t queue;        // work counter of the persistent blend
+  uint32_t pad;
+};
+
 // Device buffer that only grows.
 struct DevBuf {
   void *p = nullptr;
@@ -95,8 +108,21 @@ struct Ctx {
   int64_t n_records = 0;   // V * (N + T)
   int64_t n_tiles = 0;
   int64_t n_pixels = 0;
-  uint64_t n_dup = 0;
+  uint64_t n_dup = 0;         // duplicates of the frame as last read on the host
+  uint64_t n_launch = 0;      // elements the sort-stage grids cover (n_dup, or the capacity)
+  int sort_passes = 0;        // radix passes launched
   int tile_bits = 1;
+  uint32_t depth_base = 0;   // smallest depth-key bits of the frame
+  int depth_bits = 32;       // bits of (depth key - depth_base) in the sort key
+  DevBuf minmax;       // 2 uint32: min / max depth-key bits of the frame
+  DevBuf finfo;        // FrameInfo (device)
+  DevBuf tile_order;   // 64 bucket counters + n_tiles tile ids (persistent blend)
+  DevBuf pair_count;   // 2 uint64: evaluated (pixel, fragment) pairs (measurement)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  uint64_t key_cap = 0;      // duplicates the key buffers hold
+  bool capturing = false;    // a graph capture is in progress on the stream
+  bool fixed_cap = false;    // key capacity reserved: no host readback in umgs_bin
   std::vector<ViewParams> views;
   std::vector<int32_t> view_first_tile_x;  // host copy helpers
   DevBuf d_views;
@@ -112,7 +138,6 @@ struct Ctx {
   DevBuf ranges;       // n_tiles uint2
   DevBuf g2d;          // V*N x 9 per-view 2D gradients (backward)
   DevBuf host_pinned;  // not a device buffer: pinned host scratch for small readbacks
-  int sorted_in = 0;   // which ping-pong buffer holds the sorted result
   Prof prof;
 };
 
@@ -144,7 +169,7 @@ hipError_t launch_radix_sort(Ctx *c);
 size_t radix_hist_bytes(uint64_t n);
 hipError_t launch_tile_ranges(Ctx *c);
 hipError_t launch_blend(Ctx *c, float *image, float *T_final, int32_t *n_contrib,
-                        float *T_entity_in);
+                        float *T_entity_in, unsigned long long *pairs = nullptr);
 hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32_t *nc,
                            const float *Te, const float *means, const float *scales,
                            const float *quats, const float *xform, const float *sh,
@@ -156,6 +181,25 @@ hipError_t launch_transfer(Ctx *c, const float *V_def, int32_t N, const int32_t 
                            float *cov3d_out, float *xform_out, float *vertex_out);
 
 inline unsigned ceil_div(uint64_t a, uint64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip, each
+// with its own L2.  Give every XCD a contiguous range of logical block ids so
+// that neighbouring blocks -- whose outputs abut in memory -- share an L2.
+__device__ __forceinline__ uint32_t xcd_block(uint32_t bid, uint32_t nb) {
+  const uint32_t xcd = bid & 7u, k = bid >> 3;
+  const uint32_t per = nb >> 3, rem = nb & 7u;
+  return xcd * per + min(xcd, rem) + k;
+}
+
+// Wave-wide minimum / maximum of a uint32 (wave64).
+__device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));
+  return v;
+}
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+  return v;
+}
 
 }  // namespace umgs
 

@@ -4,6 +4,9 @@
 // (FP32 bits of the view depth, or kCulled), its tile rectangle, its tile
 // count (for the bin stage's scan) and the record the blend stage reads.
 //
+// The kernels also reduce the frame's range of depth keys, so that the sort
+// keys can hold depth relative to the nearest primitive in fewer bits.
+//
 // Decision values -- view depth, pixel coordinates of triangle vertices and
 // their 1/256-px snapping, the triangle depth key -- are evaluated with FP
 // contraction disabled in a fixed operation order, so that they are
@@ -79,20 +82,18 @@ __device__ __forceinline__ void sh_colour(const float *sh, int deg, float x, flo
   b = fmaxf(acc[2] + 0.5f, 0.0f);
 }
 
-__global__ void project_gaussians_kernel(const ViewParams *__restrict__ views, int N, int T,
-                                         int sh_deg, int tile_w, int tile_h,
-                                         const float *__restrict__ means,
-                                         const float *__restrict__ cov3d,
-                                         const float *__restrict__ scales,
-                                         const float *__restrict__ quats,
-                                         const float *__restrict__ opacity,
-                                         const float *__restrict__ sh,
-                                         uint32_t *__restrict__ keys, uint2 *__restrict__ rects,
-                                         uint64_t *__restrict__ counts,
-                                         GaussRec *__restrict__ grec) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int v = blockIdx.y;
-  if (i >= N) return;
+// Projects Gaussian i into view v; returns its depth key (kCulled if culled).
+__device__ uint32_t project_gaussian(const ViewParams *__restrict__ views, int N, int T,
+                                     int sh_deg, int tile_w, int tile_h,
+                                     const float *__restrict__ means,
+                                     const float *__restrict__ cov3d,
+                                     const float *__restrict__ scales,
+                                     const float *__restrict__ quats,
+                                     const float *__restrict__ opacity,
+                                     const float *__restrict__ sh,
+                                     uint32_t *__restrict__ keys, uint2 *__restrict__ rects,
+                                     uint64_t *__restrict__ counts,
+                                     GaussRec *__restrict__ grec, int i, int v) {
   const ViewParams &vp = views[v];
   const int64_t rid = (int64_t)v * (N + T) + i;
   const float mx_w = means[3 * i], my_w = means[3 * i + 1], mz_w = means[3 * i + 2];
@@ -103,7 +104,7 @@ __global__ void project_gaussians_kernel(const ViewParams *__restrict__ views, i
     keys[rid] = kCulled;
     counts[rid] = 0;
     rects[rid] = make_uint2(0, 0);
-    return;
+    return kCulled;
   }
   const float xv = view_row(vp.R, vp.t[0], mx_w, my_w, mz_w);
   const float yv = view_row(vp.R + 3, vp.t[1], mx_w, my_w, mz_w);
@@ -165,7 +166,7 @@ __global__ void project_gaussians_kernel(const ViewParams *__restrict__ views, i
     keys[rid] = kCulled;
     counts[rid] = 0;
     rects[rid] = make_uint2(0, 0);
-    return;
+    return kCulled;
   }
   const float idet = 1.0f / det;
   const float mx = vp.fx * xv * iz + vp.cx;
@@ -217,18 +218,47 @@ __global__ void project_gaussians_kernel(const ViewParams *__restrict__ views, i
   rec.b = b;
   rec.pad[0] = rec.pad[1] = rec.pad[2] = 0.0f;
   grec[(int64_t)v * N + i] = rec;
+  return __float_as_uint(zv);
 }
 
-__global__ void setup_triangles_kernel(const ViewParams *__restrict__ views, int N, int T,
-                                       int tile_w, int tile_h, const float *__restrict__ xyz,
-                                       const float *__restrict__ rgb,
-                                       const float *__restrict__ alpha,
-                                       uint32_t *__restrict__ keys, uint2 *__restrict__ rects,
-                                       uint64_t *__restrict__ counts,
-                                       TriRec *__restrict__ trec) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// Folds a wave's valid depth keys into the frame's [min, max] (one atomic
+// pair per wave); the sort keys store depth relative to the minimum.
+__device__ __forceinline__ void reduce_key_range(uint32_t key, uint32_t *minmax) {
+  const uint32_t lo = wave_min_u32(key);
+  const uint32_t hi = wave_max_u32(key == kCulled ? 0u : key);
+  if ((threadIdx.x & 63) == 0 && lo != kCulled) {
+    atomicMin(minmax, lo);
+    atomicMax(minmax + 1, hi);
+  }
+}
+
+__global__ void project_gaussians_kernel(const ViewParams *__restrict__ views, int N, int T,
+                                         int sh_deg, int tile_w, int tile_h,
+                                         const float *__restrict__ means,
+                                         const float *__restrict__ cov3d,
+                                         const float *__restrict__ scales,
+                                         const float *__restrict__ quats,
+                                         const float *__restrict__ opacity,
+                                         const float *__restrict__ sh,
+                                         uint32_t *__restrict__ keys, uint2 *__restrict__ rects,
+                                         uint64_t *__restrict__ counts,
+                                         GaussRec *__restrict__ grec, uint32_t *__restrict__ minmax) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int v = blockIdx.y;
-  if (j >= T) return;
+  uint32_t key = kCulled;
+  if (i < N)
+    key = project_gaussian(views, N, T, sh_deg, tile_w, tile_h, means, cov3d, scales, quats,
+                           opacity, sh, keys, rects, counts, grec, i, v);
+  reduce_key_range(key, minmax);
+}
+
+// Sets up triangle j for view v; returns its depth key (kCulled if culled).
+__device__ uint32_t setup_triangle(const ViewParams *__restrict__ views, int N, int T,
+                                   int tile_w, int tile_h, const float *__restrict__ xyz,
+                                   const float *__restrict__ rgb, const float *__restrict__ alpha,
+                                   uint32_t *__restrict__ keys, uint2 *__restrict__ rects,
+                                   uint64_t *__restrict__ counts, TriRec *__restrict__ trec,
+                                   int j, int v) {
   const ViewParams &vp = views[v];
   const int64_t rid = (int64_t)v * (N + T) + N + j;
   const float *P = xyz + 9 * (int64_t)j;
@@ -262,7 +292,7 @@ __global__ void setup_triangles_kernel(const ViewParams *__restrict__ views, int
     rects[rid] = make_uint2(0, 0);
     TriRec z = {};
     trec[(int64_t)v * T + j] = z;
-    return;
+    return kCulled;
   }
   const float key = tri_key(zv[0], zv[1], zv[2]);
   int perm[3] = {0, 1, 2};
@@ -309,6 +339,22 @@ __global__ void setup_triangles_kernel(const ViewParams *__restrict__ views, int
   keys[rid] = __float_as_uint(key);
   counts[rid] = cnt;
   rects[rid] = rect;
+  return __float_as_uint(key);
+}
+
+__global__ void setup_triangles_kernel(const ViewParams *__restrict__ views, int N, int T,
+                                       int tile_w, int tile_h, const float *__restrict__ xyz,
+                                       const float *__restrict__ rgb,
+                                       const float *__restrict__ alpha,
+                                       uint32_t *__restrict__ keys, uint2 *__restrict__ rects,
+                                       uint64_t *__restrict__ counts,
+                                       TriRec *__restrict__ trec, uint32_t *__restrict__ minmax) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int v = blockIdx.y;
+  uint32_t key = kCulled;
+  if (j < T)
+    key = setup_triangle(views, N, T, tile_w, tile_h, xyz, rgb, alpha, keys, rects, counts, trec, j, v);
+  reduce_key_range(key, minmax);
 }
 
 }  // namespace
@@ -323,7 +369,7 @@ hipError_t launch_project_gaussians(Ctx *c, const float *means, const float *cov
                      (const ViewParams *)c->d_views.p, c->N, c->T, c->sh_degree, c->tile_w,
                      c->tile_h, means, cov3d, scales, quats, opacity, sh,
                      (uint32_t *)c->keys.p, (uint2 *)c->rects.p, (uint64_t *)c->counts.p,
-                     (GaussRec *)c->grec.p);
+                     (GaussRec *)c->grec.p, (uint32_t *)c->minmax.p);
   return hipGetLastError();
 }
 
@@ -335,7 +381,7 @@ hipError_t launch_setup_triangles(Ctx *c, const float *tri_xyz, const float *tri
   hipLaunchKernelGGL(setup_triangles_kernel, grid, dim3(256), 0, c->stream,
                      (const ViewParams *)c->d_views.p, c->N, c->T, c->tile_w, c->tile_h,
                      tri_xyz, tri_rgb, tri_alpha, (uint32_t *)c->keys.p, (uint2 *)c->rects.p,
-                     (uint64_t *)c->counts.p, (TriRec *)c->trec.p);
+                     (uint64_t *)c->counts.p, (TriRec *)c->trec.p, (uint32_t *)c->minmax.p);
   return hipGetLastError();
 }
 

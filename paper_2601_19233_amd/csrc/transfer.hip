@@ -9,10 +9,10 @@
 //   polar D = R S with R = [u1 u2 u1 x u2][v1 v2 v3]^T from the eigenvectors
 //   of D^T D (a proper rotation; the nearest one to D);
 //   r_v = log R (axis-angle), written with S as a 12-float row.
-// transfer_kernel (one thread per Gaussian, FP32): Eq. 12 at each of the K
-//   bound points, Eq. 13 averages: R' = exp(mean r_i), S' = mean S_i,
-//   A = R'S', Sigma' = A Sigma A^T, mu' = mu + mean Delta_i (pinned order),
-//   q' = quat(R') * q.
+// transfer kernels (FP32): Eq. 12 at each of the K bound points, Eq. 13
+//   averages: R' = exp(mean r_i), S' = mean S_i, A = R'S',
+//   Sigma' = A Sigma A^T, mu' = mu + mean Delta_i (pinned order),
+//   q' = quat(R') * q.  For K = 8 one lane handles one corner.
 #include "internal.h"
 
 namespace umgs {
@@ -228,49 +228,22 @@ __device__ __forceinline__ float pinned_mean(float m, float s, float invk) {
   return m + s * invk;
 }
 
-template <int K>
-__global__ void transfer_kernel(int N, const float4 *__restrict__ vtab,
-                                const int32_t *__restrict__ faces,
-                                const int32_t *__restrict__ bind_face,
-                                const float *__restrict__ bind_bary,
-                                const float *__restrict__ means, const float *__restrict__ quats,
-                                const float *__restrict__ scales, float *__restrict__ means_out,
-                                float *__restrict__ quats_out, float *__restrict__ cov3d_out,
-                                float *__restrict__ xform_out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  float3 dsum = make_float3(0.f, 0.f, 0.f);
-  float rs[3] = {0.f, 0.f, 0.f};
-  float Ss[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = bind_face[(int64_t)K * i + k];
-    const float u = bind_bary[2 * ((int64_t)K * i + k)];
-    const float v = bind_bary[2 * ((int64_t)K * i + k) + 1];
-    const float w = pinned_w(u, v);
-    const int va = faces[3 * f], vb = faces[3 * f + 1], vc = faces[3 * f + 2];
-    const float4 a0 = vtab[3 * va], a1 = vtab[3 * va + 1], a2 = vtab[3 * va + 2];
-    const float4 b0 = vtab[3 * vb], b1 = vtab[3 * vb + 1], b2 = vtab[3 * vb + 2];
-    const float4 c0 = vtab[3 * vc], c1 = vtab[3 * vc + 1], c2 = vtab[3 * vc + 2];
-    const float3 di = interp_delta(u, v, w, a0, b0, c0);
-    dsum = (k == 0) ? di : add3(dsum, di);
-    // Eq. 12: log-rotation and shear interpolated with the same barycentrics
-    rs[0] += u * a0.w + v * b0.w + w * c0.w;
-    rs[1] += u * a1.x + v * b1.x + w * c1.x;
-    rs[2] += u * a1.y + v * b1.y + w * c1.y;
-    Ss[0] += u * a1.z + v * b1.z + w * c1.z;
-    Ss[1] += u * a1.w + v * b1.w + w * c1.w;
-    Ss[2] += u * a2.x + v * b2.x + w * c2.x;
-    Ss[3] += u * a2.y + v * b2.y + w * c2.y;
-    Ss[4] += u * a2.z + v * b2.z + w * c2.z;
-    Ss[5] += u * a2.w + v * b2.w + w * c2.w;
-  }
-  const float invk = 1.0f / (float)K;
+// Eq. 13 for Gaussian i from its corner sums: dsum = sum_k Delta_k (pinned
+// order), rs = sum_k r_k, Ss = sum_k S_k (xx, xy, xz, yy, yz, zz).
+__device__ __forceinline__ void finish_gaussian(int i, float3 dsum, const float rs[3],
+                                                const float Ss[6], float invk,
+                                                const float *__restrict__ means,
+                                                const float *__restrict__ quats,
+                                                const float *__restrict__ scales,
+                                                float *__restrict__ means_out,
+                                                float *__restrict__ quats_out,
+                                                float *__restrict__ cov3d_out,
+                                                float *__restrict__ xform_out) {
   means_out[3 * i] = pinned_mean(means[3 * i], dsum.x, invk);
   means_out[3 * i + 1] = pinned_mean(means[3 * i + 1], dsum.y, invk);
   means_out[3 * i + 2] = pinned_mean(means[3 * i + 2], dsum.z, invk);
 
-  // Eq. 13: R' = exp(mean r), S' = mean S, A = R'S'
+  // R' = exp(mean r), S' = mean S, A = R'S'
   const float r0 = rs[0] * invk, r1 = rs[1] * invk, r2 = rs[2] * invk;
   const float th2 = r0 * r0 + r1 * r1 + r2 * r2;
   const float th = sqrtf(th2);
@@ -280,8 +253,8 @@ __global__ void transfer_kernel(int N, const float4 *__restrict__ vtab,
     hb = 0.5f - th2 * (1.0f / 24.0f);
     sh_over = 0.5f - th2 * (1.0f / 48.0f);
   } else {
-    const float s = sinf(th), h = sinf(0.5f * th);
-    sa = s / th;
+    const float sn = sinf(th), h = sinf(0.5f * th);
+    sa = sn / th;
     const float q = h / (0.5f * th);
     hb = 0.5f * q * q;
     sh_over = h / th;
@@ -335,6 +308,100 @@ __global__ void transfer_kernel(int N, const float4 *__restrict__ vtab,
   }
 }
 
+// Eq. 12 at one bound point: Delta (pinned), r and S interpolated from the
+// face's three vertex rows.
+__device__ __forceinline__ void corner_terms(const float4 *__restrict__ vtab,
+                                             const int32_t *__restrict__ faces, int f, float u,
+                                             float v, float3 &di, float r[3], float S[6]) {
+  const float w = pinned_w(u, v);
+  const int va = faces[3 * f], vb = faces[3 * f + 1], vc = faces[3 * f + 2];
+  const float4 a0 = vtab[3 * va], a1 = vtab[3 * va + 1], a2 = vtab[3 * va + 2];
+  const float4 b0 = vtab[3 * vb], b1 = vtab[3 * vb + 1], b2 = vtab[3 * vb + 2];
+  const float4 c0 = vtab[3 * vc], c1 = vtab[3 * vc + 1], c2 = vtab[3 * vc + 2];
+  di = interp_delta(u, v, w, a0, b0, c0);
+  r[0] = u * a0.w + v * b0.w + w * c0.w;
+  r[1] = u * a1.x + v * b1.x + w * c1.x;
+  r[2] = u * a1.y + v * b1.y + w * c1.y;
+  S[0] = u * a1.z + v * b1.z + w * c1.z;
+  S[1] = u * a1.w + v * b1.w + w * c1.w;
+  S[2] = u * a2.x + v * b2.x + w * c2.x;
+  S[3] = u * a2.y + v * b2.y + w * c2.y;
+  S[4] = u * a2.z + v * b2.z + w * c2.z;
+  S[5] = u * a2.w + v * b2.w + w * c2.w;
+}
+
+// K = 1: one thread per Gaussian.
+__global__ void transfer1_kernel(int N, const float4 *__restrict__ vtab,
+                                 const int32_t *__restrict__ faces,
+                                 const int32_t *__restrict__ bind_face,
+                                 const float *__restrict__ bind_bary,
+                                 const float *__restrict__ means, const float *__restrict__ quats,
+                                 const float *__restrict__ scales, float *__restrict__ means_out,
+                                 float *__restrict__ quats_out, float *__restrict__ cov3d_out,
+                                 float *__restrict__ xform_out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  float3 d;
+  float r[3], S[6];
+  corner_terms(vtab, faces, bind_face[i], bind_bary[2 * i], bind_bary[2 * i + 1], d, r, S);
+  finish_gaussian(i, d, r, S, 1.0f, means, quats, scales, means_out, quats_out, cov3d_out,
+                  xform_out);
+}
+
+// K = 8: one lane per (Gaussian, corner) so the eight gather chains run in
+// parallel; the 8-lane group then reduces its corners (the mean offset in
+// corner order, as pinned) into LDS and one lane per Gaussian finishes it.
+constexpr int kT8Threads = 256;
+constexpr int kT8Gauss = kT8Threads / 8;
+
+__global__ __launch_bounds__(kT8Threads) void transfer8_kernel(
+    int N, const float4 *__restrict__ vtab, const int32_t *__restrict__ faces,
+    const int32_t *__restrict__ bind_face, const float *__restrict__ bind_bary,
+    const float *__restrict__ means, const float *__restrict__ quats,
+    const float *__restrict__ scales, float *__restrict__ means_out,
+    float *__restrict__ quats_out, float *__restrict__ cov3d_out, float *__restrict__ xform_out) {
+  __shared__ float sums[kT8Gauss][12];
+  const int tid = threadIdx.x, grp = tid >> 3, k = tid & 7;
+  const int i = blockIdx.x * kT8Gauss + grp;
+  float3 d = make_float3(0.f, 0.f, 0.f);
+  float r[3] = {0.f, 0.f, 0.f}, S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (i < N) {
+    const int64_t b = 8 * (int64_t)i + k;
+    corner_terms(vtab, faces, bind_face[b], bind_bary[2 * b], bind_bary[2 * b + 1], d, r, S);
+  }
+  // r, S: sum over the 8 lanes of the group
+#pragma unroll
+  for (int o = 1; o < 8; o <<= 1) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j) r[j] += __shfl_xor(r[j], o, 8);
+#pragma unroll
+    for (int j = 0; j < 6; ++j) S[j] += __shfl_xor(S[j], o, 8);
+  }
+  // Delta: ((D0 + D1) + D2) + ... in corner order
+  float3 ds = d;
+#pragma unroll
+  for (int j = 1; j < 8; ++j) {
+    const float3 dj = make_float3(__shfl(d.x, j, 8), __shfl(d.y, j, 8), __shfl(d.z, j, 8));
+    if (j == 1) ds = make_float3(__shfl(d.x, 0, 8), __shfl(d.y, 0, 8), __shfl(d.z, 0, 8));
+    ds = add3(ds, dj);
+  }
+  if (k == 0) {
+    sums[grp][0] = ds.x; sums[grp][1] = ds.y; sums[grp][2] = ds.z;
+    sums[grp][3] = r[0]; sums[grp][4] = r[1]; sums[grp][5] = r[2];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) sums[grp][6 + j] = S[j];
+  }
+  __syncthreads();
+  if (tid < kT8Gauss) {
+    const int g = blockIdx.x * kT8Gauss + tid;
+    if (g < N) {
+      const float *q = sums[tid];
+      finish_gaussian(g, make_float3(q[0], q[1], q[2]), q + 3, q + 6, 0.125f, means, quats, scales,
+                      means_out, quats_out, cov3d_out, xform_out);
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_transfer(Ctx *c, const float *V_def, int32_t N, const int32_t *bind_face,
@@ -353,11 +420,11 @@ hipError_t launch_transfer(Ctx *c, const float *V_def, int32_t N, const int32_t 
   if (e != hipSuccess || N == 0) return e;
   ScopedTimer tt(c, K_TRANSFER);
   if (c->opt.k_bind == 8)
-    hipLaunchKernelGGL(transfer_kernel<8>, dim3(ceil_div(N, 256)), dim3(256), 0, c->stream, N,
-                       (const float4 *)vtab, (const int32_t *)c->faces.p, bind_face, bind_bary,
-                       means, quats, scales, means_out, quats_out, cov3d_out, xform_out);
+    hipLaunchKernelGGL(transfer8_kernel, dim3(ceil_div(N, kT8Gauss)), dim3(kT8Threads), 0,
+                       c->stream, N, (const float4 *)vtab, (const int32_t *)c->faces.p, bind_face,
+                       bind_bary, means, quats, scales, means_out, quats_out, cov3d_out, xform_out);
   else
-    hipLaunchKernelGGL(transfer_kernel<1>, dim3(ceil_div(N, 256)), dim3(256), 0, c->stream, N,
+    hipLaunchKernelGGL(transfer1_kernel, dim3(ceil_div(N, 256)), dim3(256), 0, c->stream, N,
                        (const float4 *)vtab, (const int32_t *)c->faces.p, bind_face, bind_bary,
                        means, quats, scales, means_out, quats_out, cov3d_out, xform_out);
   return hipGetLastError();

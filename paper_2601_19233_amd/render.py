@@ -5,6 +5,7 @@ provides device memory and the stream.  Names follow the C entry points.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 from typing import Dict, List, Optional, Sequence
 
@@ -53,7 +54,7 @@ def camera_struct(cam) -> L.Camera:
     return c
 
 
-def make_options(tile=(16, 16), frag_batch=128, sh_degree=0, k_bind=8, mode=0,
+def make_options(tile=(16, 16), frag_batch=128, sh_degree=0, k_bind=8, mode=0, schedule=0,
                  bg=(0.0, 0.0, 0.0)) -> L.Options:
     o = L.Options()
     o.tile_w, o.tile_h = int(tile[0]), int(tile[1])
@@ -61,19 +62,30 @@ def make_options(tile=(16, 16), frag_batch=128, sh_degree=0, k_bind=8, mode=0,
     o.sh_degree = int(sh_degree)
     o.k_bind = int(k_bind)
     o.mode = int(mode)
+    o.schedule = int(schedule)
     for k in range(3):
         o.bg[k] = float(bg[k])
     return o
 
 
 class Rasterizer:
-    """One library context bound to a torch stream on one device."""
+    """One library context bound to a stream on one device.
 
-    def __init__(self, device="cuda:0", stream: Optional[torch.cuda.Stream] = None, **opts):
+    By default the context uses the caller's current stream.  With
+    ``own_stream=True`` (needed for graph capture, since the null stream
+    cannot be captured) it gets a stream of its own at default priority, and
+    every call orders it after the caller's current stream and the caller's
+    stream after it."""
+
+    def __init__(self, device="cuda:0", stream: Optional[torch.cuda.Stream] = None,
+                 own_stream: bool = False, **opts):
         self.lib = L.load()
         self.device = torch.device(device)
         torch.cuda.set_device(self.device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if stream is None:
+            stream = torch.cuda.Stream(self.device) if own_stream else torch.cuda.current_stream(self.device)
+        self.stream = stream
+        self._capturing = False
         self.opts = make_options(**opts)
         h = C.c_void_p()
         st = self.lib.umgs_create(C.byref(h), C.byref(self.opts), C.c_void_p(self.stream.cuda_stream))
@@ -99,6 +111,20 @@ class Rasterizer:
         if st != L.UMGS_OK:
             raise L.UmgsError(st, self.lib.umgs_last_error(self.h).decode())
 
+    @contextlib.contextmanager
+    def _on_stream(self):
+        """Run library calls on the context stream, ordered after the caller's
+        current stream (inputs) and before it (outputs); no cross-stream
+        waits while a graph is being captured."""
+        cur = torch.cuda.current_stream(self.device)
+        other = cur.cuda_stream != self.stream.cuda_stream
+        if other and not self._capturing:
+            self.stream.wait_stream(cur)
+        with torch.cuda.stream(self.stream):
+            yield
+        if other and not self._capturing:
+            cur.wait_stream(self.stream)
+
     def set_options(self, **opts):
         self.opts = make_options(**opts)
         self._check(self.lib.umgs_set_options(self.h, C.byref(self.opts)))
@@ -113,7 +139,7 @@ class Rasterizer:
                                             F.shape[0], F.ctypes.data_as(C.c_void_p)))
 
     def bind_transfer(self, V_def, bind_face, bind_bary, means, quats, scales,
-                      with_vertex: bool = False) -> Dict[str, torch.Tensor]:
+                      with_vertex: bool = False, out: Optional[Dict] = None) -> Dict[str, torch.Tensor]:
         d = self.device
         V_def, means, quats, scales = (_f32(x, d) for x in (V_def, means, quats, scales))
         if isinstance(bind_face, np.ndarray) and bind_face.size and (
@@ -125,10 +151,11 @@ class Rasterizer:
         K = self.opts.k_bind
         if bind_face.numel() != N * K or bind_bary.numel() != 2 * N * K:
             raise ValueError(f"bindings must be (N, {K}) faces and (N, {K}, 2) barycentrics")
-        out = dict(means=torch.empty((N, 3), device=d), quats=torch.empty((N, 4), device=d),
-                   cov3d=torch.empty((N, 6), device=d), xform=torch.empty((N, 9), device=d))
+        if out is None:
+            out = dict(means=torch.empty((N, 3), device=d), quats=torch.empty((N, 4), device=d),
+                       cov3d=torch.empty((N, 6), device=d), xform=torch.empty((N, 9), device=d))
         vert = torch.empty((self.nV, 12), device=d) if with_vertex else None
-        with torch.cuda.stream(self.stream):
+        with self._on_stream():
             self._check(self.lib.umgs_bind_transfer(
                 self.h, _ptr(V_def), N, _ptr(bind_face), _ptr(bind_bary), _ptr(means), _ptr(quats),
                 _ptr(scales), _ptr(out["means"]), _ptr(out["quats"]), _ptr(out["cov3d"]),
@@ -159,27 +186,59 @@ class Rasterizer:
             raise ValueError("tri_xyz must hold 9 floats per triangle")
         arr = (L.Camera * len(cams))(*[camera_struct(c) for c in cams])
         self._keep = [means, opacity, sh, scales, quats, cov3d, tri_xyz, tri_rgb, tri_alpha]
-        self._check(self.lib.umgs_project(self.h, len(cams), arr, N, _ptr(means), _ptr(cov3d), _ptr(scales),
-                                          _ptr(quats), _ptr(opacity), _ptr(sh), T, _ptr(tri_xyz),
-                                          _ptr(tri_rgb), _ptr(tri_alpha)))
+        with self._on_stream():
+            self._check(self.lib.umgs_project(self.h, len(cams), arr, N, _ptr(means), _ptr(cov3d),
+                                              _ptr(scales), _ptr(quats), _ptr(opacity), _ptr(sh), T,
+                                              _ptr(tri_xyz), _ptr(tri_rgb), _ptr(tri_alpha)))
         self.views = [(int(c.width), int(c.height)) for c in cams]
         self.N, self.T = N, T
+        self.frame_id = getattr(self, "frame_id", 0) + 1
 
     def bin(self):
-        self._check(self.lib.umgs_bin(self.h))
+        with self._on_stream():
+            self._check(self.lib.umgs_bin(self.h))
 
     def sort(self):
-        self._check(self.lib.umgs_sort(self.h))
+        with self._on_stream():
+            self._check(self.lib.umgs_sort(self.h))
 
-    def blend(self, want_state: bool = True) -> Dict[str, torch.Tensor]:
+    def alloc_outputs(self, want_state: bool = True) -> Dict[str, torch.Tensor]:
         d = self.device
         npix = sum(w * h for w, h in self.views)
-        image = torch.empty(3 * npix, device=d)
-        Tf = torch.empty(npix, device=d) if want_state else None
-        nc = torch.empty(npix, device=d, dtype=torch.int32) if want_state else None
-        Te = torch.empty(npix, device=d) if want_state else None
-        self._check(self.lib.umgs_blend(self.h, _ptr(image), _ptr(Tf), _ptr(nc), _ptr(Te)))
-        return dict(image=image, T_final=Tf, n_contrib=nc, T_entity_in=Te)
+        return dict(image=torch.empty(3 * npix, device=d),
+                    T_final=torch.empty(npix, device=d) if want_state else None,
+                    n_contrib=torch.empty(npix, device=d, dtype=torch.int32) if want_state else None,
+                    T_entity_in=torch.empty(npix, device=d) if want_state else None)
+
+    def blend(self, want_state: bool = True, out: Optional[Dict] = None) -> Dict[str, torch.Tensor]:
+        if out is None:
+            out = self.alloc_outputs(want_state)
+        with self._on_stream():
+            self._check(self.lib.umgs_blend(self.h, _ptr(out["image"]), _ptr(out["T_final"]),
+                                            _ptr(out["n_contrib"]), _ptr(out["T_entity_in"])))
+        return out
+
+    def backward(self, dL_dimage: torch.Tensor, fwd: Dict[str, torch.Tensor], means, scales, quats,
+                 sh, xform=None, out: Optional[Dict] = None) -> Dict[str, torch.Tensor]:
+        """Gradients of the last blended frame (umgs_backward).  ``fwd`` is the
+        dict returned by blend(); ``means`` are the projected means."""
+        d = self.device
+        means, scales, quats, sh, xform = (_f32(x, d) for x in (means, scales, quats, sh, xform))
+        dL = _f32(dL_dimage, d)
+        N = self.N
+        nc = 3 * (self.opts.sh_degree + 1) ** 2
+        if out is None:
+            out = dict(means=torch.empty((N, 3), device=d), scales=torch.empty((N, 3), device=d),
+                       quats=torch.empty((N, 4), device=d), opacity=torch.empty((N,), device=d),
+                       sh=torch.empty((N, nc), device=d))
+        if dL.numel() != fwd["image"].numel():
+            raise ValueError("dL_dimage must have the image's shape")
+        with self._on_stream():
+            self._check(self.lib.umgs_backward(
+                self.h, _ptr(dL), _ptr(fwd["T_final"]), _ptr(fwd["n_contrib"]), _ptr(fwd["T_entity_in"]),
+                _ptr(means), _ptr(scales), _ptr(quats), _ptr(xform), _ptr(sh), _ptr(out["means"]),
+                _ptr(out["scales"]), _ptr(out["quats"]), _ptr(out["opacity"]), _ptr(out["sh"])))
+        return out
 
     def render(self, cams, **scene) -> Dict[str, torch.Tensor]:
         self.project(cams, **scene)
@@ -211,9 +270,59 @@ class Rasterizer:
 
     # ---- inspection ---------------------------------------------------------
     def query(self):
+        """(n_dup, n_tiles, n_records); synchronizes."""
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
-        self._check(self.lib.umgs_query(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        self._check(self.lib.umgs_query(self.h, C.byref(a), C.byref(b), C.byref(c), None))
         return a.value, b.value, c.value
+
+    def overflowed(self) -> bool:
+        """Whether duplicates were dropped for lack of reserved capacity since
+        the last call (clears the flag); synchronizes."""
+        f = C.c_int32()
+        self._check(self.lib.umgs_query(self.h, None, None, None, C.byref(f)))
+        return bool(f.value)
+
+    def blend_pairs(self):
+        """(Gaussian pairs, triangle pairs) the blend evaluates on the sorted frame."""
+        out = self.alloc_outputs(False)
+        pairs = (C.c_int64 * 2)()
+        with self._on_stream():
+            self._check(self.lib.umgs_blend_pairs(self.h, _ptr(out["image"]), pairs))
+        return int(pairs[0]), int(pairs[1])
+
+    # ---- graphs ---------------------------------------------------------------
+    def reserve(self, max_dup: int):
+        self._check(self.lib.umgs_reserve(self.h, int(max_dup)))
+
+    def capture(self, fn):
+        """Record the library calls that ``fn()`` makes into a graph (after
+        an eager frame of the same shape and a reserve()).  Output tensors
+        that fn allocates must be kept alive by the caller: replays write
+        into them."""
+        if self.stream.cuda_stream == 0:
+            raise ValueError("graph capture needs a Rasterizer with its own stream (own_stream=True)")
+        cur = torch.cuda.current_stream(self.device)
+        self.stream.wait_stream(cur)
+        self._check(self.lib.umgs_graph_begin(self.h))
+        self._capturing = True
+        try:
+            out = fn()
+        except BaseException:
+            self._capturing = False
+            self.lib.umgs_graph_end(self.h)
+            raise
+        self._capturing = False
+        self._check(self.lib.umgs_graph_end(self.h))
+        return out
+
+    def replay(self):
+        with self._on_stream():
+            self._check(self.lib.umgs_graph_launch(self.h))
+
+    def update_views(self, cams):
+        arr = (L.Camera * len(cams))(*[camera_struct(c) for c in cams])
+        with self._on_stream():
+            self._check(self.lib.umgs_update_views(self.h, len(cams), arr))
 
     def copy_state(self, which: int) -> torch.Tensor:
         n_dup, n_tiles, n_rec = self.query()
@@ -230,7 +339,8 @@ class Rasterizer:
             t = torch.empty((len(self.views) * self.T, 6), dtype=torch.int32, device=d)
         else:
             raise ValueError(which)
-        self._check(self.lib.umgs_copy_state(self.h, which, _ptr(t), t.numel() * t.element_size()))
+        with self._on_stream():
+            self._check(self.lib.umgs_copy_state(self.h, which, _ptr(t), t.numel() * t.element_size()))
         torch.cuda.synchronize(d)
         return t
 
@@ -246,3 +356,55 @@ def scene_inputs(scene, cov3d=None, means=None) -> Dict:
         kw["scales"] = scene.scales
         kw["quats"] = scene.quats
     return kw
+
+
+class _RenderFunction(torch.autograd.Function):
+    """Differentiable render of Gaussians (+ fixed triangles) through the C ABI."""
+
+    @staticmethod
+    def forward(ctx, means, scales, quats, opacity, sh, rast, cams, tris, deform):
+        with torch.no_grad():
+            if deform is not None:
+                dt = rast.bind_transfer(deform["V_def"], deform["bind_face"], deform["bind_bary"],
+                                        means, quats, scales)
+                pm, cov, xform = dt["means"], dt["cov3d"], dt["xform"]
+            else:
+                pm, cov, xform = means, None, None
+            rast.project(cams, means=pm, cov3d=cov, scales=None if cov is not None else scales,
+                         quats=None if cov is not None else quats, opacity=opacity,
+                         sh=sh.reshape(sh.shape[0], -1), **tris)
+            rast.bin()
+            rast.sort()
+            out = rast.blend(want_state=True)
+        ctx.rast = rast
+        ctx.frame_id = rast.frame_id
+        ctx.fwd = out
+        ctx.save_for_backward(pm.detach(), scales.detach(), quats.detach(), sh.detach(),
+                              xform if xform is not None else torch.empty(0, device=means.device))
+        ctx.has_xform = xform is not None
+        ctx.sh_shape = sh.shape
+        return out["image"]
+
+    @staticmethod
+    def backward(ctx, dL_dimage):
+        rast = ctx.rast
+        if rast.frame_id != ctx.frame_id:
+            raise RuntimeError("the rasterizer has projected another frame since this forward; "
+                               "run backward before the next forward on the same Rasterizer")
+        pm, scales, quats, sh, xform = ctx.saved_tensors
+        g = rast.backward(dL_dimage.contiguous(), ctx.fwd, pm, scales, quats,
+                          sh.reshape(sh.shape[0], -1), xform if ctx.has_xform else None)
+        return (g["means"], g["scales"], g["quats"], g["opacity"], g["sh"].reshape(ctx.sh_shape),
+                None, None, None, None)
+
+
+def render_differentiable(rast: Rasterizer, cams, means, scales, quats, opacity, sh, tri_xyz=None,
+                          tri_rgb=None, tri_alpha=None, deform: Optional[Dict] = None) -> torch.Tensor:
+    """Packed image (3,H,W per view) as a differentiable function of the
+    Gaussians' means, linear scales, raw quaternions, opacities and SH
+    coefficients.  ``deform`` = dict(V_def, bind_face, bind_bary) moves the
+    Gaussians with the proxy set by ``rast.set_proxy`` first (gradients are
+    then with respect to the rest parameters).  The backward must run before
+    the next forward on the same Rasterizer."""
+    tris = dict(tri_xyz=tri_xyz, tri_rgb=tri_rgb, tri_alpha=tri_alpha)
+    return _RenderFunction.apply(means, scales, quats, opacity, sh, rast, list(cams), tris, deform)

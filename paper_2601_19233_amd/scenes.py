@@ -272,55 +272,52 @@ def _sample_on_mesh(rng, V, F, n, offset):
 # ----------------------------------------------------------------------------
 
 def _closest_on_triangles(P, A, B, C):
-    """Closest point on triangles (A,B,C) to P, vectorised (Ericson's regions).
-
-    Returns barycentric (u, v, w) of the closest point w.r.t. (A, B, C) and
-    the squared distance.
-    """
+    """Closest point on triangles (A,B,C) to P, vectorised: the projection onto
+    the plane when it falls inside the triangle, else the nearest point on the
+    three edges.  Returns barycentrics (u, v, w) w.r.t. (A, B, C) and the
+    squared distance."""
     ab, ac, ap = B - A, C - A, P - A
-    d1 = (ab * ap).sum(-1); d2 = (ac * ap).sum(-1)
-    bp = P - B
-    d3 = (ab * bp).sum(-1); d4 = (ac * bp).sum(-1)
-    cp = P - C
-    d5 = (ab * cp).sum(-1); d6 = (ac * cp).sum(-1)
-    va = d3 * d6 - d5 * d4
-    vb = d5 * d2 - d1 * d6
-    vc = d1 * d4 - d3 * d2
-    shape = d1.shape
-    u = np.zeros(shape); v = np.zeros(shape); w = np.zeros(shape)
-    done = np.zeros(shape, bool)
-
-    def setr(mask, uu, vv, ww):
-        nonlocal done
-        m = mask & ~done
-        u[m] = uu[m] if np.ndim(uu) else uu
-        v[m] = vv[m] if np.ndim(vv) else vv
-        w[m] = ww[m] if np.ndim(ww) else ww
-        done |= m
-
-    one = np.ones(shape); zero = np.zeros(shape)
-    setr((d1 <= 0) & (d2 <= 0), one, zero, zero)                       # A
-    setr((d3 >= 0) & (d4 <= d3), zero, one, zero)                       # B
+    d00 = (ab * ab).sum(-1)
+    d01 = (ab * ac).sum(-1)
+    d11 = (ac * ac).sum(-1)
+    d20 = (ap * ab).sum(-1)
+    d21 = (ap * ac).sum(-1)
+    den = d00 * d11 - d01 * d01
     with np.errstate(divide="ignore", invalid="ignore"):
-        t = d1 / (d1 - d3)
-        setr((vc <= 0) & (d1 >= 0) & (d3 <= 0), 1 - t, t, zero)         # AB
-        setr((d6 >= 0) & (d5 <= d6), zero, zero, one)                   # C
-        t = d2 / (d2 - d6)
-        setr((vb <= 0) & (d2 >= 0) & (d6 <= 0), 1 - t, zero, t)         # AC
-        t = (d4 - d3) / ((d4 - d3) + (d5 - d6))
-        setr((va <= 0) & ((d4 - d3) >= 0) & ((d5 - d6) >= 0), zero, 1 - t, t)  # BC
-        den = 1.0 / (va + vb + vc)
-        vv = vb * den; ww = vc * den
-        setr(np.ones(shape, bool), 1 - vv - ww, vv, ww)                 # interior
+        bv = (d11 * d20 - d01 * d21) / den
+        bw = (d00 * d21 - d01 * d20) / den
+    bu = 1.0 - bv - bw
+    inside = (bu >= 0) & (bv >= 0) & (bw >= 0)
+
+    def seg(X, Y):
+        xy = Y - X
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t = np.clip(((P - X) * xy).sum(-1) / (xy * xy).sum(-1), 0.0, 1.0)
+        t = np.nan_to_num(t)
+        Q = X + t[..., None] * xy
+        return t, ((P - Q) ** 2).sum(-1)
+
+    t_ab, e_ab = seg(A, B)
+    t_bc, e_bc = seg(B, C)
+    t_ca, e_ca = seg(C, A)
+    best = np.argmin(np.stack([e_ab, e_bc, e_ca], -1), axis=-1)
+    z = np.zeros_like(t_ab)
+    eu = np.choose(best, [1 - t_ab, z, t_ca])
+    ev = np.choose(best, [t_ab, 1 - t_bc, z])
+    ew = np.choose(best, [z, t_bc, 1 - t_ca])
+    u = np.where(inside, bu, eu)
+    v = np.where(inside, bv, ev)
+    w = np.where(inside, bw, ew)
     Q = u[..., None] * A + v[..., None] * B + w[..., None] * C
-    d2s = ((P - Q) ** 2).sum(-1)
-    return u, v, w, d2s
+    return u, v, w, ((P - Q) ** 2).sum(-1)
 
 
-def bind_nearest(points, V, F, candidates: int = 8, chunk: int = 1 << 18):
+def bind_nearest(points, V, F, candidates: int = 8, chunk: int = 1 << 15):
     """Associate each point with the nearest proxy face (among the faces whose
     centroids are the ``candidates`` nearest), returning (face, u, v) with
-    the closest point = u*V[f0] + v*V[f1] + (1-u-v)*V[f2]."""
+    the closest point = u*V[f0] + v*V[f1] + (1-u-v)*V[f2].  Chunks run on a
+    thread pool (NumPy releases the GIL in its array operations)."""
+    from concurrent.futures import ThreadPoolExecutor
     from scipy.spatial import cKDTree
     cen = V[F].mean(axis=1)
     tree = cKDTree(cen)
@@ -328,9 +325,10 @@ def bind_nearest(points, V, F, candidates: int = 8, chunk: int = 1 << 18):
     face = np.empty(n, np.int32)
     bu = np.empty(n, np.float32)
     bv = np.empty(n, np.float32)
-    for s in range(0, n, chunk):
+
+    def work(s):
         P = points[s:s + chunk]
-        _, cand = tree.query(P, k=candidates, workers=-1)
+        _, cand = tree.query(P, k=candidates)
         A, B, C = V[F[cand, 0]], V[F[cand, 1]], V[F[cand, 2]]
         u, v, w, d2 = _closest_on_triangles(P[:, None, :], A, B, C)
         best = np.argmin(d2, axis=1)
@@ -338,6 +336,9 @@ def bind_nearest(points, V, F, candidates: int = 8, chunk: int = 1 << 18):
         face[s:s + chunk] = cand[r, best]
         bu[s:s + chunk] = u[r, best]
         bv[s:s + chunk] = v[r, best]
+
+    with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+        list(ex.map(work, range(0, n, chunk)))
     return face, bu, bv
 
 

@@ -1,0 +1,192 @@
+"""Full-size workloads on the GPU, checked against the oracle on sampled
+outputs.
+
+* 1920x1080, 1M deformed Gaussians + 100,128 triangles (the benchmark frame,
+  same launch configuration): pinned deformed means and depth keys of every
+  primitive bit-exact; 160 sampled pixels within 1e-4 (plus the last blended
+  fragment's id); sampled gradients of the backward against the oracle
+  gradient restricted to those pixels.
+* 800x800, 300k Gaussians with SH degree 3 + 50,176 triangles: sampled pixels.
+* 64 views of uneven size, 500k Gaussians (captured graph, persistent
+  schedule): sampled pixels on four views.
+* 16 views at 1080p, 2M deformed Gaussians with SH degree 3 + 200k
+  triangles (captured forward+backward graph): sampled pixels on two views.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import grad as OG
+from oracle import render as OR
+from oracle import transfer as OT
+from paper_2601_19233_amd import scenes
+from tests import _parity as PT
+
+pytestmark = pytest.mark.gpu
+
+
+def note(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def sample_pixels(cam, n, seed):
+    rng = np.random.default_rng(seed)
+    return list(zip(rng.integers(0, cam.width, n).tolist(), rng.integers(0, cam.height, n).tolist()))
+
+
+def dev_tensors(s):
+    import torch
+    dev = torch.device("cuda:0")
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
+    out = dict(means=f(s.means), scales=f(s.scales), quats=f(s.quats), opacity=f(s.opacity),
+               sh=f(s.sh.reshape(s.N, -1)), tri_xyz=f(s.tri_xyz.reshape(s.T, 9)),
+               tri_rgb=f(s.tri_rgb.reshape(s.T, 9)), tri_alpha=f(s.tri_alpha))
+    if s.proxy is not None:
+        out["deform"] = dict(V_def=f(s.proxy.V_def),
+                             bind_face=torch.from_numpy(s.bind_face.astype(np.int32)).to(dev),
+                             bind_bary=f(s.bind_bary))
+    return out
+
+
+def check_view(fr, r, out, v, pixels):
+    img = r.split_views(out["image"], 3)[v].cpu().numpy()
+    Tf = r.split_views(out["T_final"], 1)[v].cpu().numpy()
+    return PT.compare_pixels(fr, img, Tf, None, pixels)
+
+
+@pytest.fixture(scope="module")
+def cfg1():
+    return scenes.make_config(1)
+
+
+def test_cfg1_full_frame(gpu, cfg1):
+    import torch
+    from paper_2601_19233_amd import _lib as L
+    from paper_2601_19233_amd.render import Rasterizer
+    from tests.test_gpu_forward import last_gids
+    s = cfg1
+    cam = s.cams[0]
+    note(f"cfg1 full: N={s.N} T={s.T} {cam.width}x{cam.height}")
+    d = dev_tensors(s)
+    r = Rasterizer("cuda:0", tile=(16, 16), frag_batch=128)
+    r.set_proxy(s.proxy.V_rest, s.proxy.faces)
+    df = d["deform"]
+    dt = r.bind_transfer(df["V_def"], df["bind_face"], df["bind_bary"], d["means"], d["quats"], d["scales"])
+    out = r.render([cam], means=dt["means"], cov3d=dt["cov3d"], opacity=d["opacity"], sh=d["sh"],
+                   tri_xyz=d["tri_xyz"], tri_rgb=d["tri_rgb"], tri_alpha=d["tri_alpha"])
+    torch.cuda.synchronize()
+    ot = OT.transfer(s.proxy.V_rest, s.proxy.faces, s.proxy.V_def, s.means, s.quats, s.scales,
+                     s.bind_face, s.bind_bary)
+    assert np.array_equal(dt["means"].cpu().numpy(), ot["means"])
+    fr = OR.Frame(cam, ot["means"], s.opacity, s.sh, 0, s.tri_xyz, s.tri_rgb, s.tri_alpha, cov3d=ot["cov3d"])
+    keys = r.copy_state(L.STATE_KEYS).cpu().numpy().view(np.uint32)
+    live = s.opacity.astype(np.float32) * np.float32(255) > 1
+    gk = np.where(fr.g.valid & live, fr.g.key.view(np.uint32), np.uint32(0xFFFFFFFF))
+    tk = np.where(fr.t.valid, fr.t.key.view(np.uint32), np.uint32(0xFFFFFFFF))
+    # a Gaussian whose FP32 2D covariance loses positive definiteness could be
+    # culled on one side only; none may differ in its key otherwise
+    g_gpu = keys[: s.N]
+    both = (g_gpu != 0xFFFFFFFF) & (gk != 0xFFFFFFFF)
+    assert np.array_equal(g_gpu[both], gk[both])
+    assert np.sum((g_gpu == 0xFFFFFFFF) != (gk == 0xFFFFFFFF)) <= 2
+    assert np.array_equal(keys[s.N:], tk)
+    nc = r.split_views(out["n_contrib"], 1)[0].cpu().numpy()
+    lg = last_gids(r, nc)
+    px = sample_pixels(cam, 160, 11)
+    # bias half the samples to the proxy sphere's silhouette region, where lists are long
+    px += [(int(cam.cx + 330 * np.cos(a)), int(cam.cy + 330 * np.sin(a))) for a in np.linspace(0, 6.2, 40)]
+    img = r.split_views(out["image"], 3)[0].cpu().numpy()
+    Tf = r.split_views(out["T_final"], 1)[0].cpu().numpy()
+    res = PT.compare_pixels(fr, img, Tf, lg, px)
+    note(f"cfg1 full frame: {res}")
+
+    # gradients: dL nonzero only at 48 sampled pixels
+    note("cfg1 full backward (sampled pixels)")
+    gp = sample_pixels(cam, 48, 12)
+    amb = [fr.pixel(x, y).margin <= 1e-4 for x, y in gp]
+    rng = np.random.default_rng(13)
+    w = rng.normal(size=(len(gp), 3))
+    w[np.array(amb)] = 0.0
+    dL = np.zeros((3, cam.height, cam.width), np.float32)
+    for (x, y), wi in zip(gp, w):
+        dL[:, y, x] = wi
+    dLt = torch.from_numpy(dL.reshape(-1)).cuda()
+    g = r.backward(dLt, out, dt["means"], d["scales"], d["quats"], d["sh"], dt["xform"])
+    off = ot["means"].astype(np.float64) - s.means.astype(np.float64)
+    ref = OG.gradients(cam, gp, w, s.means, s.scales, s.quats, s.opacity, s.sh, 0, s.tri_xyz,
+                       s.tri_rgb, s.tri_alpha, xform=ot["A"], mean_offset=off)
+    touched = np.flatnonzero(np.abs(ref["opacity"]) > 0)
+    assert touched.size > 50
+    for n in ("means", "scales", "quats", "opacity", "sh"):
+        gg = g[n].cpu().numpy().astype(np.float64).reshape(ref[n].shape)
+        rr = ref[n]
+        scale = np.abs(rr).max()
+        err = np.abs(gg - rr)
+        bad = err > 2e-3 * np.abs(rr) + 1e-5 * scale
+        assert not bad.any(), (n, int(bad.sum()), float(err.max()), float(scale))
+
+
+def test_cfg2_full_frame(gpu):
+    import torch
+    from paper_2601_19233_amd.render import Rasterizer
+    s = scenes.make_config(2)
+    cam = s.cams[0]
+    note(f"cfg2 full: N={s.N} T={s.T}")
+    d = dev_tensors(s)
+    r = Rasterizer("cuda:0", sh_degree=3)
+    out = r.render([cam], **{k: d[k] for k in ("means", "scales", "quats", "opacity", "sh", "tri_xyz",
+                                               "tri_rgb", "tri_alpha")})
+    torch.cuda.synchronize()
+    fr = OR.Frame(cam, s.means, s.opacity, s.sh, 3, s.tri_xyz, s.tri_rgb, s.tri_alpha,
+                  scales=s.scales, quats=s.quats)
+    note(f"cfg2: {check_view(fr, r, out, 0, sample_pixels(cam, 200, 21))}")
+
+
+def test_cfg3_batched_graph(gpu):
+    import torch
+    from paper_2601_19233_amd.batched import BatchedStep
+    from paper_2601_19233_amd.render import Rasterizer
+    s = scenes.make_config(3)
+    note(f"cfg3 full: N={s.N} T={s.T} views={len(s.cams)}")
+    d = dev_tensors(s)
+    sc = {k: d[k] for k in ("means", "scales", "quats", "opacity", "sh", "tri_xyz", "tri_rgb", "tri_alpha")}
+    r = Rasterizer("cuda:0", own_stream=True, tile=(16, 16), frag_batch=128, schedule=1)
+    step = BatchedStep(r, s.cams, sc)
+    step()
+    out = step()
+    torch.cuda.synchronize()
+    assert not r.overflowed()
+    for v in (0, 17, 40, 63):
+        fr = OR.Frame(s.cams[v], s.means, s.opacity, s.sh, 0, s.tri_xyz, s.tri_rgb, s.tri_alpha,
+                      scales=s.scales, quats=s.quats)
+        note(f"cfg3 view {v} {s.cams[v].width}x{s.cams[v].height}: "
+             f"{check_view(fr, r, out, v, sample_pixels(s.cams[v], 40, 30 + v))}")
+
+
+def test_cfg4_batched_forward_backward(gpu):
+    import torch
+    from paper_2601_19233_amd.batched import BatchedStep
+    from paper_2601_19233_amd.render import Rasterizer
+    s = scenes.make_config(4)
+    note(f"cfg4 full: N={s.N} T={s.T} views={len(s.cams)}")
+    d = dev_tensors(s)
+    sc = {k: d[k] for k in ("means", "scales", "quats", "opacity", "sh", "tri_xyz", "tri_rgb", "tri_alpha")}
+    r = Rasterizer("cuda:0", own_stream=True, sh_degree=3, schedule=1)
+    r.set_proxy(s.proxy.V_rest, s.proxy.faces)
+    step = BatchedStep(r, s.cams, sc, deform=d["deform"], backward=True)
+    step.prepare()
+    step.set_loss_gradient(torch.ones_like(step.out["image"]))
+    out = step()
+    torch.cuda.synchronize()
+    assert not r.overflowed()
+    for name, gt in step.grads.items():
+        assert torch.isfinite(gt).all(), name
+    ot = OT.transfer(s.proxy.V_rest, s.proxy.faces, s.proxy.V_def, s.means, s.quats, s.scales,
+                     s.bind_face, s.bind_bary)
+    for v in (0, 9):
+        fr = OR.Frame(s.cams[v], ot["means"], s.opacity, s.sh, 3, s.tri_xyz, s.tri_rgb, s.tri_alpha,
+                      cov3d=ot["cov3d"])
+        note(f"cfg4 view {v}: {check_view(fr, r, out, v, sample_pixels(s.cams[v], 25, 50 + v))}")
