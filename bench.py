@@ -96,7 +96,9 @@ def run_batched(scene, args, deform, sc):
     tsc = dict(means=dt["means"], cov3d=dt["cov3d"], opacity=sc["opacity"], sh=sc["sh"],
                tri_xyz=sc["tri_xyz"], tri_rgb=sc["tri_rgb"], tri_alpha=sc["tri_alpha"])
     t0 = time.time()
-    best = autotune.tune(cams, tsc, sh_degree=scene.sh_degree, k_bind=k_bind, reps=2,
+    # tuned on the first four views (one frame of them fits the key buffers at
+    # every tile shape); the step itself renders all views in budgeted groups
+    best = autotune.tune(cams[:4], tsc, sh_degree=scene.sh_degree, k_bind=k_bind, reps=2,
                          batches=(64, 128, 256), use_cache=False)
     log(f"autotune {best['tile']} batch {best['frag_batch']} schedule {best['schedule']} "
         f"in {time.time() - t0:.1f} s")
@@ -147,6 +149,7 @@ def run_batched(scene, args, deform, sc):
         res[f"{key}_mpix_s"] = round(V * W * H / (ms * 1e-3) / 1e6, 2)
         res[f"{key}_ms_per_step"] = round(ms, 3)
         res["n_dup"] = int(step.n_dup_seen)
+        res["groups"] = [list(g) for g in step.groups]
         log(f"batched {key}: {ms:.2f} ms per {V}-view step")
         del step, rb
         torch.cuda.empty_cache()

@@ -180,9 +180,11 @@ umgs_status umgs_blend(umgs_ctx *ctx, float *image, float *T_final, int32_t *n_c
  * Sigma(scales, quats) when xform is NULL (deformed scenes pass the A
  * written by umgs_bind_transfer; the mean offset is constant, so the
  * gradient of the rest mean equals that of the deformed mean).
- * Outputs [device], written (not accumulated): dL_dmeans (N,3),
- * dL_dscales (N,3) w.r.t. linear scales, dL_dquats (N,4) w.r.t. the raw
- * quaternion before normalisation, dL_dopacity (N,), dL_dsh (N,(deg+1)^2,3).
+ * Outputs [device]: dL_dmeans (N,3), dL_dscales (N,3) w.r.t. linear scales,
+ * dL_dquats (N,4) w.r.t. the raw quaternion before normalisation,
+ * dL_dopacity (N,), dL_dsh (N,(deg+1)^2,3); written when accumulate is 0,
+ * added to their contents otherwise (to sum over groups of views rendered
+ * by separate frames).
  * Triangles receive no gradients.  Float atomics make the summation order,
  * hence the last bits, run-dependent.  Errors: STATE without a blended
  * frame; UNSUPPORTED for UMGS_MODE_ONE_ENTITY and UMGS_MODE_LITERAL_T;
@@ -191,7 +193,7 @@ umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_
                           const int32_t *n_contrib, const float *T_entity_in, const float *means,
                           const float *scales, const float *quats, const float *xform,
                           const float *sh, float *dL_dmeans, float *dL_dscales, float *dL_dquats,
-                          float *dL_dopacity, float *dL_dsh);
+                          float *dL_dopacity, float *dL_dsh, int32_t accumulate);
 
 /* ---- graphs: capture one step, replay it ----------------------------------- */
 
@@ -202,19 +204,26 @@ umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_
 umgs_status umgs_reserve(umgs_ctx *ctx, int64_t max_dup);
 /* Begin capturing the context stream into a graph: the entry points called
  * until umgs_graph_end are recorded, not run.  Requires a reservation,
- * profiling off, and umgs_project with the cameras of the last eager frame
- * (update them between replays with umgs_update_views).  Any entry point
- * that would allocate or synchronize while capturing fails with STATE or
- * CAPACITY.  Errors: STATE, HIP. */
+ * profiling off, a non-null stream, and umgs_project calls with camera sets
+ * that eager frames have used before (the context keeps one device table per
+ * distinct camera set; a frame rendered in several view groups has one per
+ * group).  Any entry point that would allocate or synchronize while
+ * capturing fails with STATE or CAPACITY.  Errors: STATE, HIP. */
 umgs_status umgs_graph_begin(umgs_ctx *ctx);
 /* End the capture and instantiate the graph (replacing any previous one). */
 umgs_status umgs_graph_end(umgs_ctx *ctx);
 /* Launch the instantiated graph on the context stream (asynchronous). */
 umgs_status umgs_graph_launch(umgs_ctx *ctx);
-/* Upload new cameras [host] for the next replays; V and every view's width
- * and height must equal those of the captured frame.  Asynchronous on the
- * stream.  Errors: INVALID_ARG, STATE. */
-umgs_status umgs_update_views(umgs_ctx *ctx, int32_t V, const umgs_camera *cams);
+/* Replace the stored camera set old_cams [host] (V views) by new_cams for the
+ * next replays; every view keeps its width and height.  Asynchronous on the
+ * stream.  Errors: INVALID_ARG, STATE (no stored set equals old_cams). */
+umgs_status umgs_update_views(umgs_ctx *ctx, int32_t V, const umgs_camera *old_cams,
+                              const umgs_camera *new_cams);
+/* Duplicates each view of the projected frame will produce, dups [host] (V
+ * entries), before umgs_bin allocates anything: used to split a batch whose
+ * duplicates exceed the 32-bit positions of one frame into view groups.
+ * Runs the count scan if needed; synchronous.  Errors: STATE. */
+umgs_status umgs_view_dups(umgs_ctx *ctx, int64_t *dups);
 
 /* Measurement: blend the sorted frame again into image [device] while
  * counting, over all pixels, the fragments each pixel evaluates before it is

@@ -52,9 +52,10 @@ PROTOTYPES = {
     "umgs_graph_begin": (C.c_int, [P]),
     "umgs_graph_end": (C.c_int, [P]),
     "umgs_graph_launch": (C.c_int, [P]),
-    "umgs_update_views": (C.c_int, [P, I32, C.POINTER(Camera)]),
+    "umgs_update_views": (C.c_int, [P, I32, C.POINTER(Camera), C.POINTER(Camera)]),
+    "umgs_view_dups": (C.c_int, [P, C.POINTER(I64)]),
     "umgs_copy_state": (C.c_int, [P, I32, P, I64]),
-    "umgs_backward": (C.c_int, [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P]),
+    "umgs_backward": (C.c_int, [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, I32]),
     "umgs_set_profiling": (C.c_int, [P, I32]),
     "umgs_profile_read": (C.c_int, [P, I32, C.POINTER(I64), C.POINTER(C.c_double)]),
 }

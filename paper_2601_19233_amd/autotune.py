@@ -17,6 +17,7 @@ from typing import Dict, Iterable, Optional, Sequence, Tuple
 
 import torch
 
+from . import _lib as L
 from .render import Rasterizer
 
 TILES = ((8, 8), (16, 16), (32, 8))
@@ -75,7 +76,15 @@ def tune(cams: Sequence, scene: Dict[str, torch.Tensor], sh_degree: int = 0, k_b
             for sched in schedules:
                 r.set_options(tile=tile, frag_batch=batch, sh_degree=sh_degree, k_bind=k_bind,
                               schedule=sched)
-                r.render(cams, **scene)          # warm-up (allocation)
+                try:
+                    r.render(cams, **scene)      # warm-up (allocation)
+                except L.UmgsError as e:
+                    # too many duplicates for one frame with this tile shape
+                    if e.status != -2:              # CAPACITY
+                        raise
+                    if verbose:
+                        print(f"[autotune] {tile} skipped: {e}", flush=True)
+                    break
                 blend_ms, frame_ms = [], []
                 for _ in range(reps):
                     r.set_profiling(True)
@@ -94,6 +103,8 @@ def tune(cams: Sequence, scene: Dict[str, torch.Tensor], sh_degree: int = 0, k_b
                 if verbose:
                     print(f"[autotune] {res}", flush=True)
         r.close()
+    if not results:
+        raise RuntimeError("autotune: no candidate could render the frame")
     best_blend = min(x["blend_ms"] for x in results)
     near = [x for x in results if x["blend_ms"] <= best_blend * 1.02]
     best = min(near, key=lambda x: x["frame_ms"])

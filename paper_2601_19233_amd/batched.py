@@ -1,15 +1,20 @@
 """Batched multi-view step: one frame of V views rendered (and optionally
 differentiated) by a captured HIP graph.
 
-The first call runs the step eagerly to size every buffer, reserves key
-capacity for ``headroom`` times the duplicates it saw, captures the step on
-the rasterizer's stream, and from then on each step is one graph launch with
-all sizes read on the device.  Views share one global tile space: every
-kernel of the path runs once for all views.
+Planning runs once: the deformation transfer and the projection of all views
+give every view's duplicate count (``view_dups``) before anything is sorted;
+consecutive views are grouped so that no group exceeds ``group_budget``
+duplicates (32-bit sort positions, bounded key memory).  One eager step then
+renders every group (allocating buffers and storing one device view table
+per group), key capacity is reserved for the largest group times
+``headroom``, and the whole step -- transfer, then per group project, bin,
+sort, blend and (optionally) backward, gradients summed over groups -- is
+captured on the rasterizer's stream.  Each later step is one graph launch
+with all sizes read on the device.
 """
 from __future__ import annotations
 
-from typing import Dict, Optional, Sequence
+from typing import Dict, List, Optional, Sequence, Tuple
 
 import torch
 
@@ -19,7 +24,7 @@ from .render import Rasterizer
 class BatchedStep:
     def __init__(self, rast: Rasterizer, cams: Sequence, scene: Dict[str, torch.Tensor],
                  deform: Optional[Dict[str, torch.Tensor]] = None, backward: bool = False,
-                 headroom: float = 1.25):
+                 headroom: float = 1.25, group_budget: int = 1_500_000_000):
         """scene: device tensors means, opacity, sh (N, nc*3), scales, quats and
         optionally tri_xyz, tri_rgb, tri_alpha.  deform: V_def, bind_face,
         bind_bary (the proxy must already be set on ``rast``).  ``rast`` must
@@ -33,42 +38,99 @@ class BatchedStep:
         self.deform = deform
         self.do_backward = backward
         self.headroom = headroom
+        self.group_budget = int(group_budget)
         self.graph_ready = False
         self.tout = None
         self.out = None
         self.grads = None
         self.dL = None
+        self.groups: List[Tuple[int, int]] = []
+        self.n_dup_seen = 0
+        npix = [c.width * c.height for c in self.cams]
+        self.pix0 = [0]
+        for n in npix:
+            self.pix0.append(self.pix0[-1] + n)
 
+    # -- helpers ------------------------------------------------------------
+    def _tris(self):
+        return {k: self.scene[k] for k in ("tri_xyz", "tri_rgb", "tri_alpha") if k in self.scene}
+
+    def _transfer(self):
+        s, d = self.scene, self.deform
+        if d is None:
+            return
+        self.tout = self.r.bind_transfer(d["V_def"], d["bind_face"], d["bind_bary"], s["means"],
+                                         s["quats"], s["scales"], out=self.tout)
+
+    def _project(self, cams):
+        s = self.scene
+        if self.deform is not None:
+            self.r.project(cams, means=self.tout["means"], cov3d=self.tout["cov3d"],
+                           opacity=s["opacity"], sh=s["sh"], **self._tris())
+        else:
+            self.r.project(cams, means=s["means"], scales=s["scales"], quats=s["quats"],
+                           opacity=s["opacity"], sh=s["sh"], **self._tris())
+
+    def _slice(self, a, b):
+        p0, p1 = self.pix0[a], self.pix0[b]
+        o = self.out
+        return dict(image=o["image"][3 * p0:3 * p1], T_final=o["T_final"][p0:p1],
+                    n_contrib=o["n_contrib"][p0:p1], T_entity_in=o["T_entity_in"][p0:p1])
+
+    # -- planning -----------------------------------------------------------
+    def plan(self) -> List[Tuple[int, int]]:
+        """Group consecutive views so each group stays within the budget."""
+        self._transfer()
+        dups: List[int] = []
+        step = max(1, min(len(self.cams), 64))
+        for a in range(0, len(self.cams), step):
+            self._project(self.cams[a:a + step])
+            dups += self.r.view_dups()
+        groups, a, acc = [], 0, 0
+        for v, n in enumerate(dups):
+            if n >= 0xFFFF0000:
+                raise RuntimeError(f"view {v} alone produces {n} duplicates (32-bit positions)")
+            if v > a and acc + n > self.group_budget:
+                groups.append((a, v))
+                a, acc = v, 0
+            acc += n
+        groups.append((a, len(dups)))
+        self.view_dup_counts = dups
+        self.groups = groups
+        self.max_group_dups = max(sum(dups[a:b]) for a, b in groups)
+        return groups
+
+    # -- the step -----------------------------------------------------------
     def _step(self):
         s, r = self.scene, self.r
-        tris = {k: s[k] for k in ("tri_xyz", "tri_rgb", "tri_alpha") if k in s}
-        if self.deform is not None:
-            d = self.deform
-            self.tout = r.bind_transfer(d["V_def"], d["bind_face"], d["bind_bary"], s["means"],
-                                        s["quats"], s["scales"], out=self.tout)
-            r.project(self.cams, means=self.tout["means"], cov3d=self.tout["cov3d"],
-                      opacity=s["opacity"], sh=s["sh"], **tris)
-        else:
-            r.project(self.cams, means=s["means"], scales=s["scales"], quats=s["quats"],
-                      opacity=s["opacity"], sh=s["sh"], **tris)
-        r.bin()
-        r.sort()
-        self.out = r.blend(want_state=True, out=self.out)
-        if self.do_backward:
-            if self.dL is None:
-                self.dL = torch.zeros_like(self.out["image"])
-            pm = self.tout["means"] if self.deform is not None else s["means"]
-            xf = self.tout["xform"] if self.deform is not None else None
-            self.grads = r.backward(self.dL, self.out, pm, s["scales"], s["quats"], s["sh"], xf,
-                                    out=self.grads)
+        self._transfer()
+        for gi, (a, b) in enumerate(self.groups):
+            self._project(self.cams[a:b])
+            r.bin()
+            r.sort()
+            part = self._slice(a, b)
+            r.blend(want_state=True, out=part)
+            if self.do_backward:
+                pm = self.tout["means"] if self.deform is not None else s["means"]
+                xf = self.tout["xform"] if self.deform is not None else None
+                p0, p1 = self.pix0[a], self.pix0[b]
+                self.grads = r.backward(self.dL[3 * p0:3 * p1], part, pm, s["scales"], s["quats"],
+                                        s["sh"], xf, out=self.grads, accumulate=gi > 0)
         return self.out
 
     def prepare(self):
-        """Eager frame, reservation and capture."""
+        """Plan, render one eager step, reserve, capture."""
+        dev = self.r.device
+        P = self.pix0[-1]
+        self.out = dict(image=torch.empty(3 * P, device=dev), T_final=torch.empty(P, device=dev),
+                        n_contrib=torch.empty(P, device=dev, dtype=torch.int32),
+                        T_entity_in=torch.empty(P, device=dev))
+        if self.do_backward:
+            self.dL = torch.zeros(3 * P, device=dev)
+        self.plan()
         self._step()
-        n_dup, _, _ = self.r.query()
-        self.n_dup_seen = n_dup
-        self.r.reserve(max(1, int(n_dup * self.headroom)))
+        self.n_dup_seen = sum(self.view_dup_counts)
+        self.r.reserve(max(1, int(self.max_group_dups * self.headroom)))
         torch.cuda.synchronize()
         self.r.capture(self._step)
         self.graph_ready = True
@@ -82,3 +144,10 @@ class BatchedStep:
     def set_loss_gradient(self, dL: torch.Tensor):
         """Copy dL/dimage into the buffer the captured backward reads."""
         self.dL.copy_(dL.reshape(-1))
+
+    def update_views(self, new_cams: Sequence):
+        """New cameras (same sizes) for the next replays."""
+        new_cams = list(new_cams)
+        for a, b in self.groups:
+            self.r.update_views(self.cams[a:b], new_cams[a:b])
+        self.cams = new_cams

@@ -308,17 +308,20 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
   int64_t tiles = 0, pix = 0;
   umgs_status s = build_views(c, V, cams, vps, tiles, pix);
   if (s != UMGS_OK) return s;
-  if (c->capturing) {
-    // a capture replays the device view table: it must describe this frame
-    bool same = (int)c->views.size() == V && V == c->V && N == c->N && T == c->T &&
-                o.tile_w == c->tile_w && o.tile_h == c->tile_h;
-    for (int v = 0; same && v < V; ++v) same = memcmp(&vps[v], &c->views[v], sizeof(ViewParams)) == 0;
-    if (!same)
-      return fail(c, UMGS_ERR_STATE, "umgs_project: while capturing, the cameras and sizes must be "
-                                     "those of the last eager frame");
+  // Device view tables are stored once per distinct camera set, so a captured
+  // graph can replay frames (or view groups) whose tables were uploaded by
+  // eager calls.
+  int set = -1;
+  for (size_t k = 0; k < c->view_sets.size() && set < 0; ++k) {
+    const std::vector<ViewParams> &t = c->view_sets[k];
+    if ((int)t.size() == V && memcmp(t.data(), vps.data(), sizeof(ViewParams) * V) == 0) set = (int)k;
   }
+  if (set < 0 && c->capturing)
+    return fail(c, UMGS_ERR_STATE, "umgs_project: while capturing, the cameras must be those of "
+                                   "an eager frame (update them with umgs_update_views)");
+  if (V > kViewSlots) return fail(c, UMGS_ERR_CAPACITY, "umgs_project: %d views", V);
   const int64_t nrec = (int64_t)V * (N + T);
-  if ((s = ensure(c, c->d_views, sizeof(ViewParams) * V, "view table")) ||
+  if ((s = ensure(c, c->d_views, sizeof(ViewParams) * kViewSlots, "view tables")) ||
       (s = ensure(c, c->keys, sizeof(uint32_t) * std::max<int64_t>(nrec, 1), "depth keys")) ||
       (s = ensure(c, c->rects, sizeof(uint2) * std::max<int64_t>(nrec, 1), "tile rects")) ||
       (s = ensure(c, c->counts, sizeof(uint64_t) * (nrec + 1), "tile counts")) ||
@@ -331,7 +334,23 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
       (s = ensure(c, c->tile_order, sizeof(uint32_t) * (64 + tiles), "tile order")))
     return s;
   const bool fresh_info = c->finfo.cap && c->views.empty();
+  bool upload = false;
+  if (set < 0) {
+    if (c->view_used + V > kViewSlots) {   // store full: start over (eager only)
+      c->view_sets.clear();
+      c->view_set_off.clear();
+      c->view_used = 0;
+    }
+    set = (int)c->view_sets.size();
+    c->view_sets.push_back(vps);
+    c->view_set_off.push_back(c->view_used);
+    c->view_used += V;
+    upload = true;
+  }
+  ViewParams *dv = (ViewParams *)c->d_views.p + c->view_set_off[set];
+  c->cur_views = dv;
   c->views = vps;
+  c->scanned = false;
   c->V = V; c->N = N; c->T = T;
   c->tile_w = o.tile_w; c->tile_h = o.tile_h; c->frag_batch = o.frag_batch;
   c->mode = o.mode; c->sh_degree = o.sh_degree;
@@ -345,9 +364,8 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
   c->stage = 0;
   hipError_t e = hipSuccess;
   if (fresh_info) e = launch_fill_u32(c, (uint32_t *)c->finfo.p, sizeof(FrameInfo) / 4, 0u);
-  if (e == hipSuccess && !c->capturing)
-    e = hipMemcpyAsync(c->d_views.p, vps.data(), sizeof(ViewParams) * V, hipMemcpyHostToDevice,
-                       c->stream);
+  if (e == hipSuccess && upload)
+    e = hipMemcpyAsync(dv, vps.data(), sizeof(ViewParams) * V, hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return hip_check(c, e, "view upload");
   // the scan's total lands in counts[nrec]
   e = launch_fill_u32(c, (uint32_t *)((uint64_t *)c->counts.p + nrec), 2, 0u);
@@ -380,9 +398,13 @@ umgs_status umgs_bin(umgs_ctx *ctx) {
   if (!ctx) return UMGS_ERR_INVALID_ARG;
   Ctx *c = &ctx->c;
   if (c->stage < 1) return fail(c, UMGS_ERR_STATE, "umgs_bin: no projected frame");
-  hipError_t e = launch_exclusive_scan_u64(c, (uint64_t *)c->counts.p, c->n_records + 1,
-                                           (uint64_t *)c->scan_tmp.p);
-  if (e != hipSuccess) return hip_check(c, e, "count scan");
+  hipError_t e = hipSuccess;
+  if (!c->scanned) {
+    e = launch_exclusive_scan_u64(c, (uint64_t *)c->counts.p, c->n_records + 1,
+                                  (uint64_t *)c->scan_tmp.p);
+    if (e != hipSuccess) return hip_check(c, e, "count scan");
+    c->scanned = true;
+  }
   if (c->fixed_cap) {
     // sizes stay on the device; every sort-stage grid covers the capacity
     if (ensure_keys(c, c->key_cap) != UMGS_OK) return UMGS_ERR_CAPACITY;
@@ -446,7 +468,7 @@ umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_
                           const int32_t *n_contrib, const float *T_entity_in, const float *means,
                           const float *scales, const float *quats, const float *xform,
                           const float *sh, float *dL_dmeans, float *dL_dscales, float *dL_dquats,
-                          float *dL_dopacity, float *dL_dsh) {
+                          float *dL_dopacity, float *dL_dsh, int32_t accumulate) {
   if (!ctx) return UMGS_ERR_INVALID_ARG;
   Ctx *c = &ctx->c;
   if (c->stage < 4) return fail(c, UMGS_ERR_STATE, "umgs_backward: no blended frame on this context");
@@ -462,7 +484,7 @@ umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_
   if (s != UMGS_OK) return s;
   return hip_check(c, launch_backward(c, dL_dimage, T_final, n_contrib, T_entity_in, means, scales,
                                       quats, xform, sh, dL_dmeans, dL_dscales, dL_dquats,
-                                      dL_dopacity, dL_dsh),
+                                      dL_dopacity, dL_dsh, accumulate != 0),
                    "backward launch");
 }
 
@@ -607,23 +629,57 @@ umgs_status umgs_graph_launch(umgs_ctx *ctx) {
   return hip_check(c, hipGraphLaunch(c->graph_exec, c->stream), "hipGraphLaunch");
 }
 
-umgs_status umgs_update_views(umgs_ctx *ctx, int32_t V, const umgs_camera *cams) {
+umgs_status umgs_update_views(umgs_ctx *ctx, int32_t V, const umgs_camera *old_cams,
+                              const umgs_camera *new_cams) {
   if (!ctx) return UMGS_ERR_INVALID_ARG;
   Ctx *c = &ctx->c;
   if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_update_views: capturing");
-  if (!cams || V != c->V || c->views.empty())
-    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_update_views: need the captured frame's %d views", c->V);
-  std::vector<ViewParams> vps;
-  int64_t tiles = 0, pix = 0;
-  umgs_status s = build_views(c, V, cams, vps, tiles, pix);
+  if (!old_cams || !new_cams || V < 1)
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_update_views: NULL cameras or V=%d", V);
+  std::vector<ViewParams> oldv, newv;
+  int64_t tiles = 0, pix = 0, tiles2 = 0, pix2 = 0;
+  umgs_status s = build_views(c, V, old_cams, oldv, tiles, pix);
+  if (s == UMGS_OK) s = build_views(c, V, new_cams, newv, tiles2, pix2);
   if (s != UMGS_OK) return s;
   for (int v = 0; v < V; ++v)
-    if (vps[v].W != c->views[v].W || vps[v].H != c->views[v].H)
+    if (oldv[v].W != newv[v].W || oldv[v].H != newv[v].H)
       return fail(c, UMGS_ERR_INVALID_ARG, "umgs_update_views: view %d changed size", v);
-  c->views = vps;
-  return hip_check(c, hipMemcpyAsync(c->d_views.p, vps.data(), sizeof(ViewParams) * V,
-                                     hipMemcpyHostToDevice, c->stream),
-                   "view upload");
+  for (size_t k = 0; k < c->view_sets.size(); ++k) {
+    std::vector<ViewParams> &t = c->view_sets[k];
+    if ((int)t.size() != V || memcmp(t.data(), oldv.data(), sizeof(ViewParams) * V) != 0) continue;
+    t = newv;
+    ViewParams *dv = (ViewParams *)c->d_views.p + c->view_set_off[k];
+    if (dv == c->cur_views) c->views = newv;
+    return hip_check(c, hipMemcpyAsync(dv, newv.data(), sizeof(ViewParams) * V,
+                                       hipMemcpyHostToDevice, c->stream),
+                     "view upload");
+  }
+  return fail(c, UMGS_ERR_STATE, "umgs_update_views: no stored view table matches old_cams");
+}
+
+umgs_status umgs_view_dups(umgs_ctx *ctx, int64_t *dups) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (!dups) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_view_dups: NULL output");
+  if (c->stage < 1) return fail(c, UMGS_ERR_STATE, "umgs_view_dups: no projected frame");
+  if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_view_dups: capturing");
+  hipError_t e = hipSuccess;
+  if (!c->scanned) {
+    e = launch_exclusive_scan_u64(c, (uint64_t *)c->counts.p, c->n_records + 1,
+                                  (uint64_t *)c->scan_tmp.p);
+    if (e != hipSuccess) return hip_check(c, e, "count scan");
+    c->scanned = true;
+  }
+  // offsets at the view boundaries of the record array (records are view-major)
+  std::vector<uint64_t> b(c->V + 1);
+  const int64_t per = (int64_t)c->N + c->T;
+  for (int v = 0; v <= c->V && e == hipSuccess; ++v)
+    e = hipMemcpyAsync(&b[v], (uint64_t *)c->counts.p + per * v, sizeof(uint64_t),
+                       hipMemcpyDeviceToHost, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "umgs_view_dups readback");
+  for (int v = 0; v < c->V; ++v) dups[v] = (int64_t)(b[v + 1] - b[v]);
+  return UMGS_OK;
 }
 
 umgs_status umgs_set_profiling(umgs_ctx *ctx, int32_t enable) {

@@ -258,7 +258,7 @@ __global__ void project_backward_kernel(const ViewParams *__restrict__ views, in
                                         const float *__restrict__ g2d,
                                         float *__restrict__ d_means, float *__restrict__ d_scales,
                                         float *__restrict__ d_quats, float *__restrict__ d_opac,
-                                        float *__restrict__ d_sh) {
+                                        float *__restrict__ d_sh, int accumulate) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   const int nc = (sh_deg + 1) * (sh_deg + 1);
@@ -442,9 +442,11 @@ __global__ void project_backward_kernel(const ViewParams *__restrict__ views, in
       dM[3 * r + c] = acc;
     }
   float gR[9];
+  // write, or add to what an earlier call (another view group) wrote
+  auto put = [accumulate](float *p, float v) { *p = accumulate ? *p + v : v; };
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    d_scales[3 * (int64_t)i + c] = dM[c] * Rq[c] + dM[3 + c] * Rq[3 + c] + dM[6 + c] * Rq[6 + c];
+    put(&d_scales[3 * (int64_t)i + c], dM[c] * Rq[c] + dM[3 + c] * Rq[3 + c] + dM[6 + c] * Rq[6 + c]);
 #pragma unroll
     for (int r = 0; r < 3; ++r) gR[3 * r + c] = dM[3 * r + c] * sc[c];
   }
@@ -454,15 +456,15 @@ __global__ void project_backward_kernel(const ViewParams *__restrict__ views, in
   float gz = 2.f * (-2.f * qz * gR[0] - qw * gR[1] + qx * gR[2] + qw * gR[3] - 2.f * qz * gR[4] + qy * gR[5] + qx * gR[6] + qy * gR[7]);
   // through the normalisation q_hat = q / |q|
   const float pr = qw * gw + qx * gx + qy * gy + qz * gz;
-  d_quats[4 * (int64_t)i] = (gw - qw * pr) * iq;
-  d_quats[4 * (int64_t)i + 1] = (gx - qx * pr) * iq;
-  d_quats[4 * (int64_t)i + 2] = (gy - qy * pr) * iq;
-  d_quats[4 * (int64_t)i + 3] = (gz - qz * pr) * iq;
-  d_means[3 * (int64_t)i] = dmu[0];
-  d_means[3 * (int64_t)i + 1] = dmu[1];
-  d_means[3 * (int64_t)i + 2] = dmu[2];
-  d_opac[i] = dop;
-  for (int k = 0; k < nc * 3; ++k) d_sh[(int64_t)i * nc * 3 + k] = dshv[k];
+  put(&d_quats[4 * (int64_t)i], (gw - qw * pr) * iq);
+  put(&d_quats[4 * (int64_t)i + 1], (gx - qx * pr) * iq);
+  put(&d_quats[4 * (int64_t)i + 2], (gy - qy * pr) * iq);
+  put(&d_quats[4 * (int64_t)i + 3], (gz - qz * pr) * iq);
+  put(&d_means[3 * (int64_t)i], dmu[0]);
+  put(&d_means[3 * (int64_t)i + 1], dmu[1]);
+  put(&d_means[3 * (int64_t)i + 2], dmu[2]);
+  put(&d_opac[i], dop);
+  for (int k = 0; k < nc * 3; ++k) put(&d_sh[(int64_t)i * nc * 3 + k], dshv[k]);
 }
 
 template <int TW, int TH>
@@ -470,7 +472,7 @@ hipError_t launch_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int32_t
   const size_t lds = (size_t)c->frag_batch * (kSlotWords + 9) * sizeof(uint32_t);
   ScopedTimer t(c, K_BLEND_BWD);
   hipLaunchKernelGGL((blend_backward_kernel<TW, TH>), dim3((unsigned)c->n_tiles), dim3(TW * TH), lds,
-                     c->stream, (const ViewParams *)c->d_views.p, c->V, c->N, c->T, c->mode,
+                     c->stream, c->cur_views, c->V, c->N, c->T, c->mode,
                      c->frag_batch, c->bg[0], c->bg[1], c->bg[2], (const uint2 *)c->ranges.p,
                      (const uint32_t *)c->v0.p, (const uint32_t *)c->v1.p,
                      (const FrameInfo *)c->finfo.p, (const GaussRec *)c->grec.p, (const TriRec *)c->trec.p, dL, Tf, nc, Te,
@@ -486,7 +488,7 @@ hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32
                            const float *Te, const float *means, const float *scales,
                            const float *quats, const float *xform, const float *sh,
                            float *d_means, float *d_scales, float *d_quats, float *d_opac,
-                           float *d_sh) {
+                           float *d_sh, bool accumulate) {
   hipError_t e = launch_fill_u32(c, (uint32_t *)c->g2d.p, 9 * (int64_t)c->V * c->N, 0u);
   if (e != hipSuccess) return e;
   if (c->n_tiles > 0) {
@@ -498,9 +500,9 @@ hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32
   if (c->N == 0) return hipSuccess;
   ScopedTimer t(c, K_PROJECT_BWD);
   hipLaunchKernelGGL(project_backward_kernel, dim3(ceil_div(c->N, 128)), dim3(128), 0, c->stream,
-                     (const ViewParams *)c->d_views.p, c->V, c->N, c->sh_degree, means, scales,
+                     c->cur_views, c->V, c->N, c->sh_degree, means, scales,
                      quats, xform, sh, (const float *)c->g2d.p, d_means, d_scales, d_quats, d_opac,
-                     d_sh);
+                     d_sh, accumulate ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -297,7 +297,7 @@ hipError_t launch_emit_keys(Ctx *c) {
   if (c->n_launch == 0) return hipSuccess;
   ScopedTimer t(c, K_EMIT);
   hipLaunchKernelGGL(emit_balanced_kernel, dim3(ceil_div(c->n_launch, kEmitSpan)),
-                     dim3(kEmitThreads), 0, c->stream, (const ViewParams *)c->d_views.p,
+                     dim3(kEmitThreads), 0, c->stream, c->cur_views,
                      c->N + c->T, c->n_records, (const uint32_t *)c->keys.p,
                      (const uint2 *)c->rects.p, (const uint64_t *)c->counts.p,
                      (const FrameInfo *)c->finfo.p, (uint64_t *)c->k0.p, (uint32_t *)c->v0.p);

@@ -313,7 +313,7 @@ hipError_t launch_blend(Ctx *c, float *image, float *T_final, int32_t *n_contrib
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   BlendArgs a;
-  a.views = (const ViewParams *)c->d_views.p;
+  a.views = c->cur_views;
   a.V = c->V; a.N = c->N; a.T = c->T; a.mode = c->mode; a.batch = c->frag_batch;
   a.bg0 = c->bg[0]; a.bg1 = c->bg[1]; a.bg2 = c->bg[2];
   a.ranges = (const uint2 *)c->ranges.p;

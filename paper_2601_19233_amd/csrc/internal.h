@@ -22,6 +22,8 @@ constexpr int kSubpx = 256;                  // fixed-point vertex resolution: 1
 constexpr int kCoordLimit = 1 << 24;         // |snapped coordinate| bound (1/256 px)
 constexpr uint32_t kCulled = 0xFFFFFFFFu;    // depth key of a culled primitive
 
+constexpr int64_t kViewSlots = 8192;   // ViewParams the device table store holds
+
 // Per-view parameters in device memory.
 struct ViewParams {
   float R[9];
@@ -125,7 +127,12 @@ struct Ctx {
   bool fixed_cap = false;    // key capacity reserved: no host readback in umgs_bin
   std::vector<ViewParams> views;
   std::vector<int32_t> view_first_tile_x;  // host copy helpers
-  DevBuf d_views;
+  DevBuf d_views;            // kViewSlots view tables, appended as new camera sets appear
+  std::vector<std::vector<ViewParams>> view_sets;   // host copies of the stored tables
+  std::vector<int64_t> view_set_off;                // offset of each table in d_views
+  int64_t view_used = 0;                            // ViewParams stored
+  const ViewParams *cur_views = nullptr;            // table of the current frame
+  bool scanned = false;      // the count scan of the current frame has run
   DevBuf keys;         // n_records uint32 depth bits
   DevBuf rects;        // n_records uint2: (tx0 | ty0 << 16, tx1 | ty1 << 16) inclusive-exclusive
   DevBuf counts;       // n_records + 1 uint64 (scanned in place to offsets)
@@ -174,7 +181,7 @@ hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32
                            const float *Te, const float *means, const float *scales,
                            const float *quats, const float *xform, const float *sh,
                            float *d_means, float *d_scales, float *d_quats, float *d_opac,
-                           float *d_sh);
+                           float *d_sh, bool accumulate);
 hipError_t launch_transfer(Ctx *c, const float *V_def, int32_t N, const int32_t *bind_face,
                            const float *bind_bary, const float *means, const float *quats,
                            const float *scales, float *means_out, float *quats_out,

@@ -366,7 +366,7 @@ hipError_t launch_project_gaussians(Ctx *c, const float *means, const float *cov
   dim3 grid(ceil_div(c->N, 256), c->V);
   ScopedTimer t(c, K_PROJECT);
   hipLaunchKernelGGL(project_gaussians_kernel, grid, dim3(256), 0, c->stream,
-                     (const ViewParams *)c->d_views.p, c->N, c->T, c->sh_degree, c->tile_w,
+                     c->cur_views, c->N, c->T, c->sh_degree, c->tile_w,
                      c->tile_h, means, cov3d, scales, quats, opacity, sh,
                      (uint32_t *)c->keys.p, (uint2 *)c->rects.p, (uint64_t *)c->counts.p,
                      (GaussRec *)c->grec.p, (uint32_t *)c->minmax.p);
@@ -379,7 +379,7 @@ hipError_t launch_setup_triangles(Ctx *c, const float *tri_xyz, const float *tri
   dim3 grid(ceil_div(c->T, 256), c->V);
   ScopedTimer t(c, K_TRIANGLES);
   hipLaunchKernelGGL(setup_triangles_kernel, grid, dim3(256), 0, c->stream,
-                     (const ViewParams *)c->d_views.p, c->N, c->T, c->tile_w, c->tile_h,
+                     c->cur_views, c->N, c->T, c->tile_w, c->tile_h,
                      tri_xyz, tri_rgb, tri_alpha, (uint32_t *)c->keys.p, (uint2 *)c->rects.p,
                      (uint64_t *)c->counts.p, (TriRec *)c->trec.p, (uint32_t *)c->minmax.p);
   return hipGetLastError();

@@ -213,13 +213,19 @@ class Rasterizer:
     def blend(self, want_state: bool = True, out: Optional[Dict] = None) -> Dict[str, torch.Tensor]:
         if out is None:
             out = self.alloc_outputs(want_state)
+        npix = sum(w * h for w, h in self.views)
+        for name, per in (("image", 3), ("T_final", 1), ("n_contrib", 1), ("T_entity_in", 1)):
+            t = out.get(name)
+            if t is not None and (t.numel() != per * npix or not t.is_contiguous()):
+                raise ValueError(f"blend output {name} must be contiguous with {per * npix} elements")
         with self._on_stream():
             self._check(self.lib.umgs_blend(self.h, _ptr(out["image"]), _ptr(out["T_final"]),
                                             _ptr(out["n_contrib"]), _ptr(out["T_entity_in"])))
         return out
 
     def backward(self, dL_dimage: torch.Tensor, fwd: Dict[str, torch.Tensor], means, scales, quats,
-                 sh, xform=None, out: Optional[Dict] = None) -> Dict[str, torch.Tensor]:
+                 sh, xform=None, out: Optional[Dict] = None, accumulate: bool = False
+                 ) -> Dict[str, torch.Tensor]:
         """Gradients of the last blended frame (umgs_backward).  ``fwd`` is the
         dict returned by blend(); ``means`` are the projected means."""
         d = self.device
@@ -237,7 +243,8 @@ class Rasterizer:
             self._check(self.lib.umgs_backward(
                 self.h, _ptr(dL), _ptr(fwd["T_final"]), _ptr(fwd["n_contrib"]), _ptr(fwd["T_entity_in"]),
                 _ptr(means), _ptr(scales), _ptr(quats), _ptr(xform), _ptr(sh), _ptr(out["means"]),
-                _ptr(out["scales"]), _ptr(out["quats"]), _ptr(out["opacity"]), _ptr(out["sh"])))
+                _ptr(out["scales"]), _ptr(out["quats"]), _ptr(out["opacity"]), _ptr(out["sh"]),
+                1 if accumulate else 0))
         return out
 
     def render(self, cams, **scene) -> Dict[str, torch.Tensor]:
@@ -319,10 +326,21 @@ class Rasterizer:
         with self._on_stream():
             self._check(self.lib.umgs_graph_launch(self.h))
 
-    def update_views(self, cams):
-        arr = (L.Camera * len(cams))(*[camera_struct(c) for c in cams])
+    def update_views(self, old_cams, new_cams):
+        """Replace a stored camera set (same sizes) for the next replays."""
+        if len(old_cams) != len(new_cams):
+            raise ValueError("old and new camera sets differ in length")
+        a = (L.Camera * len(old_cams))(*[camera_struct(c) for c in old_cams])
+        b = (L.Camera * len(new_cams))(*[camera_struct(c) for c in new_cams])
         with self._on_stream():
-            self._check(self.lib.umgs_update_views(self.h, len(cams), arr))
+            self._check(self.lib.umgs_update_views(self.h, len(old_cams), a, b))
+
+    def view_dups(self) -> List[int]:
+        """Duplicates per view of the projected frame (before bin())."""
+        arr = (C.c_int64 * len(self.views))()
+        with self._on_stream():
+            self._check(self.lib.umgs_view_dups(self.h, arr))
+        return [int(x) for x in arr]
 
     def copy_state(self, which: int) -> torch.Tensor:
         n_dup, n_tiles, n_rec = self.query()
