@@ -233,8 +233,9 @@ def main():
     stages = {k: round(v[1] / args.steps, 4) for k, v in prof.items()}
     per_launch = {k: v[1] / v[0] for k, v in prof.items()}
     dominant = max(prof, key=lambda k: prof[k][1])
-    g_pairs, t_pairs = r.blend_pairs()
-    log(f"blend pairs: {g_pairs} Gaussian, {t_pairs} triangle")
+    bp = r.blend_pairs()
+    g_pairs, t_pairs = bp["gauss"], bp["tri"]
+    log(f"blend work: {bp}")
     # algorithmic HBM bytes per launch of the bandwidth-bound kernels
     algo_bytes = {
         "sort_downsweep": 24.0 * n_dup,          # read key+value, write key+value
@@ -256,7 +257,9 @@ def main():
             return {"kernel": k, "bound": "alu", "achieved": round(ach, 1), "peak": VALU_PEAK_GOPS,
                     "unit": "Gop/s", "frac": round(ach / VALU_PEAK_GOPS, 4), "traffic": None,
                     "ms_per_launch": round(per_launch[k], 4), "gauss_pairs": g_pairs,
-                    "tri_pairs": t_pairs}
+                    "tri_pairs": t_pairs, "wave_iters": bp["wave_iters"],
+                    "staged_fragments": bp["staged"],
+                    "lane_occupancy": round((g_pairs + t_pairs) / max(1, 64 * bp["wave_iters"]), 4)}
         return None
 
     roof = roofline(dominant)

@@ -226,10 +226,14 @@ umgs_status umgs_update_views(umgs_ctx *ctx, int32_t V, const umgs_camera *old_c
 umgs_status umgs_view_dups(umgs_ctx *ctx, int64_t *dups);
 
 /* Measurement: blend the sorted frame again into image [device] while
- * counting, over all pixels, the fragments each pixel evaluates before it is
- * done; pairs [host] receives {Gaussian pairs, triangle pairs}.  The
- * algorithmic work of the blend is these counts times the per-pair
- * operation counts.  Synchronous.  Errors: STATE before umgs_sort. */
+ * counting; pairs [host, 4 entries] receives {Gaussian pairs, triangle
+ * pairs, wave iterations, staged fragments}: the (pixel, fragment) pairs
+ * evaluated before each pixel is done, the fragment-loop iterations of all
+ * 64-lane waves, and the fragments loaded into LDS.  The algorithmic work of
+ * the blend is the pair counts times the per-pair operation counts; 64 times
+ * the wave iterations over the pairs is the SIMD-lane occupancy lost to
+ * pixels of one wave finishing at different depths.  Synchronous.  Errors:
+ * STATE before umgs_sort. */
 umgs_status umgs_blend_pairs(umgs_ctx *ctx, float *image, int64_t *pairs);
 
 /* Sizes of the current frame: n_dup (duplicates sorted, at most the
@@ -264,7 +268,7 @@ umgs_status umgs_copy_state(umgs_ctx *ctx, int32_t which, void *dst, int64_t cap
 enum { UMGS_K_VERTEX_FRAMES = 0, UMGS_K_TRANSFER = 1, UMGS_K_PROJECT = 2, UMGS_K_TRIANGLES = 3,
        UMGS_K_SCAN = 4, UMGS_K_EMIT = 5, UMGS_K_SORT_UPSWEEP = 6, UMGS_K_SORT_SCAN = 7,
        UMGS_K_SORT_DOWNSWEEP = 8, UMGS_K_RANGES = 9, UMGS_K_BLEND = 10, UMGS_K_BLEND_BWD = 11,
-       UMGS_K_PROJECT_BWD = 12, UMGS_K_COUNT = 13 };
+       UMGS_K_PROJECT_BWD = 12, UMGS_K_DEPTH_SORT = 13, UMGS_K_COUNT = 14 };
 umgs_status umgs_set_profiling(umgs_ctx *ctx, int32_t enable);
 umgs_status umgs_profile_read(umgs_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms);
 

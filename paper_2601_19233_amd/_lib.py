@@ -62,7 +62,7 @@ PROTOTYPES = {
 
 KERNEL_NAMES = ["vertex_frames", "transfer", "project_gaussians", "setup_triangles", "count_scan",
                 "emit_keys", "sort_upsweep", "sort_scan", "sort_downsweep", "tile_ranges", "blend",
-                "blend_backward", "project_backward"]
+                "blend_backward", "project_backward", "depth_sort"]
 
 _lib = None
 

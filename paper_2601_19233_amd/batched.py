@@ -141,6 +141,15 @@ class BatchedStep:
         self.r.replay()
         return self.out
 
+    def split_views(self, flat: torch.Tensor, channels: int):
+        """Per-view (channels, H, W) views of a packed output of all groups."""
+        out = []
+        for v, c in enumerate(self.cams):
+            a, b = channels * self.pix0[v], channels * self.pix0[v + 1]
+            out.append(flat[a:b].view(channels, c.height, c.width) if channels > 1
+                       else flat[a:b].view(c.height, c.width))
+        return out
+
     def set_loss_gradient(self, dL: torch.Tensor):
         """Copy dL/dimage into the buffer the captured backward reads."""
         self.dL.copy_(dL.reshape(-1))

@@ -85,7 +85,7 @@ static hipEvent_t get_event(Ctx *c) {
 }
 
 ScopedTimer::ScopedTimer(Ctx *ctx, int kid) : c(ctx), id(kid) {
-  if (!c->prof.on) return;
+  if (!c->prof.on || kid < 0) return;
   a = get_event(c);
   b = get_event(c);
   if (a && b) (void)hipEventRecord(a, c->stream);
@@ -112,10 +112,6 @@ static umgs_status drain_profile(Ctx *c) {
   c->prof.pending.clear();
   return UMGS_OK;
 }
-
-hipError_t launch_exclusive_scan_u64(Ctx *c, uint64_t *data, int64_t n, uint64_t *tmp);
-hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v);
-hipError_t launch_expand_keys(Ctx *c, uint64_t *dst);
 
 }  // namespace umgs
 
@@ -168,9 +164,10 @@ void umgs_destroy(umgs_ctx *ctx) {
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   DevBuf *bufs[] = {&c->V_rest, &c->faces, &c->vf_ptr, &c->vf_idx, &c->vtab, &c->d_views,
-                    &c->keys, &c->rects, &c->counts, &c->grec, &c->trec, &c->scan_tmp,
+                    &c->keys, &c->rects, &c->counts, &c->dk[0], &c->dk[1], &c->dv[0],
+                    &c->dv[1], &c->offs, &c->grec, &c->trec, &c->scan_tmp,
                     &c->k0, &c->k1, &c->v0, &c->v1, &c->hist, &c->ranges, &c->g2d,
-                    &c->minmax, &c->finfo, &c->tile_order, &c->pair_count};
+                    &c->minmax, &c->finfo, &c->tile_order, &c->pair_count, &c->view_sums};
   for (DevBuf *b : bufs) free_buf(*b);
   for (auto &p : c->prof.pending) {
     (void)hipEventDestroy(p.a);
@@ -286,8 +283,6 @@ static umgs_status build_views(Ctx *c, int32_t V, const umgs_camera *cams,
   return UMGS_OK;
 }
 
-static int sort_passes_for(int total_bits) { return (total_bits + 7) / 8; }
-
 umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int32_t N,
                          const float *means, const float *cov3d, const float *scales,
                          const float *quats, const float *opacity, const float *sh,
@@ -324,10 +319,20 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
   if ((s = ensure(c, c->d_views, sizeof(ViewParams) * kViewSlots, "view tables")) ||
       (s = ensure(c, c->keys, sizeof(uint32_t) * std::max<int64_t>(nrec, 1), "depth keys")) ||
       (s = ensure(c, c->rects, sizeof(uint2) * std::max<int64_t>(nrec, 1), "tile rects")) ||
-      (s = ensure(c, c->counts, sizeof(uint64_t) * (nrec + 1), "tile counts")) ||
+      (s = ensure(c, c->counts, sizeof(uint64_t) * std::max<int64_t>(nrec, 1), "tile counts")) ||
+      (s = ensure(c, c->dk[0], sizeof(uint32_t) * std::max<int64_t>(nrec, 1), "depth order")) ||
+      (s = ensure(c, c->dk[1], sizeof(uint32_t) * std::max<int64_t>(nrec, 1), "depth order")) ||
+      (s = ensure(c, c->dv[0], sizeof(uint32_t) * std::max<int64_t>(nrec, 1), "depth order")) ||
+      (s = ensure(c, c->dv[1], sizeof(uint32_t) * std::max<int64_t>(nrec, 1), "depth order")) ||
+      (s = ensure(c, c->offs, sizeof(uint64_t) * (nrec + 1), "record offsets")) ||
+      (s = ensure(c, c->hist, radix_hist_bytes(std::max<int64_t>(nrec, 1)), "radix histograms")) ||
+      (s = ensure(c, c->view_sums, sizeof(uint64_t) * V, "view sums")) ||
       (s = ensure(c, c->grec, sizeof(GaussRec) * std::max<int64_t>((int64_t)V * N, 1), "Gaussian records")) ||
       (s = ensure(c, c->trec, sizeof(TriRec) * std::max<int64_t>((int64_t)V * T, 1), "triangle records")) ||
-      (s = ensure(c, c->scan_tmp, scan_tmp_bytes(std::max<int64_t>(nrec + 1, 1 << 20)), "scan scratch")) ||
+      (s = ensure(c, c->scan_tmp,
+                  scan_tmp_bytes(std::max<int64_t>({nrec + 1, 1 << 20,
+                                                    (int64_t)radix_hist_bytes(std::max<int64_t>(nrec, 1)) / 4})),
+                  "scan scratch")) ||
       (s = ensure(c, c->ranges, sizeof(uint2) * tiles, "tile ranges")) ||
       (s = ensure(c, c->minmax, 2 * sizeof(uint32_t), "depth range")) ||
       (s = ensure(c, c->finfo, sizeof(FrameInfo), "frame info")) ||
@@ -350,7 +355,6 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
   ViewParams *dv = (ViewParams *)c->d_views.p + c->view_set_off[set];
   c->cur_views = dv;
   c->views = vps;
-  c->scanned = false;
   c->V = V; c->N = N; c->T = T;
   c->tile_w = o.tile_w; c->tile_h = o.tile_h; c->frag_batch = o.frag_batch;
   c->mode = o.mode; c->sh_degree = o.sh_degree;
@@ -367,9 +371,6 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
   if (e == hipSuccess && upload)
     e = hipMemcpyAsync(dv, vps.data(), sizeof(ViewParams) * V, hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return hip_check(c, e, "view upload");
-  // the scan's total lands in counts[nrec]
-  e = launch_fill_u32(c, (uint32_t *)((uint64_t *)c->counts.p + nrec), 2, 0u);
-  if (e != hipSuccess) return hip_check(c, e, "count reset");
   e = launch_fill_u32(c, (uint32_t *)c->minmax.p, 1, kCulled);
   if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t *)c->minmax.p + 1, 1, 0u);
   if (e != hipSuccess) return hip_check(c, e, "depth range reset");
@@ -384,9 +385,9 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
 static umgs_status ensure_keys(Ctx *c, uint64_t n) {
   umgs_status s;
   n = std::max<uint64_t>(n, 1);
-  if ((s = ensure(c, c->k0, 8 * n, "keys")) || (s = ensure(c, c->k1, 8 * n, "keys")) ||
+  if ((s = ensure(c, c->k0, 4 * n, "keys")) || (s = ensure(c, c->k1, 4 * n, "keys")) ||
       (s = ensure(c, c->v0, 4 * n, "values")) || (s = ensure(c, c->v1, 4 * n, "values")) ||
-      (s = ensure(c, c->hist, radix_hist_bytes(n), "radix histograms")) ||
+      (s = ensure(c, c->hist, radix_hist_bytes(std::max<uint64_t>(n, c->n_records)), "radix histograms")) ||
       (s = ensure(c, c->scan_tmp,
                   scan_tmp_bytes(std::max<int64_t>(radix_hist_bytes(n) / 4, c->n_records + 1)),
                   "scan scratch")))
@@ -398,44 +399,34 @@ umgs_status umgs_bin(umgs_ctx *ctx) {
   if (!ctx) return UMGS_ERR_INVALID_ARG;
   Ctx *c = &ctx->c;
   if (c->stage < 1) return fail(c, UMGS_ERR_STATE, "umgs_bin: no projected frame");
-  hipError_t e = hipSuccess;
-  if (!c->scanned) {
-    e = launch_exclusive_scan_u64(c, (uint64_t *)c->counts.p, c->n_records + 1,
-                                  (uint64_t *)c->scan_tmp.p);
-    if (e != hipSuccess) return hip_check(c, e, "count scan");
-    c->scanned = true;
-  }
+  if (!c->fixed_cap && c->capturing)
+    return fail(c, UMGS_ERR_STATE, "umgs_bin: capturing without a reservation");
+  hipError_t e = launch_depth_order(c);
+  if (e != hipSuccess) return hip_check(c, e, "depth order launch");
+  c->sort_passes = radix_passes(c->tile_bits);
   if (c->fixed_cap) {
     // sizes stay on the device; every sort-stage grid covers the capacity
     if (ensure_keys(c, c->key_cap) != UMGS_OK) return UMGS_ERR_CAPACITY;
     c->n_launch = c->key_cap;
-    c->sort_passes = sort_passes_for(32 + c->tile_bits);
   } else {
-    if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_bin: capturing without a reservation");
     if (!c->host_pinned.p) {
       if ((e = hipHostMalloc(&c->host_pinned.p, 256, hipHostMallocDefault)) != hipSuccess)
         return hip_check(c, e, "pinned scratch");
       c->host_pinned.cap = 256;
     }
     uint64_t *h = (uint64_t *)c->host_pinned.p;
-    if ((e = hipMemcpyAsync(h, (uint64_t *)c->counts.p + c->n_records, sizeof(uint64_t),
+    if ((e = hipMemcpyAsync(h, (uint64_t *)c->offs.p + c->n_records, sizeof(uint64_t),
                             hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(h + 1, c->minmax.p, 2 * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                            c->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(c->stream)) != hipSuccess)
       return hip_check(c, e, "duplicate count readback");
     const uint64_t nd = h[0];
     if (nd >= 0xFFFF0000ull)
       return fail(c, UMGS_ERR_CAPACITY, "umgs_bin: %llu duplicates exceed 2^32", (unsigned long long)nd);
-    const uint32_t dmin = ((uint32_t *)(h + 1))[0], dmax = ((uint32_t *)(h + 1))[1];
-    int db = 1;
-    while (dmin <= dmax && db < 32 && (uint64_t)(dmax - dmin) >= (1ull << db)) ++db;
     umgs_status s = ensure_keys(c, nd);
     if (s != UMGS_OK) return s;
     c->key_cap = std::max<uint64_t>(nd, 1);
     c->n_dup = nd;
     c->n_launch = nd;
-    c->sort_passes = sort_passes_for(db + c->tile_bits);
   }
   if ((e = launch_emit_keys(c)) != hipSuccess) return hip_check(c, e, "emit_keys launch");
   c->stage = 2;
@@ -446,8 +437,8 @@ umgs_status umgs_sort(umgs_ctx *ctx) {
   if (!ctx) return UMGS_ERR_INVALID_ARG;
   Ctx *c = &ctx->c;
   if (c->stage < 2) return fail(c, UMGS_ERR_STATE, "umgs_sort: frame not binned");
-  hipError_t e = launch_radix_sort(c);
-  if (e != hipSuccess) return hip_check(c, e, "radix sort launch");
+  hipError_t e = launch_tile_sort(c);
+  if (e != hipSuccess) return hip_check(c, e, "tile sort launch");
   if ((e = launch_tile_ranges(c)) != hipSuccess) return hip_check(c, e, "tile ranges launch");
   c->stage = 3;
   return UMGS_OK;
@@ -562,13 +553,13 @@ umgs_status umgs_blend_pairs(umgs_ctx *ctx, float *image, int64_t *pairs) {
   if (c->stage < 3) return fail(c, UMGS_ERR_STATE, "umgs_blend_pairs: frame not sorted");
   if (!image || !pairs) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_blend_pairs: NULL argument");
   if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_blend_pairs: capturing");
-  umgs_status s = ensure(c, c->pair_count, 2 * sizeof(uint64_t), "pair counters");
+  umgs_status s = ensure(c, c->pair_count, 4 * sizeof(uint64_t), "pair counters");
   if (s != UMGS_OK) return s;
-  hipError_t e = launch_fill_u32(c, (uint32_t *)c->pair_count.p, 4, 0u);
+  hipError_t e = launch_fill_u32(c, (uint32_t *)c->pair_count.p, 8, 0u);
   if (e == hipSuccess)
     e = launch_blend(c, image, nullptr, nullptr, nullptr, (unsigned long long *)c->pair_count.p);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(pairs, c->pair_count.p, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream);
+    e = hipMemcpyAsync(pairs, c->pair_count.p, 4 * sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   return hip_check(c, e, "umgs_blend_pairs");
 }
@@ -663,22 +654,14 @@ umgs_status umgs_view_dups(umgs_ctx *ctx, int64_t *dups) {
   if (!dups) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_view_dups: NULL output");
   if (c->stage < 1) return fail(c, UMGS_ERR_STATE, "umgs_view_dups: no projected frame");
   if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_view_dups: capturing");
-  hipError_t e = hipSuccess;
-  if (!c->scanned) {
-    e = launch_exclusive_scan_u64(c, (uint64_t *)c->counts.p, c->n_records + 1,
-                                  (uint64_t *)c->scan_tmp.p);
-    if (e != hipSuccess) return hip_check(c, e, "count scan");
-    c->scanned = true;
-  }
-  // offsets at the view boundaries of the record array (records are view-major)
-  std::vector<uint64_t> b(c->V + 1);
-  const int64_t per = (int64_t)c->N + c->T;
-  for (int v = 0; v <= c->V && e == hipSuccess; ++v)
-    e = hipMemcpyAsync(&b[v], (uint64_t *)c->counts.p + per * v, sizeof(uint64_t),
-                       hipMemcpyDeviceToHost, c->stream);
+  std::vector<uint64_t> b(c->V);
+  hipError_t e = launch_view_sums(c, (unsigned long long *)c->view_sums.p);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b.data(), c->view_sums.p, sizeof(uint64_t) * c->V, hipMemcpyDeviceToHost,
+                       c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  if (e != hipSuccess) return hip_check(c, e, "umgs_view_dups readback");
-  for (int v = 0; v < c->V; ++v) dups[v] = (int64_t)(b[v + 1] - b[v]);
+  if (e != hipSuccess) return hip_check(c, e, "umgs_view_dups");
+  for (int v = 0; v < c->V; ++v) dups[v] = (int64_t)b[v];
   return UMGS_OK;
 }
 

@@ -18,8 +18,9 @@
 // and when the entity closes B = mean_j s^j, tau = mean_j p^j.  Triangles
 // are fixed occluders: they pass gradients through T but receive none.
 // Per fragment the 9 gradient terms (mean 2D, the 3 power coefficients,
-// opacity, colour) are summed over the wave with shuffles, over the
-// workgroup's waves in LDS, then added once per tile with float atomics.
+// opacity, colour) are summed over the wave with DPP moves, stored per wave
+// in LDS, summed over the workgroup's waves and added once per tile with
+// float atomics.
 //
 // project_backward_kernel: one thread per Gaussian, looping over views:
 // the chain rule back through the conic inverse, the EWA Jacobian (with the
@@ -27,13 +28,24 @@
 // direction, Sigma' = A Sigma A^T (when deformed) and Sigma = R S S R^T.
 #include "blend_common.h"
 
+#include <algorithm>
+
 namespace umgs {
 
 namespace {
 
-__device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+// Sum over the 64 lanes of the wave, complete in lane 63, with DPP moves on
+// the vector ALU: swap neighbours, swap pairs, mirror half-rows and rows
+// (every lane holds its 16-lane row's sum), then broadcast lane 15 of each
+// row into the next row and lane 31 into the upper half.  Every lane of the
+// wave must be active.
+__device__ __forceinline__ float wave_total(float v) {
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
   return v;
 }
 
@@ -49,7 +61,7 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
   constexpr int NT = TW * TH;
   extern __shared__ uint32_t smem[];
   uint32_t *slots = smem;                                 // batch * kSlotWords
-  float *gl = (float *)(smem + batch * kSlotWords);       // batch * 9
+  float *gl = (float *)(smem + batch * kSlotWords);       // [wave][batch][9] partial sums
   __shared__ int smax;
   const uint32_t *vals = fi->sorted_in ? v1 : v0;
 
@@ -109,8 +121,7 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
       } else {
         stage_tri(s, trec[(int64_t)v * T + (local - N)], P0x, P0y);
       }
-#pragma unroll
-      for (int k = 0; k < 9; ++k) gl[f * 9 + k] = 0.0f;
+      for (int k = 0; k < (NT / 64) * 9; ++k) gl[(k / 9) * batch * 9 + f * 9 + k % 9] = 0.0f;
     }
     __syncthreads();
 
@@ -120,45 +131,47 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
       const bool mine = pos < last;
       if (!__any(mine)) continue;
       if ((s[31] & 1u) == 0u) {
-        float alpha = 0.f, G = 0.f, dx = 0.f, dy = 0.f;
-        const bool contrib = mine && gauss_eval(s, pcx, pcy, alpha, G, dx, dy);
-        float g[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        // selects rather than branches keep every lane active for the row sums
+        float alpha, G, dx, dy;
+        const bool contrib = mine && gauss_terms(s, pcx, pcy, alpha, G, dx, dy);
+        if (contrib && in_ent) {
+          B0 = 0.25f * ((s0[0] + s1[0]) + (s2[0] + s3[0]));
+          B1 = 0.25f * ((s0[1] + s1[1]) + (s2[1] + s3[1]));
+          B2 = 0.25f * ((s0[2] + s1[2]) + (s2[2] + s3[2]));
+          Tr = term_ent ? Tterm : Tr / (0.25f * ((p0 + p1) + (p2 + p3)));
+          in_ent = false;
+        }
+        const float Tb = (pos == last - 1) ? Tterm : Tr / (1.0f - alpha);
+        const float c0 = __uint_as_float(s[6]), c1 = __uint_as_float(s[7]), c2 = __uint_as_float(s[8]);
+        const float w = contrib ? Tb * alpha : 0.0f;
+        const float dLda = contrib ? Tb * ((c0 - B0) * dC0 + (c1 - B1) * dC1 + (c2 - B2) * dC2) : 0.0f;
         if (contrib) {
-          if (in_ent) {
-            B0 = 0.25f * ((s0[0] + s1[0]) + (s2[0] + s3[0]));
-            B1 = 0.25f * ((s0[1] + s1[1]) + (s2[1] + s3[1]));
-            B2 = 0.25f * ((s0[2] + s1[2]) + (s2[2] + s3[2]));
-            Tr = term_ent ? Tterm : Tr / (0.25f * ((p0 + p1) + (p2 + p3)));
-            in_ent = false;
-          }
-          const float Tb = (pos == last - 1) ? Tterm : Tr / (1.0f - alpha);
-          const float c0 = __uint_as_float(s[6]), c1 = __uint_as_float(s[7]), c2 = __uint_as_float(s[8]);
-          const float w = Tb * alpha;
-          g[6] = w * dC0;
-          g[7] = w * dC1;
-          g[8] = w * dC2;
-          const float dLda = Tb * ((c0 - B0) * dC0 + (c1 - B1) * dC1 + (c2 - B2) * dC2);
           B0 = fmaf(alpha, c0 - B0, B0);
           B1 = fmaf(alpha, c1 - B1, B1);
           B2 = fmaf(alpha, c2 - B2, B2);
           Tr = Tb;
-          const float op = __uint_as_float(s[5]);
-          if (op * G < kAlphaMax) {
-            const float qa = __uint_as_float(s[2]), qb = __uint_as_float(s[3]), qc = __uint_as_float(s[4]);
-            g[5] = G * dLda;
-            const float dp = alpha * dLda;     // d alpha / d power = o G = alpha
-            g[0] = dp * (2.0f * qa * dx + qb * dy);
-            g[1] = dp * (qb * dx + 2.0f * qc * dy);
-            g[2] = dp * dx * dx;
-            g[3] = dp * dx * dy;
-            g[4] = dp * dy * dy;
-          }
         }
+        // alpha below the 0.99 clamp depends on power and opacity
+        const float op = __uint_as_float(s[5]);
+        const float dpow = (op * G < kAlphaMax) ? dLda : 0.0f;
+        const float qa = __uint_as_float(s[2]), qb = __uint_as_float(s[3]), qc = __uint_as_float(s[4]);
+        const float dp = alpha * dpow;     // d alpha / d power = o G = alpha
+        float g[9];
+        g[0] = dp * (2.0f * qa * dx + qb * dy);
+        g[1] = dp * (qb * dx + 2.0f * qc * dy);
+        g[2] = dp * dx * dx;
+        g[3] = dp * dx * dy;
+        g[4] = dp * dy * dy;
+        g[5] = G * dpow;
+        g[6] = w * dC0;
+        g[7] = w * dC1;
+        g[8] = w * dC2;
         if (__any(contrib)) {
+          float *dst = gl + (tid >> 6) * batch * 9 + f * 9;
 #pragma unroll
           for (int k = 0; k < 9; ++k) {
-            const float r = wave_sum(g[k]);
-            if (lane == 0 && r != 0.0f) atomicAdd(&gl[f * 9 + k], r);
+            const float r = wave_total(g[k]);
+            if (lane == 63) dst[k] = r;
           }
         }
       } else {
@@ -200,7 +213,9 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
       float *dst = g2d + 9 * (int64_t)s[9];
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
-        const float r = gl[f * 9 + k];
+        float r = 0.0f;
+#pragma unroll
+        for (int w = 0; w < NT / 64; ++w) r += gl[w * batch * 9 + f * 9 + k];
         if (r != 0.0f) unsafeAtomicAdd(dst + k, r);
       }
     }
@@ -469,11 +484,14 @@ __global__ void project_backward_kernel(const ViewParams *__restrict__ views, in
 
 template <int TW, int TH>
 hipError_t launch_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int32_t *nc, const float *Te) {
-  const size_t lds = (size_t)c->frag_batch * (kSlotWords + 9) * sizeof(uint32_t);
+  // the backward's own LDS batch (fragments and per-wave partial sums), at
+  // most 128 fragments: 128 x (32 + 36) words = 34 KB for 16x16 tiles
+  const int batch = std::min(c->frag_batch, 128);
+  const size_t lds = (size_t)batch * (kSlotWords + 9 * (TW * TH / 64)) * sizeof(uint32_t);
   ScopedTimer t(c, K_BLEND_BWD);
   hipLaunchKernelGGL((blend_backward_kernel<TW, TH>), dim3((unsigned)c->n_tiles), dim3(TW * TH), lds,
                      c->stream, c->cur_views, c->V, c->N, c->T, c->mode,
-                     c->frag_batch, c->bg[0], c->bg[1], c->bg[2], (const uint2 *)c->ranges.p,
+                     batch, c->bg[0], c->bg[1], c->bg[2], (const uint2 *)c->ranges.p,
                      (const uint32_t *)c->v0.p, (const uint32_t *)c->v1.p,
                      (const FrameInfo *)c->finfo.p, (const GaussRec *)c->grec.p, (const TriRec *)c->trec.p, dL, Tf, nc, Te,
                      (float *)c->g2d.p);

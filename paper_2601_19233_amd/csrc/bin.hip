@@ -1,7 +1,11 @@
-// Bin stage: exclusive scan of per-primitive tile counts, emission of one
-// (global tile << 32 | depth bits, record id) pair per overlapped tile, and
-// per-tile [start, end) ranges of the sorted pairs.
-#include "internal.h"
+// Bin stage.  The records are put in depth order first (a radix sort of
+// 1 key per record), their tile counts scanned in that order, and one
+// (global tile id, record id) pair emitted per overlapped tile at the
+// record's scanned offset.  Duplicates thus leave the bin stage in depth
+// order, and a stable sort by tile id alone (sort.hip) yields every tile's
+// front-to-back list; per-tile [start, end) ranges are then read off the
+// sorted tile ids.
+#include "support.h"
 
 namespace umgs {
 
@@ -98,49 +102,68 @@ hipError_t excl_scan(hipStream_t s, T *data, int64_t n, T *tmp) {
   return hipGetLastError();
 }
 
-// One thread per record: write one key/value pair per overlapped tile.  The
-// key is (global tile << depth_bits) | (depth key - depth_base): the order of
-// (tile, depth) with the depth range of the frame in as few bits as it needs.
-__global__ void emit_keys_kernel(const ViewParams *__restrict__ views, int V, int per_view,
-                                 int64_t n_records, const uint32_t *__restrict__ depth,
-                                 const uint2 *__restrict__ rects,
-                                 const uint64_t *__restrict__ offs,
-                                 const FrameInfo *__restrict__ fi,
-                                 uint64_t *__restrict__ keys_out,
-                                 uint32_t *__restrict__ vals_out) {
+// Per-view duplicate totals (records are view-major): one partial sum per
+// block, one atomic per block.
+__global__ void view_sum_kernel(const uint64_t *__restrict__ counts, int64_t per_view,
+                                unsigned long long *__restrict__ sums) {
+  const int v = blockIdx.y;
+  const int64_t i = (int64_t)blockIdx.x * kScanTile;
+  uint64_t s = 0;
+  for (int k = threadIdx.x; k < kScanTile; k += kScanThreads)
+    if (i + k < per_view) s += counts[(int64_t)v * per_view + i + k];
+  uint64_t total;
+  block_excl_scan(s, total);
+  if (threadIdx.x == 0 && total) atomicAdd(sums + v, (unsigned long long)total);
+}
+
+// Depth range of the frame: sort keys hold (depth key - base) in depth_bits.
+__global__ void depth_range_kernel(const uint32_t *__restrict__ minmax, FrameInfo *__restrict__ fi) {
+  const uint32_t lo = minmax[0], hi = minmax[1];
+  const bool any = lo <= hi;
+  fi->depth_base = any ? lo : 0u;
+  int db = 1;
+  while (any && db < 32 && (uint64_t)(hi - lo) >= (1ull << db)) ++db;
+  fi->depth_bits = db;
+}
+
+// Depth-sort input: relative depth keys (culled records get all ones, after
+// every visible one) and record ids in id order.
+__global__ void depth_prep_kernel(const uint32_t *__restrict__ depth, int64_t n,
+                                  const FrameInfo *__restrict__ fi, uint32_t *__restrict__ dk,
+                                  uint32_t *__restrict__ dv) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n_records) return;
-  const uint64_t o0 = offs[r], o1 = offs[r + 1];
-  const uint64_t cap = fi->n_dup;          // pairs beyond the key capacity are dropped
-  if (o0 == o1 || o0 >= cap) return;
-  const uint32_t depth_base = fi->depth_base;
-  const int depth_bits = fi->depth_bits;
-  const int v = (int)(r / per_view);
-  const ViewParams &vp = views[v];
-  const uint2 rc = rects[r];
-  const int tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF, ty1 = rc.y >> 16;
-  const uint64_t d = depth[r] - depth_base;
-  uint64_t o = o0;
-  for (int ty = ty0; ty < ty1; ++ty) {
-    const uint64_t row = (uint64_t)vp.tile_base + (uint64_t)ty * vp.ntx;
-    for (int tx = tx0; tx < tx1 && o < cap; ++tx) {
-      keys_out[o] = ((row + tx) << depth_bits) | d;
-      vals_out[o] = (uint32_t)r;
-      ++o;
-    }
-  }
+  if (r >= n) return;
+  const uint32_t k = depth[r];
+  dk[r] = k == kCulled ? 0xFFFFFFFFu : k - fi->depth_base;
+  dv[r] = (uint32_t)r;
+}
+
+// Tile counts in depth order (the count scan then gives each record's first
+// output position); the entry past the end receives the total.
+__global__ void gather_counts_kernel(const uint32_t *__restrict__ order, int64_t n,
+                                     const uint64_t *__restrict__ counts,
+                                     uint64_t *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = counts[order[i]];
+  else if (i == n) out[n] = 0;
 }
 
 // Load-balanced emission: each block owns kEmitSpan consecutive output
 // positions and writes them with consecutive lanes on consecutive addresses.
-// The records covering the block's range are found by binary search in the
-// scanned offsets and staged in LDS; every lane then finds its position's
-// record by binary search in LDS and derives the tile from the position's
-// rank inside the record's tile rectangle (row-major, as the scan counted).
+// Positions follow the depth order of the records; inside a record, its
+// tiles in row-major order, each row cut to the record's support
+// (support.h) exactly as the projection counted them.
+//
+// The block finds the records covering its range by binary search in the
+// scanned offsets and stages them in LDS, then lays out all their tile rows
+// in LDS (first column and tile count of each, scanned), so every lane finds
+// its position's record, row and column by two binary searches in LDS.
+// Output: global tile id (the tile sort's key) and record id.
 constexpr int kEmitThreads = 256;
 constexpr int kEmitPer = 8;
 constexpr int kEmitSpan = kEmitThreads * kEmitPer;
 constexpr int kEmitRecCap = 1024;
+constexpr int kEmitRowCap = 4096;
 
 // last r in [lo, hi] with offs[r] <= d (offs is non-decreasing)
 __device__ __forceinline__ int64_t last_record_at(const uint64_t *__restrict__ offs, int64_t lo,
@@ -152,69 +175,195 @@ __device__ __forceinline__ int64_t last_record_at(const uint64_t *__restrict__ o
   return lo;
 }
 
-__device__ __forceinline__ uint64_t tile_key(const ViewParams *__restrict__ views, int v, uint2 rc,
-                                             uint64_t j, uint32_t dep, int bits) {
-  const uint32_t tx0 = rc.x & 0xFFFF, ty0 = rc.x >> 16, tx1 = rc.y & 0xFFFF;
-  const uint32_t w = tx1 - tx0;
-  const uint32_t jj = (uint32_t)j;
-  const uint32_t ty = ty0 + jj / w, tx = tx0 + jj % w;
-  const uint64_t tile = (uint64_t)views[v].tile_base + (uint64_t)ty * views[v].ntx + tx;
-  return (tile << bits) | dep;
+struct EmitArgs {
+  const ViewParams *views;
+  int per_view, N, tile_w, tile_h;
+  int64_t n_records;
+  const uint32_t *order;
+  const uint2 *rects;
+  const uint64_t *offs;
+  const GaussRec *grec;
+  const FrameInfo *fi;
+  uint32_t *keys_out, *vals_out;
+};
+
+// Columns [a, b) of row ty of record r (tile coordinates of its view).
+__device__ __forceinline__ void record_row(const EmitArgs &e, uint32_t r, uint2 rc, int ty,
+                                           int &a, int &b) {
+  const int v = (int)(r / (uint32_t)e.per_view);
+  const int i = (int)(r - (uint32_t)v * (uint32_t)e.per_view);
+  const int tx0 = rc.x & 0xFFFF, tx1 = rc.y & 0xFFFF;
+  if (i >= e.N) {            // triangle: the whole rectangle
+    a = tx0;
+    b = tx1;
+    return;
+  }
+  const ViewParams &vp = e.views[v];
+  const Support s = make_support(e.grec[(int64_t)v * e.N + i]);
+  support_row(s, ty, e.tile_w, e.tile_h, vp.W, vp.H, tx0, tx1, a, b);
 }
 
-__global__ __launch_bounds__(kEmitThreads) void emit_balanced_kernel(
-    const ViewParams *__restrict__ views, int per_view, int64_t n_records,
-    const uint32_t *__restrict__ depth, const uint2 *__restrict__ rects,
-    const uint64_t *__restrict__ offs, const FrameInfo *__restrict__ fi,
-    uint64_t *__restrict__ keys_out, uint32_t *__restrict__ vals_out) {
+// (clamps keep a tile inside its record's rectangle, hence inside its view,
+// whatever the counts say)
+__device__ __forceinline__ int clampi(int x, int lo, int hi) { return max(lo, min(x, hi)); }
+
+__device__ __forceinline__ uint32_t global_tile(const EmitArgs &e, uint32_t r, int ty, int tx) {
+  const ViewParams &vp = e.views[r / (uint32_t)e.per_view];
+  return vp.tile_base + (uint32_t)ty * (uint32_t)vp.ntx + (uint32_t)tx;
+}
+
+__global__ __launch_bounds__(kEmitThreads) void emit_balanced_kernel(EmitArgs e) {
   __shared__ uint64_t s_off[kEmitRecCap];
   __shared__ uint2 s_rect[kEmitRecCap];
-  __shared__ uint32_t s_dep[kEmitRecCap];
-  __shared__ int32_t s_view[kEmitRecCap];
+  __shared__ uint32_t s_rec[kEmitRecCap];
+  __shared__ uint32_t s_row0[kEmitRecCap + 1];   // first row slot of each staged record
+  __shared__ uint32_t r_pre[kEmitRowCap + 1];    // tiles before each row slot (block scan)
+  __shared__ uint16_t r_lo[kEmitRowCap];         // first tile column of each row slot
+  __shared__ uint32_t s_wsum[kEmitThreads / 64];
   __shared__ int64_t s_lo, s_hi;
-  const uint64_t n = fi->n_dup;
+  __shared__ uint32_t s_rows;
+  const uint64_t n = e.fi->n_dup;
   const uint64_t d0 = (uint64_t)blockIdx.x * kEmitSpan;
   if (d0 >= n) return;
   const uint64_t d1 = min(d0 + (uint64_t)kEmitSpan, n);
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (tid == 0) {
-    s_lo = last_record_at(offs, 0, n_records, d0);
-    s_hi = last_record_at(offs, s_lo, n_records, d1 - 1);
+    s_lo = last_record_at(e.offs, 0, e.n_records, d0);
+    s_hi = last_record_at(e.offs, s_lo, e.n_records, d1 - 1);
   }
   __syncthreads();
   const int64_t rlo = s_lo, rhi = s_hi;
-  const int64_t nr = rhi - rlo + 1;
-  const uint32_t base = fi->depth_base;
-  const int bits = fi->depth_bits;
+  const int nr = (int)min<int64_t>(rhi - rlo + 1, (int64_t)kEmitRecCap + 1);
+  bool staged = false;
   if (nr <= kEmitRecCap) {
-    for (int64_t i = tid; i < nr; i += kEmitThreads) {
-      const int64_t r = rlo + i;
-      s_off[i] = offs[r];
-      s_rect[i] = rects[r];
-      s_dep[i] = depth[r] - base;
-      s_view[i] = (int32_t)(r / per_view);
+    // records and an exclusive scan of their row counts (4 records a thread)
+    uint32_t rows[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = tid * 4 + q;
+      rows[q] = 0;
+      if (k < nr) {
+        const uint32_t r = e.order[rlo + k];
+        const uint2 rc = e.rects[r];
+        s_off[k] = e.offs[rlo + k];
+        s_rec[k] = r;
+        s_rect[k] = rc;
+        rows[q] = (rc.y >> 16) - (rc.x >> 16);
+      }
+      sum += rows[q];
+    }
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) s_wsum[w] = incl;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int k = 0; k < w; ++k) base += s_wsum[k];
+    uint32_t run = base + incl - sum;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = tid * 4 + q;
+      if (k < nr) s_row0[k] = run;
+      run += rows[q];
+    }
+    if (tid == kEmitThreads - 1) {
+      s_rows = run;
+      s_row0[nr] = run;
+    }
+    __syncthreads();
+    staged = s_rows <= kEmitRowCap;
+  }
+  if (staged) {
+    const int R = (int)s_rows;
+    // each row slot: its columns, then a block scan of the tile counts
+    uint32_t cnt[kEmitRowCap / kEmitThreads], sum = 0;
+#pragma unroll
+    for (int q = 0; q < kEmitRowCap / kEmitThreads; ++q) {
+      const int slot = tid * (kEmitRowCap / kEmitThreads) + q;
+      cnt[q] = 0;
+      if (slot < R) {
+        int lo = 0, hi = nr - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if ((int)s_row0[mid] <= slot) lo = mid; else hi = mid - 1;
+        }
+        const uint2 rc = s_rect[lo];
+        int a, b;
+        record_row(e, s_rec[lo], rc, (int)(rc.x >> 16) + (slot - (int)s_row0[lo]), a, b);
+        r_lo[slot] = (uint16_t)a;
+        cnt[q] = (uint32_t)(b - a);
+      }
+      sum += cnt[q];
+    }
+    uint32_t incl = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    __syncthreads();
+    if (lane == 63) s_wsum[w] = incl;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int k = 0; k < w; ++k) base += s_wsum[k];
+    uint32_t run = base + incl - sum;
+#pragma unroll
+    for (int q = 0; q < kEmitRowCap / kEmitThreads; ++q) {
+      const int slot = tid * (kEmitRowCap / kEmitThreads) + q;
+      if (slot <= R) r_pre[slot] = run;
+      run += cnt[q];
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kEmitPer; ++k) {
       const uint64_t d = d0 + (uint64_t)k * kEmitThreads + tid;
       if (d >= d1) break;
-      int lo = 0, hi = (int)nr - 1;
+      int lo = 0, hi = nr - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (s_off[mid] <= d) lo = mid; else hi = mid - 1;
       }
-      keys_out[d] = tile_key(views, s_view[lo], s_rect[lo], d - s_off[lo], s_dep[lo], bits);
-      vals_out[d] = (uint32_t)(rlo + lo);
+      // the record's rows are slots [q0, q1); its j-th tile lies in the last
+      // slot whose scanned count does not exceed r_pre[q0] + j
+      const int q0 = (int)s_row0[lo], q1 = (int)s_row0[lo + 1];
+      const uint32_t target = r_pre[q0] + (uint32_t)(d - s_off[lo]);
+      int a = q0, c = q1 - 1;
+      while (a < c) {
+        const int mid = (a + c + 1) >> 1;
+        if (r_pre[mid] <= target) a = mid; else c = mid - 1;
+      }
+      a = min(a, R - 1);
+      const uint2 rc = s_rect[lo];
+      const int ty = clampi((int)(rc.x >> 16) + (a - q0), (int)(rc.x >> 16), (int)(rc.y >> 16) - 1);
+      const int tx = clampi((int)r_lo[a] + (int)min(target - r_pre[a], 0xFFFFu), (int)(rc.x & 0xFFFF),
+                            (int)(rc.y & 0xFFFF) - 1);
+      e.keys_out[d] = global_tile(e, s_rec[lo], ty, tx);
+      e.vals_out[d] = s_rec[lo];
     }
   } else {
-    // many empty records inside the range: search the offsets in memory
+    // more records or rows than LDS holds: search the offsets in memory and
+    // walk the record's rows
     for (int k = 0; k < kEmitPer; ++k) {
       const uint64_t d = d0 + (uint64_t)k * kEmitThreads + tid;
       if (d >= d1) break;
-      const int64_t r = last_record_at(offs, rlo, rhi, d);
-      keys_out[d] = tile_key(views, (int)(r / per_view), rects[r], d - offs[r], depth[r] - base, bits);
-      vals_out[d] = (uint32_t)r;
+      const int64_t i = last_record_at(e.offs, rlo, rhi, d);
+      const uint32_t r = e.order[i];
+      const uint2 rc = e.rects[r];
+      uint32_t j = (uint32_t)(d - e.offs[i]);
+      const int ty0 = (int)(rc.x >> 16), ty1 = (int)(rc.y >> 16);
+      int ty = ty0, a = 0, b = 0;
+      for (; ty < ty1; ++ty) {
+        record_row(e, r, rc, ty, a, b);
+        if (j < (uint32_t)(b - a)) break;
+        j -= (uint32_t)(b - a);
+      }
+      ty = clampi(ty, ty0, ty1 - 1);
+      const int tx = clampi(a + (int)min(j, 0xFFFFu), (int)(rc.x & 0xFFFF), (int)(rc.y & 0xFFFF) - 1);
+      e.keys_out[d] = global_tile(e, r, ty, tx);
+      e.vals_out[d] = r;
     }
   }
 }
@@ -224,46 +373,38 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
-// Turns the scanned total and the depth range into the frame's sizes.
-__global__ void frame_info_kernel(const uint64_t *__restrict__ total,
-                                  const uint32_t *__restrict__ minmax, uint64_t cap,
-                                  int tile_bits, FrameInfo *__restrict__ fi) {
+// Turns the scanned total into the frame's duplicate count (clamped to the
+// key capacity, overflow flagged) and resets the persistent blend's queue.
+__global__ void frame_info_kernel(const uint64_t *__restrict__ total, uint64_t cap,
+                                  int sorted_in, FrameInfo *__restrict__ fi) {
   const uint64_t raw = *total;
   fi->n_dup = (uint32_t)(raw < cap ? raw : cap);
   if (raw > cap) fi->overflow = 1u;
-  const uint32_t lo = minmax[0], hi = minmax[1];
-  const bool any = lo <= hi;
-  fi->depth_base = any ? lo : 0u;
-  int db = 1;
-  while (any && db < 32 && (uint64_t)(hi - lo) >= (1ull << db)) ++db;
-  fi->depth_bits = db;
-  fi->total_bits = db + tile_bits;
-  fi->sorted_in = ((db + tile_bits + 7) / 8) & 1;
+  fi->sorted_in = sorted_in;
   fi->queue = 0u;
 }
 
-__global__ void tile_ranges_kernel(const uint64_t *__restrict__ k0, const uint64_t *__restrict__ k1,
+__global__ void tile_ranges_kernel(const uint32_t *__restrict__ k0, const uint32_t *__restrict__ k1,
                                    const FrameInfo *__restrict__ fi, uint2 *__restrict__ ranges) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint64_t n = fi->n_dup;
   if (i >= n) return;
-  const int shift = fi->depth_bits;
-  const uint64_t *keys = fi->sorted_in ? k1 : k0;
-  const uint32_t t = (uint32_t)(keys[i] >> shift);
-  if (i == 0 || (uint32_t)(keys[i - 1] >> shift) != t) ranges[t].x = (uint32_t)i;
-  if (i == n - 1 || (uint32_t)(keys[i + 1] >> shift) != t) ranges[t].y = (uint32_t)(i + 1);
+  const uint32_t *keys = fi->sorted_in ? k1 : k0;
+  const uint32_t t = keys[i];
+  if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
+  if (i == n - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
 }
 
-// Sorted keys back in the exported (tile << 32 | depth key bits) form.
-__global__ void expand_keys_kernel(const uint64_t *__restrict__ k0, const uint64_t *__restrict__ k1,
+// Sorted pairs in the exported (tile << 32 | depth key bits) form.
+__global__ void expand_keys_kernel(const uint32_t *__restrict__ k0, const uint32_t *__restrict__ k1,
+                                   const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1,
+                                   const uint32_t *__restrict__ depth,
                                    const FrameInfo *__restrict__ fi, uint64_t *__restrict__ out) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= fi->n_dup) return;
-  const int shift = fi->depth_bits;
-  const uint32_t base = fi->depth_base;
-  const uint64_t k = (fi->sorted_in ? k1 : k0)[i];
-  const uint64_t mask = shift >= 64 ? ~0ull : ((1ull << shift) - 1ull);
-  out[i] = ((k >> shift) << 32) | (uint64_t)((uint32_t)(k & mask) + base);
+  const uint32_t t = (fi->sorted_in ? k1 : k0)[i];
+  const uint32_t r = (fi->sorted_in ? v1 : v0)[i];
+  out[i] = ((uint64_t)t << 32) | (uint64_t)depth[r];
 }
 
 }  // namespace
@@ -279,29 +420,11 @@ size_t scan_tmp_bytes(int64_t n) {
 }
 
 hipError_t launch_exclusive_scan_u64(Ctx *c, uint64_t *data, int64_t n, uint64_t *tmp) {
-  ScopedTimer t(c, K_SCAN);
   return excl_scan<uint64_t>(c->stream, data, n, tmp);
 }
 
 hipError_t launch_exclusive_scan_u32(Ctx *c, uint32_t *data, int64_t n, uint32_t *tmp) {
-  ScopedTimer t(c, K_SORT_SCAN);
   return excl_scan<uint32_t>(c->stream, data, n, tmp);
-}
-
-hipError_t launch_emit_keys(Ctx *c) {
-  hipLaunchKernelGGL(frame_info_kernel, dim3(1), dim3(1), 0, c->stream,
-                     (const uint64_t *)c->counts.p + c->n_records, (const uint32_t *)c->minmax.p,
-                     (uint64_t)c->key_cap, c->tile_bits, (FrameInfo *)c->finfo.p);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || c->n_records == 0) return e;
-  if (c->n_launch == 0) return hipSuccess;
-  ScopedTimer t(c, K_EMIT);
-  hipLaunchKernelGGL(emit_balanced_kernel, dim3(ceil_div(c->n_launch, kEmitSpan)),
-                     dim3(kEmitThreads), 0, c->stream, c->cur_views,
-                     c->N + c->T, c->n_records, (const uint32_t *)c->keys.p,
-                     (const uint2 *)c->rects.p, (const uint64_t *)c->counts.p,
-                     (const FrameInfo *)c->finfo.p, (uint64_t *)c->k0.p, (uint32_t *)c->v0.p);
-  return hipGetLastError();
 }
 
 hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v) {
@@ -310,12 +433,89 @@ hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v) {
   return hipGetLastError();
 }
 
+hipError_t launch_view_sums(Ctx *c, unsigned long long *sums) {
+  hipError_t e = launch_fill_u32(c, (uint32_t *)sums, 2 * (int64_t)c->V, 0u);
+  const int64_t per = (int64_t)c->N + c->T;
+  if (e != hipSuccess || per == 0) return e;
+  hipLaunchKernelGGL(view_sum_kernel, dim3(ceil_div(per, kScanTile), c->V), dim3(kScanThreads), 0,
+                     c->stream, (const uint64_t *)c->counts.p, per, sums);
+  return hipGetLastError();
+}
+
+// Records in (depth key, record id) order, then their tile counts in that
+// order scanned into output offsets (total at index n_records).  The depth
+// sort runs four 8-bit passes; those beyond the frame's depth bits (known on
+// the device) copy through, so the order lands in dk[0]/dv[0].
+hipError_t launch_depth_order(Ctx *c) {
+  const int64_t n = c->n_records;
+  FrameInfo *fi = (FrameInfo *)c->finfo.p;
+  hipError_t e;
+  {
+    ScopedTimer t(c, K_DEPTH_SORT);
+    hipLaunchKernelGGL(depth_range_kernel, dim3(1), dim3(1), 0, c->stream,
+                       (const uint32_t *)c->minmax.p, fi);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (n == 0) return launch_fill_u32(c, (uint32_t *)c->offs.p, 2, 0u);   // total: 0
+    hipLaunchKernelGGL(depth_prep_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, c->stream,
+                       (const uint32_t *)c->keys.p, n, (const FrameInfo *)fi,
+                       (uint32_t *)c->dk[0].p, (uint32_t *)c->dv[0].p);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    uint32_t *k[2] = {(uint32_t *)c->dk[0].p, (uint32_t *)c->dk[1].p};
+    uint32_t *v[2] = {(uint32_t *)c->dv[0].p, (uint32_t *)c->dv[1].p};
+    e = launch_radix_sort_u32(c, k, v, (uint64_t)n, nullptr, &fi->depth_bits, 32, -1, -1, -1);
+    if (e != hipSuccess) return e;
+  }
+  ScopedTimer t(c, K_SCAN);
+  hipLaunchKernelGGL(gather_counts_kernel, dim3(ceil_div(n + 1, 256)), dim3(256), 0, c->stream,
+                     (const uint32_t *)c->dv[0].p, n, (const uint64_t *)c->counts.p,
+                     (uint64_t *)c->offs.p);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return excl_scan<uint64_t>(c->stream, (uint64_t *)c->offs.p, n + 1, (uint64_t *)c->scan_tmp.p);
+}
+
+hipError_t launch_emit_keys(Ctx *c) {
+  hipLaunchKernelGGL(frame_info_kernel, dim3(1), dim3(1), 0, c->stream,
+                     (const uint64_t *)c->offs.p + c->n_records, (uint64_t)c->key_cap,
+                     c->sort_passes & 1, (FrameInfo *)c->finfo.p);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || c->n_records == 0) return e;
+  if (c->n_launch == 0) return hipSuccess;
+  ScopedTimer t(c, K_EMIT);
+  EmitArgs a;
+  a.views = c->cur_views;
+  a.per_view = c->N + c->T;
+  a.N = c->N;
+  a.tile_w = c->tile_w;
+  a.tile_h = c->tile_h;
+  a.n_records = c->n_records;
+  a.order = (const uint32_t *)c->dv[0].p;
+  a.rects = (const uint2 *)c->rects.p;
+  a.offs = (const uint64_t *)c->offs.p;
+  a.grec = (const GaussRec *)c->grec.p;
+  a.fi = (const FrameInfo *)c->finfo.p;
+  a.keys_out = (uint32_t *)c->k0.p;
+  a.vals_out = (uint32_t *)c->v0.p;
+  hipLaunchKernelGGL(emit_balanced_kernel, dim3(ceil_div(c->n_launch, kEmitSpan)),
+                     dim3(kEmitThreads), 0, c->stream, a);
+  return hipGetLastError();
+}
+
+// Duplicates by global tile id: radix passes over the tile bits, element
+// count read on the device.
+hipError_t launch_tile_sort(Ctx *c) {
+  uint32_t *k[2] = {(uint32_t *)c->k0.p, (uint32_t *)c->k1.p};
+  uint32_t *v[2] = {(uint32_t *)c->v0.p, (uint32_t *)c->v1.p};
+  return launch_radix_sort_u32(c, k, v, c->n_launch, &((const FrameInfo *)c->finfo.p)->n_dup,
+                               nullptr, c->tile_bits, K_SORT_UPSWEEP, K_SORT_SCAN,
+                               K_SORT_DOWNSWEEP);
+}
+
 hipError_t launch_tile_ranges(Ctx *c) {
   ScopedTimer t(c, K_RANGES);
   hipError_t e = launch_fill_u32(c, (uint32_t *)c->ranges.p, 2 * c->n_tiles, 0u);
   if (e != hipSuccess || c->n_launch == 0) return e;
   hipLaunchKernelGGL(tile_ranges_kernel, dim3(ceil_div(c->n_launch, 256)), dim3(256), 0, c->stream,
-                     (const uint64_t *)c->k0.p, (const uint64_t *)c->k1.p,
+                     (const uint32_t *)c->k0.p, (const uint32_t *)c->k1.p,
                      (const FrameInfo *)c->finfo.p, (uint2 *)c->ranges.p);
   return hipGetLastError();
 }
@@ -323,8 +523,9 @@ hipError_t launch_tile_ranges(Ctx *c) {
 hipError_t launch_expand_keys(Ctx *c, uint64_t *dst) {
   if (c->n_launch == 0) return hipSuccess;
   hipLaunchKernelGGL(expand_keys_kernel, dim3(ceil_div(c->n_launch, 256)), dim3(256), 0, c->stream,
-                     (const uint64_t *)c->k0.p, (const uint64_t *)c->k1.p,
-                     (const FrameInfo *)c->finfo.p, dst);
+                     (const uint32_t *)c->k0.p, (const uint32_t *)c->k1.p,
+                     (const uint32_t *)c->v0.p, (const uint32_t *)c->v1.p,
+                     (const uint32_t *)c->keys.p, (const FrameInfo *)c->finfo.p, dst);
   return hipGetLastError();
 }
 

@@ -27,8 +27,10 @@ namespace umgs {
 
 namespace {
 
-// COUNT instantiations also count the (pixel, fragment) pairs each pixel
-// evaluates before it is done (Gaussian, triangle) into pairs[0..1].
+// COUNT instantiations also count into pairs[0..3]: the (pixel, fragment)
+// pairs each pixel evaluates before it is done (Gaussian, triangle), the
+// wave iterations of the fragment loop (times 64 lanes: the SIMD slots the
+// pairs occupy) and the fragments staged into LDS.
 template <int TW, int TH, bool COUNT = false>
 __device__ __forceinline__ void blend_tile(
     uint32_t tile, uint32_t *__restrict__ slots, const ViewParams *__restrict__ views, int V,
@@ -37,7 +39,7 @@ __device__ __forceinline__ void blend_tile(
     const GaussRec *__restrict__ grec, const TriRec *__restrict__ trec,
     float *__restrict__ image, float *__restrict__ Tout, int32_t *__restrict__ ncontrib,
     float *__restrict__ Tent_out, unsigned long long *__restrict__ pairs = nullptr) {
-  uint32_t n_gp = 0, n_tp = 0;
+  uint32_t n_gp = 0, n_tp = 0, n_wit = 0;
   constexpr int NT = TW * TH;
   const int v = find_view(views, V, tile);
   const ViewParams &vp = views[v];
@@ -66,7 +68,9 @@ __device__ __forceinline__ void blend_tile(
 
   for (uint32_t bstart = rg.x; bstart < rg.y; bstart += batch) {
     const uint32_t bn = min((uint32_t)batch, rg.y - bstart);
+    if (COUNT && tid == 0) atomicAdd(pairs + 3, (unsigned long long)bn);
     // ---- stage fragments into LDS
+    int tri_here = 0;
     for (uint32_t f = tid; f < bn; f += NT) {
       uint32_t *s = slots + f * kSlotWords;
       const int64_t local = (int64_t)vals[bstart + f] - rbase;
@@ -75,14 +79,73 @@ __device__ __forceinline__ void blend_tile(
         stage_gauss(s, grec[rec], rec);
       } else {
         stage_tri(s, trec[(int64_t)v * T + (local - N)], P0x, P0y);
+        tri_here = 1;
       }
     }
-    __syncthreads();
+    const bool any_tri = __syncthreads_or(tri_here) != 0;
 
     // ---- blend the batch
-    if (!done) {
+    if (!done && !any_tri) {
+      // Gaussians only: alpha of kUnroll fragments evaluated together (they
+      // do not depend on the pixel's state), then blended in list order.
+      constexpr int kUnroll = 4;
+      uint32_t f = 0;
+      for (; f + kUnroll <= bn; f += kUnroll) {
+        if (__all(done)) break;
+        if (COUNT) n_wit += kUnroll;
+        float al[kUnroll], cr[kUnroll], cg[kUnroll], cb[kUnroll];
+        bool ok[kUnroll];
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+          const uint32_t *s = slots + (f + k) * kSlotWords;
+          ok[k] = gauss_alpha(s, pcx, pcy, al[k]);
+          cr[k] = __uint_as_float(s[6]);
+          cg[k] = __uint_as_float(s[7]);
+          cb[k] = __uint_as_float(s[8]);
+        }
+        // selects instead of branches: a fragment that is not blended adds
+        // w = 0 (C + 0 c == C exactly for the finite, non-negative colours)
+#pragma unroll
+        for (int k = 0; k < kUnroll; ++k) {
+          if (COUNT) n_gp += done ? 0u : 1u;
+          const bool take = !done && ok[k];
+          const float test_T = Tr * (1.0f - al[k]);
+          const bool stop = take && test_T < kTStop;
+          const bool blend = take && !stop;
+          done = done || stop;
+          const float w = blend ? Tr * al[k] : 0.0f;
+          C0 = fmaf(w, cr[k], C0);
+          C1 = fmaf(w, cg[k], C1);
+          C2 = fmaf(w, cb[k], C2);
+          Tent = blend ? Tr : Tent;
+          Tr = blend ? test_T : Tr;
+          if (mode != UMGS_MODE_ONE_ENTITY) in_entity = in_entity && !blend;
+          last = blend ? (int32_t)(bstart - rg.x + f + k + 1) : last;
+        }
+      }
+      for (; f < bn; ++f) {
+        if (__all(done)) break;
+        if (COUNT) ++n_wit;
+        if (done) continue;
+        if (COUNT) ++n_gp;
+        const uint32_t *s = slots + f * kSlotWords;
+        float alpha, G, dx, dy;
+        if (!gauss_eval(s, pcx, pcy, alpha, G, dx, dy)) continue;
+        const float test_T = Tr * (1.0f - alpha);
+        if (test_T < kTStop) { done = true; continue; }
+        const float w = Tr * alpha;
+        C0 = fmaf(w, __uint_as_float(s[6]), C0);
+        C1 = fmaf(w, __uint_as_float(s[7]), C1);
+        C2 = fmaf(w, __uint_as_float(s[8]), C2);
+        Tent = Tr;
+        Tr = test_T;
+        if (mode != UMGS_MODE_ONE_ENTITY) in_entity = false;
+        last = (int32_t)(bstart - rg.x + f + 1);
+      }
+    } else if (!done) {
       for (uint32_t f = 0; f < bn; ++f) {
         if (__all(done)) break;
+        if (COUNT) ++n_wit;
         const uint32_t *s = slots + f * kSlotWords;
         const uint32_t tag = s[31];
         if (done) continue;
@@ -162,6 +225,7 @@ __device__ __forceinline__ void blend_tile(
     if ((threadIdx.x & 63) == 0) {
       atomicAdd(pairs, g);
       atomicAdd(pairs + 1, t);
+      atomicAdd(pairs + 2, (unsigned long long)n_wit);
     }
   }
 }

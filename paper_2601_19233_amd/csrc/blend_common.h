@@ -65,6 +65,34 @@ __device__ __forceinline__ bool gauss_eval(const uint32_t *s, float pcx, float p
   return alpha >= kAlphaMin;
 }
 
+// The same decision without branches (exp evaluated even where power > 0;
+// the result is then discarded): lets several fragments be evaluated
+// together.  Bit-identical alpha and decision to gauss_eval.
+__device__ __forceinline__ bool gauss_alpha(const uint32_t *s, float pcx, float pcy, float &alpha) {
+  const float4 a = *(const float4 *)(s + 0);
+  const float4 b = *(const float4 *)(s + 4);
+  const float dx = a.x - pcx;
+  const float dy = a.y - pcy;
+  const float power = fmaf(a.z, dx * dx, fmaf(a.w, dx * dy, b.x * (dy * dy)));
+  alpha = fminf(kAlphaMax, b.y * __expf(power));
+  return power <= 0.0f && alpha >= kAlphaMin;
+}
+
+// gauss_alpha that also returns G = exp(power) and the offsets the
+// gradients need (all finite for any record; meaningful when it returns true).
+__device__ __forceinline__ bool gauss_terms(const uint32_t *s, float pcx, float pcy, float &alpha,
+                                            float &G, float &dx, float &dy) {
+  const float4 a = *(const float4 *)(s + 0);
+  const float4 b = *(const float4 *)(s + 4);
+  dx = a.x - pcx;
+  dy = a.y - pcy;
+  const float power = fmaf(a.z, dx * dx, fmaf(a.w, dx * dy, b.x * (dy * dy)));
+  const bool inside = power <= 0.0f;
+  G = __expf(inside ? power : 0.0f);
+  alpha = fminf(kAlphaMax, b.y * G);
+  return inside && alpha >= kAlphaMin;
+}
+
 // Triangle: edge functions at the pixel centre (exact) and sub-sample
 // coverage.  Returns the number of covered samples (0: not a fragment of
 // this pixel).  In direct mode only the pixel centre is tested and o[] is 1.

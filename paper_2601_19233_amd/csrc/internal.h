@@ -60,7 +60,8 @@ struct __align__(16) TriRec {
 // Kernel ids for the event-based profiler (same order as UMGS_K_* in unimgs.h).
 enum KernelId {
   K_VERTEX_FRAMES = 0, K_TRANSFER, K_PROJECT, K_TRIANGLES, K_SCAN, K_EMIT, K_SORT_UPSWEEP,
-  K_SORT_SCAN, K_SORT_DOWNSWEEP, K_RANGES, K_BLEND, K_BLEND_BWD, K_PROJECT_BWD, K_COUNT
+  K_SORT_SCAN, K_SORT_DOWNSWEEP, K_RANGES, K_BLEND, K_BLEND_BWD, K_PROJECT_BWD, K_DEPTH_SORT,
+  K_COUNT
 };
 
 struct Prof {
@@ -77,8 +78,8 @@ struct Prof {
 struct FrameInfo {
   uint32_t n_dup;        // duplicates in the sort (clamped to the key capacity)
   uint32_t depth_base;   // smallest depth-key bits of the frame
-  int32_t depth_bits;    // bits of (depth key - depth_base) in a sort key
-  int32_t total_bits;    // depth_bits + tile bits
+  int32_t depth_bits;    // significant bits of (depth key - depth_base)
+  int32_t pad0;
   int32_t sorted_in;     // 0: sorted pairs in k0/v0, 1: in k1/v1
   uint32_t overflow;     // sticky: the duplicates exceeded the key capacity
   uint32_t queue;        // work counter of the persistent blend
@@ -112,14 +113,13 @@ struct Ctx {
   int64_t n_pixels = 0;
   uint64_t n_dup = 0;         // duplicates of the frame as last read on the host
   uint64_t n_launch = 0;      // elements the sort-stage grids cover (n_dup, or the capacity)
-  int sort_passes = 0;        // radix passes launched
+  int sort_passes = 0;        // radix passes of the tile sort
   int tile_bits = 1;
-  uint32_t depth_base = 0;   // smallest depth-key bits of the frame
-  int depth_bits = 32;       // bits of (depth key - depth_base) in the sort key
   DevBuf minmax;       // 2 uint32: min / max depth-key bits of the frame
   DevBuf finfo;        // FrameInfo (device)
   DevBuf tile_order;   // 64 bucket counters + n_tiles tile ids (persistent blend)
-  DevBuf pair_count;   // 2 uint64: evaluated (pixel, fragment) pairs (measurement)
+  DevBuf pair_count;   // 4 uint64: blend work counters (measurement)
+  DevBuf view_sums;    // V uint64: duplicates per view
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   uint64_t key_cap = 0;      // duplicates the key buffers hold
@@ -132,15 +132,16 @@ struct Ctx {
   std::vector<int64_t> view_set_off;                // offset of each table in d_views
   int64_t view_used = 0;                            // ViewParams stored
   const ViewParams *cur_views = nullptr;            // table of the current frame
-  bool scanned = false;      // the count scan of the current frame has run
   DevBuf keys;         // n_records uint32 depth bits
   DevBuf rects;        // n_records uint2: (tx0 | ty0 << 16, tx1 | ty1 << 16) inclusive-exclusive
-  DevBuf counts;       // n_records + 1 uint64 (scanned in place to offsets)
+  DevBuf counts;       // n_records uint64 tile counts
+  DevBuf dk[2], dv[2]; // n_records uint32: depth-sort keys / record ids (ping-pong)
+  DevBuf offs;         // n_records + 1 uint64: tile counts in depth order, scanned
   DevBuf grec;         // V*N GaussRec
   DevBuf trec;         // V*T TriRec
   DevBuf scan_tmp;
-  DevBuf k0, k1;       // n_dup uint64 keys (ping-pong)
-  DevBuf v0, v1;       // n_dup uint32 values
+  DevBuf k0, k1;       // n_dup uint32 global tile ids (ping-pong)
+  DevBuf v0, v1;       // n_dup uint32 record ids
   DevBuf hist;         // radix per-block histograms
   DevBuf ranges;       // n_tiles uint2
   DevBuf g2d;          // V*N x 9 per-view 2D gradients (backward)
@@ -170,11 +171,20 @@ hipError_t launch_project_gaussians(Ctx *c, const float *means, const float *cov
 hipError_t launch_setup_triangles(Ctx *c, const float *tri_xyz, const float *tri_rgb,
                                   const float *tri_alpha);
 hipError_t launch_exclusive_scan_u32(Ctx *c, uint32_t *data, int64_t n, uint32_t *tmp);
+hipError_t launch_exclusive_scan_u64(Ctx *c, uint64_t *data, int64_t n, uint64_t *tmp);
+hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v);
 size_t scan_tmp_bytes(int64_t n);
+hipError_t launch_view_sums(Ctx *c, unsigned long long *sums);
+hipError_t launch_depth_order(Ctx *c);
 hipError_t launch_emit_keys(Ctx *c);
-hipError_t launch_radix_sort(Ctx *c);
+hipError_t launch_radix_sort_u32(Ctx *c, uint32_t *keys[2], uint32_t *vals[2], uint64_t n_launch,
+                                 const uint32_t *n_dev, const int32_t *bits_dev, int bits,
+                                 int kid_up, int kid_scan, int kid_down);
+int radix_passes(int bits);
 size_t radix_hist_bytes(uint64_t n);
+hipError_t launch_tile_sort(Ctx *c);
 hipError_t launch_tile_ranges(Ctx *c);
+hipError_t launch_expand_keys(Ctx *c, uint64_t *dst);
 hipError_t launch_blend(Ctx *c, float *image, float *T_final, int32_t *n_contrib,
                         float *T_entity_in, unsigned long long *pairs = nullptr);
 hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32_t *nc,

@@ -13,7 +13,7 @@
 // reproducible bit for bit: x_view = ((R0 x + R1 y) + R2 z) + t,
 // u = (fx x_view) / z_view + cx, X = rint(u * 256),
 // key_tri = ((z0 + z1) + z2) * (1/3).
-#include "internal.h"
+#include "support.h"
 
 namespace umgs {
 
@@ -183,18 +183,6 @@ __device__ uint32_t project_gaussian(const ViewParams *__restrict__ views, int N
   int py1 = (int)floorf(fminf(my + hy - 0.5f, (float)vp.H)) + 1;
   px0 = max(px0, 0); py0 = max(py0, 0);
   px1 = min(px1, vp.W); py1 = min(py1, vp.H);
-  uint32_t cnt = 0;
-  uint2 rect = make_uint2(0, 0);
-  if (px0 < px1 && py0 < py1) {
-    const int tx0 = px0 / tile_w, tx1 = (px1 - 1) / tile_w + 1;
-    const int ty0 = py0 / tile_h, ty1 = (py1 - 1) / tile_h + 1;
-    cnt = (uint32_t)((tx1 - tx0) * (ty1 - ty0));
-    rect = pack_rect(tx0, ty0, tx1, ty1);
-  }
-  keys[rid] = __float_as_uint(zv);
-  counts[rid] = cnt;
-  rects[rid] = rect;
-
   // view-dependent colour from the camera centre -R^T t
   const float ccx = -(W[0] * vp.t[0] + W[3] * vp.t[1] + W[6] * vp.t[2]);
   const float ccy = -(W[1] * vp.t[0] + W[4] * vp.t[1] + W[7] * vp.t[2]);
@@ -218,6 +206,24 @@ __device__ uint32_t project_gaussian(const ViewParams *__restrict__ views, int N
   rec.b = b;
   rec.pad[0] = rec.pad[1] = rec.pad[2] = 0.0f;
   grec[(int64_t)v * N + i] = rec;
+
+  // tiles: the rows of the bounding rectangle, each cut to the support
+  uint32_t cnt = 0;
+  uint2 rect = make_uint2(0, 0);
+  if (px0 < px1 && py0 < py1) {
+    const int tx0 = px0 / tile_w, tx1 = (px1 - 1) / tile_w + 1;
+    const int ty0 = py0 / tile_h, ty1 = (py1 - 1) / tile_h + 1;
+    const Support sup = make_support(rec);
+    for (int ty = ty0; ty < ty1; ++ty) {
+      int a, b;
+      support_row(sup, ty, tile_w, tile_h, vp.W, vp.H, tx0, tx1, a, b);
+      cnt += (uint32_t)(b - a);
+    }
+    if (cnt) rect = pack_rect(tx0, ty0, tx1, ty1);
+  }
+  keys[rid] = __float_as_uint(zv);
+  counts[rid] = cnt;
+  rects[rid] = rect;
   return __float_as_uint(zv);
 }
 

@@ -1,6 +1,8 @@
-// Stable LSD radix sort of 64-bit (tile << 32 | depth) keys with 32-bit
-// values, 8-bit digits, over the significant bits only (32 depth bits plus
-// the bits of the largest global tile id).
+// Stable LSD radix sort of 32-bit keys with 32-bit values, at most 8 bits a
+// pass.  Two sorts use it: the records by depth key (values: record ids, so
+// equal depths stay in id order), and the duplicates -- emitted in that
+// depth order -- by global tile id, which leaves every tile's list ordered
+// by (depth key, record id).
 //
 // Each pass is reduce-then-scan: an upsweep writes per-block digit counts in
 // digit-major order, an exclusive scan turns them into global offsets, and a
@@ -11,11 +13,16 @@
 // 4 waves x 16 rounds x 64 lanes, wave-major, so block order is key order.
 // Logical blocks are laid out contiguously per XCD, so the digit runs that
 // neighbouring blocks write side by side are merged in the same L2.
+//
+// The element count may live on the device (a captured frame does not know
+// it on the host), and so may the number of significant key bits: a pass
+// whose shift reaches them copies its input through unchanged.
 #include "internal.h"
 
 namespace umgs {
 
 hipError_t launch_exclusive_scan_u32(Ctx *c, uint32_t *data, int64_t n, uint32_t *tmp);
+hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v);
 
 namespace {
 
@@ -25,83 +32,110 @@ constexpr int kRounds = 16;
 constexpr int kTile = kThreads * kRounds;   // 4096
 constexpr int kBins = 256;
 
-__global__ __launch_bounds__(kThreads) void rs_upsweep(const uint64_t *__restrict__ keys,
-                                                       const FrameInfo *__restrict__ fi, int shift,
-                                                       uint32_t *__restrict__ hist,
-                                                       uint32_t nblocks) {
-  if (shift >= fi->total_bits) return;     // pass beyond the significant bits
-  const uint32_t n = fi->n_dup;
+struct PassArgs {
+  uint32_t n_host;           // element count if n_dev is null
+  const uint32_t *n_dev;     // element count on the device (clamped to n_host)
+  const int32_t *bits_dev;   // significant key bits on the device, or null
+  int shift;
+  uint32_t mask;             // digit mask (2^bits - 1)
+  uint32_t nblocks;
+};
+
+__device__ __forceinline__ uint32_t pass_count(const PassArgs &a) {
+  return a.n_dev ? min(*a.n_dev, a.n_host) : a.n_host;
+}
+
+__device__ __forceinline__ bool pass_through(const PassArgs &a) {
+  return a.bits_dev && a.shift >= *a.bits_dev;
+}
+
+// Equal-digit lane mask of the wave (8 ballots over the digit's bits).
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+  uint64_t m = __ballot(valid);
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const uint64_t bb = __ballot((d >> b) & 1);
+    m &= ((d >> b) & 1) ? bb : ~bb;
+  }
+  return m;
+}
+
+__global__ __launch_bounds__(kThreads) void rs_upsweep(const uint32_t *__restrict__ keys,
+                                                       PassArgs a, uint32_t *__restrict__ hist) {
+  if (pass_through(a)) return;
+  const uint32_t n = pass_count(a);
   __shared__ uint32_t h[kWaves][kBins];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int k = tid; k < kWaves * kBins; k += kThreads) (&h[0][0])[k] = 0;
   __syncthreads();
-  const uint32_t blk = xcd_block(blockIdx.x, nblocks);
+  const uint32_t blk = xcd_block(blockIdx.x, a.nblocks);
   const uint32_t wbase = blk * kTile + w * (kRounds * 64);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint64_t key[kRounds];
+  uint32_t key[kRounds];
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t idx = wbase + r * 64 + lane;
-    key[r] = idx < n ? keys[idx] : 0ull;
+    key[r] = idx < n ? keys[idx] : 0u;
   }
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     // one LDS add per distinct digit of the wave: the lowest lane of each
     // equal-digit lane set adds the set's size
     const bool valid = wbase + r * 64 + lane < n;
-    const uint32_t d = (uint32_t)(key[r] >> shift) & 0xFF;
-    uint64_t m = __ballot(valid);
-#pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint64_t bb = __ballot((d >> b) & 1);
-      m &= ((d >> b) & 1) ? bb : ~bb;
-    }
+    const uint32_t d = (key[r] >> a.shift) & a.mask;
+    const uint64_t m = digit_peers(d, valid);
     if (valid && (m & lt) == 0) h[w][d] += (uint32_t)__popcll(m);
     __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
   const uint32_t s = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
-  hist[(uint64_t)tid * nblocks + blk] = s;
+  hist[(uint64_t)tid * a.nblocks + blk] = s;
 }
 
 __global__ __launch_bounds__(kThreads) void rs_downsweep(
-    const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-    uint64_t *__restrict__ kout, uint32_t *__restrict__ vout, const FrameInfo *__restrict__ fi,
-    int shift, const uint32_t *__restrict__ offs, uint32_t nblocks) {
-  if (shift >= fi->total_bits) return;
-  const uint32_t n = fi->n_dup;
-  const uint32_t blk = xcd_block(blockIdx.x, nblocks);
-  if (blk * (uint32_t)kTile >= n) return;
-  __shared__ uint64_t sk[kTile];
+    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+    uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, PassArgs a,
+    const uint32_t *__restrict__ offs) {
+  const uint32_t n = pass_count(a);
+  const uint32_t blk = xcd_block(blockIdx.x, a.nblocks);
+  const uint32_t base = blk * kTile;
+  if (base >= n) return;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (pass_through(a)) {
+    const uint32_t end = min(base + (uint32_t)kTile, n);
+    for (uint32_t i = base + tid; i < end; i += kThreads) {
+      kout[i] = kin[i];
+      vout[i] = vin[i];
+    }
+    return;
+  }
+  __shared__ uint32_t sk[kTile];
   __shared__ uint32_t sv[kTile];
   __shared__ uint32_t wcnt[kWaves][kBins];
   __shared__ uint32_t lstart[kBins];
   __shared__ uint32_t gbase[kBins];
   __shared__ uint32_t wscan[kWaves];
 
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int k = tid; k < kWaves * kBins; k += kThreads) (&wcnt[0][0])[k] = 0;
   __syncthreads();
 
-  const uint32_t base = blk * kTile;
   const uint32_t wbase = base + w * (kRounds * 64);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint64_t key[kRounds];
+  uint32_t key[kRounds];
   uint32_t val[kRounds];
   uint32_t rank[kRounds];   // digit | (rank within the wave) << 8
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t idx = wbase + r * 64 + lane;
     const bool valid = idx < n;
-    key[r] = valid ? kin[idx] : 0ull;
+    key[r] = valid ? kin[idx] : 0u;
     val[r] = valid ? vin[idx] : 0u;
-    const uint32_t d = (uint32_t)(key[r] >> shift) & 0xFF;
-    uint64_t m = __ballot(valid);
+  }
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
-      const uint64_t bb = __ballot((d >> b) & 1);
-      m &= ((d >> b) & 1) ? bb : ~bb;
-    }
+  for (int r = 0; r < kRounds; ++r) {
+    const bool valid = wbase + r * 64 + lane < n;
+    const uint32_t d = (key[r] >> a.shift) & a.mask;
+    const uint64_t m = digit_peers(d, valid);
     const uint32_t before = (uint32_t)__popcll(m & lt);
     const uint32_t prev = wcnt[w][d];
     if (valid && before == 0) wcnt[w][d] = prev + (uint32_t)__popcll(m);
@@ -113,9 +147,8 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
   // per digit: counts over waves, exclusive prefix over waves, block scan over digits
   {
     const int d = tid;
-    uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
+    const uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
     const uint32_t tot = c0 + c1 + c2 + c3;
-    // inclusive scan of tot over the 256 digits
     uint32_t x = tot;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
@@ -128,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
     for (int k = 0; k < w; ++k) pre += wscan[k];
     const uint32_t ls = pre + x - tot;
     lstart[d] = ls;
-    gbase[d] = offs[(uint64_t)d * nblocks + blk];
+    gbase[d] = tot ? offs[(uint64_t)d * a.nblocks + blk] : 0u;
     wcnt[0][d] = ls;
     wcnt[1][d] = ls + c0;
     wcnt[2][d] = ls + c0 + c1;
@@ -150,8 +183,8 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
 
   const uint32_t cnt = min((uint32_t)kTile, n - base);
   for (uint32_t i = tid; i < cnt; i += kThreads) {
-    const uint64_t k = sk[i];
-    const uint32_t d = (uint32_t)(k >> shift) & 0xFF;
+    const uint32_t k = sk[i];
+    const uint32_t d = (k >> a.shift) & a.mask;
     const uint32_t o = gbase[d] + (i - lstart[d]);
     kout[o] = k;
     vout[o] = sv[i];
@@ -165,42 +198,55 @@ size_t radix_hist_bytes(uint64_t n) {
   return (size_t)(nb * kBins + 16) * sizeof(uint32_t);
 }
 
-// Launches c->sort_passes passes over c->n_launch elements; the kernels read
-// the frame's true size and significant bits from the device, so passes
-// beyond them (launched when the host does not know the frame's sizes, as
-// in a captured graph) return immediately.
-hipError_t launch_radix_sort(Ctx *c) {
-  const uint64_t n64 = c->n_launch;
-  if (n64 == 0) return hipSuccess;
-  const uint32_t n = (uint32_t)n64;
+int radix_passes(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
+
+// Sorts keys[0]/vals[0] over `bits` key bits in radix_passes(bits) passes,
+// ping-ponging with keys[1]/vals[1]; the result lies in index passes & 1.
+// Grids cover n_launch elements; n_dev (if not null) holds the true count
+// and bits_dev (if not null) the significant bits, both read on the device.
+// The passes split the bits evenly (13 bits: 7 + 6), which keeps the digit
+// runs that the downsweep writes long.
+hipError_t launch_radix_sort_u32(Ctx *c, uint32_t *keys[2], uint32_t *vals[2], uint64_t n_launch,
+                                 const uint32_t *n_dev, const int32_t *bits_dev, int bits,
+                                 int kid_up, int kid_scan, int kid_down) {
+  if (n_launch == 0 || bits <= 0) return hipSuccess;
+  const uint32_t n = (uint32_t)n_launch;
   const uint32_t nb = (n + kTile - 1) / kTile;
-  const int passes = c->sort_passes;
-  const FrameInfo *fi = (const FrameInfo *)c->finfo.p;
-  uint64_t *ka = (uint64_t *)c->k0.p, *kb = (uint64_t *)c->k1.p;
-  uint32_t *va = (uint32_t *)c->v0.p, *vb = (uint32_t *)c->v1.p;
+  const int passes = radix_passes(bits);
   uint32_t *hist = (uint32_t *)c->hist.p;
+  int shift = 0;
   for (int p = 0; p < passes; ++p) {
-    const int shift = 8 * p;
+    const int pb = bits / passes + (p < bits % passes ? 1 : 0);
+    PassArgs a;
+    a.n_host = n;
+    a.n_dev = n_dev;
+    a.bits_dev = bits_dev;
+    a.shift = shift;
+    a.mask = (1u << pb) - 1u;
+    a.nblocks = nb;
+    const int src = p & 1, dst = src ^ 1;
     hipError_t e;
     {
-      ScopedTimer t(c, K_SORT_UPSWEEP);
+      ScopedTimer t(c, kid_up);
       hipLaunchKernelGGL(rs_upsweep, dim3(nb), dim3(kThreads), 0, c->stream,
-                         (const uint64_t *)ka, fi, shift, hist, nb);
+                         (const uint32_t *)keys[src], a, hist);
       e = hipGetLastError();
     }
-    if (e != hipSuccess) return e;
-    e = launch_exclusive_scan_u32(c, hist, (int64_t)nb * kBins, (uint32_t *)c->scan_tmp.p);
     if (e != hipSuccess) return e;
     {
-      ScopedTimer t(c, K_SORT_DOWNSWEEP);
+      ScopedTimer t(c, kid_scan);
+      e = launch_exclusive_scan_u32(c, hist, (int64_t)nb * kBins, (uint32_t *)c->scan_tmp.p);
+    }
+    if (e != hipSuccess) return e;
+    {
+      ScopedTimer t(c, kid_down);
       hipLaunchKernelGGL(rs_downsweep, dim3(nb), dim3(kThreads), 0, c->stream,
-                         (const uint64_t *)ka, (const uint32_t *)va, kb, vb, fi, shift,
-                         (const uint32_t *)hist, nb);
+                         (const uint32_t *)keys[src], (const uint32_t *)vals[src], keys[dst],
+                         vals[dst], a, (const uint32_t *)hist);
       e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
-    uint64_t *tk = ka; ka = kb; kb = tk;
-    uint32_t *tv = va; va = vb; vb = tv;
+    shift += pb;
   }
   return hipSuccess;
 }

@@ -289,13 +289,16 @@ class Rasterizer:
         self._check(self.lib.umgs_query(self.h, None, None, None, C.byref(f)))
         return bool(f.value)
 
-    def blend_pairs(self):
-        """(Gaussian pairs, triangle pairs) the blend evaluates on the sorted frame."""
+    def blend_pairs(self) -> Dict[str, int]:
+        """Work counters of the blend on the sorted frame: Gaussian and
+        triangle (pixel, fragment) pairs evaluated, wave iterations of the
+        fragment loop, fragments staged into LDS."""
         out = self.alloc_outputs(False)
-        pairs = (C.c_int64 * 2)()
+        pairs = (C.c_int64 * 4)()
         with self._on_stream():
             self._check(self.lib.umgs_blend_pairs(self.h, _ptr(out["image"]), pairs))
-        return int(pairs[0]), int(pairs[1])
+        return dict(gauss=int(pairs[0]), tri=int(pairs[1]), wave_iters=int(pairs[2]),
+                    staged=int(pairs[3]))
 
     # ---- graphs ---------------------------------------------------------------
     def reserve(self, max_dup: int):

@@ -52,6 +52,7 @@ def dev_tensors(s):
 
 
 def check_view(fr, r, out, v, pixels):
+    """r: the Rasterizer or BatchedStep whose packed outputs these are."""
     img = r.split_views(out["image"], 3)[v].cpu().numpy()
     Tf = r.split_views(out["T_final"], 1)[v].cpu().numpy()
     return PT.compare_pixels(fr, img, Tf, None, pixels)
@@ -163,7 +164,7 @@ def test_cfg3_batched_graph(gpu):
         fr = OR.Frame(s.cams[v], s.means, s.opacity, s.sh, 0, s.tri_xyz, s.tri_rgb, s.tri_alpha,
                       scales=s.scales, quats=s.quats)
         note(f"cfg3 view {v} {s.cams[v].width}x{s.cams[v].height}: "
-             f"{check_view(fr, r, out, v, sample_pixels(s.cams[v], 40, 30 + v))}")
+             f"{check_view(fr, step, out, v, sample_pixels(s.cams[v], 40, 30 + v))}")
 
 
 def test_cfg4_batched_forward_backward(gpu):
@@ -189,4 +190,5 @@ def test_cfg4_batched_forward_backward(gpu):
     for v in (0, 9):
         fr = OR.Frame(s.cams[v], ot["means"], s.opacity, s.sh, 3, s.tri_xyz, s.tri_rgb, s.tri_alpha,
                       cov3d=ot["cov3d"])
-        note(f"cfg4 view {v}: {check_view(fr, r, out, v, sample_pixels(s.cams[v], 25, 50 + v))}")
+        note(f"cfg4 view {v}: {check_view(fr, step, out, v, sample_pixels(s.cams[v], 25, 50 + v))}")
+    note(f"cfg4 groups {step.groups}")
