@@ -8,10 +8,14 @@ per-vertex proxy transforms and per-Gaussian deformation transfer, Gaussian
 projection and triangle set-up, binning, the (tile, depth) radix sort and the
 front-to-back blend.  Inputs are resident in device memory before timing.
 
-Also measured on the same scene: the forward+backward step (gradients to
-every Gaussian parameter through the deformation), and the batched form --
-16 orbit views at 1920x1080 in one captured graph per step, blend launch
-autotuned -- against rendering the same 16 views one by one.
+Also measured: the forward+backward step on the same frame (gradients to
+every Gaussian parameter through the deformation); an 800x800 frame of 300k
+SH-3 Gaussians and 50k triangles, forward + backward of an L2 loss; 64 views
+of uneven size (500k Gaussians) in one captured graph with the persistent
+blend against rendering them one by one; and the batched training step -- 16
+views at 1920x1080 of 2M SH-3 Gaussians bound to a deformed 50k-face proxy
+with 200k triangles, one captured graph per step (forward, and forward +
+backward), blend launch autotuned -- against the plain per-view forward.
 
 Prints ONE JSON line (metric, value = forward Mpixels/s, roofline of the
 dominant kernel measured live with HIP events, CPU-oracle baseline).
@@ -76,21 +80,54 @@ def cpu_baseline(scene, budget_pixels=400, seed=0):
                       f"extrapolated to {cam.width}x{cam.height}: {full:.0f} s per frame"}
 
 
-def run_batched(scene, args, deform, sc):
-    """16 orbit views at 1080p of the same scene: one captured graph per step
-    (autotuned blend launch) vs rendering the views one by one (eager)."""
+def device_scene(s, dev):
+    import torch
+    f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
+    out = dict(means=f(s.means), scales=f(s.scales), quats=f(s.quats), opacity=f(s.opacity),
+               sh=f(s.sh.reshape(s.N, -1)), tri_xyz=f(s.tri_xyz.reshape(s.T, 9)),
+               tri_rgb=f(s.tri_rgb.reshape(s.T, 9)), tri_alpha=f(s.tri_alpha))
+    deform = None
+    if s.proxy is not None:
+        deform = dict(V_def=f(s.proxy.V_def),
+                      bind_face=torch.from_numpy(s.bind_face.astype(np.int32)).to(dev),
+                      bind_bary=f(s.bind_bary))
+    return out, deform
+
+
+def timed(fn, steps):
+    """Average wall-clock ms of fn over `steps` calls after one untimed call,
+    bracketed by device synchronisation (covers every stream)."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def run_batched(args):
+    """16 views at 1920x1080 of a 2M-Gaussian SH-3 scene bound to a deformed
+    50k-face proxy, 200k triangles: rendering the views one by one (eager,
+    forward only) against the batched step captured in one HIP graph
+    (forward, and forward + backward with gradients to every Gaussian
+    parameter), blend launch autotuned."""
     import torch
     from paper_2601_19233_amd import autotune, scenes
     from paper_2601_19233_amd.batched import BatchedStep
     from paper_2601_19233_amd.render import Rasterizer
-    V = args.batched_views
-    W = max(1, int(round(1920 * args.res_scale)))
-    H = max(1, int(round(1080 * args.res_scale)))
-    cams = scenes.orbit_cameras(np.random.default_rng(101), V, [(W, H)] * V)
-    k_bind = int(scene.bind_face.shape[1])
-    # deformed inputs once (the autotuner times the rasterizer on them)
-    r0 = Rasterizer("cuda:0", sh_degree=scene.sh_degree, k_bind=k_bind)
-    r0.set_proxy(scene.proxy.V_rest, scene.proxy.faces)
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    s = scenes.make_config(4, scale=args.scale, res_scale=args.res_scale)
+    log(f"batched scene {s.name}: N={s.N} T={s.T} views={len(s.cams)} in {time.time() - t0:.1f} s")
+    cams = s.cams
+    V = len(cams)
+    W, H = cams[0].width, cams[0].height
+    sc, deform = device_scene(s, dev)
+    k_bind = int(s.bind_face.shape[1])
+    r0 = Rasterizer("cuda:0", sh_degree=s.sh_degree, k_bind=k_bind)
+    r0.set_proxy(s.proxy.V_rest, s.proxy.faces)
     dt = r0.bind_transfer(deform["V_def"], deform["bind_face"], deform["bind_bary"], sc["means"],
                           sc["quats"], sc["scales"])
     tsc = dict(means=dt["means"], cov3d=dt["cov3d"], opacity=sc["opacity"], sh=sc["sh"],
@@ -98,13 +135,15 @@ def run_batched(scene, args, deform, sc):
     t0 = time.time()
     # tuned on the first four views (one frame of them fits the key buffers at
     # every tile shape); the step itself renders all views in budgeted groups
-    best = autotune.tune(cams[:4], tsc, sh_degree=scene.sh_degree, k_bind=k_bind, reps=2,
+    best = autotune.tune(cams[:4], tsc, sh_degree=s.sh_degree, k_bind=k_bind, reps=2,
                          batches=(64, 128, 256), use_cache=False)
     log(f"autotune {best['tile']} batch {best['frag_batch']} schedule {best['schedule']} "
         f"in {time.time() - t0:.1f} s")
-    # plain: the same views one at a time
-    rp = Rasterizer("cuda:0", sh_degree=scene.sh_degree, k_bind=k_bind)
-    rp.set_proxy(scene.proxy.V_rest, scene.proxy.faces)
+    del r0, dt, tsc
+    steps = max(2, min(args.steps, 5))
+    # plain: the same views one at a time, deformation once per step
+    rp = Rasterizer("cuda:0", sh_degree=s.sh_degree, k_bind=k_bind)
+    rp.set_proxy(s.proxy.V_rest, s.proxy.faces)
 
     def plain_views():
         d = rp.bind_transfer(deform["V_def"], deform["bind_face"], deform["bind_bary"], sc["means"],
@@ -116,27 +155,18 @@ def run_batched(scene, args, deform, sc):
             rp.sort()
             rp.blend(want_state=False)
 
-    def timed(fn, steps):
-        fn()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(steps):
-            fn()
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps
-
-    steps = max(2, min(args.steps, 5))
     ms_plain = timed(plain_views, steps)
     del rp
-    res = {"views": V, "width": W, "height": H, "tile": "%dx%d" % best["tile"],
+    torch.cuda.empty_cache()
+    res = {"workload": s.name, "views": V, "width": W, "height": H, "gaussians": s.N,
+           "triangles": s.T, "sh_degree": s.sh_degree, "tile": "%dx%d" % best["tile"],
            "frag_batch": best["frag_batch"], "schedule": ["tile_grid", "persistent"][best["schedule"]],
-           "plain_fwd_views_s": round(V / (ms_plain * 1e-3), 2)}
+           "plain_fwd_views_s": round(V / (ms_plain * 1e-3), 2),
+           "plain_fwd_ms_per_step": round(ms_plain, 3)}
     for bwd in (False, True):
-        rb = Rasterizer("cuda:0", sh_degree=scene.sh_degree, k_bind=k_bind, tile=best["tile"],
+        rb = Rasterizer("cuda:0", sh_degree=s.sh_degree, k_bind=k_bind, tile=best["tile"],
                         frag_batch=best["frag_batch"], schedule=best["schedule"], own_stream=True)
-        rb.set_proxy(scene.proxy.V_rest, scene.proxy.faces)
+        rb.set_proxy(s.proxy.V_rest, s.proxy.faces)
         step = BatchedStep(rb, cams, sc, deform=deform, backward=bwd)
         step.prepare()
         if bwd:
@@ -153,7 +183,81 @@ def run_batched(scene, args, deform, sc):
         log(f"batched {key}: {ms:.2f} ms per {V}-view step")
         del step, rb
         torch.cuda.empty_cache()
+    res["fwd_bwd_vs_plain_fwd"] = round(res["fwd_bwd_views_s"] / res["plain_fwd_views_s"], 3)
     return res
+
+
+def run_uneven(args):
+    """64 orbit views of uneven size (256^2 .. 1920x1080 log-uniform area) of
+    a 500k-Gaussian scene: one captured graph with the persistent
+    longest-first blend against the views rendered one by one."""
+    import torch
+    from paper_2601_19233_amd import scenes
+    from paper_2601_19233_amd.batched import BatchedStep
+    from paper_2601_19233_amd.render import Rasterizer
+    dev = torch.device("cuda:0")
+    s = scenes.make_config(3, scale=args.scale, res_scale=args.res_scale)
+    sc, _ = device_scene(s, dev)
+    cams = s.cams
+    npix = sum(c.width * c.height for c in cams)
+    steps = max(2, min(args.steps, 5))
+    rp = Rasterizer("cuda:0", sh_degree=s.sh_degree)
+
+    def plain():
+        for c in cams:
+            rp.project([c], **sc)
+            rp.bin()
+            rp.sort()
+            rp.blend(want_state=False)
+
+    ms_plain = timed(plain, steps)
+    del rp
+    rb = Rasterizer("cuda:0", sh_degree=s.sh_degree, schedule=1, own_stream=True)
+    step = BatchedStep(rb, cams, sc)
+    step.prepare()
+    ms = timed(step, steps)
+    if rb.overflowed():
+        raise RuntimeError("batched step overflowed its reserved key capacity")
+    res = {"workload": s.name, "views": len(cams), "pixels": npix, "gaussians": s.N, "triangles": s.T,
+           "plain_views_s": round(len(cams) / (ms_plain * 1e-3), 2),
+           "batched_views_s": round(len(cams) / (ms * 1e-3), 2),
+           "batched_mpix_s": round(npix / (ms * 1e-3) / 1e6, 2),
+           "groups": [list(g) for g in step.groups]}
+    log(f"uneven: plain {ms_plain:.2f} ms, batched {ms:.2f} ms per {len(cams)}-view step")
+    del step, rb
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_backward_800(args):
+    """800x800, 300k Gaussians with SH degree 3 and 50k triangles: one
+    forward + backward step of the L2 loss against the image rendered from
+    parameters perturbed by N(0, 0.01)."""
+    import torch
+    from paper_2601_19233_amd import scenes
+    from paper_2601_19233_amd.render import Rasterizer
+    dev = torch.device("cuda:0")
+    s = scenes.make_config(2, scale=args.scale, res_scale=args.res_scale)
+    cam = s.cams[0]
+    sc, _ = device_scene(s, dev)
+    tgt_sc, _ = device_scene(scenes.perturbed(s, seed=102), dev)
+    r = Rasterizer("cuda:0", sh_degree=s.sh_degree)
+    target = r.render([cam], **tgt_sc)["image"].clone()
+    state = {}
+
+    def step():
+        out = r.render([cam], **sc)
+        dL = 2.0 * (out["image"] - target)
+        state["g"] = r.backward(dL, out, sc["means"], sc["scales"], sc["quats"], sc["sh"], None)
+
+    steps = max(2, min(args.steps, 10))
+    ms = timed(step, steps)
+    npix = cam.width * cam.height
+    log(f"backward 800: {ms:.3f} ms per forward+backward step")
+    return {"workload": s.name, "width": cam.width, "height": cam.height, "gaussians": s.N,
+            "triangles": s.T, "sh_degree": s.sh_degree, "fwd_bwd_ms_per_step": round(ms, 4),
+            "fwd_bwd_mpix_s": round(npix / (ms * 1e-3) / 1e6, 2),
+            "loss": "L2 against the render of N(0, 0.01)-perturbed parameters"}
 
 
 def main():
@@ -167,11 +271,11 @@ def main():
     ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batched-views", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              f"(the path is single-GPU by design; see the sharding notes in DESIGN.md).")
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the path "
+              f"is built and measured on a single GPU (views would shard across GPUs with no "
+              f"exchange in the forward and one gradient all-reduce per step).")
         sys.exit(2)
 
     import torch
@@ -238,10 +342,10 @@ def main():
     log(f"blend work: {bp}")
     # algorithmic HBM bytes per launch of the bandwidth-bound kernels
     algo_bytes = {
-        "sort_downsweep": 24.0 * n_dup,          # read key+value, write key+value
-        "sort_upsweep": 8.0 * n_dup,             # read key
-        "emit_keys": 12.0 * n_dup + 24.0 * n_rec,
-        "tile_ranges": 8.0 * n_dup + 8.0 * n_tiles,
+        "sort_downsweep": 16.0 * n_dup,          # read 32-bit tile id + record id, write both
+        "sort_upsweep": 4.0 * n_dup,             # read tile id
+        "emit_keys": 8.0 * n_dup + 20.0 * n_rec, # write tile id + record id; offsets, order, rects
+        "tile_ranges": 4.0 * n_dup + 8.0 * n_tiles,
         "transfer": scene.N * (40.0 + 12.0 * scene.bind_face.shape[1] + 88.0),
         "project_gaussians": scene.N * (12 + 24 + 4 + 12 + 4 + 8 + 8 + 48.0),
     }
@@ -264,7 +368,7 @@ def main():
 
     roof = roofline(dominant)
     rooflines = {k: roofline(k) for k in ("sort_downsweep", "sort_upsweep", "emit_keys", "blend",
-                                          "transfer") if k in prof}
+                                          "tile_ranges", "transfer", "project_gaussians") if k in prof}
 
     # ---- forward + backward (plain, eager) ---------------------------------
     g = torch.Generator(device="cpu").manual_seed(0)
@@ -293,11 +397,15 @@ def main():
                "path": "plain forward + backward (eager), gradients to means/scales/quats/opacity/SH"}
     log(f"fwd+bwd {ms_fb:.3f} ms/step")
 
-    batched = None
+    del r, fwd_state
+    torch.cuda.empty_cache()
+    batched = uneven = bwd800 = None
     if not args.no_batched:
-        batched = run_batched(scene, args, dict(V_def=V_def, bind_face=bface, bind_bary=bbary),
-                              dict(means=means, scales=scales, quats=quats, opacity=opac, sh=sh,
-                                   tri_xyz=txyz, tri_rgb=trgb, tri_alpha=tal))
+        bwd800 = run_backward_800(args)
+        torch.cuda.empty_cache()
+        uneven = run_uneven(args)
+        torch.cuda.empty_cache()
+        batched = run_batched(args)
 
     out = {
         "metric": METRIC, "value": round(fwd_mpix, 2), "unit": "Mpixels/s", "n_gpus": 1,
@@ -309,7 +417,7 @@ def main():
                    "tile": args.tile, "frag_batch": args.batch, "path": "plain forward"},
         "n_dup": n_dup, "stages_ms": stages, "roofline": roof, "rooflines": rooflines,
         "wall_s": round(wall, 3),
-        "fwd_bwd": fwd_bwd, "batched": batched,
+        "fwd_bwd": fwd_bwd, "backward_800": bwd800, "batched": batched, "batched_uneven": uneven,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

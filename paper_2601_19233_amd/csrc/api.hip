@@ -334,7 +334,7 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
                                                     (int64_t)radix_hist_bytes(std::max<int64_t>(nrec, 1)) / 4})),
                   "scan scratch")) ||
       (s = ensure(c, c->ranges, sizeof(uint2) * tiles, "tile ranges")) ||
-      (s = ensure(c, c->minmax, 2 * sizeof(uint32_t), "depth range")) ||
+      (s = ensure(c, c->minmax, 2 * kMinMaxSlots * sizeof(uint32_t), "depth range")) ||
       (s = ensure(c, c->finfo, sizeof(FrameInfo), "frame info")) ||
       (s = ensure(c, c->tile_order, sizeof(uint32_t) * (64 + tiles), "tile order")))
     return s;
@@ -371,8 +371,8 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
   if (e == hipSuccess && upload)
     e = hipMemcpyAsync(dv, vps.data(), sizeof(ViewParams) * V, hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return hip_check(c, e, "view upload");
-  e = launch_fill_u32(c, (uint32_t *)c->minmax.p, 1, kCulled);
-  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t *)c->minmax.p + 1, 1, 0u);
+  e = launch_fill_u32(c, (uint32_t *)c->minmax.p, kMinMaxSlots, kCulled);
+  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t *)c->minmax.p + kMinMaxSlots, kMinMaxSlots, 0u);
   if (e != hipSuccess) return hip_check(c, e, "depth range reset");
   if ((e = launch_project_gaussians(c, means, cov3d, scales, quats, opacity, sh)) != hipSuccess)
     return hip_check(c, e, "project_gaussians launch");

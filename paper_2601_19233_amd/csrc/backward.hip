@@ -132,8 +132,11 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
       if (!__any(mine)) continue;
       if ((s[31] & 1u) == 0u) {
         // selects rather than branches keep every lane active for the row sums
+        // evaluated on every lane (not short-circuited by `mine`): lanes
+        // past their last fragment feed the sums with exact zeros
         float alpha, G, dx, dy;
-        const bool contrib = mine && gauss_terms(s, pcx, pcy, alpha, G, dx, dy);
+        const bool hit = gauss_terms(s, pcx, pcy, alpha, G, dx, dy);
+        const bool contrib = mine && hit;
         if (contrib && in_ent) {
           B0 = 0.25f * ((s0[0] + s1[0]) + (s2[0] + s3[0]));
           B1 = 0.25f * ((s0[1] + s1[1]) + (s2[1] + s3[1]));
@@ -156,6 +159,9 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
         const float dpow = (op * G < kAlphaMax) ? dLda : 0.0f;
         const float qa = __uint_as_float(s[2]), qb = __uint_as_float(s[3]), qc = __uint_as_float(s[4]);
         const float dp = alpha * dpow;     // d alpha / d power = o G = alpha
+        // offsets of other lanes may be huge (a far mean): keep 0 x inf out
+        dx = contrib ? dx : 0.0f;
+        dy = contrib ? dy : 0.0f;
         float g[9];
         g[0] = dp * (2.0f * qa * dx + qb * dy);
         g[1] = dp * (qb * dx + 2.0f * qc * dy);

@@ -117,8 +117,11 @@ __global__ void view_sum_kernel(const uint64_t *__restrict__ counts, int64_t per
 }
 
 // Depth range of the frame: sort keys hold (depth key - base) in depth_bits.
+// One wave folds the slot pairs the projection kernels filled.
 __global__ void depth_range_kernel(const uint32_t *__restrict__ minmax, FrameInfo *__restrict__ fi) {
-  const uint32_t lo = minmax[0], hi = minmax[1];
+  const uint32_t lo = wave_min_u32(minmax[threadIdx.x]);
+  const uint32_t hi = wave_max_u32(minmax[kMinMaxSlots + threadIdx.x]);
+  if (threadIdx.x != 0) return;
   const bool any = lo <= hi;
   fi->depth_base = any ? lo : 0u;
   int db = 1;
@@ -384,15 +387,33 @@ __global__ void frame_info_kernel(const uint64_t *__restrict__ total, uint64_t c
   fi->queue = 0u;
 }
 
+// Tile ranges from the sorted tile ids: 4 consecutive ids per thread (one
+// 16-byte load), a range starts or ends where the id changes.
 __global__ void tile_ranges_kernel(const uint32_t *__restrict__ k0, const uint32_t *__restrict__ k1,
                                    const FrameInfo *__restrict__ fi, uint2 *__restrict__ ranges) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t i0 = 4 * ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
   const uint64_t n = fi->n_dup;
-  if (i >= n) return;
+  if (i0 >= n) return;
   const uint32_t *keys = fi->sorted_in ? k1 : k0;
-  const uint32_t t = keys[i];
-  if (i == 0 || keys[i - 1] != t) ranges[t].x = (uint32_t)i;
-  if (i == n - 1 || keys[i + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+  uint32_t k[5];
+  if (i0 + 4 <= n) {
+    const uint4 q = *(const uint4 *)(keys + i0);
+    k[0] = q.x; k[1] = q.y; k[2] = q.z; k[3] = q.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) k[j] = i0 + j < n ? keys[i0 + j] : 0xFFFFFFFFu;
+  }
+  k[4] = i0 + 4 < n ? keys[i0 + 4] : 0xFFFFFFFFu;
+  uint32_t prev = i0 > 0 ? keys[i0 - 1] : 0xFFFFFFFFu;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint64_t i = i0 + j;
+    if (i >= n) break;
+    const uint32_t t = k[j];
+    if (i == 0 || prev != t) ranges[t].x = (uint32_t)i;
+    if (i == n - 1 || k[j + 1] != t) ranges[t].y = (uint32_t)(i + 1);
+    prev = t;
+  }
 }
 
 // Sorted pairs in the exported (tile << 32 | depth key bits) form.
@@ -452,7 +473,8 @@ hipError_t launch_depth_order(Ctx *c) {
   hipError_t e;
   {
     ScopedTimer t(c, K_DEPTH_SORT);
-    hipLaunchKernelGGL(depth_range_kernel, dim3(1), dim3(1), 0, c->stream,
+    static_assert(kMinMaxSlots == 64, "one wave folds the slots");
+    hipLaunchKernelGGL(depth_range_kernel, dim3(1), dim3(kMinMaxSlots), 0, c->stream,
                        (const uint32_t *)c->minmax.p, fi);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n == 0) return launch_fill_u32(c, (uint32_t *)c->offs.p, 2, 0u);   // total: 0
@@ -514,7 +536,7 @@ hipError_t launch_tile_ranges(Ctx *c) {
   ScopedTimer t(c, K_RANGES);
   hipError_t e = launch_fill_u32(c, (uint32_t *)c->ranges.p, 2 * c->n_tiles, 0u);
   if (e != hipSuccess || c->n_launch == 0) return e;
-  hipLaunchKernelGGL(tile_ranges_kernel, dim3(ceil_div(c->n_launch, 256)), dim3(256), 0, c->stream,
+  hipLaunchKernelGGL(tile_ranges_kernel, dim3(ceil_div(c->n_launch, 1024)), dim3(256), 0, c->stream,
                      (const uint32_t *)c->k0.p, (const uint32_t *)c->k1.p,
                      (const FrameInfo *)c->finfo.p, (uint2 *)c->ranges.p);
   return hipGetLastError();

@@ -23,6 +23,7 @@ constexpr int kCoordLimit = 1 << 24;         // |snapped coordinate| bound (1/25
 constexpr uint32_t kCulled = 0xFFFFFFFFu;    // depth key of a culled primitive
 
 constexpr int64_t kViewSlots = 8192;   // ViewParams the device table store holds
+constexpr int kMinMaxSlots = 64;       // slot pairs of the frame's depth-key range
 
 // Per-view parameters in device memory.
 struct ViewParams {
@@ -115,7 +116,7 @@ struct Ctx {
   uint64_t n_launch = 0;      // elements the sort-stage grids cover (n_dup, or the capacity)
   int sort_passes = 0;        // radix passes of the tile sort
   int tile_bits = 1;
-  DevBuf minmax;       // 2 uint32: min / max depth-key bits of the frame
+  DevBuf minmax;       // 2 x kMinMaxSlots uint32: min / max depth-key bits (folded in bin)
   DevBuf finfo;        // FrameInfo (device)
   DevBuf tile_order;   // 64 bucket counters + n_tiles tile ids (persistent blend)
   DevBuf pair_count;   // 4 uint64: blend work counters (measurement)

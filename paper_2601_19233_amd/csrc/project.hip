@@ -227,14 +227,16 @@ __device__ uint32_t project_gaussian(const ViewParams *__restrict__ views, int N
   return __float_as_uint(zv);
 }
 
-// Folds a wave's valid depth keys into the frame's [min, max] (one atomic
-// pair per wave); the sort keys store depth relative to the minimum.
+// Folds a wave's valid depth keys into the frame's [min, max]: one atomic
+// pair per wave, spread over kMinMaxSlots slot pairs (a single address would
+// serialise every wave of the grid); the bin stage folds the slots.
 __device__ __forceinline__ void reduce_key_range(uint32_t key, uint32_t *minmax) {
   const uint32_t lo = wave_min_u32(key);
   const uint32_t hi = wave_max_u32(key == kCulled ? 0u : key);
   if ((threadIdx.x & 63) == 0 && lo != kCulled) {
-    atomicMin(minmax, lo);
-    atomicMax(minmax + 1, hi);
+    const uint32_t slot = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kMinMaxSlots - 1);
+    atomicMin(minmax + slot, lo);
+    atomicMax(minmax + kMinMaxSlots + slot, hi);
   }
 }
 

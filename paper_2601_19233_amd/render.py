@@ -358,6 +358,8 @@ class Rasterizer:
             t = torch.empty((n_tiles, 2), dtype=torch.int32, device=d)
         elif which == L.STATE_TRI_FIXED:
             t = torch.empty((len(self.views) * self.T, 6), dtype=torch.int32, device=d)
+        elif which == L.STATE_GRAD2D:
+            t = torch.empty((len(self.views) * self.N, 9), dtype=torch.float32, device=d)
         else:
             raise ValueError(which)
         with self._on_stream():

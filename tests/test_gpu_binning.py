@@ -52,10 +52,10 @@ def stressed(s):
     rng = np.random.default_rng(7)
     sc = s.scales.copy()
     op = s.opacity.copy()
-    n = s.N
-    sel = rng.permutation(n)
-    sc[sel[: n // 3], rng.integers(0, 3, n // 3)] *= 40.0
-    op[sel[n // 3: 2 * n // 3]] = (1.0 + rng.uniform(0.001, 0.2, n // 3)) / 255.0
+    sel = rng.permutation(s.N)
+    needles, faint = sel[: s.N // 3], sel[s.N // 3: 2 * (s.N // 3)]
+    sc[needles, rng.integers(0, 3, needles.size)] *= 40.0
+    op[faint] = (1.0 + rng.uniform(0.001, 0.2, faint.size)) / 255.0
     return dataclasses.replace(s, scales=sc.astype(np.float32), opacity=op.astype(np.float32))
 
 
