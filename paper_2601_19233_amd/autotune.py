@@ -1,12 +1,12 @@
 """Autotuner for the blend launch: tile shape, LDS fragment batch and schedule.
 
-Each candidate renders the given frame eagerly; the blend kernel's duration
-is read from the library's event timer (median of ``reps`` launches after a
-warm-up), and the fastest candidate wins.  Results are cached in a JSON file
+Each candidate renders the given frame eagerly (median of ``reps`` frames
+after a warm-up); the candidate with the fastest whole frame -- projection,
+binning, sorting and blend, since the tile shape changes the duplicate count
+as much as the blend -- wins.  The blend kernel's own duration (the library's
+event timer) is recorded alongside.  Results are cached in a JSON file
 (``UMGS_AUTOTUNE_CACHE``, default ~/.cache/unimgs/autotune.json) keyed by the
 frame's shape: views and their sizes, Gaussian and triangle counts, SH degree.
-The tile shape changes binning and sorting too, so the whole frame time is
-also recorded and used to break near-ties (within 2 %).
 """
 from __future__ import annotations
 
@@ -105,9 +105,7 @@ def tune(cams: Sequence, scene: Dict[str, torch.Tensor], sh_degree: int = 0, k_b
         r.close()
     if not results:
         raise RuntimeError("autotune: no candidate could render the frame")
-    best_blend = min(x["blend_ms"] for x in results)
-    near = [x for x in results if x["blend_ms"] <= best_blend * 1.02]
-    best = min(near, key=lambda x: x["frame_ms"])
+    best = min(results, key=lambda x: x["frame_ms"])
     entry = dict(tile=best["tile"], frag_batch=best["frag_batch"], schedule=best["schedule"],
                  results=results)
     if use_cache:

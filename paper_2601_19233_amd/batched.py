@@ -4,7 +4,8 @@ differentiated) by a captured HIP graph.
 Planning runs once: the deformation transfer and the projection of all views
 give every view's duplicate count (``view_dups``) before anything is sorted;
 consecutive views are grouped so that no group exceeds ``group_budget``
-duplicates (32-bit sort positions, bounded key memory).  One eager step then
+duplicates (32-bit sort positions, bounded key memory) or ``group_tiles``
+screen tiles (the tile sort's passes grow with the bits of the tile ids).  One eager step then
 renders every group (allocating buffers and storing one device view table
 per group), key capacity is reserved for the largest group times
 ``headroom``, and the whole step -- transfer, then per group project, bin,
@@ -24,7 +25,8 @@ from .render import Rasterizer
 class BatchedStep:
     def __init__(self, rast: Rasterizer, cams: Sequence, scene: Dict[str, torch.Tensor],
                  deform: Optional[Dict[str, torch.Tensor]] = None, backward: bool = False,
-                 headroom: float = 1.25, group_budget: int = 1_500_000_000):
+                 headroom: float = 1.25, group_budget: int = 1_500_000_000,
+                 group_tiles: int = 1 << 16):
         """scene: device tensors means, opacity, sh (N, nc*3), scales, quats and
         optionally tri_xyz, tri_rgb, tri_alpha.  deform: V_def, bind_face,
         bind_bary (the proxy must already be set on ``rast``).  ``rast`` must
@@ -39,6 +41,7 @@ class BatchedStep:
         self.do_backward = backward
         self.headroom = headroom
         self.group_budget = int(group_budget)
+        self.group_tiles = int(group_tiles)
         self.graph_ready = False
         self.tout = None
         self.out = None
@@ -79,21 +82,26 @@ class BatchedStep:
 
     # -- planning -----------------------------------------------------------
     def plan(self) -> List[Tuple[int, int]]:
-        """Group consecutive views so each group stays within the budget."""
+        """Group consecutive views so each group stays within the duplicate
+        budget and within ``group_tiles`` screen tiles (2^16 tiles keep the
+        tile sort at two 8-bit passes)."""
         self._transfer()
         dups: List[int] = []
         step = max(1, min(len(self.cams), 64))
         for a in range(0, len(self.cams), step):
             self._project(self.cams[a:a + step])
             dups += self.r.view_dups()
-        groups, a, acc = [], 0, 0
+        tw, th = self.r.opts.tile_w, self.r.opts.tile_h
+        tiles = [((c.width + tw - 1) // tw) * ((c.height + th - 1) // th) for c in self.cams]
+        groups, a, acc, acc_t = [], 0, 0, 0
         for v, n in enumerate(dups):
             if n >= 0xFFFF0000:
                 raise RuntimeError(f"view {v} alone produces {n} duplicates (32-bit positions)")
-            if v > a and acc + n > self.group_budget:
+            if v > a and (acc + n > self.group_budget or acc_t + tiles[v] > self.group_tiles):
                 groups.append((a, v))
-                a, acc = v, 0
+                a, acc, acc_t = v, 0, 0
             acc += n
+            acc_t += tiles[v]
         groups.append((a, len(dups)))
         self.view_dup_counts = dups
         self.groups = groups

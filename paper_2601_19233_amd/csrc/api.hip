@@ -167,7 +167,8 @@ void umgs_destroy(umgs_ctx *ctx) {
                     &c->keys, &c->rects, &c->counts, &c->dk[0], &c->dk[1], &c->dv[0],
                     &c->dv[1], &c->offs, &c->grec, &c->trec, &c->scan_tmp,
                     &c->k0, &c->k1, &c->v0, &c->v1, &c->hist, &c->ranges, &c->g2d,
-                    &c->minmax, &c->finfo, &c->tile_order, &c->pair_count, &c->view_sums};
+                    &c->minmax, &c->finfo, &c->tile_order, &c->pair_count, &c->view_sums,
+                    &c->blk_first};
   for (DevBuf *b : bufs) free_buf(*b);
   for (auto &p : c->prof.pending) {
     (void)hipEventDestroy(p.a);
@@ -388,6 +389,7 @@ static umgs_status ensure_keys(Ctx *c, uint64_t n) {
   if ((s = ensure(c, c->k0, 4 * n, "keys")) || (s = ensure(c, c->k1, 4 * n, "keys")) ||
       (s = ensure(c, c->v0, 4 * n, "values")) || (s = ensure(c, c->v1, 4 * n, "values")) ||
       (s = ensure(c, c->hist, radix_hist_bytes(std::max<uint64_t>(n, c->n_records)), "radix histograms")) ||
+      (s = ensure(c, c->blk_first, emit_blocks_bytes(n), "emit blocks")) ||
       (s = ensure(c, c->scan_tmp,
                   scan_tmp_bytes(std::max<int64_t>(radix_hist_bytes(n) / 4, c->n_records + 1)),
                   "scan scratch")))

@@ -39,13 +39,15 @@ namespace {
 // (every lane holds its 16-lane row's sum), then broadcast lane 15 of each
 // row into the next row and lane 31 into the upper half.  Every lane of the
 // wave must be active.
+// (bound_ctrl set: the permutes have no invalid source lanes, and with it
+// the compiler folds each move into the add as one DPP instruction)
 __device__ __forceinline__ float wave_total(float v) {
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, false));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, false));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, true));
   return v;
 }
 
@@ -137,6 +139,7 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
         float alpha, G, dx, dy;
         const bool hit = gauss_terms(s, pcx, pcy, alpha, G, dx, dy);
         const bool contrib = mine && hit;
+        if (!__any(contrib)) continue;     // no lane of the wave blends it
         if (contrib && in_ent) {
           B0 = 0.25f * ((s0[0] + s1[0]) + (s2[0] + s3[0]));
           B1 = 0.25f * ((s0[1] + s1[1]) + (s2[1] + s3[1]));
@@ -144,7 +147,8 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
           Tr = term_ent ? Tterm : Tr / (0.25f * ((p0 + p1) + (p2 + p3)));
           in_ent = false;
         }
-        const float Tb = (pos == last - 1) ? Tterm : Tr / (1.0f - alpha);
+        // T in front of the fragment: one rcp (1 ulp) per step of the walk
+        const float Tb = (pos == last - 1) ? Tterm : Tr * __builtin_amdgcn_rcpf(1.0f - alpha);
         const float c0 = __uint_as_float(s[6]), c1 = __uint_as_float(s[7]), c2 = __uint_as_float(s[8]);
         const float w = contrib ? Tb * alpha : 0.0f;
         const float dLda = contrib ? Tb * ((c0 - B0) * dC0 + (c1 - B1) * dC1 + (c2 - B2) * dC2) : 0.0f;
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
         g[6] = w * dC0;
         g[7] = w * dC1;
         g[8] = w * dC2;
-        if (__any(contrib)) {
+        {
           float *dst = gl + (tid >> 6) * batch * 9 + f * 9;
 #pragma unroll
           for (int k = 0; k < 9; ++k) {

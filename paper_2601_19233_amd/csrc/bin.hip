@@ -158,15 +158,17 @@ __global__ void gather_counts_kernel(const uint32_t *__restrict__ order, int64_t
 // (support.h) exactly as the projection counted them.
 //
 // The block finds the records covering its range by binary search in the
-// scanned offsets and stages them in LDS, then lays out all their tile rows
-// in LDS (first column and tile count of each, scanned), so every lane finds
-// its position's record, row and column by two binary searches in LDS.
-// Output: global tile id (the tile sort's key) and record id.
+// scanned offsets and stages them in LDS; one thread per record then lays
+// out the record's tile rows in LDS (first column, first output position),
+// so every lane finds its position's row, hence record and column, by one
+// binary search in LDS.  Output: global tile id (the tile sort's key) and
+// record id.
 constexpr int kEmitThreads = 256;
 constexpr int kEmitPer = 8;
 constexpr int kEmitSpan = kEmitThreads * kEmitPer;
-constexpr int kEmitRecCap = 1024;
-constexpr int kEmitRowCap = 4096;
+constexpr int kEmitRecCap = 512;
+constexpr int kEmitRowCap = 2048;
+constexpr int kEmitRowPer = kEmitRowCap / kEmitThreads;
 
 // last r in [lo, hi] with offs[r] <= d (offs is non-decreasing)
 __device__ __forceinline__ int64_t last_record_at(const uint64_t *__restrict__ offs, int64_t lo,
@@ -187,23 +189,27 @@ struct EmitArgs {
   const uint64_t *offs;
   const GaussRec *grec;
   const FrameInfo *fi;
+  const uint32_t *blk_first;   // per block: the (depth-order) record holding its first position,
+                               // then one entry: the record holding the last position
   uint32_t *keys_out, *vals_out;
 };
 
-// Columns [a, b) of row ty of record r (tile coordinates of its view).
-__device__ __forceinline__ void record_row(const EmitArgs &e, uint32_t r, uint2 rc, int ty,
-                                           int &a, int &b) {
-  const int v = (int)(r / (uint32_t)e.per_view);
-  const int i = (int)(r - (uint32_t)v * (uint32_t)e.per_view);
-  const int tx0 = rc.x & 0xFFFF, tx1 = rc.y & 0xFFFF;
-  if (i >= e.N) {            // triangle: the whole rectangle
-    a = tx0;
-    b = tx1;
-    return;
-  }
-  const ViewParams &vp = e.views[v];
-  const Support s = make_support(e.grec[(int64_t)v * e.N + i]);
-  support_row(s, ty, e.tile_w, e.tile_h, vp.W, vp.H, tx0, tx1, a, b);
+// For every emit block, the record (in depth order) that holds the block's
+// first output position, found by the records themselves: record i covers
+// the positions [offs[i], offs[i+1]) and writes its index for each block
+// starting inside that range, so no block searches the offsets.  The
+// record holding the frame's last position is stored after the blocks.
+__global__ void emit_blocks_kernel(const uint64_t *__restrict__ offs, int64_t n_records,
+                                   const FrameInfo *__restrict__ fi, uint32_t nblocks,
+                                   uint32_t *__restrict__ blk_first) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n_records) return;
+  const uint64_t n = fi->n_dup;
+  const uint64_t o0 = offs[i], o1 = min(offs[i + 1], n);
+  if (o0 >= o1) return;
+  const uint64_t b0 = (o0 + kEmitSpan - 1) / kEmitSpan, b1 = (o1 + kEmitSpan - 1) / kEmitSpan;
+  for (uint64_t b = b0; b < b1 && b < nblocks; ++b) blk_first[b] = (uint32_t)i;
+  if (o1 == n) blk_first[nblocks] = (uint32_t)i;
 }
 
 // (clamps keep a tile inside its record's rectangle, hence inside its view,
@@ -215,136 +221,140 @@ __device__ __forceinline__ uint32_t global_tile(const EmitArgs &e, uint32_t r, i
   return vp.tile_base + (uint32_t)ty * (uint32_t)vp.ntx + (uint32_t)tx;
 }
 
+// Block-wide exclusive scan of LDS values [0, n) (n <= per * kEmitThreads,
+// each thread a contiguous chunk of `per`); returns the total.
+template <int PER>
+__device__ __forceinline__ uint32_t block_scan_lds(uint32_t *vals, int n, uint32_t *wsum) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint32_t v[PER], sum = 0;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int q = tid * PER + j;
+    v[j] = q < n ? vals[q] : 0u;
+    sum += v[j];
+  }
+  uint32_t incl = sum;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  __syncthreads();                       // vals fully read, wsum free
+  if (lane == 63) wsum[w] = incl;
+  __syncthreads();
+  uint32_t base = 0, total = 0;
+#pragma unroll
+  for (int k = 0; k < kEmitThreads / 64; ++k) {
+    if (k < w) base += wsum[k];
+    total += wsum[k];
+  }
+  uint32_t run = base + incl - sum;
+#pragma unroll
+  for (int j = 0; j < PER; ++j) {
+    const int q = tid * PER + j;
+    if (q < n) vals[q] = run;
+    run += v[j];
+  }
+  __syncthreads();
+  return total;
+}
+
 __global__ __launch_bounds__(kEmitThreads) void emit_balanced_kernel(EmitArgs e) {
-  __shared__ uint64_t s_off[kEmitRecCap];
-  __shared__ uint2 s_rect[kEmitRecCap];
-  __shared__ uint32_t s_rec[kEmitRecCap];
-  __shared__ uint32_t s_row0[kEmitRecCap + 1];   // first row slot of each staged record
-  __shared__ uint32_t r_pre[kEmitRowCap + 1];    // tiles before each row slot (block scan)
-  __shared__ uint16_t r_lo[kEmitRowCap];         // first tile column of each row slot
+  // staged records
+  __shared__ uint32_t s_rec[kEmitRecCap];        // record id
+  __shared__ int32_t s_off[kEmitRecCap];         // first output position, relative to d0
+  __shared__ uint2 s_rect[kEmitRecCap];          // tile rectangle
+  __shared__ uint32_t s_tb[kEmitRecCap];         // global id of its view's tile (0, 0)
+  __shared__ uint32_t s_ntx[kEmitRecCap];        // tiles per row of its view
+  __shared__ int32_t s_gidx[kEmitRecCap];        // Gaussian record index, -1: triangle
+  __shared__ uint32_t s_row0[kEmitRecCap + 1];   // rows, scanned to the first row slot
+  __shared__ uint32_t s_pbase[kEmitRecCap];      // scanned tile count at the first row slot
+  // row slots: one per tile row of a staged record
+  __shared__ int32_t q_start[kEmitRowCap];       // first output position (relative to d0)
+  __shared__ uint32_t q_tile0[kEmitRowCap];      // global tile id of the row's first tile
+  __shared__ uint16_t q_k[kEmitRowCap];          // staged record index
+  __shared__ uint16_t q_cnt[kEmitRowCap];        // tiles in the row
   __shared__ uint32_t s_wsum[kEmitThreads / 64];
-  __shared__ int64_t s_lo, s_hi;
-  __shared__ uint32_t s_rows;
   const uint64_t n = e.fi->n_dup;
   const uint64_t d0 = (uint64_t)blockIdx.x * kEmitSpan;
   if (d0 >= n) return;
   const uint64_t d1 = min(d0 + (uint64_t)kEmitSpan, n);
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  if (tid == 0) {
-    s_lo = last_record_at(e.offs, 0, e.n_records, d0);
-    s_hi = last_record_at(e.offs, s_lo, e.n_records, d1 - 1);
-  }
-  __syncthreads();
-  const int64_t rlo = s_lo, rhi = s_hi;
+  const int tid = threadIdx.x;
+  // records [rlo, rhi] cover the block: rhi is the next block's first record
+  // (possibly one record too many, which no position maps to) or, for the
+  // frame's last block, the record holding the last position
+  const int64_t rlo = e.blk_first[blockIdx.x];
+  const int64_t rhi = d1 < n ? (int64_t)e.blk_first[blockIdx.x + 1] : (int64_t)e.blk_first[gridDim.x];
   const int nr = (int)min<int64_t>(rhi - rlo + 1, (int64_t)kEmitRecCap + 1);
-  bool staged = false;
+  int R = kEmitRowCap + 1;
   if (nr <= kEmitRecCap) {
-    // records and an exclusive scan of their row counts (4 records a thread)
-    uint32_t rows[4], sum = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = tid * 4 + q;
-      rows[q] = 0;
-      if (k < nr) {
-        const uint32_t r = e.order[rlo + k];
-        const uint2 rc = e.rects[r];
-        s_off[k] = e.offs[rlo + k];
-        s_rec[k] = r;
-        s_rect[k] = rc;
-        rows[q] = (rc.y >> 16) - (rc.x >> 16);
-      }
-      sum += rows[q];
-    }
-    uint32_t incl = sum;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += y;
-    }
-    if (lane == 63) s_wsum[w] = incl;
-    __syncthreads();
-    uint32_t base = 0;
-    for (int k = 0; k < w; ++k) base += s_wsum[k];
-    uint32_t run = base + incl - sum;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int k = tid * 4 + q;
-      if (k < nr) s_row0[k] = run;
-      run += rows[q];
-    }
-    if (tid == kEmitThreads - 1) {
-      s_rows = run;
-      s_row0[nr] = run;
+    // records (strided over the threads, so their loads overlap)
+    for (int k = tid; k < nr; k += kEmitThreads) {
+      const uint32_t r = e.order[rlo + k];
+      const uint2 rc = e.rects[r];
+      const uint32_t v = r / (uint32_t)e.per_view;
+      const int i = (int)(r - v * (uint32_t)e.per_view);
+      s_rec[k] = r;
+      s_off[k] = (int32_t)((int64_t)e.offs[rlo + k] - (int64_t)d0);
+      s_rect[k] = rc;
+      s_tb[k] = e.views[v].tile_base;
+      s_ntx[k] = (uint32_t)e.views[v].ntx;
+      s_gidx[k] = i < e.N ? (int32_t)(v * (uint32_t)e.N + (uint32_t)i) : -1;
+      s_row0[k] = (rc.y >> 16) - (rc.x >> 16);
     }
     __syncthreads();
-    staged = s_rows <= kEmitRowCap;
+    R = (int)block_scan_lds<kEmitRecCap / kEmitThreads>(s_row0, nr, s_wsum);
+    if (tid == 0) s_row0[nr] = (uint32_t)R;
+    __syncthreads();
   }
-  if (staged) {
-    const int R = (int)s_rows;
-    // each row slot: its columns, then a block scan of the tile counts
-    uint32_t cnt[kEmitRowCap / kEmitThreads], sum = 0;
-#pragma unroll
-    for (int q = 0; q < kEmitRowCap / kEmitThreads; ++q) {
-      const int slot = tid * (kEmitRowCap / kEmitThreads) + q;
-      cnt[q] = 0;
-      if (slot < R) {
-        int lo = 0, hi = nr - 1;
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if ((int)s_row0[mid] <= slot) lo = mid; else hi = mid - 1;
-        }
-        const uint2 rc = s_rect[lo];
-        int a, b;
-        record_row(e, s_rec[lo], rc, (int)(rc.x >> 16) + (slot - (int)s_row0[lo]), a, b);
-        r_lo[slot] = (uint16_t)a;
-        cnt[q] = (uint32_t)(b - a);
+  if (R <= kEmitRowCap) {
+    // row slot -> staged record
+    for (int k = tid; k < nr; k += kEmitThreads)
+      for (uint32_t q = s_row0[k]; q < s_row0[k + 1]; ++q) q_k[q] = (uint16_t)k;
+    __syncthreads();
+    // each row slot's columns (strided), then a block scan of the tile counts
+    for (int q = tid; q < R; q += kEmitThreads) {
+      const int k = q_k[q];
+      const uint2 rc = s_rect[k];
+      const int tx0 = rc.x & 0xFFFF, tx1 = rc.y & 0xFFFF;
+      const int ty = (int)(rc.x >> 16) + (q - (int)s_row0[k]);
+      int a = tx0, b = tx1;
+      const int gi = s_gidx[k];
+      if (gi >= 0) {
+        const ViewParams &vp = e.views[(uint32_t)gi / (uint32_t)e.N];
+        support_row(make_support(e.grec[gi]), ty, e.tile_w, e.tile_h, vp.W, vp.H, tx0, tx1, a, b);
       }
-      sum += cnt[q];
-    }
-    uint32_t incl = sum;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += y;
+      q_tile0[q] = s_tb[k] + (uint32_t)ty * s_ntx[k] + (uint32_t)a;
+      q_cnt[q] = (uint16_t)(b - a);
+      q_start[q] = b - a;
     }
     __syncthreads();
-    if (lane == 63) s_wsum[w] = incl;
+    block_scan_lds<kEmitRowPer>((uint32_t *)q_start, R, s_wsum);
+    for (int q = tid; q < R; q += kEmitThreads) {
+      const int k = q_k[q];
+      if ((uint32_t)q == s_row0[k]) s_pbase[k] = (uint32_t)q_start[q];
+    }
     __syncthreads();
-    uint32_t base = 0;
-    for (int k = 0; k < w; ++k) base += s_wsum[k];
-    uint32_t run = base + incl - sum;
-#pragma unroll
-    for (int q = 0; q < kEmitRowCap / kEmitThreads; ++q) {
-      const int slot = tid * (kEmitRowCap / kEmitThreads) + q;
-      if (slot <= R) r_pre[slot] = run;
-      run += cnt[q];
+    for (int q = tid; q < R; q += kEmitThreads) {
+      const int k = q_k[q];
+      q_start[q] = s_off[k] + (int32_t)((uint32_t)q_start[q] - s_pbase[k]);
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < kEmitPer; ++k) {
       const uint64_t d = d0 + (uint64_t)k * kEmitThreads + tid;
       if (d >= d1) break;
-      int lo = 0, hi = nr - 1;
+      // the last row slot starting at or before d (slots without tiles share
+      // their start with the next slot, which the search then picks)
+      const int rel = (int)(d - d0);
+      int lo = 0, hi = R - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (s_off[mid] <= d) lo = mid; else hi = mid - 1;
+        if (q_start[mid] <= rel) lo = mid; else hi = mid - 1;
       }
-      // the record's rows are slots [q0, q1); its j-th tile lies in the last
-      // slot whose scanned count does not exceed r_pre[q0] + j
-      const int q0 = (int)s_row0[lo], q1 = (int)s_row0[lo + 1];
-      const uint32_t target = r_pre[q0] + (uint32_t)(d - s_off[lo]);
-      int a = q0, c = q1 - 1;
-      while (a < c) {
-        const int mid = (a + c + 1) >> 1;
-        if (r_pre[mid] <= target) a = mid; else c = mid - 1;
-      }
-      a = min(a, R - 1);
-      const uint2 rc = s_rect[lo];
-      const int ty = clampi((int)(rc.x >> 16) + (a - q0), (int)(rc.x >> 16), (int)(rc.y >> 16) - 1);
-      const int tx = clampi((int)r_lo[a] + (int)min(target - r_pre[a], 0xFFFFu), (int)(rc.x & 0xFFFF),
-                            (int)(rc.y & 0xFFFF) - 1);
-      e.keys_out[d] = global_tile(e, s_rec[lo], ty, tx);
-      e.vals_out[d] = s_rec[lo];
+      const int col = min(rel - q_start[lo], max((int)q_cnt[lo], 1) - 1);
+      e.keys_out[d] = q_tile0[lo] + (uint32_t)max(col, 0);
+      e.vals_out[d] = s_rec[q_k[lo]];
     }
   } else {
     // more records or rows than LDS holds: search the offsets in memory and
@@ -357,14 +367,23 @@ __global__ __launch_bounds__(kEmitThreads) void emit_balanced_kernel(EmitArgs e)
       const uint2 rc = e.rects[r];
       uint32_t j = (uint32_t)(d - e.offs[i]);
       const int ty0 = (int)(rc.x >> 16), ty1 = (int)(rc.y >> 16);
-      int ty = ty0, a = 0, b = 0;
+      const int v = (int)(r / (uint32_t)e.per_view);
+      const int li = (int)(r - (uint32_t)v * (uint32_t)e.per_view);
+      const int tx0 = rc.x & 0xFFFF, tx1 = rc.y & 0xFFFF;
+      const bool gauss = li < e.N;
+      Support sup;
+      if (gauss) sup = make_support(e.grec[(int64_t)v * e.N + li]);
+      const ViewParams &vp = e.views[v];
+      int ty = ty0, a = tx0, b = tx1;
       for (; ty < ty1; ++ty) {
-        record_row(e, r, rc, ty, a, b);
+        a = tx0;
+        b = tx1;
+        if (gauss) support_row(sup, ty, e.tile_w, e.tile_h, vp.W, vp.H, tx0, tx1, a, b);
         if (j < (uint32_t)(b - a)) break;
         j -= (uint32_t)(b - a);
       }
       ty = clampi(ty, ty0, ty1 - 1);
-      const int tx = clampi(a + (int)min(j, 0xFFFFu), (int)(rc.x & 0xFFFF), (int)(rc.y & 0xFFFF) - 1);
+      const int tx = clampi(a + (int)min(j, 0xFFFFu), tx0, tx1 - 1);
       e.keys_out[d] = global_tile(e, r, ty, tx);
       e.vals_out[d] = r;
     }
@@ -448,6 +467,8 @@ hipError_t launch_exclusive_scan_u32(Ctx *c, uint32_t *data, int64_t n, uint32_t
   return excl_scan<uint32_t>(c->stream, data, n, tmp);
 }
 
+size_t emit_blocks_bytes(uint64_t n) { return (size_t)((n + kEmitSpan - 1) / kEmitSpan + 2) * 4; }
+
 hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u32_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, c->stream, p, n, v);
@@ -503,6 +524,11 @@ hipError_t launch_emit_keys(Ctx *c) {
   if (e != hipSuccess || c->n_records == 0) return e;
   if (c->n_launch == 0) return hipSuccess;
   ScopedTimer t(c, K_EMIT);
+  const uint32_t nblocks = ceil_div(c->n_launch, kEmitSpan);
+  hipLaunchKernelGGL(emit_blocks_kernel, dim3(ceil_div(c->n_records, 256)), dim3(256), 0, c->stream,
+                     (const uint64_t *)c->offs.p, c->n_records, (const FrameInfo *)c->finfo.p,
+                     nblocks, (uint32_t *)c->blk_first.p);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
   EmitArgs a;
   a.views = c->cur_views;
   a.per_view = c->N + c->T;
@@ -515,10 +541,10 @@ hipError_t launch_emit_keys(Ctx *c) {
   a.offs = (const uint64_t *)c->offs.p;
   a.grec = (const GaussRec *)c->grec.p;
   a.fi = (const FrameInfo *)c->finfo.p;
+  a.blk_first = (const uint32_t *)c->blk_first.p;
   a.keys_out = (uint32_t *)c->k0.p;
   a.vals_out = (uint32_t *)c->v0.p;
-  hipLaunchKernelGGL(emit_balanced_kernel, dim3(ceil_div(c->n_launch, kEmitSpan)),
-                     dim3(kEmitThreads), 0, c->stream, a);
+  hipLaunchKernelGGL(emit_balanced_kernel, dim3(nblocks), dim3(kEmitThreads), 0, c->stream, a);
   return hipGetLastError();
 }
 

@@ -144,6 +144,7 @@ struct Ctx {
   DevBuf k0, k1;       // n_dup uint32 global tile ids (ping-pong)
   DevBuf v0, v1;       // n_dup uint32 record ids
   DevBuf hist;         // radix per-block histograms
+  DevBuf blk_first;    // emit blocks + 1 uint32: first record of each emit block
   DevBuf ranges;       // n_tiles uint2
   DevBuf g2d;          // V*N x 9 per-view 2D gradients (backward)
   DevBuf host_pinned;  // not a device buffer: pinned host scratch for small readbacks
@@ -183,6 +184,7 @@ hipError_t launch_radix_sort_u32(Ctx *c, uint32_t *keys[2], uint32_t *vals[2], u
                                  int kid_up, int kid_scan, int kid_down);
 int radix_passes(int bits);
 size_t radix_hist_bytes(uint64_t n);
+size_t emit_blocks_bytes(uint64_t n);
 hipError_t launch_tile_sort(Ctx *c);
 hipError_t launch_tile_ranges(Ctx *c);
 hipError_t launch_expand_keys(Ctx *c, uint64_t *dst);

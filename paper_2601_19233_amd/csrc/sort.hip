@@ -60,32 +60,32 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
   return m;
 }
 
+// Per-block digit counts.  Order does not matter here, so each thread reads
+// 16 consecutive keys with 16-byte loads and counts them with LDS atomics
+// into its wave's histogram (neighbouring keys -- a record's tiles -- mostly
+// carry different digits, so lanes rarely collide on an address).
 __global__ __launch_bounds__(kThreads) void rs_upsweep(const uint32_t *__restrict__ keys,
                                                        PassArgs a, uint32_t *__restrict__ hist) {
   if (pass_through(a)) return;
   const uint32_t n = pass_count(a);
   __shared__ uint32_t h[kWaves][kBins];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, w = tid >> 6;
   for (int k = tid; k < kWaves * kBins; k += kThreads) (&h[0][0])[k] = 0;
   __syncthreads();
   const uint32_t blk = xcd_block(blockIdx.x, a.nblocks);
-  const uint32_t wbase = blk * kTile + w * (kRounds * 64);
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint32_t i0 = blk * kTile + tid * kRounds;
   uint32_t key[kRounds];
+  if (i0 + kRounds <= n) {
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
-    const uint32_t idx = wbase + r * 64 + lane;
-    key[r] = idx < n ? keys[idx] : 0u;
-  }
+    for (int q = 0; q < kRounds / 4; ++q) {
+      const uint4 v = *(const uint4 *)(keys + i0 + 4 * q);
+      key[4 * q] = v.x; key[4 * q + 1] = v.y; key[4 * q + 2] = v.z; key[4 * q + 3] = v.w;
+    }
 #pragma unroll
-  for (int r = 0; r < kRounds; ++r) {
-    // one LDS add per distinct digit of the wave: the lowest lane of each
-    // equal-digit lane set adds the set's size
-    const bool valid = wbase + r * 64 + lane < n;
-    const uint32_t d = (key[r] >> a.shift) & a.mask;
-    const uint64_t m = digit_peers(d, valid);
-    if (valid && (m & lt) == 0) h[w][d] += (uint32_t)__popcll(m);
-    __builtin_amdgcn_wave_barrier();
+    for (int r = 0; r < kRounds; ++r) atomicAdd(&h[w][(key[r] >> a.shift) & a.mask], 1u);
+  } else {
+    for (int r = 0; r < kRounds; ++r)
+      if (i0 + r < n) atomicAdd(&h[w][(keys[i0 + r] >> a.shift) & a.mask], 1u);
   }
   __syncthreads();
   const uint32_t s = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];

@@ -1,6 +1,6 @@
 // Tile rows of a projected Gaussian's support, shared by the projection
 // (which counts a record's tiles) and the bin stage (which emits them), so
-// both derive the same tiles with the same arithmetic.
+// both derive the same tiles from the same arithmetic (contraction off).
 //
 // A Gaussian contributes to a pixel only where alpha = min(0.99, o exp(power))
 // >= 1/255 (Eq. 1-2 with the 3DGS cut-off), i.e. where
@@ -9,12 +9,16 @@
 // numbers the blend evaluates.  The blend evaluates Q in FP32: each term
 // carries a few roundings, so |Q_fp32 - Q| <= 1e-6 kappa Q with kappa the
 // condition number of the form, and exp and the products move the threshold
-// by well under 1e-3.  The support used here is therefore the ellipse
-// Q <= tau = (L + 1e-3) / (1 - 1e-6 kappa), evaluated in FP64 with another
-// 1e-3 px of slack; a tile is kept if one of its pixel centres lies inside.
-// Dropping the other tiles of the bounding rectangle changes no pixel.
-// Forms that are degenerate or too ill-conditioned for the bound keep the
-// whole rectangle.
+// by well under 1e-3.  The support used here is the ellipse
+//   Q <= tau = (L + 1e-3) (1 + 1e-4) / (1 - 1e-6 kappa),
+// whose chords are evaluated in FP32 with the hardware square root and
+// reciprocal (1 ulp; D = 4AC - B^2 in FP64, then rounded) and widened by
+// 0.02 px plus 2e-3 of the ellipse's extent, which covers the FP32 error of
+// the chord ends (at most a few 1e-4 of the extent, where the square root's
+// argument cancels).  A tile is kept if one of its pixel
+// centres lies inside; dropping the other tiles of the bounding rectangle
+// changes no pixel.  Forms that are degenerate or too ill-conditioned for
+// the bound keep the whole rectangle.
 #pragma once
 
 #include "internal.h"
@@ -22,26 +26,31 @@
 namespace umgs {
 
 struct Support {
-  double mx, my, A, B, C, D, tau;
-  bool exact;   // false: every tile of the rectangle is kept
+  float mx, my, A, B, C, D, tau, ex, ey, m;   // ex, ey: half extents; m: chord slack
+  bool exact;                                 // false: every tile of the rectangle is kept
 };
 
 __device__ __forceinline__ Support make_support(const GaussRec &g) {
 #pragma clang fp contract(off)
   Support s;
-  s.mx = (double)g.mx;
-  s.my = (double)g.my;
-  s.A = -(double)g.qa;
-  s.B = -(double)g.qb;
-  s.C = -(double)g.qc;
-  s.D = 4.0 * s.A * s.C - s.B * s.B;
-  const double L = log(255.0 * (double)g.opacity);
-  const double h = sqrt((s.A - s.C) * (s.A - s.C) + s.B * s.B);
-  const double lmax = 0.5 * ((s.A + s.C) + h);
-  const double lmin = s.D / (4.0 * lmax);          // product of the eigenvalues is D/4
-  const double kappa = lmax / lmin;
-  s.exact = s.A > 0.0 && s.C > 0.0 && s.D > 0.0 && lmin > 0.0 && kappa < 1e5 && L > 0.0;
-  s.tau = (L + 1e-3) / (1.0 - 1e-6 * kappa);
+  s.mx = g.mx;
+  s.my = g.my;
+  s.A = -g.qa;
+  s.B = -g.qb;
+  s.C = -g.qc;
+  const double Dd = 4.0 * (double)s.A * (double)s.C - (double)s.B * (double)s.B;
+  s.D = (float)Dd;
+  const float L = __logf(255.0f * g.opacity);
+  const float h = __builtin_amdgcn_sqrtf((s.A - s.C) * (s.A - s.C) + s.B * s.B);
+  const float lmax = 0.5f * ((s.A + s.C) + h);
+  const float lmin = s.D * __builtin_amdgcn_rcpf(4.0f * lmax);   // eigenvalue product is D/4
+  const float kappa = lmax * __builtin_amdgcn_rcpf(lmin);
+  s.exact = s.A > 0.0f && s.C > 0.0f && s.D > 0.0f && lmin > 0.0f && kappa < 1e5f && L > 0.0f;
+  s.tau = ((L + 1e-3f) * 1.0001f) * __builtin_amdgcn_rcpf(1.0f - 1e-6f * kappa);
+  const float iD = __builtin_amdgcn_rcpf(s.D);
+  s.ey = __builtin_amdgcn_sqrtf(4.0f * s.A * s.tau * iD);
+  s.ex = __builtin_amdgcn_sqrtf(4.0f * s.C * s.tau * iD);
+  s.m = 0.02f + 2e-3f * (s.ex + s.ey);
   return s;
 }
 
@@ -53,28 +62,27 @@ __device__ __forceinline__ void support_row(const Support &s, int ty, int tile_w
   a = tx0;
   b = tx1;
   if (!s.exact) return;
-  const double m = 1e-3;
   // pixel-centre rows of the tile row, relative to the mean
-  const double y0 = ((double)(ty * tile_h) + 0.5) - s.my - m;
-  const double y1 = ((double)min(ty * tile_h + tile_h, H) - 0.5) - s.my + m;
-  const double ey = sqrt(4.0 * s.A * s.tau / s.D);           // half height of the ellipse
-  const double lo = fmax(y0, -ey), hi = fmin(y1, ey);
+  const float y0 = ((float)(ty * tile_h) + 0.5f) - s.my - s.m;
+  const float y1 = ((float)min(ty * tile_h + tile_h, H) - 0.5f) - s.my + s.m;
+  const float lo = fmaxf(y0, -s.ey), hi = fminf(y1, s.ey);
   if (lo > hi) {
     b = a;
     return;
   }
   // the rightmost point of the ellipse lies at dy = -ys, the leftmost at +ys;
   // x at the ends of a chord: (-B dy +- sqrt(4 A tau - D dy^2)) / (2 A)
-  const double ys = s.B * sqrt(s.tau / (s.C * s.D));
-  const double dr = fmin(fmax(-ys, lo), hi), dl = fmin(fmax(ys, lo), hi);
-  const double sr = sqrt(fmax(4.0 * s.A * s.tau - s.D * dr * dr, 0.0));
-  const double sl = sqrt(fmax(4.0 * s.A * s.tau - s.D * dl * dl, 0.0));
-  const double xmax = s.mx + (-s.B * dr + sr) / (2.0 * s.A) + m;
-  const double xmin = s.mx + (-s.B * dl - sl) / (2.0 * s.A) - m;
+  const float ys = s.B * __builtin_amdgcn_sqrtf(s.tau * __builtin_amdgcn_rcpf(s.C * s.D));
+  const float dr = fminf(fmaxf(-ys, lo), hi), dl = fminf(fmaxf(ys, lo), hi);
+  const float sr = __builtin_amdgcn_sqrtf(fmaxf(4.0f * s.A * s.tau - s.D * dr * dr, 0.0f));
+  const float sl = __builtin_amdgcn_sqrtf(fmaxf(4.0f * s.A * s.tau - s.D * dl * dl, 0.0f));
+  const float i2A = __builtin_amdgcn_rcpf(2.0f * s.A);
+  const float xmax = s.mx + (-s.B * dr + sr) * i2A + s.m;
+  const float xmin = s.mx + (-s.B * dl - sl) * i2A - s.m;
   // pixel columns px with px + 0.5 in [xmin, xmax], inside the rectangle
-  const double plo = (double)(tx0 * tile_w), phi = (double)(min(tx1 * tile_w, W) - 1);
-  const double c0 = fmin(fmax(ceil(xmin - 0.5), plo), phi + 1.0);
-  const double c1 = fmax(fmin(floor(xmax - 0.5), phi), plo - 1.0);
+  const float plo = (float)(tx0 * tile_w), phi = (float)(min(tx1 * tile_w, W) - 1);
+  const float c0 = fminf(fmaxf(ceilf(xmin - 0.5f), plo), phi + 1.0f);
+  const float c1 = fmaxf(fminf(floorf(xmax - 0.5f), phi), plo - 1.0f);
   if (c0 > c1) {
     b = a;
     return;
