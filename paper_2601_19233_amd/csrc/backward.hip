@@ -34,21 +34,33 @@ namespace umgs {
 
 namespace {
 
-// Sum over the 64 lanes of the wave, complete in lane 63, with DPP moves on
-// the vector ALU: swap neighbours, swap pairs, mirror half-rows and rows
-// (every lane holds its 16-lane row's sum), then broadcast lane 15 of each
-// row into the next row and lane 31 into the upper half.  Every lane of the
-// wave must be active.
+// Sums over the 64 lanes of the wave, complete in lane 63 (other lanes end
+// with partial sums), with DPP moves on the vector ALU: swap neighbours,
+// swap pairs, mirror half-rows and rows (every lane holds its 16-lane row's
+// sum), then broadcast lane 15 of each row into the next row and lane 31
+// into the upper rows.  Every lane of the wave must be active.
 // (bound_ctrl set: the permutes have no invalid source lanes, and with it
-// the compiler folds each move into the add as one DPP instruction)
-__device__ __forceinline__ float wave_total(float v) {
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x142, 0xA, 0xF, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x143, 0xC, 0xF, true));
-  return v;
+// the compiler folds each move into the add as one DPP instruction.)  The
+// K values advance step by step together, so the dependent DPP operations
+// of one value are separated by those of the others instead of by nops.
+template <int CTRL, int ROWS, int K>
+__device__ __forceinline__ void dpp_add_step(float (&v)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+    v[k] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[k]), CTRL, ROWS, 0xF, true));
+}
+
+template <int K>
+__device__ __forceinline__ void wave_totals(float (&v)[K]) {
+  dpp_add_step<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
+  dpp_add_step<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
+  dpp_add_step<0x141, 0xF>(v);   // row_half_mirror
+  dpp_add_step<0x140, 0xF>(v);   // row_mirror
+  // Only lane 63 is read: it takes lane 47 (row 2's sum) here and then
+  // lane 31 (rows 0 + 1); what the other rows receive does not reach it, so
+  // these steps write every row and fold into single DPP adds as well.
+  dpp_add_step<0x142, 0xF>(v);   // row_bcast:15
+  dpp_add_step<0x143, 0xF>(v);   // row_bcast:31
 }
 
 template <int TW, int TH>
@@ -176,13 +188,11 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
         g[6] = w * dC0;
         g[7] = w * dC1;
         g[8] = w * dC2;
-        {
+        wave_totals(g);
+        if (lane == 63) {
           float *dst = gl + (tid >> 6) * batch * 9 + f * 9;
 #pragma unroll
-          for (int k = 0; k < 9; ++k) {
-            const float r = wave_total(g[k]);
-            if (lane == 63) dst[k] = r;
-          }
+          for (int k = 0; k < 9; ++k) dst[k] = g[k];
         }
       } else {
         double e[3];

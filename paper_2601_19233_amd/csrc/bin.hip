@@ -340,21 +340,39 @@ __global__ __launch_bounds__(kEmitThreads) void emit_balanced_kernel(EmitArgs e)
       q_start[q] = s_off[k] + (int32_t)((uint32_t)q_start[q] - s_pbase[k]);
     }
     __syncthreads();
-#pragma unroll
-    for (int k = 0; k < kEmitPer; ++k) {
-      const uint64_t d = d0 + (uint64_t)k * kEmitThreads + tid;
-      if (d >= d1) break;
-      // the last row slot starting at or before d (slots without tiles share
-      // their start with the next slot, which the search then picks)
-      const int rel = (int)(d - d0);
-      int lo = 0, hi = R - 1;
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (q_start[mid] <= rel) lo = mid; else hi = mid - 1;
+    // each thread writes kEmitPer consecutive positions: one search for the
+    // row slot of its first position (the last slot starting at or before
+    // it; slots without tiles share their start with the next slot, which
+    // the search then picks), then a forward walk, and 16-byte stores
+    const int p0 = tid * kEmitPer;
+    if (d0 + (uint64_t)p0 < d1) {
+      int q = 0, hi = R - 1;
+      while (q < hi) {
+        const int mid = (q + hi + 1) >> 1;
+        if (q_start[mid] <= p0) q = mid; else hi = mid - 1;
       }
-      const int col = min(rel - q_start[lo], max((int)q_cnt[lo], 1) - 1);
-      e.keys_out[d] = q_tile0[lo] + (uint32_t)max(col, 0);
-      e.vals_out[d] = s_rec[q_k[lo]];
+      uint32_t kk[kEmitPer], vv[kEmitPer];
+#pragma unroll
+      for (int j = 0; j < kEmitPer; ++j) {
+        const int p = p0 + j;
+        while (q + 1 < R && q_start[q + 1] <= p) ++q;
+        const int col = min(p - q_start[q], max((int)q_cnt[q], 1) - 1);
+        kk[j] = q_tile0[q] + (uint32_t)max(col, 0);
+        vv[j] = s_rec[q_k[q]];
+      }
+      const uint64_t d = d0 + (uint64_t)p0;
+      if (d + kEmitPer <= d1) {
+#pragma unroll
+        for (int j = 0; j < kEmitPer; j += 4) {
+          *(uint4 *)(e.keys_out + d + j) = make_uint4(kk[j], kk[j + 1], kk[j + 2], kk[j + 3]);
+          *(uint4 *)(e.vals_out + d + j) = make_uint4(vv[j], vv[j + 1], vv[j + 2], vv[j + 3]);
+        }
+      } else {
+        for (int j = 0; j < kEmitPer && d + j < d1; ++j) {
+          e.keys_out[d + j] = kk[j];
+          e.vals_out[d + j] = vv[j];
+        }
+      }
     }
   } else {
     // more records or rows than LDS holds: search the offsets in memory and
