@@ -63,6 +63,64 @@ __device__ __forceinline__ void wave_totals(float (&v)[K]) {
   dpp_add_step<0x143, 0xF>(v);   // row_bcast:31
 }
 
+// Backward state of one pixel while its list is walked from the back.
+struct PixBwd {
+  float Tr, Tterm, dC0, dC1, dC2, B0, B1, B2;
+  int last;
+  bool in_ent, term_ent;
+  float s0[3], s1[3], s2[3], s3[3];
+  float p0, p1, p2, p3;
+};
+
+// One Gaussian fragment (list position pos) of the walk: updates the
+// pixel's state where it blended the fragment and leaves the pixel's 9
+// gradient terms in g (exact zeros where it did not).  Returns whether it
+// blended it.  Every lane evaluates every term (no short-circuit), so the
+// wave sums that follow see defined values on all lanes.
+__device__ __forceinline__ bool gauss_bwd(const uint32_t *s, int pos, float pcx, float pcy,
+                                          PixBwd &q, float *g) {
+  float alpha, G, dx, dy;
+  const bool hit = gauss_terms(s, pcx, pcy, alpha, G, dx, dy);
+  const bool contrib = pos < q.last && hit;
+  if (contrib && q.in_ent) {
+    q.B0 = 0.25f * ((q.s0[0] + q.s1[0]) + (q.s2[0] + q.s3[0]));
+    q.B1 = 0.25f * ((q.s0[1] + q.s1[1]) + (q.s2[1] + q.s3[1]));
+    q.B2 = 0.25f * ((q.s0[2] + q.s1[2]) + (q.s2[2] + q.s3[2]));
+    q.Tr = q.term_ent ? q.Tterm : q.Tr / (0.25f * ((q.p0 + q.p1) + (q.p2 + q.p3)));
+    q.in_ent = false;
+  }
+  // T in front of the fragment: one rcp (1 ulp) per step of the walk
+  const float Tb = (pos == q.last - 1) ? q.Tterm : q.Tr * __builtin_amdgcn_rcpf(1.0f - alpha);
+  const float c0 = __uint_as_float(s[6]), c1 = __uint_as_float(s[7]), c2 = __uint_as_float(s[8]);
+  const float w = contrib ? Tb * alpha : 0.0f;
+  const float dLda =
+      contrib ? Tb * ((c0 - q.B0) * q.dC0 + (c1 - q.B1) * q.dC1 + (c2 - q.B2) * q.dC2) : 0.0f;
+  if (contrib) {
+    q.B0 = fmaf(alpha, c0 - q.B0, q.B0);
+    q.B1 = fmaf(alpha, c1 - q.B1, q.B1);
+    q.B2 = fmaf(alpha, c2 - q.B2, q.B2);
+    q.Tr = Tb;
+  }
+  // alpha below the 0.99 clamp depends on power and opacity
+  const float op = __uint_as_float(s[5]);
+  const float dpow = (op * G < kAlphaMax) ? dLda : 0.0f;
+  const float qa = __uint_as_float(s[2]), qb = __uint_as_float(s[3]), qc = __uint_as_float(s[4]);
+  const float dp = alpha * dpow;     // d alpha / d power = o G = alpha
+  // offsets of other lanes may be huge (a far mean): keep 0 x inf out
+  dx = contrib ? dx : 0.0f;
+  dy = contrib ? dy : 0.0f;
+  g[0] = dp * (2.0f * qa * dx + qb * dy);
+  g[1] = dp * (qb * dx + 2.0f * qc * dy);
+  g[2] = dp * dx * dx;
+  g[3] = dp * dx * dy;
+  g[4] = dp * dy * dy;
+  g[5] = G * dpow;
+  g[6] = w * q.dC0;
+  g[7] = w * q.dC1;
+  g[8] = w * q.dC2;
+  return contrib;
+}
+
 template <int TW, int TH>
 __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
     const ViewParams *__restrict__ views, int V, int N, int T, int mode, int batch,
@@ -98,34 +156,36 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
 
   const int64_t HW = (int64_t)vp.W * vp.H;
   const int64_t pix = (int64_t)py * vp.W + px;
-  int last = 0;
-  float Tr = 1.0f, Tterm = 1.0f, dC0 = 0.f, dC1 = 0.f, dC2 = 0.f;
+  PixBwd q;
+  q.last = 0;
+  q.Tr = 1.0f; q.Tterm = 1.0f; q.dC0 = 0.f; q.dC1 = 0.f; q.dC2 = 0.f;
   const int count = (int)(rg.y - rg.x);
   if (inside) {
     // positions are 1-based within this tile's list; clamp so a per-pixel
     // array from another frame can never index past the tile's range
-    last = min(max(ncontrib[vp.pix_base + pix], 0), count);
-    Tr = Tfin[vp.pix_base + pix];
-    Tterm = Tent[vp.pix_base + pix];
+    q.last = min(max(ncontrib[vp.pix_base + pix], 0), count);
+    q.Tr = Tfin[vp.pix_base + pix];
+    q.Tterm = Tent[vp.pix_base + pix];
     const float *d = dLdimg + 3 * vp.pix_base;
-    dC0 = d[pix];
-    dC1 = d[HW + pix];
-    dC2 = d[2 * HW + pix];
+    q.dC0 = d[pix];
+    q.dC1 = d[HW + pix];
+    q.dC2 = d[2 * HW + pix];
   }
   if (tid == 0) smax = 0;
   __syncthreads();
-  atomicMax(&smax, last);
+  atomicMax(&smax, q.last);
   __syncthreads();
   const int max_last = smax;
 
-  float B0 = bg0, B1 = bg1, B2 = bg2;
-  bool in_ent = false, term_ent = false;
-  float s0[3], s1[3], s2[3], s3[3];
-  float p0 = 1.f, p1 = 1.f, p2 = 1.f, p3 = 1.f;
+  q.B0 = bg0; q.B1 = bg1; q.B2 = bg2;
+  q.in_ent = false; q.term_ent = false;
+  q.p0 = q.p1 = q.p2 = q.p3 = 1.f;
+  float *const glw = gl + (tid >> 6) * batch * 9;     // this wave's partial sums
 
   for (int bend = max_last; bend > 0; bend -= batch) {
     const int bstart = max(0, bend - batch);
     const int bn = bend - bstart;
+    int tri_here = 0;
     for (int f = tid; f < bn; f += NT) {
       uint32_t *s = slots + f * kSlotWords;
       const int64_t local = (int64_t)vals[rg.x + bstart + f] - rbase;
@@ -134,94 +194,73 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
         stage_gauss(s, grec[rec], rec);
       } else {
         stage_tri(s, trec[(int64_t)v * T + (local - N)], P0x, P0y);
+        tri_here = 1;
       }
       for (int k = 0; k < (NT / 64) * 9; ++k) gl[(k / 9) * batch * 9 + f * 9 + k % 9] = 0.0f;
     }
-    __syncthreads();
+    const bool any_tri = __syncthreads_or(tri_here) != 0;
 
-    for (int f = bn - 1; f >= 0; --f) {
-      const uint32_t *s = slots + f * kSlotWords;
-      const int pos = bstart + f;
-      const bool mine = pos < last;
-      if (!__any(mine)) continue;
-      if ((s[31] & 1u) == 0u) {
-        // selects rather than branches keep every lane active for the row sums
-        // evaluated on every lane (not short-circuited by `mine`): lanes
-        // past their last fragment feed the sums with exact zeros
-        float alpha, G, dx, dy;
-        const bool hit = gauss_terms(s, pcx, pcy, alpha, G, dx, dy);
-        const bool contrib = mine && hit;
-        if (!__any(contrib)) continue;     // no lane of the wave blends it
-        if (contrib && in_ent) {
-          B0 = 0.25f * ((s0[0] + s1[0]) + (s2[0] + s3[0]));
-          B1 = 0.25f * ((s0[1] + s1[1]) + (s2[1] + s3[1]));
-          B2 = 0.25f * ((s0[2] + s1[2]) + (s2[2] + s3[2]));
-          Tr = term_ent ? Tterm : Tr / (0.25f * ((p0 + p1) + (p2 + p3)));
-          in_ent = false;
-        }
-        // T in front of the fragment: one rcp (1 ulp) per step of the walk
-        const float Tb = (pos == last - 1) ? Tterm : Tr * __builtin_amdgcn_rcpf(1.0f - alpha);
-        const float c0 = __uint_as_float(s[6]), c1 = __uint_as_float(s[7]), c2 = __uint_as_float(s[8]);
-        const float w = contrib ? Tb * alpha : 0.0f;
-        const float dLda = contrib ? Tb * ((c0 - B0) * dC0 + (c1 - B1) * dC1 + (c2 - B2) * dC2) : 0.0f;
-        if (contrib) {
-          B0 = fmaf(alpha, c0 - B0, B0);
-          B1 = fmaf(alpha, c1 - B1, B1);
-          B2 = fmaf(alpha, c2 - B2, B2);
-          Tr = Tb;
-        }
-        // alpha below the 0.99 clamp depends on power and opacity
-        const float op = __uint_as_float(s[5]);
-        const float dpow = (op * G < kAlphaMax) ? dLda : 0.0f;
-        const float qa = __uint_as_float(s[2]), qb = __uint_as_float(s[3]), qc = __uint_as_float(s[4]);
-        const float dp = alpha * dpow;     // d alpha / d power = o G = alpha
-        // offsets of other lanes may be huge (a far mean): keep 0 x inf out
-        dx = contrib ? dx : 0.0f;
-        dy = contrib ? dy : 0.0f;
-        float g[9];
-        g[0] = dp * (2.0f * qa * dx + qb * dy);
-        g[1] = dp * (qb * dx + 2.0f * qc * dy);
-        g[2] = dp * dx * dx;
-        g[3] = dp * dx * dy;
-        g[4] = dp * dy * dy;
-        g[5] = G * dpow;
-        g[6] = w * dC0;
-        g[7] = w * dC1;
-        g[8] = w * dC2;
+    int f = bn - 1;
+    if (!any_tri) {
+      // Gaussians only: two fragments a step (their alphas are independent;
+      // the state updates run in list order) and 18 wave sums together
+      for (; f >= 1; f -= 2) {
+        if (!__any(bstart + f - 1 < q.last)) continue;
+        float g[18];
+        const bool c1 = gauss_bwd(slots + f * kSlotWords, bstart + f, pcx, pcy, q, g);
+        const bool c0 = gauss_bwd(slots + (f - 1) * kSlotWords, bstart + f - 1, pcx, pcy, q, g + 9);
+        if (!__any(c0 || c1)) continue;
         wave_totals(g);
         if (lane == 63) {
-          float *dst = gl + (tid >> 6) * batch * 9 + f * 9;
 #pragma unroll
-          for (int k = 0; k < 9; ++k) dst[k] = g[k];
+          for (int k = 0; k < 9; ++k) {
+            glw[f * 9 + k] = g[k];
+            glw[(f - 1) * 9 + k] = g[9 + k];
+          }
+        }
+      }
+    }
+    for (; f >= 0; --f) {
+      const uint32_t *s = slots + f * kSlotWords;
+      const int pos = bstart + f;
+      if (!__any(pos < q.last)) continue;
+      if ((s[31] & 1u) == 0u) {
+        float g[9];
+        const bool contrib = gauss_bwd(s, pos, pcx, pcy, q, g);
+        if (!__any(contrib)) continue;     // no lane of the wave blends it
+        wave_totals(g);
+        if (lane == 63) {
+#pragma unroll
+          for (int k = 0; k < 9; ++k) glw[f * 9 + k] = g[k];
         }
       } else {
         double e[3];
         float o[4];
-        const bool contrib = mine && tri_eval(s, rlx, rly, direct, e, o) > 0;
+        const bool contrib = pos < q.last && tri_eval(s, rlx, rly, direct, e, o) > 0;
         if (contrib) {
           float cr, cg, cbl;
           tri_colour(s, e, cr, cg, cbl);
           const float alpha = __uint_as_float(s[30]);
           if (direct) {
-            Tr = (pos == last - 1) ? Tterm : Tr / (1.0f - alpha);
-            B0 = fmaf(alpha, cr - B0, B0);
-            B1 = fmaf(alpha, cg - B1, B1);
-            B2 = fmaf(alpha, cbl - B2, B2);
+            q.Tr = (pos == q.last - 1) ? q.Tterm : q.Tr / (1.0f - alpha);
+            q.B0 = fmaf(alpha, cr - q.B0, q.B0);
+            q.B1 = fmaf(alpha, cg - q.B1, q.B1);
+            q.B2 = fmaf(alpha, cbl - q.B2, q.B2);
           } else {
-            if (!in_ent) {
-              in_ent = true;
-              term_ent = (pos == last - 1);
-              s0[0] = s1[0] = s2[0] = s3[0] = B0;
-              s0[1] = s1[1] = s2[1] = s3[1] = B1;
-              s0[2] = s1[2] = s2[2] = s3[2] = B2;
-              p0 = p1 = p2 = p3 = 1.0f;
+            if (!q.in_ent) {
+              q.in_ent = true;
+              q.term_ent = (pos == q.last - 1);
+              q.s0[0] = q.s1[0] = q.s2[0] = q.s3[0] = q.B0;
+              q.s0[1] = q.s1[1] = q.s2[1] = q.s3[1] = q.B1;
+              q.s0[2] = q.s1[2] = q.s2[2] = q.s3[2] = q.B2;
+              q.p0 = q.p1 = q.p2 = q.p3 = 1.0f;
             }
             const float a0 = o[0] * alpha, a1 = o[1] * alpha, a2 = o[2] * alpha, a3 = o[3] * alpha;
-            s0[0] = fmaf(a0, cr - s0[0], s0[0]); s0[1] = fmaf(a0, cg - s0[1], s0[1]); s0[2] = fmaf(a0, cbl - s0[2], s0[2]);
-            s1[0] = fmaf(a1, cr - s1[0], s1[0]); s1[1] = fmaf(a1, cg - s1[1], s1[1]); s1[2] = fmaf(a1, cbl - s1[2], s1[2]);
-            s2[0] = fmaf(a2, cr - s2[0], s2[0]); s2[1] = fmaf(a2, cg - s2[1], s2[1]); s2[2] = fmaf(a2, cbl - s2[2], s2[2]);
-            s3[0] = fmaf(a3, cr - s3[0], s3[0]); s3[1] = fmaf(a3, cg - s3[1], s3[1]); s3[2] = fmaf(a3, cbl - s3[2], s3[2]);
-            p0 *= 1.0f - a0; p1 *= 1.0f - a1; p2 *= 1.0f - a2; p3 *= 1.0f - a3;
+            q.s0[0] = fmaf(a0, cr - q.s0[0], q.s0[0]); q.s0[1] = fmaf(a0, cg - q.s0[1], q.s0[1]); q.s0[2] = fmaf(a0, cbl - q.s0[2], q.s0[2]);
+            q.s1[0] = fmaf(a1, cr - q.s1[0], q.s1[0]); q.s1[1] = fmaf(a1, cg - q.s1[1], q.s1[1]); q.s1[2] = fmaf(a1, cbl - q.s1[2], q.s1[2]);
+            q.s2[0] = fmaf(a2, cr - q.s2[0], q.s2[0]); q.s2[1] = fmaf(a2, cg - q.s2[1], q.s2[1]); q.s2[2] = fmaf(a2, cbl - q.s2[2], q.s2[2]);
+            q.s3[0] = fmaf(a3, cr - q.s3[0], q.s3[0]); q.s3[1] = fmaf(a3, cg - q.s3[1], q.s3[1]); q.s3[2] = fmaf(a3, cbl - q.s3[2], q.s3[2]);
+            q.p0 *= 1.0f - a0; q.p1 *= 1.0f - a1; q.p2 *= 1.0f - a2; q.p3 *= 1.0f - a3;
           }
         }
       }

@@ -166,8 +166,8 @@ __global__ void gather_counts_kernel(const uint32_t *__restrict__ order, int64_t
 constexpr int kEmitThreads = 256;
 constexpr int kEmitPer = 8;
 constexpr int kEmitSpan = kEmitThreads * kEmitPer;
-constexpr int kEmitRecCap = 512;
-constexpr int kEmitRowCap = 2048;
+constexpr int kEmitRecCap = 256;
+constexpr int kEmitRowCap = 1024;
 constexpr int kEmitRowPer = kEmitRowCap / kEmitThreads;
 
 // last r in [lo, hi] with offs[r] <= d (offs is non-decreasing)
@@ -266,7 +266,8 @@ __global__ __launch_bounds__(kEmitThreads) void emit_balanced_kernel(EmitArgs e)
   __shared__ uint2 s_rect[kEmitRecCap];          // tile rectangle
   __shared__ uint32_t s_tb[kEmitRecCap];         // global id of its view's tile (0, 0)
   __shared__ uint32_t s_ntx[kEmitRecCap];        // tiles per row of its view
-  __shared__ int32_t s_gidx[kEmitRecCap];        // Gaussian record index, -1: triangle
+  __shared__ int2 s_wh[kEmitRecCap];             // its view's width and height
+  __shared__ Support s_sup[kEmitRecCap];         // support of a Gaussian (exact = false: triangle)
   __shared__ uint32_t s_row0[kEmitRecCap + 1];   // rows, scanned to the first row slot
   __shared__ uint32_t s_pbase[kEmitRecCap];      // scanned tile count at the first row slot
   // row slots: one per tile row of a staged record
@@ -299,7 +300,11 @@ __global__ __launch_bounds__(kEmitThreads) void emit_balanced_kernel(EmitArgs e)
       s_rect[k] = rc;
       s_tb[k] = e.views[v].tile_base;
       s_ntx[k] = (uint32_t)e.views[v].ntx;
-      s_gidx[k] = i < e.N ? (int32_t)(v * (uint32_t)e.N + (uint32_t)i) : -1;
+      s_wh[k] = make_int2(e.views[v].W, e.views[v].H);
+      Support sup;
+      sup.exact = false;
+      if (i < e.N) sup = make_support(e.grec[(int64_t)v * e.N + i]);
+      s_sup[k] = sup;
       s_row0[k] = (rc.y >> 16) - (rc.x >> 16);
     }
     __syncthreads();
@@ -318,12 +323,9 @@ __global__ __launch_bounds__(kEmitThreads) void emit_balanced_kernel(EmitArgs e)
       const uint2 rc = s_rect[k];
       const int tx0 = rc.x & 0xFFFF, tx1 = rc.y & 0xFFFF;
       const int ty = (int)(rc.x >> 16) + (q - (int)s_row0[k]);
-      int a = tx0, b = tx1;
-      const int gi = s_gidx[k];
-      if (gi >= 0) {
-        const ViewParams &vp = e.views[(uint32_t)gi / (uint32_t)e.N];
-        support_row(make_support(e.grec[gi]), ty, e.tile_w, e.tile_h, vp.W, vp.H, tx0, tx1, a, b);
-      }
+      int a, b;
+      const int2 wh = s_wh[k];
+      support_row(s_sup[k], ty, e.tile_w, e.tile_h, wh.x, wh.y, tx0, tx1, a, b);
       q_tile0[q] = s_tb[k] + (uint32_t)ty * s_ntx[k] + (uint32_t)a;
       q_cnt[q] = (uint16_t)(b - a);
       q_start[q] = b - a;
