@@ -121,8 +121,43 @@ __device__ __forceinline__ bool gauss_bwd(const uint32_t *s, int pos, float pcx,
   return contrib;
 }
 
-template <int TW, int TH>
-__global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
+// Triangle fragment of the walk for one pixel (a fixed occluder: it passes
+// gradients through T and receives none).
+__device__ __forceinline__ void tri_bwd(const uint32_t *s, int pos, double rlx, double rly,
+                                        bool direct, PixBwd &q) {
+  double e[3];
+  float o[4];
+  if (!(pos < q.last && tri_eval(s, rlx, rly, direct, e, o) > 0)) return;
+  float cr, cg, cbl;
+  tri_colour(s, e, cr, cg, cbl);
+  const float alpha = __uint_as_float(s[30]);
+  if (direct) {
+    q.Tr = (pos == q.last - 1) ? q.Tterm : q.Tr / (1.0f - alpha);
+    q.B0 = fmaf(alpha, cr - q.B0, q.B0);
+    q.B1 = fmaf(alpha, cg - q.B1, q.B1);
+    q.B2 = fmaf(alpha, cbl - q.B2, q.B2);
+    return;
+  }
+  if (!q.in_ent) {
+    q.in_ent = true;
+    q.term_ent = (pos == q.last - 1);
+    q.s0[0] = q.s1[0] = q.s2[0] = q.s3[0] = q.B0;
+    q.s0[1] = q.s1[1] = q.s2[1] = q.s3[1] = q.B1;
+    q.s0[2] = q.s1[2] = q.s2[2] = q.s3[2] = q.B2;
+    q.p0 = q.p1 = q.p2 = q.p3 = 1.0f;
+  }
+  const float a0 = o[0] * alpha, a1 = o[1] * alpha, a2 = o[2] * alpha, a3 = o[3] * alpha;
+  q.s0[0] = fmaf(a0, cr - q.s0[0], q.s0[0]); q.s0[1] = fmaf(a0, cg - q.s0[1], q.s0[1]); q.s0[2] = fmaf(a0, cbl - q.s0[2], q.s0[2]);
+  q.s1[0] = fmaf(a1, cr - q.s1[0], q.s1[0]); q.s1[1] = fmaf(a1, cg - q.s1[1], q.s1[1]); q.s1[2] = fmaf(a1, cbl - q.s1[2], q.s1[2]);
+  q.s2[0] = fmaf(a2, cr - q.s2[0], q.s2[0]); q.s2[1] = fmaf(a2, cg - q.s2[1], q.s2[1]); q.s2[2] = fmaf(a2, cbl - q.s2[2], q.s2[2]);
+  q.s3[0] = fmaf(a3, cr - q.s3[0], q.s3[0]); q.s3[1] = fmaf(a3, cg - q.s3[1], q.s3[1]); q.s3[2] = fmaf(a3, cbl - q.s3[2], q.s3[2]);
+  q.p0 *= 1.0f - a0; q.p1 *= 1.0f - a1; q.p2 *= 1.0f - a2; q.p3 *= 1.0f - a3;
+}
+
+// One workgroup per tile; each thread walks PPT pixels of the tile (rows
+// ly and ly + TH/PPT), so one set of wave sums serves 64 x PPT pixels.
+template <int TW, int TH, int PPT>
+__global__ __launch_bounds__(TW *TH / PPT) void blend_backward_kernel(
     const ViewParams *__restrict__ views, int V, int N, int T, int mode, int batch,
     float bg0, float bg1, float bg2, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1,
@@ -130,7 +165,9 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
     const TriRec *__restrict__ trec, const float *__restrict__ dLdimg,
     const float *__restrict__ Tfin, const int32_t *__restrict__ ncontrib,
     const float *__restrict__ Tent, float *__restrict__ g2d) {
-  constexpr int NT = TW * TH;
+  constexpr int NTH = TW * TH / PPT;                      // threads
+  constexpr int NW = NTH / 64;                            // waves
+  static_assert(NTH % 64 == 0, "whole waves");
   extern __shared__ uint32_t smem[];
   uint32_t *slots = smem;                                 // batch * kSlotWords
   float *gl = (float *)(smem + batch * kSlotWords);       // [wave][batch][9] partial sums
@@ -143,50 +180,59 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
   const uint32_t lt = tile - vp.tile_base;
   const int tx = (int)(lt % (uint32_t)vp.ntx), ty = (int)(lt / (uint32_t)vp.ntx);
   const int tid = threadIdx.x, lane = tid & 63;
-  const int lx = tid % TW, ly = tid / TW;
-  const int px = tx * TW + lx, py = ty * TH + ly;
-  const bool inside = px < vp.W && py < vp.H;
-  const float pcx = (float)px + 0.5f, pcy = (float)py + 0.5f;
+  const int lx = tid % TW, ly0 = tid / TW;
+  const int px = tx * TW + lx;
+  const float pcx = (float)px + 0.5f;
   const int64_t P0x = (int64_t)(tx * TW) * kSubpx + kSubpx / 2;
   const int64_t P0y = (int64_t)(ty * TH) * kSubpx + kSubpx / 2;
-  const double rlx = (double)(lx * kSubpx), rly = (double)(ly * kSubpx);
+  const double rlx = (double)(lx * kSubpx);
   const bool direct = mode == UMGS_MODE_DIRECT;
   const uint2 rg = ranges[tile];
   const int64_t rbase = (int64_t)v * (N + T);
-
   const int64_t HW = (int64_t)vp.W * vp.H;
-  const int64_t pix = (int64_t)py * vp.W + px;
-  PixBwd q;
-  q.last = 0;
-  q.Tr = 1.0f; q.Tterm = 1.0f; q.dC0 = 0.f; q.dC1 = 0.f; q.dC2 = 0.f;
   const int count = (int)(rg.y - rg.x);
-  if (inside) {
-    // positions are 1-based within this tile's list; clamp so a per-pixel
-    // array from another frame can never index past the tile's range
-    q.last = min(max(ncontrib[vp.pix_base + pix], 0), count);
-    q.Tr = Tfin[vp.pix_base + pix];
-    q.Tterm = Tent[vp.pix_base + pix];
-    const float *d = dLdimg + 3 * vp.pix_base;
-    q.dC0 = d[pix];
-    q.dC1 = d[HW + pix];
-    q.dC2 = d[2 * HW + pix];
+
+  PixBwd q[PPT];
+  float pcy[PPT];
+  double rly[PPT];
+  int my_last = 0;
+#pragma unroll
+  for (int p = 0; p < PPT; ++p) {
+    const int ly = ly0 + p * (TH / PPT);
+    const int py = ty * TH + ly;
+    pcy[p] = (float)py + 0.5f;
+    rly[p] = (double)(ly * kSubpx);
+    q[p].last = 0;
+    q[p].Tr = 1.0f; q[p].Tterm = 1.0f; q[p].dC0 = 0.f; q[p].dC1 = 0.f; q[p].dC2 = 0.f;
+    if (px < vp.W && py < vp.H) {
+      const int64_t pix = (int64_t)py * vp.W + px;
+      // positions are 1-based within this tile's list; clamp so a per-pixel
+      // array from another frame can never index past the tile's range
+      q[p].last = min(max(ncontrib[vp.pix_base + pix], 0), count);
+      q[p].Tr = Tfin[vp.pix_base + pix];
+      q[p].Tterm = Tent[vp.pix_base + pix];
+      const float *d = dLdimg + 3 * vp.pix_base;
+      q[p].dC0 = d[pix];
+      q[p].dC1 = d[HW + pix];
+      q[p].dC2 = d[2 * HW + pix];
+    }
+    q[p].B0 = bg0; q[p].B1 = bg1; q[p].B2 = bg2;
+    q[p].in_ent = false; q[p].term_ent = false;
+    q[p].p0 = q[p].p1 = q[p].p2 = q[p].p3 = 1.f;
+    my_last = max(my_last, q[p].last);
   }
   if (tid == 0) smax = 0;
   __syncthreads();
-  atomicMax(&smax, q.last);
+  atomicMax(&smax, my_last);
   __syncthreads();
   const int max_last = smax;
-
-  q.B0 = bg0; q.B1 = bg1; q.B2 = bg2;
-  q.in_ent = false; q.term_ent = false;
-  q.p0 = q.p1 = q.p2 = q.p3 = 1.f;
   float *const glw = gl + (tid >> 6) * batch * 9;     // this wave's partial sums
 
   for (int bend = max_last; bend > 0; bend -= batch) {
     const int bstart = max(0, bend - batch);
     const int bn = bend - bstart;
     int tri_here = 0;
-    for (int f = tid; f < bn; f += NT) {
+    for (int f = tid; f < bn; f += NTH) {
       uint32_t *s = slots + f * kSlotWords;
       const int64_t local = (int64_t)vals[rg.x + bstart + f] - rbase;
       if (local < N) {
@@ -196,20 +242,28 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
         stage_tri(s, trec[(int64_t)v * T + (local - N)], P0x, P0y);
         tri_here = 1;
       }
-      for (int k = 0; k < (NT / 64) * 9; ++k) gl[(k / 9) * batch * 9 + f * 9 + k % 9] = 0.0f;
+      for (int k = 0; k < NW * 9; ++k) gl[(k / 9) * batch * 9 + f * 9 + k % 9] = 0.0f;
     }
     const bool any_tri = __syncthreads_or(tri_here) != 0;
 
     int f = bn - 1;
     if (!any_tri) {
       // Gaussians only: two fragments a step (their alphas are independent;
-      // the state updates run in list order) and 18 wave sums together
+      // each pixel's state updates run in list order) and 18 wave sums
+      // together, over the thread's PPT pixels
       for (; f >= 1; f -= 2) {
-        if (!__any(bstart + f - 1 < q.last)) continue;
+        if (!__any(bstart + f - 1 < my_last)) continue;
         float g[18];
-        const bool c1 = gauss_bwd(slots + f * kSlotWords, bstart + f, pcx, pcy, q, g);
-        const bool c0 = gauss_bwd(slots + (f - 1) * kSlotWords, bstart + f - 1, pcx, pcy, q, g + 9);
-        if (!__any(c0 || c1)) continue;
+        bool c = false;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          float h[18];
+          c |= gauss_bwd(slots + f * kSlotWords, bstart + f, pcx, pcy[p], q[p], h);
+          c |= gauss_bwd(slots + (f - 1) * kSlotWords, bstart + f - 1, pcx, pcy[p], q[p], h + 9);
+#pragma unroll
+          for (int k = 0; k < 18; ++k) g[k] = p == 0 ? h[k] : g[k] + h[k];
+        }
+        if (!__any(c)) continue;
         wave_totals(g);
         if (lane == 63) {
 #pragma unroll
@@ -223,50 +277,30 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
     for (; f >= 0; --f) {
       const uint32_t *s = slots + f * kSlotWords;
       const int pos = bstart + f;
-      if (!__any(pos < q.last)) continue;
+      if (!__any(pos < my_last)) continue;
       if ((s[31] & 1u) == 0u) {
         float g[9];
-        const bool contrib = gauss_bwd(s, pos, pcx, pcy, q, g);
-        if (!__any(contrib)) continue;     // no lane of the wave blends it
+        bool c = false;
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) {
+          float h[9];
+          c |= gauss_bwd(s, pos, pcx, pcy[p], q[p], h);
+#pragma unroll
+          for (int k = 0; k < 9; ++k) g[k] = p == 0 ? h[k] : g[k] + h[k];
+        }
+        if (!__any(c)) continue;     // no lane of the wave blends it
         wave_totals(g);
         if (lane == 63) {
 #pragma unroll
           for (int k = 0; k < 9; ++k) glw[f * 9 + k] = g[k];
         }
       } else {
-        double e[3];
-        float o[4];
-        const bool contrib = pos < q.last && tri_eval(s, rlx, rly, direct, e, o) > 0;
-        if (contrib) {
-          float cr, cg, cbl;
-          tri_colour(s, e, cr, cg, cbl);
-          const float alpha = __uint_as_float(s[30]);
-          if (direct) {
-            q.Tr = (pos == q.last - 1) ? q.Tterm : q.Tr / (1.0f - alpha);
-            q.B0 = fmaf(alpha, cr - q.B0, q.B0);
-            q.B1 = fmaf(alpha, cg - q.B1, q.B1);
-            q.B2 = fmaf(alpha, cbl - q.B2, q.B2);
-          } else {
-            if (!q.in_ent) {
-              q.in_ent = true;
-              q.term_ent = (pos == q.last - 1);
-              q.s0[0] = q.s1[0] = q.s2[0] = q.s3[0] = q.B0;
-              q.s0[1] = q.s1[1] = q.s2[1] = q.s3[1] = q.B1;
-              q.s0[2] = q.s1[2] = q.s2[2] = q.s3[2] = q.B2;
-              q.p0 = q.p1 = q.p2 = q.p3 = 1.0f;
-            }
-            const float a0 = o[0] * alpha, a1 = o[1] * alpha, a2 = o[2] * alpha, a3 = o[3] * alpha;
-            q.s0[0] = fmaf(a0, cr - q.s0[0], q.s0[0]); q.s0[1] = fmaf(a0, cg - q.s0[1], q.s0[1]); q.s0[2] = fmaf(a0, cbl - q.s0[2], q.s0[2]);
-            q.s1[0] = fmaf(a1, cr - q.s1[0], q.s1[0]); q.s1[1] = fmaf(a1, cg - q.s1[1], q.s1[1]); q.s1[2] = fmaf(a1, cbl - q.s1[2], q.s1[2]);
-            q.s2[0] = fmaf(a2, cr - q.s2[0], q.s2[0]); q.s2[1] = fmaf(a2, cg - q.s2[1], q.s2[1]); q.s2[2] = fmaf(a2, cbl - q.s2[2], q.s2[2]);
-            q.s3[0] = fmaf(a3, cr - q.s3[0], q.s3[0]); q.s3[1] = fmaf(a3, cg - q.s3[1], q.s3[1]); q.s3[2] = fmaf(a3, cbl - q.s3[2], q.s3[2]);
-            q.p0 *= 1.0f - a0; q.p1 *= 1.0f - a1; q.p2 *= 1.0f - a2; q.p3 *= 1.0f - a3;
-          }
-        }
+#pragma unroll
+        for (int p = 0; p < PPT; ++p) tri_bwd(s, pos, rlx, rly[p], direct, q[p]);
       }
     }
     __syncthreads();
-    for (int f = tid; f < bn; f += NT) {
+    for (int f = tid; f < bn; f += NTH) {
       const uint32_t *s = slots + f * kSlotWords;
       if ((s[31] & 1u) != 0u) continue;
       float *dst = g2d + 9 * (int64_t)s[9];
@@ -274,7 +308,7 @@ __global__ __launch_bounds__(TW *TH) void blend_backward_kernel(
       for (int k = 0; k < 9; ++k) {
         float r = 0.0f;
 #pragma unroll
-        for (int w = 0; w < NT / 64; ++w) r += gl[w * batch * 9 + f * 9 + k];
+        for (int w = 0; w < NW; ++w) r += gl[w * batch * 9 + f * 9 + k];
         if (r != 0.0f) unsafeAtomicAdd(dst + k, r);
       }
     }
@@ -541,19 +575,20 @@ __global__ void project_backward_kernel(const ViewParams *__restrict__ views, in
   for (int k = 0; k < nc * 3; ++k) put(&d_sh[(int64_t)i * nc * 3 + k], dshv[k]);
 }
 
-template <int TW, int TH>
+template <int TW, int TH, int PPT>
 hipError_t launch_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int32_t *nc, const float *Te) {
   // the backward's own LDS batch (fragments and per-wave partial sums), at
-  // most 128 fragments: 128 x (32 + 36) words = 34 KB for 16x16 tiles
+  // most 128 fragments: 128 x (32 + 9 x waves) words
+  constexpr int NW = TW * TH / PPT / 64;
   const int batch = std::min(c->frag_batch, 128);
-  const size_t lds = (size_t)batch * (kSlotWords + 9 * (TW * TH / 64)) * sizeof(uint32_t);
+  const size_t lds = (size_t)batch * (kSlotWords + 9 * NW) * sizeof(uint32_t);
   ScopedTimer t(c, K_BLEND_BWD);
-  hipLaunchKernelGGL((blend_backward_kernel<TW, TH>), dim3((unsigned)c->n_tiles), dim3(TW * TH), lds,
-                     c->stream, c->cur_views, c->V, c->N, c->T, c->mode,
+  hipLaunchKernelGGL((blend_backward_kernel<TW, TH, PPT>), dim3((unsigned)c->n_tiles),
+                     dim3(TW * TH / PPT), lds, c->stream, c->cur_views, c->V, c->N, c->T, c->mode,
                      batch, c->bg[0], c->bg[1], c->bg[2], (const uint2 *)c->ranges.p,
                      (const uint32_t *)c->v0.p, (const uint32_t *)c->v1.p,
-                     (const FrameInfo *)c->finfo.p, (const GaussRec *)c->grec.p, (const TriRec *)c->trec.p, dL, Tf, nc, Te,
-                     (float *)c->g2d.p);
+                     (const FrameInfo *)c->finfo.p, (const GaussRec *)c->grec.p,
+                     (const TriRec *)c->trec.p, dL, Tf, nc, Te, (float *)c->g2d.p);
   return hipGetLastError();
 }
 
@@ -569,9 +604,9 @@ hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32
   hipError_t e = launch_fill_u32(c, (uint32_t *)c->g2d.p, 9 * (int64_t)c->V * c->N, 0u);
   if (e != hipSuccess) return e;
   if (c->n_tiles > 0) {
-    if (c->tile_w == 16 && c->tile_h == 16) e = launch_bwd_tw<16, 16>(c, dL, Tf, nc, Te);
-    else if (c->tile_w == 8 && c->tile_h == 8) e = launch_bwd_tw<8, 8>(c, dL, Tf, nc, Te);
-    else e = launch_bwd_tw<32, 8>(c, dL, Tf, nc, Te);
+    if (c->tile_w == 16 && c->tile_h == 16) e = launch_bwd_tw<16, 16, 2>(c, dL, Tf, nc, Te);
+    else if (c->tile_w == 8 && c->tile_h == 8) e = launch_bwd_tw<8, 8, 1>(c, dL, Tf, nc, Te);
+    else e = launch_bwd_tw<32, 8, 2>(c, dL, Tf, nc, Te);
     if (e != hipSuccess) return e;
   }
   if (c->N == 0) return hipSuccess;

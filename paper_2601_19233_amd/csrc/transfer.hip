@@ -354,13 +354,28 @@ __global__ void transfer1_kernel(int N, const float4 *__restrict__ vtab,
 constexpr int kT8Threads = 256;
 constexpr int kT8Gauss = kT8Threads / 8;
 
+// Sum over the 8 lanes of each aligned lane group, left in every lane of the
+// group: swap neighbours, swap pairs, mirror half-rows (DPP, vector ALU).
+__device__ __forceinline__ float group8_sum(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));
+  return v;
+}
+
+// Value of lane (this lane + J) within the 16-lane row (row_shl:J); for the
+// first lane of an 8-lane group that is corner J of the same Gaussian.
+template <int J>
+__device__ __forceinline__ float from_lane_plus(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + J, 0xF, 0xF, true));
+}
+
 __global__ __launch_bounds__(kT8Threads) void transfer8_kernel(
     int N, const float4 *__restrict__ vtab, const int32_t *__restrict__ faces,
     const int32_t *__restrict__ bind_face, const float *__restrict__ bind_bary,
     const float *__restrict__ means, const float *__restrict__ quats,
     const float *__restrict__ scales, float *__restrict__ means_out,
     float *__restrict__ quats_out, float *__restrict__ cov3d_out, float *__restrict__ xform_out) {
-  __shared__ float sums[kT8Gauss][12];
   const int tid = threadIdx.x, grp = tid >> 3, k = tid & 7;
   const int i = blockIdx.x * kT8Gauss + grp;
   float3 d = make_float3(0.f, 0.f, 0.f);
@@ -369,37 +384,23 @@ __global__ __launch_bounds__(kT8Threads) void transfer8_kernel(
     const int64_t b = 8 * (int64_t)i + k;
     corner_terms(vtab, faces, bind_face[b], bind_bary[2 * b], bind_bary[2 * b + 1], d, r, S);
   }
-  // r, S: sum over the 8 lanes of the group
+  // r, S: sum over the 8 lanes of the group (every lane of the wave takes part)
 #pragma unroll
-  for (int o = 1; o < 8; o <<= 1) {
+  for (int j = 0; j < 3; ++j) r[j] = group8_sum(r[j]);
 #pragma unroll
-    for (int j = 0; j < 3; ++j) r[j] += __shfl_xor(r[j], o, 8);
-#pragma unroll
-    for (int j = 0; j < 6; ++j) S[j] += __shfl_xor(S[j], o, 8);
-  }
-  // Delta: ((D0 + D1) + D2) + ... in corner order
+  for (int j = 0; j < 6; ++j) S[j] = group8_sum(S[j]);
+  // Delta in the group's first lane: ((D0 + D1) + D2) + ... in corner order
   float3 ds = d;
-#pragma unroll
-  for (int j = 1; j < 8; ++j) {
-    const float3 dj = make_float3(__shfl(d.x, j, 8), __shfl(d.y, j, 8), __shfl(d.z, j, 8));
-    if (j == 1) ds = make_float3(__shfl(d.x, 0, 8), __shfl(d.y, 0, 8), __shfl(d.z, 0, 8));
-    ds = add3(ds, dj);
-  }
-  if (k == 0) {
-    sums[grp][0] = ds.x; sums[grp][1] = ds.y; sums[grp][2] = ds.z;
-    sums[grp][3] = r[0]; sums[grp][4] = r[1]; sums[grp][5] = r[2];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) sums[grp][6 + j] = S[j];
-  }
-  __syncthreads();
-  if (tid < kT8Gauss) {
-    const int g = blockIdx.x * kT8Gauss + tid;
-    if (g < N) {
-      const float *q = sums[tid];
-      finish_gaussian(g, make_float3(q[0], q[1], q[2]), q + 3, q + 6, 0.125f, means, quats, scales,
-                      means_out, quats_out, cov3d_out, xform_out);
-    }
-  }
+  ds = add3(ds, make_float3(from_lane_plus<1>(d.x), from_lane_plus<1>(d.y), from_lane_plus<1>(d.z)));
+  ds = add3(ds, make_float3(from_lane_plus<2>(d.x), from_lane_plus<2>(d.y), from_lane_plus<2>(d.z)));
+  ds = add3(ds, make_float3(from_lane_plus<3>(d.x), from_lane_plus<3>(d.y), from_lane_plus<3>(d.z)));
+  ds = add3(ds, make_float3(from_lane_plus<4>(d.x), from_lane_plus<4>(d.y), from_lane_plus<4>(d.z)));
+  ds = add3(ds, make_float3(from_lane_plus<5>(d.x), from_lane_plus<5>(d.y), from_lane_plus<5>(d.z)));
+  ds = add3(ds, make_float3(from_lane_plus<6>(d.x), from_lane_plus<6>(d.y), from_lane_plus<6>(d.z)));
+  ds = add3(ds, make_float3(from_lane_plus<7>(d.x), from_lane_plus<7>(d.y), from_lane_plus<7>(d.z)));
+  if (k == 0 && i < N)
+    finish_gaussian(i, ds, r, S, 0.125f, means, quats, scales, means_out, quats_out, cov3d_out,
+                    xform_out);
 }
 
 }  // namespace
