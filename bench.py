@@ -298,6 +298,7 @@ def main():
     ap.add_argument("--res-scale", type=float, default=1.0)
     ap.add_argument("--tile", default="16x16")
     ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--schedule", type=int, default=0, help="blend schedule: 0 tile grid, 1 persistent")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -332,7 +333,7 @@ def main():
     tw, th = (int(x) for x in args.tile.split("x"))
     dev = torch.device("cuda:0")
     r = Rasterizer("cuda:0", tile=(tw, th), frag_batch=args.batch, sh_degree=scene.sh_degree,
-                   k_bind=scene.bind_face.shape[1])
+                   k_bind=scene.bind_face.shape[1], schedule=args.schedule)
     f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(dev)
     V_def = f32(scene.proxy.V_def)
     bface = torch.from_numpy(scene.bind_face.astype(np.int32)).to(dev)
@@ -456,7 +457,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": scene.name, "width": cam.width, "height": cam.height,
                    "gaussians": scene.N, "triangles": scene.T, "k_bind": int(scene.bind_face.shape[1]),
-                   "tile": args.tile, "frag_batch": args.batch, "path": "plain forward"},
+                   "tile": args.tile, "frag_batch": args.batch,
+                   "schedule": ["tile_grid", "persistent"][args.schedule], "path": "plain forward"},
         "n_dup": n_dup, "stages_ms": stages, "roofline": roof, "rooflines": rooflines,
         "wall_s": round(wall, 3),
         "fwd_bwd": fwd_bwd, "backward_800": bwd800, "batched": batched, "batched_uneven": uneven,

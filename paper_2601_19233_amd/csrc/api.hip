@@ -406,6 +406,7 @@ umgs_status umgs_bin(umgs_ctx *ctx) {
   hipError_t e = launch_depth_order(c);
   if (e != hipSuccess) return hip_check(c, e, "depth order launch");
   c->sort_passes = radix_passes(c->tile_bits);
+  c->key16 = c->n_tiles <= 65536;
   if (c->fixed_cap) {
     // sizes stay on the device; every sort-stage grid covers the capacity
     if (ensure_keys(c, c->key_cap) != UMGS_OK) return UMGS_ERR_CAPACITY;

@@ -191,7 +191,8 @@ struct EmitArgs {
   const FrameInfo *fi;
   const uint32_t *blk_first;   // per block: the (depth-order) record holding its first position,
                                // then one entry: the record holding the last position
-  uint32_t *keys_out, *vals_out;
+  void *keys_out;              // K (uint16_t or uint32_t) global tile ids
+  uint32_t *vals_out;
 };
 
 // For every emit block, the record (in depth order) that holds the block's
@@ -259,7 +260,9 @@ __device__ __forceinline__ uint32_t block_scan_lds(uint32_t *vals, int n, uint32
   return total;
 }
 
+template <typename K>
 __global__ __launch_bounds__(kEmitThreads) void emit_balanced_kernel(EmitArgs e) {
+  K *const keys_out = (K *)e.keys_out;
   // staged records
   __shared__ uint32_t s_rec[kEmitRecCap];        // record id
   __shared__ int32_t s_off[kEmitRecCap];         // first output position, relative to d0
@@ -364,14 +367,18 @@ __global__ __launch_bounds__(kEmitThreads) void emit_balanced_kernel(EmitArgs e)
       }
       const uint64_t d = d0 + (uint64_t)p0;
       if (d + kEmitPer <= d1) {
+        union { uint4 v[kEmitPer * sizeof(K) / 16]; K k[kEmitPer]; } ku;
 #pragma unroll
-        for (int j = 0; j < kEmitPer; j += 4) {
-          *(uint4 *)(e.keys_out + d + j) = make_uint4(kk[j], kk[j + 1], kk[j + 2], kk[j + 3]);
+        for (int j = 0; j < kEmitPer; ++j) ku.k[j] = (K)kk[j];
+#pragma unroll
+        for (int j = 0; j < (int)(kEmitPer * sizeof(K) / 16); ++j)
+          *((uint4 *)(keys_out + d) + j) = ku.v[j];
+#pragma unroll
+        for (int j = 0; j < kEmitPer; j += 4)
           *(uint4 *)(e.vals_out + d + j) = make_uint4(vv[j], vv[j + 1], vv[j + 2], vv[j + 3]);
-        }
       } else {
         for (int j = 0; j < kEmitPer && d + j < d1; ++j) {
-          e.keys_out[d + j] = kk[j];
+          keys_out[d + j] = (K)kk[j];
           e.vals_out[d + j] = vv[j];
         }
       }
@@ -404,7 +411,7 @@ __global__ __launch_bounds__(kEmitThreads) void emit_balanced_kernel(EmitArgs e)
       }
       ty = clampi(ty, ty0, ty1 - 1);
       const int tx = clampi(a + (int)min(j, 0xFFFFu), tx0, tx1 - 1);
-      e.keys_out[d] = global_tile(e, r, ty, tx);
+      keys_out[d] = (K)global_tile(e, r, ty, tx);
       e.vals_out[d] = r;
     }
   }
@@ -426,24 +433,19 @@ __global__ void frame_info_kernel(const uint64_t *__restrict__ total, uint64_t c
   fi->queue = 0u;
 }
 
-// Tile ranges from the sorted tile ids: 4 consecutive ids per thread (one
-// 16-byte load), a range starts or ends where the id changes.
-__global__ void tile_ranges_kernel(const uint32_t *__restrict__ k0, const uint32_t *__restrict__ k1,
+// Tile ranges from the sorted tile ids: 4 consecutive ids per thread, a
+// range starts or ends where the id changes.
+template <typename K>
+__global__ void tile_ranges_kernel(const K *__restrict__ k0, const K *__restrict__ k1,
                                    const FrameInfo *__restrict__ fi, uint2 *__restrict__ ranges) {
   const uint64_t i0 = 4 * ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
   const uint64_t n = fi->n_dup;
   if (i0 >= n) return;
-  const uint32_t *keys = fi->sorted_in ? k1 : k0;
+  const K *keys = fi->sorted_in ? k1 : k0;
   uint32_t k[5];
-  if (i0 + 4 <= n) {
-    const uint4 q = *(const uint4 *)(keys + i0);
-    k[0] = q.x; k[1] = q.y; k[2] = q.z; k[3] = q.w;
-  } else {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) k[j] = i0 + j < n ? keys[i0 + j] : 0xFFFFFFFFu;
-  }
-  k[4] = i0 + 4 < n ? keys[i0 + 4] : 0xFFFFFFFFu;
-  uint32_t prev = i0 > 0 ? keys[i0 - 1] : 0xFFFFFFFFu;
+  for (int j = 0; j < 5; ++j) k[j] = i0 + j < n ? (uint32_t)keys[i0 + j] : 0xFFFFFFFFu;
+  uint32_t prev = i0 > 0 ? (uint32_t)keys[i0 - 1] : 0xFFFFFFFFu;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const uint64_t i = i0 + j;
@@ -456,13 +458,14 @@ __global__ void tile_ranges_kernel(const uint32_t *__restrict__ k0, const uint32
 }
 
 // Sorted pairs in the exported (tile << 32 | depth key bits) form.
-__global__ void expand_keys_kernel(const uint32_t *__restrict__ k0, const uint32_t *__restrict__ k1,
+template <typename K>
+__global__ void expand_keys_kernel(const K *__restrict__ k0, const K *__restrict__ k1,
                                    const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1,
                                    const uint32_t *__restrict__ depth,
                                    const FrameInfo *__restrict__ fi, uint64_t *__restrict__ out) {
   const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= fi->n_dup) return;
-  const uint32_t t = (fi->sorted_in ? k1 : k0)[i];
+  const uint32_t t = (uint32_t)(fi->sorted_in ? k1 : k0)[i];
   const uint32_t r = (fi->sorted_in ? v1 : v0)[i];
   out[i] = ((uint64_t)t << 32) | (uint64_t)depth[r];
 }
@@ -562,38 +565,59 @@ hipError_t launch_emit_keys(Ctx *c) {
   a.grec = (const GaussRec *)c->grec.p;
   a.fi = (const FrameInfo *)c->finfo.p;
   a.blk_first = (const uint32_t *)c->blk_first.p;
-  a.keys_out = (uint32_t *)c->k0.p;
+  a.keys_out = c->k0.p;
   a.vals_out = (uint32_t *)c->v0.p;
-  hipLaunchKernelGGL(emit_balanced_kernel, dim3(nblocks), dim3(kEmitThreads), 0, c->stream, a);
+  if (c->key16)
+    hipLaunchKernelGGL(emit_balanced_kernel<uint16_t>, dim3(nblocks), dim3(kEmitThreads), 0,
+                       c->stream, a);
+  else
+    hipLaunchKernelGGL(emit_balanced_kernel<uint32_t>, dim3(nblocks), dim3(kEmitThreads), 0,
+                       c->stream, a);
   return hipGetLastError();
 }
 
 // Duplicates by global tile id: radix passes over the tile bits, element
 // count read on the device.
 hipError_t launch_tile_sort(Ctx *c) {
-  uint32_t *k[2] = {(uint32_t *)c->k0.p, (uint32_t *)c->k1.p};
   uint32_t *v[2] = {(uint32_t *)c->v0.p, (uint32_t *)c->v1.p};
-  return launch_radix_sort_u32(c, k, v, c->n_launch, &((const FrameInfo *)c->finfo.p)->n_dup,
-                               nullptr, c->tile_bits, K_SORT_UPSWEEP, K_SORT_SCAN,
-                               K_SORT_DOWNSWEEP);
+  const uint32_t *n_dev = &((const FrameInfo *)c->finfo.p)->n_dup;
+  if (c->key16) {
+    uint16_t *k[2] = {(uint16_t *)c->k0.p, (uint16_t *)c->k1.p};
+    return launch_radix_sort_u16(c, k, v, c->n_launch, n_dev, c->tile_bits, K_SORT_UPSWEEP,
+                                 K_SORT_SCAN, K_SORT_DOWNSWEEP);
+  }
+  uint32_t *k[2] = {(uint32_t *)c->k0.p, (uint32_t *)c->k1.p};
+  return launch_radix_sort_u32(c, k, v, c->n_launch, n_dev, nullptr, c->tile_bits, K_SORT_UPSWEEP,
+                               K_SORT_SCAN, K_SORT_DOWNSWEEP);
 }
 
 hipError_t launch_tile_ranges(Ctx *c) {
   ScopedTimer t(c, K_RANGES);
   hipError_t e = launch_fill_u32(c, (uint32_t *)c->ranges.p, 2 * c->n_tiles, 0u);
   if (e != hipSuccess || c->n_launch == 0) return e;
-  hipLaunchKernelGGL(tile_ranges_kernel, dim3(ceil_div(c->n_launch, 1024)), dim3(256), 0, c->stream,
-                     (const uint32_t *)c->k0.p, (const uint32_t *)c->k1.p,
-                     (const FrameInfo *)c->finfo.p, (uint2 *)c->ranges.p);
+  if (c->key16)
+    hipLaunchKernelGGL(tile_ranges_kernel<uint16_t>, dim3(ceil_div(c->n_launch, 1024)), dim3(256),
+                       0, c->stream, (const uint16_t *)c->k0.p, (const uint16_t *)c->k1.p,
+                       (const FrameInfo *)c->finfo.p, (uint2 *)c->ranges.p);
+  else
+    hipLaunchKernelGGL(tile_ranges_kernel<uint32_t>, dim3(ceil_div(c->n_launch, 1024)), dim3(256),
+                       0, c->stream, (const uint32_t *)c->k0.p, (const uint32_t *)c->k1.p,
+                       (const FrameInfo *)c->finfo.p, (uint2 *)c->ranges.p);
   return hipGetLastError();
 }
 
 hipError_t launch_expand_keys(Ctx *c, uint64_t *dst) {
   if (c->n_launch == 0) return hipSuccess;
-  hipLaunchKernelGGL(expand_keys_kernel, dim3(ceil_div(c->n_launch, 256)), dim3(256), 0, c->stream,
-                     (const uint32_t *)c->k0.p, (const uint32_t *)c->k1.p,
-                     (const uint32_t *)c->v0.p, (const uint32_t *)c->v1.p,
-                     (const uint32_t *)c->keys.p, (const FrameInfo *)c->finfo.p, dst);
+  if (c->key16)
+    hipLaunchKernelGGL(expand_keys_kernel<uint16_t>, dim3(ceil_div(c->n_launch, 256)), dim3(256), 0,
+                       c->stream, (const uint16_t *)c->k0.p, (const uint16_t *)c->k1.p,
+                       (const uint32_t *)c->v0.p, (const uint32_t *)c->v1.p,
+                       (const uint32_t *)c->keys.p, (const FrameInfo *)c->finfo.p, dst);
+  else
+    hipLaunchKernelGGL(expand_keys_kernel<uint32_t>, dim3(ceil_div(c->n_launch, 256)), dim3(256), 0,
+                       c->stream, (const uint32_t *)c->k0.p, (const uint32_t *)c->k1.p,
+                       (const uint32_t *)c->v0.p, (const uint32_t *)c->v1.p,
+                       (const uint32_t *)c->keys.p, (const FrameInfo *)c->finfo.p, dst);
   return hipGetLastError();
 }
 

@@ -109,11 +109,13 @@ __device__ __forceinline__ void blend_tile(
         for (int k = 0; k < kUnroll; ++k) {
           if (COUNT) n_gp += done ? 0u : 1u;
           const bool take = !done && ok[k];
-          const float test_T = Tr * (1.0f - al[k]);
-          const bool stop = take && test_T < kTStop;
-          const bool blend = take && !stop;
+          const float wk = Tr * al[k];
+          const float test_T = Tr - wk;     // T (1 - alpha)
+          const bool below = test_T < kTStop;
+          const bool stop = take && below;
+          const bool blend = take && !below;
           done = done || stop;
-          const float w = blend ? Tr * al[k] : 0.0f;
+          const float w = blend ? wk : 0.0f;
           C0 = fmaf(w, cr[k], C0);
           C1 = fmaf(w, cg[k], C1);
           C2 = fmaf(w, cb[k], C2);
@@ -131,9 +133,9 @@ __device__ __forceinline__ void blend_tile(
         const uint32_t *s = slots + f * kSlotWords;
         float alpha, G, dx, dy;
         if (!gauss_eval(s, pcx, pcy, alpha, G, dx, dy)) continue;
-        const float test_T = Tr * (1.0f - alpha);
-        if (test_T < kTStop) { done = true; continue; }
         const float w = Tr * alpha;
+        const float test_T = Tr - w;
+        if (test_T < kTStop) { done = true; continue; }
         C0 = fmaf(w, __uint_as_float(s[6]), C0);
         C1 = fmaf(w, __uint_as_float(s[7]), C1);
         C2 = fmaf(w, __uint_as_float(s[8]), C2);
@@ -156,9 +158,9 @@ __device__ __forceinline__ void blend_tile(
         if ((tag & 1u) == 0u) {
           float alpha, G, dx, dy;
           if (!gauss_eval(s, pcx, pcy, alpha, G, dx, dy)) continue;
-          const float test_T = Tr * (1.0f - alpha);
-          if (test_T < kTStop) { done = true; continue; }
           const float w = Tr * alpha;
+          const float test_T = Tr - w;
+          if (test_T < kTStop) { done = true; continue; }
           C0 = fmaf(w, __uint_as_float(s[6]), C0);
           C1 = fmaf(w, __uint_as_float(s[7]), C1);
           C2 = fmaf(w, __uint_as_float(s[8]), C2);
@@ -177,7 +179,7 @@ __device__ __forceinline__ void blend_tile(
             const float w = Tr * alpha;
             C0 = fmaf(w, cr, C0); C1 = fmaf(w, cg, C1); C2 = fmaf(w, cbl, C2);
             Tent = Tr;
-            Tr = Tr * (1.0f - alpha);
+            Tr = Tr - w;
             last = pos;
             if (Tr < kTStop) done = true;
             continue;
@@ -341,10 +343,12 @@ hipError_t launch_tw(Ctx *c, BlendArgs a, bool persistent, unsigned long long *p
   }
   ScopedTimer t(c, K_BLEND);
   if (persistent) {
+    // enough workgroups to fill every CU (LDS and registers allow several per
+    // CU); workgroups that find the queue drained exit at once
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, blend_persistent_kernel<TW, TH>,
-                                                     TW * TH, lds) != hipSuccess || per_cu < 1)
-      per_cu = 1;
+                                                     TW * TH, lds) != hipSuccess || per_cu < 8)
+      per_cu = 8;
     const uint64_t grid = std::min<uint64_t>((uint64_t)c->num_cu * per_cu, (uint64_t)c->n_tiles);
     hipLaunchKernelGGL((blend_persistent_kernel<TW, TH>), dim3((unsigned)grid), dim3(TW * TH), lds,
                        c->stream, a);

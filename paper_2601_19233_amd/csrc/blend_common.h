@@ -50,6 +50,13 @@ __device__ __forceinline__ void stage_tri(uint32_t *s, const TriRec &tr, int64_t
   s[31] = 1u | (tr.owned << 8);
 }
 
+// power = qa dx^2 + qb dx dy + qc dy^2, evaluated as (qa dx + qb dy) dx +
+// qc dy^2 (5 operations); every kernel takes its decisions from this one
+// expression.
+__device__ __forceinline__ float gauss_power(float qa, float qb, float qc, float dx, float dy) {
+  return fmaf(fmaf(qa, dx, qb * dy), dx, qc * (dy * dy));
+}
+
 // Gaussian: power and alpha at the pixel centre.  Returns whether the
 // fragment contributes (power <= 0 and alpha >= 1/255).
 __device__ __forceinline__ bool gauss_eval(const uint32_t *s, float pcx, float pcy, float &alpha,
@@ -58,7 +65,7 @@ __device__ __forceinline__ bool gauss_eval(const uint32_t *s, float pcx, float p
   const float4 b = *(const float4 *)(s + 4);
   dx = a.x - pcx;
   dy = a.y - pcy;
-  const float power = fmaf(a.z, dx * dx, fmaf(a.w, dx * dy, b.x * (dy * dy)));
+  const float power = gauss_power(a.z, a.w, b.x, dx, dy);
   if (power > 0.0f) return false;
   G = __expf(power);
   alpha = fminf(kAlphaMax, b.y * G);
@@ -73,7 +80,7 @@ __device__ __forceinline__ bool gauss_alpha(const uint32_t *s, float pcx, float 
   const float4 b = *(const float4 *)(s + 4);
   const float dx = a.x - pcx;
   const float dy = a.y - pcy;
-  const float power = fmaf(a.z, dx * dx, fmaf(a.w, dx * dy, b.x * (dy * dy)));
+  const float power = gauss_power(a.z, a.w, b.x, dx, dy);
   alpha = fminf(kAlphaMax, b.y * __expf(power));
   return power <= 0.0f && alpha >= kAlphaMin;
 }
@@ -86,7 +93,7 @@ __device__ __forceinline__ bool gauss_terms(const uint32_t *s, float pcx, float 
   const float4 b = *(const float4 *)(s + 4);
   dx = a.x - pcx;
   dy = a.y - pcy;
-  const float power = fmaf(a.z, dx * dx, fmaf(a.w, dx * dy, b.x * (dy * dy)));
+  const float power = gauss_power(a.z, a.w, b.x, dx, dy);
   const bool inside = power <= 0.0f;
   G = __expf(inside ? power : 0.0f);
   alpha = fminf(kAlphaMax, b.y * G);

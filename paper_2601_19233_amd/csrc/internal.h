@@ -116,6 +116,7 @@ struct Ctx {
   uint64_t n_launch = 0;      // elements the sort-stage grids cover (n_dup, or the capacity)
   int sort_passes = 0;        // radix passes of the tile sort
   int tile_bits = 1;
+  bool key16 = false;         // tile ids fit 16 bits: k0/k1 hold uint16 keys
   DevBuf minmax;       // 2 x kMinMaxSlots uint32: min / max depth-key bits (folded in bin)
   DevBuf finfo;        // FrameInfo (device)
   DevBuf tile_order;   // 64 bucket counters + n_tiles tile ids (persistent blend)
@@ -141,7 +142,7 @@ struct Ctx {
   DevBuf grec;         // V*N GaussRec
   DevBuf trec;         // V*T TriRec
   DevBuf scan_tmp;
-  DevBuf k0, k1;       // n_dup uint32 global tile ids (ping-pong)
+  DevBuf k0, k1;       // n_dup global tile ids, uint16 or uint32 (ping-pong)
   DevBuf v0, v1;       // n_dup uint32 record ids
   DevBuf hist;         // radix per-block histograms
   DevBuf blk_first;    // emit blocks + 1 uint32: first record of each emit block
@@ -182,6 +183,9 @@ hipError_t launch_emit_keys(Ctx *c);
 hipError_t launch_radix_sort_u32(Ctx *c, uint32_t *keys[2], uint32_t *vals[2], uint64_t n_launch,
                                  const uint32_t *n_dev, const int32_t *bits_dev, int bits,
                                  int kid_up, int kid_scan, int kid_down);
+hipError_t launch_radix_sort_u16(Ctx *c, uint16_t *keys[2], uint32_t *vals[2], uint64_t n_launch,
+                                 const uint32_t *n_dev, int bits, int kid_up, int kid_scan,
+                                 int kid_down);
 int radix_passes(int bits);
 size_t radix_hist_bytes(uint64_t n);
 size_t emit_blocks_bytes(uint64_t n);

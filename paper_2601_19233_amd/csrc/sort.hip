@@ -1,8 +1,9 @@
-// Stable LSD radix sort of 32-bit keys with 32-bit values, at most 8 bits a
-// pass.  Two sorts use it: the records by depth key (values: record ids, so
-// equal depths stay in id order), and the duplicates -- emitted in that
-// depth order -- by global tile id, which leaves every tile's list ordered
-// by (depth key, record id).
+// Stable LSD radix sort of 32- or 16-bit keys with 32-bit values, at most 8
+// bits a pass.  Two sorts use it: the records by depth key (values: record
+// ids, so equal depths stay in id order), and the duplicates -- emitted in
+// that depth order -- by global tile id (16-bit keys while a frame has at
+// most 2^16 tiles), which leaves every tile's list ordered by (depth key,
+// record id).
 //
 // Each pass is reduce-then-scan: an upsweep writes per-block digit counts in
 // digit-major order, an exclusive scan turns them into global offsets, and a
@@ -64,8 +65,9 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 // 16 consecutive keys with 16-byte loads and counts them with LDS atomics
 // into its wave's histogram (neighbouring keys -- a record's tiles -- mostly
 // carry different digits, so lanes rarely collide on an address).
-__global__ __launch_bounds__(kThreads) void rs_upsweep(const uint32_t *__restrict__ keys,
-                                                       PassArgs a, uint32_t *__restrict__ hist) {
+template <typename K>
+__global__ __launch_bounds__(kThreads) void rs_upsweep(const K *__restrict__ keys, PassArgs a,
+                                                       uint32_t *__restrict__ hist) {
   if (pass_through(a)) return;
   const uint32_t n = pass_count(a);
   __shared__ uint32_t h[kWaves][kBins];
@@ -74,27 +76,28 @@ __global__ __launch_bounds__(kThreads) void rs_upsweep(const uint32_t *__restric
   __syncthreads();
   const uint32_t blk = xcd_block(blockIdx.x, a.nblocks);
   const uint32_t i0 = blk * kTile + tid * kRounds;
-  uint32_t key[kRounds];
+  constexpr int kPerLoad = 16 / sizeof(K);
   if (i0 + kRounds <= n) {
 #pragma unroll
-    for (int q = 0; q < kRounds / 4; ++q) {
-      const uint4 v = *(const uint4 *)(keys + i0 + 4 * q);
-      key[4 * q] = v.x; key[4 * q + 1] = v.y; key[4 * q + 2] = v.z; key[4 * q + 3] = v.w;
-    }
+    for (int q = 0; q < kRounds / kPerLoad; ++q) {
+      union { uint4 v; K k[kPerLoad]; } u;
+      u.v = *(const uint4 *)(keys + i0 + kPerLoad * q);
 #pragma unroll
-    for (int r = 0; r < kRounds; ++r) atomicAdd(&h[w][(key[r] >> a.shift) & a.mask], 1u);
+      for (int j = 0; j < kPerLoad; ++j) atomicAdd(&h[w][((uint32_t)u.k[j] >> a.shift) & a.mask], 1u);
+    }
   } else {
     for (int r = 0; r < kRounds; ++r)
-      if (i0 + r < n) atomicAdd(&h[w][(keys[i0 + r] >> a.shift) & a.mask], 1u);
+      if (i0 + r < n) atomicAdd(&h[w][((uint32_t)keys[i0 + r] >> a.shift) & a.mask], 1u);
   }
   __syncthreads();
   const uint32_t s = h[0][tid] + h[1][tid] + h[2][tid] + h[3][tid];
   hist[(uint64_t)tid * a.nblocks + blk] = s;
 }
 
+template <typename K>
 __global__ __launch_bounds__(kThreads) void rs_downsweep(
-    const uint32_t *__restrict__ kin, const uint32_t *__restrict__ vin,
-    uint32_t *__restrict__ kout, uint32_t *__restrict__ vout, PassArgs a,
+    const K *__restrict__ kin, const uint32_t *__restrict__ vin,
+    K *__restrict__ kout, uint32_t *__restrict__ vout, PassArgs a,
     const uint32_t *__restrict__ offs) {
   const uint32_t n = pass_count(a);
   const uint32_t blk = xcd_block(blockIdx.x, a.nblocks);
@@ -109,7 +112,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
     }
     return;
   }
-  __shared__ uint32_t sk[kTile];
+  __shared__ K sk[kTile];
   __shared__ uint32_t sv[kTile];
   __shared__ uint32_t wcnt[kWaves][kBins];
   __shared__ uint32_t lstart[kBins];
@@ -121,20 +124,20 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
 
   const uint32_t wbase = base + w * (kRounds * 64);
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  uint32_t key[kRounds];
+  K key[kRounds];
   uint32_t val[kRounds];
   uint32_t rank[kRounds];   // digit | (rank within the wave) << 8
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const uint32_t idx = wbase + r * 64 + lane;
     const bool valid = idx < n;
-    key[r] = valid ? kin[idx] : 0u;
+    key[r] = valid ? kin[idx] : K(0);
     val[r] = valid ? vin[idx] : 0u;
   }
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
     const bool valid = wbase + r * 64 + lane < n;
-    const uint32_t d = (key[r] >> a.shift) & a.mask;
+    const uint32_t d = ((uint32_t)key[r] >> a.shift) & a.mask;
     const uint64_t m = digit_peers(d, valid);
     const uint32_t before = (uint32_t)__popcll(m & lt);
     const uint32_t prev = wcnt[w][d];
@@ -183,8 +186,8 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
 
   const uint32_t cnt = min((uint32_t)kTile, n - base);
   for (uint32_t i = tid; i < cnt; i += kThreads) {
-    const uint32_t k = sk[i];
-    const uint32_t d = (k >> a.shift) & a.mask;
+    const K k = sk[i];
+    const uint32_t d = ((uint32_t)k >> a.shift) & a.mask;
     const uint32_t o = gbase[d] + (i - lstart[d]);
     kout[o] = k;
     vout[o] = sv[i];
@@ -206,9 +209,10 @@ int radix_passes(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
 // and bits_dev (if not null) the significant bits, both read on the device.
 // The passes split the bits evenly (13 bits: 7 + 6), which keeps the digit
 // runs that the downsweep writes long.
-hipError_t launch_radix_sort_u32(Ctx *c, uint32_t *keys[2], uint32_t *vals[2], uint64_t n_launch,
-                                 const uint32_t *n_dev, const int32_t *bits_dev, int bits,
-                                 int kid_up, int kid_scan, int kid_down) {
+template <typename K>
+hipError_t launch_radix_sort(Ctx *c, K *keys[2], uint32_t *vals[2], uint64_t n_launch,
+                             const uint32_t *n_dev, const int32_t *bits_dev, int bits, int kid_up,
+                             int kid_scan, int kid_down) {
   if (n_launch == 0 || bits <= 0) return hipSuccess;
   const uint32_t n = (uint32_t)n_launch;
   const uint32_t nb = (n + kTile - 1) / kTile;
@@ -228,8 +232,8 @@ hipError_t launch_radix_sort_u32(Ctx *c, uint32_t *keys[2], uint32_t *vals[2], u
     hipError_t e;
     {
       ScopedTimer t(c, kid_up);
-      hipLaunchKernelGGL(rs_upsweep, dim3(nb), dim3(kThreads), 0, c->stream,
-                         (const uint32_t *)keys[src], a, hist);
+      hipLaunchKernelGGL(rs_upsweep<K>, dim3(nb), dim3(kThreads), 0, c->stream,
+                         (const K *)keys[src], a, hist);
       e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -240,15 +244,29 @@ hipError_t launch_radix_sort_u32(Ctx *c, uint32_t *keys[2], uint32_t *vals[2], u
     if (e != hipSuccess) return e;
     {
       ScopedTimer t(c, kid_down);
-      hipLaunchKernelGGL(rs_downsweep, dim3(nb), dim3(kThreads), 0, c->stream,
-                         (const uint32_t *)keys[src], (const uint32_t *)vals[src], keys[dst],
-                         vals[dst], a, (const uint32_t *)hist);
+      hipLaunchKernelGGL(rs_downsweep<K>, dim3(nb), dim3(kThreads), 0, c->stream,
+                         (const K *)keys[src], (const uint32_t *)vals[src], keys[dst], vals[dst], a,
+                         (const uint32_t *)hist);
       e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
     shift += pb;
   }
   return hipSuccess;
+}
+
+hipError_t launch_radix_sort_u32(Ctx *c, uint32_t *keys[2], uint32_t *vals[2], uint64_t n_launch,
+                                 const uint32_t *n_dev, const int32_t *bits_dev, int bits,
+                                 int kid_up, int kid_scan, int kid_down) {
+  return launch_radix_sort<uint32_t>(c, keys, vals, n_launch, n_dev, bits_dev, bits, kid_up,
+                                     kid_scan, kid_down);
+}
+
+hipError_t launch_radix_sort_u16(Ctx *c, uint16_t *keys[2], uint32_t *vals[2], uint64_t n_launch,
+                                 const uint32_t *n_dev, int bits, int kid_up, int kid_scan,
+                                 int kid_down) {
+  return launch_radix_sort<uint16_t>(c, keys, vals, n_launch, n_dev, nullptr, bits, kid_up,
+                                     kid_scan, kid_down);
 }
 
 }  // namespace umgs

@@ -376,6 +376,7 @@ __global__ __launch_bounds__(kT8Threads) void transfer8_kernel(
     const float *__restrict__ means, const float *__restrict__ quats,
     const float *__restrict__ scales, float *__restrict__ means_out,
     float *__restrict__ quats_out, float *__restrict__ cov3d_out, float *__restrict__ xform_out) {
+  __shared__ float sums[kT8Gauss][12];
   const int tid = threadIdx.x, grp = tid >> 3, k = tid & 7;
   const int i = blockIdx.x * kT8Gauss + grp;
   float3 d = make_float3(0.f, 0.f, 0.f);
@@ -398,9 +399,23 @@ __global__ __launch_bounds__(kT8Threads) void transfer8_kernel(
   ds = add3(ds, make_float3(from_lane_plus<5>(d.x), from_lane_plus<5>(d.y), from_lane_plus<5>(d.z)));
   ds = add3(ds, make_float3(from_lane_plus<6>(d.x), from_lane_plus<6>(d.y), from_lane_plus<6>(d.z)));
   ds = add3(ds, make_float3(from_lane_plus<7>(d.x), from_lane_plus<7>(d.y), from_lane_plus<7>(d.z)));
-  if (k == 0 && i < N)
-    finish_gaussian(i, ds, r, S, 0.125f, means, quats, scales, means_out, quats_out, cov3d_out,
-                    xform_out);
+  // the group sums go through LDS so that one wave finishes 32 Gaussians
+  // with every lane busy
+  if (k == 0) {
+    sums[grp][0] = ds.x; sums[grp][1] = ds.y; sums[grp][2] = ds.z;
+    sums[grp][3] = r[0]; sums[grp][4] = r[1]; sums[grp][5] = r[2];
+#pragma unroll
+    for (int j = 0; j < 6; ++j) sums[grp][6 + j] = S[j];
+  }
+  __syncthreads();
+  if (tid < kT8Gauss) {
+    const int g = blockIdx.x * kT8Gauss + tid;
+    if (g < N) {
+      const float *q = sums[tid];
+      finish_gaussian(g, make_float3(q[0], q[1], q[2]), q + 3, q + 6, 0.125f, means, quats, scales,
+                      means_out, quats_out, cov3d_out, xform_out);
+    }
+  }
 }
 
 }  // namespace

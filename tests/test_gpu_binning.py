@@ -85,3 +85,43 @@ def test_tile_lists_hold_every_contributing_pair(gpu, tile, kind):
     px = [(x, y) for y in range(0, cam.height, 3) for x in range(0, cam.width, 3)]
     res = PT.compare_pixels(fr, img, Tf, None, px)
     assert res["ambiguous"] < 0.02 * len(px)
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_per_pixel_order_is_oracle_contributor_order(gpu, tile):
+    """Every pixel's front-to-back list on the GPU -- its tile's sorted list
+    restricted to the fragments that contribute at the pixel -- is the
+    oracle's contributor order, (FP32 key, global id), bit for bit; and the
+    fragments the GPU blended are the oracle's blended prefix."""
+    import torch
+    from paper_2601_19233_amd import _lib as L
+    from paper_2601_19233_amd.render import Rasterizer, scene_inputs
+    s = scenes.make_config(0)
+    cam = s.cams[0]
+    note(f"per-pixel order tile={tile}")
+    r = Rasterizer("cuda:0", tile=tile, sh_degree=s.sh_degree)
+    out = r.render([cam], **scene_inputs(s))
+    torch.cuda.synchronize()
+    vals = r.copy_state(L.STATE_SORTED_VALS).cpu().numpy().view(np.uint32).astype(np.int64)
+    rg = r.copy_state(L.STATE_RANGES).cpu().numpy().astype(np.int64)
+    nc = r.split_views(out["n_contrib"], 1)[0].cpu().numpy()
+    fr = PT.oracle_frame(s, cam)
+    tw, th = tile
+    ntx = (cam.width + tw - 1) // tw
+    checked = 0
+    for py in range(0, cam.height, 2):
+        for px in range(0, cam.width, 2):
+            p = fr.pixel(px, py)
+            if p.ambiguous:
+                continue
+            t = (py // th) * ntx + px // tw
+            lst = vals[rg[t, 0]:rg[t, 1]]
+            want = set(p.contributors)
+            got = [int(g) for g in lst if int(g) in want]
+            assert got == list(p.contributors), (px, py)
+            # the blended prefix ends at the GPU's last blended position
+            blended_gpu = [int(g) for g in lst[: nc[py, px]] if int(g) in want]
+            assert blended_gpu == list(p.order), (px, py)
+            checked += 1
+    assert checked > 800
+    note(f"per-pixel order {tile}: {checked} pixels")
