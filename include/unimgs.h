@@ -168,6 +168,27 @@ umgs_status umgs_sort(umgs_ctx *ctx);
 umgs_status umgs_blend(umgs_ctx *ctx, float *image, float *T_final, int32_t *n_contrib,
                        float *T_entity_in);
 
+/* Batched frame of V views (Section 3.2's renderer over many views at
+ * once): umgs_project, umgs_bin, umgs_sort and umgs_blend in one call, the
+ * blend with the persistent longest-list-first schedule, which evens out
+ * views of very different size.  view_offsets [host, V + 1 entries; NULL =
+ * views packed in order] places view v's pixels at element view_offsets[v]
+ * of the per-pixel outputs (and at 3 x that of image, whose views are
+ * (3,H,W) blocks); view v must end at or before view_offsets[v + 1], and
+ * view_offsets[V] is the outputs' length in pixels.  Elements between views
+ * are not written.  The other arguments are those of umgs_project and
+ * umgs_blend.  Like every call it may be captured into a graph between
+ * umgs_graph_begin and umgs_graph_end (after umgs_reserve).  Errors: those
+ * of the four calls; INVALID_ARG, before any launch, for offsets that
+ * decrease or let views overlap or overrun view_offsets[V]. */
+umgs_status umgs_render_batched(umgs_ctx *ctx, int32_t V, const umgs_camera *cams,
+                                const int64_t *view_offsets, int32_t N, const float *means,
+                                const float *cov3d, const float *scales, const float *quats,
+                                const float *opacity, const float *sh, int32_t T,
+                                const float *tri_xyz, const float *tri_rgb, const float *tri_alpha,
+                                float *image, float *T_final, int32_t *n_contrib,
+                                float *T_entity_in);
+
 /* ---- backward (gradients through the blend of Section 3.2) ----------------- */
 
 /* Gradients of a loss L with respect to the Gaussians of the last blended

@@ -46,6 +46,8 @@ PROTOTYPES = {
     "umgs_bin": (C.c_int, [P]),
     "umgs_sort": (C.c_int, [P]),
     "umgs_blend": (C.c_int, [P, P, P, P, P]),
+    "umgs_render_batched": (C.c_int, [P, I32, C.POINTER(Camera), C.POINTER(I64), I32, P, P, P, P, P,
+                                      P, I32, P, P, P, P, P, P, P]),
     "umgs_query": (C.c_int, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I32)]),
     "umgs_reserve": (C.c_int, [P, I64]),
     "umgs_blend_pairs": (C.c_int, [P, P, C.POINTER(I64)]),

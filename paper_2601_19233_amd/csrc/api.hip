@@ -277,9 +277,21 @@ static umgs_status build_views(Ctx *c, int32_t V, const umgs_camera *cams,
     p.tile_base = (uint32_t)tiles;
     p.pad0 = 0;
     p.pix_base = pix;
+    if (c->view_offsets) {
+      // caller-placed views: increasing, non-overlapping pixel ranges
+      const int64_t off = c->view_offsets[v];
+      if (off < pix)
+        return fail(c, UMGS_ERR_INVALID_ARG, "view %d offset %lld overlaps the previous view", v,
+                    (long long)off);
+      p.pix_base = off;
+      pix = off;
+    }
     tiles += (int64_t)p.ntx * p.nty;
     pix += (int64_t)cm.width * cm.height;
   }
+  if (c->view_offsets && pix > c->view_offsets[V])
+    return fail(c, UMGS_ERR_INVALID_ARG, "last view ends at %lld, past view_offsets[V] = %lld",
+                (long long)pix, (long long)c->view_offsets[V]);
   if (tiles >= (1LL << 31)) return fail(c, UMGS_ERR_CAPACITY, "%lld tiles", (long long)tiles);
   return UMGS_OK;
 }
@@ -455,6 +467,29 @@ umgs_status umgs_blend(umgs_ctx *ctx, float *image, float *T_final, int32_t *n_c
   if (!image) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_blend: NULL image");
   umgs_status s = hip_check(c, launch_blend(c, image, T_final, n_contrib, T_entity_in), "blend launch");
   if (s == UMGS_OK) c->stage = 4;
+  return s;
+}
+
+umgs_status umgs_render_batched(umgs_ctx *ctx, int32_t V, const umgs_camera *cams,
+                                const int64_t *view_offsets, int32_t N, const float *means,
+                                const float *cov3d, const float *scales, const float *quats,
+                                const float *opacity, const float *sh, int32_t T,
+                                const float *tri_xyz, const float *tri_rgb, const float *tri_alpha,
+                                float *image, float *T_final, int32_t *n_contrib,
+                                float *T_entity_in) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (!image) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_render_batched: NULL image");
+  c->view_offsets = view_offsets;
+  umgs_status s = umgs_project(ctx, V, cams, N, means, cov3d, scales, quats, opacity, sh, T,
+                               tri_xyz, tri_rgb, tri_alpha);
+  c->view_offsets = nullptr;
+  if (s != UMGS_OK) return s;
+  if ((s = umgs_bin(ctx)) != UMGS_OK || (s = umgs_sort(ctx)) != UMGS_OK) return s;
+  const int32_t sched = c->opt.schedule;
+  c->opt.schedule = UMGS_SCHEDULE_PERSISTENT;
+  s = umgs_blend(ctx, image, T_final, n_contrib, T_entity_in);
+  c->opt.schedule = sched;
   return s;
 }
 
@@ -640,7 +675,10 @@ umgs_status umgs_update_views(umgs_ctx *ctx, int32_t V, const umgs_camera *old_c
       return fail(c, UMGS_ERR_INVALID_ARG, "umgs_update_views: view %d changed size", v);
   for (size_t k = 0; k < c->view_sets.size(); ++k) {
     std::vector<ViewParams> &t = c->view_sets[k];
-    if ((int)t.size() != V || memcmp(t.data(), oldv.data(), sizeof(ViewParams) * V) != 0) continue;
+    if ((int)t.size() != V) continue;
+    // a table keeps its pixel placement (packed, or the caller's offsets)
+    for (int v = 0; v < V; ++v) oldv[v].pix_base = newv[v].pix_base = t[v].pix_base;
+    if (memcmp(t.data(), oldv.data(), sizeof(ViewParams) * V) != 0) continue;
     t = newv;
     ViewParams *dv = (ViewParams *)c->d_views.p + c->view_set_off[k];
     if (dv == c->cur_views) c->views = newv;

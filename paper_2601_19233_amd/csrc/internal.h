@@ -117,6 +117,7 @@ struct Ctx {
   int sort_passes = 0;        // radix passes of the tile sort
   int tile_bits = 1;
   bool key16 = false;         // tile ids fit 16 bits: k0/k1 hold uint16 keys
+  const int64_t *view_offsets = nullptr;   // caller's per-view pixel offsets (render_batched)
   DevBuf minmax;       // 2 x kMinMaxSlots uint32: min / max depth-key bits (folded in bin)
   DevBuf finfo;        // FrameInfo (device)
   DevBuf tile_order;   // 64 bucket counters + n_tiles tile ids (persistent blend)

@@ -165,8 +165,10 @@ class Rasterizer:
         return out
 
     # ---- forward ------------------------------------------------------------
-    def project(self, cams: Sequence, means=None, opacity=None, sh=None, scales=None, quats=None,
-                cov3d=None, tri_xyz=None, tri_rgb=None, tri_alpha=None):
+    def _scene_args(self, means=None, opacity=None, sh=None, scales=None, quats=None, cov3d=None,
+                    tri_xyz=None, tri_rgb=None, tri_alpha=None):
+        """Device float32 copies of the scene arrays, checked against the sizes
+        the kernels read (N Gaussians, T triangles)."""
         d = self.device
         means, opacity, sh, scales, quats, cov3d = (_f32(x, d) for x in (means, opacity, sh, scales, quats, cov3d))
         tri_xyz, tri_rgb, tri_alpha = (_f32(x, d) for x in (tri_xyz, tri_rgb, tri_alpha))
@@ -175,6 +177,10 @@ class Rasterizer:
         nc = 3 * (self.opts.sh_degree + 1) ** 2
         if N and (sh is None or sh.numel() != N * nc):
             raise ValueError(f"sh must hold {nc} floats per Gaussian for sh_degree {self.opts.sh_degree}")
+        if N and opacity is None:
+            raise ValueError("opacity is required")
+        if N and cov3d is None and (scales is None or quats is None):
+            raise ValueError("give cov3d, or scales and quats")
         for name, t, w in (("means", means, 3), ("opacity", opacity, 1), ("scales", scales, 3),
                            ("quats", quats, 4), ("cov3d", cov3d, 6)):
             if N and t is not None and t.numel() != N * w:
@@ -184,6 +190,16 @@ class Rasterizer:
                 raise ValueError(f"{name} must hold {w} floats per triangle")
         if T and tri_xyz.numel() != T * 9:
             raise ValueError("tri_xyz must hold 9 floats per triangle")
+        g = dict(means=means, opacity=opacity, sh=sh, scales=scales, quats=quats, cov3d=cov3d,
+                 tri_xyz=tri_xyz, tri_rgb=tri_rgb, tri_alpha=tri_alpha)
+        return g, N, T
+
+    def project(self, cams: Sequence, means=None, opacity=None, sh=None, scales=None, quats=None,
+                cov3d=None, tri_xyz=None, tri_rgb=None, tri_alpha=None):
+        g, N, T = self._scene_args(means, opacity, sh, scales, quats, cov3d, tri_xyz, tri_rgb, tri_alpha)
+        means, opacity, sh, scales, quats, cov3d = (g[k] for k in ("means", "opacity", "sh", "scales",
+                                                                  "quats", "cov3d"))
+        tri_xyz, tri_rgb, tri_alpha = g["tri_xyz"], g["tri_rgb"], g["tri_alpha"]
         arr = (L.Camera * len(cams))(*[camera_struct(c) for c in cams])
         self._keep = [means, opacity, sh, scales, quats, cov3d, tri_xyz, tri_rgb, tri_alpha]
         with self._on_stream():
@@ -245,6 +261,46 @@ class Rasterizer:
                 _ptr(means), _ptr(scales), _ptr(quats), _ptr(xform), _ptr(sh), _ptr(out["means"]),
                 _ptr(out["scales"]), _ptr(out["quats"]), _ptr(out["opacity"]), _ptr(out["sh"]),
                 1 if accumulate else 0))
+        return out
+
+    def render_batched(self, cams: Sequence, view_offsets: Optional[Sequence[int]] = None,
+                       out: Optional[Dict] = None, **scene) -> Dict[str, torch.Tensor]:
+        """umgs_render_batched: project, bin, sort and blend V views in one
+        call with the persistent blend schedule.  ``view_offsets`` (V + 1
+        pixel offsets: view v starts at element offs[v] of the per-pixel
+        outputs and must end by offs[v + 1]; offs[V] is their length) places
+        each view inside the outputs; by default views are packed in order."""
+        d = self.device
+        g, N, T = self._scene_args(**scene)
+        sizes = [int(c.width) * int(c.height) for c in cams]
+        if view_offsets is None:
+            offs = None
+            npix = sum(sizes)
+        else:
+            offs = [int(o) for o in view_offsets]
+            if len(offs) != len(cams) + 1:
+                raise ValueError("view_offsets needs V + 1 entries")
+            npix = offs[-1]
+        if out is None:
+            out = dict(image=torch.zeros(3 * npix, device=d), T_final=torch.zeros(npix, device=d),
+                       n_contrib=torch.zeros(npix, device=d, dtype=torch.int32),
+                       T_entity_in=torch.zeros(npix, device=d))
+        for name, per in (("image", 3), ("T_final", 1), ("n_contrib", 1), ("T_entity_in", 1)):
+            tt = out.get(name)
+            if tt is not None and (tt.numel() < per * npix or not tt.is_contiguous()):
+                raise ValueError(f"output {name} must be contiguous with at least {per * npix} elements")
+        arr = (L.Camera * len(cams))(*[camera_struct(c) for c in cams])
+        off_arr = (C.c_int64 * len(offs))(*offs) if offs is not None else None
+        self._keep = list(g.values())
+        with self._on_stream():
+            self._check(self.lib.umgs_render_batched(
+                self.h, len(cams), arr, off_arr, N, _ptr(g["means"]), _ptr(g["cov3d"]),
+                _ptr(g["scales"]), _ptr(g["quats"]), _ptr(g["opacity"]), _ptr(g["sh"]), T,
+                _ptr(g["tri_xyz"]), _ptr(g["tri_rgb"]), _ptr(g["tri_alpha"]), _ptr(out["image"]),
+                _ptr(out.get("T_final")), _ptr(out.get("n_contrib")), _ptr(out.get("T_entity_in"))))
+        self.views = [(int(c.width), int(c.height)) for c in cams]
+        self.N, self.T = N, T
+        self.frame_id = getattr(self, "frame_id", 0) + 1
         return out
 
     def render(self, cams, **scene) -> Dict[str, torch.Tensor]:

@@ -95,6 +95,65 @@ def test_persistent_schedule_matches_tile_grid(gpu, tile):
     assert torch.equal(a["T_final"], b["T_final"])
 
 
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8)])
+def test_render_batched_matches_separate_calls(gpu, tile):
+    """umgs_render_batched (one call, persistent blend) gives the frame of
+    project + bin + sort + blend bit for bit, packed or at the caller's
+    view offsets, leaving the gaps between views untouched; a second frame
+    at other cameras reuses the context."""
+    import torch
+    from paper_2601_19233_amd.render import Rasterizer
+    s = scenes.make_config(3, scale=0.01, res_scale=0.15, n_views=5)
+    sc = device_scene(s)
+    cams = s.cams
+    note(f"render_batched tile={tile} views={[(c.width, c.height) for c in cams]}")
+    ref = eager(s, cams, sc, tile=tile, schedule=0)
+    r = Rasterizer("cuda:0", sh_degree=s.sh_degree, tile=tile)
+    packed = r.render_batched(cams, **sc)
+    torch.cuda.synchronize()
+    for k in ("image", "T_final", "n_contrib", "T_entity_in"):
+        assert torch.equal(packed[k], ref[k]), k
+    # caller-placed views with gaps, filled with a sentinel first
+    sizes = [c.width * c.height for c in cams]
+    offs, o = [], 7
+    for n in sizes:
+        offs.append(o)
+        o += n + 13
+    P = o
+    offs.append(P)
+    out = dict(image=torch.full((3 * P,), -7.0, device="cuda:0"),
+               T_final=torch.full((P,), -7.0, device="cuda:0"),
+               n_contrib=torch.full((P,), -7, device="cuda:0", dtype=torch.int32),
+               T_entity_in=torch.full((P,), -7.0, device="cuda:0"))
+    r.render_batched(cams, view_offsets=offs, out=out, **sc)
+    torch.cuda.synchronize()
+    ref_pos = np.cumsum([0] + sizes)
+    covered = np.zeros(P, bool)
+    for v, (off, n) in enumerate(zip(offs[:-1], sizes)):
+        a = int(ref_pos[v])
+        covered[off:off + n] = True
+        for k in ("T_final", "n_contrib", "T_entity_in"):
+            assert torch.equal(out[k][off:off + n], ref[k][a:a + n]), (v, k)
+        assert torch.equal(out["image"][3 * off:3 * (off + n)], ref["image"][3 * a:3 * (a + n)]), v
+    gap = torch.from_numpy(~covered).to("cuda:0")
+    assert bool((out["T_final"][gap] == -7.0).all())
+    assert bool((out["n_contrib"][gap] == -7).all())
+    gap3 = gap.repeat_interleave(3)
+    assert bool((out["image"][gap3] == -7.0).all())
+    # overlapping offsets are refused before any launch
+    with pytest.raises(Exception):
+        r.render_batched(cams[:2], view_offsets=[0, sizes[0] - 1, P], **sc)
+    with pytest.raises(Exception):
+        r.render_batched(cams[:2], view_offsets=[0, sizes[0], sizes[0] + sizes[1] - 1], **sc)
+    # next frame: other cameras, packed
+    cams2 = list(reversed(cams))
+    ref2 = eager(s, cams2, sc, tile=tile, schedule=0)
+    again = r.render_batched(cams2, **sc)
+    torch.cuda.synchronize()
+    assert torch.equal(again["image"], ref2["image"])
+    assert torch.equal(again["n_contrib"], ref2["n_contrib"])
+
+
 def test_reservation_overflow_is_flagged(gpu):
     import torch
     from paper_2601_19233_amd.render import Rasterizer
