@@ -15,7 +15,10 @@ of uneven size (500k Gaussians) in one captured graph with the persistent
 blend against rendering them one by one; and the batched training step -- 16
 views at 1920x1080 of 2M SH-3 Gaussians bound to a deformed 50k-face proxy
 with 200k triangles, one captured graph per step (forward, and forward +
-backward), blend launch autotuned -- against the plain per-view forward.
+backward), blend launch autotuned -- against the plain per-view forward,
+and the same batched step on the 1M-Gaussian scene from 16 orbit cameras.
+Every backward differentiates an L2 loss against the render of perturbed
+parameters.
 
 Prints ONE JSON line (metric, value = forward Mpixels/s, roofline of the
 dominant kernel measured live with HIP events, CPU-oracle baseline).
@@ -81,7 +84,7 @@ def measured_traffic():
     return out
 
 
-def cpu_baseline(scene, budget_pixels=400, seed=0):
+def cpu_baseline(scene, budget_pixels=1200, seed=0):
     """Time the CPU FP64 oracle on a bounded sample of the same frame."""
     from threadpoolctl import threadpool_limits
     from oracle import render as OR
@@ -138,19 +141,35 @@ def timed(fn, steps):
 
 def run_batched(args):
     """16 views at 1920x1080 of a 2M-Gaussian SH-3 scene bound to a deformed
-    50k-face proxy, 200k triangles: rendering the views one by one (eager,
-    forward only) against the batched step captured in one HIP graph
-    (forward, and forward + backward with gradients to every Gaussian
-    parameter), blend launch autotuned."""
+    50k-face proxy, 200k triangles (plus the same step on the 1M-Gaussian
+    1080p scene seen from 16 orbit cameras): rendering the views one by one
+    (eager, forward only) against the batched step captured in one HIP graph
+    (forward, and forward + backward of the L2 loss against the render of
+    perturbed parameters, gradients to every Gaussian parameter), blend
+    launch autotuned."""
+    from paper_2601_19233_amd import scenes
+    t0 = time.time()
+    s = scenes.make_config(4, scale=args.scale, res_scale=args.res_scale)
+    log(f"batched scene {s.name}: N={s.N} T={s.T} views={len(s.cams)} in {time.time() - t0:.1f} s")
+    return batched_leg(s, s.cams, s.name, args)
+
+
+def run_batched_orbit(args, scene):
+    """The 1080p, 1M-Gaussian frame's scene from 16 orbit cameras (direction
+    uniform on the sphere, distance U[2.5, 4]), batched against plain."""
+    from paper_2601_19233_amd import scenes
+    rng = np.random.default_rng(1001)
+    cam0 = scene.cams[0]
+    cams = scenes.orbit_cameras(rng, 16, [(cam0.width, cam0.height)] * 16)
+    return batched_leg(scene, cams, scene.name + "_x16_orbit", args)
+
+
+def batched_leg(s, cams, name, args):
     import torch
     from paper_2601_19233_amd import autotune, scenes
     from paper_2601_19233_amd.batched import BatchedStep
     from paper_2601_19233_amd.render import Rasterizer
     dev = torch.device("cuda:0")
-    t0 = time.time()
-    s = scenes.make_config(4, scale=args.scale, res_scale=args.res_scale)
-    log(f"batched scene {s.name}: N={s.N} T={s.T} views={len(s.cams)} in {time.time() - t0:.1f} s")
-    cams = s.cams
     V = len(cams)
     W, H = cams[0].width, cams[0].height
     sc, deform = device_scene(s, dev)
@@ -187,19 +206,36 @@ def run_batched(args):
     ms_plain = timed(plain_views, steps)
     del rp
     torch.cuda.empty_cache()
-    res = {"workload": s.name, "views": V, "width": W, "height": H, "gaussians": s.N,
+    res = {"workload": name, "views": V, "width": W, "height": H, "gaussians": s.N,
            "triangles": s.T, "sh_degree": s.sh_degree, "tile": "%dx%d" % best["tile"],
            "frag_batch": best["frag_batch"], "schedule": ["tile_grid", "persistent"][best["schedule"]],
            "plain_fwd_views_s": round(V / (ms_plain * 1e-3), 2),
-           "plain_fwd_ms_per_step": round(ms_plain, 3)}
+           "plain_fwd_ms_per_step": round(ms_plain, 3),
+           "loss": "L2 against the batched render of N(0, 0.01)-perturbed parameters"}
+    target = None
     for bwd in (False, True):
         rb = Rasterizer("cuda:0", sh_degree=s.sh_degree, k_bind=k_bind, tile=best["tile"],
                         frag_batch=best["frag_batch"], schedule=best["schedule"], own_stream=True)
         rb.set_proxy(s.proxy.V_rest, s.proxy.faces)
-        step = BatchedStep(rb, cams, sc, deform=deform, backward=bwd)
-        step.prepare()
         if bwd:
-            step.set_loss_gradient(torch.ones_like(step.out["image"]))
+            # target frame: the same step on perturbed parameters, rendered once
+            tsc, _ = device_scene(scenes.perturbed(s, seed=1000 + 4), dev)
+            tstep = BatchedStep(rb, cams, tsc, deform=deform)
+            tstep.prepare()
+            target = tstep()["image"].clone()
+            torch.cuda.synchronize()
+            del tstep, tsc
+            rb.close()
+            rb = Rasterizer("cuda:0", sh_degree=s.sh_degree, k_bind=k_bind, tile=best["tile"],
+                            frag_batch=best["frag_batch"], schedule=best["schedule"], own_stream=True)
+            rb.set_proxy(s.proxy.V_rest, s.proxy.faces)
+        def l2_grad(img, dl, p0, p1):
+            torch.sub(img, target[3 * p0:3 * p1], out=dl)
+            dl.mul_(2.0)
+
+        step = BatchedStep(rb, cams, sc, deform=deform, backward=bwd,
+                           loss_grad=l2_grad if bwd else None)
+        step.prepare()
         ms = timed(step, steps)
         if rb.overflowed():
             raise RuntimeError("batched step overflowed its reserved key capacity")
@@ -209,7 +245,7 @@ def run_batched(args):
         res[f"{key}_ms_per_step"] = round(ms, 3)
         res["n_dup"] = int(step.n_dup_seen)
         res["groups"] = [list(g) for g in step.groups]
-        log(f"batched {key}: {ms:.2f} ms per {V}-view step")
+        log(f"batched {name} {key}: {ms:.2f} ms per {V}-view step")
         del step, rb
         torch.cuda.empty_cache()
     res["fwd_bwd_vs_plain_fwd"] = round(res["fwd_bwd_views_s"] / res["plain_fwd_views_s"], 3)
@@ -414,8 +450,19 @@ def main():
                                           "tile_ranges", "transfer", "project_gaussians") if k in prof}
 
     # ---- forward + backward (plain, eager) ---------------------------------
-    g = torch.Generator(device="cpu").manual_seed(0)
-    dL = torch.randn(3 * npix, generator=g).to(dev)
+    # L2 loss against the frame rendered from N(0, 0.01)-perturbed raw
+    # Gaussian parameters (same deformation, camera and triangles)
+    pert = scenes.perturbed(scene, seed=1000 + 1)
+    pm, pq, ps = f32(pert.means), f32(pert.quats), f32(pert.scales)
+    po, psh = f32(pert.opacity), f32(pert.sh.reshape(scene.N, -1))
+    dtp = r.bind_transfer(V_def, bface, bbary, pm, pq, ps)
+    r.project([cam], means=dtp["means"], cov3d=dtp["cov3d"], opacity=po, sh=psh,
+              tri_xyz=txyz, tri_rgb=trgb, tri_alpha=tal)
+    r.bin()
+    r.sort()
+    target = r.blend(want_state=False)["image"].clone()
+    del pert, pm, pq, ps, po, psh, dtp
+    dL = torch.empty(3 * npix, device=dev)
     fwd_state = {}
 
     def step_fb():
@@ -425,6 +472,8 @@ def main():
         r.bin()
         r.sort()
         o = r.blend(want_state=True)
+        torch.sub(o["image"], target, out=dL)
+        dL.mul_(2.0)
         return r.backward(dL, o, dt["means"], scales, quats, sh, dt["xform"])
 
     for _ in range(args.warmup):
@@ -437,16 +486,19 @@ def main():
     torch.cuda.synchronize()
     ms_fb = e0.elapsed_time(e1) / args.steps
     fwd_bwd = {"mpix_s": round(npix / (ms_fb * 1e-3) / 1e6, 2), "ms_per_step": round(ms_fb, 4),
-               "path": "plain forward + backward (eager), gradients to means/scales/quats/opacity/SH"}
+               "path": "plain forward + backward (eager), gradients to means/scales/quats/opacity/SH",
+               "loss": "L2 against the render of N(0, 0.01)-perturbed raw Gaussian parameters"}
     log(f"fwd+bwd {ms_fb:.3f} ms/step")
 
     del r, fwd_state
     torch.cuda.empty_cache()
-    batched = uneven = bwd800 = None
+    batched = uneven = bwd800 = orbit = None
     if not args.no_batched:
         bwd800 = run_backward_800(args)
         torch.cuda.empty_cache()
         uneven = run_uneven(args)
+        torch.cuda.empty_cache()
+        orbit = run_batched_orbit(args, scene)
         torch.cuda.empty_cache()
         batched = run_batched(args)
 
@@ -461,7 +513,8 @@ def main():
                    "schedule": ["tile_grid", "persistent"][args.schedule], "path": "plain forward"},
         "n_dup": n_dup, "stages_ms": stages, "roofline": roof, "rooflines": rooflines,
         "wall_s": round(wall, 3),
-        "fwd_bwd": fwd_bwd, "backward_800": bwd800, "batched": batched, "batched_uneven": uneven,
+        "fwd_bwd": fwd_bwd, "backward_800": bwd800, "batched": batched,
+        "batched_1080p_x16_orbit": orbit, "batched_uneven": uneven,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

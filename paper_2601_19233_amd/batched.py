@@ -15,7 +15,7 @@ with all sizes read on the device.
 """
 from __future__ import annotations
 
-from typing import Dict, List, Optional, Sequence, Tuple
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 import torch
 
@@ -26,12 +26,20 @@ class BatchedStep:
     def __init__(self, rast: Rasterizer, cams: Sequence, scene: Dict[str, torch.Tensor],
                  deform: Optional[Dict[str, torch.Tensor]] = None, backward: bool = False,
                  headroom: float = 1.25, group_budget: int = 1_500_000_000,
-                 group_tiles: int = 1 << 16):
+                 group_tiles: int = 1 << 16, loss_grad: Optional[Callable] = None):
         """scene: device tensors means, opacity, sh (N, nc*3), scales, quats and
         optionally tri_xyz, tri_rgb, tri_alpha.  deform: V_def, bind_face,
         bind_bary (the proxy must already be set on ``rast``).  ``rast`` must
         own its stream (Rasterizer(own_stream=True)): the null stream cannot
-        be captured."""
+        be captured.
+
+        With ``backward``, the gradient of the loss with respect to the image
+        is either copied in by set_loss_gradient, or -- with ``loss_grad`` --
+        computed inside the step: ``loss_grad(image, dL, p0, p1)`` is called
+        after each group's blend with that group's image slice, the slice of
+        the dL buffer to fill and the group's pixel range [p0, p1), on the
+        rasterizer's stream; it is captured with the rest, so it must launch
+        device work only (no allocation, no synchronisation)."""
         if rast.stream.cuda_stream == 0:
             raise ValueError("BatchedStep needs a Rasterizer created with own_stream=True")
         self.r = rast
@@ -39,6 +47,7 @@ class BatchedStep:
         self.scene = scene
         self.deform = deform
         self.do_backward = backward
+        self.loss_grad = loss_grad
         self.headroom = headroom
         self.group_budget = int(group_budget)
         self.group_tiles = int(group_tiles)
@@ -122,6 +131,9 @@ class BatchedStep:
                 pm = self.tout["means"] if self.deform is not None else s["means"]
                 xf = self.tout["xform"] if self.deform is not None else None
                 p0, p1 = self.pix0[a], self.pix0[b]
+                if self.loss_grad is not None:
+                    with torch.cuda.stream(r.stream):
+                        self.loss_grad(part["image"], self.dL[3 * p0:3 * p1], p0, p1)
                 self.grads = r.backward(self.dL[3 * p0:3 * p1], part, pm, s["scales"], s["quats"],
                                         s["sh"], xf, out=self.grads, accumulate=gi > 0)
         return self.out

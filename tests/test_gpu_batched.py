@@ -214,6 +214,47 @@ def test_graph_forward_backward_matches_eager(gpu):
         _ = dL.sum().item()
 
 
+def test_loss_gradient_inside_the_graph(gpu):
+    """A loss gradient computed inside the captured step (L2 against a target
+    image, per view group) gives the gradients of the eager forward,
+    dL = 2 (I - I*), backward; replays follow a changed target."""
+    import torch
+    from paper_2601_19233_amd.batched import BatchedStep
+    from paper_2601_19233_amd.render import Rasterizer
+    s = scenes.make_config(0, scale=0.5)
+    sc = device_scene(s)
+    cams = scenes.orbit_cameras(np.random.default_rng(11), 3, [(40, 30), (33, 21), (48, 40)])
+    note("loss gradient in graph")
+    r0 = Rasterizer("cuda:0")
+    ref = r0.render(cams, **sc)
+    g = torch.Generator(device="cpu").manual_seed(2)
+    target = torch.rand(ref["image"].shape, generator=g).to("cuda:0")
+    dL = 2.0 * (ref["image"] - target)
+    gref = r0.backward(dL, ref, sc["means"], sc["scales"], sc["quats"], sc["sh"], None)
+
+    def l2_grad(img, dl, p0, p1):
+        torch.sub(img, target[3 * p0:3 * p1], out=dl)
+        dl.mul_(2.0)
+
+    r = Rasterizer("cuda:0", own_stream=True)
+    step = BatchedStep(r, cams, sc, backward=True, group_budget=1, loss_grad=l2_grad)
+    step.prepare()
+    assert len(step.groups) == 3
+    for k in range(3):
+        out = step()
+        torch.cuda.synchronize()
+        assert torch.equal(out["image"], ref["image"]), k
+        assert torch.equal(step.dL, dL), k
+        for n in ("means", "scales", "quats", "opacity", "sh"):
+            torch.testing.assert_close(step.grads[n], gref[n], rtol=1e-4,
+                                       atol=1e-6 * float(gref[n].abs().max()) + 1e-12)
+        _ = target.sum().item()
+    target.mul_(0.5)
+    out = step()
+    torch.cuda.synchronize()
+    assert torch.equal(step.dL, 2.0 * (ref["image"] - target))
+
+
 def test_view_groups_replay_matches_eager(gpu):
     """A budget below one view's duplicates puts every view in a group of its
     own: the captured step runs project/bin/sort/blend once per group into

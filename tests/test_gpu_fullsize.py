@@ -8,7 +8,8 @@ outputs.
   gradient restricted to those pixels.
 * 800x800, 300k Gaussians with SH degree 3 + 50,176 triangles: sampled pixels.
 * 64 views of uneven size, 500k Gaussians (captured graph, persistent
-  schedule): sampled pixels on four views.
+  schedule): sampled pixels on four views, each view bit-identical to its
+  plain per-view frame.
 * 16 views at 1080p, 2M deformed Gaussians with SH degree 3 + 200k
   triangles (captured forward+backward graph): sampled pixels on two views.
 """
@@ -160,7 +161,13 @@ def test_cfg3_batched_graph(gpu):
     out = step()
     torch.cuda.synchronize()
     assert not r.overflowed()
+    rp = Rasterizer("cuda:0", tile=(16, 16), frag_batch=128, schedule=0)
+    imgs = step.split_views(out["image"], 3)
     for v in (0, 17, 40, 63):
+        # the plain per-view frame is bit-identical to the batched one
+        plain = rp.render([s.cams[v]], **sc)
+        torch.cuda.synchronize()
+        assert torch.equal(plain["image"].view_as(imgs[v]), imgs[v]), v
         fr = OR.Frame(s.cams[v], s.means, s.opacity, s.sh, 0, s.tri_xyz, s.tri_rgb, s.tri_alpha,
                       scales=s.scales, quats=s.quats)
         note(f"cfg3 view {v} {s.cams[v].width}x{s.cams[v].height}: "
