@@ -418,11 +418,21 @@ def main():
     g_pairs, t_pairs = bp["gauss"], bp["tri"]
     log(f"blend work: {bp}")
     # algorithmic HBM bytes per launch of the bandwidth-bound kernels
+    # (n1 supertile entries; their ids are 16-bit while a frame has at most
+    # 2^16 supertiles)
+    n_st, n1 = r.query_bins()
+    kb = 2.0 if n_st <= 65536 else 4.0
     algo_bytes = {
-        "sort_downsweep": 16.0 * n_dup,          # read 32-bit tile id + record id, write both
-        "sort_upsweep": 4.0 * n_dup,             # read tile id
-        "emit_keys": 8.0 * n_dup + 20.0 * n_rec, # write tile id + record id; offsets, order, rects
-        "tile_ranges": 4.0 * n_dup + 8.0 * n_tiles,
+        # first level: per record its order, offsets, rectangle and Gaussian
+        # record; per entry its supertile id and record id
+        "emit_keys": 76.0 * n_rec + (kb + 4.0) * n1,
+        "sort_downsweep": 2.0 * (kb + 4.0) * n1,  # read and write id + record id
+        "sort_upsweep": kb * n1,                  # read the ids
+        # second level: per entry its record id, rectangle, Gaussian record
+        # and the mask written
+        "tile_count": (4.0 + 8.0 + 48.0 + 8.0) * n1,
+        # per entry its mask and record id; per duplicate one record id written
+        "tile_scatter": 12.0 * n1 + 4.0 * n_dup,
         "transfer": scene.N * (40.0 + 12.0 * scene.bind_face.shape[1] + 88.0),
         "project_gaussians": scene.N * (12 + 24 + 4 + 12 + 4 + 8 + 8 + 48.0),
     }
@@ -446,8 +456,9 @@ def main():
         return None
 
     roof = roofline(dominant)
-    rooflines = {k: roofline(k) for k in ("sort_downsweep", "sort_upsweep", "emit_keys", "blend",
-                                          "tile_ranges", "transfer", "project_gaussians") if k in prof}
+    rooflines = {k: roofline(k) for k in ("tile_scatter", "tile_count", "sort_downsweep",
+                                          "sort_upsweep", "emit_keys", "blend", "transfer",
+                                          "project_gaussians") if k in prof}
 
     # ---- forward + backward (plain, eager) ---------------------------------
     # L2 loss against the frame rendered from N(0, 0.01)-perturbed raw
@@ -511,7 +522,7 @@ def main():
                    "gaussians": scene.N, "triangles": scene.T, "k_bind": int(scene.bind_face.shape[1]),
                    "tile": args.tile, "frag_batch": args.batch,
                    "schedule": ["tile_grid", "persistent"][args.schedule], "path": "plain forward"},
-        "n_dup": n_dup, "stages_ms": stages, "roofline": roof, "rooflines": rooflines,
+        "n_dup": n_dup, "n_supertile_entries": n1, "stages_ms": stages, "roofline": roof, "rooflines": rooflines,
         "wall_s": round(wall, 3),
         "fwd_bwd": fwd_bwd, "backward_800": bwd800, "batched": batched,
         "batched_1080p_x16_orbit": orbit, "batched_uneven": uneven,

@@ -142,18 +142,24 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
                          int32_t T, const float *tri_xyz, const float *tri_rgb,
                          const float *tri_alpha);
 
-/* Bin: duplicate every projected primitive into each screen tile its support
- * touches, with a key ordering (global tile, depth) and value = record id.
- * Without a reservation it synchronizes the stream once to size the key
- * buffers; after umgs_reserve it does not synchronize, and duplicates beyond
- * the reserved capacity are dropped and flagged (see umgs_query).  Errors:
- * STATE before umgs_project; CAPACITY if the duplicate count reaches
- * 2^32 - 2^16 or a buffer cannot be allocated. */
+/* Bin (first level of the mixed depth sort of Section 3.2): the projected
+ * primitives in (depth key, record id) order, then one (supertile, record)
+ * entry for every supertile -- a block of 8 x 8 tiles -- that the
+ * primitive's support reaches, stably sorted by supertile id, so each
+ * supertile's entries are front to back.  Without a reservation it
+ * synchronizes the stream once to size the buffers of the duplicates (one
+ * per (tile, primitive) pair the support reaches) and of the entries; after
+ * umgs_reserve it does not synchronize, and duplicates or entries beyond the
+ * reserved capacity are dropped and flagged (see umgs_query).  Errors:
+ * STATE before umgs_project; CAPACITY if the duplicate or entry count
+ * reaches 2^32 - 2^16 or a buffer cannot be allocated. */
 umgs_status umgs_bin(umgs_ctx *ctx);
 
-/* Sort the duplicates by key (device LSD radix sort; equal keys keep the
- * ascending-id emission order) and find every tile's [start, end) range.
- * This is the single mixed depth sort of Section 3.2.  Errors: STATE. */
+/* Sort (second level): every tile's list of record ids, front to back --
+ * the order of the (tile, depth key, record id) keys, ties by ascending id --
+ * and every tile's [start, end) range in it.  Each supertile's entries are
+ * split into the tiles they reach by a counting sort, so each duplicate is
+ * written once, to its final place.  Errors: STATE before umgs_bin. */
 umgs_status umgs_sort(umgs_ctx *ctx);
 
 /* Blend every tile front to back (Eq. 1-2 for Gaussians, Eq. 7-9 for
@@ -218,10 +224,12 @@ umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_
 
 /* ---- graphs: capture one step, replay it ----------------------------------- */
 
-/* Reserve key buffers for max_dup duplicates and stop synchronizing in
- * umgs_bin (the sort stages then read the frame's sizes on the device); 0
- * returns to the synchronizing mode.  Call it after one eager frame of the
- * same shape (which sizes every other buffer).  Errors: CAPACITY. */
+/* Reserve the tile lists for max_dup duplicates and stop synchronizing in
+ * umgs_bin (the later stages then read the frame's sizes on the device); 0
+ * returns to the synchronizing mode.  The supertile entries get 1.25 x
+ * max_dup x the entries-per-duplicate ratio of the last eager frame (at
+ * least 2^16, at most max_dup).  Call it after one eager frame of the same
+ * shape (which sizes every other buffer).  Errors: CAPACITY. */
 umgs_status umgs_reserve(umgs_ctx *ctx, int64_t max_dup);
 /* Begin capturing the context stream into a graph: the entry points called
  * until umgs_graph_end are recorded, not run.  Requires a reservation,
@@ -264,6 +272,11 @@ umgs_status umgs_blend_pairs(umgs_ctx *ctx, float *image, int64_t *pairs);
 umgs_status umgs_query(umgs_ctx *ctx, int64_t *n_dup, int64_t *n_tiles, int64_t *n_records,
                        int32_t *overflow);
 
+/* First-level sizes of the last binned frame: supertiles (blocks of 8 x 8
+ * tiles over all views) and (supertile, primitive) entries.  Synchronizes
+ * the stream.  Errors: STATE before umgs_bin or while capturing. */
+umgs_status umgs_query_bins(umgs_ctx *ctx, int64_t *n_supertiles, int64_t *n_entries);
+
 /* Copy internal per-frame state into caller memory [device] (for tests):
  *   UMGS_STATE_KEYS    n_records uint32 depth-key bits (0xFFFFFFFF = culled)
  *   UMGS_STATE_SORTED_KEYS  n_dup uint64 sorted keys
@@ -289,7 +302,8 @@ umgs_status umgs_copy_state(umgs_ctx *ctx, int32_t which, void *dst, int64_t cap
 enum { UMGS_K_VERTEX_FRAMES = 0, UMGS_K_TRANSFER = 1, UMGS_K_PROJECT = 2, UMGS_K_TRIANGLES = 3,
        UMGS_K_SCAN = 4, UMGS_K_EMIT = 5, UMGS_K_SORT_UPSWEEP = 6, UMGS_K_SORT_SCAN = 7,
        UMGS_K_SORT_DOWNSWEEP = 8, UMGS_K_RANGES = 9, UMGS_K_BLEND = 10, UMGS_K_BLEND_BWD = 11,
-       UMGS_K_PROJECT_BWD = 12, UMGS_K_DEPTH_SORT = 13, UMGS_K_COUNT = 14 };
+       UMGS_K_PROJECT_BWD = 12, UMGS_K_DEPTH_SORT = 13, UMGS_K_TILE_COUNT = 14,
+       UMGS_K_TILE_SCATTER = 15, UMGS_K_COUNT = 16 };
 umgs_status umgs_set_profiling(umgs_ctx *ctx, int32_t enable);
 umgs_status umgs_profile_read(umgs_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms);
 

@@ -50,6 +50,7 @@ PROTOTYPES = {
                                       P, I32, P, P, P, P, P, P, P]),
     "umgs_query": (C.c_int, [P, C.POINTER(I64), C.POINTER(I64), C.POINTER(I64), C.POINTER(I32)]),
     "umgs_reserve": (C.c_int, [P, I64]),
+    "umgs_query_bins": (C.c_int, [P, C.POINTER(I64), C.POINTER(I64)]),
     "umgs_blend_pairs": (C.c_int, [P, P, C.POINTER(I64)]),
     "umgs_graph_begin": (C.c_int, [P]),
     "umgs_graph_end": (C.c_int, [P]),
@@ -64,7 +65,7 @@ PROTOTYPES = {
 
 KERNEL_NAMES = ["vertex_frames", "transfer", "project_gaussians", "setup_triangles", "count_scan",
                 "emit_keys", "sort_upsweep", "sort_scan", "sort_downsweep", "tile_ranges", "blend",
-                "blend_backward", "project_backward", "depth_sort"]
+                "blend_backward", "project_backward", "depth_sort", "tile_count", "tile_scatter"]
 
 _lib = None
 

@@ -4,8 +4,8 @@ differentiated) by a captured HIP graph.
 Planning runs once: the deformation transfer and the projection of all views
 give every view's duplicate count (``view_dups``) before anything is sorted;
 consecutive views are grouped so that no group exceeds ``group_budget``
-duplicates (32-bit sort positions, bounded key memory) or ``group_tiles``
-screen tiles (the tile sort's passes grow with the bits of the tile ids).  One eager step then
+duplicates (32-bit list positions, 4 bytes each) or ``group_tiles`` screen
+tiles (2^22 tiles keep supertile ids within 16 bits).  One eager step then
 renders every group (allocating buffers and storing one device view table
 per group), key capacity is reserved for the largest group times
 ``headroom``, and the whole step -- transfer, then per group project, bin,
@@ -25,8 +25,8 @@ from .render import Rasterizer
 class BatchedStep:
     def __init__(self, rast: Rasterizer, cams: Sequence, scene: Dict[str, torch.Tensor],
                  deform: Optional[Dict[str, torch.Tensor]] = None, backward: bool = False,
-                 headroom: float = 1.25, group_budget: int = 1_500_000_000,
-                 group_tiles: int = 1 << 16, loss_grad: Optional[Callable] = None):
+                 headroom: float = 1.25, group_budget: int = 3_000_000_000,
+                 group_tiles: int = 1 << 22, loss_grad: Optional[Callable] = None):
         """scene: device tensors means, opacity, sh (N, nc*3), scales, quats and
         optionally tri_xyz, tri_rgb, tri_alpha.  deform: V_def, bind_face,
         bind_bary (the proxy must already be set on ``rast``).  ``rast`` must
@@ -92,8 +92,7 @@ class BatchedStep:
     # -- planning -----------------------------------------------------------
     def plan(self) -> List[Tuple[int, int]]:
         """Group consecutive views so each group stays within the duplicate
-        budget and within ``group_tiles`` screen tiles (2^16 tiles keep the
-        tile sort at two 8-bit passes)."""
+        budget and within ``group_tiles`` screen tiles."""
         self._transfer()
         dups: List[int] = []
         step = max(1, min(len(self.cams), 64))

@@ -166,9 +166,10 @@ void umgs_destroy(umgs_ctx *ctx) {
   DevBuf *bufs[] = {&c->V_rest, &c->faces, &c->vf_ptr, &c->vf_idx, &c->vtab, &c->d_views,
                     &c->keys, &c->rects, &c->counts, &c->dk[0], &c->dk[1], &c->dv[0],
                     &c->dv[1], &c->offs, &c->grec, &c->trec, &c->scan_tmp,
-                    &c->k0, &c->k1, &c->v0, &c->v1, &c->hist, &c->ranges, &c->g2d,
-                    &c->minmax, &c->finfo, &c->tile_order, &c->pair_count, &c->view_sums,
-                    &c->blk_first};
+                    &c->sk[0], &c->sk[1], &c->sv[0], &c->sv[1], &c->masks, &c->st_rng,
+                    &c->chunk_base, &c->cnt2, &c->tstart, &c->totals,
+                    &c->v0, &c->v1, &c->hist, &c->ranges, &c->g2d,
+                    &c->minmax, &c->finfo, &c->tile_order, &c->pair_count, &c->view_sums};
   for (DevBuf *b : bufs) free_buf(*b);
   for (auto &p : c->prof.pending) {
     (void)hipEventDestroy(p.a);
@@ -254,11 +255,13 @@ umgs_status umgs_bind_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
 }
 
 static umgs_status build_views(Ctx *c, int32_t V, const umgs_camera *cams,
-                               std::vector<ViewParams> &vps, int64_t &tiles, int64_t &pix) {
+                               std::vector<ViewParams> &vps, int64_t &tiles, int64_t &pix,
+                               int64_t *st_total = nullptr) {
   const umgs_options &o = c->opt;
   vps.assign(V, ViewParams());
   tiles = 0;
   pix = 0;
+  int64_t sts = 0;
   for (int v = 0; v < V; ++v) {
     const umgs_camera &cm = cams[v];
     if (cm.width < 1 || cm.height < 1 || cm.width > 16384 || cm.height > 16384)
@@ -275,7 +278,7 @@ static umgs_status build_views(Ctx *c, int32_t V, const umgs_camera *cams,
     p.ntx = (cm.width + o.tile_w - 1) / o.tile_w;
     p.nty = (cm.height + o.tile_h - 1) / o.tile_h;
     p.tile_base = (uint32_t)tiles;
-    p.pad0 = 0;
+    p.st_base = (uint32_t)sts;
     p.pix_base = pix;
     if (c->view_offsets) {
       // caller-placed views: increasing, non-overlapping pixel ranges
@@ -287,8 +290,10 @@ static umgs_status build_views(Ctx *c, int32_t V, const umgs_camera *cams,
       pix = off;
     }
     tiles += (int64_t)p.ntx * p.nty;
+    sts += (int64_t)((p.ntx + kST - 1) / kST) * ((p.nty + kST - 1) / kST);
     pix += (int64_t)cm.width * cm.height;
   }
+  if (st_total) *st_total = sts;
   if (c->view_offsets && pix > c->view_offsets[V])
     return fail(c, UMGS_ERR_INVALID_ARG, "last view ends at %lld, past view_offsets[V] = %lld",
                 (long long)pix, (long long)c->view_offsets[V]);
@@ -313,8 +318,8 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
     return fail(c, UMGS_ERR_CAPACITY, "umgs_project: V*(N+T) = %lld records", (long long)V * (N + T));
   const umgs_options &o = c->opt;
   std::vector<ViewParams> vps;
-  int64_t tiles = 0, pix = 0;
-  umgs_status s = build_views(c, V, cams, vps, tiles, pix);
+  int64_t tiles = 0, pix = 0, sts = 0;
+  umgs_status s = build_views(c, V, cams, vps, tiles, pix, &sts);
   if (s != UMGS_OK) return s;
   // Device view tables are stored once per distinct camera set, so a captured
   // graph can replay frames (or view groups) whose tables were uploaded by
@@ -347,6 +352,10 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
                                                     (int64_t)radix_hist_bytes(std::max<int64_t>(nrec, 1)) / 4})),
                   "scan scratch")) ||
       (s = ensure(c, c->ranges, sizeof(uint2) * tiles, "tile ranges")) ||
+      (s = ensure(c, c->tstart, sizeof(uint32_t) * (tiles + 1), "tile starts")) ||
+      (s = ensure(c, c->st_rng, sizeof(uint2) * sts, "supertile ranges")) ||
+      (s = ensure(c, c->chunk_base, sizeof(uint32_t) * (sts + 1), "supertile chunks")) ||
+      (s = ensure(c, c->totals, 2 * sizeof(uint64_t), "frame totals")) ||
       (s = ensure(c, c->minmax, 2 * kMinMaxSlots * sizeof(uint32_t), "depth range")) ||
       (s = ensure(c, c->finfo, sizeof(FrameInfo), "frame info")) ||
       (s = ensure(c, c->tile_order, sizeof(uint32_t) * (64 + tiles), "tile order")))
@@ -375,9 +384,12 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
   c->n_records = nrec;
   c->n_tiles = tiles;
   c->n_pixels = pix;
+  c->n_st = sts;
+  c->n_st_max = std::max(c->n_st_max, sts);
   int bits = 1;
-  while (bits < 31 && (1LL << bits) < tiles) ++bits;
-  c->tile_bits = bits;
+  while (bits < 31 && (1LL << bits) < sts) ++bits;
+  c->st_bits = bits;
+  c->st_key16 = sts <= 65536;
   c->stage = 0;
   hipError_t e = hipSuccess;
   if (fresh_info) e = launch_fill_u32(c, (uint32_t *)c->finfo.p, sizeof(FrameInfo) / 4, 0u);
@@ -395,15 +407,24 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
   return UMGS_OK;
 }
 
-static umgs_status ensure_keys(Ctx *c, uint64_t n) {
+// Buffers of the tile lists (n duplicates) and of the first binning level
+// (st supertile entries) for the current frame's supertiles.
+static umgs_status ensure_lists(Ctx *c, uint64_t n, uint64_t st) {
   umgs_status s;
   n = std::max<uint64_t>(n, 1);
-  if ((s = ensure(c, c->k0, 4 * n, "keys")) || (s = ensure(c, c->k1, 4 * n, "keys")) ||
-      (s = ensure(c, c->v0, 4 * n, "values")) || (s = ensure(c, c->v1, 4 * n, "values")) ||
-      (s = ensure(c, c->hist, radix_hist_bytes(std::max<uint64_t>(n, c->n_records)), "radix histograms")) ||
-      (s = ensure(c, c->blk_first, emit_blocks_bytes(n), "emit blocks")) ||
+  st = std::max<uint64_t>(st, 1);
+  const int64_t n_st = std::max(c->n_st, c->n_st_max);
+  if ((s = ensure(c, c->v0, 4 * n, "tile lists")) ||
+      (s = ensure(c, c->sk[0], 4 * st, "supertile entries")) ||
+      (s = ensure(c, c->sk[1], 4 * st, "supertile entries")) ||
+      (s = ensure(c, c->sv[0], 4 * st, "supertile entries")) ||
+      (s = ensure(c, c->sv[1], 4 * st, "supertile entries")) ||
+      (s = ensure(c, c->masks, 8 * st, "supertile masks")) ||
+      (s = ensure(c, c->cnt2, 64 * sizeof(uint32_t) * max_chunks(st, n_st), "chunk counts")) ||
+      (s = ensure(c, c->hist, radix_hist_bytes(std::max<uint64_t>(st, c->n_records)), "radix histograms")) ||
       (s = ensure(c, c->scan_tmp,
-                  scan_tmp_bytes(std::max<int64_t>(radix_hist_bytes(n) / 4, c->n_records + 1)),
+                  scan_tmp_bytes(std::max<int64_t>({(int64_t)radix_hist_bytes(st) / 4, c->n_records + 1,
+                                                    c->n_tiles + 1, n_st + 1})),
                   "scan scratch")))
     return s;
   return UMGS_OK;
@@ -417,12 +438,10 @@ umgs_status umgs_bin(umgs_ctx *ctx) {
     return fail(c, UMGS_ERR_STATE, "umgs_bin: capturing without a reservation");
   hipError_t e = launch_depth_order(c);
   if (e != hipSuccess) return hip_check(c, e, "depth order launch");
-  c->sort_passes = radix_passes(c->tile_bits);
-  c->key16 = c->n_tiles <= 65536;
   if (c->fixed_cap) {
-    // sizes stay on the device; every sort-stage grid covers the capacity
-    if (ensure_keys(c, c->key_cap) != UMGS_OK) return UMGS_ERR_CAPACITY;
-    c->n_launch = c->key_cap;
+    // sizes stay on the device; every first-level grid covers the capacity
+    if (ensure_lists(c, c->key_cap, c->st_cap) != UMGS_OK) return UMGS_ERR_CAPACITY;
+    c->st_launch = c->st_cap;
   } else {
     if (!c->host_pinned.p) {
       if ((e = hipHostMalloc(&c->host_pinned.p, 256, hipHostMallocDefault)) != hipSuccess)
@@ -430,20 +449,25 @@ umgs_status umgs_bin(umgs_ctx *ctx) {
       c->host_pinned.cap = 256;
     }
     uint64_t *h = (uint64_t *)c->host_pinned.p;
-    if ((e = hipMemcpyAsync(h, (uint64_t *)c->offs.p + c->n_records, sizeof(uint64_t),
-                            hipMemcpyDeviceToHost, c->stream)) != hipSuccess ||
+    if ((e = hipMemcpyAsync(h, c->totals.p, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                            c->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(c->stream)) != hipSuccess)
       return hip_check(c, e, "duplicate count readback");
-    const uint64_t nd = h[0];
+    const uint64_t nd = h[0], n1 = h[1];
     if (nd >= 0xFFFF0000ull)
       return fail(c, UMGS_ERR_CAPACITY, "umgs_bin: %llu duplicates exceed 2^32", (unsigned long long)nd);
-    umgs_status s = ensure_keys(c, nd);
+    if (n1 >= 0xFFFF0000ull)
+      return fail(c, UMGS_ERR_CAPACITY, "umgs_bin: %llu supertile entries exceed 2^32",
+                  (unsigned long long)n1);
+    umgs_status s = ensure_lists(c, nd, n1);
     if (s != UMGS_OK) return s;
     c->key_cap = std::max<uint64_t>(nd, 1);
+    c->st_cap = std::max<uint64_t>(n1, 1);
     c->n_dup = nd;
-    c->n_launch = nd;
+    c->st_launch = n1;
+    if (nd) c->st_ratio = (double)n1 / (double)nd;
   }
-  if ((e = launch_emit_keys(c)) != hipSuccess) return hip_check(c, e, "emit_keys launch");
+  if ((e = launch_st_bin(c)) != hipSuccess) return hip_check(c, e, "supertile binning launch");
   c->stage = 2;
   return UMGS_OK;
 }
@@ -452,9 +476,8 @@ umgs_status umgs_sort(umgs_ctx *ctx) {
   if (!ctx) return UMGS_ERR_INVALID_ARG;
   Ctx *c = &ctx->c;
   if (c->stage < 2) return fail(c, UMGS_ERR_STATE, "umgs_sort: frame not binned");
-  hipError_t e = launch_tile_sort(c);
-  if (e != hipSuccess) return hip_check(c, e, "tile sort launch");
-  if ((e = launch_tile_ranges(c)) != hipSuccess) return hip_check(c, e, "tile ranges launch");
+  hipError_t e = launch_tile_lists(c);
+  if (e != hipSuccess) return hip_check(c, e, "tile lists launch");
   c->stage = 3;
   return UMGS_OK;
 }
@@ -549,6 +572,19 @@ umgs_status umgs_query(umgs_ctx *ctx, int64_t *n_dup, int64_t *n_tiles, int64_t 
   return UMGS_OK;
 }
 
+umgs_status umgs_query_bins(umgs_ctx *ctx, int64_t *n_supertiles, int64_t *n_entries) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_query_bins: the stream is being captured");
+  if (c->stage < 2) return fail(c, UMGS_ERR_STATE, "umgs_query_bins: frame not binned");
+  FrameInfo fi;
+  umgs_status s = read_frame_info(c, &fi);
+  if (s != UMGS_OK) return s;
+  if (n_supertiles) *n_supertiles = c->n_st;
+  if (n_entries) *n_entries = (int64_t)fi.n1;
+  return UMGS_OK;
+}
+
 umgs_status umgs_copy_state(umgs_ctx *ctx, int32_t which, void *dst, int64_t cap_bytes) {
   if (!ctx) return UMGS_ERR_INVALID_ARG;
   Ctx *c = &ctx->c;
@@ -562,9 +598,9 @@ umgs_status umgs_copy_state(umgs_ctx *ctx, int32_t which, void *dst, int64_t cap
   int need = 1;
   switch (which) {
     case UMGS_STATE_KEYS: src = c->keys.p; bytes = 4 * c->n_records; need = 1; break;
-    case UMGS_STATE_SORTED_KEYS: src = nullptr; bytes = 8 * (int64_t)c->n_dup; need = 3; break;
+    case UMGS_STATE_SORTED_KEYS: src = nullptr; bytes = 8 * (int64_t)fi.n_dup; need = 3; break;
     case UMGS_STATE_GRAD2D: src = c->g2d.p; bytes = 36 * (int64_t)c->V * c->N; need = 4; break;
-    case UMGS_STATE_SORTED_VALS: src = fi.sorted_in ? c->v1.p : c->v0.p; bytes = 4 * (int64_t)c->n_dup; need = 3; break;
+    case UMGS_STATE_SORTED_VALS: src = c->v0.p; bytes = 4 * (int64_t)fi.n_dup; need = 3; break;
     case UMGS_STATE_RANGES: src = c->ranges.p; bytes = 8 * c->n_tiles; need = 3; break;
     case UMGS_STATE_TRI_FIXED: src = c->trec.p; bytes = 24 * (int64_t)c->V * c->T; need = 1; break;
     default: return fail(c, UMGS_ERR_INVALID_ARG, "umgs_copy_state: unknown state %d", which);
@@ -612,9 +648,15 @@ umgs_status umgs_reserve(umgs_ctx *ctx, int64_t max_dup) {
     c->fixed_cap = false;
     return UMGS_OK;
   }
-  umgs_status s = ensure_keys(c, (uint64_t)max_dup);
+  // first-level capacity: the last eager frame's entries per duplicate (a
+  // quarter before any), with 25% headroom
+  const double ratio = c->st_ratio > 0.0 ? c->st_ratio : 0.25;
+  const uint64_t st = std::min<uint64_t>(
+      (uint64_t)max_dup, std::max<uint64_t>((uint64_t)(1.25 * ratio * (double)max_dup) + 1, 1u << 16));
+  umgs_status s = ensure_lists(c, (uint64_t)max_dup, st);
   if (s != UMGS_OK) return s;
   c->key_cap = (uint64_t)max_dup;
+  c->st_cap = st;
   c->fixed_cap = true;
   return UMGS_OK;
 }

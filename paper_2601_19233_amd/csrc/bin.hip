@@ -1,10 +1,21 @@
-// Bin stage.  The records are put in depth order first (a radix sort of
-// 1 key per record), their tile counts scanned in that order, and one
-// (global tile id, record id) pair emitted per overlapped tile at the
-// record's scanned offset.  Duplicates thus leave the bin stage in depth
-// order, and a stable sort by tile id alone (sort.hip) yields every tile's
-// front-to-back list; per-tile [start, end) ranges are then read off the
-// sorted tile ids.
+// Bin and sort stages: every tile's list of the records whose support
+// reaches it, front to back, built as a two-digit MSD counting sort whose
+// digits are the supertile (8 x 8 tiles) and the tile inside it.
+//
+//  1. The records are put in depth order (a radix sort of one key per
+//     record, values = record ids, so equal depths keep id order).
+//  2. First level: every record emits one (supertile, record) entry per
+//     supertile its support reaches, in depth order at its scanned offset,
+//     and a stable radix sort by supertile id (sort.hip) leaves each
+//     supertile's entries front to back.
+//  3. Second level, per chunk of a supertile's entries: each entry's 64-bit
+//     mask of the supertile's tiles its support reaches (the same support
+//     rows the projection counted), per-chunk tile counts, their prefix over
+//     the supertile's chunks and over all tiles, then each entry's record id
+//     written to every tile of its mask at its rank there.
+//
+// No per-duplicate key is ever stored: each duplicate's record id is written
+// once, to its final place, and the tile ranges come out of the tile scan.
 #include "support.h"
 
 namespace umgs {
@@ -102,18 +113,33 @@ hipError_t excl_scan(hipStream_t s, T *data, int64_t n, T *tmp) {
   return hipGetLastError();
 }
 
-// Per-view duplicate totals (records are view-major): one partial sum per
-// block, one atomic per block.
+// Per-view duplicate totals (records are view-major; the low 32 bits of a
+// record's count are its tiles): one partial sum per block, one atomic per
+// block.
 __global__ void view_sum_kernel(const uint64_t *__restrict__ counts, int64_t per_view,
                                 unsigned long long *__restrict__ sums) {
   const int v = blockIdx.y;
   const int64_t i = (int64_t)blockIdx.x * kScanTile;
   uint64_t s = 0;
   for (int k = threadIdx.x; k < kScanTile; k += kScanThreads)
-    if (i + k < per_view) s += counts[(int64_t)v * per_view + i + k];
+    if (i + k < per_view) s += counts[(int64_t)v * per_view + i + k] & 0xFFFFFFFFull;
   uint64_t total;
   block_excl_scan(s, total);
   if (threadIdx.x == 0 && total) atomicAdd(sums + v, (unsigned long long)total);
+}
+
+// Frame totals: duplicates (sum of the view totals) and supertile entries
+// (the scanned entry counts' total).
+__global__ void frame_totals_kernel(const unsigned long long *__restrict__ view_sums, int V,
+                                    const uint64_t *__restrict__ st_total,
+                                    uint64_t *__restrict__ totals) {
+  uint64_t s = 0;
+  for (int v = threadIdx.x; v < V; v += 64) s += view_sums[v];
+  for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+  if (threadIdx.x == 0) {
+    totals[0] = s;
+    totals[1] = *st_total;
+  }
 }
 
 // Depth range of the frame: sort keys hold (depth key - base) in depth_bits.
@@ -141,280 +167,14 @@ __global__ void depth_prep_kernel(const uint32_t *__restrict__ depth, int64_t n,
   dv[r] = (uint32_t)r;
 }
 
-// Tile counts in depth order (the count scan then gives each record's first
-// output position); the entry past the end receives the total.
-__global__ void gather_counts_kernel(const uint32_t *__restrict__ order, int64_t n,
-                                     const uint64_t *__restrict__ counts,
-                                     uint64_t *__restrict__ out) {
+// Supertile-entry counts (high 32 bits of a record's count) in depth order;
+// the entry past the end receives 0, so the scan leaves the total there.
+__global__ void gather_st_counts_kernel(const uint32_t *__restrict__ order, int64_t n,
+                                        const uint64_t *__restrict__ counts,
+                                        uint64_t *__restrict__ out) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) out[i] = counts[order[i]];
+  if (i < n) out[i] = counts[order[i]] >> 32;
   else if (i == n) out[n] = 0;
-}
-
-// Load-balanced emission: each block owns kEmitSpan consecutive output
-// positions and writes them with consecutive lanes on consecutive addresses.
-// Positions follow the depth order of the records; inside a record, its
-// tiles in row-major order, each row cut to the record's support
-// (support.h) exactly as the projection counted them.
-//
-// The block finds the records covering its range by binary search in the
-// scanned offsets and stages them in LDS; one thread per record then lays
-// out the record's tile rows in LDS (first column, first output position),
-// so every lane finds its position's row, hence record and column, by one
-// binary search in LDS.  Output: global tile id (the tile sort's key) and
-// record id.
-constexpr int kEmitThreads = 256;
-constexpr int kEmitPer = 8;
-constexpr int kEmitSpan = kEmitThreads * kEmitPer;
-constexpr int kEmitRecCap = 256;
-constexpr int kEmitRowCap = 1024;
-constexpr int kEmitRowPer = kEmitRowCap / kEmitThreads;
-
-// last r in [lo, hi] with offs[r] <= d (offs is non-decreasing)
-__device__ __forceinline__ int64_t last_record_at(const uint64_t *__restrict__ offs, int64_t lo,
-                                                  int64_t hi, uint64_t d) {
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (offs[mid] <= d) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-struct EmitArgs {
-  const ViewParams *views;
-  int per_view, N, tile_w, tile_h;
-  int64_t n_records;
-  const uint32_t *order;
-  const uint2 *rects;
-  const uint64_t *offs;
-  const GaussRec *grec;
-  const FrameInfo *fi;
-  const uint32_t *blk_first;   // per block: the (depth-order) record holding its first position,
-                               // then one entry: the record holding the last position
-  void *keys_out;              // K (uint16_t or uint32_t) global tile ids
-  uint32_t *vals_out;
-};
-
-// For every emit block, the record (in depth order) that holds the block's
-// first output position, found by the records themselves: record i covers
-// the positions [offs[i], offs[i+1]) and writes its index for each block
-// starting inside that range, so no block searches the offsets.  The
-// record holding the frame's last position is stored after the blocks.
-__global__ void emit_blocks_kernel(const uint64_t *__restrict__ offs, int64_t n_records,
-                                   const FrameInfo *__restrict__ fi, uint32_t nblocks,
-                                   uint32_t *__restrict__ blk_first) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n_records) return;
-  const uint64_t n = fi->n_dup;
-  const uint64_t o0 = offs[i], o1 = min(offs[i + 1], n);
-  if (o0 >= o1) return;
-  const uint64_t b0 = (o0 + kEmitSpan - 1) / kEmitSpan, b1 = (o1 + kEmitSpan - 1) / kEmitSpan;
-  for (uint64_t b = b0; b < b1 && b < nblocks; ++b) blk_first[b] = (uint32_t)i;
-  if (o1 == n) blk_first[nblocks] = (uint32_t)i;
-}
-
-// (clamps keep a tile inside its record's rectangle, hence inside its view,
-// whatever the counts say)
-__device__ __forceinline__ int clampi(int x, int lo, int hi) { return max(lo, min(x, hi)); }
-
-__device__ __forceinline__ uint32_t global_tile(const EmitArgs &e, uint32_t r, int ty, int tx) {
-  const ViewParams &vp = e.views[r / (uint32_t)e.per_view];
-  return vp.tile_base + (uint32_t)ty * (uint32_t)vp.ntx + (uint32_t)tx;
-}
-
-// Block-wide exclusive scan of LDS values [0, n) (n <= per * kEmitThreads,
-// each thread a contiguous chunk of `per`); returns the total.
-template <int PER>
-__device__ __forceinline__ uint32_t block_scan_lds(uint32_t *vals, int n, uint32_t *wsum) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  uint32_t v[PER], sum = 0;
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int q = tid * PER + j;
-    v[j] = q < n ? vals[q] : 0u;
-    sum += v[j];
-  }
-  uint32_t incl = sum;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(incl, o, 64);
-    if (lane >= o) incl += y;
-  }
-  __syncthreads();                       // vals fully read, wsum free
-  if (lane == 63) wsum[w] = incl;
-  __syncthreads();
-  uint32_t base = 0, total = 0;
-#pragma unroll
-  for (int k = 0; k < kEmitThreads / 64; ++k) {
-    if (k < w) base += wsum[k];
-    total += wsum[k];
-  }
-  uint32_t run = base + incl - sum;
-#pragma unroll
-  for (int j = 0; j < PER; ++j) {
-    const int q = tid * PER + j;
-    if (q < n) vals[q] = run;
-    run += v[j];
-  }
-  __syncthreads();
-  return total;
-}
-
-template <typename K>
-__global__ __launch_bounds__(kEmitThreads) void emit_balanced_kernel(EmitArgs e) {
-  K *const keys_out = (K *)e.keys_out;
-  // staged records
-  __shared__ uint32_t s_rec[kEmitRecCap];        // record id
-  __shared__ int32_t s_off[kEmitRecCap];         // first output position, relative to d0
-  __shared__ uint2 s_rect[kEmitRecCap];          // tile rectangle
-  __shared__ uint32_t s_tb[kEmitRecCap];         // global id of its view's tile (0, 0)
-  __shared__ uint32_t s_ntx[kEmitRecCap];        // tiles per row of its view
-  __shared__ int2 s_wh[kEmitRecCap];             // its view's width and height
-  __shared__ Support s_sup[kEmitRecCap];         // support of a Gaussian (exact = false: triangle)
-  __shared__ uint32_t s_row0[kEmitRecCap + 1];   // rows, scanned to the first row slot
-  __shared__ uint32_t s_pbase[kEmitRecCap];      // scanned tile count at the first row slot
-  // row slots: one per tile row of a staged record
-  __shared__ int32_t q_start[kEmitRowCap];       // first output position (relative to d0)
-  __shared__ uint32_t q_tile0[kEmitRowCap];      // global tile id of the row's first tile
-  __shared__ uint16_t q_k[kEmitRowCap];          // staged record index
-  __shared__ uint16_t q_cnt[kEmitRowCap];        // tiles in the row
-  __shared__ uint32_t s_wsum[kEmitThreads / 64];
-  const uint64_t n = e.fi->n_dup;
-  const uint64_t d0 = (uint64_t)blockIdx.x * kEmitSpan;
-  if (d0 >= n) return;
-  const uint64_t d1 = min(d0 + (uint64_t)kEmitSpan, n);
-  const int tid = threadIdx.x;
-  // records [rlo, rhi] cover the block: rhi is the next block's first record
-  // (possibly one record too many, which no position maps to) or, for the
-  // frame's last block, the record holding the last position
-  const int64_t rlo = e.blk_first[blockIdx.x];
-  const int64_t rhi = d1 < n ? (int64_t)e.blk_first[blockIdx.x + 1] : (int64_t)e.blk_first[gridDim.x];
-  const int nr = (int)min<int64_t>(rhi - rlo + 1, (int64_t)kEmitRecCap + 1);
-  int R = kEmitRowCap + 1;
-  if (nr <= kEmitRecCap) {
-    // records (strided over the threads, so their loads overlap)
-    for (int k = tid; k < nr; k += kEmitThreads) {
-      const uint32_t r = e.order[rlo + k];
-      const uint2 rc = e.rects[r];
-      const uint32_t v = r / (uint32_t)e.per_view;
-      const int i = (int)(r - v * (uint32_t)e.per_view);
-      s_rec[k] = r;
-      s_off[k] = (int32_t)((int64_t)e.offs[rlo + k] - (int64_t)d0);
-      s_rect[k] = rc;
-      s_tb[k] = e.views[v].tile_base;
-      s_ntx[k] = (uint32_t)e.views[v].ntx;
-      s_wh[k] = make_int2(e.views[v].W, e.views[v].H);
-      Support sup;
-      sup.exact = false;
-      if (i < e.N) sup = make_support(e.grec[(int64_t)v * e.N + i]);
-      s_sup[k] = sup;
-      s_row0[k] = (rc.y >> 16) - (rc.x >> 16);
-    }
-    __syncthreads();
-    R = (int)block_scan_lds<kEmitRecCap / kEmitThreads>(s_row0, nr, s_wsum);
-    if (tid == 0) s_row0[nr] = (uint32_t)R;
-    __syncthreads();
-  }
-  if (R <= kEmitRowCap) {
-    // row slot -> staged record
-    for (int k = tid; k < nr; k += kEmitThreads)
-      for (uint32_t q = s_row0[k]; q < s_row0[k + 1]; ++q) q_k[q] = (uint16_t)k;
-    __syncthreads();
-    // each row slot's columns (strided), then a block scan of the tile counts
-    for (int q = tid; q < R; q += kEmitThreads) {
-      const int k = q_k[q];
-      const uint2 rc = s_rect[k];
-      const int tx0 = rc.x & 0xFFFF, tx1 = rc.y & 0xFFFF;
-      const int ty = (int)(rc.x >> 16) + (q - (int)s_row0[k]);
-      int a, b;
-      const int2 wh = s_wh[k];
-      support_row(s_sup[k], ty, e.tile_w, e.tile_h, wh.x, wh.y, tx0, tx1, a, b);
-      q_tile0[q] = s_tb[k] + (uint32_t)ty * s_ntx[k] + (uint32_t)a;
-      q_cnt[q] = (uint16_t)(b - a);
-      q_start[q] = b - a;
-    }
-    __syncthreads();
-    block_scan_lds<kEmitRowPer>((uint32_t *)q_start, R, s_wsum);
-    for (int q = tid; q < R; q += kEmitThreads) {
-      const int k = q_k[q];
-      if ((uint32_t)q == s_row0[k]) s_pbase[k] = (uint32_t)q_start[q];
-    }
-    __syncthreads();
-    for (int q = tid; q < R; q += kEmitThreads) {
-      const int k = q_k[q];
-      q_start[q] = s_off[k] + (int32_t)((uint32_t)q_start[q] - s_pbase[k]);
-    }
-    __syncthreads();
-    // each thread writes kEmitPer consecutive positions: one search for the
-    // row slot of its first position (the last slot starting at or before
-    // it; slots without tiles share their start with the next slot, which
-    // the search then picks), then a forward walk, and 16-byte stores
-    const int p0 = tid * kEmitPer;
-    if (d0 + (uint64_t)p0 < d1) {
-      int q = 0, hi = R - 1;
-      while (q < hi) {
-        const int mid = (q + hi + 1) >> 1;
-        if (q_start[mid] <= p0) q = mid; else hi = mid - 1;
-      }
-      uint32_t kk[kEmitPer], vv[kEmitPer];
-#pragma unroll
-      for (int j = 0; j < kEmitPer; ++j) {
-        const int p = p0 + j;
-        while (q + 1 < R && q_start[q + 1] <= p) ++q;
-        const int col = min(p - q_start[q], max((int)q_cnt[q], 1) - 1);
-        kk[j] = q_tile0[q] + (uint32_t)max(col, 0);
-        vv[j] = s_rec[q_k[q]];
-      }
-      const uint64_t d = d0 + (uint64_t)p0;
-      if (d + kEmitPer <= d1) {
-        union { uint4 v[kEmitPer * sizeof(K) / 16]; K k[kEmitPer]; } ku;
-#pragma unroll
-        for (int j = 0; j < kEmitPer; ++j) ku.k[j] = (K)kk[j];
-#pragma unroll
-        for (int j = 0; j < (int)(kEmitPer * sizeof(K) / 16); ++j)
-          *((uint4 *)(keys_out + d) + j) = ku.v[j];
-#pragma unroll
-        for (int j = 0; j < kEmitPer; j += 4)
-          *(uint4 *)(e.vals_out + d + j) = make_uint4(vv[j], vv[j + 1], vv[j + 2], vv[j + 3]);
-      } else {
-        for (int j = 0; j < kEmitPer && d + j < d1; ++j) {
-          keys_out[d + j] = (K)kk[j];
-          e.vals_out[d + j] = vv[j];
-        }
-      }
-    }
-  } else {
-    // more records or rows than LDS holds: search the offsets in memory and
-    // walk the record's rows
-    for (int k = 0; k < kEmitPer; ++k) {
-      const uint64_t d = d0 + (uint64_t)k * kEmitThreads + tid;
-      if (d >= d1) break;
-      const int64_t i = last_record_at(e.offs, rlo, rhi, d);
-      const uint32_t r = e.order[i];
-      const uint2 rc = e.rects[r];
-      uint32_t j = (uint32_t)(d - e.offs[i]);
-      const int ty0 = (int)(rc.x >> 16), ty1 = (int)(rc.y >> 16);
-      const int v = (int)(r / (uint32_t)e.per_view);
-      const int li = (int)(r - (uint32_t)v * (uint32_t)e.per_view);
-      const int tx0 = rc.x & 0xFFFF, tx1 = rc.y & 0xFFFF;
-      const bool gauss = li < e.N;
-      Support sup;
-      if (gauss) sup = make_support(e.grec[(int64_t)v * e.N + li]);
-      const ViewParams &vp = e.views[v];
-      int ty = ty0, a = tx0, b = tx1;
-      for (; ty < ty1; ++ty) {
-        a = tx0;
-        b = tx1;
-        if (gauss) support_row(sup, ty, e.tile_w, e.tile_h, vp.W, vp.H, tx0, tx1, a, b);
-        if (j < (uint32_t)(b - a)) break;
-        j -= (uint32_t)(b - a);
-      }
-      ty = clampi(ty, ty0, ty1 - 1);
-      const int tx = clampi(a + (int)min(j, 0xFFFFu), tx0, tx1 - 1);
-      keys_out[d] = (K)global_tile(e, r, ty, tx);
-      e.vals_out[d] = r;
-    }
-  }
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
@@ -422,26 +182,82 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
   if (i < n) p[i] = v;
 }
 
-// Turns the scanned total into the frame's duplicate count (clamped to the
-// key capacity, overflow flagged) and resets the persistent blend's queue.
-__global__ void frame_info_kernel(const uint64_t *__restrict__ total, uint64_t cap,
-                                  int sorted_in, FrameInfo *__restrict__ fi) {
-  const uint64_t raw = *total;
-  fi->n_dup = (uint32_t)(raw < cap ? raw : cap);
-  if (raw > cap) fi->overflow = 1u;
-  fi->sorted_in = sorted_in;
+// The frame's sizes on the device, each clamped to its buffer's capacity
+// (overflow flagged, sticky), and the persistent blend's queue reset.
+__global__ void frame_info_kernel(const uint64_t *__restrict__ totals, uint64_t cap,
+                                  uint64_t st_cap, FrameInfo *__restrict__ fi) {
+  const uint64_t nd = totals[0], n1 = totals[1];
+  fi->n_dup = (uint32_t)(nd < cap ? nd : cap);
+  fi->n1 = (uint32_t)(n1 < st_cap ? n1 : st_cap);
+  if (nd > cap || n1 > st_cap) fi->overflow = 1u;
+  fi->sorted_in = 0;
   fi->queue = 0u;
 }
 
-// Tile ranges from the sorted tile ids: 4 consecutive ids per thread, a
-// range starts or ends where the id changes.
+// ---- first level: supertile entries -----------------------------------------
+
+struct StEmitArgs {
+  const ViewParams *views;
+  int per_view, N, tile_w, tile_h;
+  int64_t n_records;
+  const uint32_t *order;   // records in depth order
+  const uint2 *rects;
+  const uint64_t *offs;    // scanned entry counts in depth order
+  const GaussRec *grec;
+  const FrameInfo *fi;
+  void *keys;              // K global supertile ids
+  uint32_t *vals;          // record ids
+};
+
+__device__ __forceinline__ void unpack_rect(uint2 rc, int &tx0, int &ty0, int &tx1, int &ty1) {
+  tx0 = rc.x & 0xFFFF;
+  ty0 = rc.x >> 16;
+  tx1 = rc.y & 0xFFFF;
+  ty1 = rc.y >> 16;
+}
+
+// One thread per record (in depth order) writes its supertile entries,
+// supertile rows top to bottom, columns left to right (their order does not
+// matter: a record has at most one entry per supertile).
 template <typename K>
-__global__ void tile_ranges_kernel(const K *__restrict__ k0, const K *__restrict__ k1,
-                                   const FrameInfo *__restrict__ fi, uint2 *__restrict__ ranges) {
+__global__ void st_emit_kernel(StEmitArgs e) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= e.n_records) return;
+  uint64_t pos = e.offs[i];
+  const uint64_t end = min(e.offs[i + 1], (uint64_t)e.fi->n1);
+  if (pos >= end) return;
+  K *keys = (K *)e.keys;
+  const uint32_t r = e.order[i];
+  int tx0, ty0, tx1, ty1;
+  unpack_rect(e.rects[r], tx0, ty0, tx1, ty1);
+  const uint32_t v = r / (uint32_t)e.per_view;
+  const int li = (int)(r - v * (uint32_t)e.per_view);
+  const ViewParams &vp = e.views[v];
+  Support sup;
+  sup.exact = false;
+  if (li < e.N) sup = make_support(e.grec[(int64_t)v * e.N + li]);
+  const uint32_t nstx = (uint32_t)(vp.ntx + kST - 1) >> kSTLog;
+  uint32_t tiles = 0;
+  for (int sy = ty0 >> kSTLog; sy <= (ty1 - 1) >> kSTLog; ++sy) {
+    int lo, hi;
+    st_row_span(sup, sy, tx0, ty0, tx1, ty1, e.tile_w, e.tile_h, vp.W, vp.H, lo, hi, tiles);
+    for (int sx = lo; sx < hi; ++sx) {
+      if (pos >= end) return;
+      keys[pos] = (K)(vp.st_base + (uint32_t)sy * nstx + (uint32_t)sx);
+      e.vals[pos] = r;
+      ++pos;
+    }
+  }
+}
+
+// Per-supertile [start, end) of the sorted entries: 4 consecutive ids per
+// thread, a range starts or ends where the id changes.
+template <typename K>
+__global__ void st_ranges_kernel(const K *__restrict__ keys, const FrameInfo *__restrict__ fi,
+                                 uint2 *__restrict__ rng) {
   const uint64_t i0 = 4 * ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x);
-  const uint64_t n = fi->n_dup;
+  const uint64_t n = fi->n1;
   if (i0 >= n) return;
-  const K *keys = fi->sorted_in ? k1 : k0;
   uint32_t k[5];
 #pragma unroll
   for (int j = 0; j < 5; ++j) k[j] = i0 + j < n ? (uint32_t)keys[i0 + j] : 0xFFFFFFFFu;
@@ -450,24 +266,250 @@ __global__ void tile_ranges_kernel(const K *__restrict__ k0, const K *__restrict
   for (int j = 0; j < 4; ++j) {
     const uint64_t i = i0 + j;
     if (i >= n) break;
-    const uint32_t t = k[j];
-    if (i == 0 || prev != t) ranges[t].x = (uint32_t)i;
-    if (i == n - 1 || k[j + 1] != t) ranges[t].y = (uint32_t)(i + 1);
-    prev = t;
+    const uint32_t s = k[j];
+    if (i == 0 || prev != s) rng[s].x = (uint32_t)i;
+    if (i == n - 1 || k[j + 1] != s) rng[s].y = (uint32_t)(i + 1);
+    prev = s;
   }
 }
 
-// Sorted pairs in the exported (tile << 32 | depth key bits) form.
-template <typename K>
-__global__ void expand_keys_kernel(const K *__restrict__ k0, const K *__restrict__ k1,
-                                   const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1,
-                                   const uint32_t *__restrict__ depth,
-                                   const FrameInfo *__restrict__ fi, uint64_t *__restrict__ out) {
-  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= fi->n_dup) return;
-  const uint32_t t = (uint32_t)(fi->sorted_in ? k1 : k0)[i];
-  const uint32_t r = (fi->sorted_in ? v1 : v0)[i];
-  out[i] = ((uint64_t)t << 32) | (uint64_t)depth[r];
+// ---- second level: tiles inside a supertile ---------------------------------
+
+constexpr int kChunk = 1024;          // entries of one supertile's list per workgroup
+constexpr int kL2Threads = 256;
+constexpr int kL2Waves = kL2Threads / 64;
+
+// Chunks per supertile (the entry past the end receives 0 for the scan).
+__global__ void st_chunks_kernel(const uint2 *__restrict__ rng, int64_t n_st,
+                                 uint32_t *__restrict__ chunk_base) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < n_st) {
+    const uint2 r = rng[s];
+    chunk_base[s] = r.y > r.x ? (r.y - r.x + kChunk - 1) / kChunk : 0u;
+  } else if (s == n_st) {
+    chunk_base[n_st] = 0;
+  }
+}
+
+__global__ void chunk_total_kernel(const uint32_t *__restrict__ chunk_base, int64_t n_st,
+                                   FrameInfo *__restrict__ fi) {
+  fi->n_chunks = chunk_base[n_st];
+}
+
+struct L2Args {
+  const ViewParams *views;
+  int V, per_view, N, tile_w, tile_h;
+  int64_t n_st, n_tiles;
+  const uint2 *st_rng;         // per supertile [start, end) of its sorted entries
+  const uint32_t *chunk_base;  // scanned chunks per supertile (n_st + 1)
+  const uint32_t *rec;         // sorted entries' record ids
+  const uint2 *rects;
+  const GaussRec *grec;
+  const FrameInfo *fi;
+  uint64_t *masks;             // per entry: tiles of its supertile it reaches
+  uint32_t *cnt;               // per chunk 64 tile counts, then their prefix over the chunks
+  uint32_t *tstart;            // per tile: count, then (scanned) first position
+  uint32_t *out;               // record ids in tile order
+};
+
+// The view whose supertiles [st_base, next st_base) hold s.
+__device__ __forceinline__ int view_of_st(const ViewParams *views, int V, uint32_t s) {
+  int lo = 0, hi = V - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (views[mid].st_base <= s) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Chunk c's supertile (the last one whose first chunk is <= c: empty
+// supertiles share their first chunk with the next one) and its entries.
+struct ChunkInfo {
+  uint32_t s, e0, e1;
+  int v, cx0, cy0;   // view, first tile column / row of the supertile
+};
+
+__device__ __forceinline__ ChunkInfo chunk_info(const L2Args &a, uint32_t c) {
+  ChunkInfo ci;
+  int64_t lo = 0, hi = a.n_st - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (a.chunk_base[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  ci.s = (uint32_t)lo;
+  const uint2 r = a.st_rng[lo];
+  ci.e0 = r.x + (c - a.chunk_base[lo]) * (uint32_t)kChunk;
+  ci.e1 = min(ci.e0 + (uint32_t)kChunk, r.y);
+  ci.v = view_of_st(a.views, a.V, ci.s);
+  const ViewParams &vp = a.views[ci.v];
+  const uint32_t sl = ci.s - vp.st_base;
+  const uint32_t nstx = (uint32_t)(vp.ntx + kST - 1) >> kSTLog;
+  ci.cy0 = (int)(sl / nstx) << kSTLog;
+  ci.cx0 = (int)(sl % nstx) << kSTLog;
+  return ci;
+}
+
+// Bit (ty - cy0) * 8 + (tx - cx0): tile (tx, ty) of the supertile at
+// (cx0, cy0) is reached by record r -- the support rows of the projection's
+// count, cut to the supertile's columns.
+__device__ __forceinline__ uint64_t st_mask(const L2Args &a, uint32_t r, int cx0, int cy0) {
+  int tx0, ty0, tx1, ty1;
+  unpack_rect(a.rects[r], tx0, ty0, tx1, ty1);
+  const uint32_t v = r / (uint32_t)a.per_view;
+  const int li = (int)(r - v * (uint32_t)a.per_view);
+  const ViewParams &vp = a.views[v];
+  Support sup;
+  sup.exact = false;
+  if (li < a.N) sup = make_support(a.grec[(int64_t)v * a.N + li]);
+  uint64_t m = 0;
+  const int r0 = max(ty0, cy0), r1 = min(ty1, cy0 + kST);
+  for (int ty = r0; ty < r1; ++ty) {
+    int lo, hi;
+    support_row(sup, ty, a.tile_w, a.tile_h, vp.W, vp.H, tx0, tx1, lo, hi);
+    lo = max(lo, cx0);
+    hi = min(hi, cx0 + kST);
+    if (lo < hi) m |= ((1ull << (hi - lo)) - 1ull) << ((lo - cx0) + ((ty - cy0) << kSTLog));
+  }
+  return m;
+}
+
+// Lane j's result: how many lanes of the wave have bit j of m set.
+__device__ __forceinline__ uint32_t wave_bit_counts(uint64_t m) {
+  const int lane = threadIdx.x & 63;
+  uint32_t mine = 0;
+#pragma unroll
+  for (int j = 0; j < 64; ++j) {
+    const uint32_t n = (uint32_t)__popcll(__ballot((m >> j) & 1ull));
+    mine = lane == j ? n : mine;
+  }
+  return mine;
+}
+
+__device__ __forceinline__ ChunkInfo chunk_prologue(const L2Args &a, uint32_t c) {
+  __shared__ ChunkInfo s_ci;
+  if (threadIdx.x == 0) s_ci = chunk_info(a, c);
+  __syncthreads();
+  return s_ci;
+}
+
+// Masks of a chunk's entries and the chunk's per-tile counts.
+__global__ __launch_bounds__(kL2Threads) void tile_masks_kernel(L2Args a) {
+  const uint32_t c = blockIdx.x;
+  if (c >= a.fi->n_chunks) return;
+  __shared__ uint32_t wc[kL2Waves][64];
+  const ChunkInfo ci = chunk_prologue(a, c);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  uint32_t acc = 0;
+  for (uint32_t e0 = ci.e0; e0 < ci.e1; e0 += kL2Threads) {
+    const uint32_t e = e0 + tid;
+    uint64_t m = 0;
+    if (e < ci.e1) {
+      m = st_mask(a, a.rec[e], ci.cx0, ci.cy0);
+      a.masks[e] = m;
+    }
+    acc += wave_bit_counts(m);
+  }
+  wc[w][lane] = acc;
+  __syncthreads();
+  if (tid < 64) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kL2Waves; ++k) s += wc[k][tid];
+    a.cnt[(uint64_t)c * 64 + tid] = s;
+  }
+}
+
+// Per (supertile, tile j): exclusive prefix of the chunk counts over the
+// supertile's chunks (in place) and the tile's total at its global tile id
+// (every tile of every view is one (supertile, j) pair).
+__global__ void tile_prefix_kernel(L2Args a) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g == 0) a.tstart[a.n_tiles] = 0;
+  const int64_t s = g >> 6;
+  const int j = (int)(g & 63);
+  if (s >= a.n_st) return;
+  const uint32_t c0 = a.chunk_base[s], c1 = a.chunk_base[s + 1];
+  uint32_t run = 0;
+  for (uint32_t c = c0; c < c1; ++c) {
+    const uint32_t x = a.cnt[(uint64_t)c * 64 + j];
+    a.cnt[(uint64_t)c * 64 + j] = run;
+    run += x;
+  }
+  const int v = view_of_st(a.views, a.V, (uint32_t)s);
+  const ViewParams &vp = a.views[v];
+  const uint32_t sl = (uint32_t)s - vp.st_base;
+  const uint32_t nstx = (uint32_t)(vp.ntx + kST - 1) >> kSTLog;
+  const int tx = (int)(sl % nstx) * kST + (j & (kST - 1));
+  const int ty = (int)(sl / nstx) * kST + (j >> kSTLog);
+  if (tx < vp.ntx && ty < vp.nty) a.tstart[vp.tile_base + (uint32_t)ty * vp.ntx + tx] = run;
+}
+
+// Tile ranges from the scanned tile counts (clamped to the stored duplicates).
+__global__ void ranges_kernel(const uint32_t *__restrict__ tstart, int64_t n_tiles,
+                              const FrameInfo *__restrict__ fi, uint2 *__restrict__ ranges) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_tiles) return;
+  const uint32_t n = fi->n_dup;
+  ranges[t] = make_uint2(min(tstart[t], n), min(tstart[t + 1], n));
+}
+
+// Each entry's record id to every tile of its mask, at the tile's first
+// position + the chunk's prefix + the entry's rank among the chunk's
+// entries with that bit (earlier rounds, earlier waves, earlier lanes).
+// Stores go tile by tile, so the lanes of a store write consecutive words.
+__global__ __launch_bounds__(kL2Threads) void tile_scatter_kernel(L2Args a) {
+  const uint32_t c = blockIdx.x;
+  if (c >= a.fi->n_chunks) return;
+  __shared__ uint32_t base[64];
+  __shared__ uint32_t wc[kL2Waves][64];
+  const ChunkInfo ci = chunk_prologue(a, c);
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid < 64) {
+    const ViewParams &vp = a.views[ci.v];
+    const int tx = ci.cx0 + (tid & (kST - 1)), ty = ci.cy0 + (tid >> kSTLog);
+    uint32_t b = 0;
+    if (tx < vp.ntx && ty < vp.nty)
+      b = a.tstart[vp.tile_base + (uint32_t)ty * vp.ntx + tx] + a.cnt[(uint64_t)c * 64 + tid];
+    base[tid] = b;
+  }
+  const uint32_t cap = a.fi->n_dup;
+  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  for (uint32_t e0 = ci.e0; e0 < ci.e1; e0 += kL2Threads) {
+    const uint32_t e = e0 + tid;
+    const bool valid = e < ci.e1;
+    const uint64_t m = valid ? a.masks[e] : 0ull;
+    const uint32_t r = valid ? a.rec[e] : 0u;
+    wc[w][lane] = wave_bit_counts(m);
+    __syncthreads();   // counts of every wave; base of the previous round
+    uint32_t off = base[lane], tot = 0;
+#pragma unroll
+    for (int k = 0; k < kL2Waves; ++k) {
+      off += k < w ? wc[k][lane] : 0u;
+      tot += wc[k][lane];
+    }
+    __syncthreads();   // every wave has read base and wc (the next round rewrites wc)
+    if (w == 0) base[lane] += tot;
+#pragma unroll 4
+    for (int j = 0; j < 64; ++j) {
+      const uint64_t b = __ballot((m >> j) & 1ull);
+      if (b == 0) continue;
+      const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)off, j);
+      if ((m >> j) & 1ull) {
+        const uint32_t pos = o + (uint32_t)__popcll(b & lt);
+        if (pos < cap) a.out[pos] = r;
+      }
+    }
+  }
+}
+
+// Sorted pairs in the exported (tile << 32 | depth key bits) form, one block
+// per tile.
+__global__ void expand_keys_kernel(const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
+                                   const uint32_t *__restrict__ depth, uint64_t *__restrict__ out) {
+  const uint32_t t = blockIdx.x;
+  const uint2 r = ranges[t];
+  for (uint32_t i = r.x + threadIdx.x; i < r.y; i += blockDim.x)
+    out[i] = ((uint64_t)t << 32) | (uint64_t)depth[vals[i]];
 }
 
 }  // namespace
@@ -490,8 +532,6 @@ hipError_t launch_exclusive_scan_u32(Ctx *c, uint32_t *data, int64_t n, uint32_t
   return excl_scan<uint32_t>(c->stream, data, n, tmp);
 }
 
-size_t emit_blocks_bytes(uint64_t n) { return (size_t)((n + kEmitSpan - 1) / kEmitSpan + 2) * 4; }
-
 hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u32_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, c->stream, p, n, v);
@@ -507,10 +547,13 @@ hipError_t launch_view_sums(Ctx *c, unsigned long long *sums) {
   return hipGetLastError();
 }
 
-// Records in (depth key, record id) order, then their tile counts in that
-// order scanned into output offsets (total at index n_records).  The depth
-// sort runs four 8-bit passes; those beyond the frame's depth bits (known on
-// the device) copy through, so the order lands in dk[0]/dv[0].
+uint64_t max_chunks(uint64_t n1, int64_t n_st) { return n1 / kChunk + (uint64_t)n_st + 1; }
+
+// Records in (depth key, record id) order, their supertile-entry counts in
+// that order scanned into entry offsets (total at index n_records), and the
+// frame totals (duplicates, entries) in c->totals.  The depth sort runs four
+// 8-bit passes; those beyond the frame's depth bits (known on the device)
+// copy through, so the order lands in dk[0]/dv[0].
 hipError_t launch_depth_order(Ctx *c) {
   const int64_t n = c->n_records;
   FrameInfo *fi = (FrameInfo *)c->finfo.p;
@@ -521,103 +564,159 @@ hipError_t launch_depth_order(Ctx *c) {
     hipLaunchKernelGGL(depth_range_kernel, dim3(1), dim3(kMinMaxSlots), 0, c->stream,
                        (const uint32_t *)c->minmax.p, fi);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (n == 0) return launch_fill_u32(c, (uint32_t *)c->offs.p, 2, 0u);   // total: 0
-    hipLaunchKernelGGL(depth_prep_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, c->stream,
-                       (const uint32_t *)c->keys.p, n, (const FrameInfo *)fi,
-                       (uint32_t *)c->dk[0].p, (uint32_t *)c->dv[0].p);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    uint32_t *k[2] = {(uint32_t *)c->dk[0].p, (uint32_t *)c->dk[1].p};
-    uint32_t *v[2] = {(uint32_t *)c->dv[0].p, (uint32_t *)c->dv[1].p};
-    e = launch_radix_sort_u32(c, k, v, (uint64_t)n, nullptr, &fi->depth_bits, 32, -1, -1, -1);
-    if (e != hipSuccess) return e;
+    if (n > 0) {
+      hipLaunchKernelGGL(depth_prep_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, c->stream,
+                         (const uint32_t *)c->keys.p, n, (const FrameInfo *)fi,
+                         (uint32_t *)c->dk[0].p, (uint32_t *)c->dv[0].p);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+      uint32_t *k[2] = {(uint32_t *)c->dk[0].p, (uint32_t *)c->dk[1].p};
+      uint32_t *v[2] = {(uint32_t *)c->dv[0].p, (uint32_t *)c->dv[1].p};
+      e = launch_radix_sort_u32(c, k, v, (uint64_t)n, nullptr, &fi->depth_bits, 32, -1, -1, -1);
+      if (e != hipSuccess) return e;
+    }
   }
   ScopedTimer t(c, K_SCAN);
-  hipLaunchKernelGGL(gather_counts_kernel, dim3(ceil_div(n + 1, 256)), dim3(256), 0, c->stream,
+  hipLaunchKernelGGL(gather_st_counts_kernel, dim3(ceil_div(n + 1, 256)), dim3(256), 0, c->stream,
                      (const uint32_t *)c->dv[0].p, n, (const uint64_t *)c->counts.p,
                      (uint64_t *)c->offs.p);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  return excl_scan<uint64_t>(c->stream, (uint64_t *)c->offs.p, n + 1, (uint64_t *)c->scan_tmp.p);
+  if ((e = excl_scan<uint64_t>(c->stream, (uint64_t *)c->offs.p, n + 1,
+                               (uint64_t *)c->scan_tmp.p)) != hipSuccess)
+    return e;
+  if ((e = launch_view_sums(c, (unsigned long long *)c->view_sums.p)) != hipSuccess) return e;
+  hipLaunchKernelGGL(frame_totals_kernel, dim3(1), dim3(64), 0, c->stream,
+                     (const unsigned long long *)c->view_sums.p, c->V,
+                     (const uint64_t *)c->offs.p + n, (uint64_t *)c->totals.p);
+  return hipGetLastError();
 }
 
-hipError_t launch_emit_keys(Ctx *c) {
+// Frame sizes on the device, then the first level: supertile entries in
+// depth order, sorted by supertile, and the supertiles' ranges and chunks.
+hipError_t launch_st_bin(Ctx *c) {
+  FrameInfo *fi = (FrameInfo *)c->finfo.p;
   hipLaunchKernelGGL(frame_info_kernel, dim3(1), dim3(1), 0, c->stream,
-                     (const uint64_t *)c->offs.p + c->n_records, (uint64_t)c->key_cap,
-                     c->sort_passes & 1, (FrameInfo *)c->finfo.p);
+                     (const uint64_t *)c->totals.p, (uint64_t)c->key_cap, (uint64_t)c->st_cap, fi);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess || c->n_records == 0) return e;
-  if (c->n_launch == 0) return hipSuccess;
-  ScopedTimer t(c, K_EMIT);
-  const uint32_t nblocks = ceil_div(c->n_launch, kEmitSpan);
-  hipLaunchKernelGGL(emit_blocks_kernel, dim3(ceil_div(c->n_records, 256)), dim3(256), 0, c->stream,
-                     (const uint64_t *)c->offs.p, c->n_records, (const FrameInfo *)c->finfo.p,
-                     nblocks, (uint32_t *)c->blk_first.p);
+  if (e != hipSuccess) return e;
+  uint32_t *cb = (uint32_t *)c->chunk_base.p;
+  if (c->n_records == 0 || c->st_launch == 0) {
+    if ((e = launch_fill_u32(c, cb, c->n_st + 1, 0u)) != hipSuccess) return e;
+    hipLaunchKernelGGL(chunk_total_kernel, dim3(1), dim3(1), 0, c->stream, (const uint32_t *)cb,
+                       c->n_st, fi);
+    return hipGetLastError();
+  }
+  {
+    ScopedTimer t(c, K_EMIT);
+    StEmitArgs a;
+    a.views = c->cur_views;
+    a.per_view = c->N + c->T;
+    a.N = c->N;
+    a.tile_w = c->tile_w;
+    a.tile_h = c->tile_h;
+    a.n_records = c->n_records;
+    a.order = (const uint32_t *)c->dv[0].p;
+    a.rects = (const uint2 *)c->rects.p;
+    a.offs = (const uint64_t *)c->offs.p;
+    a.grec = (const GaussRec *)c->grec.p;
+    a.fi = fi;
+    a.keys = c->sk[0].p;
+    a.vals = (uint32_t *)c->sv[0].p;
+    if (c->st_key16)
+      hipLaunchKernelGGL(st_emit_kernel<uint16_t>, dim3(ceil_div(c->n_records, 256)), dim3(256), 0,
+                         c->stream, a);
+    else
+      hipLaunchKernelGGL(st_emit_kernel<uint32_t>, dim3(ceil_div(c->n_records, 256)), dim3(256), 0,
+                         c->stream, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  uint32_t *v[2] = {(uint32_t *)c->sv[0].p, (uint32_t *)c->sv[1].p};
+  const uint32_t *n_dev = &fi->n1;
+  const int out = radix_passes(c->st_bits) & 1;
+  if (c->st_key16) {
+    uint16_t *k[2] = {(uint16_t *)c->sk[0].p, (uint16_t *)c->sk[1].p};
+    e = launch_radix_sort_u16(c, k, v, c->st_launch, n_dev, c->st_bits, K_SORT_UPSWEEP, K_SORT_SCAN,
+                              K_SORT_DOWNSWEEP);
+  } else {
+    uint32_t *k[2] = {(uint32_t *)c->sk[0].p, (uint32_t *)c->sk[1].p};
+    e = launch_radix_sort_u32(c, k, v, c->st_launch, n_dev, nullptr, c->st_bits, K_SORT_UPSWEEP,
+                              K_SORT_SCAN, K_SORT_DOWNSWEEP);
+  }
+  if (e != hipSuccess) return e;
+  c->st_sorted = out;
+  ScopedTimer t(c, K_RANGES);
+  uint2 *rng = (uint2 *)c->st_rng.p;
+  if ((e = launch_fill_u32(c, (uint32_t *)rng, 2 * c->n_st, 0u)) != hipSuccess) return e;
+  if (c->st_key16)
+    hipLaunchKernelGGL(st_ranges_kernel<uint16_t>, dim3(ceil_div(c->st_launch, 1024)), dim3(256), 0,
+                       c->stream, (const uint16_t *)c->sk[out].p, (const FrameInfo *)fi, rng);
+  else
+    hipLaunchKernelGGL(st_ranges_kernel<uint32_t>, dim3(ceil_div(c->st_launch, 1024)), dim3(256), 0,
+                       c->stream, (const uint32_t *)c->sk[out].p, (const FrameInfo *)fi, rng);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  EmitArgs a;
+  hipLaunchKernelGGL(st_chunks_kernel, dim3(ceil_div(c->n_st + 1, 256)), dim3(256), 0, c->stream,
+                     (const uint2 *)rng, c->n_st, cb);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = excl_scan<uint32_t>(c->stream, cb, c->n_st + 1, (uint32_t *)c->scan_tmp.p)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(chunk_total_kernel, dim3(1), dim3(1), 0, c->stream, (const uint32_t *)cb,
+                     c->n_st, fi);
+  return hipGetLastError();
+}
+
+// Second level: tile masks and counts per chunk, the tile scan, the tile
+// ranges, and the record ids in tile order (into v0).
+hipError_t launch_tile_lists(Ctx *c) {
+  L2Args a;
   a.views = c->cur_views;
+  a.V = c->V;
   a.per_view = c->N + c->T;
   a.N = c->N;
   a.tile_w = c->tile_w;
   a.tile_h = c->tile_h;
-  a.n_records = c->n_records;
-  a.order = (const uint32_t *)c->dv[0].p;
+  a.n_st = c->n_st;
+  a.n_tiles = c->n_tiles;
+  a.st_rng = (const uint2 *)c->st_rng.p;
+  a.chunk_base = (const uint32_t *)c->chunk_base.p;
+  a.rec = (const uint32_t *)c->sv[c->st_sorted].p;
   a.rects = (const uint2 *)c->rects.p;
-  a.offs = (const uint64_t *)c->offs.p;
   a.grec = (const GaussRec *)c->grec.p;
   a.fi = (const FrameInfo *)c->finfo.p;
-  a.blk_first = (const uint32_t *)c->blk_first.p;
-  a.keys_out = c->k0.p;
-  a.vals_out = (uint32_t *)c->v0.p;
-  if (c->key16)
-    hipLaunchKernelGGL(emit_balanced_kernel<uint16_t>, dim3(nblocks), dim3(kEmitThreads), 0,
+  a.masks = (uint64_t *)c->masks.p;
+  a.cnt = (uint32_t *)c->cnt2.p;
+  a.tstart = (uint32_t *)c->tstart.p;
+  a.out = (uint32_t *)c->v0.p;
+  const unsigned nchunks = (unsigned)max_chunks(c->st_launch, c->n_st);
+  hipError_t e;
+  {
+    ScopedTimer t(c, K_TILE_COUNT);
+    if (c->st_launch > 0) {
+      hipLaunchKernelGGL(tile_masks_kernel, dim3(nchunks), dim3(kL2Threads), 0, c->stream, a);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(tile_prefix_kernel, dim3(ceil_div(c->n_st * 64, 256)), dim3(256), 0,
                        c->stream, a);
-  else
-    hipLaunchKernelGGL(emit_balanced_kernel<uint32_t>, dim3(nblocks), dim3(kEmitThreads), 0,
-                       c->stream, a);
-  return hipGetLastError();
-}
-
-// Duplicates by global tile id: radix passes over the tile bits, element
-// count read on the device.
-hipError_t launch_tile_sort(Ctx *c) {
-  uint32_t *v[2] = {(uint32_t *)c->v0.p, (uint32_t *)c->v1.p};
-  const uint32_t *n_dev = &((const FrameInfo *)c->finfo.p)->n_dup;
-  if (c->key16) {
-    uint16_t *k[2] = {(uint16_t *)c->k0.p, (uint16_t *)c->k1.p};
-    return launch_radix_sort_u16(c, k, v, c->n_launch, n_dev, c->tile_bits, K_SORT_UPSWEEP,
-                                 K_SORT_SCAN, K_SORT_DOWNSWEEP);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = excl_scan<uint32_t>(c->stream, a.tstart, c->n_tiles + 1,
+                                 (uint32_t *)c->scan_tmp.p)) != hipSuccess)
+      return e;
   }
-  uint32_t *k[2] = {(uint32_t *)c->k0.p, (uint32_t *)c->k1.p};
-  return launch_radix_sort_u32(c, k, v, c->n_launch, n_dev, nullptr, c->tile_bits, K_SORT_UPSWEEP,
-                               K_SORT_SCAN, K_SORT_DOWNSWEEP);
-}
-
-hipError_t launch_tile_ranges(Ctx *c) {
-  ScopedTimer t(c, K_RANGES);
-  hipError_t e = launch_fill_u32(c, (uint32_t *)c->ranges.p, 2 * c->n_tiles, 0u);
-  if (e != hipSuccess || c->n_launch == 0) return e;
-  if (c->key16)
-    hipLaunchKernelGGL(tile_ranges_kernel<uint16_t>, dim3(ceil_div(c->n_launch, 1024)), dim3(256),
-                       0, c->stream, (const uint16_t *)c->k0.p, (const uint16_t *)c->k1.p,
-                       (const FrameInfo *)c->finfo.p, (uint2 *)c->ranges.p);
-  else
-    hipLaunchKernelGGL(tile_ranges_kernel<uint32_t>, dim3(ceil_div(c->n_launch, 1024)), dim3(256),
-                       0, c->stream, (const uint32_t *)c->k0.p, (const uint32_t *)c->k1.p,
-                       (const FrameInfo *)c->finfo.p, (uint2 *)c->ranges.p);
+  {
+    ScopedTimer t(c, K_RANGES);
+    hipLaunchKernelGGL(ranges_kernel, dim3(ceil_div(c->n_tiles, 256)), dim3(256), 0, c->stream,
+                       (const uint32_t *)a.tstart, c->n_tiles, a.fi, (uint2 *)c->ranges.p);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  if (c->st_launch == 0) return hipSuccess;
+  ScopedTimer t(c, K_TILE_SCATTER);
+  hipLaunchKernelGGL(tile_scatter_kernel, dim3(nchunks), dim3(kL2Threads), 0, c->stream, a);
   return hipGetLastError();
 }
 
 hipError_t launch_expand_keys(Ctx *c, uint64_t *dst) {
-  if (c->n_launch == 0) return hipSuccess;
-  if (c->key16)
-    hipLaunchKernelGGL(expand_keys_kernel<uint16_t>, dim3(ceil_div(c->n_launch, 256)), dim3(256), 0,
-                       c->stream, (const uint16_t *)c->k0.p, (const uint16_t *)c->k1.p,
-                       (const uint32_t *)c->v0.p, (const uint32_t *)c->v1.p,
-                       (const uint32_t *)c->keys.p, (const FrameInfo *)c->finfo.p, dst);
-  else
-    hipLaunchKernelGGL(expand_keys_kernel<uint32_t>, dim3(ceil_div(c->n_launch, 256)), dim3(256), 0,
-                       c->stream, (const uint32_t *)c->k0.p, (const uint32_t *)c->k1.p,
-                       (const uint32_t *)c->v0.p, (const uint32_t *)c->v1.p,
-                       (const uint32_t *)c->keys.p, (const FrameInfo *)c->finfo.p, dst);
+  if (c->n_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(expand_keys_kernel, dim3((unsigned)c->n_tiles), dim3(256), 0, c->stream,
+                     (const uint2 *)c->ranges.p, (const uint32_t *)c->v0.p,
+                     (const uint32_t *)c->keys.p, dst);
   return hipGetLastError();
 }
 

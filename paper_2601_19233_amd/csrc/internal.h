@@ -24,6 +24,10 @@ constexpr uint32_t kCulled = 0xFFFFFFFFu;    // depth key of a culled primitive
 
 constexpr int64_t kViewSlots = 8192;   // ViewParams the device table store holds
 constexpr int kMinMaxSlots = 64;       // slot pairs of the frame's depth-key range
+// Supertiles: blocks of kST x kST tiles (kST = 8, so a supertile's tiles
+// index the 64 bits of a mask), the unit of the first binning level.
+constexpr int kSTLog = 3;
+constexpr int kST = 1 << kSTLog;
 
 // Per-view parameters in device memory.
 struct ViewParams {
@@ -34,7 +38,7 @@ struct ViewParams {
   int32_t W, H;
   int32_t ntx, nty;      // tile grid
   uint32_t tile_base;    // first global tile id of this view
-  int32_t pad0;
+  uint32_t st_base;      // first global supertile id of this view (8 x 8 tiles each)
   int64_t pix_base;      // first pixel of this view in the packed per-pixel arrays
 };
 
@@ -62,7 +66,7 @@ struct __align__(16) TriRec {
 enum KernelId {
   K_VERTEX_FRAMES = 0, K_TRANSFER, K_PROJECT, K_TRIANGLES, K_SCAN, K_EMIT, K_SORT_UPSWEEP,
   K_SORT_SCAN, K_SORT_DOWNSWEEP, K_RANGES, K_BLEND, K_BLEND_BWD, K_PROJECT_BWD, K_DEPTH_SORT,
-  K_COUNT
+  K_TILE_COUNT, K_TILE_SCATTER, K_COUNT
 };
 
 struct Prof {
@@ -77,14 +81,14 @@ struct Prof {
 // Per-frame sizes that the kernels after the count scan read on the device,
 // so a captured graph needs no host synchronisation.
 struct FrameInfo {
-  uint32_t n_dup;        // duplicates in the sort (clamped to the key capacity)
+  uint32_t n_dup;        // duplicates (clamped to the capacity of v0)
   uint32_t depth_base;   // smallest depth-key bits of the frame
   int32_t depth_bits;    // significant bits of (depth key - depth_base)
-  int32_t pad0;
-  int32_t sorted_in;     // 0: sorted pairs in k0/v0, 1: in k1/v1
-  uint32_t overflow;     // sticky: the duplicates exceeded the key capacity
+  uint32_t n1;           // supertile entries (clamped to their capacity)
+  int32_t sorted_in;     // 0: tile lists in v0 (1: in v1)
+  uint32_t overflow;     // sticky: duplicates or entries exceeded a capacity
   uint32_t queue;        // work counter of the persistent blend
-  uint32_t pad;
+  uint32_t n_chunks;     // second-level chunks of the frame
 };
 
 // Device buffer that only grows.
@@ -113,10 +117,14 @@ struct Ctx {
   int64_t n_tiles = 0;
   int64_t n_pixels = 0;
   uint64_t n_dup = 0;         // duplicates of the frame as last read on the host
-  uint64_t n_launch = 0;      // elements the sort-stage grids cover (n_dup, or the capacity)
-  int sort_passes = 0;        // radix passes of the tile sort
-  int tile_bits = 1;
-  bool key16 = false;         // tile ids fit 16 bits: k0/k1 hold uint16 keys
+  int64_t n_st = 0;           // supertiles of the frame
+  int64_t n_st_max = 0;       // most supertiles of any frame so far (sizes the chunk counts)
+  int st_bits = 1;            // bits of a global supertile id
+  bool st_key16 = false;      // supertile ids fit 16 bits: sk holds uint16 keys
+  int st_sorted = 0;          // which of sk/sv holds the sorted entries
+  uint64_t st_launch = 0;     // entries the first-level grids cover (n1, or the capacity)
+  uint64_t st_cap = 0;        // entries the first-level buffers hold
+  double st_ratio = 0.0;      // entries / duplicates of the last eager frame
   const int64_t *view_offsets = nullptr;   // caller's per-view pixel offsets (render_batched)
   DevBuf minmax;       // 2 x kMinMaxSlots uint32: min / max depth-key bits (folded in bin)
   DevBuf finfo;        // FrameInfo (device)
@@ -137,16 +145,22 @@ struct Ctx {
   const ViewParams *cur_views = nullptr;            // table of the current frame
   DevBuf keys;         // n_records uint32 depth bits
   DevBuf rects;        // n_records uint2: (tx0 | ty0 << 16, tx1 | ty1 << 16) inclusive-exclusive
-  DevBuf counts;       // n_records uint64 tile counts
+  DevBuf counts;       // n_records uint64: tiles | supertile entries << 32
   DevBuf dk[2], dv[2]; // n_records uint32: depth-sort keys / record ids (ping-pong)
-  DevBuf offs;         // n_records + 1 uint64: tile counts in depth order, scanned
+  DevBuf offs;         // n_records + 1 uint64: supertile-entry counts in depth order, scanned
+  DevBuf totals;       // 2 uint64: the frame's duplicates and supertile entries
   DevBuf grec;         // V*N GaussRec
   DevBuf trec;         // V*T TriRec
   DevBuf scan_tmp;
-  DevBuf k0, k1;       // n_dup global tile ids, uint16 or uint32 (ping-pong)
-  DevBuf v0, v1;       // n_dup uint32 record ids
+  DevBuf sk[2], sv[2]; // st_cap supertile ids (uint16 or uint32) / record ids (ping-pong)
+  DevBuf masks;        // st_cap uint64: tiles of its supertile an entry reaches
+  DevBuf st_rng;       // n_st uint2: [start, end) of each supertile's sorted entries
+  DevBuf chunk_base;   // n_st + 1 uint32: scanned second-level chunks per supertile
+  DevBuf cnt2;         // chunks x 64 uint32: per-chunk tile counts / prefixes
+  DevBuf tstart;       // n_tiles + 1 uint32: tile counts, scanned
+  DevBuf v0;           // key_cap uint32: record ids in tile order (the tile lists)
+  DevBuf v1;           // unused (kept null: the lists always land in v0)
   DevBuf hist;         // radix per-block histograms
-  DevBuf blk_first;    // emit blocks + 1 uint32: first record of each emit block
   DevBuf ranges;       // n_tiles uint2
   DevBuf g2d;          // V*N x 9 per-view 2D gradients (backward)
   DevBuf host_pinned;  // not a device buffer: pinned host scratch for small readbacks
@@ -180,7 +194,9 @@ hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v);
 size_t scan_tmp_bytes(int64_t n);
 hipError_t launch_view_sums(Ctx *c, unsigned long long *sums);
 hipError_t launch_depth_order(Ctx *c);
-hipError_t launch_emit_keys(Ctx *c);
+hipError_t launch_st_bin(Ctx *c);
+hipError_t launch_tile_lists(Ctx *c);
+uint64_t max_chunks(uint64_t n1, int64_t n_st);
 hipError_t launch_radix_sort_u32(Ctx *c, uint32_t *keys[2], uint32_t *vals[2], uint64_t n_launch,
                                  const uint32_t *n_dev, const int32_t *bits_dev, int bits,
                                  int kid_up, int kid_scan, int kid_down);
@@ -189,9 +205,6 @@ hipError_t launch_radix_sort_u16(Ctx *c, uint16_t *keys[2], uint32_t *vals[2], u
                                  int kid_down);
 int radix_passes(int bits);
 size_t radix_hist_bytes(uint64_t n);
-size_t emit_blocks_bytes(uint64_t n);
-hipError_t launch_tile_sort(Ctx *c);
-hipError_t launch_tile_ranges(Ctx *c);
 hipError_t launch_expand_keys(Ctx *c, uint64_t *dst);
 hipError_t launch_blend(Ctx *c, float *image, float *T_final, int32_t *n_contrib,
                         float *T_entity_in, unsigned long long *pairs = nullptr);

@@ -91,4 +91,26 @@ __device__ __forceinline__ void support_row(const Support &s, int ty, int tile_w
   b = (int)c1 / tile_w + 1;
 }
 
+// Supertile columns [lo, hi) of supertile row sy that a record reaches: the
+// hull of the supertile columns of its tile rows' support spans in that row
+// (empty: lo = hi); tiles += the record's tiles in the row.  Triangles pass a
+// Support with exact = false (whole rectangle rows).
+__device__ __forceinline__ void st_row_span(const Support &s, int sy, int tx0, int ty0, int tx1,
+                                            int ty1, int tile_w, int tile_h, int W, int H,
+                                            int &lo, int &hi, uint32_t &tiles) {
+  lo = 0x7FFFFFFF;
+  hi = 0;
+  const int r0 = max(ty0, sy << kSTLog), r1 = min(ty1, (sy + 1) << kSTLog);
+  for (int ty = r0; ty < r1; ++ty) {
+    int a, b;
+    support_row(s, ty, tile_w, tile_h, W, H, tx0, tx1, a, b);
+    if (a < b) {
+      tiles += (uint32_t)(b - a);
+      lo = min(lo, a >> kSTLog);
+      hi = max(hi, ((b - 1) >> kSTLog) + 1);
+    }
+  }
+  if (lo >= hi) lo = hi = 0;
+}
+
 }  // namespace umgs

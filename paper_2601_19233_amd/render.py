@@ -338,6 +338,12 @@ class Rasterizer:
         self._check(self.lib.umgs_query(self.h, C.byref(a), C.byref(b), C.byref(c), None))
         return a.value, b.value, c.value
 
+    def query_bins(self):
+        """(supertiles, supertile entries) of the last binned frame; synchronizes."""
+        a, b = C.c_int64(), C.c_int64()
+        self._check(self.lib.umgs_query_bins(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
     def overflowed(self) -> bool:
         """Whether duplicates were dropped for lack of reserved capacity since
         the last call (clears the flag); synchronizes."""
