@@ -424,13 +424,13 @@ def main():
     kb = 2.0 if n_st <= 65536 else 4.0
     algo_bytes = {
         # first level: per record its order, offsets, rectangle and Gaussian
-        # record; per entry its supertile id and record id
-        "emit_keys": 76.0 * n_rec + (kb + 4.0) * n1,
-        "sort_downsweep": 2.0 * (kb + 4.0) * n1,  # read and write id + record id
-        "sort_upsweep": kb * n1,                  # read the ids
-        # second level: per entry its record id, rectangle, Gaussian record
-        # and the mask written
-        "tile_count": (4.0 + 8.0 + 48.0 + 8.0) * n1,
+        # record; per entry its supertile id, record id and tile mask
+        "emit_keys": 76.0 * n_rec + (kb + 12.0) * n1,
+        "sort_downsweep": 2.0 * (kb + 12.0) * n1,  # read and write id, record id, mask
+        "sort_upsweep": kb * n1,                   # read the ids
+        # masks: per entry its supertile id, record id, rectangle, Gaussian
+        # record and the mask written; counts: the sorted masks read
+        "tile_count": (kb + 4.0 + 8.0 + 48.0 + 8.0 + 8.0) * n1,
         # per entry its mask and record id; per duplicate one record id written
         "tile_scatter": 12.0 * n1 + 4.0 * n_dup,
         "transfer": scene.N * (40.0 + 12.0 * scene.bind_face.shape[1] + 88.0),

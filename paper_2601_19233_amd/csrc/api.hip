@@ -166,8 +166,8 @@ void umgs_destroy(umgs_ctx *ctx) {
   DevBuf *bufs[] = {&c->V_rest, &c->faces, &c->vf_ptr, &c->vf_idx, &c->vtab, &c->d_views,
                     &c->keys, &c->rects, &c->counts, &c->dk[0], &c->dk[1], &c->dv[0],
                     &c->dv[1], &c->offs, &c->grec, &c->trec, &c->scan_tmp,
-                    &c->sk[0], &c->sk[1], &c->sv[0], &c->sv[1], &c->masks, &c->st_rng,
-                    &c->chunk_base, &c->cnt2, &c->tstart, &c->totals,
+                    &c->sk[0], &c->sk[1], &c->sv[0], &c->sv[1], &c->masks[0], &c->masks[1], &c->st_rng,
+                    &c->chunk_base, &c->cnt2, &c->chunk_tab, &c->tstart, &c->totals,
                     &c->v0, &c->v1, &c->hist, &c->ranges, &c->g2d,
                     &c->minmax, &c->finfo, &c->tile_order, &c->pair_count, &c->view_sums};
   for (DevBuf *b : bufs) free_buf(*b);
@@ -419,8 +419,10 @@ static umgs_status ensure_lists(Ctx *c, uint64_t n, uint64_t st) {
       (s = ensure(c, c->sk[1], 4 * st, "supertile entries")) ||
       (s = ensure(c, c->sv[0], 4 * st, "supertile entries")) ||
       (s = ensure(c, c->sv[1], 4 * st, "supertile entries")) ||
-      (s = ensure(c, c->masks, 8 * st, "supertile masks")) ||
+      (s = ensure(c, c->masks[0], 8 * st, "supertile masks")) ||
+      (s = ensure(c, c->masks[1], 8 * st, "supertile masks")) ||
       (s = ensure(c, c->cnt2, 64 * sizeof(uint32_t) * max_chunks(st, n_st), "chunk counts")) ||
+      (s = ensure(c, c->chunk_tab, chunk_rec_bytes() * max_chunks(st, n_st), "chunk table")) ||
       (s = ensure(c, c->hist, radix_hist_bytes(std::max<uint64_t>(st, c->n_records)), "radix histograms")) ||
       (s = ensure(c, c->scan_tmp,
                   scan_tmp_bytes(std::max<int64_t>({(int64_t)radix_hist_bytes(st) / 4, c->n_records + 1,

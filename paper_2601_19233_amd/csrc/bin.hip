@@ -8,11 +8,12 @@
 //     supertile its support reaches, in depth order at its scanned offset,
 //     and a stable radix sort by supertile id (sort.hip) leaves each
 //     supertile's entries front to back.
-//  3. Second level, per chunk of a supertile's entries: each entry's 64-bit
-//     mask of the supertile's tiles its support reaches (the same support
-//     rows the projection counted), per-chunk tile counts, their prefix over
-//     the supertile's chunks and over all tiles, then each entry's record id
-//     written to every tile of its mask at its rank there.
+//     Each entry carries a 64-bit mask of the supertile's tiles its support
+//     reaches (the support rows the projection counted), sorted with it.
+//  3. Second level, per chunk of a supertile's entries: per-chunk tile
+//     counts, their prefix over the supertile's chunks and over all tiles,
+//     then each entry's record id written to every tile of its mask at its
+//     rank there.
 //
 // No per-duplicate key is ever stored: each duplicate's record id is written
 // once, to its final place, and the tile ranges come out of the tile scan.
@@ -207,6 +208,7 @@ struct StEmitArgs {
   const FrameInfo *fi;
   void *keys;              // K global supertile ids
   uint32_t *vals;          // record ids
+  uint64_t *masks;         // tiles of the supertile the record reaches (mask kernel)
 };
 
 __device__ __forceinline__ void unpack_rect(uint2 rc, int &tx0, int &ty0, int &tx1, int &ty1) {
@@ -240,7 +242,7 @@ __global__ void st_emit_kernel(StEmitArgs e) {
   uint32_t tiles = 0;
   for (int sy = ty0 >> kSTLog; sy <= (ty1 - 1) >> kSTLog; ++sy) {
     int lo, hi;
-    st_row_span(sup, sy, tx0, ty0, tx1, ty1, e.tile_w, e.tile_h, vp.W, vp.H, lo, hi, tiles);
+    st_row_hull(sup, sy, tx0, ty0, tx1, ty1, e.tile_w, e.tile_h, vp.W, vp.H, lo, hi, tiles);
     for (int sx = lo; sx < hi; ++sx) {
       if (pos >= end) return;
       keys[pos] = (K)(vp.st_base + (uint32_t)sy * nstx + (uint32_t)sx);
@@ -248,6 +250,29 @@ __global__ void st_emit_kernel(StEmitArgs e) {
       ++pos;
     }
   }
+}
+
+// One thread per entry (in emit order, so neighbouring threads mostly share
+// a record): the mask of the supertile's tiles the record reaches -- the
+// support rows of the projection's count, cut to the supertile.
+template <typename K>
+__global__ void st_mask_kernel(StEmitArgs e) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= e.fi->n1) return;
+  const uint32_t s = (uint32_t)((const K *)e.keys)[i];
+  const uint32_t r = e.vals[i];
+  int tx0, ty0, tx1, ty1;
+  unpack_rect(e.rects[r], tx0, ty0, tx1, ty1);
+  const uint32_t v = r / (uint32_t)e.per_view;
+  const int li = (int)(r - v * (uint32_t)e.per_view);
+  const ViewParams &vp = e.views[v];
+  Support sup;
+  sup.exact = false;
+  if (li < e.N) sup = make_support(e.grec[(int64_t)v * e.N + li]);
+  const uint32_t nstx = (uint32_t)(vp.ntx + kST - 1) >> kSTLog;
+  const uint32_t sl = s - vp.st_base;
+  e.masks[i] = st_mask(sup, (int)(sl % nstx), (int)(sl / nstx), tx0, ty0, tx1, ty1, e.tile_w,
+                       e.tile_h, vp.W, vp.H);
 }
 
 // Per-supertile [start, end) of the sorted entries: 4 consecutive ids per
@@ -296,20 +321,10 @@ __global__ void chunk_total_kernel(const uint32_t *__restrict__ chunk_base, int6
   fi->n_chunks = chunk_base[n_st];
 }
 
-struct L2Args {
-  const ViewParams *views;
-  int V, per_view, N, tile_w, tile_h;
-  int64_t n_st, n_tiles;
-  const uint2 *st_rng;         // per supertile [start, end) of its sorted entries
-  const uint32_t *chunk_base;  // scanned chunks per supertile (n_st + 1)
-  const uint32_t *rec;         // sorted entries' record ids
-  const uint2 *rects;
-  const GaussRec *grec;
-  const FrameInfo *fi;
-  uint64_t *masks;             // per entry: tiles of its supertile it reaches
-  uint32_t *cnt;               // per chunk 64 tile counts, then their prefix over the chunks
-  uint32_t *tstart;            // per tile: count, then (scanned) first position
-  uint32_t *out;               // record ids in tile order
+// A second-level chunk: entries [e0, e1) of the supertile whose first tile
+// is (cxy & 0xFFFF, cxy >> 16) in view v.
+struct __align__(16) ChunkRec {
+  uint32_t e0, e1, v, cxy;
 };
 
 // The view whose supertiles [st_base, next st_base) hold s.
@@ -322,56 +337,44 @@ __device__ __forceinline__ int view_of_st(const ViewParams *views, int V, uint32
   return lo;
 }
 
-// Chunk c's supertile (the last one whose first chunk is <= c: empty
-// supertiles share their first chunk with the next one) and its entries.
-struct ChunkInfo {
-  uint32_t s, e0, e1;
-  int v, cx0, cy0;   // view, first tile column / row of the supertile
-};
-
-__device__ __forceinline__ ChunkInfo chunk_info(const L2Args &a, uint32_t c) {
-  ChunkInfo ci;
-  int64_t lo = 0, hi = a.n_st - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if (a.chunk_base[mid] <= c) lo = mid; else hi = mid - 1;
-  }
-  ci.s = (uint32_t)lo;
-  const uint2 r = a.st_rng[lo];
-  ci.e0 = r.x + (c - a.chunk_base[lo]) * (uint32_t)kChunk;
-  ci.e1 = min(ci.e0 + (uint32_t)kChunk, r.y);
-  ci.v = view_of_st(a.views, a.V, ci.s);
-  const ViewParams &vp = a.views[ci.v];
-  const uint32_t sl = ci.s - vp.st_base;
+// One thread per supertile writes the records of its chunks.
+__global__ void chunk_table_kernel(const ViewParams *__restrict__ views, int V,
+                                   const uint2 *__restrict__ rng, const uint32_t *__restrict__ chunk_base,
+                                   int64_t n_st, ChunkRec *__restrict__ tab) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n_st) return;
+  const uint32_t c0 = chunk_base[s], c1 = chunk_base[s + 1];
+  if (c0 >= c1) return;
+  const uint2 r = rng[s];
+  const int v = view_of_st(views, V, (uint32_t)s);
+  const ViewParams &vp = views[v];
+  const uint32_t sl = (uint32_t)s - vp.st_base;
   const uint32_t nstx = (uint32_t)(vp.ntx + kST - 1) >> kSTLog;
-  ci.cy0 = (int)(sl / nstx) << kSTLog;
-  ci.cx0 = (int)(sl % nstx) << kSTLog;
-  return ci;
+  const uint32_t cxy = ((sl % nstx) << kSTLog) | ((sl / nstx) << (kSTLog + 16));
+  for (uint32_t c = c0; c < c1; ++c) {
+    ChunkRec k;
+    k.e0 = r.x + (c - c0) * (uint32_t)kChunk;
+    k.e1 = min(k.e0 + (uint32_t)kChunk, r.y);
+    k.v = (uint32_t)v;
+    k.cxy = cxy;
+    tab[c] = k;
+  }
 }
 
-// Bit (ty - cy0) * 8 + (tx - cx0): tile (tx, ty) of the supertile at
-// (cx0, cy0) is reached by record r -- the support rows of the projection's
-// count, cut to the supertile's columns.
-__device__ __forceinline__ uint64_t st_mask(const L2Args &a, uint32_t r, int cx0, int cy0) {
-  int tx0, ty0, tx1, ty1;
-  unpack_rect(a.rects[r], tx0, ty0, tx1, ty1);
-  const uint32_t v = r / (uint32_t)a.per_view;
-  const int li = (int)(r - v * (uint32_t)a.per_view);
-  const ViewParams &vp = a.views[v];
-  Support sup;
-  sup.exact = false;
-  if (li < a.N) sup = make_support(a.grec[(int64_t)v * a.N + li]);
-  uint64_t m = 0;
-  const int r0 = max(ty0, cy0), r1 = min(ty1, cy0 + kST);
-  for (int ty = r0; ty < r1; ++ty) {
-    int lo, hi;
-    support_row(sup, ty, a.tile_w, a.tile_h, vp.W, vp.H, tx0, tx1, lo, hi);
-    lo = max(lo, cx0);
-    hi = min(hi, cx0 + kST);
-    if (lo < hi) m |= ((1ull << (hi - lo)) - 1ull) << ((lo - cx0) + ((ty - cy0) << kSTLog));
-  }
-  return m;
-}
+struct L2Args {
+  const ViewParams *views;
+  int V, per_view, N, tile_w, tile_h;
+  int64_t n_st, n_tiles;
+  const uint2 *st_rng;         // per supertile [start, end) of its sorted entries
+  const uint32_t *chunk_base;  // scanned chunks per supertile (n_st + 1)
+  const ChunkRec *chunks;      // per chunk: its entries, view and supertile
+  const uint32_t *rec;         // sorted entries' record ids
+  const FrameInfo *fi;
+  const uint64_t *masks;       // sorted entries' masks: tiles of the supertile they reach
+  uint32_t *cnt;               // per chunk 64 tile counts, then their prefix over the chunks
+  uint32_t *tstart;            // per tile: count, then (scanned) first position
+  uint32_t *out;               // record ids in tile order
+};
 
 // Lane j's result: how many lanes of the wave have bit j of m set.
 __device__ __forceinline__ uint32_t wave_bit_counts(uint64_t m) {
@@ -385,29 +388,18 @@ __device__ __forceinline__ uint32_t wave_bit_counts(uint64_t m) {
   return mine;
 }
 
-__device__ __forceinline__ ChunkInfo chunk_prologue(const L2Args &a, uint32_t c) {
-  __shared__ ChunkInfo s_ci;
-  if (threadIdx.x == 0) s_ci = chunk_info(a, c);
-  __syncthreads();
-  return s_ci;
-}
-
-// Masks of a chunk's entries and the chunk's per-tile counts.
-__global__ __launch_bounds__(kL2Threads) void tile_masks_kernel(L2Args a) {
-  const uint32_t c = blockIdx.x;
+// A chunk's per-tile counts (bit counts of its entries' masks).
+__global__ __launch_bounds__(kL2Threads) void tile_count_kernel(L2Args a) {
+  // consecutive chunks (mostly of one supertile) on one XCD
+  const uint32_t c = xcd_block(blockIdx.x, gridDim.x);
   if (c >= a.fi->n_chunks) return;
   __shared__ uint32_t wc[kL2Waves][64];
-  const ChunkInfo ci = chunk_prologue(a, c);
+  const ChunkRec ck = a.chunks[c];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   uint32_t acc = 0;
-  for (uint32_t e0 = ci.e0; e0 < ci.e1; e0 += kL2Threads) {
+  for (uint32_t e0 = ck.e0; e0 < ck.e1; e0 += kL2Threads) {
     const uint32_t e = e0 + tid;
-    uint64_t m = 0;
-    if (e < ci.e1) {
-      m = st_mask(a, a.rec[e], ci.cx0, ci.cy0);
-      a.masks[e] = m;
-    }
-    acc += wave_bit_counts(m);
+    acc += wave_bit_counts(e < ck.e1 ? a.masks[e] : 0ull);
   }
   wc[w][lane] = acc;
   __syncthreads();
@@ -458,15 +450,16 @@ __global__ void ranges_kernel(const uint32_t *__restrict__ tstart, int64_t n_til
 // entries with that bit (earlier rounds, earlier waves, earlier lanes).
 // Stores go tile by tile, so the lanes of a store write consecutive words.
 __global__ __launch_bounds__(kL2Threads) void tile_scatter_kernel(L2Args a) {
-  const uint32_t c = blockIdx.x;
+  const uint32_t c = xcd_block(blockIdx.x, gridDim.x);
   if (c >= a.fi->n_chunks) return;
   __shared__ uint32_t base[64];
   __shared__ uint32_t wc[kL2Waves][64];
-  const ChunkInfo ci = chunk_prologue(a, c);
+  const ChunkRec ck = a.chunks[c];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (tid < 64) {
-    const ViewParams &vp = a.views[ci.v];
-    const int tx = ci.cx0 + (tid & (kST - 1)), ty = ci.cy0 + (tid >> kSTLog);
+    const ViewParams &vp = a.views[ck.v];
+    const int tx = (int)(ck.cxy & 0xFFFF) + (tid & (kST - 1));
+    const int ty = (int)(ck.cxy >> 16) + (tid >> kSTLog);
     uint32_t b = 0;
     if (tx < vp.ntx && ty < vp.nty)
       b = a.tstart[vp.tile_base + (uint32_t)ty * vp.ntx + tx] + a.cnt[(uint64_t)c * 64 + tid];
@@ -474,9 +467,9 @@ __global__ __launch_bounds__(kL2Threads) void tile_scatter_kernel(L2Args a) {
   }
   const uint32_t cap = a.fi->n_dup;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  for (uint32_t e0 = ci.e0; e0 < ci.e1; e0 += kL2Threads) {
+  for (uint32_t e0 = ck.e0; e0 < ck.e1; e0 += kL2Threads) {
     const uint32_t e = e0 + tid;
-    const bool valid = e < ci.e1;
+    const bool valid = e < ck.e1;
     const uint64_t m = valid ? a.masks[e] : 0ull;
     const uint32_t r = valid ? a.rec[e] : 0u;
     wc[w][lane] = wave_bit_counts(m);
@@ -548,6 +541,7 @@ hipError_t launch_view_sums(Ctx *c, unsigned long long *sums) {
 }
 
 uint64_t max_chunks(uint64_t n1, int64_t n_st) { return n1 / kChunk + (uint64_t)n_st + 1; }
+size_t chunk_rec_bytes() { return sizeof(ChunkRec); }
 
 // Records in (depth key, record id) order, their supertile-entry counts in
 // that order scanned into entry offsets (total at index n_records), and the
@@ -621,6 +615,7 @@ hipError_t launch_st_bin(Ctx *c) {
     a.fi = fi;
     a.keys = c->sk[0].p;
     a.vals = (uint32_t *)c->sv[0].p;
+    a.masks = (uint64_t *)c->masks[0].p;
     if (c->st_key16)
       hipLaunchKernelGGL(st_emit_kernel<uint16_t>, dim3(ceil_div(c->n_records, 256)), dim3(256), 0,
                          c->stream, a);
@@ -629,17 +624,41 @@ hipError_t launch_st_bin(Ctx *c) {
                          c->stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
+  {
+    ScopedTimer t(c, K_TILE_COUNT);
+    StEmitArgs a;
+    a.views = c->cur_views;
+    a.per_view = c->N + c->T;
+    a.N = c->N;
+    a.tile_w = c->tile_w;
+    a.tile_h = c->tile_h;
+    a.n_records = c->n_records;
+    a.rects = (const uint2 *)c->rects.p;
+    a.grec = (const GaussRec *)c->grec.p;
+    a.fi = fi;
+    a.keys = c->sk[0].p;
+    a.vals = (uint32_t *)c->sv[0].p;
+    a.masks = (uint64_t *)c->masks[0].p;
+    if (c->st_key16)
+      hipLaunchKernelGGL(st_mask_kernel<uint16_t>, dim3(ceil_div(c->st_launch, 256)), dim3(256), 0,
+                         c->stream, a);
+    else
+      hipLaunchKernelGGL(st_mask_kernel<uint32_t>, dim3(ceil_div(c->st_launch, 256)), dim3(256), 0,
+                         c->stream, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   uint32_t *v[2] = {(uint32_t *)c->sv[0].p, (uint32_t *)c->sv[1].p};
+  uint64_t *m[2] = {(uint64_t *)c->masks[0].p, (uint64_t *)c->masks[1].p};
   const uint32_t *n_dev = &fi->n1;
   const int out = radix_passes(c->st_bits) & 1;
   if (c->st_key16) {
     uint16_t *k[2] = {(uint16_t *)c->sk[0].p, (uint16_t *)c->sk[1].p};
-    e = launch_radix_sort_u16(c, k, v, c->st_launch, n_dev, c->st_bits, K_SORT_UPSWEEP, K_SORT_SCAN,
-                              K_SORT_DOWNSWEEP);
+    e = launch_radix_sort_pay_u16(c, k, v, m, c->st_launch, n_dev, c->st_bits, K_SORT_UPSWEEP,
+                                  K_SORT_SCAN, K_SORT_DOWNSWEEP);
   } else {
     uint32_t *k[2] = {(uint32_t *)c->sk[0].p, (uint32_t *)c->sk[1].p};
-    e = launch_radix_sort_u32(c, k, v, c->st_launch, n_dev, nullptr, c->st_bits, K_SORT_UPSWEEP,
-                              K_SORT_SCAN, K_SORT_DOWNSWEEP);
+    e = launch_radix_sort_pay_u32(c, k, v, m, c->st_launch, n_dev, c->st_bits, K_SORT_UPSWEEP,
+                                  K_SORT_SCAN, K_SORT_DOWNSWEEP);
   }
   if (e != hipSuccess) return e;
   c->st_sorted = out;
@@ -660,6 +679,10 @@ hipError_t launch_st_bin(Ctx *c) {
     return e;
   hipLaunchKernelGGL(chunk_total_kernel, dim3(1), dim3(1), 0, c->stream, (const uint32_t *)cb,
                      c->n_st, fi);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(chunk_table_kernel, dim3(ceil_div(c->n_st, 256)), dim3(256), 0, c->stream,
+                     c->cur_views, c->V, (const uint2 *)rng, (const uint32_t *)cb, c->n_st,
+                     (ChunkRec *)c->chunk_tab.p);
   return hipGetLastError();
 }
 
@@ -677,11 +700,10 @@ hipError_t launch_tile_lists(Ctx *c) {
   a.n_tiles = c->n_tiles;
   a.st_rng = (const uint2 *)c->st_rng.p;
   a.chunk_base = (const uint32_t *)c->chunk_base.p;
+  a.chunks = (const ChunkRec *)c->chunk_tab.p;
   a.rec = (const uint32_t *)c->sv[c->st_sorted].p;
-  a.rects = (const uint2 *)c->rects.p;
-  a.grec = (const GaussRec *)c->grec.p;
   a.fi = (const FrameInfo *)c->finfo.p;
-  a.masks = (uint64_t *)c->masks.p;
+  a.masks = (const uint64_t *)c->masks[c->st_sorted].p;
   a.cnt = (uint32_t *)c->cnt2.p;
   a.tstart = (uint32_t *)c->tstart.p;
   a.out = (uint32_t *)c->v0.p;
@@ -690,7 +712,7 @@ hipError_t launch_tile_lists(Ctx *c) {
   {
     ScopedTimer t(c, K_TILE_COUNT);
     if (c->st_launch > 0) {
-      hipLaunchKernelGGL(tile_masks_kernel, dim3(nchunks), dim3(kL2Threads), 0, c->stream, a);
+      hipLaunchKernelGGL(tile_count_kernel, dim3(nchunks), dim3(kL2Threads), 0, c->stream, a);
       if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(tile_prefix_kernel, dim3(ceil_div(c->n_st * 64, 256)), dim3(256), 0,

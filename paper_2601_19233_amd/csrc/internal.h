@@ -153,10 +153,11 @@ struct Ctx {
   DevBuf trec;         // V*T TriRec
   DevBuf scan_tmp;
   DevBuf sk[2], sv[2]; // st_cap supertile ids (uint16 or uint32) / record ids (ping-pong)
-  DevBuf masks;        // st_cap uint64: tiles of its supertile an entry reaches
+  DevBuf masks[2];     // st_cap uint64: tiles of its supertile an entry reaches (ping-pong)
   DevBuf st_rng;       // n_st uint2: [start, end) of each supertile's sorted entries
   DevBuf chunk_base;   // n_st + 1 uint32: scanned second-level chunks per supertile
   DevBuf cnt2;         // chunks x 64 uint32: per-chunk tile counts / prefixes
+  DevBuf chunk_tab;    // chunks x 16 B: each chunk's entries, view and supertile
   DevBuf tstart;       // n_tiles + 1 uint32: tile counts, scanned
   DevBuf v0;           // key_cap uint32: record ids in tile order (the tile lists)
   DevBuf v1;           // unused (kept null: the lists always land in v0)
@@ -197,12 +198,16 @@ hipError_t launch_depth_order(Ctx *c);
 hipError_t launch_st_bin(Ctx *c);
 hipError_t launch_tile_lists(Ctx *c);
 uint64_t max_chunks(uint64_t n1, int64_t n_st);
+size_t chunk_rec_bytes();
 hipError_t launch_radix_sort_u32(Ctx *c, uint32_t *keys[2], uint32_t *vals[2], uint64_t n_launch,
                                  const uint32_t *n_dev, const int32_t *bits_dev, int bits,
                                  int kid_up, int kid_scan, int kid_down);
-hipError_t launch_radix_sort_u16(Ctx *c, uint16_t *keys[2], uint32_t *vals[2], uint64_t n_launch,
-                                 const uint32_t *n_dev, int bits, int kid_up, int kid_scan,
-                                 int kid_down);
+hipError_t launch_radix_sort_pay_u32(Ctx *c, uint32_t *keys[2], uint32_t *vals[2],
+                                     uint64_t *pay[2], uint64_t n_launch, const uint32_t *n_dev,
+                                     int bits, int kid_up, int kid_scan, int kid_down);
+hipError_t launch_radix_sort_pay_u16(Ctx *c, uint16_t *keys[2], uint32_t *vals[2],
+                                     uint64_t *pay[2], uint64_t n_launch, const uint32_t *n_dev,
+                                     int bits, int kid_up, int kid_scan, int kid_down);
 int radix_passes(int bits);
 size_t radix_hist_bytes(uint64_t n);
 hipError_t launch_expand_keys(Ctx *c, uint64_t *dst);

@@ -217,7 +217,7 @@ __device__ uint32_t project_gaussian(const ViewParams *__restrict__ views, int N
     const Support sup = make_support(rec);
     for (int sy = ty0 >> kSTLog; sy <= (ty1 - 1) >> kSTLog; ++sy) {
       int lo, hi;
-      st_row_span(sup, sy, tx0, ty0, tx1, ty1, tile_w, tile_h, vp.W, vp.H, lo, hi, cnt);
+      st_row_hull(sup, sy, tx0, ty0, tx1, ty1, tile_w, tile_h, vp.W, vp.H, lo, hi, cnt);
       nst += (uint32_t)(hi - lo);
     }
     if (cnt) rect = pack_rect(tx0, ty0, tx1, ty1);

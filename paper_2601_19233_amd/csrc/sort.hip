@@ -1,9 +1,10 @@
-// Stable LSD radix sort of 32- or 16-bit keys with 32-bit values, at most 8
-// bits a pass.  Two sorts use it: the records by depth key (values: record
-// ids, so equal depths stay in id order), and the duplicates -- emitted in
-// that depth order -- by global tile id (16-bit keys while a frame has at
-// most 2^16 tiles), which leaves every tile's list ordered by (depth key,
-// record id).
+// Stable LSD radix sort of 32- or 16-bit keys with 32-bit values (and, for
+// the second use, a 64-bit payload), at most 8 bits a pass.  Two sorts use
+// it: the records by depth key (values: record ids, so equal depths stay in
+// id order), and the supertile entries -- emitted in that depth order -- by
+// supertile id (16-bit keys while a frame has at most 2^16 supertiles;
+// payload: the entry's tile mask), which leaves every supertile's entries
+// ordered by (depth key, record id).
 //
 // Each pass is reduce-then-scan: an upsweep writes per-block digit counts in
 // digit-major order, an exclusive scan turns them into global offsets, and a
@@ -94,10 +95,11 @@ __global__ __launch_bounds__(kThreads) void rs_upsweep(const K *__restrict__ key
   hist[(uint64_t)tid * a.nblocks + blk] = s;
 }
 
-template <typename K>
+// With P64, a 64-bit payload per element (pin/pout) moves with its key.
+template <typename K, bool P64>
 __global__ __launch_bounds__(kThreads) void rs_downsweep(
-    const K *__restrict__ kin, const uint32_t *__restrict__ vin,
-    K *__restrict__ kout, uint32_t *__restrict__ vout, PassArgs a,
+    const K *__restrict__ kin, const uint32_t *__restrict__ vin, const uint64_t *__restrict__ pin,
+    K *__restrict__ kout, uint32_t *__restrict__ vout, uint64_t *__restrict__ pout, PassArgs a,
     const uint32_t *__restrict__ offs) {
   const uint32_t n = pass_count(a);
   const uint32_t blk = xcd_block(blockIdx.x, a.nblocks);
@@ -109,11 +111,13 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
     for (uint32_t i = base + tid; i < end; i += kThreads) {
       kout[i] = kin[i];
       vout[i] = vin[i];
+      if (P64) pout[i] = pin[i];
     }
     return;
   }
   __shared__ K sk[kTile];
   __shared__ uint32_t sv[kTile];
+  __shared__ uint64_t sp[P64 ? kTile : 1];
   __shared__ uint32_t wcnt[kWaves][kBins];
   __shared__ uint32_t lstart[kBins];
   __shared__ uint32_t gbase[kBins];
@@ -126,6 +130,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   K key[kRounds];
   uint32_t val[kRounds];
+  uint64_t pay[P64 ? kRounds : 1];
   uint32_t rank[kRounds];   // digit | (rank within the wave) << 8
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
@@ -133,6 +138,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
     const bool valid = idx < n;
     key[r] = valid ? kin[idx] : K(0);
     val[r] = valid ? vin[idx] : 0u;
+    if (P64) pay[P64 ? r : 0] = valid ? pin[idx] : 0ull;
   }
 #pragma unroll
   for (int r = 0; r < kRounds; ++r) {
@@ -180,6 +186,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
       const uint32_t pos = wcnt[w][d] + (rank[r] >> 8);
       sk[pos] = key[r];
       sv[pos] = val[r];
+      if (P64) sp[P64 ? pos : 0] = pay[P64 ? r : 0];
     }
   }
   __syncthreads();
@@ -191,6 +198,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
     const uint32_t o = gbase[d] + (i - lstart[d]);
     kout[o] = k;
     vout[o] = sv[i];
+    if (P64) pout[o] = sp[P64 ? i : 0];
   }
 }
 
@@ -210,9 +218,9 @@ int radix_passes(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
 // The passes split the bits evenly (13 bits: 7 + 6), which keeps the digit
 // runs that the downsweep writes long.
 template <typename K>
-hipError_t launch_radix_sort(Ctx *c, K *keys[2], uint32_t *vals[2], uint64_t n_launch,
-                             const uint32_t *n_dev, const int32_t *bits_dev, int bits, int kid_up,
-                             int kid_scan, int kid_down) {
+hipError_t launch_radix_sort(Ctx *c, K *keys[2], uint32_t *vals[2], uint64_t *pay[2],
+                             uint64_t n_launch, const uint32_t *n_dev, const int32_t *bits_dev,
+                             int bits, int kid_up, int kid_scan, int kid_down) {
   if (n_launch == 0 || bits <= 0) return hipSuccess;
   const uint32_t n = (uint32_t)n_launch;
   const uint32_t nb = (n + kTile - 1) / kTile;
@@ -244,9 +252,16 @@ hipError_t launch_radix_sort(Ctx *c, K *keys[2], uint32_t *vals[2], uint64_t n_l
     if (e != hipSuccess) return e;
     {
       ScopedTimer t(c, kid_down);
-      hipLaunchKernelGGL(rs_downsweep<K>, dim3(nb), dim3(kThreads), 0, c->stream,
-                         (const K *)keys[src], (const uint32_t *)vals[src], keys[dst], vals[dst], a,
-                         (const uint32_t *)hist);
+      if (pay)
+        hipLaunchKernelGGL((rs_downsweep<K, true>), dim3(nb), dim3(kThreads), 0, c->stream,
+                           (const K *)keys[src], (const uint32_t *)vals[src],
+                           (const uint64_t *)pay[src], keys[dst], vals[dst], pay[dst], a,
+                           (const uint32_t *)hist);
+      else
+        hipLaunchKernelGGL((rs_downsweep<K, false>), dim3(nb), dim3(kThreads), 0, c->stream,
+                           (const K *)keys[src], (const uint32_t *)vals[src],
+                           (const uint64_t *)nullptr, keys[dst], vals[dst], (uint64_t *)nullptr, a,
+                           (const uint32_t *)hist);
       e = hipGetLastError();
     }
     if (e != hipSuccess) return e;
@@ -258,14 +273,21 @@ hipError_t launch_radix_sort(Ctx *c, K *keys[2], uint32_t *vals[2], uint64_t n_l
 hipError_t launch_radix_sort_u32(Ctx *c, uint32_t *keys[2], uint32_t *vals[2], uint64_t n_launch,
                                  const uint32_t *n_dev, const int32_t *bits_dev, int bits,
                                  int kid_up, int kid_scan, int kid_down) {
-  return launch_radix_sort<uint32_t>(c, keys, vals, n_launch, n_dev, bits_dev, bits, kid_up,
+  return launch_radix_sort<uint32_t>(c, keys, vals, nullptr, n_launch, n_dev, bits_dev, bits,
+                                     kid_up, kid_scan, kid_down);
+}
+
+hipError_t launch_radix_sort_pay_u32(Ctx *c, uint32_t *keys[2], uint32_t *vals[2],
+                                     uint64_t *pay[2], uint64_t n_launch, const uint32_t *n_dev,
+                                     int bits, int kid_up, int kid_scan, int kid_down) {
+  return launch_radix_sort<uint32_t>(c, keys, vals, pay, n_launch, n_dev, nullptr, bits, kid_up,
                                      kid_scan, kid_down);
 }
 
-hipError_t launch_radix_sort_u16(Ctx *c, uint16_t *keys[2], uint32_t *vals[2], uint64_t n_launch,
-                                 const uint32_t *n_dev, int bits, int kid_up, int kid_scan,
-                                 int kid_down) {
-  return launch_radix_sort<uint16_t>(c, keys, vals, n_launch, n_dev, nullptr, bits, kid_up,
+hipError_t launch_radix_sort_pay_u16(Ctx *c, uint16_t *keys[2], uint32_t *vals[2],
+                                     uint64_t *pay[2], uint64_t n_launch, const uint32_t *n_dev,
+                                     int bits, int kid_up, int kid_scan, int kid_down) {
+  return launch_radix_sort<uint16_t>(c, keys, vals, pay, n_launch, n_dev, nullptr, bits, kid_up,
                                      kid_scan, kid_down);
 }
 

@@ -91,11 +91,11 @@ __device__ __forceinline__ void support_row(const Support &s, int ty, int tile_w
   b = (int)c1 / tile_w + 1;
 }
 
-// Supertile columns [lo, hi) of supertile row sy that a record reaches: the
-// hull of the supertile columns of its tile rows' support spans in that row
-// (empty: lo = hi); tiles += the record's tiles in the row.  Triangles pass a
-// Support with exact = false (whole rectangle rows).
-__device__ __forceinline__ void st_row_span(const Support &s, int sy, int tx0, int ty0, int tx1,
+// Supertile row sy of a record: the hull [lo, hi) of the supertile columns
+// of its tile rows' support spans (lo = hi: none), and tiles += the record's
+// tiles in the row.  Triangles pass a Support with exact = false (whole
+// rectangle rows).
+__device__ __forceinline__ void st_row_hull(const Support &s, int sy, int tx0, int ty0, int tx1,
                                             int ty1, int tile_w, int tile_h, int W, int H,
                                             int &lo, int &hi, uint32_t &tiles) {
   lo = 0x7FFFFFFF;
@@ -111,6 +111,24 @@ __device__ __forceinline__ void st_row_span(const Support &s, int sy, int tx0, i
     }
   }
   if (lo >= hi) lo = hi = 0;
+}
+
+// Tiles of supertile (sx, sy) that the record reaches, as the 64 bits
+// (ty - sy kST) kST + (tx - sx kST): the same support rows, cut to the
+// supertile's columns.
+__device__ __forceinline__ uint64_t st_mask(const Support &s, int sx, int sy, int tx0, int ty0,
+                                            int tx1, int ty1, int tile_w, int tile_h, int W,
+                                            int H) {
+  const int c0 = sx << kSTLog, y0 = sy << kSTLog;
+  const int r0 = max(ty0, y0), r1 = min(ty1, y0 + kST);
+  uint64_t m = 0;
+  for (int ty = r0; ty < r1; ++ty) {
+    int a, b;
+    support_row(s, ty, tile_w, tile_h, W, H, tx0, tx1, a, b);
+    const int l = max(a, c0), h = min(b, c0 + kST);
+    if (l < h) m |= ((1ull << (h - l)) - 1ull) << ((l - c0) + ((ty - y0) << kSTLog));
+  }
+  return m;
 }
 
 }  // namespace umgs
