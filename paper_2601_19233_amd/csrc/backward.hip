@@ -79,8 +79,8 @@ struct PixBwd {
 // wave sums that follow see defined values on all lanes.
 __device__ __forceinline__ bool gauss_bwd(const uint32_t *s, int pos, float pcx, float pcy,
                                           PixBwd &q, float *g) {
-  float alpha, G, dx, dy;
-  const bool hit = gauss_terms(s, pcx, pcy, alpha, G, dx, dy);
+  float alpha, a_un, dx, dy;
+  const bool hit = gauss_terms(s, pcx, pcy, alpha, a_un, dx, dy);
   const bool contrib = pos < q.last && hit;
   if (contrib && q.in_ent) {
     q.B0 = 0.25f * ((q.s0[0] + q.s1[0]) + (q.s2[0] + q.s3[0]));
@@ -102,19 +102,19 @@ __device__ __forceinline__ bool gauss_bwd(const uint32_t *s, int pos, float pcx,
     q.Tr = Tb;
   }
   // alpha below the 0.99 clamp depends on power and opacity
-  const float op = __uint_as_float(s[5]);
-  const float dpow = (op * G < kAlphaMax) ? dLda : 0.0f;
+  const float dpow = (a_un < kAlphaMax) ? dLda : 0.0f;
   const float qa = __uint_as_float(s[2]), qb = __uint_as_float(s[3]), qc = __uint_as_float(s[4]);
-  const float dp = alpha * dpow;     // d alpha / d power = o G = alpha
+  const float dp = alpha * dpow;     // d alpha / d power = o exp(power) = alpha
+  const float dpl = dp * kLn2;       // the stored coefficients carry log2(e)
   // offsets of other lanes may be huge (a far mean): keep 0 x inf out
   dx = contrib ? dx : 0.0f;
   dy = contrib ? dy : 0.0f;
-  g[0] = dp * (2.0f * qa * dx + qb * dy);
-  g[1] = dp * (qb * dx + 2.0f * qc * dy);
+  g[0] = dpl * (2.0f * qa * dx + qb * dy);
+  g[1] = dpl * (qb * dx + 2.0f * qc * dy);
   g[2] = dp * dx * dx;
   g[3] = dp * dx * dy;
   g[4] = dp * dy * dy;
-  g[5] = G * dpow;
+  g[5] = a_un * __uint_as_float(s[kSlotInvO]) * dpow;   // d alpha / d o = exp(power)
   g[6] = w * q.dC0;
   g[7] = w * q.dC1;
   g[8] = w * q.dC2;
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(TW *TH / PPT) void blend_backward_kernel(
     for (int f = tid; f < bn; f += NTH) {
       const uint32_t *s = slots + f * kSlotWords;
       if ((s[31] & 1u) != 0u) continue;
-      float *dst = g2d + 9 * (int64_t)s[9];
+      float *dst = g2d + 9 * (int64_t)s[kSlotRec];
 #pragma unroll
       for (int k = 0; k < 9; ++k) {
         float r = 0.0f;

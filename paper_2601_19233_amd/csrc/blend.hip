@@ -88,51 +88,58 @@ __device__ __forceinline__ void blend_tile(
     if (!done && !any_tri) {
       // Gaussians only: alpha of kUnroll fragments evaluated together (they
       // do not depend on the pixel's state), then blended in list order.
+      // Every decision is a per-lane select: a fragment that does not
+      // contribute gets alpha 0; Tl, the live transmittance, drops to exactly
+      // 0 when the pixel stops (so later fragments add w = 0 and never blend)
+      // while Tf keeps the pixel's final value.  A stop is a fragment whose
+      // T (1 - alpha) would fall below 1e-4 (once stopped, T l = 0 satisfies
+      // that test again, which changes nothing).
       constexpr int kUnroll = 4;
+      float Tl = Tr, Tf = Tr;
+      const int32_t last0 = last;
       uint32_t f = 0;
       for (; f + kUnroll <= bn; f += kUnroll) {
-        if (__all(done)) break;
+        if (__all(Tl == 0.0f)) break;
         if (COUNT) n_wit += kUnroll;
         float al[kUnroll], cr[kUnroll], cg[kUnroll], cb[kUnroll];
-        bool ok[kUnroll];
 #pragma unroll
         for (int k = 0; k < kUnroll; ++k) {
           const uint32_t *s = slots + (f + k) * kSlotWords;
-          ok[k] = gauss_alpha(s, pcx, pcy, al[k]);
+          float a;
+          const bool ok = gauss_alpha(s, pcx, pcy, a);
+          al[k] = ok ? a : 0.0f;
           cr[k] = __uint_as_float(s[6]);
           cg[k] = __uint_as_float(s[7]);
           cb[k] = __uint_as_float(s[8]);
         }
-        // selects instead of branches: a fragment that is not blended adds
-        // w = 0 (C + 0 c == C exactly for the finite, non-negative colours)
 #pragma unroll
         for (int k = 0; k < kUnroll; ++k) {
-          if (COUNT) n_gp += done ? 0u : 1u;
-          const bool take = !done && ok[k];
-          const float wk = Tr * al[k];
-          const float test_T = Tr - wk;     // T (1 - alpha)
-          const bool below = test_T < kTStop;
-          const bool stop = take && below;
-          const bool blend = take && !below;
-          done = done || stop;
-          const float w = blend ? wk : 0.0f;
-          C0 = fmaf(w, cr[k], C0);
-          C1 = fmaf(w, cg[k], C1);
-          C2 = fmaf(w, cb[k], C2);
-          Tent = blend ? Tr : Tent;
-          Tr = blend ? test_T : Tr;
-          if (mode != UMGS_MODE_ONE_ENTITY) in_entity = in_entity && !blend;
+          if (COUNT) n_gp += Tl == 0.0f ? 0u : 1u;
+          const float w = Tl * al[k];
+          const float test_T = Tl - w;      // T (1 - alpha)
+          const bool stop = test_T < kTStop;
+          const bool blend = !stop && w > 0.0f;
+          const float wc = stop ? 0.0f : w;
+          C0 = fmaf(wc, cr[k], C0);
+          C1 = fmaf(wc, cg[k], C1);
+          C2 = fmaf(wc, cb[k], C2);
+          Tent = blend ? Tl : Tent;
           last = blend ? (int32_t)(bstart - rg.x + f + k + 1) : last;
+          Tf = stop ? Tf : test_T;
+          Tl = stop ? 0.0f : test_T;
         }
       }
+      Tr = Tf;
+      done = Tl == 0.0f;
+      if (mode != UMGS_MODE_ONE_ENTITY && last != last0) in_entity = false;
       for (; f < bn; ++f) {
         if (__all(done)) break;
         if (COUNT) ++n_wit;
         if (done) continue;
         if (COUNT) ++n_gp;
         const uint32_t *s = slots + f * kSlotWords;
-        float alpha, G, dx, dy;
-        if (!gauss_eval(s, pcx, pcy, alpha, G, dx, dy)) continue;
+        float alpha;
+        if (!gauss_alpha(s, pcx, pcy, alpha)) continue;
         const float w = Tr * alpha;
         const float test_T = Tr - w;
         if (test_T < kTStop) { done = true; continue; }
@@ -156,8 +163,8 @@ __device__ __forceinline__ void blend_tile(
           if ((tag & 1u) == 0u) ++n_gp; else ++n_tp;
         }
         if ((tag & 1u) == 0u) {
-          float alpha, G, dx, dy;
-          if (!gauss_eval(s, pcx, pcy, alpha, G, dx, dy)) continue;
+          float alpha;
+          if (!gauss_alpha(s, pcx, pcy, alpha)) continue;
           const float w = Tr * alpha;
           const float test_T = Tr - w;
           if (test_T < kTStop) { done = true; continue; }
@@ -248,8 +255,12 @@ struct BlendArgs {
   float *Tent;
 };
 
+// Six waves per SIMD (at most 80 VGPRs, no spills): while one workgroup
+// waits for its batch's records at the staging barrier, others blend.
+constexpr int kBlendWaves = 6;
+
 template <int TW, int TH>
-__global__ __launch_bounds__(TW *TH) void blend_kernel(BlendArgs a) {
+__global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(kBlendWaves, kBlendWaves))) void blend_kernel(BlendArgs a) {
   extern __shared__ uint32_t slots[];   // batch * kSlotWords
   const uint32_t *vals = a.fi->sorted_in ? a.v1 : a.v0;
   blend_tile<TW, TH>(blockIdx.x, slots, a.views, a.V, a.N, a.T, a.mode, a.batch, a.bg0, a.bg1,
@@ -257,7 +268,7 @@ __global__ __launch_bounds__(TW *TH) void blend_kernel(BlendArgs a) {
 }
 
 template <int TW, int TH>
-__global__ __launch_bounds__(TW *TH) void blend_count_kernel(BlendArgs a,
+__global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(kBlendWaves, kBlendWaves))) void blend_count_kernel(BlendArgs a,
                                                              unsigned long long *pairs) {
   extern __shared__ uint32_t slots[];
   const uint32_t *vals = a.fi->sorted_in ? a.v1 : a.v0;
@@ -270,7 +281,7 @@ __global__ __launch_bounds__(TW *TH) void blend_count_kernel(BlendArgs a,
 // longest-first order until the queue is exhausted (each wave reaches the
 // exit once the counter passes the tile count).
 template <int TW, int TH>
-__global__ __launch_bounds__(TW *TH) void blend_persistent_kernel(BlendArgs a) {
+__global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(kBlendWaves, kBlendWaves))) void blend_persistent_kernel(BlendArgs a) {
   extern __shared__ uint32_t slots[];
   __shared__ uint32_t item;
   const uint32_t *vals = a.fi->sorted_in ? a.v1 : a.v0;

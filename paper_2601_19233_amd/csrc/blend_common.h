@@ -11,8 +11,8 @@ namespace umgs {
 constexpr int kSlotWords = 32;   // one staged fragment: 128 B of LDS
 
 // Slot layout (32-bit words)
-//   Gaussian: 0 mx, 1 my, 2 qa, 3 qb, 4 qc, 5 opacity, 6 r, 7 g, 8 b,
-//             9 record index (view * N + i), 31 tag = 0
+//   Gaussian: 0 mx, 1 my, 2 qa, 3 qb, 4 qc (times log2(e)), 5 lo = log2(o),
+//             6 r, 7 g, 8 b, 9 1/o, 10 record index (view * N + i), 31 tag = 0
 //   triangle: 0-5 E0[3] (FP64 edge functions at the tile's first pixel
 //             centre), 6-11 dmax[3] (FP64, max |offset term| over samples),
 //             12-14 dx[3], 15-17 dy[3] (int32), 18-20 1/z, 21-29 colour/z,
@@ -22,11 +22,15 @@ constexpr int kSlotWords = 32;   // one staged fragment: 128 B of LDS
 __device__ __forceinline__ int sample_ox(int j) { return j == 0 ? -32 : j == 1 ? 96 : j == 2 ? -96 : 32; }
 __device__ __forceinline__ int sample_oy(int j) { return j == 0 ? -96 : j == 1 ? -32 : j == 2 ? 32 : 96; }
 
+constexpr int kSlotInvO = 9;
+constexpr int kSlotRec = 10;
+
 __device__ __forceinline__ void stage_gauss(uint32_t *s, const GaussRec &g, uint32_t rec) {
   *(float4 *)(s + 0) = make_float4(g.mx, g.my, g.qa, g.qb);
-  *(float4 *)(s + 4) = make_float4(g.qc, g.opacity, g.r, g.g);
+  *(float4 *)(s + 4) = make_float4(g.qc, g.lo, g.r, g.g);
   s[8] = __float_as_uint(g.b);
-  s[9] = rec;
+  s[kSlotInvO] = __float_as_uint(g.inv_o);
+  s[kSlotRec] = rec;
   s[31] = 0u;
 }
 
@@ -50,53 +54,41 @@ __device__ __forceinline__ void stage_tri(uint32_t *s, const TriRec &tr, int64_t
   s[31] = 1u | (tr.owned << 8);
 }
 
-// power = qa dx^2 + qb dx dy + qc dy^2, evaluated as (qa dx + qb dy) dx +
-// qc dy^2 (5 operations); every kernel takes its decisions from this one
+// p = log2(o exp(power)) = (qa dx + qb dy) dx + (qc dy dy + lo) with the
+// record's log2(e)-scaled coefficients and lo = log2(o) (5 operations);
+// power <= 0 iff p <= lo.  Every kernel takes its decisions from this one
 // expression.
-__device__ __forceinline__ float gauss_power(float qa, float qb, float qc, float dx, float dy) {
-  return fmaf(fmaf(qa, dx, qb * dy), dx, qc * (dy * dy));
+__device__ __forceinline__ float gauss_logalpha(float qa, float qb, float qc, float lo, float dx,
+                                                float dy) {
+  return fmaf(fmaf(qa, dx, qb * dy), dx, fmaf(qc * dy, dy, lo));
 }
 
-// Gaussian: power and alpha at the pixel centre.  Returns whether the
-// fragment contributes (power <= 0 and alpha >= 1/255).
-__device__ __forceinline__ bool gauss_eval(const uint32_t *s, float pcx, float pcy, float &alpha,
-                                           float &G, float &dx, float &dy) {
-  const float4 a = *(const float4 *)(s + 0);
-  const float4 b = *(const float4 *)(s + 4);
-  dx = a.x - pcx;
-  dy = a.y - pcy;
-  const float power = gauss_power(a.z, a.w, b.x, dx, dy);
-  if (power > 0.0f) return false;
-  G = __expf(power);
-  alpha = fminf(kAlphaMax, b.y * G);
-  return alpha >= kAlphaMin;
-}
-
-// The same decision without branches (exp evaluated even where power > 0;
-// the result is then discarded): lets several fragments be evaluated
-// together.  Bit-identical alpha and decision to gauss_eval.
+// Gaussian: alpha = min(0.99, 2^p) at the pixel centre, without branches
+// (lanes where power > 0 compute a value that is then discarded).  Returns
+// whether the fragment contributes (power <= 0 and alpha >= 1/255).
 __device__ __forceinline__ bool gauss_alpha(const uint32_t *s, float pcx, float pcy, float &alpha) {
   const float4 a = *(const float4 *)(s + 0);
   const float4 b = *(const float4 *)(s + 4);
   const float dx = a.x - pcx;
   const float dy = a.y - pcy;
-  const float power = gauss_power(a.z, a.w, b.x, dx, dy);
-  alpha = fminf(kAlphaMax, b.y * __expf(power));
-  return power <= 0.0f && alpha >= kAlphaMin;
+  const float p = gauss_logalpha(a.z, a.w, b.x, b.y, dx, dy);
+  alpha = fminf(kAlphaMax, __builtin_amdgcn_exp2f(p));
+  return p <= b.y && alpha >= kAlphaMin;
 }
 
-// gauss_alpha that also returns G = exp(power) and the offsets the
-// gradients need (all finite for any record; meaningful when it returns true).
+// gauss_alpha that also returns a = o exp(power) before the clamp (o where
+// power > 0) and the offsets the gradients need (all finite for any record;
+// meaningful when it returns true).  Bit-identical alpha and decision.
 __device__ __forceinline__ bool gauss_terms(const uint32_t *s, float pcx, float pcy, float &alpha,
-                                            float &G, float &dx, float &dy) {
+                                            float &a_un, float &dx, float &dy) {
   const float4 a = *(const float4 *)(s + 0);
   const float4 b = *(const float4 *)(s + 4);
   dx = a.x - pcx;
   dy = a.y - pcy;
-  const float power = gauss_power(a.z, a.w, b.x, dx, dy);
-  const bool inside = power <= 0.0f;
-  G = __expf(inside ? power : 0.0f);
-  alpha = fminf(kAlphaMax, b.y * G);
+  const float p = gauss_logalpha(a.z, a.w, b.x, b.y, dx, dy);
+  const bool inside = p <= b.y;
+  a_un = __builtin_amdgcn_exp2f(inside ? p : b.y);
+  alpha = fminf(kAlphaMax, a_un);
   return inside && alpha >= kAlphaMin;
 }
 

@@ -42,14 +42,23 @@ struct ViewParams {
   int64_t pix_base;      // first pixel of this view in the packed per-pixel arrays
 };
 
-// Projected Gaussian as the blend stage reads it (48 B, 16-B aligned).
+// Projected Gaussian as the blend stage reads it (48 B, 16-B aligned).  The
+// power coefficients are stored times log2(e) next to lo = log2(opacity), so
+// that p = (qa dx^2 + qb dx dy + qc dy^2) + lo is log2(o exp(power)) and
+// alpha = min(0.99, 2^p) takes one exp2 and no further products.
 struct __align__(16) GaussRec {
   float mx, my;          // mean in pixels
-  float qa, qb, qc;      // power = qa dx^2 + qb dx dy + qc dy^2 (= -conic/2 form)
+  float qa, qb, qc;      // log2(e) x power coefficients (power = -d^T conic d / 2)
   float opacity;
   float r, g, b;
-  float pad[3];
+  float lo;              // log2(opacity)
+  float inv_o;           // 1 / opacity
+  float pad;
 };
+
+constexpr float kLog2e = 1.44269504088896341f;
+constexpr float kLn2 = 0.69314718055994531f;
+constexpr float kLog2_255 = 7.99435343685885793f;   // log2(255): alpha >= 1/255 iff p >= -this
 
 // Set-up triangle (80 B): snapped vertices after orientation normalisation,
 // per-vertex 1/z and colour/z for perspective-correct colour, alpha, and the

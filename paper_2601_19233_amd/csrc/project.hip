@@ -197,14 +197,17 @@ __device__ uint32_t project_gaussian(const ViewParams *__restrict__ views, int N
   GaussRec rec;
   rec.mx = mx;
   rec.my = my;
-  rec.qa = -0.5f * cc * idet;   // -conic_a / 2
-  rec.qb = cb * idet;           // -conic_b
-  rec.qc = -0.5f * ca * idet;   // -conic_c / 2
+  const float sdet = idet * kLog2e;
+  rec.qa = -0.5f * cc * sdet;   // log2(e) x (-conic_a / 2)
+  rec.qb = cb * sdet;           // log2(e) x (-conic_b)
+  rec.qc = -0.5f * ca * sdet;   // log2(e) x (-conic_c / 2)
   rec.opacity = o;
   rec.r = r;
   rec.g = g;
   rec.b = b;
-  rec.pad[0] = rec.pad[1] = rec.pad[2] = 0.0f;
+  rec.lo = __builtin_amdgcn_logf(o);   // log2
+  rec.inv_o = 1.0f / o;
+  rec.pad = 0.0f;
   grec[(int64_t)v * N + i] = rec;
 
   // tiles: the rows of the bounding rectangle, each cut to the support;

@@ -4,9 +4,9 @@
 //
 // A Gaussian contributes to a pixel only where alpha = min(0.99, o exp(power))
 // >= 1/255 (Eq. 1-2 with the 3DGS cut-off), i.e. where
-//   Q(d) = A dx^2 + B dx dy + C dy^2 <= L = ln(255 o),
-// with A, B, C the negated FP32 power coefficients of its record -- the very
-// numbers the blend evaluates.  The blend evaluates Q in FP32: each term
+//   Q(d) = A dx^2 + B dx dy + C dy^2 <= L = log2(o) + log2(255),
+// with A, B, C the negated FP32 power coefficients of its record (stored times
+// log2(e), next to log2(o)) -- the very numbers the blend evaluates.  The blend evaluates Q in FP32: each term
 // carries a few roundings, so |Q_fp32 - Q| <= 1e-6 kappa Q with kappa the
 // condition number of the form, and exp and the products move the threshold
 // by well under 1e-3.  The support used here is the ellipse
@@ -40,7 +40,7 @@ __device__ __forceinline__ Support make_support(const GaussRec &g) {
   s.C = -g.qc;
   const double Dd = 4.0 * (double)s.A * (double)s.C - (double)s.B * (double)s.B;
   s.D = (float)Dd;
-  const float L = __logf(255.0f * g.opacity);
+  const float L = g.lo + kLog2_255;
   const float h = __builtin_amdgcn_sqrtf((s.A - s.C) * (s.A - s.C) + s.B * s.B);
   const float lmax = 0.5f * ((s.A + s.C) + h);
   const float lmin = s.D * __builtin_amdgcn_rcpf(4.0f * lmax);   // eigenvalue product is D/4
