@@ -321,10 +321,11 @@ __global__ void chunk_total_kernel(const uint32_t *__restrict__ chunk_base, int6
   fi->n_chunks = chunk_base[n_st];
 }
 
-// A second-level chunk: entries [e0, e1) of the supertile whose first tile
-// is (cxy & 0xFFFF, cxy >> 16) in view v.
+// A second-level chunk: entries [e0, e0 + n) of the supertile whose first
+// tile is (cxy & 0xFFFF, cxy >> 16) in view v, the supertile's chunk k
+// (nk = n | k << 11; n <= kChunk = 1024).
 struct __align__(16) ChunkRec {
-  uint32_t e0, e1, v, cxy;
+  uint32_t e0, nk, v, cxy;
 };
 
 // The view whose supertiles [st_base, next st_base) hold s.
@@ -354,7 +355,7 @@ __global__ void chunk_table_kernel(const ViewParams *__restrict__ views, int V,
   for (uint32_t c = c0; c < c1; ++c) {
     ChunkRec k;
     k.e0 = r.x + (c - c0) * (uint32_t)kChunk;
-    k.e1 = min(k.e0 + (uint32_t)kChunk, r.y);
+    k.nk = (min(k.e0 + (uint32_t)kChunk, r.y) - k.e0) | ((c - c0) << 11);
     k.v = (uint32_t)v;
     k.cxy = cxy;
     tab[c] = k;
@@ -371,7 +372,7 @@ struct L2Args {
   const uint32_t *rec;         // sorted entries' record ids
   const FrameInfo *fi;
   const uint64_t *masks;       // sorted entries' masks: tiles of the supertile they reach
-  uint32_t *cnt;               // per chunk 64 tile counts, then their prefix over the chunks
+  uint32_t *cnt;               // per chunk 64 tile counts
   uint32_t *tstart;            // per tile: count, then (scanned) first position
   uint32_t *out;               // record ids in tile order
 };
@@ -397,9 +398,10 @@ __global__ __launch_bounds__(kL2Threads) void tile_count_kernel(L2Args a) {
   const ChunkRec ck = a.chunks[c];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   uint32_t acc = 0;
-  for (uint32_t e0 = ck.e0; e0 < ck.e1; e0 += kL2Threads) {
+  const uint32_t e1 = ck.e0 + (ck.nk & 0x7FFu);
+  for (uint32_t e0 = ck.e0; e0 < e1; e0 += kL2Threads) {
     const uint32_t e = e0 + tid;
-    acc += wave_bit_counts(e < ck.e1 ? a.masks[e] : 0ull);
+    acc += wave_bit_counts(e < e1 ? a.masks[e] : 0ull);
   }
   wc[w][lane] = acc;
   __syncthreads();
@@ -411,9 +413,9 @@ __global__ __launch_bounds__(kL2Threads) void tile_count_kernel(L2Args a) {
   }
 }
 
-// Per (supertile, tile j): exclusive prefix of the chunk counts over the
-// supertile's chunks (in place) and the tile's total at its global tile id
-// (every tile of every view is one (supertile, j) pair).
+// Per (supertile, tile j): the tile's total over the supertile's chunks, at
+// its global tile id (every tile of every view is one (supertile, j) pair).
+// Loads only, so they are all in flight together.
 __global__ void tile_prefix_kernel(L2Args a) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g == 0) a.tstart[a.n_tiles] = 0;
@@ -422,11 +424,8 @@ __global__ void tile_prefix_kernel(L2Args a) {
   if (s >= a.n_st) return;
   const uint32_t c0 = a.chunk_base[s], c1 = a.chunk_base[s + 1];
   uint32_t run = 0;
-  for (uint32_t c = c0; c < c1; ++c) {
-    const uint32_t x = a.cnt[(uint64_t)c * 64 + j];
-    a.cnt[(uint64_t)c * 64 + j] = run;
-    run += x;
-  }
+#pragma unroll 8
+  for (uint32_t c = c0; c < c1; ++c) run += a.cnt[(uint64_t)c * 64 + j];
   const int v = view_of_st(a.views, a.V, (uint32_t)s);
   const ViewParams &vp = a.views[v];
   const uint32_t sl = (uint32_t)s - vp.st_base;
@@ -446,8 +445,9 @@ __global__ void ranges_kernel(const uint32_t *__restrict__ tstart, int64_t n_til
 }
 
 // Each entry's record id to every tile of its mask, at the tile's first
-// position + the chunk's prefix + the entry's rank among the chunk's
-// entries with that bit (earlier rounds, earlier waves, earlier lanes).
+// position + the counts of the supertile's earlier chunks + the entry's rank
+// among the chunk's entries with that bit (earlier rounds, earlier waves,
+// earlier lanes).
 // Stores go tile by tile, so the lanes of a store write consecutive words.
 __global__ __launch_bounds__(kL2Threads) void tile_scatter_kernel(L2Args a) {
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x);
@@ -461,15 +461,20 @@ __global__ __launch_bounds__(kL2Threads) void tile_scatter_kernel(L2Args a) {
     const int tx = (int)(ck.cxy & 0xFFFF) + (tid & (kST - 1));
     const int ty = (int)(ck.cxy >> 16) + (tid >> kSTLog);
     uint32_t b = 0;
-    if (tx < vp.ntx && ty < vp.nty)
-      b = a.tstart[vp.tile_base + (uint32_t)ty * vp.ntx + tx] + a.cnt[(uint64_t)c * 64 + tid];
+    if (tx < vp.ntx && ty < vp.nty) {
+      b = a.tstart[vp.tile_base + (uint32_t)ty * vp.ntx + tx];
+      const uint32_t k = ck.nk >> 11;   // earlier chunks of the supertile: c - k .. c - 1
+#pragma unroll 8
+      for (uint32_t i = 0; i < k; ++i) b += a.cnt[(uint64_t)(c - k + i) * 64 + tid];
+    }
     base[tid] = b;
   }
   const uint32_t cap = a.fi->n_dup;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-  for (uint32_t e0 = ck.e0; e0 < ck.e1; e0 += kL2Threads) {
+  const uint32_t e1 = ck.e0 + (ck.nk & 0x7FFu);
+  for (uint32_t e0 = ck.e0; e0 < e1; e0 += kL2Threads) {
     const uint32_t e = e0 + tid;
-    const bool valid = e < ck.e1;
+    const bool valid = e < e1;
     const uint64_t m = valid ? a.masks[e] : 0ull;
     const uint32_t r = valid ? a.rec[e] : 0u;
     wc[w][lane] = wave_bit_counts(m);
