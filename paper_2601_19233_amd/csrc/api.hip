@@ -396,8 +396,7 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
   if (e == hipSuccess && upload)
     e = hipMemcpyAsync(dv, vps.data(), sizeof(ViewParams) * V, hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return hip_check(c, e, "view upload");
-  e = launch_fill_u32(c, (uint32_t *)c->minmax.p, kMinMaxSlots, kCulled);
-  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t *)c->minmax.p + kMinMaxSlots, kMinMaxSlots, 0u);
+  e = launch_minmax_reset(c);
   if (e != hipSuccess) return hip_check(c, e, "depth range reset");
   if ((e = launch_project_gaussians(c, means, cov3d, scales, quats, opacity, sh)) != hipSuccess)
     return hip_check(c, e, "project_gaussians launch");

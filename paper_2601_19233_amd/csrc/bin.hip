@@ -145,7 +145,11 @@ __global__ void frame_totals_kernel(const unsigned long long *__restrict__ view_
 
 // Depth range of the frame: sort keys hold (depth key - base) in depth_bits.
 // One wave folds the slot pairs the projection kernels filled.
-__global__ void depth_range_kernel(const uint32_t *__restrict__ minmax, FrameInfo *__restrict__ fi) {
+// It also clears the per-view duplicate sums (V x uint64) the count stage
+// adds into.
+__global__ void depth_range_kernel(const uint32_t *__restrict__ minmax, FrameInfo *__restrict__ fi,
+                                   uint32_t *__restrict__ view_sums, int V) {
+  for (int k = threadIdx.x; k < 2 * V; k += blockDim.x) view_sums[k] = 0u;
   const uint32_t lo = wave_min_u32(minmax[threadIdx.x]);
   const uint32_t hi = wave_max_u32(minmax[kMinMaxSlots + threadIdx.x]);
   if (threadIdx.x != 0) return;
@@ -170,12 +174,21 @@ __global__ void depth_prep_kernel(const uint32_t *__restrict__ depth, int64_t n,
 
 // Supertile-entry counts (high 32 bits of a record's count) in depth order;
 // the entry past the end receives 0, so the scan leaves the total there.
+// The grid also clears the supertile ranges (empty supertiles keep [0, 0)).
 __global__ void gather_st_counts_kernel(const uint32_t *__restrict__ order, int64_t n,
                                         const uint64_t *__restrict__ counts,
-                                        uint64_t *__restrict__ out) {
+                                        uint64_t *__restrict__ out, uint32_t *__restrict__ st_rng,
+                                        int64_t n_rng) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = counts[order[i]] >> 32;
   else if (i == n) out[n] = 0;
+  for (int64_t k = i; k < n_rng; k += (int64_t)gridDim.x * blockDim.x) st_rng[k] = 0u;
+}
+
+// Resets the depth-key range slots the projection folds into.
+__global__ void minmax_reset_kernel(uint32_t *__restrict__ minmax) {
+  const int k = threadIdx.x;
+  minmax[k] = k < kMinMaxSlots ? kCulled : 0u;
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
@@ -530,6 +543,13 @@ hipError_t launch_exclusive_scan_u32(Ctx *c, uint32_t *data, int64_t n, uint32_t
   return excl_scan<uint32_t>(c->stream, data, n, tmp);
 }
 
+hipError_t launch_minmax_reset(Ctx *c) {
+  static_assert(2 * kMinMaxSlots <= 1024, "one workgroup");
+  hipLaunchKernelGGL(minmax_reset_kernel, dim3(1), dim3(2 * kMinMaxSlots), 0, c->stream,
+                     (uint32_t *)c->minmax.p);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u32_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, c->stream, p, n, v);
@@ -561,7 +581,7 @@ hipError_t launch_depth_order(Ctx *c) {
     ScopedTimer t(c, K_DEPTH_SORT);
     static_assert(kMinMaxSlots == 64, "one wave folds the slots");
     hipLaunchKernelGGL(depth_range_kernel, dim3(1), dim3(kMinMaxSlots), 0, c->stream,
-                       (const uint32_t *)c->minmax.p, fi);
+                       (const uint32_t *)c->minmax.p, fi, (uint32_t *)c->view_sums.p, c->V);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n > 0) {
       hipLaunchKernelGGL(depth_prep_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, c->stream,
@@ -577,12 +597,19 @@ hipError_t launch_depth_order(Ctx *c) {
   ScopedTimer t(c, K_SCAN);
   hipLaunchKernelGGL(gather_st_counts_kernel, dim3(ceil_div(n + 1, 256)), dim3(256), 0, c->stream,
                      (const uint32_t *)c->dv[0].p, n, (const uint64_t *)c->counts.p,
-                     (uint64_t *)c->offs.p);
+                     (uint64_t *)c->offs.p, (uint32_t *)c->st_rng.p, 2 * c->n_st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if ((e = excl_scan<uint64_t>(c->stream, (uint64_t *)c->offs.p, n + 1,
                                (uint64_t *)c->scan_tmp.p)) != hipSuccess)
     return e;
-  if ((e = launch_view_sums(c, (unsigned long long *)c->view_sums.p)) != hipSuccess) return e;
+  // the view sums were cleared by depth_range_kernel
+  const int64_t per = (int64_t)c->N + c->T;
+  if (per > 0) {
+    hipLaunchKernelGGL(view_sum_kernel, dim3(ceil_div(per, kScanTile), c->V), dim3(kScanThreads), 0,
+                       c->stream, (const uint64_t *)c->counts.p, per,
+                       (unsigned long long *)c->view_sums.p);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(frame_totals_kernel, dim3(1), dim3(64), 0, c->stream,
                      (const unsigned long long *)c->view_sums.p, c->V,
                      (const uint64_t *)c->offs.p + n, (uint64_t *)c->totals.p);
@@ -668,8 +695,7 @@ hipError_t launch_st_bin(Ctx *c) {
   if (e != hipSuccess) return e;
   c->st_sorted = out;
   ScopedTimer t(c, K_RANGES);
-  uint2 *rng = (uint2 *)c->st_rng.p;
-  if ((e = launch_fill_u32(c, (uint32_t *)rng, 2 * c->n_st, 0u)) != hipSuccess) return e;
+  uint2 *rng = (uint2 *)c->st_rng.p;   // cleared by gather_st_counts_kernel
   if (c->st_key16)
     hipLaunchKernelGGL(st_ranges_kernel<uint16_t>, dim3(ceil_div(c->st_launch, 1024)), dim3(256), 0,
                        c->stream, (const uint16_t *)c->sk[out].p, (const FrameInfo *)fi, rng);

@@ -201,6 +201,7 @@ hipError_t launch_setup_triangles(Ctx *c, const float *tri_xyz, const float *tri
 hipError_t launch_exclusive_scan_u32(Ctx *c, uint32_t *data, int64_t n, uint32_t *tmp);
 hipError_t launch_exclusive_scan_u64(Ctx *c, uint64_t *data, int64_t n, uint64_t *tmp);
 hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v);
+hipError_t launch_minmax_reset(Ctx *c);
 size_t scan_tmp_bytes(int64_t n);
 hipError_t launch_view_sums(Ctx *c, unsigned long long *sums);
 hipError_t launch_depth_order(Ctx *c);
