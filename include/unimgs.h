@@ -248,10 +248,12 @@ umgs_status umgs_graph_launch(umgs_ctx *ctx);
  * stream.  Errors: INVALID_ARG, STATE (no stored set equals old_cams). */
 umgs_status umgs_update_views(umgs_ctx *ctx, int32_t V, const umgs_camera *old_cams,
                               const umgs_camera *new_cams);
-/* Duplicates each view of the projected frame will produce, dups [host] (V
- * entries), before umgs_bin allocates anything: used to split a batch whose
- * duplicates exceed the 32-bit positions of one frame into view groups.
- * Runs the count scan if needed; synchronous.  Errors: STATE. */
+/* Upper bound of the duplicates each view of the projected frame will
+ * produce, dups [host] (V entries): the tiles of its primitives' bounding
+ * rectangles (the tile lists keep those the support reaches), known before
+ * umgs_bin allocates anything: used to split a batch whose duplicates exceed
+ * the 32-bit positions of one frame into view groups.  Synchronous.
+ * Errors: STATE. */
 umgs_status umgs_view_dups(umgs_ctx *ctx, int64_t *dups);
 
 /* Measurement: blend the sorted frame again into image [device] while
@@ -265,8 +267,9 @@ umgs_status umgs_view_dups(umgs_ctx *ctx, int64_t *dups);
  * STATE before umgs_sort. */
 umgs_status umgs_blend_pairs(umgs_ctx *ctx, float *image, int64_t *pairs);
 
-/* Sizes of the current frame: n_dup (duplicates sorted, at most the
- * reserved capacity), n_tiles (all views), the record count V*(N+T) and
+/* Sizes of the current frame: n_dup (duplicates in the tile lists after
+ * umgs_sort, at most the reserved capacity; after umgs_bin alone, the
+ * rectangles' upper bound), n_tiles (all views), the record count V*(N+T) and
  * overflow (1 if duplicates were dropped since the flag was last read; the
  * flag is cleared by reading it).  Any pointer may be NULL.  Synchronous. */
 umgs_status umgs_query(umgs_ctx *ctx, int64_t *n_dup, int64_t *n_tiles, int64_t *n_records,

@@ -197,13 +197,15 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
 }
 
 // The frame's sizes on the device, each clamped to its buffer's capacity
-// (overflow flagged, sticky), and the persistent blend's queue reset.
+// (overflow flagged, sticky), and the persistent blend's queue reset.  The
+// duplicates are bounded by the records' rectangles here; the tile scan
+// replaces the bound by the exact count (ranges_kernel).
 __global__ void frame_info_kernel(const uint64_t *__restrict__ totals, uint64_t cap,
                                   uint64_t st_cap, FrameInfo *__restrict__ fi) {
   const uint64_t nd = totals[0], n1 = totals[1];
   fi->n_dup = (uint32_t)(nd < cap ? nd : cap);
   fi->n1 = (uint32_t)(n1 < st_cap ? n1 : st_cap);
-  if (nd > cap || n1 > st_cap) fi->overflow = 1u;
+  if (n1 > st_cap || nd >= 0xFFFF0000ull) fi->overflow = 1u;
   fi->sorted_in = 0;
   fi->queue = 0u;
 }
@@ -231,9 +233,9 @@ __device__ __forceinline__ void unpack_rect(uint2 rc, int &tx0, int &ty0, int &t
   ty1 = rc.y >> 16;
 }
 
-// One thread per record (in depth order) writes its supertile entries,
-// supertile rows top to bottom, columns left to right (their order does not
-// matter: a record has at most one entry per supertile).
+// One thread per record (in depth order) writes one entry per supertile of
+// its tile rectangle, rows top to bottom, columns left to right (their order
+// does not matter: a record has at most one entry per supertile).
 template <typename K>
 __global__ void st_emit_kernel(StEmitArgs e) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -246,16 +248,10 @@ __global__ void st_emit_kernel(StEmitArgs e) {
   int tx0, ty0, tx1, ty1;
   unpack_rect(e.rects[r], tx0, ty0, tx1, ty1);
   const uint32_t v = r / (uint32_t)e.per_view;
-  const int li = (int)(r - v * (uint32_t)e.per_view);
   const ViewParams &vp = e.views[v];
-  Support sup;
-  sup.exact = false;
-  if (li < e.N) sup = make_support(e.grec[(int64_t)v * e.N + li]);
   const uint32_t nstx = (uint32_t)(vp.ntx + kST - 1) >> kSTLog;
-  uint32_t tiles = 0;
+  const int lo = tx0 >> kSTLog, hi = ((tx1 - 1) >> kSTLog) + 1;
   for (int sy = ty0 >> kSTLog; sy <= (ty1 - 1) >> kSTLog; ++sy) {
-    int lo, hi;
-    st_row_hull(sup, sy, tx0, ty0, tx1, ty1, e.tile_w, e.tile_h, vp.W, vp.H, lo, hi, tiles);
     for (int sx = lo; sx < hi; ++sx) {
       if (pos >= end) return;
       keys[pos] = (K)(vp.st_base + (uint32_t)sy * nstx + (uint32_t)sx);
@@ -388,6 +384,7 @@ struct L2Args {
   uint32_t *cnt;               // per chunk 64 tile counts
   uint32_t *tstart;            // per tile: count, then (scanned) first position
   uint32_t *out;               // record ids in tile order
+  uint32_t cap;                // record ids out holds
 };
 
 // Lane j's result: how many lanes of the wave have bit j of m set.
@@ -448,13 +445,19 @@ __global__ void tile_prefix_kernel(L2Args a) {
   if (tx < vp.ntx && ty < vp.nty) a.tstart[vp.tile_base + (uint32_t)ty * vp.ntx + tx] = run;
 }
 
-// Tile ranges from the scanned tile counts (clamped to the stored duplicates).
-__global__ void ranges_kernel(const uint32_t *__restrict__ tstart, int64_t n_tiles,
-                              const FrameInfo *__restrict__ fi, uint2 *__restrict__ ranges) {
+// Tile ranges from the scanned tile counts, clamped to the capacity of the
+// lists; the first thread stores the frame's exact duplicate count (flagging
+// an overflow of the capacity).
+__global__ void ranges_kernel(const uint32_t *__restrict__ tstart, int64_t n_tiles, uint32_t cap,
+                              FrameInfo *__restrict__ fi, uint2 *__restrict__ ranges) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) {
+    const uint32_t total = tstart[n_tiles];
+    fi->n_dup = min(total, cap);
+    if (total > cap) fi->overflow = 1u;
+  }
   if (t >= n_tiles) return;
-  const uint32_t n = fi->n_dup;
-  ranges[t] = make_uint2(min(tstart[t], n), min(tstart[t + 1], n));
+  ranges[t] = make_uint2(min(tstart[t], cap), min(tstart[t + 1], cap));
 }
 
 // Each entry's record id to every tile of its mask, at the tile's first
@@ -482,7 +485,7 @@ __global__ __launch_bounds__(kL2Threads) void tile_scatter_kernel(L2Args a) {
     }
     base[tid] = b;
   }
-  const uint32_t cap = a.fi->n_dup;
+  const uint32_t cap = a.cap;
   const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const uint32_t e1 = ck.e0 + (ck.nk & 0x7FFu);
   for (uint32_t e0 = ck.e0; e0 < e1; e0 += kL2Threads) {
@@ -738,6 +741,7 @@ hipError_t launch_tile_lists(Ctx *c) {
   a.cnt = (uint32_t *)c->cnt2.p;
   a.tstart = (uint32_t *)c->tstart.p;
   a.out = (uint32_t *)c->v0.p;
+  a.cap = (uint32_t)std::min<uint64_t>(c->key_cap, 0xFFFFFFFFull);
   const unsigned nchunks = (unsigned)max_chunks(c->st_launch, c->n_st);
   hipError_t e;
   {
@@ -756,7 +760,8 @@ hipError_t launch_tile_lists(Ctx *c) {
   {
     ScopedTimer t(c, K_RANGES);
     hipLaunchKernelGGL(ranges_kernel, dim3(ceil_div(c->n_tiles, 256)), dim3(256), 0, c->stream,
-                       (const uint32_t *)a.tstart, c->n_tiles, a.fi, (uint2 *)c->ranges.p);
+                       (const uint32_t *)a.tstart, c->n_tiles, a.cap, (FrameInfo *)c->finfo.p,
+                       (uint2 *)c->ranges.p);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (c->st_launch == 0) return hipSuccess;

@@ -210,21 +210,17 @@ __device__ uint32_t project_gaussian(const ViewParams *__restrict__ views, int N
   rec.pad = 0.0f;
   grec[(int64_t)v * N + i] = rec;
 
-  // tiles: the rows of the bounding rectangle, each cut to the support;
-  // supertile entries: per supertile row, the hull of those rows' supertiles
+  // tiles and supertiles of the bounding rectangle (upper bounds: the masks
+  // of the bin stage cut every row to the support)
   uint32_t cnt = 0, nst = 0;
   uint2 rect = make_uint2(0, 0);
   if (px0 < px1 && py0 < py1) {
     const int tx0 = px0 / tile_w, tx1 = (px1 - 1) / tile_w + 1;
     const int ty0 = py0 / tile_h, ty1 = (py1 - 1) / tile_h + 1;
-    const Support sup = make_support(rec);
-    for (int sy = ty0 >> kSTLog; sy <= (ty1 - 1) >> kSTLog; ++sy) {
-      int lo, hi;
-      st_row_hull(sup, sy, tx0, ty0, tx1, ty1, tile_w, tile_h, vp.W, vp.H, lo, hi, cnt);
-      nst += (uint32_t)(hi - lo);
-    }
-    if (cnt) rect = pack_rect(tx0, ty0, tx1, ty1);
-    else nst = 0;
+    cnt = (uint32_t)((tx1 - tx0) * (ty1 - ty0));
+    nst = (uint32_t)((((tx1 - 1) >> kSTLog) - (tx0 >> kSTLog) + 1) *
+                     (((ty1 - 1) >> kSTLog) - (ty0 >> kSTLog) + 1));
+    rect = pack_rect(tx0, ty0, tx1, ty1);
   }
   keys[rid] = __float_as_uint(zv);
   counts[rid] = (uint64_t)nst << 32 | cnt;

@@ -1,6 +1,5 @@
-// Tile rows of a projected Gaussian's support, shared by the projection
-// (which counts a record's tiles) and the bin stage (which emits them), so
-// both derive the same tiles from the same arithmetic (contraction off).
+// Tile rows of a projected Gaussian's support: the bin stage cuts every
+// entry's supertile to the tiles whose pixel centres the support reaches.
 //
 // A Gaussian contributes to a pixel only where alpha = min(0.99, o exp(power))
 // >= 1/255 (Eq. 1-2 with the 3DGS cut-off), i.e. where
@@ -8,8 +7,8 @@
 // with A, B, C the negated FP32 power coefficients of its record (stored times
 // log2(e), next to log2(o)) -- the very numbers the blend evaluates.  The blend evaluates Q in FP32: each term
 // carries a few roundings, so |Q_fp32 - Q| <= 1e-6 kappa Q with kappa the
-// condition number of the form, and exp and the products move the threshold
-// by well under 1e-3.  The support used here is the ellipse
+// condition number of the form, and exp2 moves the threshold by well under
+// 1e-3.  The support used here is the ellipse
 //   Q <= tau = (L + 1e-3) (1 + 1e-4) / (1 - 1e-6 kappa),
 // whose chords are evaluated in FP32 with the hardware square root and
 // reciprocal (1 ulp; D = 4AC - B^2 in FP64, then rounded) and widened by
@@ -89,28 +88,6 @@ __device__ __forceinline__ void support_row(const Support &s, int ty, int tile_w
   }
   a = (int)c0 / tile_w;
   b = (int)c1 / tile_w + 1;
-}
-
-// Supertile row sy of a record: the hull [lo, hi) of the supertile columns
-// of its tile rows' support spans (lo = hi: none), and tiles += the record's
-// tiles in the row.  Triangles pass a Support with exact = false (whole
-// rectangle rows).
-__device__ __forceinline__ void st_row_hull(const Support &s, int sy, int tx0, int ty0, int tx1,
-                                            int ty1, int tile_w, int tile_h, int W, int H,
-                                            int &lo, int &hi, uint32_t &tiles) {
-  lo = 0x7FFFFFFF;
-  hi = 0;
-  const int r0 = max(ty0, sy << kSTLog), r1 = min(ty1, (sy + 1) << kSTLog);
-  for (int ty = r0; ty < r1; ++ty) {
-    int a, b;
-    support_row(s, ty, tile_w, tile_h, W, H, tx0, tx1, a, b);
-    if (a < b) {
-      tiles += (uint32_t)(b - a);
-      lo = min(lo, a >> kSTLog);
-      hi = max(hi, ((b - 1) >> kSTLog) + 1);
-    }
-  }
-  if (lo >= hi) lo = hi = 0;
 }
 
 // Tiles of supertile (sx, sy) that the record reaches, as the 64 bits
