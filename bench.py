@@ -184,7 +184,7 @@ def batched_leg(s, cams, name, args):
     # tuned on the first four views (one frame of them fits the key buffers at
     # every tile shape); the step itself renders all views in budgeted groups
     best = autotune.tune(cams[:4], tsc, sh_degree=s.sh_degree, k_bind=k_bind, reps=2,
-                         batches=(64, 128, 256), use_cache=False)
+                         batches=(32, 64, 128), use_cache=False)
     log(f"autotune {best['tile']} batch {best['frag_batch']} schedule {best['schedule']} "
         f"in {time.time() - t0:.1f} s")
     del r0, dt, tsc
@@ -333,7 +333,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="primitive-count scale (1 = full workload)")
     ap.add_argument("--res-scale", type=float, default=1.0)
     ap.add_argument("--tile", default="16x16")
-    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--schedule", type=int, default=0, help="blend schedule: 0 tile grid, 1 persistent")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
@@ -501,6 +501,35 @@ def main():
                "loss": "L2 against the render of N(0, 0.01)-perturbed raw Gaussian parameters"}
     log(f"fwd+bwd {ms_fb:.3f} ms/step")
 
+    # ---- the same frame captured in one HIP graph ---------------------------
+    # (sizes stay on the device after one eager frame and a reservation, so
+    # the bin stage needs no host synchronisation)
+    from paper_2601_19233_amd.batched import BatchedStep
+    rg = Rasterizer("cuda:0", tile=(tw, th), frag_batch=args.batch, sh_degree=scene.sh_degree,
+                    k_bind=scene.bind_face.shape[1], schedule=args.schedule, own_stream=True)
+    rg.set_proxy(scene.proxy.V_rest, scene.proxy.faces)
+    gsc = dict(means=means, scales=scales, quats=quats, opacity=opac, sh=sh, tri_xyz=txyz,
+               tri_rgb=trgb, tri_alpha=tal)
+    gstep = BatchedStep(rg, [cam], gsc, deform=dict(V_def=V_def, bind_face=bface, bind_bary=bbary))
+    gstep.prepare()
+    for _ in range(args.warmup):
+        gstep()
+    torch.cuda.synchronize()
+    gs = rg.stream
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record(gs)
+    for _ in range(args.steps):
+        gstep()
+    g1.record(gs)
+    torch.cuda.synchronize()
+    ms_graph = g0.elapsed_time(g1) / args.steps
+    if rg.overflowed():
+        raise RuntimeError("graph frame overflowed its reservation")
+    fwd_graph = {"mpix_s": round(npix / (ms_graph * 1e-3) / 1e6, 2), "ms_per_step": round(ms_graph, 4),
+                 "path": "the forward step captured in one HIP graph (one launch per frame)"}
+    log(f"graph fwd {ms_graph:.3f} ms/step")
+    del gstep, rg
+
     del r, fwd_state
     torch.cuda.empty_cache()
     batched = uneven = bwd800 = orbit = None
@@ -524,7 +553,7 @@ def main():
                    "schedule": ["tile_grid", "persistent"][args.schedule], "path": "plain forward"},
         "n_dup": n_dup, "n_supertile_entries": n1, "stages_ms": stages, "roofline": roof, "rooflines": rooflines,
         "wall_s": round(wall, 3),
-        "fwd_bwd": fwd_bwd, "backward_800": bwd800, "batched": batched,
+        "fwd_graph": fwd_graph, "fwd_bwd": fwd_bwd, "backward_800": bwd800, "batched": batched,
         "batched_1080p_x16_orbit": orbit, "batched_uneven": uneven,
     }
     if not args.no_cpu_baseline:

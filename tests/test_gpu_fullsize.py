@@ -73,7 +73,7 @@ def test_cfg1_full_frame(gpu, cfg1):
     cam = s.cams[0]
     note(f"cfg1 full: N={s.N} T={s.T} {cam.width}x{cam.height}")
     d = dev_tensors(s)
-    r = Rasterizer("cuda:0", tile=(16, 16), frag_batch=128)
+    r = Rasterizer("cuda:0", tile=(16, 16), frag_batch=64)
     r.set_proxy(s.proxy.V_rest, s.proxy.faces)
     df = d["deform"]
     dt = r.bind_transfer(df["V_def"], df["bind_face"], df["bind_bary"], d["means"], d["quats"], d["scales"])
@@ -155,13 +155,13 @@ def test_cfg3_batched_graph(gpu):
     note(f"cfg3 full: N={s.N} T={s.T} views={len(s.cams)}")
     d = dev_tensors(s)
     sc = {k: d[k] for k in ("means", "scales", "quats", "opacity", "sh", "tri_xyz", "tri_rgb", "tri_alpha")}
-    r = Rasterizer("cuda:0", own_stream=True, tile=(16, 16), frag_batch=128, schedule=1)
+    r = Rasterizer("cuda:0", own_stream=True, tile=(16, 16), frag_batch=64, schedule=1)
     step = BatchedStep(r, s.cams, sc)
     step()
     out = step()
     torch.cuda.synchronize()
     assert not r.overflowed()
-    rp = Rasterizer("cuda:0", tile=(16, 16), frag_batch=128, schedule=0)
+    rp = Rasterizer("cuda:0", tile=(16, 16), frag_batch=64, schedule=0)
     imgs = step.split_views(out["image"], 3)
     for v in (0, 17, 40, 63):
         # the plain per-view frame is bit-identical to the batched one
