@@ -423,9 +423,9 @@ def main():
     n_st, n1 = r.query_bins()
     kb = 2.0 if n_st <= 65536 else 4.0
     algo_bytes = {
-        # first level: per record its order, offsets, rectangle and Gaussian
-        # record; per entry its supertile id, record id and tile mask
-        "emit_keys": 76.0 * n_rec + (kb + 12.0) * n1,
+        # first level: per record its order, offsets and rectangle; per entry
+        # its supertile id and record id
+        "emit_keys": 28.0 * n_rec + (kb + 4.0) * n1,
         "sort_downsweep": 2.0 * (kb + 12.0) * n1,  # read and write id, record id, mask
         "sort_upsweep": kb * n1,                   # read the ids
         # masks: per entry its supertile id, record id, rectangle, Gaussian
