@@ -113,12 +113,14 @@ umgs_status umgs_set_proxy(umgs_ctx *ctx, int32_t nV, const float *V_rest, int32
  * [device] (N,K,2) = (u,v) with w = 1-u-v, then Eq. 13.
  * Outputs [device]: means_out (N,3), quats_out (N,4) = quat(R') * q,
  * cov3d_out (N,6) = A Sigma A^T packed, xform_out (N,9) = A = R'S' row-major;
- * vertex_out (nV,12) = (Delta 3, log R 3, S xx,xy,xz,yy,yz,zz) may be NULL.
+ * vertex_out (nV,12) = (Delta 3, log R 3, S xx,xy,xz,yy,yz,zz) may be NULL
+ * (else 16-byte aligned).
  * means_out follows a fixed FP32 operation order (the deformed mean orders
  * the Gaussians): Delta = V'-V; w = (1-u)-v; Delta_i = (u Da + v Db) + w Dc;
  * s = ((Delta_1 + Delta_2) + ...) + Delta_K; mu' = mu + s * (1/K).
- * Errors: STATE without umgs_set_proxy; INVALID_ARG for NULL inputs or
- * N < 0.  Face indices are not range-checked on the device (caller's
+ * Errors: STATE without umgs_set_proxy; INVALID_ARG for NULL inputs,
+ * N < 0, a misaligned vertex_out, or (K = 8) bind_face / bind_bary not
+ * 16-byte aligned.  Face indices are not range-checked on the device (caller's
  * responsibility: 0 <= face < nF). */
 umgs_status umgs_bind_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
                                const int32_t *bind_face, const float *bind_bary,

@@ -163,7 +163,7 @@ void umgs_destroy(umgs_ctx *ctx) {
   (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
-  DevBuf *bufs[] = {&c->V_rest, &c->faces, &c->vf_ptr, &c->vf_idx, &c->vtab, &c->d_views,
+  DevBuf *bufs[] = {&c->V_rest, &c->faces, &c->vf_ptr, &c->vf_idx, &c->vtab, &c->ftab, &c->d_views,
                     &c->keys, &c->rects, &c->counts, &c->dk[0], &c->dk[1], &c->dv[0],
                     &c->dv[1], &c->offs, &c->grec, &c->trec, &c->scan_tmp,
                     &c->sk[0], &c->sk[1], &c->sv[0], &c->sv[1], &c->masks[0], &c->masks[1], &c->st_rng,
@@ -223,7 +223,8 @@ umgs_status umgs_set_proxy(umgs_ctx *ctx, int32_t nV, const float *V_rest, int32
       (s = ensure(c, c->faces, sizeof(int32_t) * 3 * nF, "proxy faces")) ||
       (s = ensure(c, c->vf_ptr, sizeof(int32_t) * (nV + 1), "vertex-face offsets")) ||
       (s = ensure(c, c->vf_idx, sizeof(int32_t) * idx.size(), "vertex-face lists")) ||
-      (s = ensure(c, c->vtab, sizeof(float) * 12 * nV, "vertex transforms")))
+      (s = ensure(c, c->vtab, sizeof(float) * 12 * nV, "vertex transforms")) ||
+      (s = ensure(c, c->ftab, sizeof(float) * 36 * (size_t)nF, "face transforms")))
     return s;
   hipError_t e;
   if ((e = hipMemcpy(c->V_rest.p, V_rest, sizeof(float) * 3 * nV, hipMemcpyHostToDevice)) ||
@@ -249,6 +250,11 @@ umgs_status umgs_bind_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
   if (N > 0 && (!bind_face || !bind_bary || !means || !quats || !scales || !means_out ||
                 !cov3d_out))
     return fail(c, UMGS_ERR_INVALID_ARG, "umgs_bind_transfer: NULL Gaussian array");
+  if (((uintptr_t)vertex_out & 15) != 0)
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_bind_transfer: vertex_out is not 16-byte aligned");
+  if (c->opt.k_bind == 8 && N > 0 && ((((uintptr_t)bind_face) | ((uintptr_t)bind_bary)) & 15) != 0)
+    return fail(c, UMGS_ERR_INVALID_ARG,
+                "umgs_bind_transfer: bind_face and bind_bary must be 16-byte aligned");
   return hip_check(c, launch_transfer(c, V_def, N, bind_face, bind_bary, means, quats, scales,
                                       means_out, quats_out, cov3d_out, xform_out, vertex_out),
                    "transfer launch");

@@ -116,6 +116,7 @@ struct Ctx {
   // proxy mesh
   int32_t nV = 0, nF = 0;
   DevBuf V_rest, faces, vf_ptr, vf_idx, vtab;
+  DevBuf ftab;   // per face: its three vertex rows (9 float4, 144 B)
 
   // per-frame state
   int stage = 0;         // 0 none, 1 projected, 2 binned, 3 sorted, 4 blended

@@ -9,10 +9,14 @@
 //   polar D = R S with R = [u1 u2 u1 x u2][v1 v2 v3]^T from the eigenvectors
 //   of D^T D (a proper rotation; the nearest one to D);
 //   r_v = log R (axis-angle), written with S as a 12-float row.
+// face_rows_kernel: each face's three vertex rows side by side (144 B), so a
+//   bound point reads one row that spans exactly two 128-B cache lines
+//   (rows start at multiples of 16 B) instead of a face lookup followed by
+//   three vertex rows in three places.
 // transfer kernels (FP32): Eq. 12 at each of the K bound points, Eq. 13
 //   averages: R' = exp(mean r_i), S' = mean S_i, A = R'S',
 //   Sigma' = A Sigma A^T, mu' = mu + mean Delta_i (pinned order),
-//   q' = quat(R') * q.  For K = 8 one lane handles one corner.
+//   q' = quat(R') * q, one lane per Gaussian.
 #include "internal.h"
 
 namespace umgs {
@@ -203,8 +207,22 @@ __global__ void vertex_frames_kernel(int nV, const float *__restrict__ Vr,
   out[11] = (float)S[8];
 }
 
-__device__ __forceinline__ float3 interp_delta(float u, float v, float w, const float4 &a,
-                                               const float4 &b, const float4 &c) {
+// One thread per (face, float4 of the face row): row f = rows of vertices
+// faces[3f], faces[3f+1], faces[3f+2], 3 float4 each.
+__global__ void face_rows_kernel(int nF, const int32_t *__restrict__ faces,
+                                 const float4 *__restrict__ vtab, float4 *__restrict__ ftab) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 9 * (int64_t)nF) return;
+  const int64_t f = t / 9;
+  const int j = (int)(t - 9 * f);
+  const int v = faces[3 * f + j / 3];
+  ftab[t] = vtab[3 * (int64_t)v + j % 3];
+}
+
+typedef float f4v __attribute__((ext_vector_type(4)));   // arrays of it stay in registers
+
+__device__ __forceinline__ float3 interp_delta(float u, float v, float w, const f4v &a,
+                                               const f4v &b, const f4v &c) {
 #pragma clang fp contract(off)
   float3 d;
   d.x = (u * a.x + v * b.x) + w * c.x;
@@ -308,114 +326,113 @@ __device__ __forceinline__ void finish_gaussian(int i, float3 dsum, const float 
   }
 }
 
-// Eq. 12 at one bound point: Delta (pinned), r and S interpolated from the
-// face's three vertex rows.
-__device__ __forceinline__ void corner_terms(const float4 *__restrict__ vtab,
-                                             const int32_t *__restrict__ faces, int f, float u,
-                                             float v, float3 &di, float r[3], float S[6]) {
-  const float w = pinned_w(u, v);
-  const int va = faces[3 * f], vb = faces[3 * f + 1], vc = faces[3 * f + 2];
-  const float4 a0 = vtab[3 * va], a1 = vtab[3 * va + 1], a2 = vtab[3 * va + 2];
-  const float4 b0 = vtab[3 * vb], b1 = vtab[3 * vb + 1], b2 = vtab[3 * vb + 2];
-  const float4 c0 = vtab[3 * vc], c1 = vtab[3 * vc + 1], c2 = vtab[3 * vc + 2];
-  di = interp_delta(u, v, w, a0, b0, c0);
-  r[0] = u * a0.w + v * b0.w + w * c0.w;
-  r[1] = u * a1.x + v * b1.x + w * c1.x;
-  r[2] = u * a1.y + v * b1.y + w * c1.y;
-  S[0] = u * a1.z + v * b1.z + w * c1.z;
-  S[1] = u * a1.w + v * b1.w + w * c1.w;
-  S[2] = u * a2.x + v * b2.x + w * c2.x;
-  S[3] = u * a2.y + v * b2.y + w * c2.y;
-  S[4] = u * a2.z + v * b2.z + w * c2.z;
-  S[5] = u * a2.w + v * b2.w + w * c2.w;
-}
+// Transfer kernel: one lane per Gaussian, its K bound points taken in K
+// rounds.  In round k the wave first gathers the 64 face rows it needs
+// (corner k of each of its Gaussians) into its own LDS block: the 576 float4
+// are read in 9 instructions, lane L taking slot s = 64 m + L (row s / 9,
+// part s % 9), so one instruction reads about seven whole rows, i.e. some 15
+// cache lines, where one row per lane would touch 64.  Each lane then reads
+// its row from LDS and adds Eq. 12's terms in corner order (the pinned order
+// of the mean offset); the next round's rows are already loading meanwhile.
+// A lane finally applies Eq. 13 to its own Gaussian.
+constexpr int kTrRows = 64;   // Gaussians per wave (one wave per block)
 
-// K = 1: one thread per Gaussian.
-__global__ void transfer1_kernel(int N, const float4 *__restrict__ vtab,
-                                 const int32_t *__restrict__ faces,
-                                 const int32_t *__restrict__ bind_face,
-                                 const float *__restrict__ bind_bary,
-                                 const float *__restrict__ means, const float *__restrict__ quats,
-                                 const float *__restrict__ scales, float *__restrict__ means_out,
-                                 float *__restrict__ quats_out, float *__restrict__ cov3d_out,
-                                 float *__restrict__ xform_out) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  float3 d;
-  float r[3], S[6];
-  corner_terms(vtab, faces, bind_face[i], bind_bary[2 * i], bind_bary[2 * i + 1], d, r, S);
-  finish_gaussian(i, d, r, S, 1.0f, means, quats, scales, means_out, quats_out, cov3d_out,
-                  xform_out);
-}
-
-// K = 8: one lane per (Gaussian, corner) so the eight gather chains run in
-// parallel; the 8-lane group then reduces its corners (the mean offset in
-// corner order, as pinned) into LDS and one lane per Gaussian finishes it.
-constexpr int kT8Threads = 256;
-constexpr int kT8Gauss = kT8Threads / 8;
-
-// Sum over the 8 lanes of each aligned lane group, left in every lane of the
-// group: swap neighbours, swap pairs, mirror half-rows (DPP, vector ALU).
-__device__ __forceinline__ float group8_sum(float v) {
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, true));
-  return v;
-}
-
-// Value of lane (this lane + J) within the 16-lane row (row_shl:J); for the
-// first lane of an 8-lane group that is corner J of the same Gaussian.
-template <int J>
-__device__ __forceinline__ float from_lane_plus(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x100 + J, 0xF, 0xF, true));
-}
-
-__global__ __launch_bounds__(kT8Threads) void transfer8_kernel(
-    int N, const float4 *__restrict__ vtab, const int32_t *__restrict__ faces,
-    const int32_t *__restrict__ bind_face, const float *__restrict__ bind_bary,
-    const float *__restrict__ means, const float *__restrict__ quats,
-    const float *__restrict__ scales, float *__restrict__ means_out,
-    float *__restrict__ quats_out, float *__restrict__ cov3d_out, float *__restrict__ xform_out) {
-  __shared__ float sums[kT8Gauss][12];
-  const int tid = threadIdx.x, grp = tid >> 3, k = tid & 7;
-  const int i = blockIdx.x * kT8Gauss + grp;
-  float3 d = make_float3(0.f, 0.f, 0.f);
-  float r[3] = {0.f, 0.f, 0.f}, S[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  if (i < N) {
-    const int64_t b = 8 * (int64_t)i + k;
-    corner_terms(vtab, faces, bind_face[b], bind_bary[2 * b], bind_bary[2 * b + 1], d, r, S);
+__device__ __forceinline__ void gather_rows(const f4v *__restrict__ ftab, int face, int lane,
+                                            f4v (&buf)[9]) {
+#pragma unroll
+  for (int m = 0; m < 9; ++m) {
+    const int s = 64 * m + lane;
+    const int row = s / 9;
+    const int f = __shfl(face, row, 64);
+    buf[m] = ftab[9 * (int64_t)f + (s - 9 * row)];
   }
-  // r, S: sum over the 8 lanes of the group (every lane of the wave takes part)
+}
+
+template <int K>
+__global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) void transfer_kernel(
+    int N, const float4 *__restrict__ ftab, const int32_t *__restrict__ bind_face,
+    const float *__restrict__ bind_bary, const float *__restrict__ means,
+    const float *__restrict__ quats, const float *__restrict__ scales,
+    float *__restrict__ means_out, float *__restrict__ quats_out, float *__restrict__ cov3d_out,
+    float *__restrict__ xform_out) {
+  __shared__ f4v rows[kTrRows * 9];
+  const f4v *__restrict__ ftab4 = reinterpret_cast<const f4v *>(ftab);
+  const int lane = threadIdx.x;
+  const int i = blockIdx.x * kTrRows + lane;
+  const bool valid = i < N;
+  // this lane's K bindings (face 0 stands in past the end: its row is read
+  // and the result dropped)
+  int face[K];
+  float bu[K], bv[K];
+  if constexpr (K == 8) {
+    int4 f0 = make_int4(0, 0, 0, 0), f1 = f0;
+    float4 b0 = make_float4(0.f, 0.f, 0.f, 0.f), b1 = b0, b2 = b0, b3 = b0;
+    if (valid) {
+      const int4 *fp = reinterpret_cast<const int4 *>(bind_face) + 2 * (int64_t)i;
+      const float4 *bp = reinterpret_cast<const float4 *>(bind_bary) + 4 * (int64_t)i;
+      f0 = fp[0]; f1 = fp[1];
+      b0 = bp[0]; b1 = bp[1]; b2 = bp[2]; b3 = bp[3];
+    }
+    face[0] = f0.x; face[1] = f0.y; face[2] = f0.z; face[3] = f0.w;
+    face[4] = f1.x; face[5] = f1.y; face[6] = f1.z; face[7] = f1.w;
+    bu[0] = b0.x; bv[0] = b0.y; bu[1] = b0.z; bv[1] = b0.w;
+    bu[2] = b1.x; bv[2] = b1.y; bu[3] = b1.z; bv[3] = b1.w;
+    bu[4] = b2.x; bv[4] = b2.y; bu[5] = b2.z; bv[5] = b2.w;
+    bu[6] = b3.x; bv[6] = b3.y; bu[7] = b3.z; bv[7] = b3.w;
+  } else {
 #pragma unroll
-  for (int j = 0; j < 3; ++j) r[j] = group8_sum(r[j]);
-#pragma unroll
-  for (int j = 0; j < 6; ++j) S[j] = group8_sum(S[j]);
-  // Delta in the group's first lane: ((D0 + D1) + D2) + ... in corner order
-  float3 ds = d;
-  ds = add3(ds, make_float3(from_lane_plus<1>(d.x), from_lane_plus<1>(d.y), from_lane_plus<1>(d.z)));
-  ds = add3(ds, make_float3(from_lane_plus<2>(d.x), from_lane_plus<2>(d.y), from_lane_plus<2>(d.z)));
-  ds = add3(ds, make_float3(from_lane_plus<3>(d.x), from_lane_plus<3>(d.y), from_lane_plus<3>(d.z)));
-  ds = add3(ds, make_float3(from_lane_plus<4>(d.x), from_lane_plus<4>(d.y), from_lane_plus<4>(d.z)));
-  ds = add3(ds, make_float3(from_lane_plus<5>(d.x), from_lane_plus<5>(d.y), from_lane_plus<5>(d.z)));
-  ds = add3(ds, make_float3(from_lane_plus<6>(d.x), from_lane_plus<6>(d.y), from_lane_plus<6>(d.z)));
-  ds = add3(ds, make_float3(from_lane_plus<7>(d.x), from_lane_plus<7>(d.y), from_lane_plus<7>(d.z)));
-  // the group sums go through LDS so that one wave finishes 32 Gaussians
-  // with every lane busy
-  if (k == 0) {
-    sums[grp][0] = ds.x; sums[grp][1] = ds.y; sums[grp][2] = ds.z;
-    sums[grp][3] = r[0]; sums[grp][4] = r[1]; sums[grp][5] = r[2];
-#pragma unroll
-    for (int j = 0; j < 6; ++j) sums[grp][6 + j] = S[j];
-  }
-  __syncthreads();
-  if (tid < kT8Gauss) {
-    const int g = blockIdx.x * kT8Gauss + tid;
-    if (g < N) {
-      const float *q = sums[tid];
-      finish_gaussian(g, make_float3(q[0], q[1], q[2]), q + 3, q + 6, 0.125f, means, quats, scales,
-                      means_out, quats_out, cov3d_out, xform_out);
+    for (int k = 0; k < K; ++k) {
+      face[k] = valid ? bind_face[K * (int64_t)i + k] : 0;
+      bu[k] = valid ? bind_bary[2 * (K * (int64_t)i + k)] : 0.f;
+      bv[k] = valid ? bind_bary[2 * (K * (int64_t)i + k) + 1] : 0.f;
     }
   }
+  float3 ds = make_float3(0.f, 0.f, 0.f);
+  float rs[3] = {0.f, 0.f, 0.f}, Ss[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  f4v buf[9];
+  gather_rows(ftab4, face[0], lane, buf);
+  // one round per bound point; the bindings shift down one place per round,
+  // so every index below is static
+  auto round = [&](bool first, bool prefetch) {
+#pragma unroll
+    for (int m = 0; m < 9; ++m) rows[64 * m + lane] = buf[m];
+    __syncthreads();
+    if (prefetch) gather_rows(ftab4, face[K > 1 ? 1 : 0], lane, buf);
+    const f4v *row = rows + 9 * lane;
+    const f4v a0 = row[0], a1 = row[1], a2 = row[2];
+    const f4v b0 = row[3], b1 = row[4], b2 = row[5];
+    const f4v c0 = row[6], c1 = row[7], c2 = row[8];
+    const float u = bu[0], v = bv[0], w = pinned_w(u, v);
+    const float3 di = interp_delta(u, v, w, a0, b0, c0);
+    ds = first ? di : add3(ds, di);
+    rs[0] += u * a0.w + v * b0.w + w * c0.w;
+    rs[1] += u * a1.x + v * b1.x + w * c1.x;
+    rs[2] += u * a1.y + v * b1.y + w * c1.y;
+    Ss[0] += u * a1.z + v * b1.z + w * c1.z;
+    Ss[1] += u * a1.w + v * b1.w + w * c1.w;
+    Ss[2] += u * a2.x + v * b2.x + w * c2.x;
+    Ss[3] += u * a2.y + v * b2.y + w * c2.y;
+    Ss[4] += u * a2.z + v * b2.z + w * c2.z;
+    Ss[5] += u * a2.w + v * b2.w + w * c2.w;
+#pragma unroll
+    for (int j = 0; j + 1 < K; ++j) {
+      face[j] = face[j + 1];
+      bu[j] = bu[j + 1];
+      bv[j] = bv[j + 1];
+    }
+    __syncthreads();
+  };
+  if constexpr (K > 1) {
+    round(true, true);
+#pragma unroll 1
+    for (int k = 1; k + 1 < K; ++k) round(false, true);
+    round(false, false);
+  } else {
+    round(true, false);
+  }
+  if (valid)
+    finish_gaussian(i, ds, rs, Ss, 1.0f / K, means, quats, scales, means_out, quats_out, cov3d_out,
+                    xform_out);
 }
 
 }  // namespace
@@ -432,17 +449,24 @@ hipError_t launch_transfer(Ctx *c, const float *V_def, int32_t N, const int32_t 
                        c->nV, (const float *)c->V_rest.p, V_def, (const int32_t *)c->faces.p,
                        (const int32_t *)c->vf_ptr.p, (const int32_t *)c->vf_idx.p, vtab);
     e = hipGetLastError();
+    if (e == hipSuccess && N > 0) {
+      hipLaunchKernelGGL(face_rows_kernel, dim3((unsigned)ceil_div(9 * (int64_t)c->nF, 256)),
+                         dim3(256), 0, c->stream, c->nF, (const int32_t *)c->faces.p,
+                         (const float4 *)vtab, (float4 *)c->ftab.p);
+      e = hipGetLastError();
+    }
   }
   if (e != hipSuccess || N == 0) return e;
   ScopedTimer tt(c, K_TRANSFER);
+  const dim3 grid(ceil_div(N, kTrRows)), block(kTrRows);
   if (c->opt.k_bind == 8)
-    hipLaunchKernelGGL(transfer8_kernel, dim3(ceil_div(N, kT8Gauss)), dim3(kT8Threads), 0,
-                       c->stream, N, (const float4 *)vtab, (const int32_t *)c->faces.p, bind_face,
-                       bind_bary, means, quats, scales, means_out, quats_out, cov3d_out, xform_out);
+    hipLaunchKernelGGL(transfer_kernel<8>, grid, block, 0, c->stream, N, (const float4 *)c->ftab.p,
+                       bind_face, bind_bary, means, quats, scales, means_out, quats_out, cov3d_out,
+                       xform_out);
   else
-    hipLaunchKernelGGL(transfer1_kernel, dim3(ceil_div(N, 256)), dim3(256), 0, c->stream, N,
-                       (const float4 *)vtab, (const int32_t *)c->faces.p, bind_face, bind_bary,
-                       means, quats, scales, means_out, quats_out, cov3d_out, xform_out);
+    hipLaunchKernelGGL(transfer_kernel<1>, grid, block, 0, c->stream, N, (const float4 *)c->ftab.p,
+                       bind_face, bind_bary, means, quats, scales, means_out, quats_out, cov3d_out,
+                       xform_out);
   return hipGetLastError();
 }
 

@@ -209,15 +209,19 @@ def test_empty_and_degenerate_scenes(torch_dev):
     PT.compare_pixels(fr, img, Tf, None, [(0, 0)])
 
 
-def test_deformed_scene_parity(torch_dev):
-    """Scaled deformed workload: GPU transfer then GPU render, against the
-    oracle transfer then oracle render, on every pixel of a small view."""
+@pytest.mark.parametrize("K", [8, 1])
+def test_deformed_scene_parity(torch_dev, K):
+    """Scaled deformed workload (a ragged last wave of Gaussians): GPU
+    transfer then GPU render, against the oracle transfer then oracle
+    render, on every pixel of a small view; the transferred means bit for
+    bit, covariances, rotations and A = R'S' to FP32 accuracy."""
     import torch
     from oracle import transfer as OT
     from paper_2601_19233_amd.render import Rasterizer, scene_inputs
-    s = scenes.make_config(1, scale=0.004, res_scale=0.06)
-    note(f"deformed N={s.N} T={s.T} view={s.cams[0].width}x{s.cams[0].height}")
-    r = Rasterizer("cuda:0")
+    s = scenes.make_config(1, scale=0.004, res_scale=0.06, K=K)
+    note(f"deformed K={K} N={s.N} T={s.T} view={s.cams[0].width}x{s.cams[0].height}")
+    assert s.N % 64 != 0
+    r = Rasterizer("cuda:0", k_bind=K)
     r.set_proxy(s.proxy.V_rest, s.proxy.faces)
     dt = r.bind_transfer(s.proxy.V_def, s.bind_face, s.bind_bary, s.means, s.quats, s.scales)
     ot = OT.transfer(s.proxy.V_rest, s.proxy.faces, s.proxy.V_def, s.means, s.quats, s.scales,
@@ -226,6 +230,12 @@ def test_deformed_scene_parity(torch_dev):
     assert np.array_equal(gm, ot["means"])            # pinned FP32 mean
     np.testing.assert_allclose(to_np(dt["cov3d"]), ot["cov3d"], rtol=2e-4,
                                atol=1e-5 * np.abs(ot["cov3d"]).max())
+    # unit quaternions and A near a rotation: O(1) entries, FP32 sums of K
+    # interpolated terms, an FP32 exponential map and one 3x3 product
+    np.testing.assert_allclose(to_np(dt["quats"]), ot["quats"], rtol=0, atol=1e-5)
+    np.testing.assert_allclose(to_np(dt["xform"]).reshape(-1, 3, 3), ot["A"], rtol=0, atol=1e-5)
+    if K == 1:
+        return
     out = r.render(s.cams, **scene_inputs(s, cov3d=dt["cov3d"], means=dt["means"]))
     img, Tf, nc = view_arrays(r, out)
     fr = PT.oracle_frame(s, s.cams[0], cov3d=ot["cov3d"], means=ot["means"])
