@@ -27,6 +27,17 @@ namespace umgs {
 
 namespace {
 
+// First set bit at or after slot f among the first bn slots of the batch's
+// triangle mask (bn if none).
+__device__ __forceinline__ uint32_t next_set_slot(const uint64_t *m, uint32_t f, uint32_t bn) {
+  while (f < bn) {
+    const uint64_t w = m[f >> 6] >> (f & 63u);
+    if (w) return min(bn, f + (uint32_t)__builtin_ctzll(w));
+    f = (f | 63u) + 1u;
+  }
+  return bn;
+}
+
 // COUNT instantiations also count into pairs[0..3]: the (pixel, fragment)
 // pairs each pixel evaluates before it is done (Gaussian, triangle), the
 // wave iterations of the fragment loop (times 64 lanes: the SIMD slots the
@@ -66,148 +77,157 @@ __device__ __forceinline__ void blend_tile(
   bool done = !inside;
   int32_t last = 0;
 
+  // triangle slots of the staged batch, one bit per slot (batch <= 256)
+  __shared__ uint64_t tmask[4];
+
   for (uint32_t bstart = rg.x; bstart < rg.y; bstart += batch) {
     const uint32_t bn = min((uint32_t)batch, rg.y - bstart);
     if (COUNT && tid == 0) atomicAdd(pairs + 3, (unsigned long long)bn);
-    // ---- stage fragments into LDS
-    int tri_here = 0;
-    for (uint32_t f = tid; f < bn; f += NT) {
-      uint32_t *s = slots + f * kSlotWords;
-      const int64_t local = (int64_t)vals[bstart + f] - rbase;
-      if (local < N) {
-        const uint32_t rec = (uint32_t)((int64_t)v * N + local);
-        stage_gauss(s, grec[rec], rec);
-      } else {
-        stage_tri(s, trec[(int64_t)v * T + (local - N)], P0x, P0y);
-        tri_here = 1;
-      }
-    }
-    const bool any_tri = __syncthreads_or(tri_here) != 0;
-
-    // ---- blend the batch
-    if (!done && !any_tri) {
-      // Gaussians only: alpha of kUnroll fragments evaluated together (they
-      // do not depend on the pixel's state), then blended in list order.
-      // Every decision is a per-lane select: a fragment that does not
-      // contribute gets alpha 0; Tl, the live transmittance, drops to exactly
-      // 0 when the pixel stops (so later fragments add w = 0 and never blend)
-      // while Tf keeps the pixel's final value.  A stop is a fragment whose
-      // T (1 - alpha) would fall below 1e-4 (once stopped, T l = 0 satisfies
-      // that test again, which changes nothing).
-      constexpr int kUnroll = 4;
-      float Tl = Tr, Tf = Tr;
-      const int32_t last0 = last;
-      uint32_t f = 0;
-      for (; f + kUnroll <= bn; f += kUnroll) {
-        if (__all(Tl == 0.0f)) break;
-        if (COUNT) n_wit += kUnroll;
-        float al[kUnroll], cr[kUnroll], cg[kUnroll], cb[kUnroll];
-#pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
-          const uint32_t *s = slots + (f + k) * kSlotWords;
-          float a;
-          const bool ok = gauss_alpha(s, pcx, pcy, a);
-          al[k] = ok ? a : 0.0f;
-          cr[k] = __uint_as_float(s[6]);
-          cg[k] = __uint_as_float(s[7]);
-          cb[k] = __uint_as_float(s[8]);
-        }
-#pragma unroll
-        for (int k = 0; k < kUnroll; ++k) {
-          if (COUNT) n_gp += Tl == 0.0f ? 0u : 1u;
-          const float w = Tl * al[k];
-          const float test_T = Tl - w;      // T (1 - alpha)
-          const bool stop = test_T < kTStop;
-          const bool blend = !stop && w > 0.0f;
-          const float wc = stop ? 0.0f : w;
-          C0 = fmaf(wc, cr[k], C0);
-          C1 = fmaf(wc, cg[k], C1);
-          C2 = fmaf(wc, cb[k], C2);
-          Tent = blend ? Tl : Tent;
-          last = blend ? (int32_t)(bstart - rg.x + f + k + 1) : last;
-          Tf = stop ? Tf : test_T;
-          Tl = stop ? 0.0f : test_T;
-        }
-      }
-      Tr = Tf;
-      done = Tl == 0.0f;
-      if (mode != UMGS_MODE_ONE_ENTITY && last != last0) in_entity = false;
-      for (; f < bn; ++f) {
-        if (__all(done)) break;
-        if (COUNT) ++n_wit;
-        if (done) continue;
-        if (COUNT) ++n_gp;
-        const uint32_t *s = slots + f * kSlotWords;
-        float alpha;
-        if (!gauss_alpha(s, pcx, pcy, alpha)) continue;
-        const float w = Tr * alpha;
-        const float test_T = Tr - w;
-        if (test_T < kTStop) { done = true; continue; }
-        C0 = fmaf(w, __uint_as_float(s[6]), C0);
-        C1 = fmaf(w, __uint_as_float(s[7]), C1);
-        C2 = fmaf(w, __uint_as_float(s[8]), C2);
-        Tent = Tr;
-        Tr = test_T;
-        if (mode != UMGS_MODE_ONE_ENTITY) in_entity = false;
-        last = (int32_t)(bstart - rg.x + f + 1);
-      }
-    } else if (!done) {
-      for (uint32_t f = 0; f < bn; ++f) {
-        if (__all(done)) break;
-        if (COUNT) ++n_wit;
-        const uint32_t *s = slots + f * kSlotWords;
-        const uint32_t tag = s[31];
-        if (done) continue;
-        const int32_t pos = (int32_t)(bstart - rg.x + f + 1);
-        if (COUNT) {
-          if ((tag & 1u) == 0u) ++n_gp; else ++n_tp;
-        }
-        if ((tag & 1u) == 0u) {
-          float alpha;
-          if (!gauss_alpha(s, pcx, pcy, alpha)) continue;
-          const float w = Tr * alpha;
-          const float test_T = Tr - w;
-          if (test_T < kTStop) { done = true; continue; }
-          C0 = fmaf(w, __uint_as_float(s[6]), C0);
-          C1 = fmaf(w, __uint_as_float(s[7]), C1);
-          C2 = fmaf(w, __uint_as_float(s[8]), C2);
-          Tent = Tr;
-          Tr = test_T;
-          if (mode != UMGS_MODE_ONE_ENTITY) in_entity = false;
-          last = pos;
+    // ---- stage fragments into LDS; each wave records which of its slots
+    // hold triangles
+    for (uint32_t j0 = 0; j0 < bn; j0 += NT) {
+      const uint32_t f = j0 + tid;
+      bool is_tri = false;
+      if (f < bn) {
+        uint32_t *s = slots + f * kSlotWords;
+        const int64_t local = (int64_t)vals[bstart + f] - rbase;
+        if (local < N) {
+          const uint32_t rec = (uint32_t)((int64_t)v * N + local);
+          stage_gauss(s, grec[rec], rec);
         } else {
-          double e[3];
-          float o[4];
-          if (tri_eval(s, rlx, rly, direct, e, o) == 0) continue;
-          float cr, cg, cbl;
-          tri_colour(s, e, cr, cg, cbl);
-          const float alpha = __uint_as_float(s[30]);
-          if (direct) {
-            const float w = Tr * alpha;
-            C0 = fmaf(w, cr, C0); C1 = fmaf(w, cg, C1); C2 = fmaf(w, cbl, C2);
-            Tent = Tr;
-            Tr = Tr - w;
-            last = pos;
-            if (Tr < kTStop) done = true;
-            continue;
+          stage_tri(s, trec[(int64_t)v * T + (local - N)], P0x, P0y);
+          is_tri = true;
+        }
+      }
+      const uint64_t bits = __ballot(is_tri);
+      const uint32_t w0 = j0 + ((uint32_t)tid & ~63u);
+      if ((tid & 63) == 0 && w0 < bn) tmask[w0 >> 6] = bits;
+    }
+    __syncthreads();
+    uint64_t any_bits = 0;
+    for (uint32_t w = 0; w * 64 < bn; ++w) any_bits |= tmask[w];
+    const bool any_tri = any_bits != 0;
+
+    // ---- blend the batch: runs of Gaussians between the triangles
+    if (!done) {
+      uint32_t f = 0;
+      while (f < bn) {
+        const uint32_t fe = any_tri ? next_set_slot(tmask, f, bn) : bn;
+        if (fe > f) {
+          // Gaussians [f, fe): alpha of kUnroll fragments evaluated together
+          // (they do not depend on the pixel's state), then blended in list
+          // order.  Every decision is a per-lane select: a fragment that
+          // does not contribute gets alpha 0; Tl, the live transmittance,
+          // drops to exactly 0 when the pixel stops (so later fragments add
+          // w = 0 and never blend) while Tf keeps the pixel's final value.
+          // A stop is a fragment whose T (1 - alpha) would fall below 1e-4
+          // (once stopped, Tl = 0 satisfies that test again, which changes
+          // nothing).
+          constexpr int kUnroll = 4;
+          float Tl = done ? 0.0f : Tr, Tf = Tr;   // a pixel stopped in an earlier run stays stopped
+          const int32_t last0 = last;
+          for (; f + kUnroll <= fe; f += kUnroll) {
+            if (__all(Tl == 0.0f)) break;
+            if (COUNT) n_wit += kUnroll;
+            float al[kUnroll], cr[kUnroll], cg[kUnroll], cb[kUnroll];
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+              const uint32_t *s = slots + (f + k) * kSlotWords;
+              float a;
+              const bool ok = gauss_alpha(s, pcx, pcy, a);
+              al[k] = ok ? a : 0.0f;
+              cr[k] = __uint_as_float(s[6]);
+              cg[k] = __uint_as_float(s[7]);
+              cb[k] = __uint_as_float(s[8]);
+            }
+#pragma unroll
+            for (int k = 0; k < kUnroll; ++k) {
+              if (COUNT) n_gp += Tl == 0.0f ? 0u : 1u;
+              const float w = Tl * al[k];
+              const float test_T = Tl - w;      // T (1 - alpha)
+              const bool stop = test_T < kTStop;
+              const bool blend = !stop && w > 0.0f;
+              const float wc = stop ? 0.0f : w;
+              C0 = fmaf(wc, cr[k], C0);
+              C1 = fmaf(wc, cg[k], C1);
+              C2 = fmaf(wc, cb[k], C2);
+              Tent = blend ? Tl : Tent;
+              last = blend ? (int32_t)(bstart - rg.x + f + k + 1) : last;
+              Tf = stop ? Tf : test_T;
+              Tl = stop ? 0.0f : test_T;
+            }
           }
-          if (!in_entity) {
-            Tin = Tr;
-            Tent = Tr;
-            t0 = t1 = t2 = t3 = 1.0f;
-            in_entity = true;
+          // the rest of the run one at a time, same arithmetic
+          for (; f < fe; ++f) {
+            if (__all(Tl == 0.0f)) break;
+            if (COUNT) ++n_wit;
+            if (COUNT) n_gp += Tl == 0.0f ? 0u : 1u;
+            const uint32_t *s = slots + f * kSlotWords;
+            float a;
+            const bool ok = gauss_alpha(s, pcx, pcy, a);
+            const float w = Tl * (ok ? a : 0.0f);
+            const float test_T = Tl - w;
+            const bool stop = test_T < kTStop;
+            const bool blend = !stop && w > 0.0f;
+            const float wc = stop ? 0.0f : w;
+            C0 = fmaf(wc, __uint_as_float(s[6]), C0);
+            C1 = fmaf(wc, __uint_as_float(s[7]), C1);
+            C2 = fmaf(wc, __uint_as_float(s[8]), C2);
+            Tent = blend ? Tl : Tent;
+            last = blend ? (int32_t)(bstart - rg.x + f + 1) : last;
+            Tf = stop ? Tf : test_T;
+            Tl = stop ? 0.0f : test_T;
           }
-          const float O = 0.25f * (o[0] * t0 + o[1] * t1 + o[2] * t2 + o[3] * t3);
-          const float w = Tin * O * alpha;
-          C0 = fmaf(w, cr, C0); C1 = fmaf(w, cg, C1); C2 = fmaf(w, cbl, C2);
-          if (mode == UMGS_MODE_LITERAL_T) Tr = Tr * (1.0f - O * alpha);
-          t0 *= 1.0f - o[0] * alpha;
-          t1 *= 1.0f - o[1] * alpha;
-          t2 *= 1.0f - o[2] * alpha;
-          t3 *= 1.0f - o[3] * alpha;
-          if (mode != UMGS_MODE_LITERAL_T) Tr = Tin * (0.25f * ((t0 + t1) + (t2 + t3)));
-          last = pos;
-          if (Tr < kTStop) done = true;
+          Tr = Tf;
+          done = Tl == 0.0f;
+          // a blended Gaussian ends the run of consecutive triangles
+          if (mode != UMGS_MODE_ONE_ENTITY && last != last0) in_entity = false;
+          if (__all(done)) break;
+          f = fe;
+        }
+        if (f < bn) {
+          // the triangle at slot f
+          if (COUNT) ++n_wit;
+          if (!done) {
+            if (COUNT) ++n_tp;
+            const uint32_t *s = slots + f * kSlotWords;
+            const int32_t pos = (int32_t)(bstart - rg.x + f + 1);
+            double e[3];
+            float o[4];
+            if (tri_eval(s, rlx, rly, direct, e, o) != 0) {
+              float cr, cg, cbl;
+              tri_colour(s, e, cr, cg, cbl);
+              const float alpha = __uint_as_float(s[30]);
+              if (direct) {
+                const float w = Tr * alpha;
+                C0 = fmaf(w, cr, C0); C1 = fmaf(w, cg, C1); C2 = fmaf(w, cbl, C2);
+                Tent = Tr;
+                Tr = Tr - w;
+                last = pos;
+                if (Tr < kTStop) done = true;
+              } else {
+                if (!in_entity) {
+                  Tin = Tr;
+                  Tent = Tr;
+                  t0 = t1 = t2 = t3 = 1.0f;
+                  in_entity = true;
+                }
+                const float O = 0.25f * (o[0] * t0 + o[1] * t1 + o[2] * t2 + o[3] * t3);
+                const float w = Tin * O * alpha;
+                C0 = fmaf(w, cr, C0); C1 = fmaf(w, cg, C1); C2 = fmaf(w, cbl, C2);
+                if (mode == UMGS_MODE_LITERAL_T) Tr = Tr * (1.0f - O * alpha);
+                t0 *= 1.0f - o[0] * alpha;
+                t1 *= 1.0f - o[1] * alpha;
+                t2 *= 1.0f - o[2] * alpha;
+                t3 *= 1.0f - o[3] * alpha;
+                if (mode != UMGS_MODE_LITERAL_T) Tr = Tin * (0.25f * ((t0 + t1) + (t2 + t3)));
+                last = pos;
+                if (Tr < kTStop) done = true;
+              }
+            }
+          }
+          ++f;
+          if (__all(done)) break;
         }
       }
     }
