@@ -324,15 +324,17 @@ __device__ __forceinline__ float view_row_c(const float *Rr, float t, float x, f
 }
 
 // Real SH basis values and gradients (w.r.t. the direction components) for
-// degree <= 3, same sign convention as the forward.
-__device__ void sh_basis_grad(int deg, float x, float y, float z, float *Bv, float *Bx, float *By, float *Bz) {
+// degree DEG <= 3, same sign convention as the forward.
+template <int DEG>
+__device__ __forceinline__ void sh_basis_grad(float x, float y, float z, float *Bv, float *Bx,
+                                              float *By, float *Bz) {
   const float C0 = 0.28209479177387814f, C1 = 0.4886025119029199f;
   Bv[0] = C0; Bx[0] = By[0] = Bz[0] = 0.f;
-  if (deg < 1) return;
+  if constexpr (DEG < 1) return;
   Bv[1] = -C1 * y; Bx[1] = 0.f; By[1] = -C1; Bz[1] = 0.f;
   Bv[2] = C1 * z; Bx[2] = 0.f; By[2] = 0.f; Bz[2] = C1;
   Bv[3] = -C1 * x; Bx[3] = -C1; By[3] = 0.f; Bz[3] = 0.f;
-  if (deg < 2) return;
+  if constexpr (DEG < 2) return;
   const float xx = x * x, yy = y * y, zz = z * z;
   const float a0 = 1.0925484305920792f, a1 = -1.0925484305920792f, a2 = 0.31539156525252005f,
               a3 = -1.0925484305920792f, a4 = 0.5462742152960396f;
@@ -341,7 +343,7 @@ __device__ void sh_basis_grad(int deg, float x, float y, float z, float *Bv, flo
   Bv[6] = a2 * (2.f * zz - xx - yy); Bx[6] = -2.f * a2 * x; By[6] = -2.f * a2 * y; Bz[6] = 4.f * a2 * z;
   Bv[7] = a3 * x * z; Bx[7] = a3 * z; By[7] = 0.f; Bz[7] = a3 * x;
   Bv[8] = a4 * (xx - yy); Bx[8] = 2.f * a4 * x; By[8] = -2.f * a4 * y; Bz[8] = 0.f;
-  if (deg < 3) return;
+  if constexpr (DEG < 3) return;
   const float b0 = -0.5900435899266435f, b1 = 2.890611442640554f, b2 = -0.4570457994644658f,
               b3 = 0.3731763325901154f, b4 = -0.4570457994644658f, b5 = 1.445305721320277f,
               b6 = -0.5900435899266435f;
@@ -357,8 +359,12 @@ __device__ void sh_basis_grad(int deg, float x, float y, float z, float *Bv, flo
   Bv[15] = b6 * x * (xx - 3.f * yy); Bx[15] = b6 * (3.f * xx - 3.f * yy); By[15] = b6 * (-6.f * x * y); Bz[15] = 0.f;
 }
 
-__global__ void project_backward_kernel(const ViewParams *__restrict__ views, int V, int N,
-                                        int sh_deg, const float *__restrict__ means,
+// One instantiation per SH degree, so the coefficient loops are unrolled and
+// the per-coefficient sums stay in registers.
+template <int DEG>
+__global__ __launch_bounds__(128) void project_backward_kernel(
+                                        const ViewParams *__restrict__ views, int V, int N,
+                                        const float *__restrict__ means,
                                         const float *__restrict__ scales,
                                         const float *__restrict__ quats,
                                         const float *__restrict__ xform,
@@ -369,7 +375,7 @@ __global__ void project_backward_kernel(const ViewParams *__restrict__ views, in
                                         float *__restrict__ d_sh, int accumulate) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
-  const int nc = (sh_deg + 1) * (sh_deg + 1);
+  constexpr int nc = (DEG + 1) * (DEG + 1);
   const float mx_w = means[3 * i], my_w = means[3 * i + 1], mz_w = means[3 * i + 2];
   // Sigma = M M^T, M = R(q) diag(s); deformed: Sigma' = A Sigma A^T
   float qw = quats[4 * i], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
@@ -412,7 +418,8 @@ __global__ void project_backward_kernel(const ViewParams *__restrict__ views, in
   float dmu[3] = {0.f, 0.f, 0.f};
   float dSp[9] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   float dop = 0.f;
-  float dshv[16 * 3];
+  float dshv[nc * 3];
+#pragma unroll
   for (int k = 0; k < nc * 3; ++k) dshv[k] = 0.f;
   const float *shi = sh + (int64_t)i * nc * 3;
 
@@ -501,15 +508,17 @@ __global__ void project_backward_kernel(const ViewParams *__restrict__ views, in
     float ddx = mx_w - ccx, ddy = my_w - ccy, ddz = mz_w - ccz;
     const float dl = sqrtf(ddx * ddx + ddy * ddy + ddz * ddz), idl = 1.0f / dl;
     ddx *= idl; ddy *= idl; ddz *= idl;
-    float Bv[16], Bx[16], By[16], Bz[16];
-    sh_basis_grad(sh_deg, ddx, ddy, ddz, Bv, Bx, By, Bz);
+    float Bv[nc], Bx[nc], By[nc], Bz[nc];
+    sh_basis_grad<DEG>(ddx, ddy, ddz, Bv, Bx, By, Bz);
     float gdx = 0.f, gdy = 0.f, gdz = 0.f;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
       float raw = 0.5f;
+#pragma unroll
       for (int k = 0; k < nc; ++k) raw += Bv[k] * shi[3 * k + ch];
       if (!(raw > 0.0f)) continue;
       const float gc = gg[6 + ch];
+#pragma unroll
       for (int k = 0; k < nc; ++k) {
         dshv[3 * k + ch] += Bv[k] * gc;
         const float sk = shi[3 * k + ch] * gc;
@@ -572,6 +581,7 @@ __global__ void project_backward_kernel(const ViewParams *__restrict__ views, in
   put(&d_means[3 * (int64_t)i + 1], dmu[1]);
   put(&d_means[3 * (int64_t)i + 2], dmu[2]);
   put(&d_opac[i], dop);
+#pragma unroll
   for (int k = 0; k < nc * 3; ++k) put(&d_sh[(int64_t)i * nc * 3 + k], dshv[k]);
 }
 
@@ -611,10 +621,31 @@ hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32
   }
   if (c->N == 0) return hipSuccess;
   ScopedTimer t(c, K_PROJECT_BWD);
-  hipLaunchKernelGGL(project_backward_kernel, dim3(ceil_div(c->N, 128)), dim3(128), 0, c->stream,
-                     c->cur_views, c->V, c->N, c->sh_degree, means, scales,
-                     quats, xform, sh, (const float *)c->g2d.p, d_means, d_scales, d_quats, d_opac,
-                     d_sh, accumulate ? 1 : 0);
+  const dim3 grid(ceil_div(c->N, 128)), block(128);
+  const float *g2d = (const float *)c->g2d.p;
+  const int acc = accumulate ? 1 : 0;
+  switch (c->sh_degree) {
+    case 0:
+      hipLaunchKernelGGL(project_backward_kernel<0>, grid, block, 0, c->stream, c->cur_views, c->V,
+                         c->N, means, scales, quats, xform, sh, g2d, d_means, d_scales, d_quats,
+                         d_opac, d_sh, acc);
+      break;
+    case 1:
+      hipLaunchKernelGGL(project_backward_kernel<1>, grid, block, 0, c->stream, c->cur_views, c->V,
+                         c->N, means, scales, quats, xform, sh, g2d, d_means, d_scales, d_quats,
+                         d_opac, d_sh, acc);
+      break;
+    case 2:
+      hipLaunchKernelGGL(project_backward_kernel<2>, grid, block, 0, c->stream, c->cur_views, c->V,
+                         c->N, means, scales, quats, xform, sh, g2d, d_means, d_scales, d_quats,
+                         d_opac, d_sh, acc);
+      break;
+    default:
+      hipLaunchKernelGGL(project_backward_kernel<3>, grid, block, 0, c->stream, c->cur_views, c->V,
+                         c->N, means, scales, quats, xform, sh, g2d, d_means, d_scales, d_quats,
+                         d_opac, d_sh, acc);
+      break;
+  }
   return hipGetLastError();
 }
 
