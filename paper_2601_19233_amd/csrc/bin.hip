@@ -280,8 +280,10 @@ __global__ void st_mask_kernel(StEmitArgs e) {
   if (li < e.N) sup = make_support(e.grec[(int64_t)v * e.N + li]);
   const uint32_t nstx = (uint32_t)(vp.ntx + kST - 1) >> kSTLog;
   const uint32_t sl = s - vp.st_base;
-  e.masks[i] = st_mask(sup, (int)(sl % nstx), (int)(sl / nstx), tx0, ty0, tx1, ty1, e.tile_w,
-                       e.tile_h, vp.W, vp.H);
+  const uint32_t sy = sl / nstx;
+  e.masks[i] = st_mask(sup, (int)(sl - sy * nstx), (int)sy, tx0, ty0, tx1, ty1,
+                       __builtin_ctz((unsigned)e.tile_w), __builtin_ctz((unsigned)e.tile_h), vp.W,
+                       vp.H);
 }
 
 // Per-supertile [start, end) of the sorted entries: 4 consecutive ids per
@@ -486,7 +488,6 @@ __global__ __launch_bounds__(kL2Threads) void tile_scatter_kernel(L2Args a) {
     base[tid] = b;
   }
   const uint32_t cap = a.cap;
-  const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   const uint32_t e1 = ck.e0 + (ck.nk & 0x7FFu);
   for (uint32_t e0 = ck.e0; e0 < e1; e0 += kL2Threads) {
     const uint32_t e = e0 + tid;
@@ -503,14 +504,26 @@ __global__ __launch_bounds__(kL2Threads) void tile_scatter_kernel(L2Args a) {
     }
     __syncthreads();   // every wave has read base and wc (the next round rewrites wc)
     if (w == 0) base[lane] += tot;
+    // tile j: the lanes whose mask has bit j write consecutive positions
+    // (rank among them = set bits of the ballot below the lane)
+    const uint32_t mw[2] = {(uint32_t)m, (uint32_t)(m >> 32)};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
 #pragma unroll 4
-    for (int j = 0; j < 64; ++j) {
-      const uint64_t b = __ballot((m >> j) & 1ull);
-      if (b == 0) continue;
-      const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)off, j);
-      if ((m >> j) & 1ull) {
-        const uint32_t pos = o + (uint32_t)__popcll(b & lt);
-        if (pos < cap) a.out[pos] = r;
+      for (int jj = 0; jj < 32; ++jj) {
+        const bool bit = __builtin_amdgcn_ubfe(mw[h], jj, 1) != 0u;
+        const uint64_t b = __builtin_amdgcn_ballot_w64(bit);
+        if (b == 0) continue;
+        const int j = 32 * h + jj;
+        const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)off, j);
+        const uint32_t pos =
+            o + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+        if (o + (uint32_t)__popcll(b) <= cap) {
+          if (bit) a.out[pos] = r;
+        } else if (bit && pos < cap) {
+          a.out[pos] = r;
+        }
       }
     }
   }

@@ -26,6 +26,7 @@ namespace umgs {
 
 struct Support {
   float mx, my, A, B, C, D, tau, ex, ey, m;   // ex, ey: half extents; m: chord slack
+  float ys, i2A, fat;                         // B sqrt(tau / (C D)), 1 / (2A), 4 A tau
   bool exact;                                 // false: every tile of the rectangle is kept
 };
 
@@ -50,58 +51,61 @@ __device__ __forceinline__ Support make_support(const GaussRec &g) {
   s.ey = __builtin_amdgcn_sqrtf(4.0f * s.A * s.tau * iD);
   s.ex = __builtin_amdgcn_sqrtf(4.0f * s.C * s.tau * iD);
   s.m = 0.02f + 2e-3f * (s.ex + s.ey);
+  // per-row constants: the rightmost point of the ellipse lies at dy = -ys,
+  // the leftmost at +ys
+  s.ys = s.B * __builtin_amdgcn_sqrtf(s.tau * __builtin_amdgcn_rcpf(s.C * s.D));
+  s.i2A = __builtin_amdgcn_rcpf(2.0f * s.A);
+  s.fat = 4.0f * s.A * s.tau;
   return s;
 }
 
 // Tile columns [a, b) of tile row ty that hold a pixel centre inside the
-// support, within the bounding rectangle's columns [tx0, tx1).
-__device__ __forceinline__ void support_row(const Support &s, int ty, int tile_w, int tile_h,
-                                            int W, int H, int tx0, int tx1, int &a, int &b) {
+// support, within the pixel columns [plo, phi] of the bounding rectangle's
+// tile columns [tx0, tx1).  Tiles are 2^lw x 2^lh pixels.
+__device__ __forceinline__ void support_row(const Support &s, int ty, int lw, int lh, int H,
+                                            int tx0, int tx1, float plo, float phi, int &a,
+                                            int &b) {
 #pragma clang fp contract(off)
   a = tx0;
   b = tx1;
   if (!s.exact) return;
   // pixel-centre rows of the tile row, relative to the mean
-  const float y0 = ((float)(ty * tile_h) + 0.5f) - s.my - s.m;
-  const float y1 = ((float)min(ty * tile_h + tile_h, H) - 0.5f) - s.my + s.m;
+  const float y0 = ((float)(ty << lh) + 0.5f) - s.my - s.m;
+  const float y1 = ((float)min((ty + 1) << lh, H) - 0.5f) - s.my + s.m;
   const float lo = fmaxf(y0, -s.ey), hi = fminf(y1, s.ey);
   if (lo > hi) {
     b = a;
     return;
   }
-  // the rightmost point of the ellipse lies at dy = -ys, the leftmost at +ys;
   // x at the ends of a chord: (-B dy +- sqrt(4 A tau - D dy^2)) / (2 A)
-  const float ys = s.B * __builtin_amdgcn_sqrtf(s.tau * __builtin_amdgcn_rcpf(s.C * s.D));
-  const float dr = fminf(fmaxf(-ys, lo), hi), dl = fminf(fmaxf(ys, lo), hi);
-  const float sr = __builtin_amdgcn_sqrtf(fmaxf(4.0f * s.A * s.tau - s.D * dr * dr, 0.0f));
-  const float sl = __builtin_amdgcn_sqrtf(fmaxf(4.0f * s.A * s.tau - s.D * dl * dl, 0.0f));
-  const float i2A = __builtin_amdgcn_rcpf(2.0f * s.A);
-  const float xmax = s.mx + (-s.B * dr + sr) * i2A + s.m;
-  const float xmin = s.mx + (-s.B * dl - sl) * i2A - s.m;
+  const float dr = fminf(fmaxf(-s.ys, lo), hi), dl = fminf(fmaxf(s.ys, lo), hi);
+  const float sr = __builtin_amdgcn_sqrtf(fmaxf(s.fat - s.D * dr * dr, 0.0f));
+  const float sl = __builtin_amdgcn_sqrtf(fmaxf(s.fat - s.D * dl * dl, 0.0f));
+  const float xmax = s.mx + (-s.B * dr + sr) * s.i2A + s.m;
+  const float xmin = s.mx + (-s.B * dl - sl) * s.i2A - s.m;
   // pixel columns px with px + 0.5 in [xmin, xmax], inside the rectangle
-  const float plo = (float)(tx0 * tile_w), phi = (float)(min(tx1 * tile_w, W) - 1);
   const float c0 = fminf(fmaxf(ceilf(xmin - 0.5f), plo), phi + 1.0f);
   const float c1 = fmaxf(fminf(floorf(xmax - 0.5f), phi), plo - 1.0f);
   if (c0 > c1) {
     b = a;
     return;
   }
-  a = (int)c0 / tile_w;
-  b = (int)c1 / tile_w + 1;
+  a = (int)c0 >> lw;
+  b = ((int)c1 >> lw) + 1;
 }
 
 // Tiles of supertile (sx, sy) that the record reaches, as the 64 bits
-// (ty - sy kST) kST + (tx - sx kST): the same support rows, cut to the
+// (ty - sy kST) kST + (tx - sx kST): the support rows, cut to the
 // supertile's columns.
 __device__ __forceinline__ uint64_t st_mask(const Support &s, int sx, int sy, int tx0, int ty0,
-                                            int tx1, int ty1, int tile_w, int tile_h, int W,
-                                            int H) {
+                                            int tx1, int ty1, int lw, int lh, int W, int H) {
   const int c0 = sx << kSTLog, y0 = sy << kSTLog;
   const int r0 = max(ty0, y0), r1 = min(ty1, y0 + kST);
+  const float plo = (float)(tx0 << lw), phi = (float)(min(tx1 << lw, W) - 1);
   uint64_t m = 0;
   for (int ty = r0; ty < r1; ++ty) {
     int a, b;
-    support_row(s, ty, tile_w, tile_h, W, H, tx0, tx1, a, b);
+    support_row(s, ty, lw, lh, H, tx0, tx1, plo, phi, a, b);
     const int l = max(a, c0), h = min(b, c0 + kST);
     if (l < h) m |= ((1ull << (h - l)) - 1ull) << ((l - c0) + ((ty - y0) << kSTLog));
   }
