@@ -169,7 +169,7 @@ void umgs_destroy(umgs_ctx *ctx) {
                     &c->sk[0], &c->sk[1], &c->sv[0], &c->sv[1], &c->masks[0], &c->masks[1], &c->st_rng,
                     &c->chunk_base, &c->cnt2, &c->chunk_tab, &c->tstart, &c->totals,
                     &c->v0, &c->v1, &c->hist, &c->ranges, &c->g2d,
-                    &c->minmax, &c->finfo, &c->tile_order, &c->pair_count, &c->view_sums};
+                    &c->minmax, &c->lb, &c->finfo, &c->tile_order, &c->pair_count, &c->view_sums};
   for (DevBuf *b : bufs) free_buf(*b);
   for (auto &p : c->prof.pending) {
     (void)hipEventDestroy(p.a);
@@ -363,10 +363,12 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
       (s = ensure(c, c->chunk_base, sizeof(uint32_t) * (sts + 1), "supertile chunks")) ||
       (s = ensure(c, c->totals, 2 * sizeof(uint64_t), "frame totals")) ||
       (s = ensure(c, c->minmax, 2 * kMinMaxSlots * sizeof(uint32_t), "depth range")) ||
+      (s = ensure(c, c->lb, sizeof(LbState), "scan state")) ||
       (s = ensure(c, c->finfo, sizeof(FrameInfo), "frame info")) ||
       (s = ensure(c, c->tile_order, sizeof(uint32_t) * (64 + tiles), "tile order")))
     return s;
   const bool fresh_info = c->finfo.cap && c->views.empty();
+  const bool fresh_lb = !c->lb_zeroed;
   bool upload = false;
   if (set < 0) {
     if (c->view_used + V > kViewSlots) {   // store full: start over (eager only)
@@ -399,6 +401,10 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
   c->stage = 0;
   hipError_t e = hipSuccess;
   if (fresh_info) e = launch_fill_u32(c, (uint32_t *)c->finfo.p, sizeof(FrameInfo) / 4, 0u);
+  if (e == hipSuccess && fresh_lb) {
+    e = launch_fill_u32(c, (uint32_t *)c->lb.p, sizeof(LbState) / 4, 0u);
+    c->lb_zeroed = e == hipSuccess;
+  }
   if (e == hipSuccess && upload)
     e = hipMemcpyAsync(dv, vps.data(), sizeof(ViewParams) * V, hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return hip_check(c, e, "view upload");
@@ -554,6 +560,9 @@ static umgs_status read_frame_info(Ctx *c, FrameInfo *out) {
   hipError_t e = hipMemcpyAsync(out, c->finfo.p, sizeof *out, hipMemcpyDeviceToHost, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_check(c, e, "frame info readback");
+  if (out->fault)
+    return fail(c, UMGS_ERR_HIP, "a device scan gave up waiting for an earlier tile (look-back "
+                "limit); the frame's lists are not valid");
   if (c->stage >= 2) c->n_dup = out->n_dup;
   return UMGS_OK;
 }

@@ -93,6 +93,71 @@ __global__ void scan_apply_kernel(T *__restrict__ data, int64_t n, const T *__re
   }
 }
 
+// Single-launch exclusive scan of 32-bit data (at most kLbMaxTiles tiles).
+// Tiles take tickets in launch order; each publishes its total with a ready
+// flag in one 64-bit word, then adds the totals of all earlier tiles, read
+// in parallel (one thread per earlier tile), so no tile waits on a chain of
+// prefixes -- only on its predecessors having published, and those hold
+// earlier tickets, so they are running or done.  The wait is bounded: past
+// the limit the tile records a fault and goes on, so every wave exits.  The
+// last tile to finish zeroes the state for the next scan.
+constexpr uint32_t kLbSpinLimit = 1u << 20;
+
+__global__ __launch_bounds__(kScanThreads) void scan_lookback_kernel(
+    uint32_t *__restrict__ data, int64_t n, uint32_t ntiles, LbState *__restrict__ st,
+    uint32_t *__restrict__ fault) {
+  __shared__ uint32_t s_tile;
+  __shared__ bool s_last;
+  if (threadIdx.x == 0) s_tile = atomicAdd(&st->ticket, 1u);
+  __syncthreads();
+  const uint32_t t = s_tile;
+  const int64_t base = (int64_t)t * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = base + k;
+    v[k] = idx < n ? data[idx] : 0u;
+    s += v[k];
+  }
+  uint32_t total;
+  const uint32_t excl = block_excl_scan(s, total);
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&st->status[t], (1ull << 32) | total, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t pre = 0;
+  for (uint32_t k = threadIdx.x; k < t; k += kScanThreads) {
+    unsigned long long w =
+        __hip_atomic_load(&st->status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t spin = 0; (w >> 32) == 0ull && spin < kLbSpinLimit; ++spin) {
+      __builtin_amdgcn_s_sleep(1);
+      w = __hip_atomic_load(&st->status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if ((w >> 32) == 0ull) atomicOr(fault, 1u);
+    pre += (uint32_t)w;
+  }
+  uint32_t pre_total;
+  block_excl_scan(pre, pre_total);
+  uint32_t run = excl + pre_total;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = base + k;
+    if (idx < n) data[idx] = run;
+    run += v[k];
+  }
+  // every thread of this tile is past its reads of the state
+  if (threadIdx.x == 0) s_last = atomicAdd(&st->done, 1u) == ntiles - 1;
+  __syncthreads();
+  if (s_last) {
+    for (uint32_t k = threadIdx.x; k < ntiles; k += kScanThreads)
+      __hip_atomic_store(&st->status[k], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&st->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 template <typename T>
 hipError_t excl_scan(hipStream_t s, T *data, int64_t n, T *tmp) {
   if (n <= 0) return hipSuccess;
@@ -147,12 +212,31 @@ __global__ void frame_totals_kernel(const unsigned long long *__restrict__ view_
 // One wave folds the slot pairs the projection kernels filled.
 // It also clears the per-view duplicate sums (V x uint64) the count stage
 // adds into.
-__global__ void depth_range_kernel(const uint32_t *__restrict__ minmax, FrameInfo *__restrict__ fi,
-                                   uint32_t *__restrict__ view_sums, int V) {
+constexpr int kRangeThreads = 1024;
+
+__global__ __launch_bounds__(kRangeThreads) void depth_range_kernel(
+    const uint32_t *__restrict__ minmax, FrameInfo *__restrict__ fi,
+    uint32_t *__restrict__ view_sums, int V) {
+  __shared__ uint32_t wlo[kRangeThreads / 64], whi[kRangeThreads / 64];
   for (int k = threadIdx.x; k < 2 * V; k += blockDim.x) view_sums[k] = 0u;
-  const uint32_t lo = wave_min_u32(minmax[threadIdx.x]);
-  const uint32_t hi = wave_max_u32(minmax[kMinMaxSlots + threadIdx.x]);
+  uint32_t l = kCulled, h = 0u;
+  for (int k = threadIdx.x; k < kMinMaxSlots; k += kRangeThreads) {
+    l = min(l, minmax[k]);
+    h = max(h, minmax[kMinMaxSlots + k]);
+  }
+  l = wave_min_u32(l);
+  h = wave_max_u32(h);
+  if ((threadIdx.x & 63) == 0) {
+    wlo[threadIdx.x >> 6] = l;
+    whi[threadIdx.x >> 6] = h;
+  }
+  __syncthreads();
   if (threadIdx.x != 0) return;
+  uint32_t lo = wlo[0], hi = whi[0];
+  for (int k = 1; k < kRangeThreads / 64; ++k) {
+    lo = min(lo, wlo[k]);
+    hi = max(hi, whi[k]);
+  }
   const bool any = lo <= hi;
   fi->depth_base = any ? lo : 0u;
   int db = 1;
@@ -187,8 +271,8 @@ __global__ void gather_st_counts_kernel(const uint32_t *__restrict__ order, int6
 
 // Resets the depth-key range slots the projection folds into.
 __global__ void minmax_reset_kernel(uint32_t *__restrict__ minmax) {
-  const int k = threadIdx.x;
-  minmax[k] = k < kMinMaxSlots ? kCulled : 0u;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < 2 * kMinMaxSlots) minmax[k] = k < kMinMaxSlots ? kCulled : 0u;
 }
 
 __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
@@ -556,13 +640,17 @@ hipError_t launch_exclusive_scan_u64(Ctx *c, uint64_t *data, int64_t n, uint64_t
 }
 
 hipError_t launch_exclusive_scan_u32(Ctx *c, uint32_t *data, int64_t n, uint32_t *tmp) {
-  return excl_scan<uint32_t>(c->stream, data, n, tmp);
+  const int64_t nt = (n + kScanTile - 1) / kScanTile;
+  if (nt <= 1 || nt > kLbMaxTiles || !c->lb_zeroed) return excl_scan<uint32_t>(c->stream, data, n, tmp);
+  FrameInfo *fi = (FrameInfo *)c->finfo.p;
+  hipLaunchKernelGGL(scan_lookback_kernel, dim3((unsigned)nt), dim3(kScanThreads), 0, c->stream,
+                     data, n, (uint32_t)nt, (LbState *)c->lb.p, &fi->fault);
+  return hipGetLastError();
 }
 
 hipError_t launch_minmax_reset(Ctx *c) {
-  static_assert(2 * kMinMaxSlots <= 1024, "one workgroup");
-  hipLaunchKernelGGL(minmax_reset_kernel, dim3(1), dim3(2 * kMinMaxSlots), 0, c->stream,
-                     (uint32_t *)c->minmax.p);
+  hipLaunchKernelGGL(minmax_reset_kernel, dim3(ceil_div(2 * kMinMaxSlots, 256)), dim3(256), 0,
+                     c->stream, (uint32_t *)c->minmax.p);
   return hipGetLastError();
 }
 
@@ -595,8 +683,7 @@ hipError_t launch_depth_order(Ctx *c) {
   hipError_t e;
   {
     ScopedTimer t(c, K_DEPTH_SORT);
-    static_assert(kMinMaxSlots == 64, "one wave folds the slots");
-    hipLaunchKernelGGL(depth_range_kernel, dim3(1), dim3(kMinMaxSlots), 0, c->stream,
+    hipLaunchKernelGGL(depth_range_kernel, dim3(1), dim3(kRangeThreads), 0, c->stream,
                        (const uint32_t *)c->minmax.p, fi, (uint32_t *)c->view_sums.p, c->V);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n > 0) {
@@ -766,7 +853,7 @@ hipError_t launch_tile_lists(Ctx *c) {
     hipLaunchKernelGGL(tile_prefix_kernel, dim3(ceil_div(c->n_st * 64, 256)), dim3(256), 0,
                        c->stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = excl_scan<uint32_t>(c->stream, a.tstart, c->n_tiles + 1,
+    if ((e = launch_exclusive_scan_u32(c, a.tstart, c->n_tiles + 1,
                                  (uint32_t *)c->scan_tmp.p)) != hipSuccess)
       return e;
   }

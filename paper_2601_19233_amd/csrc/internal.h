@@ -23,7 +23,7 @@ constexpr int kCoordLimit = 1 << 24;         // |snapped coordinate| bound (1/25
 constexpr uint32_t kCulled = 0xFFFFFFFFu;    // depth key of a culled primitive
 
 constexpr int64_t kViewSlots = 8192;   // ViewParams the device table store holds
-constexpr int kMinMaxSlots = 64;       // slot pairs of the frame's depth-key range
+constexpr int kMinMaxSlots = 4096;     // slot pairs of the frame's depth-key range
 // Supertiles: blocks of kST x kST tiles (kST = 8, so a supertile's tiles
 // index the 64 bits of a mask), the unit of the first binning level.
 constexpr int kSTLog = 3;
@@ -98,6 +98,16 @@ struct FrameInfo {
   uint32_t overflow;     // sticky: duplicates or entries exceeded a capacity
   uint32_t queue;        // work counter of the persistent blend
   uint32_t n_chunks;     // second-level chunks of the frame
+  uint32_t fault;        // sticky: a single-launch scan's look-back gave up (never expected)
+};
+
+// State of the single-launch scan: per tile, its total with a ready flag in
+// the high word; the tile ticket and the finished-tile count.  The last tile
+// of every scan leaves it all zero for the next one.
+constexpr int kLbMaxTiles = 1024;
+struct LbState {
+  unsigned long long status[kLbMaxTiles];
+  uint32_t ticket, done;
 };
 
 // Device buffer that only grows.
@@ -136,6 +146,8 @@ struct Ctx {
   uint64_t st_cap = 0;        // entries the first-level buffers hold
   double st_ratio = 0.0;      // entries / duplicates of the last eager frame
   const int64_t *view_offsets = nullptr;   // caller's per-view pixel offsets (render_batched)
+  DevBuf lb;           // LbState of the single-launch scan (zero between scans)
+  bool lb_zeroed = false;
   DevBuf minmax;       // 2 x kMinMaxSlots uint32: min / max depth-key bits (folded in bin)
   DevBuf finfo;        // FrameInfo (device)
   DevBuf tile_order;   // 64 bucket counters + n_tiles tile ids (persistent blend)

@@ -228,20 +228,37 @@ __device__ uint32_t project_gaussian(const ViewParams *__restrict__ views, int N
   return __float_as_uint(zv);
 }
 
-// Folds a wave's valid depth keys into the frame's [min, max]: one atomic
-// pair per wave, spread over kMinMaxSlots slot pairs (a single address would
-// serialise every wave of the grid); the bin stage folds the slots.
+// Folds a workgroup's valid depth keys into the frame's [min, max]: one
+// atomic pair per workgroup (256 threads), into its own slot pair of
+// kMinMaxSlots.  Atomics on one address serialise at the memory side, so
+// the frame's few thousand workgroups each get an address (with 64 slots,
+// one pair per wave, they cost the projection 56 us at 1M Gaussians); the
+// bin stage folds the slots.  Every thread of the workgroup calls it.
 __device__ __forceinline__ void reduce_key_range(uint32_t key, uint32_t *minmax) {
+  __shared__ uint32_t wlo[4], whi[4];
   const uint32_t lo = wave_min_u32(key);
   const uint32_t hi = wave_max_u32(key == kCulled ? 0u : key);
-  if ((threadIdx.x & 63) == 0 && lo != kCulled) {
-    const uint32_t slot = (blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) & (kMinMaxSlots - 1);
-    atomicMin(minmax + slot, lo);
-    atomicMax(minmax + kMinMaxSlots + slot, hi);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    wlo[w] = lo;
+    whi[w] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t l = wlo[0], h = whi[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+      l = min(l, wlo[k]);
+      h = max(h, whi[k]);
+    }
+    if (l != kCulled) {
+      const uint32_t slot = (blockIdx.y * gridDim.x + blockIdx.x) & (kMinMaxSlots - 1);
+      atomicMin(minmax + slot, l);
+      atomicMax(minmax + kMinMaxSlots + slot, h);
+    }
   }
 }
 
-__global__ void project_gaussians_kernel(const ViewParams *__restrict__ views, int N, int T,
+__global__ __launch_bounds__(256) void project_gaussians_kernel(const ViewParams *__restrict__ views, int N, int T,
                                          int sh_deg, int tile_w, int tile_h,
                                          const float *__restrict__ means,
                                          const float *__restrict__ cov3d,
@@ -353,7 +370,7 @@ __device__ uint32_t setup_triangle(const ViewParams *__restrict__ views, int N, 
   return __float_as_uint(key);
 }
 
-__global__ void setup_triangles_kernel(const ViewParams *__restrict__ views, int N, int T,
+__global__ __launch_bounds__(256) void setup_triangles_kernel(const ViewParams *__restrict__ views, int N, int T,
                                        int tile_w, int tile_h, const float *__restrict__ xyz,
                                        const float *__restrict__ rgb,
                                        const float *__restrict__ alpha,
