@@ -93,18 +93,21 @@ __global__ void scan_apply_kernel(T *__restrict__ data, int64_t n, const T *__re
   }
 }
 
-// Single-launch exclusive scan of 32-bit data (at most kLbMaxTiles tiles).
-// Tiles take tickets in launch order; each publishes its total with a ready
-// flag in one 64-bit word, then adds the totals of all earlier tiles, read
+// Single-launch exclusive scan (at most kLbMaxTiles tiles; 64-bit data with
+// tile totals below 2^63).  Tiles take tickets in launch order; each
+// publishes its total with a ready flag (bit 63) in one 64-bit word, then
+// adds the totals of all earlier tiles, read
 // in parallel (one thread per earlier tile), so no tile waits on a chain of
 // prefixes -- only on its predecessors having published, and those hold
 // earlier tickets, so they are running or done.  The wait is bounded: past
 // the limit the tile records a fault and goes on, so every wave exits.  The
 // last tile to finish zeroes the state for the next scan.
 constexpr uint32_t kLbSpinLimit = 1u << 20;
+constexpr unsigned long long kLbReady = 1ull << 63;
 
+template <typename T>
 __global__ __launch_bounds__(kScanThreads) void scan_lookback_kernel(
-    uint32_t *__restrict__ data, int64_t n, uint32_t ntiles, LbState *__restrict__ st,
+    T *__restrict__ data, int64_t n, uint32_t ntiles, LbState *__restrict__ st,
     uint32_t *__restrict__ fault) {
   __shared__ uint32_t s_tile;
   __shared__ bool s_last;
@@ -112,33 +115,33 @@ __global__ __launch_bounds__(kScanThreads) void scan_lookback_kernel(
   __syncthreads();
   const uint32_t t = s_tile;
   const int64_t base = (int64_t)t * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  uint32_t s = 0;
+  T v[kScanItems];
+  T s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t idx = base + k;
-    v[k] = idx < n ? data[idx] : 0u;
+    v[k] = idx < n ? data[idx] : T(0);
     s += v[k];
   }
-  uint32_t total;
-  const uint32_t excl = block_excl_scan(s, total);
+  T total;
+  const T excl = block_excl_scan(s, total);
   if (threadIdx.x == 0)
-    __hip_atomic_store(&st->status[t], (1ull << 32) | total, __ATOMIC_RELAXED,
+    __hip_atomic_store(&st->status[t], kLbReady | (unsigned long long)total, __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
-  uint32_t pre = 0;
+  T pre = 0;
   for (uint32_t k = threadIdx.x; k < t; k += kScanThreads) {
     unsigned long long w =
         __hip_atomic_load(&st->status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (uint32_t spin = 0; (w >> 32) == 0ull && spin < kLbSpinLimit; ++spin) {
+    for (uint32_t spin = 0; !(w & kLbReady) && spin < kLbSpinLimit; ++spin) {
       __builtin_amdgcn_s_sleep(1);
       w = __hip_atomic_load(&st->status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if ((w >> 32) == 0ull) atomicOr(fault, 1u);
-    pre += (uint32_t)w;
+    if (!(w & kLbReady)) atomicOr(fault, 1u);
+    pre += (T)(w & ~kLbReady);
   }
-  uint32_t pre_total;
+  T pre_total;
   block_excl_scan(pre, pre_total);
-  uint32_t run = excl + pre_total;
+  T run = excl + pre_total;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t idx = base + k;
@@ -635,17 +638,24 @@ size_t scan_tmp_bytes(int64_t n) {
   return (total + 16) * sizeof(uint64_t);
 }
 
+// Exclusive scans: one launch (look-back) where the state is set up and the
+// tile count allows, else reduce, scan of the tile totals, apply.
+template <typename T>
+hipError_t scan_any(Ctx *c, T *data, int64_t n, T *tmp) {
+  const int64_t nt = (n + kScanTile - 1) / kScanTile;
+  if (nt <= 1 || nt > kLbMaxTiles || !c->lb_zeroed) return excl_scan<T>(c->stream, data, n, tmp);
+  FrameInfo *fi = (FrameInfo *)c->finfo.p;
+  hipLaunchKernelGGL(scan_lookback_kernel<T>, dim3((unsigned)nt), dim3(kScanThreads), 0,
+                     c->stream, data, n, (uint32_t)nt, (LbState *)c->lb.p, &fi->fault);
+  return hipGetLastError();
+}
+
 hipError_t launch_exclusive_scan_u64(Ctx *c, uint64_t *data, int64_t n, uint64_t *tmp) {
-  return excl_scan<uint64_t>(c->stream, data, n, tmp);
+  return scan_any<uint64_t>(c, data, n, tmp);
 }
 
 hipError_t launch_exclusive_scan_u32(Ctx *c, uint32_t *data, int64_t n, uint32_t *tmp) {
-  const int64_t nt = (n + kScanTile - 1) / kScanTile;
-  if (nt <= 1 || nt > kLbMaxTiles || !c->lb_zeroed) return excl_scan<uint32_t>(c->stream, data, n, tmp);
-  FrameInfo *fi = (FrameInfo *)c->finfo.p;
-  hipLaunchKernelGGL(scan_lookback_kernel, dim3((unsigned)nt), dim3(kScanThreads), 0, c->stream,
-                     data, n, (uint32_t)nt, (LbState *)c->lb.p, &fi->fault);
-  return hipGetLastError();
+  return scan_any<uint32_t>(c, data, n, tmp);
 }
 
 hipError_t launch_minmax_reset(Ctx *c) {
@@ -702,8 +712,8 @@ hipError_t launch_depth_order(Ctx *c) {
                      (const uint32_t *)c->dv[0].p, n, (const uint64_t *)c->counts.p,
                      (uint64_t *)c->offs.p, (uint32_t *)c->st_rng.p, 2 * c->n_st);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = excl_scan<uint64_t>(c->stream, (uint64_t *)c->offs.p, n + 1,
-                               (uint64_t *)c->scan_tmp.p)) != hipSuccess)
+  if ((e = scan_any<uint64_t>(c, (uint64_t *)c->offs.p, n + 1, (uint64_t *)c->scan_tmp.p)) !=
+      hipSuccess)
     return e;
   // the view sums were cleared by depth_range_kernel
   const int64_t per = (int64_t)c->N + c->T;

@@ -11,8 +11,11 @@
 // downsweep ranks every key stably inside its block (wave ballots build the
 // equal-digit lane masks, per-wave running counts order the rounds), stages
 // the block's keys in LDS in digit order and writes each digit's run with
-// consecutive lanes on consecutive addresses.  A block covers 4096 keys:
-// 4 waves x 16 rounds x 64 lanes, wave-major, so block order is key order.
+// consecutive lanes on consecutive addresses.  A block covers 256 R keys:
+// 4 waves x R rounds x 64 lanes, wave-major, so block order is key order.
+// R (4, 8 or 16) is chosen per sort so that the grid has about a thousand
+// blocks or more: a 1M-key sort in 4096-key blocks runs one block per CU,
+// four waves, and waits on latency.
 // Logical blocks are laid out contiguously per XCD, so the digit runs that
 // neighbouring blocks write side by side are merged in the same L2.
 //
@@ -30,8 +33,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kRounds = 16;
-constexpr int kTile = kThreads * kRounds;   // 4096
+constexpr int kMinRounds = 4;
 constexpr int kBins = 256;
 
 struct PassArgs {
@@ -63,31 +65,40 @@ __device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
 }
 
 // Per-block digit counts.  Order does not matter here, so each thread reads
-// 16 consecutive keys with 16-byte loads and counts them with LDS atomics
-// into its wave's histogram (neighbouring keys -- a record's tiles -- mostly
-// carry different digits, so lanes rarely collide on an address).
-template <typename K>
+// R consecutive keys with wide loads and counts them with LDS atomics into
+// its wave's histogram (neighbouring keys -- a record's tiles -- mostly carry
+// different digits, so lanes rarely collide on an address).
+template <typename K, int R>
 __global__ __launch_bounds__(kThreads) void rs_upsweep(const K *__restrict__ keys, PassArgs a,
                                                        uint32_t *__restrict__ hist) {
   if (pass_through(a)) return;
+  constexpr int kTile = kThreads * R;
   const uint32_t n = pass_count(a);
   __shared__ uint32_t h[kWaves][kBins];
   const int tid = threadIdx.x, w = tid >> 6;
   for (int k = tid; k < kWaves * kBins; k += kThreads) (&h[0][0])[k] = 0;
   __syncthreads();
   const uint32_t blk = xcd_block(blockIdx.x, a.nblocks);
-  const uint32_t i0 = blk * kTile + tid * kRounds;
-  constexpr int kPerLoad = 16 / sizeof(K);
-  if (i0 + kRounds <= n) {
+  const uint32_t i0 = blk * kTile + tid * R;
+  constexpr int kBytes = R * (int)sizeof(K);   // 8 .. 64, a multiple of 8
+  if (i0 + R <= n) {
+    if constexpr (kBytes >= 16) {
+      constexpr int kPerLoad = 16 / sizeof(K);
 #pragma unroll
-    for (int q = 0; q < kRounds / kPerLoad; ++q) {
-      union { uint4 v; K k[kPerLoad]; } u;
-      u.v = *(const uint4 *)(keys + i0 + kPerLoad * q);
+      for (int q = 0; q < R / kPerLoad; ++q) {
+        union { uint4 v; K k[kPerLoad]; } u;
+        u.v = *(const uint4 *)(keys + i0 + kPerLoad * q);
 #pragma unroll
-      for (int j = 0; j < kPerLoad; ++j) atomicAdd(&h[w][((uint32_t)u.k[j] >> a.shift) & a.mask], 1u);
+        for (int j = 0; j < kPerLoad; ++j) atomicAdd(&h[w][((uint32_t)u.k[j] >> a.shift) & a.mask], 1u);
+      }
+    } else {
+      union { uint2 v; K k[R]; } u;
+      u.v = *(const uint2 *)(keys + i0);
+#pragma unroll
+      for (int j = 0; j < R; ++j) atomicAdd(&h[w][((uint32_t)u.k[j] >> a.shift) & a.mask], 1u);
     }
   } else {
-    for (int r = 0; r < kRounds; ++r)
+    for (int r = 0; r < R; ++r)
       if (i0 + r < n) atomicAdd(&h[w][((uint32_t)keys[i0 + r] >> a.shift) & a.mask], 1u);
   }
   __syncthreads();
@@ -96,11 +107,13 @@ __global__ __launch_bounds__(kThreads) void rs_upsweep(const K *__restrict__ key
 }
 
 // With P64, a 64-bit payload per element (pin/pout) moves with its key.
-template <typename K, bool P64>
+template <typename K, bool P64, int R>
 __global__ __launch_bounds__(kThreads) void rs_downsweep(
     const K *__restrict__ kin, const uint32_t *__restrict__ vin, const uint64_t *__restrict__ pin,
     K *__restrict__ kout, uint32_t *__restrict__ vout, uint64_t *__restrict__ pout, PassArgs a,
     const uint32_t *__restrict__ offs) {
+  constexpr int kRounds = R;
+  constexpr int kTile = kThreads * R;
   const uint32_t n = pass_count(a);
   const uint32_t blk = xcd_block(blockIdx.x, a.nblocks);
   const uint32_t base = blk * kTile;
@@ -205,9 +218,56 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
 }  // namespace
 
 size_t radix_hist_bytes(uint64_t n) {
-  const uint64_t nb = (n + kTile - 1) / kTile;
+  constexpr uint64_t kSmallest = kThreads * kMinRounds;
+  const uint64_t nb = (n + kSmallest - 1) / kSmallest;
   return (size_t)(nb * kBins + 16) * sizeof(uint32_t);
 }
+
+namespace {
+
+// Rounds per thread: 16 while that still gives about a thousand blocks,
+// else fewer (at least 4); with a payload at most 8 (its LDS staging
+// otherwise allows two blocks per CU).
+int choose_rounds(uint64_t n, bool payload) {
+  int r = 16;
+  while (r > kMinRounds && n < (uint64_t)1024 * kThreads * r) r >>= 1;
+  if (payload && r > 8) r = 8;
+  return r;
+}
+
+template <typename K, int R>
+hipError_t launch_pass(Ctx *c, K *keys[2], uint32_t *vals[2], uint64_t *pay[2], int src,
+                       const PassArgs &a, uint32_t *hist, int kid_up, int kid_scan, int kid_down) {
+  const int dst = src ^ 1;
+  const uint32_t nb = a.nblocks;
+  hipError_t e;
+  {
+    ScopedTimer t(c, kid_up);
+    hipLaunchKernelGGL((rs_upsweep<K, R>), dim3(nb), dim3(kThreads), 0, c->stream,
+                       (const K *)keys[src], a, hist);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return e;
+  {
+    ScopedTimer t(c, kid_scan);
+    e = launch_exclusive_scan_u32(c, hist, (int64_t)nb * kBins, (uint32_t *)c->scan_tmp.p);
+  }
+  if (e != hipSuccess) return e;
+  ScopedTimer t(c, kid_down);
+  if (pay)
+    hipLaunchKernelGGL((rs_downsweep<K, true, R>), dim3(nb), dim3(kThreads), 0, c->stream,
+                       (const K *)keys[src], (const uint32_t *)vals[src],
+                       (const uint64_t *)pay[src], keys[dst], vals[dst], pay[dst], a,
+                       (const uint32_t *)hist);
+  else
+    hipLaunchKernelGGL((rs_downsweep<K, false, R>), dim3(nb), dim3(kThreads), 0, c->stream,
+                       (const K *)keys[src], (const uint32_t *)vals[src],
+                       (const uint64_t *)nullptr, keys[dst], vals[dst], (uint64_t *)nullptr, a,
+                       (const uint32_t *)hist);
+  return hipGetLastError();
+}
+
+}  // namespace
 
 int radix_passes(int bits) { return bits <= 0 ? 0 : (bits + 7) / 8; }
 
@@ -223,7 +283,8 @@ hipError_t launch_radix_sort(Ctx *c, K *keys[2], uint32_t *vals[2], uint64_t *pa
                              int bits, int kid_up, int kid_scan, int kid_down) {
   if (n_launch == 0 || bits <= 0) return hipSuccess;
   const uint32_t n = (uint32_t)n_launch;
-  const uint32_t nb = (n + kTile - 1) / kTile;
+  const int rounds = choose_rounds(n, pay != nullptr);
+  const uint32_t nb = (n + kThreads * rounds - 1) / (kThreads * rounds);
   const int passes = radix_passes(bits);
   uint32_t *hist = (uint32_t *)c->hist.p;
   int shift = 0;
@@ -236,34 +297,14 @@ hipError_t launch_radix_sort(Ctx *c, K *keys[2], uint32_t *vals[2], uint64_t *pa
     a.shift = shift;
     a.mask = (1u << pb) - 1u;
     a.nblocks = nb;
-    const int src = p & 1, dst = src ^ 1;
+    const int src = p & 1;
     hipError_t e;
-    {
-      ScopedTimer t(c, kid_up);
-      hipLaunchKernelGGL(rs_upsweep<K>, dim3(nb), dim3(kThreads), 0, c->stream,
-                         (const K *)keys[src], a, hist);
-      e = hipGetLastError();
-    }
-    if (e != hipSuccess) return e;
-    {
-      ScopedTimer t(c, kid_scan);
-      e = launch_exclusive_scan_u32(c, hist, (int64_t)nb * kBins, (uint32_t *)c->scan_tmp.p);
-    }
-    if (e != hipSuccess) return e;
-    {
-      ScopedTimer t(c, kid_down);
-      if (pay)
-        hipLaunchKernelGGL((rs_downsweep<K, true>), dim3(nb), dim3(kThreads), 0, c->stream,
-                           (const K *)keys[src], (const uint32_t *)vals[src],
-                           (const uint64_t *)pay[src], keys[dst], vals[dst], pay[dst], a,
-                           (const uint32_t *)hist);
-      else
-        hipLaunchKernelGGL((rs_downsweep<K, false>), dim3(nb), dim3(kThreads), 0, c->stream,
-                           (const K *)keys[src], (const uint32_t *)vals[src],
-                           (const uint64_t *)nullptr, keys[dst], vals[dst], (uint64_t *)nullptr, a,
-                           (const uint32_t *)hist);
-      e = hipGetLastError();
-    }
+    if (rounds == 16)
+      e = launch_pass<K, 16>(c, keys, vals, pay, src, a, hist, kid_up, kid_scan, kid_down);
+    else if (rounds == 8)
+      e = launch_pass<K, 8>(c, keys, vals, pay, src, a, hist, kid_up, kid_scan, kid_down);
+    else
+      e = launch_pass<K, 4>(c, keys, vals, pay, src, a, hist, kid_up, kid_scan, kid_down);
     if (e != hipSuccess) return e;
     shift += pb;
   }
