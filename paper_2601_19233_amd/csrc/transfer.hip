@@ -365,13 +365,19 @@ __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) vo
   int face[K];
   float bu[K], bv[K];
   if constexpr (K == 8) {
-    int4 f0 = make_int4(0, 0, 0, 0), f1 = f0;
-    float4 b0 = make_float4(0.f, 0.f, 0.f, 0.f), b1 = b0, b2 = b0, b3 = b0;
+    // read once: streamed past the caches the face rows live in
+    typedef int i4v __attribute__((ext_vector_type(4)));
+    i4v f0 = {0, 0, 0, 0}, f1 = f0;
+    f4v b0 = {0.f, 0.f, 0.f, 0.f}, b1 = b0, b2 = b0, b3 = b0;
     if (valid) {
-      const int4 *fp = reinterpret_cast<const int4 *>(bind_face) + 2 * (int64_t)i;
-      const float4 *bp = reinterpret_cast<const float4 *>(bind_bary) + 4 * (int64_t)i;
-      f0 = fp[0]; f1 = fp[1];
-      b0 = bp[0]; b1 = bp[1]; b2 = bp[2]; b3 = bp[3];
+      const i4v *fp = reinterpret_cast<const i4v *>(bind_face) + 2 * (int64_t)i;
+      const f4v *bp = reinterpret_cast<const f4v *>(bind_bary) + 4 * (int64_t)i;
+      f0 = __builtin_nontemporal_load(fp);
+      f1 = __builtin_nontemporal_load(fp + 1);
+      b0 = __builtin_nontemporal_load(bp);
+      b1 = __builtin_nontemporal_load(bp + 1);
+      b2 = __builtin_nontemporal_load(bp + 2);
+      b3 = __builtin_nontemporal_load(bp + 3);
     }
     face[0] = f0.x; face[1] = f0.y; face[2] = f0.z; face[3] = f0.w;
     face[4] = f1.x; face[5] = f1.y; face[6] = f1.z; face[7] = f1.w;
