@@ -408,8 +408,14 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
   if (e == hipSuccess && upload)
     e = hipMemcpyAsync(dv, vps.data(), sizeof(ViewParams) * V, hipMemcpyHostToDevice, c->stream);
   if (e != hipSuccess) return hip_check(c, e, "view upload");
-  e = launch_minmax_reset(c);
-  if (e != hipSuccess) return hip_check(c, e, "depth range reset");
+  // the range slots start reset; after that the bin stage resets them as it
+  // folds them (a projection without a bin in between widens the next
+  // frame's range, which still holds every key)
+  if (!c->minmax_ready) {
+    e = launch_minmax_reset(c);
+    if (e != hipSuccess) return hip_check(c, e, "depth range reset");
+    c->minmax_ready = true;
+  }
   if ((e = launch_project_gaussians(c, means, cov3d, scales, quats, opacity, sh)) != hipSuccess)
     return hip_check(c, e, "project_gaussians launch");
   if ((e = launch_setup_triangles(c, tri_xyz, tri_rgb, tri_alpha)) != hipSuccess)

@@ -105,10 +105,28 @@ __global__ void scan_apply_kernel(T *__restrict__ data, int64_t n, const T *__re
 constexpr uint32_t kLbSpinLimit = 1u << 20;
 constexpr unsigned long long kLbReady = 1ull << 63;
 
+// Scan inputs: the data in place, or the supertile-entry counts (high 32 bits
+// of a record's count) gathered in depth order (0 at index n_records and
+// past it).
 template <typename T>
+struct LoadPlain {
+  const T *d;
+  __device__ T operator()(int64_t i, int64_t n) const { return i < n ? d[i] : T(0); }
+};
+struct LoadStCounts {
+  const uint32_t *order;
+  const uint64_t *counts;
+  int64_t n_rec;
+  __device__ uint64_t operator()(int64_t i, int64_t) const {
+    return i < n_rec ? counts[order[i]] >> 32 : 0ull;
+  }
+};
+
+// zero_p[0, zero_n) is cleared by the grid on the side (may be empty).
+template <typename T, typename L>
 __global__ __launch_bounds__(kScanThreads) void scan_lookback_kernel(
-    T *__restrict__ data, int64_t n, uint32_t ntiles, LbState *__restrict__ st,
-    uint32_t *__restrict__ fault) {
+    T *__restrict__ data, int64_t n, L load, uint32_t ntiles, LbState *__restrict__ st,
+    uint32_t *__restrict__ fault, uint32_t *__restrict__ zero_p, int64_t zero_n) {
   __shared__ uint32_t s_tile;
   __shared__ bool s_last;
   if (threadIdx.x == 0) s_tile = atomicAdd(&st->ticket, 1u);
@@ -119,10 +137,12 @@ __global__ __launch_bounds__(kScanThreads) void scan_lookback_kernel(
   T s = 0;
 #pragma unroll
   for (int k = 0; k < kScanItems; ++k) {
-    const int64_t idx = base + k;
-    v[k] = idx < n ? data[idx] : T(0);
+    v[k] = load(base + k, n);
     s += v[k];
   }
+  for (int64_t k = (int64_t)t * kScanThreads + threadIdx.x; k < zero_n;
+       k += (int64_t)ntiles * kScanThreads)
+    zero_p[k] = 0u;
   T total;
   const T excl = block_excl_scan(s, total);
   if (threadIdx.x == 0)
@@ -217,8 +237,11 @@ __global__ void frame_totals_kernel(const unsigned long long *__restrict__ view_
 // adds into.
 constexpr int kRangeThreads = 1024;
 
+// Folds the projection's depth-key range slots into the frame info and
+// resets them for the next projection (each thread reads and resets its own
+// slots); also clears the per-view sums.
 __global__ __launch_bounds__(kRangeThreads) void depth_range_kernel(
-    const uint32_t *__restrict__ minmax, FrameInfo *__restrict__ fi,
+    uint32_t *__restrict__ minmax, FrameInfo *__restrict__ fi,
     uint32_t *__restrict__ view_sums, int V) {
   __shared__ uint32_t wlo[kRangeThreads / 64], whi[kRangeThreads / 64];
   for (int k = threadIdx.x; k < 2 * V; k += blockDim.x) view_sums[k] = 0u;
@@ -226,6 +249,8 @@ __global__ __launch_bounds__(kRangeThreads) void depth_range_kernel(
   for (int k = threadIdx.x; k < kMinMaxSlots; k += kRangeThreads) {
     l = min(l, minmax[k]);
     h = max(h, minmax[kMinMaxSlots + k]);
+    minmax[k] = kCulled;
+    minmax[kMinMaxSlots + k] = 0u;
   }
   l = wave_min_u32(l);
   h = wave_max_u32(h);
@@ -645,8 +670,9 @@ hipError_t scan_any(Ctx *c, T *data, int64_t n, T *tmp) {
   const int64_t nt = (n + kScanTile - 1) / kScanTile;
   if (nt <= 1 || nt > kLbMaxTiles || !c->lb_zeroed) return excl_scan<T>(c->stream, data, n, tmp);
   FrameInfo *fi = (FrameInfo *)c->finfo.p;
-  hipLaunchKernelGGL(scan_lookback_kernel<T>, dim3((unsigned)nt), dim3(kScanThreads), 0,
-                     c->stream, data, n, (uint32_t)nt, (LbState *)c->lb.p, &fi->fault);
+  hipLaunchKernelGGL((scan_lookback_kernel<T, LoadPlain<T>>), dim3((unsigned)nt),
+                     dim3(kScanThreads), 0, c->stream, data, n, LoadPlain<T>{data}, (uint32_t)nt,
+                     (LbState *)c->lb.p, &fi->fault, (uint32_t *)nullptr, (int64_t)0);
   return hipGetLastError();
 }
 
@@ -694,7 +720,7 @@ hipError_t launch_depth_order(Ctx *c) {
   {
     ScopedTimer t(c, K_DEPTH_SORT);
     hipLaunchKernelGGL(depth_range_kernel, dim3(1), dim3(kRangeThreads), 0, c->stream,
-                       (const uint32_t *)c->minmax.p, fi, (uint32_t *)c->view_sums.p, c->V);
+                       (uint32_t *)c->minmax.p, fi, (uint32_t *)c->view_sums.p, c->V);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (n > 0) {
       hipLaunchKernelGGL(depth_prep_kernel, dim3(ceil_div(n, 256)), dim3(256), 0, c->stream,
@@ -708,13 +734,24 @@ hipError_t launch_depth_order(Ctx *c) {
     }
   }
   ScopedTimer t(c, K_SCAN);
-  hipLaunchKernelGGL(gather_st_counts_kernel, dim3(ceil_div(n + 1, 256)), dim3(256), 0, c->stream,
-                     (const uint32_t *)c->dv[0].p, n, (const uint64_t *)c->counts.p,
-                     (uint64_t *)c->offs.p, (uint32_t *)c->st_rng.p, 2 * c->n_st);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if ((e = scan_any<uint64_t>(c, (uint64_t *)c->offs.p, n + 1, (uint64_t *)c->scan_tmp.p)) !=
-      hipSuccess)
-    return e;
+  const int64_t nt = (n + 1 + kScanTile - 1) / kScanTile;
+  if (nt > 1 && nt <= kLbMaxTiles && c->lb_zeroed) {
+    // one launch: gather in depth order, scan, clear the supertile ranges
+    hipLaunchKernelGGL((scan_lookback_kernel<uint64_t, LoadStCounts>), dim3((unsigned)nt),
+                       dim3(kScanThreads), 0, c->stream, (uint64_t *)c->offs.p, n + 1,
+                       LoadStCounts{(const uint32_t *)c->dv[0].p, (const uint64_t *)c->counts.p, n},
+                       (uint32_t)nt, (LbState *)c->lb.p, &fi->fault, (uint32_t *)c->st_rng.p,
+                       2 * c->n_st);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(gather_st_counts_kernel, dim3(ceil_div(n + 1, 256)), dim3(256), 0,
+                       c->stream, (const uint32_t *)c->dv[0].p, n, (const uint64_t *)c->counts.p,
+                       (uint64_t *)c->offs.p, (uint32_t *)c->st_rng.p, 2 * c->n_st);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan_any<uint64_t>(c, (uint64_t *)c->offs.p, n + 1, (uint64_t *)c->scan_tmp.p)) !=
+        hipSuccess)
+      return e;
+  }
   // the view sums were cleared by depth_range_kernel
   const int64_t per = (int64_t)c->N + c->T;
   if (per > 0) {

@@ -149,6 +149,7 @@ struct Ctx {
   DevBuf lb;           // LbState of the single-launch scan (zero between scans)
   bool lb_zeroed = false;
   DevBuf minmax;       // 2 x kMinMaxSlots uint32: min / max depth-key bits (folded in bin)
+  bool minmax_ready = false;   // reset once; the bin stage resets as it folds
   DevBuf finfo;        // FrameInfo (device)
   DevBuf tile_order;   // 64 bucket counters + n_tiles tile ids (persistent blend)
   DevBuf pair_count;   // 4 uint64: blend work counters (measurement)
