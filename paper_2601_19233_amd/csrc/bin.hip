@@ -579,9 +579,34 @@ __global__ void ranges_kernel(const uint32_t *__restrict__ tstart, int64_t n_til
 // among the chunk's entries with that bit (earlier rounds, earlier waves,
 // earlier lanes).
 // Stores go tile by tile, so the lanes of a store write consecutive words.
+// One round of a wave's 64 entries: for tile j, the lanes whose mask has
+// bit j write consecutive positions (rank among them = set bits of the
+// ballot below the lane).  CHECKED: some positions may reach the capacity.
+template <bool CHECKED>
+__device__ __forceinline__ void scatter_round(uint64_t m, uint32_t r, uint32_t off, uint32_t cap,
+                                              uint32_t *__restrict__ out) {
+  const uint32_t mw[2] = {(uint32_t)m, (uint32_t)(m >> 32)};
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll 4
+    for (int jj = 0; jj < 32; ++jj) {
+      const bool bit = __builtin_amdgcn_ubfe(mw[h], jj, 1) != 0u;
+      const uint64_t b = __builtin_amdgcn_ballot_w64(bit);
+      if (b == 0) continue;
+      const int j = 32 * h + jj;
+      const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)off, j);
+      const uint32_t pos = o + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+      if (bit && (!CHECKED || pos < cap)) out[pos] = r;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kL2Threads) void tile_scatter_kernel(L2Args a) {
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x);
   if (c >= a.fi->n_chunks) return;
+  // every list fits (the usual case): no per-position capacity test
+  const bool fits = a.tstart[a.n_tiles] <= a.cap;
   __shared__ uint32_t base[64];
   __shared__ uint32_t wc[kL2Waves][64];
   const ChunkRec ck = a.chunks[c];
@@ -616,28 +641,10 @@ __global__ __launch_bounds__(kL2Threads) void tile_scatter_kernel(L2Args a) {
     }
     __syncthreads();   // every wave has read base and wc (the next round rewrites wc)
     if (w == 0) base[lane] += tot;
-    // tile j: the lanes whose mask has bit j write consecutive positions
-    // (rank among them = set bits of the ballot below the lane)
-    const uint32_t mw[2] = {(uint32_t)m, (uint32_t)(m >> 32)};
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-#pragma unroll 4
-      for (int jj = 0; jj < 32; ++jj) {
-        const bool bit = __builtin_amdgcn_ubfe(mw[h], jj, 1) != 0u;
-        const uint64_t b = __builtin_amdgcn_ballot_w64(bit);
-        if (b == 0) continue;
-        const int j = 32 * h + jj;
-        const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)off, j);
-        const uint32_t pos =
-            o + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
-                                          __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-        if (o + (uint32_t)__popcll(b) <= cap) {
-          if (bit) a.out[pos] = r;
-        } else if (bit && pos < cap) {
-          a.out[pos] = r;
-        }
-      }
-    }
+    if (fits)
+      scatter_round<false>(m, r, off, cap, a.out);
+    else
+      scatter_round<true>(m, r, off, cap, a.out);
   }
 }
 

@@ -117,36 +117,36 @@ __device__ __forceinline__ void blend_tile(
           // Gaussians [f, fe): alpha of kUnroll fragments evaluated together
           // (they do not depend on the pixel's state), then blended in list
           // order.  Every decision is a per-lane select: a fragment that
-          // does not contribute gets alpha 0; Tl, the live transmittance,
-          // drops to exactly 0 when the pixel stops (so later fragments add
-          // w = 0 and never blend) while Tf keeps the pixel's final value.
-          // A stop is a fragment whose T (1 - alpha) would fall below 1e-4
-          // (once stopped, Tl = 0 satisfies that test again, which changes
-          // nothing).
+          // does not contribute gets alpha 0.  A stop is a fragment whose
+          // T (1 - alpha) would fall below 1e-4; Tf keeps the pixel's final
+          // T, while Tl, the running product, goes on falling below 1e-4,
+          // so every later fragment is a stop too and adds nothing (a live
+          // pixel always has T >= 1e-4).
           constexpr int kUnroll = 4;
           float Tl = done ? 0.0f : Tr, Tf = Tr;   // a pixel stopped in an earlier run stays stopped
           const int32_t last0 = last;
           for (; f + kUnroll <= fe; f += kUnroll) {
-            if (__all(Tl == 0.0f)) break;
+            if (__all(Tl < kTStop)) break;
             if (COUNT) n_wit += kUnroll;
             float al[kUnroll], cr[kUnroll], cg[kUnroll], cb[kUnroll];
+            bool ok[kUnroll];
 #pragma unroll
             for (int k = 0; k < kUnroll; ++k) {
               const uint32_t *s = slots + (f + k) * kSlotWords;
               float a;
-              const bool ok = gauss_alpha(s, pcx, pcy, a);
-              al[k] = ok ? a : 0.0f;
+              ok[k] = gauss_alpha(s, pcx, pcy, a);
+              al[k] = ok[k] ? a : 0.0f;
               cr[k] = __uint_as_float(s[6]);
               cg[k] = __uint_as_float(s[7]);
               cb[k] = __uint_as_float(s[8]);
             }
 #pragma unroll
             for (int k = 0; k < kUnroll; ++k) {
-              if (COUNT) n_gp += Tl == 0.0f ? 0u : 1u;
+              if (COUNT) n_gp += Tl < kTStop ? 0u : 1u;
               const float w = Tl * al[k];
               const float test_T = Tl - w;      // T (1 - alpha)
               const bool stop = test_T < kTStop;
-              const bool blend = !stop && w > 0.0f;
+              const bool blend = !stop && ok[k];
               const float wc = stop ? 0.0f : w;
               C0 = fmaf(wc, cr[k], C0);
               C1 = fmaf(wc, cg[k], C1);
@@ -154,21 +154,21 @@ __device__ __forceinline__ void blend_tile(
               Tent = blend ? Tl : Tent;
               last = blend ? (int32_t)(bstart - rg.x + f + k + 1) : last;
               Tf = stop ? Tf : test_T;
-              Tl = stop ? 0.0f : test_T;
+              Tl = test_T;
             }
           }
           // the rest of the run one at a time, same arithmetic
           for (; f < fe; ++f) {
-            if (__all(Tl == 0.0f)) break;
+            if (__all(Tl < kTStop)) break;
             if (COUNT) ++n_wit;
-            if (COUNT) n_gp += Tl == 0.0f ? 0u : 1u;
+            if (COUNT) n_gp += Tl < kTStop ? 0u : 1u;
             const uint32_t *s = slots + f * kSlotWords;
             float a;
             const bool ok = gauss_alpha(s, pcx, pcy, a);
             const float w = Tl * (ok ? a : 0.0f);
             const float test_T = Tl - w;
             const bool stop = test_T < kTStop;
-            const bool blend = !stop && w > 0.0f;
+            const bool blend = !stop && ok;
             const float wc = stop ? 0.0f : w;
             C0 = fmaf(wc, __uint_as_float(s[6]), C0);
             C1 = fmaf(wc, __uint_as_float(s[7]), C1);
@@ -176,10 +176,10 @@ __device__ __forceinline__ void blend_tile(
             Tent = blend ? Tl : Tent;
             last = blend ? (int32_t)(bstart - rg.x + f + 1) : last;
             Tf = stop ? Tf : test_T;
-            Tl = stop ? 0.0f : test_T;
+            Tl = test_T;
           }
           Tr = Tf;
-          done = Tl == 0.0f;
+          done = Tl < kTStop;
           // a blended Gaussian ends the run of consecutive triangles
           if (mode != UMGS_MODE_ONE_ENTITY && last != last0) in_entity = false;
           if (__all(done)) break;
