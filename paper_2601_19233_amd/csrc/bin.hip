@@ -503,14 +503,19 @@ struct L2Args {
 
 // Lane j's result: how many lanes of the wave have bit j of m set.
 __device__ __forceinline__ uint32_t wave_bit_counts(uint64_t m) {
-  const int lane = threadIdx.x & 63;
-  uint32_t mine = 0;
+  const uint32_t mw[2] = {(uint32_t)m, (uint32_t)(m >> 32)};
+  int mine = 0;
 #pragma unroll
-  for (int j = 0; j < 64; ++j) {
-    const uint32_t n = (uint32_t)__popcll(__ballot((m >> j) & 1ull));
-    mine = lane == j ? n : mine;
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int jj = 0; jj < 32; ++jj) {
+      // ballot of bit j, its count (scalar) written straight into lane j
+      const uint64_t b = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_ubfe(mw[h], jj, 1) != 0u);
+      const int n = (int)__popcll(b);
+      asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mine) : "s"(n), "i"(32 * h + jj));
+    }
   }
-  return mine;
+  return (uint32_t)mine;
 }
 
 // A chunk's per-tile counts (bit counts of its entries' masks).
