@@ -485,6 +485,69 @@ __global__ void chunk_table_kernel(const ViewParams *__restrict__ views, int V,
   }
 }
 
+// The three steps above in one workgroup, for frames of at most kScanTile - 1
+// supertiles: chunk counts, their exclusive scan (left in chunk_base and in
+// LDS, the total in the frame info), then the chunk table with one thread
+// per chunk (its supertile found by binary search in the scanned counts).
+__global__ __launch_bounds__(kScanThreads) void chunk_plan_kernel(
+    const ViewParams *__restrict__ views, int V, const uint2 *__restrict__ rng, int64_t n_st,
+    uint32_t *__restrict__ chunk_base, FrameInfo *__restrict__ fi, ChunkRec *__restrict__ tab) {
+  __shared__ uint32_t cb[kScanTile];
+  __shared__ uint32_t s_total;
+  const int64_t s0 = (int64_t)threadIdx.x * kScanItems;
+  uint32_t cnt[kScanItems];
+  uint32_t sum = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t s = s0 + k;
+    uint32_t n = 0;
+    if (s < n_st) {
+      const uint2 r = rng[s];
+      n = r.y > r.x ? (r.y - r.x + kChunk - 1) / kChunk : 0u;
+    }
+    cnt[k] = n;
+    sum += n;
+  }
+  uint32_t total;
+  uint32_t run = block_excl_scan(sum, total);
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t s = s0 + k;
+    if (s <= n_st) {
+      chunk_base[s] = run;
+      cb[s] = run;
+    }
+    run += cnt[k];
+  }
+  if (threadIdx.x == 0) {
+    fi->n_chunks = total;
+    s_total = total;
+  }
+  __syncthreads();
+  const uint32_t nc = s_total;
+  for (uint32_t c = threadIdx.x; c < nc; c += kScanThreads) {
+    // last supertile s with cb[s] <= c (cb is non-decreasing, cb[0] = 0)
+    uint32_t lo = 0, hi = (uint32_t)n_st;   // cb[lo] <= c < cb[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (cb[mid] <= c) lo = mid; else hi = mid;
+    }
+    const uint32_t s = lo;
+    const uint2 r = rng[s];
+    const int v = view_of_st(views, V, s);
+    const ViewParams &vp = views[v];
+    const uint32_t sl = s - vp.st_base;
+    const uint32_t nstx = (uint32_t)(vp.ntx + kST - 1) >> kSTLog;
+    const uint32_t k = c - cb[s];
+    ChunkRec ck;
+    ck.e0 = r.x + k * (uint32_t)kChunk;
+    ck.nk = (min(ck.e0 + (uint32_t)kChunk, r.y) - ck.e0) | (k << 11);
+    ck.v = (uint32_t)v;
+    ck.cxy = ((sl % nstx) << kSTLog) | ((sl / nstx) << (kSTLog + 16));
+    tab[c] = ck;
+  }
+}
+
 struct L2Args {
   const ViewParams *views;
   int V, per_view, N, tile_w, tile_h;
@@ -865,6 +928,11 @@ hipError_t launch_st_bin(Ctx *c) {
     hipLaunchKernelGGL(st_ranges_kernel<uint32_t>, dim3(ceil_div(c->st_launch, 1024)), dim3(256), 0,
                        c->stream, (const uint32_t *)c->sk[out].p, (const FrameInfo *)fi, rng);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (c->n_st + 1 <= kScanTile) {
+    hipLaunchKernelGGL(chunk_plan_kernel, dim3(1), dim3(kScanThreads), 0, c->stream, c->cur_views,
+                       c->V, (const uint2 *)rng, c->n_st, cb, fi, (ChunkRec *)c->chunk_tab.p);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(st_chunks_kernel, dim3(ceil_div(c->n_st + 1, 256)), dim3(256), 0, c->stream,
                      (const uint2 *)rng, c->n_st, cb);
   if ((e = hipGetLastError()) != hipSuccess) return e;

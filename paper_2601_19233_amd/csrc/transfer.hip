@@ -246,6 +246,9 @@ __device__ __forceinline__ float pinned_mean(float m, float s, float invk) {
   return m + s * invk;
 }
 
+__device__ __forceinline__ float nt_load(const float *p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ void nt_store(float *p, float v) { __builtin_nontemporal_store(v, p); }
+
 // Eq. 13 for Gaussian i from its corner sums: dsum = sum_k Delta_k (pinned
 // order), rs = sum_k r_k, Ss = sum_k S_k (xx, xy, xz, yy, yz, zz).
 __device__ __forceinline__ void finish_gaussian(int i, float3 dsum, const float rs[3],
@@ -257,9 +260,12 @@ __device__ __forceinline__ void finish_gaussian(int i, float3 dsum, const float 
                                                 float *__restrict__ quats_out,
                                                 float *__restrict__ cov3d_out,
                                                 float *__restrict__ xform_out) {
-  means_out[3 * i] = pinned_mean(means[3 * i], dsum.x, invk);
-  means_out[3 * i + 1] = pinned_mean(means[3 * i + 1], dsum.y, invk);
-  means_out[3 * i + 2] = pinned_mean(means[3 * i + 2], dsum.z, invk);
+  // inputs read once, and the outputs the projection does not read next
+  // (A, q'), are streamed (non-temporal), so they do not push the face rows
+  // out of L2
+  means_out[3 * i] = pinned_mean(nt_load(means + 3 * i), dsum.x, invk);
+  means_out[3 * i + 1] = pinned_mean(nt_load(means + 3 * i + 1), dsum.y, invk);
+  means_out[3 * i + 2] = pinned_mean(nt_load(means + 3 * i + 2), dsum.z, invk);
 
   // R' = exp(mean r), S' = mean S, A = R'S'
   const float r0 = rs[0] * invk, r1 = rs[1] * invk, r2 = rs[2] * invk;
@@ -290,13 +296,15 @@ __device__ __forceinline__ void finish_gaussian(int i, float3 dsum, const float 
     for (int c = 0; c < 3; ++c)
       A[3 * r + c] = Rp[3 * r] * Sm[c] + Rp[3 * r + 1] * Sm[3 + c] + Rp[3 * r + 2] * Sm[6 + c];
 
-  float qw = quats[4 * i], qx = quats[4 * i + 1], qy = quats[4 * i + 2], qz = quats[4 * i + 3];
+  float qw = nt_load(quats + 4 * i), qx = nt_load(quats + 4 * i + 1), qy = nt_load(quats + 4 * i + 2),
+        qz = nt_load(quats + 4 * i + 3);
   const float qn = rsqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
   qw *= qn; qx *= qn; qy *= qn; qz *= qn;
   const float Rq[9] = {1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy),
                        2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx),
                        2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)};
-  const float s0 = scales[3 * i], s1 = scales[3 * i + 1], s2 = scales[3 * i + 2];
+  const float s0 = nt_load(scales + 3 * i), s1 = nt_load(scales + 3 * i + 1),
+              s2 = nt_load(scales + 3 * i + 2);
   // B = A R(q) diag(s); Sigma' = B B^T
   float B[9];
 #pragma unroll
@@ -314,15 +322,15 @@ __device__ __forceinline__ void finish_gaussian(int i, float3 dsum, const float 
   cv[5] = B[6] * B[6] + B[7] * B[7] + B[8] * B[8];
   if (xform_out) {
 #pragma unroll
-    for (int k = 0; k < 9; ++k) xform_out[9 * (int64_t)i + k] = A[k];
+    for (int k = 0; k < 9; ++k) nt_store(xform_out + 9 * (int64_t)i + k, A[k]);
   }
   if (quats_out) {
     const float pw = cosf(0.5f * th), px = sh_over * r0, py = sh_over * r1, pz = sh_over * r2;
     float *qo = quats_out + 4 * (int64_t)i;
-    qo[0] = pw * qw - px * qx - py * qy - pz * qz;
-    qo[1] = pw * qx + px * qw + py * qz - pz * qy;
-    qo[2] = pw * qy - px * qz + py * qw + pz * qx;
-    qo[3] = pw * qz + px * qy - py * qx + pz * qw;
+    nt_store(qo + 0, pw * qw - px * qx - py * qy - pz * qz);
+    nt_store(qo + 1, pw * qx + px * qw + py * qz - pz * qy);
+    nt_store(qo + 2, pw * qy - px * qz + py * qw + pz * qx);
+    nt_store(qo + 3, pw * qz + px * qy - py * qx + pz * qw);
   }
 }
 
