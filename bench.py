@@ -333,7 +333,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0, help="primitive-count scale (1 = full workload)")
     ap.add_argument("--res-scale", type=float, default=1.0)
     ap.add_argument("--tile", default="16x16")
-    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--schedule", type=int, default=0, help="blend schedule: 0 tile grid, 1 persistent")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")

@@ -82,7 +82,7 @@ enum {
   UMGS_MODE_LITERAL_T = 3    /* entity with pixel T updated per Eq. 6 with Eq. 8's O */
 };
 
-/* Default options: 16x16 tiles, batch 64, SH degree 0, K = 8, UniMGS mode,
+/* Default options: 16x16 tiles, batch 128, SH degree 0, K = 8, UniMGS mode,
  * one workgroup per tile, black background. */
 void umgs_default_options(umgs_options *opt);
 

@@ -123,7 +123,7 @@ void umgs_default_options(umgs_options *opt) {
   if (!opt) return;
   opt->tile_w = 16;
   opt->tile_h = 16;
-  opt->frag_batch = 64;
+  opt->frag_batch = 128;
   opt->sh_degree = 0;
   opt->k_bind = 8;
   opt->mode = UMGS_MODE_UNIMGS;

@@ -309,7 +309,7 @@ __global__ void fill_u32_kernel(uint32_t *p, int64_t n, uint32_t v) {
 }
 
 // The frame's sizes on the device, each clamped to its buffer's capacity
-// (overflow flagged, sticky), and the persistent blend's queue reset.  The
+// (overflow flagged, sticky).  The
 // duplicates are bounded by the records' rectangles here; the tile scan
 // replaces the bound by the exact count (ranges_kernel).
 __global__ void frame_info_kernel(const uint64_t *__restrict__ totals, uint64_t cap,

@@ -96,7 +96,7 @@ struct FrameInfo {
   uint32_t n1;           // supertile entries (clamped to their capacity)
   int32_t sorted_in;     // 0: tile lists in v0 (1: in v1)
   uint32_t overflow;     // sticky: duplicates or entries exceeded a capacity
-  uint32_t queue;        // work counter of the persistent blend
+  uint32_t queue;        // reserved (kept zero)
   uint32_t n_chunks;     // second-level chunks of the frame
   uint32_t fault;        // sticky: a single-launch scan's look-back gave up (never expected)
 };

@@ -54,7 +54,7 @@ def camera_struct(cam) -> L.Camera:
     return c
 
 
-def make_options(tile=(16, 16), frag_batch=64, sh_degree=0, k_bind=8, mode=0, schedule=0,
+def make_options(tile=(16, 16), frag_batch=128, sh_degree=0, k_bind=8, mode=0, schedule=0,
                  bg=(0.0, 0.0, 0.0)) -> L.Options:
     o = L.Options()
     o.tile_w, o.tile_h = int(tile[0]), int(tile[1])

@@ -44,5 +44,5 @@ def test_option_validation_without_device():
         assert not h.value
     d = _lib.Options()
     lib.umgs_default_options(C.byref(d))
-    assert (d.tile_w, d.tile_h, d.frag_batch, d.k_bind) == (16, 16, 64, 8)
+    assert (d.tile_w, d.tile_h, d.frag_batch, d.k_bind) == (16, 16, 128, 8)
     assert lib.umgs_last_error(None) == b""

@@ -73,7 +73,7 @@ def test_cfg1_full_frame(gpu, cfg1):
     cam = s.cams[0]
     note(f"cfg1 full: N={s.N} T={s.T} {cam.width}x{cam.height}")
     d = dev_tensors(s)
-    r = Rasterizer("cuda:0", tile=(16, 16), frag_batch=64)
+    r = Rasterizer("cuda:0", tile=(16, 16), frag_batch=128)
     r.set_proxy(s.proxy.V_rest, s.proxy.faces)
     df = d["deform"]
     dt = r.bind_transfer(df["V_def"], df["bind_face"], df["bind_bary"], d["means"], d["quats"], d["scales"])
