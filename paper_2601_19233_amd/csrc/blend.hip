@@ -123,7 +123,7 @@ __device__ __forceinline__ void blend_tile(
           // T, while Tl, the running product, goes on falling below 1e-4,
           // so every later fragment is a stop too and adds nothing (a live
           // pixel always has T >= 1e-4).
-          constexpr int kUnroll = 4;
+          constexpr int kUnroll = 8;
           float Tl = done ? 0.0f : Tr, Tf = Tr;   // a pixel stopped in an earlier run stays stopped
           const int32_t last0 = last;
           for (; f + kUnroll <= fe; f += kUnroll) {
