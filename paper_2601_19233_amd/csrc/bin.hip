@@ -345,31 +345,61 @@ __device__ __forceinline__ void unpack_rect(uint2 rc, int &tx0, int &ty0, int &t
   ty1 = rc.y >> 16;
 }
 
-// One thread per record (in depth order) writes one entry per supertile of
-// its tile rectangle, rows top to bottom, columns left to right (their order
-// does not matter: a record has at most one entry per supertile).
+// Entries of a record: one per supertile of its tile rectangle, rows top to
+// bottom, columns left to right (their order within a record does not
+// matter; the sort by supertile is stable over records in depth order).
+// A wave takes 64 consecutive records and writes their entries -- one
+// contiguous run of the output -- with consecutive lanes on consecutive
+// entries: each lane finds its entry's record by binary search over the 64
+// records' first entries (LDS), so a record with many supertiles does not
+// hold the others' lanes, and every store is coalesced.
 template <typename K>
-__global__ void st_emit_kernel(StEmitArgs e) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= e.n_records) return;
-  uint64_t pos = e.offs[i];
-  const uint64_t end = min(e.offs[i + 1], (uint64_t)e.fi->n1);
-  if (pos >= end) return;
-  K *keys = (K *)e.keys;
-  const uint32_t r = e.order[i];
-  int tx0, ty0, tx1, ty1;
-  unpack_rect(e.rects[r], tx0, ty0, tx1, ty1);
-  const uint32_t v = r / (uint32_t)e.per_view;
-  const ViewParams &vp = e.views[v];
-  const uint32_t nstx = (uint32_t)(vp.ntx + kST - 1) >> kSTLog;
-  const int lo = tx0 >> kSTLog, hi = ((tx1 - 1) >> kSTLog) + 1;
-  for (int sy = ty0 >> kSTLog; sy <= (ty1 - 1) >> kSTLog; ++sy) {
-    for (int sx = lo; sx < hi; ++sx) {
-      if (pos >= end) return;
-      keys[pos] = (K)(vp.st_base + (uint32_t)sy * nstx + (uint32_t)sx);
-      e.vals[pos] = r;
-      ++pos;
+__global__ __launch_bounds__(256) void st_emit_kernel(StEmitArgs e) {
+  __shared__ uint32_t s_p0[4][64], s_rec[4][64], s_base[4][64], s_dim[4][64];
+  const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+  const uint32_t n1 = e.fi->n1;
+  uint32_t p0 = 0xFFFFFFFFu, p1 = 0u, r = 0u, base = 0u, dim = 1u;
+  if (i < e.n_records) {
+    p0 = (uint32_t)min(e.offs[i], (uint64_t)n1);
+    p1 = (uint32_t)min(e.offs[i + 1], (uint64_t)n1);
+    if (p1 > p0) {
+      r = e.order[i];
+      int tx0, ty0, tx1, ty1;
+      unpack_rect(e.rects[r], tx0, ty0, tx1, ty1);
+      const uint32_t v = r / (uint32_t)e.per_view;
+      const ViewParams &vp = e.views[v];
+      const uint32_t nstx = (uint32_t)(vp.ntx + kST - 1) >> kSTLog;
+      const uint32_t sx0 = (uint32_t)tx0 >> kSTLog, sy0 = (uint32_t)ty0 >> kSTLog;
+      const uint32_t nsx = (((uint32_t)tx1 - 1) >> kSTLog) - sx0 + 1;
+      base = vp.st_base + sy0 * nstx + sx0;
+      dim = nsx | (nstx << 16);
     }
+  }
+  s_p0[w][lane] = p0;
+  s_rec[w][lane] = r;
+  s_base[w][lane] = base;
+  s_dim[w][lane] = dim;
+  // the wave's entries: [first entry of its first record, last end)
+  const uint32_t first = (uint32_t)__builtin_amdgcn_readfirstlane((int)p0);
+  const uint32_t last = wave_max_u32(p1);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  K *keys = (K *)e.keys;
+  for (uint32_t en = first + lane; en < last; en += 64) {
+    // the last record (lane) whose first entry is at or before en
+    int lo = 0, hi = 64;
+#pragma unroll
+    for (int step = 0; step < 6; ++step) {
+      const int mid = (lo + hi) >> 1;
+      if (s_p0[w][mid] <= en) lo = mid; else hi = mid;
+    }
+    const uint32_t k = en - s_p0[w][lo];
+    const uint32_t dm = s_dim[w][lo], nsx = dm & 0xFFFFu, nstx = dm >> 16;
+    const uint32_t q = k / nsx;
+    keys[en] = (K)(s_base[w][lo] + q * nstx + (k - q * nsx));
+    e.vals[en] = s_rec[w][lo];
   }
 }
 
