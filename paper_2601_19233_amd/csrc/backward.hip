@@ -74,7 +74,11 @@ struct PixBwd {
 
 // One Gaussian fragment (list position pos) of the walk: updates the
 // pixel's state where it blended the fragment and leaves the pixel's 9
-// gradient terms in g (exact zeros where it did not).  Returns whether it
+// gradient terms in g (exact zeros where it did not), in the reduced form
+// that the wave sums: (dp dx, dp dy, dp dx^2, dp dx dy, dp dy^2, a dpow,
+// w dC); finish_terms turns the sums into the gradients of the mean and
+// opacity with the fragment's constants, once per wave instead of per
+// pixel.  Returns whether it
 // blended it.  Every lane evaluates every term (no short-circuit), so the
 // wave sums that follow see defined values on all lanes.
 __device__ __forceinline__ bool gauss_bwd(const uint32_t *s, int pos, float pcx, float pcy,
@@ -103,22 +107,32 @@ __device__ __forceinline__ bool gauss_bwd(const uint32_t *s, int pos, float pcx,
   }
   // alpha below the 0.99 clamp depends on power and opacity
   const float dpow = (a_un < kAlphaMax) ? dLda : 0.0f;
-  const float qa = __uint_as_float(s[2]), qb = __uint_as_float(s[3]), qc = __uint_as_float(s[4]);
   const float dp = alpha * dpow;     // d alpha / d power = o exp(power) = alpha
-  const float dpl = dp * kLn2;       // the stored coefficients carry log2(e)
   // offsets of other lanes may be huge (a far mean): keep 0 x inf out
   dx = contrib ? dx : 0.0f;
   dy = contrib ? dy : 0.0f;
-  g[0] = dpl * (2.0f * qa * dx + qb * dy);
-  g[1] = dpl * (qb * dx + 2.0f * qc * dy);
-  g[2] = dp * dx * dx;
-  g[3] = dp * dx * dy;
-  g[4] = dp * dy * dy;
-  g[5] = a_un * __uint_as_float(s[kSlotInvO]) * dpow;   // d alpha / d o = exp(power)
+  const float dpx = dp * dx, dpy = dp * dy;
+  g[0] = dpx;
+  g[1] = dpy;
+  g[2] = dpx * dx;
+  g[3] = dpx * dy;
+  g[4] = dpy * dy;
+  g[5] = a_un * dpow;                // times 1/o: d alpha / d o = exp(power)
   g[6] = w * q.dC0;
   g[7] = w * q.dC1;
   g[8] = w * q.dC2;
   return contrib;
+}
+
+// Gradient of the 2D mean and of the opacity from the wave's sums of the
+// reduced terms (the stored power coefficients carry log2(e)):
+// d/dmean = ln2 (2 qa S_dx + qb S_dy, qb S_dx + 2 qc S_dy), d/do = S_a / o.
+__device__ __forceinline__ void finish_terms(const uint32_t *s, float *g) {
+  const float qa = __uint_as_float(s[2]), qb = __uint_as_float(s[3]), qc = __uint_as_float(s[4]);
+  const float sx = g[0], sy = g[1];
+  g[0] = kLn2 * (2.0f * qa * sx + qb * sy);
+  g[1] = kLn2 * (qb * sx + 2.0f * qc * sy);
+  g[5] = g[5] * __uint_as_float(s[kSlotInvO]);
 }
 
 // Triangle fragment of the walk for one pixel (a fixed occluder: it passes
@@ -266,6 +280,8 @@ __global__ __launch_bounds__(TW *TH / PPT) void blend_backward_kernel(
         if (!__any(c)) continue;
         wave_totals(g);
         if (lane == 63) {
+          finish_terms(slots + f * kSlotWords, g);
+          finish_terms(slots + (f - 1) * kSlotWords, g + 9);
 #pragma unroll
           for (int k = 0; k < 9; ++k) {
             glw[f * 9 + k] = g[k];
@@ -291,6 +307,7 @@ __global__ __launch_bounds__(TW *TH / PPT) void blend_backward_kernel(
         if (!__any(c)) continue;     // no lane of the wave blends it
         wave_totals(g);
         if (lane == 63) {
+          finish_terms(s, g);
 #pragma unroll
           for (int k = 0; k < 9; ++k) glw[f * 9 + k] = g[k];
         }
