@@ -269,3 +269,22 @@ def test_multi_view_matches_single_views(torch_dev):
     W, H = s.cams[2].width, s.cams[2].height
     px = [(x, y) for y in range(0, H, 2) for x in range(0, W, 2)]
     PT.compare_pixels(fr, img, Tf, last_gids(r, nc, v=2), px)
+
+
+def test_many_views_past_one_workgroup_chunk_plan(torch_dev):
+    """40 views of 1920x1080 give 5400 supertiles, more than the single
+    workgroup that builds the chunk table handles, so the frame takes the
+    multi-launch path; views of it match their own single-view renders bit
+    for bit."""
+    import dataclasses
+    s = scenes.make_config(0)
+    cams = [scenes.look_at((0.3 * math.cos(0.15 * k), 0.2 * math.sin(0.1 * k), 3.0), 1920, 1080)
+            for k in range(40)]
+    s = dataclasses.replace(s, cams=cams)
+    assert sum(((c.width + 127) // 128) * ((c.height + 127) // 128) for c in cams) > 4096
+    note("40 views of 1080p")
+    r, out = run(s)
+    imgs = r.split_views(out["image"], 3)
+    for v in (0, 17, 39):
+        r1, o1 = run(s, cams=[cams[v]])
+        assert np.array_equal(to_np(imgs[v]), to_np(o1["image"]).reshape(3, 1080, 1920)), v
