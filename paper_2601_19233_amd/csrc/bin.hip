@@ -181,6 +181,94 @@ __global__ __launch_bounds__(kScanThreads) void scan_lookback_kernel(
   }
 }
 
+// The entry offsets of the bin stage in one launch: the look-back scan above
+// over the supertile-entry counts (high 32 bits of a record's count)
+// gathered in depth order, which also sums the tile counts (low 32 bits) and
+// leaves both frame totals: each tile's status word carries its entry total
+// (bits 0-31) and its tile total (bits 32-62; a tile of 4096 records stays
+// far below 2^31), and the last tile to finish adds up every status.  It
+// clears the supertile ranges on the side.
+__global__ __launch_bounds__(kScanThreads) void entry_offsets_kernel(
+    const uint32_t *__restrict__ order, const uint64_t *__restrict__ counts, int64_t n_rec,
+    uint64_t *__restrict__ offs, uint32_t ntiles, LbState *__restrict__ st,
+    uint32_t *__restrict__ fault, uint32_t *__restrict__ st_rng, int64_t n_rng,
+    uint64_t *__restrict__ totals) {
+  __shared__ uint32_t s_tile;
+  __shared__ bool s_last;
+  if (threadIdx.x == 0) s_tile = atomicAdd(&st->ticket, 1u);
+  __syncthreads();
+  const uint32_t t = s_tile;
+  const int64_t base = (int64_t)t * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  const int64_t n = n_rec + 1;
+  uint32_t v[kScanItems];
+  uint32_t s = 0, tl = 0;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = base + k;
+    const uint64_t c = idx < n_rec ? counts[order[idx]] : 0ull;
+    v[k] = (uint32_t)(c >> 32);
+    s += v[k];
+    tl += (uint32_t)c;
+  }
+  for (int64_t k = (int64_t)t * kScanThreads + threadIdx.x; k < n_rng;
+       k += (int64_t)ntiles * kScanThreads)
+    st_rng[k] = 0u;
+  uint32_t total, tl_total;
+  const uint32_t excl = block_excl_scan(s, total);
+  block_excl_scan(tl, tl_total);
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&st->status[t],
+                       kLbReady | ((unsigned long long)tl_total << 32) | (unsigned long long)total,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  // one thread per earlier tile (bounded wait, as in scan_lookback_kernel)
+  auto status_of = [&](uint32_t k) {
+    unsigned long long w =
+        __hip_atomic_load(&st->status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (uint32_t spin = 0; !(w & kLbReady) && spin < kLbSpinLimit; ++spin) {
+      __builtin_amdgcn_s_sleep(1);
+      w = __hip_atomic_load(&st->status[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!(w & kLbReady)) atomicOr(fault, 1u);
+    return w;
+  };
+  uint64_t pre = 0;
+  for (uint32_t k = threadIdx.x; k < t; k += kScanThreads) pre += status_of(k) & 0xFFFFFFFFull;
+  uint64_t pre_total;
+  block_excl_scan(pre, pre_total);
+  uint64_t run = pre_total + excl;
+#pragma unroll
+  for (int k = 0; k < kScanItems; ++k) {
+    const int64_t idx = base + k;
+    if (idx < n) offs[idx] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == 0) s_last = atomicAdd(&st->done, 1u) == ntiles - 1;
+  __syncthreads();
+  if (s_last) {
+    // the frame totals: tiles of the records' rectangles, entries
+    uint64_t a = 0, b = 0;
+    for (uint32_t k = threadIdx.x; k < ntiles; k += kScanThreads) {
+      const unsigned long long w = status_of(k);
+      a += (w >> 32) & 0x7FFFFFFFull;
+      b += w & 0xFFFFFFFFull;
+    }
+    uint64_t ta, tb;
+    block_excl_scan(a, ta);
+    block_excl_scan(b, tb);
+    if (threadIdx.x == 0) {
+      totals[0] = ta;
+      totals[1] = tb;
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < ntiles; k += kScanThreads)
+      __hip_atomic_store(&st->status[k], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+      __hip_atomic_store(&st->ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&st->done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
 template <typename T>
 hipError_t excl_scan(hipStream_t s, T *data, int64_t n, T *tmp) {
   if (n <= 0) return hipSuccess;
@@ -841,13 +929,13 @@ hipError_t launch_depth_order(Ctx *c) {
   ScopedTimer t(c, K_SCAN);
   const int64_t nt = (n + 1 + kScanTile - 1) / kScanTile;
   if (nt > 1 && nt <= kLbMaxTiles && c->lb_zeroed) {
-    // one launch: gather in depth order, scan, clear the supertile ranges
-    hipLaunchKernelGGL((scan_lookback_kernel<uint64_t, LoadStCounts>), dim3((unsigned)nt),
-                       dim3(kScanThreads), 0, c->stream, (uint64_t *)c->offs.p, n + 1,
-                       LoadStCounts{(const uint32_t *)c->dv[0].p, (const uint64_t *)c->counts.p, n},
-                       (uint32_t)nt, (LbState *)c->lb.p, &fi->fault, (uint32_t *)c->st_rng.p,
-                       2 * c->n_st);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    // one launch: gather in depth order, scan, both frame totals, clear the
+    // supertile ranges
+    hipLaunchKernelGGL(entry_offsets_kernel, dim3((unsigned)nt), dim3(kScanThreads), 0, c->stream,
+                       (const uint32_t *)c->dv[0].p, (const uint64_t *)c->counts.p, n,
+                       (uint64_t *)c->offs.p, (uint32_t)nt, (LbState *)c->lb.p, &fi->fault,
+                       (uint32_t *)c->st_rng.p, 2 * c->n_st, (uint64_t *)c->totals.p);
+    return hipGetLastError();
   } else {
     hipLaunchKernelGGL(gather_st_counts_kernel, dim3(ceil_div(n + 1, 256)), dim3(256), 0,
                        c->stream, (const uint32_t *)c->dv[0].p, n, (const uint64_t *)c->counts.p,
