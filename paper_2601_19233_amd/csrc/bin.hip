@@ -105,21 +105,11 @@ __global__ void scan_apply_kernel(T *__restrict__ data, int64_t n, const T *__re
 constexpr uint32_t kLbSpinLimit = 1u << 20;
 constexpr unsigned long long kLbReady = 1ull << 63;
 
-// Scan inputs: the data in place, or the supertile-entry counts (high 32 bits
-// of a record's count) gathered in depth order (0 at index n_records and
-// past it).
+// Scan input: the data in place (0 past the end).
 template <typename T>
 struct LoadPlain {
   const T *d;
   __device__ T operator()(int64_t i, int64_t n) const { return i < n ? d[i] : T(0); }
-};
-struct LoadStCounts {
-  const uint32_t *order;
-  const uint64_t *counts;
-  int64_t n_rec;
-  __device__ uint64_t operator()(int64_t i, int64_t) const {
-    return i < n_rec ? counts[order[i]] >> 32 : 0ull;
-  }
 };
 
 // zero_p[0, zero_n) is cleared by the grid on the side (may be empty).
