@@ -128,6 +128,35 @@ umgs_status umgs_bind_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
                                float *means_out, float *quats_out, float *cov3d_out,
                                float *xform_out, float *vertex_out);
 
+/* Binding association by ray casting (Section 3.3.1), a setup step run
+ * before deformation.  Each Gaussian has K target points: K = 1 its mean,
+ * K = 8 the corners mu + R(q) diag(3 s) (sx, sy, sz) of its bounding box,
+ * signs +-1 with the x sign varying fastest, then y, then z (q normalised
+ * inside).  From each of the C camera centres cam_centers [host] (C,3) a ray
+ * o + t (P - o), t > 0, is cast through the target P (at t = 1).  Every
+ * crossing of a face of the rest proxy (umgs_set_proxy) is a candidate,
+ * edges and vertices included; the target binds to the crossing nearest to
+ * it, |t - 1| |P - o|, over all faces and cameras -- not to the first
+ * crossing seen from the camera.  Ties go to the lower camera, then the lower
+ * face index.
+ * Inputs [device]: means (N,3); scales (N,3) and quats (N,4) (w,x,y,z), read
+ * only for K = 8 (may be NULL for K = 1).
+ * Outputs [device]: bind_face (N,K) int32 (-1 where no ray crosses the
+ * proxy), bind_bary (N,K,2) = (u,v) with crossing = u V[f0] + v V[f1] +
+ * (1-u-v) V[f2] ((0,0) for -1), the layout umgs_bind_transfer reads; dist
+ * (N,K) the distance from the crossing to the target (+inf for -1), may be
+ * NULL.
+ * The call builds a BVH of the proxy on the device (linear BVH over the
+ * Morton codes of the face centroids) into context buffers, casts in FP32,
+ * and returns after the stream has finished (synchronous).
+ * Errors: STATE without a proxy or during graph capture; INVALID_ARG (N < 0,
+ * K not 1 or 8, C < 1 or C > 2^20, a NULL array, a non-finite camera
+ * centre); CAPACITY (N*K >= 2^31, or a traversal deeper than the 64-entry
+ * stack, which a BVH over at most 2^31 faces never reaches); HIP. */
+umgs_status umgs_bind_raycast(umgs_ctx *ctx, int32_t N, const float *means, const float *scales,
+                              const float *quats, int32_t K, int32_t C, const float *cam_centers,
+                              int32_t *bind_face, float *bind_bary, float *dist);
+
 /* ---- forward rasterization (Section 3.2) ---------------------------------- */
 
 /* Project N Gaussians (EWA splatting: 2D covariance J W Sigma W^T J^T + 0.3 I,

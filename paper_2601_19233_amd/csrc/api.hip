@@ -163,7 +163,8 @@ void umgs_destroy(umgs_ctx *ctx) {
   (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
-  DevBuf *bufs[] = {&c->V_rest, &c->faces, &c->vf_ptr, &c->vf_idx, &c->vtab, &c->ftab, &c->d_views,
+  DevBuf *bufs[] = {&c->V_rest, &c->faces, &c->vf_ptr, &c->vf_idx, &c->vtab, &c->ftab, &c->bvh_code[0], &c->bvh_code[1],
+                    &c->bvh_id[0], &c->bvh_id[1], &c->bvh_tri, &c->bvh_node, &c->bvh_aux, &c->d_views,
                     &c->keys, &c->rects, &c->counts, &c->dk[0], &c->dk[1], &c->dv[0],
                     &c->dv[1], &c->offs, &c->grec, &c->trec, &c->scan_tmp,
                     &c->sk[0], &c->sk[1], &c->sv[0], &c->sv[1], &c->masks[0], &c->masks[1], &c->st_rng,
@@ -234,6 +235,54 @@ umgs_status umgs_set_proxy(umgs_ctx *ctx, int32_t nV, const float *V_rest, int32
     return hip_check(c, e, "umgs_set_proxy upload");
   c->nV = nV;
   c->nF = nF;
+  return UMGS_OK;
+}
+
+umgs_status umgs_bind_raycast(umgs_ctx *ctx, int32_t N, const float *means, const float *scales,
+                              const float *quats, int32_t K, int32_t C, const float *cam_centers,
+                              int32_t *bind_face, float *bind_bary, float *dist) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->nV == 0) return fail(c, UMGS_ERR_STATE, "umgs_bind_raycast: no proxy (call umgs_set_proxy)");
+  if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_bind_raycast: not allowed during graph capture");
+  if (N < 0 || (K != 1 && K != 8) || C < 1 || C > (1 << 20))
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_bind_raycast: N=%d K=%d C=%d", N, K, C);
+  if (!cam_centers) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_bind_raycast: NULL cam_centers");
+  if (N > 0 && (!means || !bind_face || !bind_bary || (K == 8 && (!scales || !quats))))
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_bind_raycast: NULL array");
+  if ((int64_t)N * K >= (1LL << 31))
+    return fail(c, UMGS_ERR_CAPACITY, "umgs_bind_raycast: N*K = %lld targets", (long long)N * K);
+  for (int64_t i = 0; i < 3LL * C; ++i)
+    if (!std::isfinite(cam_centers[i]))
+      return fail(c, UMGS_ERR_INVALID_ARG, "umgs_bind_raycast: camera %lld centre is not finite",
+                  (long long)(i / 3));
+  const int64_t nF = c->nF;
+  const int64_t hb = (int64_t)radix_hist_bytes((uint64_t)nF);
+  umgs_status s;
+  if ((s = ensure(c, c->bvh_code[0], sizeof(uint32_t) * nF, "BVH codes")) ||
+      (s = ensure(c, c->bvh_code[1], sizeof(uint32_t) * nF, "BVH codes")) ||
+      (s = ensure(c, c->bvh_id[0], sizeof(uint32_t) * nF, "BVH ids")) ||
+      (s = ensure(c, c->bvh_id[1], sizeof(uint32_t) * nF, "BVH ids")) ||
+      (s = ensure(c, c->bvh_tri, 3 * sizeof(float4) * nF, "BVH leaves")) ||
+      (s = ensure(c, c->bvh_node, 4 * sizeof(float4) * std::max<int64_t>(nF - 1, 1), "BVH nodes")) ||
+      (s = ensure(c, c->bvh_aux, bvh_aux_bytes(C), "BVH bounds and cameras")) ||
+      (s = ensure(c, c->hist, (size_t)hb, "radix histograms")) ||
+      (s = ensure(c, c->scan_tmp, scan_tmp_bytes(std::max<int64_t>({nF + 1, 1 << 20, hb / 4})),
+                  "scan scratch")))
+    return s;
+  hipError_t e = hipMemcpyAsync(bvh_cam_slots(c), cam_centers, sizeof(float) * 3 * (size_t)C,
+                                hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "umgs_bind_raycast camera upload");
+  if ((e = launch_bvh_build(c)) != hipSuccess) return hip_check(c, e, "BVH build");
+  if ((e = launch_raycast(c, N, means, scales, quats, K, C, bind_face, bind_bary, dist)) != hipSuccess)
+    return hip_check(c, e, "ray cast");
+  uint32_t fault = 0;
+  if ((e = hipMemcpyAsync(&fault, bvh_fault_flag(c), sizeof(fault), hipMemcpyDeviceToHost,
+                          c->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+    return hip_check(c, e, "umgs_bind_raycast");
+  if (fault)
+    return fail(c, UMGS_ERR_CAPACITY, "umgs_bind_raycast: BVH traversal exceeded its stack or step bound");
   return UMGS_OK;
 }
 

@@ -127,6 +127,11 @@ struct Ctx {
   int32_t nV = 0, nF = 0;
   DevBuf V_rest, faces, vf_ptr, vf_idx, vtab;
   DevBuf ftab;   // per face: its three vertex rows (9 float4, 144 B)
+  // BVH of the rest proxy for the binding association (rebuilt per call)
+  DevBuf bvh_code[2], bvh_id[2];  // nF uint32: Morton codes / face ids (ping-pong sort)
+  DevBuf bvh_tri;                 // nF x 3 float4: leaf triangles in Morton order
+  DevBuf bvh_node;                // max(nF-1,1) x 4 float4: both children's boxes + links
+  DevBuf bvh_aux;                 // centroid bounds, fault flag, camera centres
 
   // per-frame state
   int stage = 0;         // 0 none, 1 projected, 2 binned, 3 sorted, 4 blended
@@ -235,6 +240,13 @@ hipError_t launch_radix_sort_pay_u16(Ctx *c, uint16_t *keys[2], uint32_t *vals[2
 int radix_passes(int bits);
 size_t radix_hist_bytes(uint64_t n);
 hipError_t launch_expand_keys(Ctx *c, uint64_t *dst);
+hipError_t launch_bvh_build(Ctx *c);
+hipError_t launch_raycast(Ctx *c, int32_t N, const float *means, const float *scales,
+                          const float *quats, int32_t K, int32_t C, int32_t *bind_face,
+                          float *bind_bary, float *dist);
+size_t bvh_aux_bytes(int32_t C);
+uint32_t *bvh_fault_flag(Ctx *c);
+float *bvh_cam_slots(Ctx *c);
 hipError_t launch_blend(Ctx *c, float *image, float *T_final, int32_t *n_contrib,
                         float *T_entity_in, unsigned long long *pairs = nullptr);
 hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32_t *nc,

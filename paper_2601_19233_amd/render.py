@@ -138,6 +138,24 @@ class Rasterizer:
         self._check(self.lib.umgs_set_proxy(self.h, V.shape[0], V.ctypes.data_as(C.c_void_p),
                                             F.shape[0], F.ctypes.data_as(C.c_void_p)))
 
+    def bind_raycast(self, means, scales, quats, K: int, cam_centers) -> Dict[str, torch.Tensor]:
+        """Section 3.3.1 binding association on the GPU: rays from the camera
+        centres (C,3) through each Gaussian's K = 1 centre or K = 8 box
+        corners into the rest proxy; returns face (N,K) int32, bary (N,K,2)
+        and dist (N,K), ready for bind_transfer."""
+        d = self.device
+        means, scales, quats = (_f32(x, d) for x in (means, scales, quats))
+        oc = np.ascontiguousarray(np.asarray(cam_centers, np.float32).reshape(-1, 3))
+        N = means.shape[0]
+        out = dict(face=torch.empty((N, K), dtype=torch.int32, device=d),
+                   bary=torch.empty((N, K, 2), device=d), dist=torch.empty((N, K), device=d))
+        with self._on_stream():
+            self._check(self.lib.umgs_bind_raycast(
+                self.h, N, _ptr(means), _ptr(scales), _ptr(quats), K, oc.shape[0],
+                oc.ctypes.data_as(C.POINTER(C.c_float)), _ptr(out["face"]), _ptr(out["bary"]),
+                _ptr(out["dist"])))
+        return out
+
     def bind_transfer(self, V_def, bind_face, bind_bary, means, quats, scales,
                       with_vertex: bool = False, out: Optional[Dict] = None) -> Dict[str, torch.Tensor]:
         d = self.device

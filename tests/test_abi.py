@@ -19,7 +19,7 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("umgs_create", "umgs_destroy", "umgs_project", "umgs_bin", "umgs_sort", "umgs_blend",
-              "umgs_bind_transfer", "umgs_set_proxy"):
+              "umgs_bind_transfer", "umgs_bind_raycast", "umgs_set_proxy"):
         assert n in names
 
 
