@@ -325,6 +325,38 @@ def run_backward_800(args):
             "loss": "L2 against the render of N(0, 0.01)-perturbed parameters"}
 
 
+def run_binding(args, scene, n_cams=8):
+    """Section 3.3.1 binding association at the frame's full size: the
+    frame's Gaussians (8 box corners each) against its rest proxy, rays from
+    n_cams orbit camera centres; one call = BVH build + cast + readback."""
+    import torch
+    from paper_2601_19233_amd import scenes
+    from paper_2601_19233_amd.render import Rasterizer
+    rng = np.random.default_rng(7)
+    cams = scenes.orbit_cameras(rng, n_cams, [(64, 64)] * n_cams)
+    oc = np.stack([-(c.R.astype(np.float64).T @ c.t.astype(np.float64)) for c in cams])
+    oc = oc.astype(np.float32)
+    r = Rasterizer("cuda:0", k_bind=8)
+    r.set_proxy(scene.proxy.V_rest, scene.proxy.faces)
+    dev = torch.device("cuda:0")
+    means, scales, quats = (torch.from_numpy(np.ascontiguousarray(x, np.float32)).to(dev)
+                            for x in (scene.means, scene.scales, scene.quats))
+    state = {}
+
+    def call():
+        state["out"] = r.bind_raycast(means, scales, quats, 8, oc)
+
+    ms = timed(call, max(2, min(args.steps, 10)))
+    unbound = float((state["out"]["face"] < 0).float().mean().item())
+    rays = scene.N * 8 * n_cams
+    log(f"binding: {ms:.3f} ms for {rays} rays")
+    r.close()
+    return {"workload": f"{scene.N} Gaussians x 8 box corners x {n_cams} cameras, "
+                        f"{scene.proxy.faces.shape[0]}-face proxy",
+            "ms_per_call": round(ms, 4), "rays_per_s": round(rays / (ms * 1e-3), 1),
+            "unbound_fraction": round(unbound, 6)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -337,6 +369,9 @@ def main():
     ap.add_argument("--schedule", type=int, default=0, help="blend schedule: 0 tile grid, 1 persistent")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-binding", action="store_true")
+    ap.add_argument("--binding-only", action="store_true",
+                    help="time only the ray-cast binding association and print its JSON")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 256 MiB device to device once (a reference dispatch for "
                          "hardware traffic counters)")
@@ -364,6 +399,9 @@ def main():
 
     t0 = time.time()
     scene = scenes.make_config(1, scale=args.scale, res_scale=args.res_scale)
+    if args.binding_only:
+        print(json.dumps({"binding": run_binding(args, scene)}), flush=True)
+        return
     log(f"scene {scene.name}: N={scene.N} T={scene.T} in {time.time() - t0:.1f} s")
     cam = scene.cams[0]
     tw, th = (int(x) for x in args.tile.split("x"))
@@ -532,7 +570,10 @@ def main():
 
     del r, fwd_state
     torch.cuda.empty_cache()
-    batched = uneven = bwd800 = orbit = None
+    batched = uneven = bwd800 = orbit = binding = None
+    if not args.no_batched and not args.no_binding:
+        binding = run_binding(args, scene)
+        torch.cuda.empty_cache()
     if not args.no_batched:
         bwd800 = run_backward_800(args)
         torch.cuda.empty_cache()
@@ -554,7 +595,7 @@ def main():
         "n_dup": n_dup, "n_supertile_entries": n1, "stages_ms": stages, "roofline": roof, "rooflines": rooflines,
         "wall_s": round(wall, 3),
         "fwd_graph": fwd_graph, "fwd_bwd": fwd_bwd, "backward_800": bwd800, "batched": batched,
-        "batched_1080p_x16_orbit": orbit, "batched_uneven": uneven,
+        "batched_1080p_x16_orbit": orbit, "batched_uneven": uneven, "binding": binding,
     }
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
