@@ -164,7 +164,8 @@ void umgs_destroy(umgs_ctx *ctx) {
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
   DevBuf *bufs[] = {&c->V_rest, &c->faces, &c->vf_ptr, &c->vf_idx, &c->vtab, &c->ftab, &c->bvh_code[0], &c->bvh_code[1],
-                    &c->bvh_id[0], &c->bvh_id[1], &c->bvh_tri, &c->bvh_node, &c->bvh_aux, &c->d_views,
+                    &c->bvh_id[0], &c->bvh_id[1], &c->bvh_tri, &c->bvh_node, &c->bvh_aux,
+                    &c->cast_code[0], &c->cast_code[1], &c->cast_id[0], &c->cast_id[1], &c->d_views,
                     &c->keys, &c->rects, &c->counts, &c->dk[0], &c->dk[1], &c->dv[0],
                     &c->dv[1], &c->offs, &c->grec, &c->trec, &c->scan_tmp,
                     &c->sk[0], &c->sk[1], &c->sv[0], &c->sv[1], &c->masks[0], &c->masks[1], &c->st_rng,
@@ -257,7 +258,7 @@ umgs_status umgs_bind_raycast(umgs_ctx *ctx, int32_t N, const float *means, cons
       return fail(c, UMGS_ERR_INVALID_ARG, "umgs_bind_raycast: camera %lld centre is not finite",
                   (long long)(i / 3));
   const int64_t nF = c->nF;
-  const int64_t hb = (int64_t)radix_hist_bytes((uint64_t)nF);
+  const int64_t hb = (int64_t)radix_hist_bytes((uint64_t)std::max<int64_t>(nF, N));
   umgs_status s;
   if ((s = ensure(c, c->bvh_code[0], sizeof(uint32_t) * nF, "BVH codes")) ||
       (s = ensure(c, c->bvh_code[1], sizeof(uint32_t) * nF, "BVH codes")) ||
@@ -266,8 +267,13 @@ umgs_status umgs_bind_raycast(umgs_ctx *ctx, int32_t N, const float *means, cons
       (s = ensure(c, c->bvh_tri, 3 * sizeof(float4) * nF, "BVH leaves")) ||
       (s = ensure(c, c->bvh_node, 4 * sizeof(float4) * std::max<int64_t>(nF - 1, 1), "BVH nodes")) ||
       (s = ensure(c, c->bvh_aux, bvh_aux_bytes(C), "BVH bounds and cameras")) ||
+      (s = ensure(c, c->cast_code[0], sizeof(uint32_t) * std::max<int64_t>(N, 1), "cast order")) ||
+      (s = ensure(c, c->cast_code[1], sizeof(uint32_t) * std::max<int64_t>(N, 1), "cast order")) ||
+      (s = ensure(c, c->cast_id[0], sizeof(uint32_t) * std::max<int64_t>(N, 1), "cast order")) ||
+      (s = ensure(c, c->cast_id[1], sizeof(uint32_t) * std::max<int64_t>(N, 1), "cast order")) ||
       (s = ensure(c, c->hist, (size_t)hb, "radix histograms")) ||
-      (s = ensure(c, c->scan_tmp, scan_tmp_bytes(std::max<int64_t>({nF + 1, 1 << 20, hb / 4})),
+      (s = ensure(c, c->scan_tmp,
+                  scan_tmp_bytes(std::max<int64_t>({nF + 1, (int64_t)N + 1, 1 << 20, hb / 4})),
                   "scan scratch")))
     return s;
   hipError_t e = hipMemcpyAsync(bvh_cam_slots(c), cam_centers, sizeof(float) * 3 * (size_t)C,

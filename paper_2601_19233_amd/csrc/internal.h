@@ -132,6 +132,7 @@ struct Ctx {
   DevBuf bvh_tri;                 // nF x 3 float4: leaf triangles in Morton order
   DevBuf bvh_node;                // max(nF-1,1) x 4 float4: both children's boxes + links
   DevBuf bvh_aux;                 // centroid bounds, fault flag, camera centres
+  DevBuf cast_code[2], cast_id[2]; // N uint32: Gaussians in Morton order of their means
 
   // per-frame state
   int stage = 0;         // 0 none, 1 projected, 2 binned, 3 sorted, 4 blended

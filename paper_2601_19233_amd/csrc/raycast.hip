@@ -19,7 +19,8 @@
 // o + t (P - o), and a subtree is skipped when its slab interval misses
 // [1 - b, 1 + b], b the best distance so far in units of |P - o|.  Children
 // are visited nearest-interval first.  The crossing test is Moller-Trumbore
-// (1997) in FP32.
+// (1997) in FP32.  Gaussians are cast in the Morton order of their means, so
+// the lanes of a wavefront trace neighbouring rays through the same nodes.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -115,6 +116,25 @@ __global__ __launch_bounds__(256) void morton_kernel(const float *__restrict__ V
   }
   code[f] = m;
   id[f] = (uint32_t)f;
+}
+
+// Morton code of each Gaussian's mean in the proxy's centroid bounds
+// (clamped): casting in this order keeps a wavefront's rays together.
+__global__ __launch_bounds__(256) void mean_order_kernel(const float *__restrict__ means, int32_t N,
+                                                         const float *__restrict__ aux,
+                                                         uint32_t *__restrict__ code,
+                                                         uint32_t *__restrict__ id) {
+  const int g = blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= N) return;
+  uint32_t m = 0;
+  for (int k = 0; k < 3; ++k) {
+    const float ext = aux[3 + k] - aux[k];
+    const float r = ext > 0.0f ? (means[3 * (int64_t)g + k] - aux[k]) / ext : 0.0f;
+    const uint32_t q = (uint32_t)fminf(fmaxf(r * 1024.0f, 0.0f), 1023.0f);
+    m |= spread10(q) << (2 - k);
+  }
+  code[g] = m;
+  id[g] = (uint32_t)g;
 }
 
 // Leaf triangles in sorted order, arranged for the crossing test: first the
@@ -277,18 +297,25 @@ __device__ inline float safe_inv(float x) {
   return fabsf(x) > 1e-30f ? 1.0f / x : copysignf(1e30f, x);
 }
 
-// One lane per target point (Gaussian g, corner k); cameras in order.
+// One lane per target point (Gaussian g, corner k); cameras in order.  The
+// traversal stack holds internal-node indices in LDS: 16-bit entries when
+// the hierarchy has fewer than 2^16 internal nodes (half the LDS, so twice
+// the wavefronts fit on a CU), else 32-bit.
+template <typename S>
 __global__ __launch_bounds__(kCastThreads) void cast_kernel(
     const float *__restrict__ means, const float *__restrict__ scales,
-    const float *__restrict__ quats, int32_t N, int32_t K, int32_t C,
+    const float *__restrict__ quats, const uint32_t *__restrict__ order, int32_t N, int32_t K,
+    int32_t C,
     const float *__restrict__ aux, const float4 *__restrict__ node,
     const float4 *__restrict__ tri, int32_t n_int, int32_t *__restrict__ bind_face,
     float *__restrict__ bind_bary, float *__restrict__ dist_out, uint32_t *fault) {
-  __shared__ int s_stack[kStack][kCastThreads];
+  __shared__ S s_stack[kStack][kCastThreads];
   const int64_t idx = (int64_t)blockIdx.x * kCastThreads + threadIdx.x;
   if (idx >= (int64_t)N * K) return;
-  const int64_t g = idx / K;
-  const int k = (int)(idx - g * K);
+  const int64_t slot = idx / K;
+  const int k = (int)(idx - slot * K);
+  const int64_t g = order[slot];
+  const int64_t out = g * K + k;
   float3 P = make_float3(means[3 * g], means[3 * g + 1], means[3 * g + 2]);
   if (K == 8) {
     float w = quats[4 * g], x = quats[4 * g + 1], y = quats[4 * g + 2], z = quats[4 * g + 3];
@@ -345,21 +372,21 @@ __global__ __launch_bounds__(kCastThreads) void cast_kernel(
           overflow = true;
           break;
         }
-        s_stack[sp++][lane] = far;
+        s_stack[sp++][lane] = (S)far;
         cur = near;
       } else if (nn == 1) {
         cur = next[0];
       } else {
         if (sp == 0) break;
-        cur = s_stack[--sp][lane];
+        cur = (int)s_stack[--sp][lane];
       }
     }
   }
   if (overflow) *fault = 1u;
-  bind_face[idx] = best.face;
-  bind_bary[2 * idx] = best.face >= 0 ? best.b1 : 0.0f;
-  bind_bary[2 * idx + 1] = best.face >= 0 ? best.b2 : 0.0f;
-  if (dist_out) dist_out[idx] = best.dist;
+  bind_face[out] = best.face;
+  bind_bary[2 * out] = best.face >= 0 ? best.b1 : 0.0f;
+  bind_bary[2 * out + 1] = best.face >= 0 ? best.b2 : 0.0f;
+  if (dist_out) dist_out[out] = best.dist;
 }
 
 }  // namespace
@@ -400,11 +427,29 @@ hipError_t launch_raycast(Ctx *c, int32_t N, const float *means, const float *sc
                           float *bind_bary, float *dist) {
   const int64_t M = (int64_t)N * K;
   if (M == 0) return hipSuccess;
-  hipLaunchKernelGGL(cast_kernel, dim3(ceil_div(M, kCastThreads)), dim3(kCastThreads), 0,
-                     c->stream, means, scales, quats, N, K, C, (const float *)c->bvh_aux.p,
-                     (const float4 *)c->bvh_node.p, (const float4 *)c->bvh_tri.p,
-                     c->nF > 1 ? c->nF - 1 : 1, bind_face,
-                     bind_bary, dist, bvh_fault_flag(c));
+  uint32_t *code[2] = {(uint32_t *)c->cast_code[0].p, (uint32_t *)c->cast_code[1].p};
+  uint32_t *id[2] = {(uint32_t *)c->cast_id[0].p, (uint32_t *)c->cast_id[1].p};
+  hipLaunchKernelGGL(mean_order_kernel, dim3(ceil_div(N, 256)), dim3(256), 0, c->stream, means, N,
+                     (const float *)c->bvh_aux.p, code[0], id[0]);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = launch_radix_sort_u32(c, code, id, (uint64_t)N, nullptr, nullptr, 30, -1, -1, -1)) !=
+      hipSuccess)
+    return e;
+  const uint32_t *order = id[radix_passes(30) & 1];
+  const int32_t n_int = c->nF > 1 ? c->nF - 1 : 1;
+  if (n_int < (1 << 16))
+    hipLaunchKernelGGL(cast_kernel<uint16_t>, dim3(ceil_div(M, kCastThreads)), dim3(kCastThreads),
+                       0, c->stream, means, scales, quats, order, N, K, C,
+                       (const float *)c->bvh_aux.p, (const float4 *)c->bvh_node.p,
+                       (const float4 *)c->bvh_tri.p, n_int, bind_face, bind_bary, dist,
+                       bvh_fault_flag(c));
+  else
+    hipLaunchKernelGGL(cast_kernel<uint32_t>, dim3(ceil_div(M, kCastThreads)), dim3(kCastThreads),
+                       0, c->stream, means, scales, quats, order, N, K, C,
+                       (const float *)c->bvh_aux.p, (const float4 *)c->bvh_node.p,
+                       (const float4 *)c->bvh_tri.p, n_int, bind_face, bind_bary, dist,
+                       bvh_fault_flag(c));
   return hipGetLastError();
 }
 
