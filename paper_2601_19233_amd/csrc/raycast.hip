@@ -28,7 +28,6 @@
 namespace umgs {
 namespace {
 
-constexpr int kStack = 64;        // traversal stack entries per lane
 constexpr int kCastThreads = 64;  // one wavefront per workgroup (LDS stack per lane)
 constexpr int kAuxCams = 16;      // float offset of the camera centres in bvh_aux
 constexpr int kAuxFault = 8;      // uint32 offset of the fault flag in bvh_aux
@@ -298,10 +297,12 @@ __device__ inline float safe_inv(float x) {
 }
 
 // One lane per target point (Gaussian g, corner k); cameras in order.  The
-// traversal stack holds internal-node indices in LDS: 16-bit entries when
-// the hierarchy has fewer than 2^16 internal nodes (half the LDS, so twice
-// the wavefronts fit on a CU), else 32-bit.
-template <typename S>
+// traversal stack holds internal-node indices in LDS.  Each level of the
+// hierarchy lengthens the common prefix of its keys (30-bit code, then the
+// sorted position) by at least one of the bits that vary, so a path holds at
+// most 30 + log2(n) internal nodes and the stack never needs more entries:
+// 48 16-bit entries below 2^16 faces, 64 32-bit entries up to 2^31.
+template <typename S, int kStack>
 __global__ __launch_bounds__(kCastThreads) void cast_kernel(
     const float *__restrict__ means, const float *__restrict__ scales,
     const float *__restrict__ quats, const uint32_t *__restrict__ order, int32_t N, int32_t K,
@@ -438,14 +439,14 @@ hipError_t launch_raycast(Ctx *c, int32_t N, const float *means, const float *sc
     return e;
   const uint32_t *order = id[radix_passes(30) & 1];
   const int32_t n_int = c->nF > 1 ? c->nF - 1 : 1;
-  if (n_int < (1 << 16))
-    hipLaunchKernelGGL(cast_kernel<uint16_t>, dim3(ceil_div(M, kCastThreads)), dim3(kCastThreads),
+  if (c->nF <= (1 << 16))
+    hipLaunchKernelGGL((cast_kernel<uint16_t, 48>), dim3(ceil_div(M, kCastThreads)), dim3(kCastThreads),
                        0, c->stream, means, scales, quats, order, N, K, C,
                        (const float *)c->bvh_aux.p, (const float4 *)c->bvh_node.p,
                        (const float4 *)c->bvh_tri.p, n_int, bind_face, bind_bary, dist,
                        bvh_fault_flag(c));
   else
-    hipLaunchKernelGGL(cast_kernel<uint32_t>, dim3(ceil_div(M, kCastThreads)), dim3(kCastThreads),
+    hipLaunchKernelGGL((cast_kernel<uint32_t, 64>), dim3(ceil_div(M, kCastThreads)), dim3(kCastThreads),
                        0, c->stream, means, scales, quats, order, N, K, C,
                        (const float *)c->bvh_aux.p, (const float4 *)c->bvh_node.p,
                        (const float4 *)c->bvh_tri.p, n_int, bind_face, bind_bary, dist,
