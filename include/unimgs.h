@@ -151,8 +151,9 @@ umgs_status umgs_bind_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
  * and returns after the stream has finished (synchronous).
  * Errors: STATE without a proxy or during graph capture; INVALID_ARG (N < 0,
  * K not 1 or 8, C < 1 or C > 2^20, a NULL array, a non-finite camera
- * centre); CAPACITY (N*K >= 2^31, or a traversal deeper than the 64-entry
- * stack, which a BVH over at most 2^31 faces never reaches); HIP. */
+ * centre); CAPACITY (N*K >= 2^31, or a traversal past its stack or step
+ * bound, which the hierarchy's depth bound -- at most 30 + log2(nF) levels --
+ * keeps it from reaching); HIP. */
 umgs_status umgs_bind_raycast(umgs_ctx *ctx, int32_t N, const float *means, const float *scales,
                               const float *quats, int32_t K, int32_t C, const float *cam_centers,
                               int32_t *bind_face, float *bind_bary, float *dist);
