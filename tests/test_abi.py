@@ -46,3 +46,21 @@ def test_option_validation_without_device():
     lib.umgs_default_options(C.byref(d))
     assert (d.tile_w, d.tile_h, d.frag_batch, d.k_bind) == (16, 16, 128, 8)
     assert lib.umgs_last_error(None) == b""
+
+
+def test_entry_points_reject_a_null_context_without_device():
+    """Every compute entry point validates its context before touching the
+    device; the binding association's declared argument order is the one the
+    binding marshals."""
+    from paper_2601_19233_amd import _lib
+    lib = _lib.load()
+    cam = (C.c_float * 3)(0.0, 0.0, 3.0)
+    assert lib.umgs_bind_raycast(None, 1, None, None, None, 8, 1, cam, None, None, None) == -1
+    assert lib.umgs_bind_transfer(None, None, 0, None, None, None, None, None, None, None, None,
+                                  None, None) == -1
+    hdr = open(HEADER).read()
+    decl = re.search(r"umgs_status umgs_bind_raycast\((.*?)\);", hdr, re.S).group(1)
+    names = [p.split()[-1].lstrip("*") for p in decl.split(",")]
+    assert names == ["ctx", "N", "means", "scales", "quats", "K", "C", "cam_centers",
+                     "bind_face", "bind_bary", "dist"]
+    assert len(_lib.PROTOTYPES["umgs_bind_raycast"][1]) == len(names)
