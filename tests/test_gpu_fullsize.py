@@ -199,3 +199,35 @@ def test_cfg4_batched_forward_backward(gpu):
                       cov3d=ot["cov3d"])
         note(f"cfg4 view {v}: {check_view(fr, step, out, v, sample_pixels(s.cams[v], 25, 50 + v))}")
     note(f"cfg4 groups {step.groups}")
+
+
+def test_cfg1_binding_association_sampled(gpu, cfg1):
+    """Section 3.3.1 binding at the size the bench times: the frame's 1M
+    Gaussians (8 box corners each) into its 20,480-face rest proxy from 8
+    orbit cameras, in one call; 60 sampled Gaussians (480 targets) checked
+    against the FP64 oracle one by one."""
+    import torch
+    from oracle import binding as OB
+    from paper_2601_19233_amd.render import Rasterizer
+    from tests import test_gpu_binding as TB
+    s = cfg1
+    rng = np.random.default_rng(7)
+    cams = scenes.orbit_cameras(rng, 8, [(64, 64)] * 8)
+    oc = np.stack([OB.camera_center(c.R, c.t) for c in cams]).astype(np.float32)
+    note("binding association: 1M Gaussians x 8 corners x 8 cameras")
+    r = Rasterizer("cuda:0", k_bind=8)
+    r.set_proxy(s.proxy.V_rest, s.proxy.faces)
+    dev = torch.device("cuda:0")
+    means, scales, quats = (torch.from_numpy(np.ascontiguousarray(x, np.float32)).to(dev)
+                            for x in (s.means, s.scales, s.quats))
+    out = r.bind_raycast(means, scales, quats, 8, oc)
+    torch.cuda.synchronize()
+    pick = np.random.default_rng(1).choice(s.N, 60, replace=False)
+    face = out["face"].cpu().numpy()[pick].reshape(-1)
+    bary = out["bary"].cpu().numpy()[pick].reshape(-1, 2).astype(np.float64)
+    dist = out["dist"].cpu().numpy()[pick].reshape(-1).astype(np.float64)
+    P = OB.target_points(s.means[pick], s.scales[pick], s.quats[pick], 8).reshape(-1, 3)
+    clear, amb = TB.compare(P, oc, s.proxy.V_rest, s.proxy.faces, face, bary, dist)
+    note(f"binding sampled: {clear} clear, {amb} ambiguous")
+    assert amb <= 0.02 * (clear + amb)
+    r.close()
