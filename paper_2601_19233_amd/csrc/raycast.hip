@@ -246,13 +246,19 @@ __global__ __launch_bounds__(256) void node_kernel(const uint32_t *__restrict__ 
 
 // Slab interval of the ray o + t d inside [lo, hi]; returns its distance to
 // t = 1 (negative when the interval is empty, lies behind the camera, or is
-// farther from t = 1 than reach).
-__device__ inline float box_reach(float3 o, float3 inv, float4 lo, float4 hi, float reach) {
-  const float tx0 = (lo.x - o.x) * inv.x, tx1 = (hi.x - o.x) * inv.x;
-  const float ty0 = (lo.y - o.y) * inv.y, ty1 = (hi.y - o.y) * inv.y;
-  const float tz0 = (lo.z - o.z) * inv.z, tz1 = (hi.z - o.z) * inv.z;
-  const float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fminf(tz0, tz1));
-  const float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
+// farther from t = 1 than reach).  Each plane costs one FMA, x inv - o inv
+// (oi = o inv).  Plane parameters carry a relative rounding error of a few
+// units in the last place whatever the camera's distance, so the interval
+// is widened by 2^-20 of its ends (the boxes' own widening is in scene
+// units and would not cover a far camera).
+__device__ inline float box_reach(float3 oi, float3 inv, float4 lo, float4 hi, float reach) {
+  const float tx0 = fmaf(lo.x, inv.x, -oi.x), tx1 = fmaf(hi.x, inv.x, -oi.x);
+  const float ty0 = fmaf(lo.y, inv.y, -oi.y), ty1 = fmaf(hi.y, inv.y, -oi.y);
+  const float tz0 = fmaf(lo.z, inv.z, -oi.z), tz1 = fmaf(hi.z, inv.z, -oi.z);
+  float tn = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fminf(tz0, tz1));
+  float tf = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1));
+  tn = fmaf(-0x1p-20f, fabsf(tn), tn);
+  tf = fmaf(0x1p-20f, fabsf(tf), tf);
   if (!(tn <= tf) || !(tf > 0.0f)) return -1.0f;
   const float gap = fmaxf(fmaxf(tn - 1.0f, 1.0f - tf), 0.0f);
   return gap <= reach ? gap : -1.0f;
@@ -339,6 +345,7 @@ __global__ __launch_bounds__(kCastThreads) void cast_kernel(
     const float dn = sqrtf(dot3(d, d));
     if (!(dn > 0.0f)) continue;
     const float3 inv = make_float3(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
+    const float3 oi = make_float3(o.x * inv.x, o.y * inv.y, o.z * inv.z);
     int sp = 0;
     int cur = 0;
     // a traversal visits each internal node at most once; the cap bounds
@@ -354,8 +361,8 @@ __global__ __launch_bounds__(kCastThreads) void cast_kernel(
       const float4 llo = node[4 * cur], lhi = node[4 * cur + 1];
       const float4 rlo = node[4 * cur + 2], rhi = node[4 * cur + 3];
       const int lc = __float_as_int(llo.w), rc = __float_as_int(lhi.w);
-      const float gl = box_reach(o, inv, llo, lhi, reach);
-      const float gr = box_reach(o, inv, rlo, rhi, reach);
+      const float gl = box_reach(oi, inv, llo, lhi, reach);
+      const float gr = box_reach(oi, inv, rlo, rhi, reach);
       int next[2];
       int nn = 0;
       if (gl >= 0.0f) {
