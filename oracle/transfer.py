@@ -22,9 +22,17 @@ the bound point P_i, i = 1..K; K = 8 bounding-box corners or K = 1 centre):
     Sigma' = A Sigma A^T, mu' = mu + mean Delta_i.
 The output quaternion is q' = quat(R') (x) q.
 
+Unbound corners (the paper's Section 3.3.1 leaves them open: a ray that
+crosses no face binds nothing): a corner whose face index lies outside
+[0, nF) -- the ray-cast binding writes -1 there -- is left out of Eq. 13,
+which then averages over the k_b bound corners only; a Gaussian with no
+bound corner keeps its rest pose (mu' = mu, R' = I, S' = I, q' = q).
+
 mu' is defined in float32 by a fixed operation order (one rounding per op):
 Delta_v = V'_v - V_v; w = (1 - u) - v; Delta_i = (u Delta_a + v Delta_b)
-+ w Delta_c; s = ((Delta_1 + Delta_2) + ...) + Delta_K; mu' = mu + s * (1/K).
++ w Delta_c; s = ((Delta_1 + Delta_2) + ...) + Delta_K over the bound
+corners in corner order; mu' = mu + s * (1/k_b) with 1/k_b rounded to
+float32 (mu' = mu when k_b = 0).
 It is the mean that orders the deformed Gaussians, so it is pinned like the
 rasterizer's other decision values.
 """
@@ -162,42 +170,66 @@ def _cov3d(scales, quats):
     return np.einsum("nij,nj,nkj->nik", Rq, np.asarray(scales, np.float64) ** 2, Rq)
 
 
+def bound_mask(bind_face, nF):
+    """True where a corner is bound to a face of the proxy (index in [0, nF))."""
+    f = np.asarray(bind_face)
+    return (f >= 0) & (f < nF)
+
+
 def pinned_mean(means, delta32, faces, bind_face, bind_bary):
     """mu' in float32 with the fixed operation order stated in the module doc."""
     K = bind_face.shape[1]
-    fv = np.asarray(faces, np.int64)[bind_face]             # (N,K,3)
+    faces = np.asarray(faces, np.int64)
+    bound = bound_mask(bind_face, faces.shape[0])
+    fv = faces[np.where(bound, bind_face, 0)]               # (N,K,3)
     u = bind_bary[:, :, 0].astype(F32)
     v = bind_bary[:, :, 1].astype(F32)
     w = (F32(1.0) - u) - v
-    s = None
+    N = fv.shape[0]
+    s = np.zeros((N, 3), F32)
+    started = np.zeros(N, bool)
     for i in range(K):
         da, db, dc = delta32[fv[:, i, 0]], delta32[fv[:, i, 1]], delta32[fv[:, i, 2]]
         di = (u[:, i, None] * da + v[:, i, None] * db) + w[:, i, None] * dc
-        s = di if s is None else s + di
-    return np.asarray(means, F32) + s * F32(1.0 / K)
+        b = bound[:, i]
+        s = np.where((b & started)[:, None], s + di, np.where((b & ~started)[:, None], di, s))
+        started |= b
+    kb = bound.sum(1)
+    inv = np.where(kb > 0, F32(1.0) / np.maximum(kb, 1).astype(F32), F32(0.0)).astype(F32)
+    m = np.asarray(means, F32)
+    return np.where((kb > 0)[:, None], m + s * inv[:, None], m)
 
 
-def transfer(V_rest, faces, V_def, means, quats, scales, bind_face, bind_bary, chunk=1 << 17):
-    """Deformed Gaussians: means' (float32, pinned), cov3d' packed (xx,xy,xz,yy,yz,zz),
+def gaussians_from_frames(frames, faces, means, quats, scales, bind_face, bind_bary,
+                          chunk=1 << 17):
+    """Eq. 12 at every bound corner, then Eq. 13, from the per-vertex frames
+    ``frames`` = dict(delta32 (nV,3) float32, r (nV,3) axis-angle, S (nV,3,3)).
+
+    Returns means' (float32, pinned), cov3d' packed (xx,xy,xz,yy,yz,zz),
     quats' (w,x,y,z) and A = R'S' (N,3,3), all but means' in FP64."""
-    vt = vertex_transforms(V_rest, faces, V_def)
-    means32 = pinned_mean(means, vt["delta32"], faces, bind_face, bind_bary)
-    N = means.shape[0]
     faces = np.asarray(faces, np.int64)
+    bind_face = np.asarray(bind_face)
+    means32 = pinned_mean(means, frames["delta32"], faces, bind_face, bind_bary)
+    N = means.shape[0]
     cov = np.empty((N, 6))
     A_all = np.empty((N, 3, 3))
     q_all = np.empty((N, 4))
     for s0 in range(0, N, chunk):
         sl = slice(s0, min(N, s0 + chunk))
-        fv = faces[bind_face[sl]]                          # (n,K,3)
+        bound = bound_mask(bind_face[sl], faces.shape[0])            # (n,K)
+        fv = faces[np.where(bound, bind_face[sl], 0)]                # (n,K,3)
         u = bind_bary[sl, :, 0].astype(np.float64)
         v = bind_bary[sl, :, 1].astype(np.float64)
         w = 1.0 - u - v
-        bw = np.stack([u, v, w], -1)                       # (n,K,3)
-        r_i = np.einsum("nkj,nkjc->nkc", bw, vt["r"][fv])          # Eq. 12
-        S_i = np.einsum("nkj,nkjab->nkab", bw, vt["S"][fv])
-        r_bar = r_i.mean(1)                                         # Eq. 13
-        S_bar = S_i.mean(1)
+        bw = np.stack([u, v, w], -1)                                 # (n,K,3)
+        r_i = np.einsum("nkj,nkjc->nkc", bw, frames["r"][fv])        # Eq. 12
+        S_i = np.einsum("nkj,nkjab->nkab", bw, frames["S"][fv])
+        kb = bound.sum(1).astype(np.float64)
+        ks = np.maximum(kb, 1.0)
+        # Eq. 13: the mean over the bound corners; none bound: rest pose
+        r_bar = (r_i * bound[:, :, None]).sum(1) / ks[:, None]
+        S_bar = (S_i * bound[:, :, None, None]).sum(1) / ks[:, None, None]
+        S_bar[kb == 0] = np.eye(3)
         Rp = exp_rot(r_bar)
         A = Rp @ S_bar
         Sig = _cov3d(scales[sl], quats[sl])
@@ -208,4 +240,14 @@ def transfer(V_rest, faces, V_def, means, quats, scales, bind_face, bind_bary, c
         q = np.asarray(quats[sl], np.float64)
         q = q / np.linalg.norm(q, axis=1, keepdims=True)
         q_all[sl] = quat_mul(quat_of_axis_angle(r_bar), q)
-    return dict(means=means32, cov3d=cov, quats=q_all, A=A_all, vertex=vt)
+    return dict(means=means32, cov3d=cov, quats=q_all, A=A_all)
+
+
+def transfer(V_rest, faces, V_def, means, quats, scales, bind_face, bind_bary, chunk=1 << 17):
+    """Deformed Gaussians: means' (float32, pinned), cov3d' packed (xx,xy,xz,yy,yz,zz),
+    quats' (w,x,y,z) and A = R'S' (N,3,3), all but means' in FP64; ``vertex``
+    holds the per-vertex frames."""
+    vt = vertex_transforms(V_rest, faces, V_def)
+    out = gaussians_from_frames(vt, faces, means, quats, scales, bind_face, bind_bary, chunk)
+    out["vertex"] = vt
+    return out

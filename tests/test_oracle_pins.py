@@ -619,3 +619,140 @@ def test_brute_force_tiny_scenes(seed):
             assert abs(r.T - bf[1]) < 1e-9
             n += 1
     assert n > 40
+
+
+# ---------------------------------------------------------------- ablation modes
+
+def tri_at_pixels(cam, uv, depth, alpha, rgb):
+    """One triangle whose vertices project to the pixel coordinates uv (3,2)
+    at camera depth ``depth`` (inverse of the pinhole map), constant colour."""
+    R = cam.R.astype(np.float64)
+    t = cam.t.astype(np.float64)
+    pts = []
+    for u, v in uv:
+        pc = np.array([(u - cam.cx) * depth / cam.fx, (v - cam.cy) * depth / cam.fy, depth])
+        pts.append(R.T @ (pc - t))
+    return (np.array(pts, F32)[None], np.tile(np.asarray(rgb, F32), (1, 3, 1)),
+            np.array([alpha], F32))
+
+
+def upper_tri(cam, py, edge_off, depth, alpha, rgb):
+    """Large triangle covering everything above the horizontal line
+    v = py + 0.5 + edge_off/256 (edge_off in 1/256 px from the centre row of
+    pixel row py)."""
+    ve = py + 0.5 + edge_off / 256.0
+    return tri_at_pixels(cam, [(-300.0, ve), (300.0, ve), (0.0, ve - 600.0)], depth, alpha, rgb)
+
+
+def test_direct_mode_uses_the_pixel_centre_only():
+    """Direct alpha-blending (Fig. 3a) treats a triangle like a Gaussian with
+    coverage decided at the pixel centre: a triangle over the centre gives
+    C = alpha c + (1 - alpha) C_bg exactly (C = c when opaque) whatever part
+    of the pixel it covers; one that covers two of the four sub-samples but
+    not the centre gives nothing.  The UniMGS entity rule weighs both by the
+    covered fraction of the sub-samples (1/2 here)."""
+    cam = cam_at(16, 16)
+    c = np.array([0.2, 0.6, 0.9])
+    bg = np.array([0.3, 0.1, 0.5])
+    c32 = c.astype(F32).astype(np.float64)
+    for alpha in (1.0, 0.6):
+        a = float(F32(alpha))
+        # edge 16/256 px above the centre: samples at -96 and -32 covered, centre not
+        off = frame(cam, tris=upper_tri(cam, 7, -16, 2.0, alpha, c), bg=bg, mode=R.MODE_DIRECT).pixel(5, 7)
+        assert off.n_blended == 0 and off.T == 1.0
+        np.testing.assert_allclose(off.C, bg, rtol=0, atol=0)
+        # edge 16/256 px below the centre: the centre and the same two samples covered
+        on = frame(cam, tris=upper_tri(cam, 7, 16, 2.0, alpha, c), bg=bg, mode=R.MODE_DIRECT).pixel(5, 7)
+        assert on.n_blended == 1
+        assert abs(on.T - (1 - a)) < 1e-15
+        np.testing.assert_allclose(on.C, a * c32 + (1 - a) * bg, rtol=0, atol=4e-16)
+        for edge in (-16, 16):
+            uni = frame(cam, tris=upper_tri(cam, 7, edge, 2.0, alpha, c), bg=bg).pixel(5, 7)
+            assert abs(uni.T - (1 - a / 2)) < 1e-15
+            np.testing.assert_allclose(uni.C, 0.5 * a * c32 + (1 - a / 2) * bg, rtol=0, atol=4e-16)
+
+
+def test_direct_mode_blends_triangles_in_depth_order_and_stops_after_opaque():
+    """Direct mode: two full-coverage triangles (alpha_A in front, alpha_B
+    behind) give C = a_A c_A + (1-a_A) a_B c_B; an opaque front triangle ends
+    the pixel with its exact colour and nothing behind it is blended."""
+    cam = cam_at(16, 16)
+    cA, cB = np.array([1.0, 0.5, 0.0]), np.array([0.0, 0.25, 1.0])
+    for aA, aB in ((0.3, 0.8), (1.0, 0.8)):
+        tris = cat_tris(big_tri(2.0, aA, cA, cam), big_tri(3.0, aB, cB, cam))
+        r = frame(cam, tris=tris, mode=R.MODE_DIRECT).pixel(6, 9)
+        a1, a2 = float(F32(aA)), float(F32(aB))
+        if aA == 1.0:
+            assert r.order == [0] and r.T == 0.0
+            np.testing.assert_allclose(r.C, cA, rtol=0, atol=4e-16)
+        else:
+            assert r.order == [0, 1]
+            np.testing.assert_allclose(r.C, a1 * cA + (1 - a1) * a2 * cB, rtol=0, atol=1e-15)
+            assert abs(r.T - (1 - a1) * (1 - a2)) < 1e-15
+
+
+def test_one_entity_mode_closed_form():
+    """All triangles of a pixel as one entity (Fig. 3b/c): a Gaussian between
+    the front (alpha_A) and back (alpha_B) triangles does not close the
+    entity, so the back triangle is weighted by the sub-sample transmittance
+    of the front one only: C = a_A c_A + (1-a_A) a_G c_G + (1-a_A) a_B c_B
+    (the Gaussian's share is counted twice: colour overflow), and the pixel
+    transmittance after the entity is (1-a_A)(1-a_B)."""
+    W = H = 33
+    cam = scenes.look_at((0.0, 0.0, 3.0), W, H)
+    cam.cx = cam.cy = 16.5
+    aA, aB, aG = 0.4, 0.7, 0.6
+    cA, cG, cB = np.array([1.0, 0.0, 0.0]), np.array([0.0, 1.0, 0.0]), np.array([0.0, 0.0, 1.0])
+    g = single_gaussian(0.0, aG, cG, 0.05, cam)
+    tris = cat_tris(big_tri(2.0, aA, cA, cam), big_tri(4.0, aB, cB, cam))
+    r = frame(cam, **g, tris=tris, mode=R.MODE_ONE_ENTITY).pixel(16, 16)
+    assert r.order == [1, 0, 2]
+    ref = aA * cA + (1 - aA) * aG * cG + (1 - aA) * aB * cB
+    np.testing.assert_allclose(r.C, ref, rtol=0, atol=1e-7)   # colours pass through float32
+    a1, a2 = float(F32(aA)), float(F32(aB))
+    assert abs(r.T - (1 - a1) * (1 - a2)) < 1e-15
+
+
+# ---------------------------------------------------------------- EWA frustum clamp
+
+def test_ewa_jacobian_frustum_clamp_matches_numerical_jacobian():
+    """Outside 1.3 tan(fov/2) the EWA Jacobian is the derivative of the
+    pinhole map taken at the point moved onto the clamp boundary (same depth);
+    inside, at the mean itself.  The 2D mean is never clamped.  Reference:
+    central differences of the pinhole map at that point."""
+    cam = scenes.look_at((0.0, 0.0, 3.0), 64, 48)
+    tanx, tany = cam.width / (2 * cam.fx), cam.height / (2 * cam.fy)
+    W = cam.R.astype(np.float64)
+    t = cam.t.astype(np.float64)
+    z = 2.5
+    # camera-space directions: x/z, y/z in units of tan(fov/2)
+    dirs = [(1.5, 0.2), (-2.0, 0.5), (0.3, -1.8), (1.7, 1.4), (1.2, -1.25), (0.9, 0.1), (-2.6, -2.2)]
+    pc = np.array([[ax * tanx * z, ay * tany * z, z] for ax, ay in dirs])
+    means = ((pc - t) @ W).astype(F32)                 # world = R^T (p - t)
+    n = len(dirs)
+    rng = np.random.default_rng(11)
+    scales = np.exp(rng.normal(-1.5, 0.3, size=(n, 3))).astype(F32)
+    q = rng.normal(size=(n, 4)).astype(F32)
+    gp = R.project_gaussians(cam, means, np.full(n, 0.5), np.zeros((n, 1, 3)), 0, scales, q)
+    Sig = R.cov3d_from_scale_rot(scales, q)
+
+    def pinhole(p):
+        return np.array([cam.fx * p[0] / p[2] + cam.cx, cam.fy * p[1] / p[2] + cam.cy])
+
+    clamped = 0
+    for i in range(n):
+        p = W @ means[i].astype(np.float64) + t
+        lx, ly = 1.3 * tanx, 1.3 * tany
+        pcl = np.array([np.clip(p[0] / p[2], -lx, lx) * p[2], np.clip(p[1] / p[2], -ly, ly) * p[2], p[2]])
+        h = 1e-6
+        Jc = np.stack([(pinhole(pcl + h * e) - pinhole(pcl - h * e)) / (2 * h) for e in np.eye(3)], 1)
+        ref = Jc @ W @ Sig[i] @ W.T @ Jc.T + 0.3 * np.eye(2)
+        got = np.array([[gp.cov2d[i, 0], gp.cov2d[i, 1]], [gp.cov2d[i, 1], gp.cov2d[i, 2]]])
+        np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-6)
+        np.testing.assert_allclose(gp.mean2d[i], pinhole(p), atol=1e-9)
+        if not np.allclose(pcl, p):
+            clamped += 1
+            Ju = np.stack([(pinhole(p + h * e) - pinhole(p - h * e)) / (2 * h) for e in np.eye(3)], 1)
+            unc = Ju @ W @ Sig[i] @ W.T @ Ju.T + 0.3 * np.eye(2)
+            assert np.abs(unc - ref).max() > 1e-3 * np.abs(ref).max()
+    assert clamped == 5                # (1.2, -1.25) and (0.9, 0.1) lie inside the clamp

@@ -212,3 +212,163 @@ def test_interpolation_at_a_vertex_reproduces_the_vertex():
     np.testing.assert_allclose(out["A"], A_ref, atol=1e-12)
     np.testing.assert_allclose(out["A"], vt["D"][v0], atol=1e-10)    # exp(log R) S = R S = D
     np.testing.assert_allclose(out["means"], vt["delta32"][v0], atol=0)
+
+
+# ---------------------------------------------------------------- Eq. 13 averaging
+
+def _frames(r, S, nV=None):
+    """Hand-built per-vertex frames: axis-angle r (nV,3), stretch S (nV,3,3), no offset."""
+    r = np.asarray(r, np.float64)
+    nV = r.shape[0]
+    return dict(delta32=np.zeros((nV, 3), F32), r=r, S=np.asarray(S, np.float64))
+
+
+def _one_gaussian(n=1):
+    mu = np.zeros((n, 3), F32)
+    s = np.tile(F32([0.05, 0.02, 0.08]), (n, 1))
+    q = np.tile(F32([0.9, 0.1, -0.3, 0.2]), (n, 1))
+    return mu, s, q
+
+
+def test_opposite_rotations_average_to_identity():
+    """Eq. 13 averages the log-rotations of the corners, then exponentiates:
+    four corners at a vertex turned by +theta about z and four at one turned
+    by -theta give R' = I, so Sigma' = Sigma and q' = q.  Averaging the
+    rotation matrices instead would give diag(cos theta, cos theta, 1)."""
+    th = 0.7
+    fr = _frames([[0, 0, th], [0, 0, -th], [0, 0, 0]], np.tile(np.eye(3), (3, 1, 1)))
+    F = np.array([[0, 1, 2]])
+    mu, s, q = _one_gaussian()
+    bf = np.zeros((1, 8), np.int32)
+    bb = np.zeros((1, 8, 2), F32)
+    bb[0, :4, 0] = 1.0              # u = 1: vertex 0
+    bb[0, 4:, 1] = 1.0              # v = 1: vertex 1
+    out = TR.gaussians_from_frames(fr, F, mu, q, s, bf, bb)
+    np.testing.assert_allclose(out["A"][0], np.eye(3), atol=1e-15)
+    np.testing.assert_allclose(cov_of(out["cov3d"]), TR._cov3d(s, q), atol=1e-15)
+    qn = q[0].astype(np.float64) / np.linalg.norm(q[0].astype(np.float64))
+    np.testing.assert_allclose(out["quats"][0], qn, atol=1e-15)
+    # Eq. 12 interpolates the log-rotation inside a face: the edge midpoint
+    # between the two vertices carries r = 0 as well
+    bb1 = np.array([[[0.5, 0.5]]], F32)
+    out1 = TR.gaussians_from_frames(fr, F, mu, q, s, np.zeros((1, 1), np.int32), bb1)
+    np.testing.assert_allclose(out1["A"][0], np.eye(3), atol=1e-15)
+
+
+def test_distinct_rotations_log_average_closed_form():
+    """Three corners at a vertex with r = a x, five at one with r = b y, and
+    per-vertex stretches diag(1.2, 1, 1), diag(1, 0.8, 1): R' = exp((3a x +
+    5b y)/8) (scipy's rotation-vector map), S' = diag(1.075, 0.875, 1),
+    A = R'S', Sigma' = A Sigma A^T, and q' is the quaternion of R' R(q)."""
+    a, b = 0.9, -0.6
+    S0, S1 = np.diag([1.2, 1.0, 1.0]), np.diag([1.0, 0.8, 1.0])
+    fr = _frames([[a, 0, 0], [0, b, 0], [0, 0, 0]], np.stack([S0, S1, np.eye(3)]))
+    F = np.array([[0, 1, 2]])
+    mu, s, q = _one_gaussian()
+    bf = np.zeros((1, 8), np.int32)
+    bb = np.zeros((1, 8, 2), F32)
+    bb[0, [0, 3, 6], 0] = 1.0
+    bb[0, [1, 2, 4, 5, 7], 1] = 1.0
+    out = TR.gaussians_from_frames(fr, F, mu, q, s, bf, bb)
+    Rp = Rotation.from_rotvec([3 * a / 8, 5 * b / 8, 0.0]).as_matrix()
+    Sp = np.diag([1.075, 0.875, 1.0])
+    A = Rp @ Sp
+    np.testing.assert_allclose(out["A"][0], A, atol=1e-14)
+    np.testing.assert_allclose(cov_of(out["cov3d"])[0], A @ TR._cov3d(s, q)[0] @ A.T, atol=1e-15)
+    qs = out["quats"][0]
+    got = Rotation.from_quat([qs[1], qs[2], qs[3], qs[0]]).as_matrix()
+    qq = q[0].astype(np.float64)
+    ref = Rp @ Rotation.from_quat([qq[1], qq[2], qq[3], qq[0]]).as_matrix()
+    np.testing.assert_allclose(got, ref, atol=1e-14)
+    # same axis: the angles simply average
+    fz = _frames([[0, 0, 0.4], [0, 0, -0.2], [0, 0, 0]], np.tile(np.eye(3), (3, 1, 1)))
+    outz = TR.gaussians_from_frames(fz, F, mu, q, s, bf, bb)
+    ang = (3 * 0.4 + 5 * -0.2) / 8
+    Rz = np.array([[math.cos(ang), -math.sin(ang), 0], [math.sin(ang), math.cos(ang), 0], [0, 0, 1]])
+    np.testing.assert_allclose(outz["A"][0], Rz, atol=1e-15)
+
+
+# ---------------------------------------------------------------- unbound corners
+
+def test_gaussian_without_bound_corners_keeps_its_rest_pose():
+    """Every corner unbound (face -1, or any index outside the proxy): mu' = mu
+    bit for bit, A = I, Sigma' = Sigma(s, q), q' = q / |q|."""
+    V, F, mu, s, q, bf, bb = small_scene(8, seed=4, n=40)
+    Vd = scenes.bend(V)
+    bf = bf.copy()
+    bf[:20] = -1
+    bf[20:, 3] = F.shape[0]            # one past the end counts as unbound too
+    bf[30:] = F.shape[0] + 7
+    out = TR.transfer(V, F, Vd, mu, q, s, bf, bb)
+    rest = np.r_[0:20, 30:40]
+    assert np.array_equal(out["means"][rest], mu[rest])
+    np.testing.assert_allclose(out["A"][rest], np.broadcast_to(np.eye(3), (rest.size, 3, 3)), atol=0)
+    np.testing.assert_allclose(cov_of(out["cov3d"])[rest], TR._cov3d(s[rest], q[rest]), atol=1e-15)
+    qn = q[rest].astype(np.float64)
+    qn /= np.linalg.norm(qn, axis=1, keepdims=True)
+    np.testing.assert_allclose(out["quats"][rest], qn, atol=1e-15)
+
+
+@pytest.mark.parametrize("K", [1, 8])
+def test_unbound_corners_leave_the_similarity_closed_form(K):
+    """V' = s Q V + t with a random subset of corners unbound: Eq. 13 averages
+    over the bound corners only, so mu' = mu + mean over bound i of
+    ((sQ - I) P_i + t) (dividing by K instead would shrink the offset) and
+    Sigma' = s^2 Q Sigma Q^T wherever at least one corner is bound."""
+    V, F, mu, s, q, bf, bb = small_scene(K, seed=5)
+    rng = np.random.default_rng(6)
+    bf = bf.copy()
+    drop = rng.random(bf.shape) < 0.4
+    bf[drop] = -1
+    scale = 1.3
+    Qr = Rotation.from_rotvec([-0.2, 0.6, 0.1])
+    Q = Qr.as_matrix()
+    t = np.array([0.05, 0.1, -0.3])
+    Vd = scale * V @ Q.T + t
+    out = TR.transfer(V, F, Vd, mu, q, s, bf, bb)
+    bound = bf >= 0
+    kb = bound.sum(1)
+    some = kb > 0
+    P = bound_points(V, F, np.where(bound, bf, 0), bb)
+    off = ((P @ (scale * Q - np.eye(3)).T + t) * bound[..., None]).sum(1) / np.maximum(kb, 1)[:, None]
+    mu_ref = mu.astype(np.float64) + off
+    np.testing.assert_allclose(out["means"][some], mu_ref[some], atol=3e-6)
+    assert np.array_equal(out["means"][~some], mu[~some])
+    Sig = TR._cov3d(s, q)
+    ref = scale ** 2 * np.einsum("ij,njk,lk->nil", Q, Sig, Q)
+    np.testing.assert_allclose(cov_of(out["cov3d"])[some], ref[some], rtol=1e-8, atol=1e-14)
+    np.testing.assert_allclose(cov_of(out["cov3d"])[~some], Sig[~some], atol=1e-15)
+    if K == 8:
+        assert some.all() and (kb < 8).any() and (kb < 6).any()
+
+
+def test_pinned_mean_with_unbound_corners_exact_rounding():
+    """The float32 mean over the bound corners only: sum in corner order,
+    times 1/k_b rounded to float32; re-evaluated element by element."""
+    import struct
+
+    def r32(x):
+        return struct.unpack("f", struct.pack("f", x))[0]
+    V, F, mu, s, q, bf, bb = small_scene(8, seed=7, n=25)
+    bf = bf.copy()
+    rng = np.random.default_rng(8)
+    bf[rng.random(bf.shape) < 0.5] = -1
+    bf[0] = -1
+    Vd = V + rng.normal(0, 0.05, size=V.shape)
+    d32 = np.asarray(Vd, F32) - np.asarray(V, F32)
+    got = TR.pinned_mean(mu, d32, F, bf, bb)
+    for n in range(25):
+        kb = int((bf[n] >= 0).sum())
+        for c in range(3):
+            acc = None
+            for i in range(8):
+                if bf[n, i] < 0:
+                    continue
+                a, b, cc = F[bf[n, i]]
+                u, v = float(bb[n, i, 0]), float(bb[n, i, 1])
+                w = r32(r32(1.0 - u) - v)
+                di = r32(r32(r32(u * float(d32[a, c])) + r32(v * float(d32[b, c])))
+                         + r32(w * float(d32[cc, c])))
+                acc = di if acc is None else r32(acc + di)
+            ref = float(mu[n, c]) if kb == 0 else r32(float(mu[n, c]) + r32(acc * r32(1.0 / kb)))
+            assert float(got[n, c]) == ref
