@@ -115,13 +115,18 @@ umgs_status umgs_set_proxy(umgs_ctx *ctx, int32_t nV, const float *V_rest, int32
  * cov3d_out (N,6) = A Sigma A^T packed, xform_out (N,9) = A = R'S' row-major;
  * vertex_out (nV,12) = (Delta 3, log R 3, S xx,xy,xz,yy,yz,zz) may be NULL
  * (else 16-byte aligned).
+ * A binding whose face index lies outside [0, nF) -- umgs_bind_raycast
+ * writes -1 where no ray crosses the proxy -- is unbound (Section 3.3.1
+ * leaves such corners open): Eq. 13 then averages over the k_b bound
+ * bindings only, and a Gaussian with none keeps its rest pose (mu' = mu,
+ * R' = S' = A = I, Sigma' = Sigma, q' = q/|q|).
  * means_out follows a fixed FP32 operation order (the deformed mean orders
  * the Gaussians): Delta = V'-V; w = (1-u)-v; Delta_i = (u Da + v Db) + w Dc;
- * s = ((Delta_1 + Delta_2) + ...) + Delta_K; mu' = mu + s * (1/K).
+ * s = ((Delta_a + Delta_b) + ...) over the bound bindings in binding order;
+ * mu' = mu + s * (1/k_b), 1/k_b rounded to FP32.
  * Errors: STATE without umgs_set_proxy; INVALID_ARG for NULL inputs,
  * N < 0, a misaligned vertex_out, or (K = 8) bind_face / bind_bary not
- * 16-byte aligned.  Face indices are not range-checked on the device (caller's
- * responsibility: 0 <= face < nF). */
+ * 16-byte aligned. */
 umgs_status umgs_bind_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
                                const int32_t *bind_face, const float *bind_bary,
                                const float *means, const float *quats, const float *scales,
@@ -143,7 +148,8 @@ umgs_status umgs_bind_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
  * only for K = 8 (may be NULL for K = 1).
  * Outputs [device]: bind_face (N,K) int32 (-1 where no ray crosses the
  * proxy), bind_bary (N,K,2) = (u,v) with crossing = u V[f0] + v V[f1] +
- * (1-u-v) V[f2] ((0,0) for -1), the layout umgs_bind_transfer reads; dist
+ * (1-u-v) V[f2] ((0,0) for -1), the layout umgs_bind_transfer reads (which
+ * leaves -1 corners out of Eq. 13); dist
  * (N,K) the distance from the crossing to the target (+inf for -1), may be
  * NULL.
  * The call builds a BVH of the proxy on the device (linear BVH over the

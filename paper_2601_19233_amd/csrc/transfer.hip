@@ -16,7 +16,10 @@
 // transfer kernels (FP32): Eq. 12 at each of the K bound points, Eq. 13
 //   averages: R' = exp(mean r_i), S' = mean S_i, A = R'S',
 //   Sigma' = A Sigma A^T, mu' = mu + mean Delta_i (pinned order),
-//   q' = quat(R') * q, one lane per Gaussian.
+//   q' = quat(R') * q, one lane per Gaussian.  A corner whose face index
+//   lies outside [0, nF) (the ray-cast binding writes -1 where no ray
+//   crosses the proxy) is unbound: the means run over the bound corners
+//   only, and a Gaussian without a bound corner keeps its rest pose.
 #include "internal.h"
 
 namespace umgs {
@@ -252,7 +255,7 @@ __device__ __forceinline__ void nt_store(float *p, float v) { __builtin_nontempo
 // Eq. 13 for Gaussian i from its corner sums: dsum = sum_k Delta_k (pinned
 // order), rs = sum_k r_k, Ss = sum_k S_k (xx, xy, xz, yy, yz, zz).
 __device__ __forceinline__ void finish_gaussian(int i, float3 dsum, const float rs[3],
-                                                const float Ss[6], float invk,
+                                                const float Ss[6], float invk, bool any_bound,
                                                 const float *__restrict__ means,
                                                 const float *__restrict__ quats,
                                                 const float *__restrict__ scales,
@@ -263,9 +266,12 @@ __device__ __forceinline__ void finish_gaussian(int i, float3 dsum, const float 
   // inputs read once, and the outputs the projection does not read next
   // (A, q'), are streamed (non-temporal), so they do not push the face rows
   // out of L2
-  means_out[3 * i] = pinned_mean(nt_load(means + 3 * i), dsum.x, invk);
-  means_out[3 * i + 1] = pinned_mean(nt_load(means + 3 * i + 1), dsum.y, invk);
-  means_out[3 * i + 2] = pinned_mean(nt_load(means + 3 * i + 2), dsum.z, invk);
+  // no bound corner: the rest pose (mu' = mu bit for bit, R' = S' = I)
+  const float m0 = nt_load(means + 3 * i), m1 = nt_load(means + 3 * i + 1),
+              m2 = nt_load(means + 3 * i + 2);
+  means_out[3 * i] = any_bound ? pinned_mean(m0, dsum.x, invk) : m0;
+  means_out[3 * i + 1] = any_bound ? pinned_mean(m1, dsum.y, invk) : m1;
+  means_out[3 * i + 2] = any_bound ? pinned_mean(m2, dsum.z, invk) : m2;
 
   // R' = exp(mean r), S' = mean S, A = R'S'
   const float r0 = rs[0] * invk, r1 = rs[1] * invk, r2 = rs[2] * invk;
@@ -287,8 +293,10 @@ __device__ __forceinline__ void finish_gaussian(int i, float3 dsum, const float 
   const float Rp[9] = {1.f - hb * (r1 * r1 + r2 * r2), -sa * r2 + hb * r0 * r1, sa * r1 + hb * r0 * r2,
                        sa * r2 + hb * r0 * r1, 1.f - hb * (r0 * r0 + r2 * r2), -sa * r0 + hb * r1 * r2,
                        -sa * r1 + hb * r0 * r2, sa * r0 + hb * r1 * r2, 1.f - hb * (r0 * r0 + r1 * r1)};
-  const float Sm[9] = {Ss[0] * invk, Ss[1] * invk, Ss[2] * invk, Ss[1] * invk, Ss[3] * invk,
-                       Ss[4] * invk, Ss[2] * invk, Ss[4] * invk, Ss[5] * invk};
+  const float sd = any_bound ? 0.f : 1.f;   // rs = Ss = 0 without a bound corner
+  const float Sm[9] = {Ss[0] * invk + sd, Ss[1] * invk, Ss[2] * invk, Ss[1] * invk,
+                       Ss[3] * invk + sd, Ss[4] * invk, Ss[2] * invk, Ss[4] * invk,
+                       Ss[5] * invk + sd};
   float A[9];
 #pragma unroll
   for (int r = 0; r < 3; ++r)
@@ -356,9 +364,18 @@ __device__ __forceinline__ void gather_rows(const f4v *__restrict__ ftab, int fa
   }
 }
 
+// 1/k_b rounded to FP32 for k_b = 0..8 bound corners (0 unused)
+__device__ __forceinline__ float inv_bound(int kb) {
+  constexpr float t[9] = {0.f, 1.f, 1.f / 2, 1.f / 3, 1.f / 4, 1.f / 5, 1.f / 6, 1.f / 7, 1.f / 8};
+  float r = t[0];
+#pragma unroll
+  for (int k = 1; k < 9; ++k) r = kb == k ? t[k] : r;
+  return r;
+}
+
 template <int K>
 __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) void transfer_kernel(
-    int N, const float4 *__restrict__ ftab, const int32_t *__restrict__ bind_face,
+    int N, int nF, const float4 *__restrict__ ftab, const int32_t *__restrict__ bind_face,
     const float *__restrict__ bind_bary, const float *__restrict__ means,
     const float *__restrict__ quats, const float *__restrict__ scales,
     float *__restrict__ means_out, float *__restrict__ quats_out, float *__restrict__ cov3d_out,
@@ -368,8 +385,8 @@ __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) vo
   const int lane = threadIdx.x;
   const int i = blockIdx.x * kTrRows + lane;
   const bool valid = i < N;
-  // this lane's K bindings (face 0 stands in past the end: its row is read
-  // and the result dropped)
+  // this lane's K bindings (face 0 stands in past the end and for unbound
+  // corners: its row is read and the result dropped)
   int face[K];
   float bu[K], bv[K];
   if constexpr (K == 8) {
@@ -401,13 +418,23 @@ __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) vo
       bv[k] = valid ? bind_bary[2 * (K * (int64_t)i + k) + 1] : 0.f;
     }
   }
+  // bit k: corner k is bound to a face of the proxy
+  unsigned bmask = 0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const bool b = (unsigned)face[k] < (unsigned)nF;
+    bmask |= b ? 1u << k : 0u;
+    face[k] = b ? face[k] : 0;
+  }
+  const int kb = __builtin_popcount(bmask);
+  bool started = false;
   float3 ds = make_float3(0.f, 0.f, 0.f);
   float rs[3] = {0.f, 0.f, 0.f}, Ss[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   f4v buf[9];
   gather_rows(ftab4, face[0], lane, buf);
   // one round per bound point; the bindings shift down one place per round,
   // so every index below is static
-  auto round = [&](bool first, bool prefetch) {
+  auto round = [&](bool prefetch) {
 #pragma unroll
     for (int m = 0; m < 9; ++m) rows[64 * m + lane] = buf[m];
     __syncthreads();
@@ -416,9 +443,14 @@ __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) vo
     const f4v a0 = row[0], a1 = row[1], a2 = row[2];
     const f4v b0 = row[3], b1 = row[4], b2 = row[5];
     const f4v c0 = row[6], c1 = row[7], c2 = row[8];
-    const float u = bu[0], v = bv[0], w = pinned_w(u, v);
+    // an unbound corner adds nothing: zero weights (its face-0 row is finite)
+    const bool b = bmask & 1u;
+    const float u = b ? bu[0] : 0.f, v = b ? bv[0] : 0.f, w = b ? pinned_w(u, v) : 0.f;
     const float3 di = interp_delta(u, v, w, a0, b0, c0);
-    ds = first ? di : add3(ds, di);
+    // pinned order: the first bound corner's offset, then the next ones added
+    ds = b ? (started ? add3(ds, di) : di) : ds;
+    started = started || b;
+    bmask >>= 1;
     rs[0] += u * a0.w + v * b0.w + w * c0.w;
     rs[1] += u * a1.x + v * b1.x + w * c1.x;
     rs[2] += u * a1.y + v * b1.y + w * c1.y;
@@ -437,16 +469,13 @@ __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) vo
     __syncthreads();
   };
   if constexpr (K > 1) {
-    round(true, true);
 #pragma unroll 1
-    for (int k = 1; k + 1 < K; ++k) round(false, true);
-    round(false, false);
-  } else {
-    round(true, false);
+    for (int k = 0; k + 1 < K; ++k) round(true);
   }
+  round(false);
   if (valid)
-    finish_gaussian(i, ds, rs, Ss, 1.0f / K, means, quats, scales, means_out, quats_out, cov3d_out,
-                    xform_out);
+    finish_gaussian(i, ds, rs, Ss, inv_bound(kb), kb > 0, means, quats, scales, means_out,
+                    quats_out, cov3d_out, xform_out);
 }
 
 }  // namespace
@@ -474,11 +503,11 @@ hipError_t launch_transfer(Ctx *c, const float *V_def, int32_t N, const int32_t 
   ScopedTimer tt(c, K_TRANSFER);
   const dim3 grid(ceil_div(N, kTrRows)), block(kTrRows);
   if (c->opt.k_bind == 8)
-    hipLaunchKernelGGL(transfer_kernel<8>, grid, block, 0, c->stream, N, (const float4 *)c->ftab.p,
+    hipLaunchKernelGGL(transfer_kernel<8>, grid, block, 0, c->stream, N, c->nF, (const float4 *)c->ftab.p,
                        bind_face, bind_bary, means, quats, scales, means_out, quats_out, cov3d_out,
                        xform_out);
   else
-    hipLaunchKernelGGL(transfer_kernel<1>, grid, block, 0, c->stream, N, (const float4 *)c->ftab.p,
+    hipLaunchKernelGGL(transfer_kernel<1>, grid, block, 0, c->stream, N, c->nF, (const float4 *)c->ftab.p,
                        bind_face, bind_bary, means, quats, scales, means_out, quats_out, cov3d_out,
                        xform_out);
   return hipGetLastError();

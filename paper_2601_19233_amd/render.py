@@ -160,9 +160,6 @@ class Rasterizer:
                       with_vertex: bool = False, out: Optional[Dict] = None) -> Dict[str, torch.Tensor]:
         d = self.device
         V_def, means, quats, scales = (_f32(x, d) for x in (V_def, means, quats, scales))
-        if isinstance(bind_face, np.ndarray) and bind_face.size and (
-                bind_face.min() < 0 or bind_face.max() >= self.nF):
-            raise ValueError("bind_face holds a face index outside the proxy")
         bind_face = _i32(bind_face, d)
         bind_bary = _f32(bind_bary, d)
         N = means.shape[0]

@@ -189,6 +189,54 @@ def test_raycast_binding_drives_the_transfer(gpu):
     r.close()
 
 
+def test_unbound_corners_from_the_raycast_feed_the_transfer(gpu):
+    """Targets far outside the proxy leave some or all of their corners
+    unbound (face -1) in the GPU binding, which goes straight into the
+    transfer: under a rigid translation of the proxy a Gaussian with at
+    least one bound corner moves by the translation (the mean over its bound
+    corners) and one without any keeps its rest pose, bit for bit.  The
+    unbound pattern is the oracle's (every far target's rays miss or cross
+    the sphere clearly)."""
+    import torch
+    from paper_2601_19233_amd.render import Rasterizer
+    rng = np.random.default_rng(3)
+    V, F = scenes.icosphere(8, 1.0)
+    V, F = V.astype(np.float32), F.astype(np.int32)
+    m0, s0, q0 = gaussians(rng, V, F, 500)
+    cams = cam_centres(rng, 4)
+    rf = np.random.default_rng(31)
+    n = 48
+    d = rf.normal(size=(n, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    near = np.arange(n) < 32
+    rad = np.where(near, rf.uniform(1.6, 2.2, size=n), rf.uniform(6, 9, size=n))[:, None]
+    mf = (d * rad).astype(np.float32)
+    sf = (np.where(near[:, None], 0.25, 0.01) * np.ones((n, 3))).astype(np.float32)
+    qf = rf.normal(size=(n, 4)).astype(np.float32)
+    means, s, q = np.concatenate([m0, mf]), np.concatenate([s0, sf]), np.concatenate([q0, qf])
+    note(f"raycast -> transfer with unbound corners N={means.shape[0]}")
+    r = Rasterizer("cuda:0", k_bind=8)
+    r.set_proxy(V, F)
+    b = r.bind_raycast(means, s, q, 8, cams)
+    torch.cuda.synchronize()
+    face = b["face"].cpu().numpy()
+    P = OB.target_points(mf, sf, qf, 8).reshape(-1, 3)
+    f_o = OB.associate(P, cams, V, F)[0].reshape(n, 8)
+    assert np.array_equal(face[500:] < 0, f_o < 0)
+    kb = (f_o >= 0).sum(1)
+    assert (kb == 0).sum() >= 8 and ((kb > 0) & (kb < 8)).sum() >= 8
+    shift = np.array([0.25, -0.5, 0.125], np.float32)
+    out = r.bind_transfer(V + shift, b["face"], b["bary"], means, q, s)
+    torch.cuda.synchronize()
+    gm = out["means"].cpu().numpy()
+    moved = np.r_[np.ones(500, bool), kb > 0]
+    np.testing.assert_allclose(gm[moved], means[moved] + shift, atol=2e-6)
+    assert np.array_equal(gm[~moved], means[~moved])
+    A = out["xform"].cpu().numpy().reshape(-1, 3, 3)
+    np.testing.assert_allclose(A, np.broadcast_to(np.eye(3), A.shape), atol=2e-6)
+    r.close()
+
+
 def test_binding_proxy_past_16_bit_node_indices(gpu):
     """A 67,280-face proxy (more than 2^16 internal nodes): the traversal
     stack switches to 32-bit entries."""

@@ -244,6 +244,91 @@ def test_deformed_scene_parity(torch_dev, K):
     PT.compare_pixels(fr, img, Tf, last_gids(r, nc), px)
 
 
+def check_transfer(r, V_rest, F, V_def, bf, bb, mu, q, sc):
+    """GPU transfer against the oracle transfer on the same bindings: means
+    bit for bit, covariances, rotations and A to FP32 accuracy."""
+    from oracle import transfer as OT
+    dt = r.bind_transfer(V_def, bf, bb, mu, q, sc)
+    ot = OT.transfer(V_rest, F, V_def, mu, q, sc, bf, bb)
+    assert np.array_equal(to_np(dt["means"]), ot["means"])
+    np.testing.assert_allclose(to_np(dt["cov3d"]), ot["cov3d"], rtol=2e-4,
+                               atol=1e-5 * np.abs(ot["cov3d"]).max())
+    np.testing.assert_allclose(to_np(dt["quats"]), ot["quats"], rtol=0, atol=1e-5)
+    np.testing.assert_allclose(to_np(dt["xform"]).reshape(-1, 3, 3), ot["A"], rtol=0, atol=1e-5)
+    return dt, ot
+
+
+@pytest.mark.parametrize("K", [8, 1])
+def test_unbound_corners_transfer_parity(torch_dev, K):
+    """Bindings outside [0, nF) are unbound: Eq. 13 averages over the bound
+    corners only (mean offset in the pinned order with 1/k_b), and a
+    Gaussian without a bound corner keeps its rest pose.  A random 30 % of
+    the corners of the scaled deformed workload are set to -1, one past the
+    end, or far past it."""
+    from paper_2601_19233_amd.render import Rasterizer
+    s = scenes.make_config(1, scale=0.004, res_scale=0.06, K=K)
+    rng = np.random.default_rng(21)
+    nF = s.proxy.faces.shape[0]
+    bf = s.bind_face.copy()
+    bf[rng.random(bf.shape) < 0.3] = -1
+    bf[:7] = -1
+    bf[7:12, 0] = nF
+    bf[12:15] = np.int32(-2 ** 31)
+    bf[15:18, -1] = 2 ** 31 - 1
+    note(f"unbound corners K={K} N={s.N} unbound={int((bf < 0).sum() + (bf >= nF).sum())}")
+    r = Rasterizer("cuda:0", k_bind=K)
+    r.set_proxy(s.proxy.V_rest, s.proxy.faces)
+    dt, ot = check_transfer(r, s.proxy.V_rest, s.proxy.faces, s.proxy.V_def, bf, s.bind_bary,
+                            s.means, s.quats, s.scales)
+    rest = np.nonzero(((bf < 0) | (bf >= nF)).all(1))[0]
+    assert rest.size >= 10
+    assert np.array_equal(to_np(dt["means"])[rest], s.means[rest])
+    A = to_np(dt["xform"]).reshape(-1, 3, 3)[rest]
+    assert np.array_equal(A, np.broadcast_to(np.eye(3, dtype=np.float32), A.shape))
+    r.close()
+
+
+def test_twisted_proxy_log_average_of_differing_rotations(torch_dev):
+    """A proxy twisted about y by 1.5 rad per unit of height gives a
+    Gaussian's 8 box corners rotations that differ by up to about a radian:
+    Eq. 13's exp of the mean log-rotation then differs clearly from an
+    average of the rotations themselves, and the GPU must follow the
+    former."""
+    from scipy.spatial.transform import Rotation
+    from paper_2601_19233_amd.render import Rasterizer
+    rng = np.random.default_rng(5)
+    V, F = scenes.icosphere(8, 1.0)
+    V, F = V.astype(np.float32), F.astype(np.int32)
+    n = 777
+    mu = scenes._sample_on_mesh(rng, V.astype(np.float64), F, n, 0.02).astype(np.float32)
+    sc, q, _, _ = scenes._gaussian_stats(rng, n, 0)
+    sc = (sc * 3.0).astype(np.float32)
+    q = q.astype(np.float32)
+    bf, bb = scenes.make_binding(mu, sc, q, V, F, 8)
+    ang = 1.5 * V[:, 1].astype(np.float64)
+    c, s_ = np.cos(ang), np.sin(ang)
+    Vd = np.stack([c * V[:, 0] + s_ * V[:, 2], V[:, 1], -s_ * V[:, 0] + c * V[:, 2]], 1).astype(np.float32)
+    note(f"twisted proxy N={n}")
+    r = Rasterizer("cuda:0", k_bind=8)
+    r.set_proxy(V, F)
+    dt, ot = check_transfer(r, V, F, Vd, bf, bb, mu, q, sc)
+    # the reading matters here: averaging the corners' rotation matrices
+    # (then taking the nearest rotation) gives a different R'
+    vt = ot["vertex"]
+    u = bb[..., 0].astype(np.float64)
+    v = bb[..., 1].astype(np.float64)
+    w = 1 - u - v
+    fv = F[bf]
+    ri = u[..., None] * vt["r"][fv[..., 0]] + v[..., None] * vt["r"][fv[..., 1]] + w[..., None] * vt["r"][fv[..., 2]]
+    Rm = Rotation.from_rotvec(ri.reshape(-1, 3)).as_matrix().reshape(n, 8, 3, 3).mean(1)
+    U, _, Wt = np.linalg.svd(Rm)
+    Ralt = U @ Wt
+    Rlog = Rotation.from_rotvec(ri.mean(1)).as_matrix()
+    gap = np.abs(Ralt - Rlog).max((1, 2))
+    assert (gap > 1e-3).sum() > n // 4
+    r.close()
+
+
 def test_sh3_parity(torch_dev):
     s = scenes.make_config(2, scale=0.01, res_scale=0.1)
     note(f"sh3 N={s.N} T={s.T}")
