@@ -133,6 +133,25 @@ umgs_status umgs_bind_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
                                float *means_out, float *quats_out, float *cov3d_out,
                                float *xform_out, float *vertex_out);
 
+/* umgs_bind_transfer for callers that cannot allocate device memory during
+ * the call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): same arguments, kernels, results and errors, but the
+ * per-vertex table and the face rows live in a static device array of
+ * 16 MiB (16,777,216 bytes) that every GPU the library runs on holds until
+ * the process ends, instead of context buffers; the call allocates nothing
+ * and synchronizes nothing.  It needs 48 * nV bytes (rounded up to 256; none
+ * when vertex_out is given) + 144 * nF bytes of that array, and fails with
+ * CAPACITY, before any launch, for a proxy that needs more.  All calls on
+ * one GPU share the array (it keeps the last call's contents, every byte of
+ * it a call reads is written by that call first): calls that overlap on one
+ * GPU -- on two streams, or from two contexts -- race and must be ordered by
+ * the caller. */
+umgs_status umgs_bind_transfer_noalloc(umgs_ctx *ctx, const float *V_def, int32_t N,
+                                       const int32_t *bind_face, const float *bind_bary,
+                                       const float *means, const float *quats,
+                                       const float *scales, float *means_out, float *quats_out,
+                                       float *cov3d_out, float *xform_out, float *vertex_out);
+
 /* Binding association by ray casting (Section 3.3.1), a setup step run
  * before deformation.  Each Gaussian has K target points: K = 1 its mean,
  * K = 8 the corners mu + R(q) diag(3 s) (sx, sy, sz) of its bounding box,

@@ -148,6 +148,12 @@ umgs_status umgs_create(umgs_ctx **out, const umgs_options *opt, void *hip_strea
   int ncu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess)
     c->num_cu = ncu;
+  // the allocation-free entry point's scratch on this device (looked up once
+  // per device, with it current)
+  if (noalloc_scratch_init(c->device) != hipSuccess) {
+    delete h;
+    return UMGS_ERR_HIP;
+  }
   *out = h;
   return UMGS_OK;
 }
@@ -312,6 +318,41 @@ umgs_status umgs_bind_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
                 "umgs_bind_transfer: bind_face and bind_bary must be 16-byte aligned");
   return hip_check(c, launch_transfer(c, V_def, N, bind_face, bind_bary, means, quats, scales,
                                       means_out, quats_out, cov3d_out, xform_out, vertex_out),
+                   "transfer launch");
+}
+
+umgs_status umgs_bind_transfer_noalloc(umgs_ctx *ctx, const float *V_def, int32_t N,
+                                       const int32_t *bind_face, const float *bind_bary,
+                                       const float *means, const float *quats,
+                                       const float *scales, float *means_out, float *quats_out,
+                                       float *cov3d_out, float *xform_out, float *vertex_out) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->nV == 0)
+    return fail(c, UMGS_ERR_STATE, "umgs_bind_transfer_noalloc: no proxy (call umgs_set_proxy)");
+  if (N < 0) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_bind_transfer_noalloc: N=%d", N);
+  if (!V_def) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_bind_transfer_noalloc: NULL V_def");
+  if (N > 0 && (!bind_face || !bind_bary || !means || !quats || !scales || !means_out ||
+                !cov3d_out))
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_bind_transfer_noalloc: NULL Gaussian array");
+  if (((uintptr_t)vertex_out & 15) != 0)
+    return fail(c, UMGS_ERR_INVALID_ARG,
+                "umgs_bind_transfer_noalloc: vertex_out is not 16-byte aligned");
+  if (c->opt.k_bind == 8 && N > 0 && ((((uintptr_t)bind_face) | ((uintptr_t)bind_bary)) & 15) != 0)
+    return fail(c, UMGS_ERR_INVALID_ARG,
+                "umgs_bind_transfer_noalloc: bind_face and bind_bary must be 16-byte aligned");
+  const size_t need = noalloc_transfer_bytes(c->nV, c->nF, vertex_out == nullptr);
+  if (need > kNoAllocScratchBytes)
+    return fail(c, UMGS_ERR_CAPACITY,
+                "umgs_bind_transfer_noalloc: a proxy of %d vertices and %d faces needs %zu bytes "
+                "of scratch, more than the %zu the library holds per GPU",
+                c->nV, c->nF, need, kNoAllocScratchBytes);
+  void *base = noalloc_scratch(c->device);
+  if (!base)
+    return fail(c, UMGS_ERR_STATE, "umgs_bind_transfer_noalloc: no scratch on device %d", c->device);
+  return hip_check(c, launch_transfer_noalloc(c, base, V_def, N, bind_face, bind_bary, means, quats,
+                                              scales, means_out, quats_out, cov3d_out, xform_out,
+                                              vertex_out),
                    "transfer launch");
 }
 

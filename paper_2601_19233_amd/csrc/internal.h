@@ -255,6 +255,19 @@ hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32
                            const float *quats, const float *xform, const float *sh,
                            float *d_means, float *d_scales, float *d_quats, float *d_opac,
                            float *d_sh, bool accumulate);
+// Allocation-free transfer: its scratch is a static device array of
+// kNoAllocScratchBytes per GPU, whose address noalloc_scratch_init looks up
+// once per device (with that device current) and noalloc_scratch returns.
+constexpr size_t kNoAllocScratchBytes = size_t(16) << 20;
+constexpr int kMaxDevices = 64;
+hipError_t noalloc_scratch_init(int device);
+void *noalloc_scratch(int device);
+size_t noalloc_transfer_bytes(int64_t nV, int64_t nF, bool vertex_table_in_scratch);
+hipError_t launch_transfer_noalloc(Ctx *c, void *scratch_base, const float *V_def, int32_t N,
+                                   const int32_t *bind_face, const float *bind_bary,
+                                   const float *means, const float *quats, const float *scales,
+                                   float *means_out, float *quats_out, float *cov3d_out,
+                                   float *xform_out, float *vertex_out);
 hipError_t launch_transfer(Ctx *c, const float *V_def, int32_t N, const int32_t *bind_face,
                            const float *bind_bary, const float *means, const float *quats,
                            const float *scales, float *means_out, float *quats_out,

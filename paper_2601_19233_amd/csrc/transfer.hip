@@ -22,7 +22,44 @@
 //   only, and a Gaussian without a bound corner keeps its rest pose.
 #include "internal.h"
 
+#include <mutex>
+
+// Scratch of the allocation-free transfer (umgs_bind_transfer_noalloc): the
+// per-vertex table (48 B per proxy vertex, unless the caller takes it) and
+// the face rows (144 B per face, at a 256-byte boundary after it).  Every
+// GPU the library runs on holds its own copy until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns for
+// the current device.
+static __device__ __align__(256) unsigned char scratch[umgs::kNoAllocScratchBytes];
+
 namespace umgs {
+
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_addr[device]) return hipSuccess;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_addr[device] = p;
+  return hipSuccess;
+}
+
+void *noalloc_scratch(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_addr[device];
+}
+
+size_t noalloc_transfer_bytes(int64_t nV, int64_t nF, bool vertex_table_in_scratch) {
+  const size_t vt = vertex_table_in_scratch ? (size_t)(48 * nV + 255) / 256 * 256 : 0;
+  return vt + (size_t)144 * (size_t)nF;
+}
 
 namespace {
 
@@ -480,14 +517,16 @@ __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) vo
 
 }  // namespace
 
-hipError_t launch_transfer(Ctx *c, const float *V_def, int32_t N, const int32_t *bind_face,
-                           const float *bind_bary, const float *means, const float *quats,
-                           const float *scales, float *means_out, float *quats_out,
-                           float *cov3d_out, float *xform_out, float *vertex_out) {
-  float *vtab = vertex_out ? vertex_out : (float *)c->vtab.p;
+// The transfer's launches with the per-vertex table at vtab and the face rows
+// at ftab; timed launches report to the context's profiler.
+static hipError_t transfer_launches(Ctx *c, const float *V_def, int32_t N,
+                                    const int32_t *bind_face, const float *bind_bary,
+                                    const float *means, const float *quats, const float *scales,
+                                    float *means_out, float *quats_out, float *cov3d_out,
+                                    float *xform_out, float *vtab, float4 *ftab, bool timed) {
   hipError_t e;
   {
-    ScopedTimer t(c, K_VERTEX_FRAMES);
+    ScopedTimer t(c, timed ? K_VERTEX_FRAMES : -1);
     hipLaunchKernelGGL(vertex_frames_kernel, dim3(ceil_div(c->nV, 128)), dim3(128), 0, c->stream,
                        c->nV, (const float *)c->V_rest.p, V_def, (const int32_t *)c->faces.p,
                        (const int32_t *)c->vf_ptr.p, (const int32_t *)c->vf_idx.p, vtab);
@@ -495,22 +534,44 @@ hipError_t launch_transfer(Ctx *c, const float *V_def, int32_t N, const int32_t 
     if (e == hipSuccess && N > 0) {
       hipLaunchKernelGGL(face_rows_kernel, dim3((unsigned)ceil_div(9 * (int64_t)c->nF, 256)),
                          dim3(256), 0, c->stream, c->nF, (const int32_t *)c->faces.p,
-                         (const float4 *)vtab, (float4 *)c->ftab.p);
+                         (const float4 *)vtab, ftab);
       e = hipGetLastError();
     }
   }
   if (e != hipSuccess || N == 0) return e;
-  ScopedTimer tt(c, K_TRANSFER);
+  ScopedTimer tt(c, timed ? K_TRANSFER : -1);
   const dim3 grid(ceil_div(N, kTrRows)), block(kTrRows);
   if (c->opt.k_bind == 8)
-    hipLaunchKernelGGL(transfer_kernel<8>, grid, block, 0, c->stream, N, c->nF, (const float4 *)c->ftab.p,
+    hipLaunchKernelGGL(transfer_kernel<8>, grid, block, 0, c->stream, N, c->nF, (const float4 *)ftab,
                        bind_face, bind_bary, means, quats, scales, means_out, quats_out, cov3d_out,
                        xform_out);
   else
-    hipLaunchKernelGGL(transfer_kernel<1>, grid, block, 0, c->stream, N, c->nF, (const float4 *)c->ftab.p,
+    hipLaunchKernelGGL(transfer_kernel<1>, grid, block, 0, c->stream, N, c->nF, (const float4 *)ftab,
                        bind_face, bind_bary, means, quats, scales, means_out, quats_out, cov3d_out,
                        xform_out);
   return hipGetLastError();
+}
+
+hipError_t launch_transfer(Ctx *c, const float *V_def, int32_t N, const int32_t *bind_face,
+                           const float *bind_bary, const float *means, const float *quats,
+                           const float *scales, float *means_out, float *quats_out,
+                           float *cov3d_out, float *xform_out, float *vertex_out) {
+  float *vtab = vertex_out ? vertex_out : (float *)c->vtab.p;
+  return transfer_launches(c, V_def, N, bind_face, bind_bary, means, quats, scales, means_out,
+                           quats_out, cov3d_out, xform_out, vtab, (float4 *)c->ftab.p, true);
+}
+
+hipError_t launch_transfer_noalloc(Ctx *c, void *scratch_base, const float *V_def, int32_t N,
+                                   const int32_t *bind_face, const float *bind_bary,
+                                   const float *means, const float *quats, const float *scales,
+                                   float *means_out, float *quats_out, float *cov3d_out,
+                                   float *xform_out, float *vertex_out) {
+  unsigned char *base = (unsigned char *)scratch_base;
+  float *vtab = vertex_out ? vertex_out : (float *)base;
+  const size_t ftab_off = vertex_out ? 0 : noalloc_transfer_bytes(c->nV, 0, true);
+  return transfer_launches(c, V_def, N, bind_face, bind_bary, means, quats, scales, means_out,
+                           quats_out, cov3d_out, xform_out, vtab, (float4 *)(base + ftab_off),
+                           false);
 }
 
 }  // namespace umgs

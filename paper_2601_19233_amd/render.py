@@ -157,7 +157,10 @@ class Rasterizer:
         return out
 
     def bind_transfer(self, V_def, bind_face, bind_bary, means, quats, scales,
-                      with_vertex: bool = False, out: Optional[Dict] = None) -> Dict[str, torch.Tensor]:
+                      with_vertex: bool = False, out: Optional[Dict] = None,
+                      noalloc: bool = False) -> Dict[str, torch.Tensor]:
+        """Eq. 12-13 transfer (umgs_bind_transfer; umgs_bind_transfer_noalloc
+        with ``noalloc``, whose scratch is the library's static per-GPU array)."""
         d = self.device
         V_def, means, quats, scales = (_f32(x, d) for x in (V_def, means, quats, scales))
         bind_face = _i32(bind_face, d)
@@ -171,7 +174,8 @@ class Rasterizer:
                        cov3d=torch.empty((N, 6), device=d), xform=torch.empty((N, 9), device=d))
         vert = torch.empty((self.nV, 12), device=d) if with_vertex else None
         with self._on_stream():
-            self._check(self.lib.umgs_bind_transfer(
+            fn = self.lib.umgs_bind_transfer_noalloc if noalloc else self.lib.umgs_bind_transfer
+            self._check(fn(
                 self.h, _ptr(V_def), N, _ptr(bind_face), _ptr(bind_bary), _ptr(means), _ptr(quats),
                 _ptr(scales), _ptr(out["means"]), _ptr(out["quats"]), _ptr(out["cov3d"]),
                 _ptr(out["xform"]), _ptr(vert)))
