@@ -119,7 +119,8 @@ umgs_status umgs_set_proxy(umgs_ctx *ctx, int32_t nV, const float *V_rest, int32
  * writes -1 where no ray crosses the proxy -- is unbound (Section 3.3.1
  * leaves such corners open): Eq. 13 then averages over the k_b bound
  * bindings only, and a Gaussian with none keeps its rest pose (mu' = mu,
- * R' = S' = A = I, Sigma' = Sigma, q' = q/|q|).
+ * R' = S' = A = I, Sigma' = Sigma, q' = q/|q|); the barycentrics of an
+ * unbound binding must be finite, their values are otherwise unused.
  * means_out follows a fixed FP32 operation order (the deformed mean orders
  * the Gaussians): Delta = V'-V; w = (1-u)-v; Delta_i = (u Da + v Db) + w Dc;
  * s = ((Delta_a + Delta_b) + ...) over the bound bindings in binding order;
@@ -363,7 +364,7 @@ enum { UMGS_K_VERTEX_FRAMES = 0, UMGS_K_TRANSFER = 1, UMGS_K_PROJECT = 2, UMGS_K
        UMGS_K_SCAN = 4, UMGS_K_EMIT = 5, UMGS_K_SORT_UPSWEEP = 6, UMGS_K_SORT_SCAN = 7,
        UMGS_K_SORT_DOWNSWEEP = 8, UMGS_K_RANGES = 9, UMGS_K_BLEND = 10, UMGS_K_BLEND_BWD = 11,
        UMGS_K_PROJECT_BWD = 12, UMGS_K_DEPTH_SORT = 13, UMGS_K_TILE_COUNT = 14,
-       UMGS_K_TILE_SCATTER = 15, UMGS_K_COUNT = 16 };
+       UMGS_K_TILE_SCATTER = 15, UMGS_K_ST_MASK = 16, UMGS_K_COUNT = 17 };
 umgs_status umgs_set_profiling(umgs_ctx *ctx, int32_t enable);
 umgs_status umgs_profile_read(umgs_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms);
 

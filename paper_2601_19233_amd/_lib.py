@@ -67,7 +67,8 @@ PROTOTYPES = {
 
 KERNEL_NAMES = ["vertex_frames", "transfer", "project_gaussians", "setup_triangles", "count_scan",
                 "emit_keys", "sort_upsweep", "sort_scan", "sort_downsweep", "tile_ranges", "blend",
-                "blend_backward", "project_backward", "depth_sort", "tile_count", "tile_scatter"]
+                "blend_backward", "project_backward", "depth_sort", "tile_count", "tile_scatter",
+                "st_mask"]
 
 _lib = None
 

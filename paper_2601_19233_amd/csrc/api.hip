@@ -177,7 +177,8 @@ void umgs_destroy(umgs_ctx *ctx) {
                     &c->sk[0], &c->sk[1], &c->sv[0], &c->sv[1], &c->masks[0], &c->masks[1], &c->st_rng,
                     &c->chunk_base, &c->cnt2, &c->chunk_tab, &c->tstart, &c->totals,
                     &c->v0, &c->v1, &c->hist, &c->ranges, &c->g2d,
-                    &c->minmax, &c->lb, &c->finfo, &c->tile_order, &c->pair_count, &c->view_sums};
+                    &c->minmax, &c->lb, &c->finfo, &c->tile_order, &c->bwd_order, &c->pair_count,
+                    &c->view_sums};
   for (DevBuf *b : bufs) free_buf(*b);
   for (auto &p : c->prof.pending) {
     (void)hipEventDestroy(p.a);
@@ -232,7 +233,7 @@ umgs_status umgs_set_proxy(umgs_ctx *ctx, int32_t nV, const float *V_rest, int32
       (s = ensure(c, c->vf_ptr, sizeof(int32_t) * (nV + 1), "vertex-face offsets")) ||
       (s = ensure(c, c->vf_idx, sizeof(int32_t) * idx.size(), "vertex-face lists")) ||
       (s = ensure(c, c->vtab, sizeof(float) * 12 * nV, "vertex transforms")) ||
-      (s = ensure(c, c->ftab, sizeof(float) * 36 * (size_t)nF, "face transforms")))
+      (s = ensure(c, c->ftab, sizeof(float) * 36 * ((size_t)nF + 1), "face transforms")))
     return s;
   hipError_t e;
   if ((e = hipMemcpy(c->V_rest.p, V_rest, sizeof(float) * 3 * nV, hipMemcpyHostToDevice)) ||
@@ -461,7 +462,8 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
       (s = ensure(c, c->minmax, 2 * kMinMaxSlots * sizeof(uint32_t), "depth range")) ||
       (s = ensure(c, c->lb, sizeof(LbState), "scan state")) ||
       (s = ensure(c, c->finfo, sizeof(FrameInfo), "frame info")) ||
-      (s = ensure(c, c->tile_order, sizeof(uint32_t) * (64 + tiles), "tile order")))
+      (s = ensure(c, c->tile_order, sizeof(uint32_t) * (64 + tiles), "tile order")) ||
+      (s = ensure(c, c->bwd_order, sizeof(uint32_t) * (128 + 2 * tiles), "backward tile order")))
     return s;
   const bool fresh_info = c->finfo.cap && c->views.empty();
   const bool fresh_lb = !c->lb_zeroed;

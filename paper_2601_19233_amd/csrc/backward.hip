@@ -1,8 +1,9 @@
 // Backward pass of the single-pass rasterizer.
 //
-// blend_backward_kernel: one workgroup per tile, one thread per pixel,
-// walking the tile's sorted list from the pixel's last blended fragment
-// back to the front.  Every unit (a Gaussian, or a whole triangle entity)
+// blend_backward_kernel: one wave per tile (tiles launched in decreasing
+// order of their walk length), four pixels per lane, walking the tile's
+// sorted list from the pixels' last blended fragment back to the front.
+// Every unit (a Gaussian, or a whole triangle entity)
 // acts on the pixel as C += T_before x contribution, T_after = T_before x m,
 // so going backwards the pixel keeps
 //   B  -- the colour behind the current unit, normalised by the
@@ -15,12 +16,14 @@
 // Triangle entity (Eq. 7-9), per sub-sample j in reverse:
 //   s^j = o^j a c + (1 - o^j a) s^j   (starting from B),
 //   p^j = (1 - o^j a) p^j             (starting from 1),
-// and when the entity closes B = mean_j s^j, tau = mean_j p^j.  Triangles
-// are fixed occluders: they pass gradients through T but receive none.
+// and when the entity closes B = mean_j s^j, tau = mean_j p^j.  Colours
+// enter only through their dot product with the pixel's dL/dC, so B and the
+// s^j are carried as such scalars.  Triangles are fixed occluders: they
+// pass gradients through T but receive none.
 // Per fragment the 9 gradient terms (mean 2D, the 3 power coefficients,
-// opacity, colour) are summed over the wave with DPP moves, stored per wave
-// in LDS, summed over the workgroup's waves and added once per tile with
-// float atomics.
+// opacity, colour) are summed over the lane's pixels, then over the wave
+// (a transposing DPP reduction that leaves the totals in four lanes), and
+// added once per tile with three float-atomic instructions.
 //
 // project_backward_kernel: one thread per Gaussian, looping over views:
 // the chain rule back through the conic inverse, the EWA Jacobian (with the
@@ -34,41 +37,20 @@ namespace umgs {
 
 namespace {
 
-// Sums over the 64 lanes of the wave, complete in lane 63 (other lanes end
-// with partial sums), with DPP moves on the vector ALU: swap neighbours,
-// swap pairs, mirror half-rows and rows (every lane holds its 16-lane row's
-// sum), then broadcast lane 15 of each row into the next row and lane 31
-// into the upper rows.  Every lane of the wave must be active.
-// (bound_ctrl set: the permutes have no invalid source lanes, and with it
-// the compiler folds each move into the add as one DPP instruction.)  The
-// K values advance step by step together, so the dependent DPP operations
-// of one value are separated by those of the others instead of by nops.
-template <int CTRL, int ROWS, int K>
-__device__ __forceinline__ void dpp_add_step(float (&v)[K]) {
-#pragma unroll
-  for (int k = 0; k < K; ++k)
-    v[k] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[k]), CTRL, ROWS, 0xF, true));
-}
-
-template <int K>
-__device__ __forceinline__ void wave_totals(float (&v)[K]) {
-  dpp_add_step<0xB1, 0xF>(v);    // quad_perm [1,0,3,2]
-  dpp_add_step<0x4E, 0xF>(v);    // quad_perm [2,3,0,1]
-  dpp_add_step<0x141, 0xF>(v);   // row_half_mirror
-  dpp_add_step<0x140, 0xF>(v);   // row_mirror
-  // Only lane 63 is read: it takes lane 47 (row 2's sum) here and then
-  // lane 31 (rows 0 + 1); what the other rows receive does not reach it, so
-  // these steps write every row and fold into single DPP adds as well.
-  dpp_add_step<0x142, 0xF>(v);   // row_bcast:15
-  dpp_add_step<0x143, 0xF>(v);   // row_bcast:31
-}
-
 // Backward state of one pixel while its list is walked from the back.
+// Everything the gradients need of a colour is its dot product with the
+// pixel's dL/dC (all of it is linear in colours), so the colour behind the
+// current unit is carried as that scalar: Bd = B . dL/dC, and inside a
+// triangle entity one such scalar per sub-sample.  ent is +inf outside an
+// entity; inside one it holds the transmittance behind the entity (T_in
+// tau), or -1 for the pixel's last blended unit, whose front transmittance
+// the forward stored.  Each triangle of an entity leaves Bd and Tr as they
+// are in front of the entity so far, so a Gaussian in front of it closes
+// the entity by just clearing ent.
 struct PixBwd {
-  float Tr, Tterm, dC0, dC1, dC2, B0, B1, B2;
+  float Tr, Tterm, dC0, dC1, dC2, Bd, ent;
   int last;
-  bool in_ent, term_ent;
-  float s0[3], s1[3], s2[3], s3[3];
+  float sd0, sd1, sd2, sd3;
   float p0, p1, p2, p3;
 };
 
@@ -76,35 +58,26 @@ struct PixBwd {
 // pixel's state where it blended the fragment and leaves the pixel's 9
 // gradient terms in g (exact zeros where it did not), in the reduced form
 // that the wave sums: (dp dx, dp dy, dp dx^2, dp dx dy, dp dy^2, a dpow,
-// w dC); finish_terms turns the sums into the gradients of the mean and
+// w dC); add_sums9 turns the sums into the gradients of the mean and
 // opacity with the fragment's constants, once per wave instead of per
-// pixel.  Returns whether it
-// blended it.  Every lane evaluates every term (no short-circuit), so the
-// wave sums that follow see defined values on all lanes.
+// pixel.  Returns whether it blended it.  Every lane evaluates every term
+// (no branches), so the wave sums that follow see defined values on all
+// lanes.
 __device__ __forceinline__ bool gauss_bwd(const uint32_t *s, int pos, float pcx, float pcy,
                                           PixBwd &q, float *g) {
   float alpha, a_un, dx, dy;
   const bool hit = gauss_terms(s, pcx, pcy, alpha, a_un, dx, dy);
   const bool contrib = pos < q.last && hit;
-  if (contrib && q.in_ent) {
-    q.B0 = 0.25f * ((q.s0[0] + q.s1[0]) + (q.s2[0] + q.s3[0]));
-    q.B1 = 0.25f * ((q.s0[1] + q.s1[1]) + (q.s2[1] + q.s3[1]));
-    q.B2 = 0.25f * ((q.s0[2] + q.s1[2]) + (q.s2[2] + q.s3[2]));
-    q.Tr = q.term_ent ? q.Tterm : q.Tr / (0.25f * ((q.p0 + q.p1) + (q.p2 + q.p3)));
-    q.in_ent = false;
-  }
+  q.ent = contrib ? __builtin_inff() : q.ent;     // a blended Gaussian closes an entity
   // T in front of the fragment: one rcp (1 ulp) per step of the walk
   const float Tb = (pos == q.last - 1) ? q.Tterm : q.Tr * __builtin_amdgcn_rcpf(1.0f - alpha);
-  const float c0 = __uint_as_float(s[6]), c1 = __uint_as_float(s[7]), c2 = __uint_as_float(s[8]);
+  const float cd = fmaf(__uint_as_float(s[6]), q.dC0,
+                        fmaf(__uint_as_float(s[7]), q.dC1, __uint_as_float(s[8]) * q.dC2));
+  const float diff = cd - q.Bd;             // (c - B) . dL/dC
   const float w = contrib ? Tb * alpha : 0.0f;
-  const float dLda =
-      contrib ? Tb * ((c0 - q.B0) * q.dC0 + (c1 - q.B1) * q.dC1 + (c2 - q.B2) * q.dC2) : 0.0f;
-  if (contrib) {
-    q.B0 = fmaf(alpha, c0 - q.B0, q.B0);
-    q.B1 = fmaf(alpha, c1 - q.B1, q.B1);
-    q.B2 = fmaf(alpha, c2 - q.B2, q.B2);
-    q.Tr = Tb;
-  }
+  const float dLda = contrib ? Tb * diff : 0.0f;
+  q.Bd = contrib ? fmaf(alpha, diff, q.Bd) : q.Bd;
+  q.Tr = contrib ? Tb : q.Tr;
   // alpha below the 0.99 clamp depends on power and opacity
   const float dpow = (a_un < kAlphaMax) ? dLda : 0.0f;
   const float dp = alpha * dpow;     // d alpha / d power = o exp(power) = alpha
@@ -124,15 +97,71 @@ __device__ __forceinline__ bool gauss_bwd(const uint32_t *s, int pos, float pcx,
   return contrib;
 }
 
-// Gradient of the 2D mean and of the opacity from the wave's sums of the
-// reduced terms (the stored power coefficients carry log2(e)):
-// d/dmean = ln2 (2 qa S_dx + qb S_dy, qb S_dx + 2 qc S_dy), d/do = S_a / o.
-__device__ __forceinline__ void finish_terms(const uint32_t *s, float *g) {
-  const float qa = __uint_as_float(s[2]), qb = __uint_as_float(s[3]), qc = __uint_as_float(s[4]);
-  const float sx = g[0], sy = g[1];
-  g[0] = kLn2 * (2.0f * qa * sx + qb * sy);
-  g[1] = kLn2 * (qb * sx + 2.0f * qc * sy);
-  g[5] = g[5] * __uint_as_float(s[kSlotInvO]);
+// Wave sums of a fragment's 9 reduced terms, left spread over the lanes
+// by their two lowest bits (every lane holds the totals of its group):
+//   lane & 3 == 0: terms 0, 1, 2;  1: terms 5, 6, 7;  2: terms 3, 4;  3: term 8.
+// The first two steps transpose as they add: partners L and L ^ 1 each keep
+// one half of the terms, summed (5 values left), then L and L ^ 2 (3 left);
+// lanes with the same two low bits then hold the same terms, summed with
+// row rotations by 4 and 8 and across the rows with lane permutes.  That is
+// 36 additions and selects per lane instead of 54 for nine full sums, and
+// the totals end in four lanes, so three atomic instructions add them.
+template <int CTRL>
+__device__ __forceinline__ float dpp_src(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
+}
+
+__device__ __forceinline__ void wave_sums9(const float (&v)[9], float (&t)[3], bool b0, bool b1) {
+  float a[5];
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    const float hi = i < 4 ? v[5 + i] : 0.0f;
+    const float keep = b0 ? hi : v[i];
+    const float send = b0 ? v[i] : hi;
+    a[i] = keep + dpp_src<0xB1>(send);           // quad_perm [1,0,3,2]: lane ^ 1
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const float hi = i < 2 ? a[3 + i] : 0.0f;
+    const float keep = b1 ? hi : a[i];
+    const float send = b1 ? a[i] : hi;
+    t[i] = keep + dpp_src<0x4E>(send);           // quad_perm [2,3,0,1]: lane ^ 2
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) t[i] += dpp_src<0x124>(t[i]);   // row_ror:4
+#pragma unroll
+  for (int i = 0; i < 3; ++i) t[i] += dpp_src<0x128>(t[i]);   // row_ror:8
+#pragma unroll
+  for (int i = 0; i < 3; ++i) t[i] += __shfl_xor(t[i], 16, 64);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) t[i] += __shfl_xor(t[i], 32, 64);
+}
+
+// The wave totals of wave_sums9 added to the fragment's 2D gradients by
+// lanes 0..3 (three atomic instructions), the mean and opacity terms first
+// turned into gradients with the fragment's constants (the stored power
+// coefficients carry log2(e)): d/dmean = ln2 (2 qa S_dx + qb S_dy,
+// qb S_dx + 2 qc S_dy), d/do = S_a / o.
+__device__ __forceinline__ void add_sums9(const uint32_t *s, const float (&t)[3], int lane,
+                                          float *__restrict__ g2d) {
+  if (lane < 4) {
+    float *dst = g2d + 9 * (int64_t)s[kSlotRec];
+    float x0 = t[0], x1 = t[1];
+    int o0, o1, o2;
+    if (lane == 0) {
+      const float qa = __uint_as_float(s[2]), qb = __uint_as_float(s[3]),
+                  qc = __uint_as_float(s[4]);
+      x0 = kLn2 * (2.0f * qa * t[0] + qb * t[1]);
+      x1 = kLn2 * (qb * t[0] + 2.0f * qc * t[1]);
+    }
+    if (lane == 1) x0 = t[0] * __uint_as_float(s[kSlotInvO]);
+    o0 = lane == 0 ? 0 : lane == 1 ? 5 : lane == 2 ? 3 : 8;
+    o1 = lane == 0 ? 1 : lane == 1 ? 6 : 4;
+    o2 = lane == 0 ? 2 : 7;
+    unsafeAtomicAdd(dst + o0, x0);
+    if (lane < 3) unsafeAtomicAdd(dst + o1, x1);
+    if (lane < 2) unsafeAtomicAdd(dst + o2, t[2]);
+  }
 }
 
 // Triangle fragment of the walk for one pixel (a fixed occluder: it passes
@@ -144,34 +173,121 @@ __device__ __forceinline__ void tri_bwd(const uint32_t *s, int pos, double rlx, 
   if (!(pos < q.last && tri_eval(s, rlx, rly, direct, e, o) > 0)) return;
   float cr, cg, cbl;
   tri_colour(s, e, cr, cg, cbl);
+  const float cd = fmaf(cr, q.dC0, fmaf(cg, q.dC1, cbl * q.dC2));
   const float alpha = __uint_as_float(s[30]);
   if (direct) {
     q.Tr = (pos == q.last - 1) ? q.Tterm : q.Tr / (1.0f - alpha);
-    q.B0 = fmaf(alpha, cr - q.B0, q.B0);
-    q.B1 = fmaf(alpha, cg - q.B1, q.B1);
-    q.B2 = fmaf(alpha, cbl - q.B2, q.B2);
+    q.Bd = fmaf(alpha, cd - q.Bd, q.Bd);
     return;
   }
-  if (!q.in_ent) {
-    q.in_ent = true;
-    q.term_ent = (pos == q.last - 1);
-    q.s0[0] = q.s1[0] = q.s2[0] = q.s3[0] = q.B0;
-    q.s0[1] = q.s1[1] = q.s2[1] = q.s3[1] = q.B1;
-    q.s0[2] = q.s1[2] = q.s2[2] = q.s3[2] = q.B2;
+  if (q.ent == __builtin_inff()) {
+    // the walk enters an entity at its last triangle
+    q.ent = (pos == q.last - 1) ? -1.0f : q.Tr;
+    q.sd0 = q.sd1 = q.sd2 = q.sd3 = q.Bd;
     q.p0 = q.p1 = q.p2 = q.p3 = 1.0f;
   }
   const float a0 = o[0] * alpha, a1 = o[1] * alpha, a2 = o[2] * alpha, a3 = o[3] * alpha;
-  q.s0[0] = fmaf(a0, cr - q.s0[0], q.s0[0]); q.s0[1] = fmaf(a0, cg - q.s0[1], q.s0[1]); q.s0[2] = fmaf(a0, cbl - q.s0[2], q.s0[2]);
-  q.s1[0] = fmaf(a1, cr - q.s1[0], q.s1[0]); q.s1[1] = fmaf(a1, cg - q.s1[1], q.s1[1]); q.s1[2] = fmaf(a1, cbl - q.s1[2], q.s1[2]);
-  q.s2[0] = fmaf(a2, cr - q.s2[0], q.s2[0]); q.s2[1] = fmaf(a2, cg - q.s2[1], q.s2[1]); q.s2[2] = fmaf(a2, cbl - q.s2[2], q.s2[2]);
-  q.s3[0] = fmaf(a3, cr - q.s3[0], q.s3[0]); q.s3[1] = fmaf(a3, cg - q.s3[1], q.s3[1]); q.s3[2] = fmaf(a3, cbl - q.s3[2], q.s3[2]);
+  q.sd0 = fmaf(a0, cd - q.sd0, q.sd0);
+  q.sd1 = fmaf(a1, cd - q.sd1, q.sd1);
+  q.sd2 = fmaf(a2, cd - q.sd2, q.sd2);
+  q.sd3 = fmaf(a3, cd - q.sd3, q.sd3);
   q.p0 *= 1.0f - a0; q.p1 *= 1.0f - a1; q.p2 *= 1.0f - a2; q.p3 *= 1.0f - a3;
+  // in front of the entity so far: colour behind B = mean_j s^j, T_in = T / tau
+  q.Bd = 0.25f * ((q.sd0 + q.sd1) + (q.sd2 + q.sd3));
+  q.Tr = q.ent < 0.0f ? q.Tterm : q.ent / (0.25f * ((q.p0 + q.p1) + (q.p2 + q.p3)));
 }
 
-// One workgroup per tile; each thread walks PPT pixels of the tile (rows
-// ly and ly + TH/PPT), so one set of wave sums serves 64 x PPT pixels.
-template <int TW, int TH, int PPT>
-__global__ __launch_bounds__(TW *TH / PPT) void blend_backward_kernel(
+// ---- heaviest-first tile order -------------------------------------------
+// A tile's backward walks its list down from the largest last-blended
+// position of its pixels, one wave per tile, so that position is the
+// tile's critical path.  Tiles are launched in decreasing order of it
+// (buckets of a quarter octave), so the longest walks start first and the
+// short ones fill in behind them instead of leaving the long ones to run
+// last.
+constexpr int kBwdBuckets = 128;
+// parts per 256-pixel tile (1: four pixels per lane; 2: two)
+constexpr int kBwdSplit16 = 1;
+
+__device__ __forceinline__ int walk_bucket(uint32_t k) {
+  if (k < 4) return (int)k;
+  const int e = 31 - __clz(k);                     // >= 2
+  return min(kBwdBuckets - 1, 4 * (e - 1) + (int)((k >> (e - 2)) & 3u));
+}
+
+// key[tile] = the largest last-blended position of its pixels (clamped to
+// its list, as the walk clamps it); one wave per tile.
+template <int TW, int TH>
+__global__ __launch_bounds__(64) void walk_key_kernel(const ViewParams *__restrict__ views, int V,
+                                                     const uint2 *__restrict__ ranges,
+                                                     const int32_t *__restrict__ ncontrib,
+                                                     uint32_t *__restrict__ key) {
+  const uint32_t tile = blockIdx.x;
+  const int v = find_view(views, V, tile);
+  const ViewParams &vp = views[v];
+  const uint32_t lt = tile - vp.tile_base;
+  const int tx = (int)(lt % (uint32_t)vp.ntx), ty = (int)(lt / (uint32_t)vp.ntx);
+  const uint2 rg = ranges[tile];
+  const int count = (int)(rg.y - rg.x);
+  int m = 0;
+  for (int i = threadIdx.x; i < TW * TH; i += 64) {
+    const int px = tx * TW + i % TW, py = ty * TH + i / TW;
+    if (px < vp.W && py < vp.H)
+      m = max(m, min(max(ncontrib[vp.pix_base + (int64_t)py * vp.W + px], 0), count));
+  }
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+  if (threadIdx.x == 0) key[tile] = (uint32_t)m;
+}
+
+__global__ void walk_count_kernel(const uint32_t *__restrict__ key, uint32_t n,
+                                  uint32_t *__restrict__ cnt) {
+  __shared__ uint32_t h[kBwdBuckets];
+  if (threadIdx.x < kBwdBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) atomicAdd(&h[walk_bucket(key[t])], 1u);
+  __syncthreads();
+  if (threadIdx.x < kBwdBuckets && h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
+}
+
+// cursors in descending bucket order (heaviest first); one wave
+__global__ void walk_scan_kernel(uint32_t *__restrict__ cnt) {
+  if (threadIdx.x != 0) return;
+  uint32_t run = 0;
+  for (int b = kBwdBuckets - 1; b >= 0; --b) {
+    const uint32_t c = cnt[b];
+    cnt[b] = run;
+    run += c;
+  }
+}
+
+__global__ void walk_scatter_kernel(const uint32_t *__restrict__ key, uint32_t n,
+                                    uint32_t *__restrict__ cursor, uint32_t *__restrict__ order) {
+  __shared__ uint32_t h[kBwdBuckets], base[kBwdBuckets];
+  if (threadIdx.x < kBwdBuckets) h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+  int b = 0;
+  uint32_t local = 0;
+  if (t < n) {
+    b = walk_bucket(key[t]);
+    local = atomicAdd(&h[b], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kBwdBuckets && h[threadIdx.x])
+    base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]);
+  __syncthreads();
+  if (t < n) order[base[b] + local] = t;
+}
+
+// One workgroup of one wave per part of a tile (tiles taken heaviest
+// first, each split into SPLIT parts of TH / SPLIT rows); each lane walks
+// PPT pixels of its part (rows ly, ly + R, ... with R = TH / SPLIT / PPT),
+// so one set of wave sums serves all of a part's pixels and no sums cross
+// waves.
+template <int TW, int TH, int SPLIT>
+__global__ __launch_bounds__(64) void blend_backward_kernel(
+    const uint32_t *__restrict__ order,
     const ViewParams *__restrict__ views, int V, int N, int T, int mode, int batch,
     float bg0, float bg1, float bg2, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1,
@@ -179,22 +295,21 @@ __global__ __launch_bounds__(TW *TH / PPT) void blend_backward_kernel(
     const TriRec *__restrict__ trec, const float *__restrict__ dLdimg,
     const float *__restrict__ Tfin, const int32_t *__restrict__ ncontrib,
     const float *__restrict__ Tent, float *__restrict__ g2d) {
-  constexpr int NTH = TW * TH / PPT;                      // threads
-  constexpr int NW = NTH / 64;                            // waves
-  static_assert(NTH % 64 == 0, "whole waves");
-  extern __shared__ uint32_t smem[];
-  uint32_t *slots = smem;                                 // batch * kSlotWords
-  float *gl = (float *)(smem + batch * kSlotWords);       // [wave][batch][9] partial sums
-  __shared__ int smax;
+  constexpr int ROWS = TH / SPLIT;                        // rows of a part
+  constexpr int PPT = TW * ROWS / 64;                     // pixels per lane
+  constexpr int RSTEP = ROWS / PPT;                       // row step of a lane's pixels
+  static_assert(TW * ROWS == 64 * PPT && ROWS % PPT == 0, "one wave per part");
+  extern __shared__ uint32_t slots[];                     // batch * kSlotWords
   const uint32_t *vals = fi->sorted_in ? v1 : v0;
 
-  const uint32_t tile = blockIdx.x;
+  const uint32_t tile = order[blockIdx.x / SPLIT];
+  const int part = (int)(blockIdx.x % SPLIT);
   const int v = find_view(views, V, tile);
   const ViewParams &vp = views[v];
   const uint32_t lt = tile - vp.tile_base;
   const int tx = (int)(lt % (uint32_t)vp.ntx), ty = (int)(lt / (uint32_t)vp.ntx);
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int lx = tid % TW, ly0 = tid / TW;
+  const int lane = threadIdx.x;
+  const int lx = lane % TW, ly0 = part * ROWS + lane / TW;
   const int px = tx * TW + lx;
   const float pcx = (float)px + 0.5f;
   const int64_t P0x = (int64_t)(tx * TW) * kSubpx + kSubpx / 2;
@@ -207,15 +322,11 @@ __global__ __launch_bounds__(TW *TH / PPT) void blend_backward_kernel(
   const int count = (int)(rg.y - rg.x);
 
   PixBwd q[PPT];
-  float pcy[PPT];
-  double rly[PPT];
   int my_last = 0;
 #pragma unroll
   for (int p = 0; p < PPT; ++p) {
-    const int ly = ly0 + p * (TH / PPT);
+    const int ly = ly0 + p * RSTEP;
     const int py = ty * TH + ly;
-    pcy[p] = (float)py + 0.5f;
-    rly[p] = (double)(ly * kSubpx);
     q[p].last = 0;
     q[p].Tr = 1.0f; q[p].Tterm = 1.0f; q[p].dC0 = 0.f; q[p].dC1 = 0.f; q[p].dC2 = 0.f;
     if (px < vp.W && py < vp.H) {
@@ -230,23 +341,20 @@ __global__ __launch_bounds__(TW *TH / PPT) void blend_backward_kernel(
       q[p].dC1 = d[HW + pix];
       q[p].dC2 = d[2 * HW + pix];
     }
-    q[p].B0 = bg0; q[p].B1 = bg1; q[p].B2 = bg2;
-    q[p].in_ent = false; q[p].term_ent = false;
+    q[p].Bd = fmaf(bg0, q[p].dC0, fmaf(bg1, q[p].dC1, bg2 * q[p].dC2));
+    q[p].ent = __builtin_inff();
+    q[p].sd0 = q[p].sd1 = q[p].sd2 = q[p].sd3 = 0.f;
     q[p].p0 = q[p].p1 = q[p].p2 = q[p].p3 = 1.f;
     my_last = max(my_last, q[p].last);
   }
-  if (tid == 0) smax = 0;
-  __syncthreads();
-  atomicMax(&smax, my_last);
-  __syncthreads();
-  const int max_last = smax;
-  float *const glw = gl + (tid >> 6) * batch * 9;     // this wave's partial sums
+  int max_last = my_last;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) max_last = max(max_last, __shfl_xor(max_last, o, 64));
 
   for (int bend = max_last; bend > 0; bend -= batch) {
     const int bstart = max(0, bend - batch);
     const int bn = bend - bstart;
-    int tri_here = 0;
-    for (int f = tid; f < bn; f += NTH) {
+    for (int f = lane; f < bn; f += 64) {
       uint32_t *s = slots + f * kSlotWords;
       const int64_t local = (int64_t)vals[rg.x + bstart + f] - rbase;
       if (local < N) {
@@ -254,43 +362,10 @@ __global__ __launch_bounds__(TW *TH / PPT) void blend_backward_kernel(
         stage_gauss(s, grec[rec], rec);
       } else {
         stage_tri(s, trec[(int64_t)v * T + (local - N)], P0x, P0y);
-        tri_here = 1;
-      }
-      for (int k = 0; k < NW * 9; ++k) gl[(k / 9) * batch * 9 + f * 9 + k % 9] = 0.0f;
-    }
-    const bool any_tri = __syncthreads_or(tri_here) != 0;
-
-    int f = bn - 1;
-    if (!any_tri) {
-      // Gaussians only: two fragments a step (their alphas are independent;
-      // each pixel's state updates run in list order) and 18 wave sums
-      // together, over the thread's PPT pixels
-      for (; f >= 1; f -= 2) {
-        if (!__any(bstart + f - 1 < my_last)) continue;
-        float g[18];
-        bool c = false;
-#pragma unroll
-        for (int p = 0; p < PPT; ++p) {
-          float h[18];
-          c |= gauss_bwd(slots + f * kSlotWords, bstart + f, pcx, pcy[p], q[p], h);
-          c |= gauss_bwd(slots + (f - 1) * kSlotWords, bstart + f - 1, pcx, pcy[p], q[p], h + 9);
-#pragma unroll
-          for (int k = 0; k < 18; ++k) g[k] = p == 0 ? h[k] : g[k] + h[k];
-        }
-        if (!__any(c)) continue;
-        wave_totals(g);
-        if (lane == 63) {
-          finish_terms(slots + f * kSlotWords, g);
-          finish_terms(slots + (f - 1) * kSlotWords, g + 9);
-#pragma unroll
-          for (int k = 0; k < 9; ++k) {
-            glw[f * 9 + k] = g[k];
-            glw[(f - 1) * 9 + k] = g[9 + k];
-          }
-        }
       }
     }
-    for (; f >= 0; --f) {
+    __syncthreads();
+    for (int f = bn - 1; f >= 0; --f) {
       const uint32_t *s = slots + f * kSlotWords;
       const int pos = bstart + f;
       if (!__any(pos < my_last)) continue;
@@ -299,34 +374,20 @@ __global__ __launch_bounds__(TW *TH / PPT) void blend_backward_kernel(
         bool c = false;
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
+          const float pcy = (float)(ty * TH + ly0 + p * RSTEP) + 0.5f;
           float h[9];
-          c |= gauss_bwd(s, pos, pcx, pcy[p], q[p], h);
+          c |= gauss_bwd(s, pos, pcx, pcy, q[p], h);
 #pragma unroll
           for (int k = 0; k < 9; ++k) g[k] = p == 0 ? h[k] : g[k] + h[k];
         }
         if (!__any(c)) continue;     // no lane of the wave blends it
-        wave_totals(g);
-        if (lane == 63) {
-          finish_terms(s, g);
-#pragma unroll
-          for (int k = 0; k < 9; ++k) glw[f * 9 + k] = g[k];
-        }
+        float t[3];
+        wave_sums9(g, t, (lane & 1) != 0, (lane & 2) != 0);
+        add_sums9(s, t, lane, g2d);
       } else {
 #pragma unroll
-        for (int p = 0; p < PPT; ++p) tri_bwd(s, pos, rlx, rly[p], direct, q[p]);
-      }
-    }
-    __syncthreads();
-    for (int f = tid; f < bn; f += NTH) {
-      const uint32_t *s = slots + f * kSlotWords;
-      if ((s[31] & 1u) != 0u) continue;
-      float *dst = g2d + 9 * (int64_t)s[kSlotRec];
-#pragma unroll
-      for (int k = 0; k < 9; ++k) {
-        float r = 0.0f;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) r += gl[w * batch * 9 + f * 9 + k];
-        if (r != 0.0f) unsafeAtomicAdd(dst + k, r);
+        for (int p = 0; p < PPT; ++p)
+          tri_bwd(s, pos, rlx, (double)((ly0 + p * RSTEP) * kSubpx), direct, q[p]);
       }
     }
     __syncthreads();
@@ -602,16 +663,35 @@ __global__ __launch_bounds__(128) void project_backward_kernel(
   for (int k = 0; k < nc * 3; ++k) put(&d_sh[(int64_t)i * nc * 3 + k], dshv[k]);
 }
 
-template <int TW, int TH, int PPT>
+}  // namespace
+
+hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v);
+
+namespace {
+
+template <int TW, int TH, int SPLIT>
 hipError_t launch_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int32_t *nc, const float *Te) {
-  // the backward's own LDS batch (fragments and per-wave partial sums), at
-  // most 128 fragments: 128 x (32 + 9 x waves) words
-  constexpr int NW = TW * TH / PPT / 64;
-  const int batch = std::min(c->frag_batch, 128);
-  const size_t lds = (size_t)batch * (kSlotWords + 9 * NW) * sizeof(uint32_t);
+  // the backward's own LDS batch of staged fragments, at most 64 (8 KB per
+  // one-wave workgroup, so LDS does not limit the waves per CU)
+  const int batch = std::min(c->frag_batch, 64);
+  const size_t lds = (size_t)batch * kSlotWords * sizeof(uint32_t);
+  const uint32_t nt = (uint32_t)c->n_tiles;
+  uint32_t *cnt = (uint32_t *)c->bwd_order.p;
+  uint32_t *key = cnt + kBwdBuckets;
+  uint32_t *order = key + nt;
   ScopedTimer t(c, K_BLEND_BWD);
-  hipLaunchKernelGGL((blend_backward_kernel<TW, TH, PPT>), dim3((unsigned)c->n_tiles),
-                     dim3(TW * TH / PPT), lds, c->stream, c->cur_views, c->V, c->N, c->T, c->mode,
+  hipError_t e = launch_fill_u32(c, cnt, kBwdBuckets, 0u);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((walk_key_kernel<TW, TH>), dim3(nt), dim3(64), 0, c->stream, c->cur_views,
+                     c->V, (const uint2 *)c->ranges.p, nc, key);
+  hipLaunchKernelGGL(walk_count_kernel, dim3(ceil_div(nt, 256)), dim3(256), 0, c->stream, key, nt,
+                     cnt);
+  hipLaunchKernelGGL(walk_scan_kernel, dim3(1), dim3(64), 0, c->stream, cnt);
+  hipLaunchKernelGGL(walk_scatter_kernel, dim3(ceil_div(nt, 256)), dim3(256), 0, c->stream, key,
+                     nt, cnt, order);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL((blend_backward_kernel<TW, TH, SPLIT>), dim3(nt * SPLIT),
+                     dim3(64), lds, c->stream, order, c->cur_views, c->V, c->N, c->T, c->mode,
                      batch, c->bg[0], c->bg[1], c->bg[2], (const uint2 *)c->ranges.p,
                      (const uint32_t *)c->v0.p, (const uint32_t *)c->v1.p,
                      (const FrameInfo *)c->finfo.p, (const GaussRec *)c->grec.p,
@@ -631,9 +711,9 @@ hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32
   hipError_t e = launch_fill_u32(c, (uint32_t *)c->g2d.p, 9 * (int64_t)c->V * c->N, 0u);
   if (e != hipSuccess) return e;
   if (c->n_tiles > 0) {
-    if (c->tile_w == 16 && c->tile_h == 16) e = launch_bwd_tw<16, 16, 2>(c, dL, Tf, nc, Te);
+    if (c->tile_w == 16 && c->tile_h == 16) e = launch_bwd_tw<16, 16, kBwdSplit16>(c, dL, Tf, nc, Te);
     else if (c->tile_w == 8 && c->tile_h == 8) e = launch_bwd_tw<8, 8, 1>(c, dL, Tf, nc, Te);
-    else e = launch_bwd_tw<32, 8, 2>(c, dL, Tf, nc, Te);
+    else e = launch_bwd_tw<32, 8, kBwdSplit16>(c, dL, Tf, nc, Te);
     if (e != hipSuccess) return e;
   }
   if (c->N == 0) return hipSuccess;

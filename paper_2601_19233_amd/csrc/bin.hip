@@ -990,7 +990,7 @@ hipError_t launch_st_bin(Ctx *c) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   {
-    ScopedTimer t(c, K_TILE_COUNT);
+    ScopedTimer t(c, K_ST_MASK);
     StEmitArgs a;
     a.views = c->cur_views;
     a.per_view = c->N + c->T;

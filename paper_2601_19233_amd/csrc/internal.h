@@ -75,7 +75,7 @@ struct __align__(16) TriRec {
 enum KernelId {
   K_VERTEX_FRAMES = 0, K_TRANSFER, K_PROJECT, K_TRIANGLES, K_SCAN, K_EMIT, K_SORT_UPSWEEP,
   K_SORT_SCAN, K_SORT_DOWNSWEEP, K_RANGES, K_BLEND, K_BLEND_BWD, K_PROJECT_BWD, K_DEPTH_SORT,
-  K_TILE_COUNT, K_TILE_SCATTER, K_COUNT
+  K_TILE_COUNT, K_TILE_SCATTER, K_ST_MASK, K_COUNT
 };
 
 struct Prof {
@@ -158,6 +158,7 @@ struct Ctx {
   bool minmax_ready = false;   // reset once; the bin stage resets as it folds
   DevBuf finfo;        // FrameInfo (device)
   DevBuf tile_order;   // 64 bucket counters + n_tiles tile ids (persistent blend)
+  DevBuf bwd_order;    // 128 bucket counters + n_tiles keys + n_tiles tile ids (backward)
   DevBuf pair_count;   // 4 uint64: blend work counters (measurement)
   DevBuf view_sums;    // V uint64: duplicates per view
   hipGraph_t graph = nullptr;

@@ -12,7 +12,8 @@
 // face_rows_kernel: each face's three vertex rows side by side (144 B), so a
 //   bound point reads one row that spans exactly two 128-B cache lines
 //   (rows start at multiples of 16 B) instead of a face lookup followed by
-//   three vertex rows in three places.
+//   three vertex rows in three places; row nF is all zeros (what an unbound
+//   corner reads).
 // transfer kernels (FP32): Eq. 12 at each of the K bound points, Eq. 13
 //   averages: R' = exp(mean r_i), S' = mean S_i, A = R'S',
 //   Sigma' = A Sigma A^T, mu' = mu + mean Delta_i (pinned order),
@@ -58,7 +59,7 @@ void *noalloc_scratch(int device) {
 
 size_t noalloc_transfer_bytes(int64_t nV, int64_t nF, bool vertex_table_in_scratch) {
   const size_t vt = vertex_table_in_scratch ? (size_t)(48 * nV + 255) / 256 * 256 : 0;
-  return vt + (size_t)144 * (size_t)nF;
+  return vt + (size_t)144 * ((size_t)nF + 1);   // face rows and the zero row
 }
 
 namespace {
@@ -248,11 +249,15 @@ __global__ void vertex_frames_kernel(int nV, const float *__restrict__ Vr,
 }
 
 // One thread per (face, float4 of the face row): row f = rows of vertices
-// faces[3f], faces[3f+1], faces[3f+2], 3 float4 each.
+// faces[3f], faces[3f+1], faces[3f+2], 3 float4 each; row nF zeros.
 __global__ void face_rows_kernel(int nF, const int32_t *__restrict__ faces,
                                  const float4 *__restrict__ vtab, float4 *__restrict__ ftab) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 9 * (int64_t)nF) return;
+  if (t >= 9 * ((int64_t)nF + 1)) return;
+  if (t >= 9 * (int64_t)nF) {
+    ftab[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return;
+  }
   const int64_t f = t / 9;
   const int j = (int)(t - 9 * f);
   const int v = faces[3 * f + j / 3];
@@ -390,13 +395,14 @@ __device__ __forceinline__ void finish_gaussian(int i, float3 dsum, const float 
 // A lane finally applies Eq. 13 to its own Gaussian.
 constexpr int kTrRows = 64;   // Gaussians per wave (one wave per block)
 
-__device__ __forceinline__ void gather_rows(const f4v *__restrict__ ftab, int face, int lane,
+__device__ __forceinline__ void gather_rows(const f4v *__restrict__ ftab, int nF, int face, int lane,
                                             f4v (&buf)[9]) {
 #pragma unroll
   for (int m = 0; m < 9; ++m) {
     const int s = 64 * m + lane;
     const int row = s / 9;
-    const int f = __shfl(face, row, 64);
+    int f = __shfl(face, row, 64);
+    f = (unsigned)f < (unsigned)nF ? f : nF;      // unbound: the zero row
     buf[m] = ftab[9 * (int64_t)f + (s - 9 * row)];
   }
 }
@@ -418,12 +424,13 @@ __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) vo
     float *__restrict__ means_out, float *__restrict__ quats_out, float *__restrict__ cov3d_out,
     float *__restrict__ xform_out) {
   __shared__ f4v rows[kTrRows * 9];
+  __shared__ int n_bound[kTrRows];
   const f4v *__restrict__ ftab4 = reinterpret_cast<const f4v *>(ftab);
   const int lane = threadIdx.x;
   const int i = blockIdx.x * kTrRows + lane;
   const bool valid = i < N;
-  // this lane's K bindings (face 0 stands in past the end and for unbound
-  // corners: its row is read and the result dropped)
+  // this lane's K bindings (face 0 stands in past the end: its row is read
+  // and the result dropped)
   int face[K];
   float bu[K], bv[K];
   if constexpr (K == 8) {
@@ -455,39 +462,36 @@ __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) vo
       bv[k] = valid ? bind_bary[2 * (K * (int64_t)i + k) + 1] : 0.f;
     }
   }
-  // bit k: corner k is bound to a face of the proxy
-  unsigned bmask = 0;
+  // an unbound corner (face outside [0, nF)) gathers the all-zero row nF:
+  // with finite barycentrics its terms are exact zeros, which leave every
+  // sum, the pinned mean offset included, as it is.  The count of bound
+  // corners waits in LDS for Eq. 13 (registers are short in the rounds).
+  {
+    int kb = 0;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const bool b = (unsigned)face[k] < (unsigned)nF;
-    bmask |= b ? 1u << k : 0u;
-    face[k] = b ? face[k] : 0;
+    for (int k = 0; k < K; ++k) kb += (unsigned)face[k] < (unsigned)nF ? 1 : 0;
+    n_bound[lane] = kb;
   }
-  const int kb = __builtin_popcount(bmask);
-  bool started = false;
   float3 ds = make_float3(0.f, 0.f, 0.f);
   float rs[3] = {0.f, 0.f, 0.f}, Ss[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   f4v buf[9];
-  gather_rows(ftab4, face[0], lane, buf);
+  gather_rows(ftab4, nF, face[0], lane, buf);
   // one round per bound point; the bindings shift down one place per round,
   // so every index below is static
   auto round = [&](bool prefetch) {
 #pragma unroll
     for (int m = 0; m < 9; ++m) rows[64 * m + lane] = buf[m];
     __syncthreads();
-    if (prefetch) gather_rows(ftab4, face[K > 1 ? 1 : 0], lane, buf);
+    if (prefetch) gather_rows(ftab4, nF, face[K > 1 ? 1 : 0], lane, buf);
     const f4v *row = rows + 9 * lane;
     const f4v a0 = row[0], a1 = row[1], a2 = row[2];
     const f4v b0 = row[3], b1 = row[4], b2 = row[5];
     const f4v c0 = row[6], c1 = row[7], c2 = row[8];
-    // an unbound corner adds nothing: zero weights (its face-0 row is finite)
-    const bool b = bmask & 1u;
-    const float u = b ? bu[0] : 0.f, v = b ? bv[0] : 0.f, w = b ? pinned_w(u, v) : 0.f;
+    const float u = bu[0], v = bv[0], w = pinned_w(u, v);
     const float3 di = interp_delta(u, v, w, a0, b0, c0);
-    // pinned order: the first bound corner's offset, then the next ones added
-    ds = b ? (started ? add3(ds, di) : di) : ds;
-    started = started || b;
-    bmask >>= 1;
+    // pinned order: the bound corners' offsets added in corner order (0 + x
+    // and x + 0 are exact, so the zero start and unbound corners change nothing)
+    ds = add3(ds, di);
     rs[0] += u * a0.w + v * b0.w + w * c0.w;
     rs[1] += u * a1.x + v * b1.x + w * c1.x;
     rs[2] += u * a1.y + v * b1.y + w * c1.y;
@@ -510,6 +514,7 @@ __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) vo
     for (int k = 0; k + 1 < K; ++k) round(true);
   }
   round(false);
+  const int kb = n_bound[lane];
   if (valid)
     finish_gaussian(i, ds, rs, Ss, inv_bound(kb), kb > 0, means, quats, scales, means_out,
                     quats_out, cov3d_out, xform_out);
@@ -532,7 +537,7 @@ static hipError_t transfer_launches(Ctx *c, const float *V_def, int32_t N,
                        (const int32_t *)c->vf_ptr.p, (const int32_t *)c->vf_idx.p, vtab);
     e = hipGetLastError();
     if (e == hipSuccess && N > 0) {
-      hipLaunchKernelGGL(face_rows_kernel, dim3((unsigned)ceil_div(9 * (int64_t)c->nF, 256)),
+      hipLaunchKernelGGL(face_rows_kernel, dim3((unsigned)ceil_div(9 * ((int64_t)c->nF + 1), 256)),
                          dim3(256), 0, c->stream, c->nF, (const int32_t *)c->faces.p,
                          (const float4 *)vtab, ftab);
       e = hipGetLastError();
