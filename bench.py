@@ -49,6 +49,14 @@ VALU_PEAK_GOPS = 256 * 4 * 16 * 2.4
 # tests when the pixel straddles an edge, colour and the entity update).
 OPS_PER_GAUSS_PAIR = 20
 OPS_PER_TRI_PAIR = 60
+# ... and per (pixel, fragment) pair the backward walks: a Gaussian costs 51
+# (alpha again 14; T in front of it 3: 1 - alpha, reciprocal, product;
+# dL/dalpha 7; the colour behind it 6; colour terms 4; power and opacity
+# terms 8; the 9 terms added into the tile's sums 9), a triangle 96 (its
+# coverage and colour as in the forward, 60, and the reverse recursion of
+# the four sub-samples' colour and transmittance, 9 each).
+OPS_PER_GAUSS_PAIR_BWD = 51
+OPS_PER_TRI_PAIR_BWD = 96
 
 
 def log(msg):
@@ -84,12 +92,41 @@ def measured_traffic():
     return out
 
 
-def cpu_baseline(scene, budget_pixels=1200, seed=0):
-    """Time the CPU FP64 oracle on a bounded sample of the same frame."""
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+_CB = {}
+
+
+def _cb_pixels(chunk):
+    fr = _CB["frame"]
+    for x, y in chunk:
+        fr.pixel(x, y)
+    return len(chunk)
+
+
+def cpu_baseline(scene, single_pixels=300, per_worker=120, seed=0):
+    """Time the CPU FP64 oracle on a bounded sample of the same frame: the
+    frame set-up (transfer and projection of every primitive, one thread),
+    then pixels blended by one thread and by one process per host core (at
+    most 16, the host share of one GPU), extrapolated to the whole frame.
+    Runs before the GPU is initialised, so the worker processes are plain
+    forks of a CPU-only process."""
+    import multiprocessing as mp
     from threadpoolctl import threadpool_limits
     from oracle import render as OR
     from oracle import transfer as OT
     cam = scene.cams[0]
+    workers = max(1, min(16, os.cpu_count() or 1))
+    rng = np.random.default_rng(seed)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         ot = OT.transfer(scene.proxy.V_rest, scene.proxy.faces, scene.proxy.V_def, scene.means,
@@ -97,19 +134,36 @@ def cpu_baseline(scene, budget_pixels=1200, seed=0):
         fr = OR.Frame(cam, ot["means"], scene.opacity, scene.sh, scene.sh_degree, scene.tri_xyz,
                       scene.tri_rgb, scene.tri_alpha, cov3d=ot["cov3d"])
         t_setup = time.perf_counter() - t0
-        rng = np.random.default_rng(seed)
-        px = rng.integers(0, cam.width, budget_pixels)
-        py = rng.integers(0, cam.height, budget_pixels)
+        px = list(zip(rng.integers(0, cam.width, single_pixels).tolist(),
+                      rng.integers(0, cam.height, single_pixels).tolist()))
         t1 = time.perf_counter()
-        for x, y in zip(px.tolist(), py.tolist()):
+        for x, y in px:
             fr.pixel(x, y)
-        t_pix = (time.perf_counter() - t1) / budget_pixels
+        t_pix1 = (time.perf_counter() - t1) / single_pixels
     npix = cam.width * cam.height
-    full = t_setup + t_pix * npix
-    return {"value": npix / full / 1e6, "unit": "Mpixels/s", "cores": 1, "kind": "oracle",
-            "sample": f"frame set-up (transfer + projection of all primitives, {t_setup:.1f} s) "
-                      f"plus {budget_pixels} uniformly sampled pixels ({t_pix * 1e3:.1f} ms/pixel), "
-                      f"extrapolated to {cam.width}x{cam.height}: {full:.0f} s per frame"}
+    full1 = t_setup + t_pix1 * npix
+    n_par = workers * per_worker
+    pxp = list(zip(rng.integers(0, cam.width, n_par).tolist(),
+                   rng.integers(0, cam.height, n_par).tolist()))
+    _CB["frame"] = fr
+    ctx = mp.get_context("fork")
+    with threadpool_limits(limits=1):
+        with ctx.Pool(workers) as pool:
+            pool.map(_cb_pixels, [pxp[:workers]], chunksize=1)      # start the workers
+            t2 = time.perf_counter()
+            done = sum(pool.map(_cb_pixels, [pxp[i::workers] for i in range(workers)], chunksize=1))
+            t_parw = time.perf_counter() - t2
+    _CB.clear()
+    t_pixp = t_parw / done
+    full = t_setup + t_pixp * npix
+    return {"value": npix / full / 1e6, "unit": "Mpixels/s", "cores": workers, "kind": "oracle",
+            "cpu": cpu_model(), "host_cpus": os.cpu_count(),
+            "single_thread_value": npix / full1 / 1e6,
+            "sample": f"frame set-up (transfer + projection of all primitives, one thread, "
+                      f"{t_setup:.1f} s) plus {done} uniformly sampled pixels blended by {workers} "
+                      f"processes ({t_parw:.1f} s wall, {t_pixp * 1e3:.2f} ms/pixel), extrapolated "
+                      f"to {cam.width}x{cam.height}: {full:.0f} s per frame; one thread: "
+                      f"{single_pixels} pixels at {t_pix1 * 1e3:.1f} ms/pixel, {full1:.0f} s per frame"}
 
 
 def device_scene(s, dev):
@@ -137,6 +191,71 @@ def timed(fn, steps):
         fn()
     torch.cuda.synchronize()
     return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def algorithmic_bytes(r, scene, n_dup, n_rec, views=1):
+    """Algorithmic HBM bytes per launch of the bandwidth-bound kernels (n1
+    supertile entries; their ids are 16-bit while a frame has at most 2^16
+    supertiles)."""
+    n_st, n1 = r.query_bins()
+    kb = 2.0 if n_st <= 65536 else 4.0
+    out = {
+        # first level: per record its order, offsets and rectangle; per entry
+        # its supertile id and record id
+        "emit_keys": 28.0 * n_rec + (kb + 4.0) * n1,
+        "sort_downsweep": 2.0 * (kb + 12.0) * n1,  # read and write id, record id, mask
+        "sort_upsweep": kb * n1,                   # read the ids
+        # masks: per entry its supertile id, record id, rectangle and
+        # Gaussian record read, the mask written
+        "st_mask": (kb + 4.0 + 8.0 + 48.0 + 8.0) * n1,
+        # counts: the sorted masks read
+        "tile_count": 8.0 * n1,
+        # per entry its mask and record id; per duplicate one record id written
+        "tile_scatter": 12.0 * n1 + 4.0 * n_dup,
+        "project_gaussians": views * scene.N * (12 + 24 + 4 + 12 * (scene.sh_degree + 1) ** 2
+                                                + 4 + 8 + 8 + 48.0),
+    }
+    if scene.proxy is not None:
+        out["transfer"] = scene.N * (40.0 + 12.0 * scene.bind_face.shape[1] + 88.0)
+    return out, n1
+
+
+def kernel_rooflines(prof, algo_bytes, traffic=None, pairs=None, bpairs=None):
+    """Roofline entry per timed kernel: algorithmic work per launch over the
+    launch's average duration (the library's HIP events on its stream)."""
+    traffic = traffic or {}
+    per_launch = {k: v[1] / v[0] for k, v in prof.items()}
+
+    def one(k):
+        if k in algo_bytes:
+            ach = algo_bytes[k] / (per_launch[k] * 1e-3) / 1e9
+            return {"kernel": k, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic.get(k),
+                    "ms_per_launch": round(per_launch[k], 4)}
+        if k == "blend" and pairs is not None:
+            g, t = pairs["gauss"], pairs["tri"]
+            ops = OPS_PER_GAUSS_PAIR * g + OPS_PER_TRI_PAIR * t
+            ach = ops / (per_launch[k] * 1e-3) / 1e9
+            return {"kernel": k, "bound": "alu", "achieved": round(ach, 1), "peak": VALU_PEAK_GOPS,
+                    "unit": "Gop/s", "frac": round(ach / VALU_PEAK_GOPS, 4), "traffic": traffic.get(k),
+                    "ms_per_launch": round(per_launch[k], 4), "gauss_pairs": g, "tri_pairs": t,
+                    "wave_iters": pairs["wave_iters"], "staged_fragments": pairs["staged"],
+                    "lane_occupancy": round((g + t) / max(1, 64 * pairs["wave_iters"]), 4)}
+        if k == "blend_backward" and bpairs is not None:
+            g, t = bpairs["gauss"], bpairs["tri"]
+            ops = OPS_PER_GAUSS_PAIR_BWD * g + OPS_PER_TRI_PAIR_BWD * t
+            ach = ops / (per_launch[k] * 1e-3) / 1e9
+            return {"kernel": k, "bound": "alu", "achieved": round(ach, 1), "peak": VALU_PEAK_GOPS,
+                    "unit": "Gop/s", "frac": round(ach / VALU_PEAK_GOPS, 4), "traffic": traffic.get(k),
+                    "ms_per_launch": round(per_launch[k], 4), "gauss_pairs": g, "tri_pairs": t}
+        return None
+
+    out = {}
+    for k in prof:
+        e = one(k)
+        if e is not None:
+            out[k] = e
+    return out
 
 
 def run_batched(args):
@@ -240,6 +359,21 @@ def batched_leg(s, cams, name, args):
         if rb.overflowed():
             raise RuntimeError("batched step overflowed its reserved key capacity")
         key = "fwd_bwd" if bwd else "fwd"
+        if len(step.groups) == 1:
+            # the same step once more, eagerly, with the kernels timed (a
+            # captured graph cannot be), for the rooflines of this step
+            rb.set_profiling(True)
+            step._step()
+            prof = rb.profile()
+            rb.set_profiling(False)
+            n_dup_b, _, n_rec_b = rb.query()
+            ab, _ = algorithmic_bytes(rb, s, n_dup_b, n_rec_b, views=V)
+            pairs = rb.blend_pairs()
+            bp = rb.backward_pairs(step.out["n_contrib"]) if bwd else None
+            rl = kernel_rooflines(prof, ab, None, pairs, bp)
+            res[f"{key}_rooflines"] = {k: rl[k] for k in ("blend", "blend_backward", "tile_scatter",
+                                                         "transfer") if k in rl}
+            res[f"{key}_kernel_ms"] = {k: round(v[1], 4) for k, v in prof.items()}
         res[f"{key}_views_s"] = round(V / (ms * 1e-3), 2)
         res[f"{key}_mpix_s"] = round(V * W * H / (ms * 1e-3) / 1e6, 2)
         res[f"{key}_ms_per_step"] = round(ms, 3)
@@ -277,7 +411,20 @@ def run_uneven(args):
 
     ms_plain = timed(plain, steps)
     del rp
-    rb = Rasterizer("cuda:0", sh_degree=s.sh_degree, schedule=1, own_stream=True)
+    torch.cuda.empty_cache()
+    from paper_2601_19233_amd import autotune
+    # tuned on 8 views spread over the size range (one frame of them fits the
+    # key buffers at every tile shape); the step renders all 64
+    order = sorted(range(len(cams)), key=lambda v: cams[v].width * cams[v].height)
+    probe = [cams[order[i]] for i in np.linspace(0, len(cams) - 1, 8).astype(int)]
+    t0 = time.time()
+    best = autotune.tune(probe, sc, sh_degree=s.sh_degree, reps=2, batches=(32, 64, 128, 256),
+                         use_cache=False)
+    log(f"uneven autotune {best['tile']} batch {best['frag_batch']} schedule {best['schedule']} "
+        f"in {time.time() - t0:.1f} s")
+    torch.cuda.empty_cache()
+    rb = Rasterizer("cuda:0", sh_degree=s.sh_degree, tile=best["tile"], frag_batch=best["frag_batch"],
+                    schedule=best["schedule"], own_stream=True)
     step = BatchedStep(rb, cams, sc)
     step.prepare()
     ms = timed(step, steps)
@@ -287,6 +434,9 @@ def run_uneven(args):
            "plain_views_s": round(len(cams) / (ms_plain * 1e-3), 2),
            "batched_views_s": round(len(cams) / (ms * 1e-3), 2),
            "batched_mpix_s": round(npix / (ms * 1e-3) / 1e6, 2),
+           "tile": "%dx%d" % best["tile"], "frag_batch": best["frag_batch"],
+           "schedule": ["tile_grid", "persistent"][best["schedule"]],
+           "plain_config": "16x16 tiles, batch 128, one workgroup per tile, eager per-view calls",
            "groups": [list(g) for g in step.groups]}
     log(f"uneven: plain {ms_plain:.2f} ms, batched {ms:.2f} ms per {len(cams)}-view step")
     del step, rb
@@ -382,11 +532,21 @@ def main():
               f"exchange in the forward and one gradient all-reduce per step).")
         sys.exit(2)
 
+    from paper_2601_19233_amd import scenes
+    t0 = time.time()
+    scene = scenes.make_config(1, scale=args.scale, res_scale=args.res_scale)
+    cpu = None
+    if not args.no_cpu_baseline and not args.binding_only:
+        # before the GPU is initialised: the oracle's worker processes fork
+        # from a CPU-only process
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(scene)
+        log(f"cpu baseline: {cpu['value']:.3g} Mpixels/s on {cpu['cores']} processes")
+
     import torch
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
-    from paper_2601_19233_amd import scenes
     from paper_2601_19233_amd.render import Rasterizer
 
     if args.copy_calibration:
@@ -397,8 +557,6 @@ def main():
         del src, dst
         log("copy calibration: 268435456 bytes read, 268435456 bytes written")
 
-    t0 = time.time()
-    scene = scenes.make_config(1, scale=args.scale, res_scale=args.res_scale)
     if args.binding_only:
         print(json.dumps({"binding": run_binding(args, scene)}), flush=True)
         return
@@ -450,53 +608,13 @@ def main():
     fwd_mpix = npix / (ms * 1e-3) / 1e6
 
     stages = {k: round(v[1] / args.steps, 4) for k, v in prof.items()}
-    per_launch = {k: v[1] / v[0] for k, v in prof.items()}
     dominant = max(prof, key=lambda k: prof[k][1])
     bp = r.blend_pairs()
-    g_pairs, t_pairs = bp["gauss"], bp["tri"]
     log(f"blend work: {bp}")
-    # algorithmic HBM bytes per launch of the bandwidth-bound kernels
-    # (n1 supertile entries; their ids are 16-bit while a frame has at most
-    # 2^16 supertiles)
-    n_st, n1 = r.query_bins()
-    kb = 2.0 if n_st <= 65536 else 4.0
-    algo_bytes = {
-        # first level: per record its order, offsets and rectangle; per entry
-        # its supertile id and record id
-        "emit_keys": 28.0 * n_rec + (kb + 4.0) * n1,
-        "sort_downsweep": 2.0 * (kb + 12.0) * n1,  # read and write id, record id, mask
-        "sort_upsweep": kb * n1,                   # read the ids
-        # masks: per entry its supertile id, record id, rectangle, Gaussian
-        # record and the mask written; counts: the sorted masks read
-        "tile_count": (kb + 4.0 + 8.0 + 48.0 + 8.0 + 8.0) * n1,
-        # per entry its mask and record id; per duplicate one record id written
-        "tile_scatter": 12.0 * n1 + 4.0 * n_dup,
-        "transfer": scene.N * (40.0 + 12.0 * scene.bind_face.shape[1] + 88.0),
-        "project_gaussians": scene.N * (12 + 24 + 4 + 12 + 4 + 8 + 8 + 48.0),
-    }
+    algo_bytes, n1 = algorithmic_bytes(r, scene, n_dup, n_rec)
     traffic = measured_traffic() if (cam.width, cam.height, scene.N) == (1920, 1080, 1000000) else {}
-
-    def roofline(k):
-        if k in algo_bytes:
-            ach = algo_bytes[k] / (per_launch[k] * 1e-3) / 1e9
-            return {"kernel": k, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic.get(k),
-                    "ms_per_launch": round(per_launch[k], 4)}
-        if k == "blend":
-            ops = OPS_PER_GAUSS_PAIR * g_pairs + OPS_PER_TRI_PAIR * t_pairs
-            ach = ops / (per_launch[k] * 1e-3) / 1e9
-            return {"kernel": k, "bound": "alu", "achieved": round(ach, 1), "peak": VALU_PEAK_GOPS,
-                    "unit": "Gop/s", "frac": round(ach / VALU_PEAK_GOPS, 4), "traffic": traffic.get(k),
-                    "ms_per_launch": round(per_launch[k], 4), "gauss_pairs": g_pairs,
-                    "tri_pairs": t_pairs, "wave_iters": bp["wave_iters"],
-                    "staged_fragments": bp["staged"],
-                    "lane_occupancy": round((g_pairs + t_pairs) / max(1, 64 * bp["wave_iters"]), 4)}
-        return None
-
-    roof = roofline(dominant)
-    rooflines = {k: roofline(k) for k in ("tile_scatter", "tile_count", "sort_downsweep",
-                                          "sort_upsweep", "emit_keys", "blend", "transfer",
-                                          "project_gaussians") if k in prof}
+    rooflines = kernel_rooflines(prof, algo_bytes, traffic, pairs=bp)
+    roof = rooflines.get(dominant)
 
     # ---- forward + backward (plain, eager) ---------------------------------
     # L2 loss against the frame rendered from N(0, 0.01)-perturbed raw
@@ -521,6 +639,7 @@ def main():
         r.bin()
         r.sort()
         o = r.blend(want_state=True)
+        fwd_state["out"] = o
         torch.sub(o["image"], target, out=dL)
         dL.mul_(2.0)
         return r.backward(dL, o, dt["means"], scales, quats, sh, dt["xform"])
@@ -534,9 +653,20 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     ms_fb = e0.elapsed_time(e1) / args.steps
+    # the same steps again with the kernels timed, for the backward's roofline
+    r.set_profiling(True)
+    for _ in range(args.steps):
+        step_fb()
+    prof_fb = r.profile()
+    r.set_profiling(False)
+    bpairs = r.backward_pairs(fwd_state["out"]["n_contrib"])
+    log(f"backward work: {bpairs}")
+    rl_fb = kernel_rooflines(prof_fb, {}, traffic, pairs=None, bpairs=bpairs)
     fwd_bwd = {"mpix_s": round(npix / (ms_fb * 1e-3) / 1e6, 2), "ms_per_step": round(ms_fb, 4),
                "path": "plain forward + backward (eager), gradients to means/scales/quats/opacity/SH",
-               "loss": "L2 against the render of N(0, 0.01)-perturbed raw Gaussian parameters"}
+               "loss": "L2 against the render of N(0, 0.01)-perturbed raw Gaussian parameters",
+               "stages_ms": {k: round(v[1] / args.steps, 4) for k, v in prof_fb.items()},
+               "roofline": rl_fb.get("blend_backward")}
     log(f"fwd+bwd {ms_fb:.3f} ms/step")
 
     # ---- the same frame captured in one HIP graph ---------------------------
@@ -597,9 +727,8 @@ def main():
         "fwd_graph": fwd_graph, "fwd_bwd": fwd_bwd, "backward_800": bwd800, "batched": batched,
         "batched_1080p_x16_orbit": orbit, "batched_uneven": uneven, "binding": binding,
     }
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        out["cpu_baseline"] = cpu_baseline(scene)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

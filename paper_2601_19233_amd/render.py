@@ -381,6 +381,35 @@ class Rasterizer:
         return dict(gauss=int(pairs[0]), tri=int(pairs[1]), wave_iters=int(pairs[2]),
                     staged=int(pairs[3]))
 
+    def backward_pairs(self, n_contrib: torch.Tensor) -> Dict[str, int]:
+        """(pixel, fragment) pairs the backward walks on the sorted frame: every
+        pixel the positions 1..n_contrib of its tile's list (n_contrib as
+        written by the blend, views packed in order), split into Gaussian and
+        triangle fragments."""
+        ranges = self.copy_state(L.STATE_RANGES).long()
+        vals = self.copy_state(L.STATE_SORTED_VALS).long() & 0xFFFFFFFF
+        per_view = max(1, self.N + self.T)
+        is_tri = (vals % per_view) >= self.N
+        pref = torch.zeros(vals.numel() + 1, dtype=torch.int64, device=vals.device)
+        pref[1:] = torch.cumsum(is_tri.long(), 0)
+        tw, th = self.opts.tile_w, self.opts.tile_h
+        nc_all = n_contrib.reshape(-1).long()
+        g = t = 0
+        pix0 = tile0 = 0
+        for W, H in self.views:
+            ntx, nty = (W + tw - 1) // tw, (H + th - 1) // th
+            nc = nc_all[pix0:pix0 + W * H].view(H, W)
+            ys = torch.arange(H, device=nc.device)[:, None]
+            xs = torch.arange(W, device=nc.device)[None, :]
+            tiles = tile0 + (ys // th) * ntx + (xs // tw)
+            start = ranges[tiles, 0]
+            nt = pref[start + nc] - pref[start]
+            t += int(nt.sum())
+            g += int(nc.sum()) - int(nt.sum())
+            pix0 += W * H
+            tile0 += ntx * nty
+        return dict(gauss=g, tri=t)
+
     # ---- graphs ---------------------------------------------------------------
     def reserve(self, max_dup: int):
         self._check(self.lib.umgs_reserve(self.h, int(max_dup)))

@@ -157,7 +157,7 @@ def test_deformed_backward_matches_oracle(gpu):
     w = torch.tensor(dL.reshape(H, W, 3).transpose(2, 0, 1).reshape(-1), dtype=torch.float32, device=dev)
     (img * w).sum().backward()
     for n, p in zip(NAMES, P):
-        assert_close(p.grad.cpu().numpy(), ref[n], n, rtol=2e-3)
+        assert_close(p.grad.cpu().numpy(), ref[n], n)
 
 
 def test_backward_requires_a_blended_frame(gpu):

@@ -244,6 +244,65 @@ def test_deformed_scene_parity(torch_dev, K):
     PT.compare_pixels(fr, img, Tf, last_gids(r, nc), px)
 
 
+def _list_counts(lst, N, gid):
+    """Gaussian and triangle entries of a tile list up to and including the
+    fragment gid (the whole list for None)."""
+    k = lst.size if gid is None else int(np.flatnonzero(lst == gid)[0]) + 1
+    g = int((lst[:k] < N).sum())
+    return g, k - g
+
+
+def test_work_counts_match_the_oracle(torch_dev):
+    """The roofline's work counts against the oracle's per-pixel outcomes on
+    the 64x64 workload.  Blend (umgs_blend_pairs): a pixel evaluates every
+    fragment of its tile's list up to the one where the oracle stops it (a
+    Gaussian that would leave T < 1e-4, or a triangle after which T < 1e-4),
+    or the whole list.  Backward (Rasterizer.backward_pairs): the list up to
+    the pixel's last blended fragment.  Both split into Gaussian and
+    triangle fragments; a pixel with a near-threshold decision may take any
+    of its valid outcomes."""
+    from paper_2601_19233_amd import _lib as L
+    s = scenes.make_config(0)
+    cam = s.cams[0]
+    r, out = run(s)
+    pairs = r.blend_pairs()
+    bpairs = r.backward_pairs(out["n_contrib"])
+    ranges = to_np(r.copy_state(L.STATE_RANGES)).astype(np.int64)
+    vals = to_np(r.copy_state(L.STATE_SORTED_VALS)).astype(np.int64) & 0xFFFFFFFF
+    fr = PT.oracle_frame(s, cam)
+    tw, th = r.opts.tile_w, r.opts.tile_h
+    ntx = (cam.width + tw - 1) // tw
+    nom = np.zeros(4, np.int64)
+    lo = np.zeros(4, np.int64)
+    hi = np.zeros(4, np.int64)
+    for y in range(cam.height):
+        for x in range(cam.width):
+            a, b = ranges[(y // th) * ntx + x // tw]
+            lst = vals[a:b]
+            base = fr.pixel(x, y)
+            res = fr.pixel_variants(x, y) if base.margin <= 1e-4 else [base]
+            cnt = []
+            for q in res:
+                if q.T < 1e-4:
+                    stop = q.last_id                       # a triangle stopped it
+                elif len(q.order) < len(q.contributors):
+                    stop = q.contributors[len(q.order)]    # the Gaussian that would
+                else:
+                    stop = None
+                last = q.last_id if q.last_id >= 0 else None
+                fwd = _list_counts(lst, s.N, stop)
+                bwd = _list_counts(lst, s.N, last) if last is not None else (0, 0)
+                cnt.append(fwd + bwd)
+            cnt = np.array(cnt)
+            nom += cnt[0]
+            lo += cnt.min(0)
+            hi += cnt.max(0)
+    got = np.array([pairs["gauss"], pairs["tri"], bpairs["gauss"], bpairs["tri"]])
+    note(f"work counts gpu {got.tolist()} oracle {nom.tolist()} (range {lo.tolist()}..{hi.tolist()})")
+    assert nom[0] > 10000 and nom[1] > 1000
+    assert np.all(lo <= got) and np.all(got <= hi), (got, lo, hi)
+
+
 def check_transfer(r, V_rest, F, V_def, bf, bb, mu, q, sc):
     """GPU transfer against the oracle transfer on the same bindings: means
     bit for bit, covariances, rotations and A to FP32 accuracy."""

@@ -6,13 +6,25 @@ outputs.
   primitive bit-exact; 160 sampled pixels within 1e-4 (plus the last blended
   fragment's id); sampled gradients of the backward against the oracle
   gradient restricted to those pixels.
-* 800x800, 300k Gaussians with SH degree 3 + 50,176 triangles: sampled pixels.
+* 800x800, 300k Gaussians with SH degree 3 + 50,176 triangles: sampled
+  pixels; gradients on four 16 x 16 windows against FP64 central finite
+  differences of the forward oracle for 256 Gaussians x 17 parameters
+  (tests/golden/cfg2_fd_256.json, written by tests/golden/cfg2_fd.py) and
+  against the oracle gradient for every Gaussian the windows touch.
 * 64 views of uneven size, 500k Gaussians (captured graph, persistent
   schedule): sampled pixels on four views, each view bit-identical to its
   plain per-view frame.
 * 16 views at 1080p, 2M deformed Gaussians with SH degree 3 + 200k
-  triangles (captured forward+backward graph): sampled pixels on two views.
+  triangles (captured forward+backward graph): sampled pixels on two views;
+  the batched gradients of a loss on sampled pixels of those two views
+  against the oracle gradient.
+
+Gradients: 1e-3 relative per element with an absolute floor of 1e-5 times
+the largest magnitude of the same parameter array (FP32 sums of many terms
+against FP64); pixels with a decision within 1e-4 (relative) of its
+threshold get zero loss weight.
 """
+import json
 import os
 import sys
 
@@ -95,6 +107,22 @@ def test_cfg1_full_frame(gpu, cfg1):
     assert np.array_equal(g_gpu[both], gk[both])
     assert np.sum((g_gpu == 0xFFFFFFFF) != (gk == 0xFFFFFFFF)) <= 2
     assert np.array_equal(keys[s.N:], tk)
+    # order: 64 sampled tiles' lists are in the stable (oracle key, id) order
+    ranges = r.copy_state(L.STATE_RANGES).cpu().numpy().astype(np.int64)
+    vals = r.copy_state(L.STATE_SORTED_VALS).cpu().numpy().astype(np.int64) & 0xFFFFFFFF
+    okey = np.concatenate([fr.g.key, fr.t.key]).astype(np.float32)
+    busy = np.flatnonzero(ranges[:, 1] > ranges[:, 0])
+    n_checked = 0
+    for t in np.random.default_rng(14).choice(busy, 64, replace=False):
+        ids = vals[ranges[t, 0]:ranges[t, 1]]
+        assert np.all(ids < s.N + s.T)
+        gk = ids < s.N
+        assert fr.g.valid[ids[gk]].all() and fr.t.valid[ids[~gk] - s.N].all()
+        order = np.lexsort((ids, okey[ids]))
+        assert np.array_equal(order, np.arange(ids.size)), int(t)
+        assert np.unique(ids).size == ids.size
+        n_checked += ids.size
+    note(f"cfg1 order: 64 tiles, {n_checked} list entries in (key, id) order")
     nc = r.split_views(out["n_contrib"], 1)[0].cpu().numpy()
     lg = last_gids(r, nc)
     px = sample_pixels(cam, 160, 11)
@@ -127,8 +155,107 @@ def test_cfg1_full_frame(gpu, cfg1):
         rr = ref[n]
         scale = np.abs(rr).max()
         err = np.abs(gg - rr)
-        bad = err > 2e-3 * np.abs(rr) + 1e-5 * scale
+        bad = err > 1e-3 * np.abs(rr) + 1e-5 * scale
         assert not bad.any(), (n, int(bad.sum()), float(err.max()), float(scale))
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+GRAD_NAMES = ("means", "scales", "quats", "opacity", "sh")
+
+
+def assert_grad_close(gg, rr, name, rtol=1e-3, floor=1e-5):
+    gg = np.asarray(gg, np.float64).reshape(rr.shape)
+    scale = np.abs(rr).max()
+    err = np.abs(gg - rr)
+    bad = err > rtol * np.abs(rr) + floor * scale
+    assert not bad.any(), (name, int(bad.sum()), float(err.max()), float(scale))
+
+
+def clear_colours(cam, means, sh, degree, ids=None, margin=1e-5):
+    """Gaussians whose SH colour channels all lie more than ``margin`` from
+    the clamp at 0 (the colour is max(0, raw + 0.5), a decision that FP32
+    and FP64 may take differently right at it)."""
+    from oracle import sh as SH
+    ids = np.arange(means.shape[0]) if ids is None else ids
+    W = np.asarray(cam.R, np.float32).astype(np.float64)
+    t = np.asarray(cam.t, np.float32).astype(np.float64)
+    d = means[ids].astype(np.float64) + (W.T @ t)
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    nc = (degree + 1) ** 2
+    raw = np.einsum("nk,nkc->nc", SH.basis(d, degree), sh[ids, :nc].astype(np.float64)) + 0.5
+    return np.all(np.abs(raw) > margin, axis=1)
+
+
+def sub_scene(frames, pixel_sets, N, T):
+    """Gaussian and triangle ids that can reach any of the listed pixels of
+    the listed oracle frames (the frame's conservative pixel boxes), sorted
+    ascending, so a scene of just these keeps the tie order of ids."""
+    gs, ts = set(), set()
+    for fr, pixels in zip(frames, pixel_sets):
+        for x, y in pixels:
+            gs.update(fr._gauss_at(x, y, 1e-4)[0].tolist())
+            ts.update(fr._tris_at(x, y)[0].tolist())
+    return np.array(sorted(gs), np.int64), np.array(sorted(ts), np.int64)
+
+
+def test_cfg2_gradients_match_finite_differences(gpu):
+    """800x800 SH-3 frame, loss on four 16 x 16 windows: the GPU gradient
+    against FP64 central finite differences of the forward oracle for 256
+    Gaussians x 17 parameters (mean, scale, quaternion, opacity, six SH
+    coefficients), and against the oracle gradient for every Gaussian."""
+    import torch
+    from paper_2601_19233_amd.render import Rasterizer
+    with open(os.path.join(GOLDEN, "cfg2_fd_256.json")) as f:
+        gold = json.load(f)
+    s = scenes.make_config(2)
+    assert gold["workload"] == s.name
+    cam = s.cams[0]
+    note(f"cfg2 gradients: N={s.N} T={s.T}, {len(gold['pixels'])} window pixels")
+    d = dev_tensors(s)
+    r = Rasterizer("cuda:0", sh_degree=3)
+    out = r.render([cam], **{k: d[k] for k in ("means", "scales", "quats", "opacity", "sh",
+                                               "tri_xyz", "tri_rgb", "tri_alpha")})
+    w = np.array(gold["weights"])
+    dL = np.zeros((3, cam.height, cam.width), np.float32)
+    for (x, y), wi in zip(gold["pixels"], w):
+        dL[:, y, x] = wi
+    g = r.backward(torch.from_numpy(dL.reshape(-1)).cuda(), out, d["means"], d["scales"],
+                   d["quats"], d["sh"], None)
+    torch.cuda.synchronize()
+    gn = {k: g[k].cpu().numpy().astype(np.float64) for k in GRAD_NAMES}
+    gn["sh"] = gn["sh"].reshape(s.N, 16, 3)
+    # finite differences
+    fd = np.array([[np.nan if v is None else v for v in row] for row in gold["fd"]])
+    assert np.isfinite(fd).sum() >= 0.98 * fd.size
+    # a colour channel right at its clamp is a decision FP32 may take the other way
+    fd[~clear_colours(cam, s.means, s.sh, 3, np.array(gold["gaussians"]))] = np.nan
+    an = np.empty_like(fd)
+    for j, (name, comp) in enumerate(gold["params"]):
+        for i, gid in enumerate(gold["gaussians"]):
+            an[i, j] = gn[name][(gid,) + tuple(comp)]
+    groups = {}
+    for j, (name, _) in enumerate(gold["params"]):
+        groups.setdefault(name, []).append(j)
+    for name, cols in groups.items():
+        a, f_ = an[:, cols], fd[:, cols]
+        ok = np.isfinite(f_)
+        scale = np.abs(f_[ok]).max()
+        err = np.abs(a - f_)
+        for fl in (1e-5, 1e-6, 1e-7):
+            nb = int((ok & (err > 1e-3 * np.abs(f_) + fl * scale)).sum())
+            note(f"cfg2 fd {name}: {nb} of {int(ok.sum())} beyond 1e-3 rel + {fl:g} max")
+        bad = ok & (err > 1e-3 * np.abs(f_) + 1e-6 * scale)
+        assert not bad.any(), (name, int(bad.sum()), float(np.nanmax(err)), float(scale))
+    # the oracle gradient, every Gaussian
+    live = np.any(w != 0, 1)
+    px = [tuple(p) for p, l in zip(gold["pixels"], live) if l]
+    ref = OG.gradients(cam, px, w[live], s.means, s.scales, s.quats, s.opacity, s.sh, 3, s.tri_xyz,
+                       s.tri_rgb, s.tri_alpha)
+    assert np.count_nonzero(ref["opacity"]) > 300
+    clear = clear_colours(cam, s.means, s.sh, 3)
+    note(f"cfg2: {int((~clear).sum())} Gaussians with a colour channel at the clamp left out")
+    for n in GRAD_NAMES:
+        assert_grad_close(gn[n][clear], ref[n][clear], n)
 
 
 def test_cfg2_full_frame(gpu):
@@ -186,19 +313,54 @@ def test_cfg4_batched_forward_backward(gpu):
     r.set_proxy(s.proxy.V_rest, s.proxy.faces)
     step = BatchedStep(r, s.cams, sc, deform=d["deform"], backward=True)
     step.prepare()
-    step.set_loss_gradient(torch.ones_like(step.out["image"]))
+    ot = OT.transfer(s.proxy.V_rest, s.proxy.faces, s.proxy.V_def, s.means, s.quats, s.scales,
+                     s.bind_face, s.bind_bary)
+    views = (0, 9)
+    frames = [OR.Frame(s.cams[v], ot["means"], s.opacity, s.sh, 3, s.tri_xyz, s.tri_rgb,
+                       s.tri_alpha, cov3d=ot["cov3d"]) for v in views]
+    # loss on 24 sampled pixels of each of the two views (zero elsewhere, so
+    # the batched gradient, summed over all 16 views, sees only these)
+    rng = np.random.default_rng(54)
+    dL = torch.zeros_like(step.out["image"])
+    gpx, gw = [], []
+    for v, fr in zip(views, frames):
+        cam = s.cams[v]
+        px = [p for p in sample_pixels(cam, 40, 60 + v) if fr.pixel(*p).margin > 1e-4][:24]
+        w = rng.normal(size=(len(px), 3))
+        img = step.split_views(dL, 3)[v]
+        for (x, y), wi in zip(px, w):
+            img[:, y, x] = torch.tensor(wi, dtype=torch.float32)
+        gpx.append(px)
+        gw.append(w)
+    step.set_loss_gradient(dL)
     out = step()
     torch.cuda.synchronize()
     assert not r.overflowed()
     for name, gt in step.grads.items():
         assert torch.isfinite(gt).all(), name
-    ot = OT.transfer(s.proxy.V_rest, s.proxy.faces, s.proxy.V_def, s.means, s.quats, s.scales,
-                     s.bind_face, s.bind_bary)
-    for v in (0, 9):
-        fr = OR.Frame(s.cams[v], ot["means"], s.opacity, s.sh, 3, s.tri_xyz, s.tri_rgb, s.tri_alpha,
-                      cov3d=ot["cov3d"])
+    for v, fr in zip(views, frames):
         note(f"cfg4 view {v}: {check_view(fr, step, out, v, sample_pixels(s.cams[v], 25, 50 + v))}")
     note(f"cfg4 groups {step.groups}")
+    # oracle gradient on a scene of the primitives that reach those pixels
+    gs, ts = sub_scene(frames, gpx, s.N, s.T)
+    note(f"cfg4 gradient check: {gs.size} Gaussians, {ts.size} triangles reach the pixels")
+    off = ot["means"][gs].astype(np.float64) - s.means[gs].astype(np.float64)
+    ref = None
+    for v, px, w in zip(views, gpx, gw):
+        rv = OG.gradients(s.cams[v], px, w, s.means[gs], s.scales[gs], s.quats[gs], s.opacity[gs],
+                          s.sh[gs], 3, s.tri_xyz[ts], s.tri_rgb[ts], s.tri_alpha[ts],
+                          xform=ot["A"][gs], mean_offset=off)
+        ref = rv if ref is None else {k: ref[k] + rv[k] for k in GRAD_NAMES}
+    assert np.count_nonzero(ref["opacity"]) > 100
+    rest = np.ones(s.N, bool)
+    rest[gs] = False
+    clear = np.ones(gs.size, bool)
+    for v in views:
+        clear &= clear_colours(s.cams[v], ot["means"], s.sh, 3, gs)
+    for n in GRAD_NAMES:
+        gt = step.grads[n].cpu().numpy().astype(np.float64).reshape((s.N,) + ref[n].shape[1:])
+        assert_grad_close(gt[gs][clear], ref[n][clear], n)
+        assert np.abs(gt[rest]).max() == 0.0, n
 
 
 def test_cfg1_binding_association_sampled(gpu, cfg1):

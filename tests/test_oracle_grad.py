@@ -148,3 +148,42 @@ def test_gradients_deformed_match_finite_differences():
     gids = [0, 3, 5]
     checked, skipped = check_fd(cam, params, 0, xyz, rgb, al, 0, gids, xform=A, off=off)
     assert checked >= 20
+
+
+@pytest.mark.slow
+def test_gradients_at_800px_sh3_match_stored_finite_differences():
+    """The 800x800 SH-3 workload (300,000 Gaussians, 50,176 triangles), loss
+    on four 16 x 16 windows: the gradient oracle against the FP64 central
+    differences of the forward oracle stored by tests/golden/cfg2_fd.py for
+    256 Gaussians x 17 parameters (1e-4 relative, with a floor of 1e-8 of
+    the largest difference of the same parameter kind: the differences
+    carry rounding of order 1e-9 in absolute terms).  The stored pixel weights are the
+    script's seeded draw."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg2_fd_256.json")
+    with open(path) as f:
+        gold = json.load(f)
+    s = scenes.make_config(2)
+    assert gold["workload"] == s.name
+    w = np.array(gold["weights"])
+    draw = np.random.default_rng(2002).normal(size=w.shape)
+    live = np.any(w != 0, 1)
+    assert np.array_equal(w[live], draw[live]) and live.mean() > 0.5
+    px = [tuple(p) for p, l in zip(gold["pixels"], live) if l]
+    ref = OG.gradients(s.cams[0], px, w[live], s.means, s.scales, s.quats, s.opacity, s.sh, 3,
+                       s.tri_xyz, s.tri_rgb, s.tri_alpha)
+    fd = np.array([[np.nan if v is None else v for v in row] for row in gold["fd"]])
+    assert np.isfinite(fd).sum() >= 0.98 * fd.size
+    kinds = {}
+    for j, (name, comp) in enumerate(gold["params"]):
+        kinds.setdefault(name, []).append(j)
+        for i, gid in enumerate(gold["gaussians"]):
+            fd[i, j] = fd[i, j] - ref[name][(gid,) + tuple(comp)] if np.isfinite(fd[i, j]) else np.nan
+    raw = np.array([[np.nan if v is None else v for v in row] for row in gold["fd"]])
+    for name, cols in kinds.items():
+        err, f_ = np.abs(fd[:, cols]), raw[:, cols]
+        ok = np.isfinite(f_)
+        scale = np.abs(f_[ok]).max()
+        bad = ok & (err > 1e-4 * np.abs(f_) + 1e-8 * scale)
+        assert not bad.any(), (name, int(bad.sum()), float(np.nanmax(err)), float(scale))
