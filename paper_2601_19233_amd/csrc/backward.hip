@@ -63,27 +63,49 @@ struct PixBwd {
 // pixel.  Returns whether it blended it.  Every lane evaluates every term
 // (no branches), so the wave sums that follow see defined values on all
 // lanes.
-__device__ __forceinline__ bool gauss_bwd(const uint32_t *s, int pos, float pcx, float pcy,
+// A staged Gaussian's constants, read from LDS once per fragment for all
+// of a lane's pixels.
+struct GFrag {
+  float4 a;     // mean x, mean y, qa, qb
+  float2 b;     // qc, log2(o)
+  float c0, c1, c2;
+};
+
+__device__ __forceinline__ GFrag load_gfrag(const uint32_t *s) {
+  GFrag f;
+  f.a = *(const float4 *)(s + 0);
+  f.b = *(const float2 *)(s + 4);
+  f.c0 = __uint_as_float(s[6]);
+  f.c1 = __uint_as_float(s[7]);
+  f.c2 = __uint_as_float(s[8]);
+  return f;
+}
+
+__device__ __forceinline__ bool gauss_bwd(const GFrag &fr, int pos, float pcx, float pcy,
                                           PixBwd &q, float *g) {
-  float alpha, a_un, dx, dy;
-  const bool hit = gauss_terms(s, pcx, pcy, alpha, a_un, dx, dy);
+  // alpha and the decision exactly as gauss_terms takes them
+  float dx = fr.a.x - pcx;
+  float dy = fr.a.y - pcy;
+  const float pw = gauss_logalpha(fr.a.z, fr.a.w, fr.b.x, fr.b.y, dx, dy);
+  const bool inside = pw <= fr.b.y;
+  const float a_un = __builtin_amdgcn_exp2f(inside ? pw : fr.b.y);
+  const float alpha = fminf(kAlphaMax, a_un);
+  const bool hit = inside && alpha >= kAlphaMin;
   const bool contrib = pos < q.last && hit;
   q.ent = contrib ? __builtin_inff() : q.ent;     // a blended Gaussian closes an entity
   // T in front of the fragment: one rcp (1 ulp) per step of the walk
   const float Tb = (pos == q.last - 1) ? q.Tterm : q.Tr * __builtin_amdgcn_rcpf(1.0f - alpha);
-  const float cd = fmaf(__uint_as_float(s[6]), q.dC0,
-                        fmaf(__uint_as_float(s[7]), q.dC1, __uint_as_float(s[8]) * q.dC2));
+  const float cd = fmaf(fr.c0, q.dC0, fmaf(fr.c1, q.dC1, fr.c2 * q.dC2));
   const float diff = cd - q.Bd;             // (c - B) . dL/dC
-  const float w = contrib ? Tb * alpha : 0.0f;
-  const float dLda = contrib ? Tb * diff : 0.0f;
-  q.Bd = contrib ? fmaf(alpha, diff, q.Bd) : q.Bd;
+  // where the pixel does not blend it every term is an exact zero (all
+  // factors are finite) and the state is left as it is
+  const float ac = contrib ? alpha : 0.0f;
+  const float w = Tb * ac;
+  q.Bd = fmaf(ac, diff, q.Bd);
   q.Tr = contrib ? Tb : q.Tr;
   // alpha below the 0.99 clamp depends on power and opacity
-  const float dpow = (a_un < kAlphaMax) ? dLda : 0.0f;
+  const float dpow = (contrib && a_un < kAlphaMax) ? Tb * diff : 0.0f;
   const float dp = alpha * dpow;     // d alpha / d power = o exp(power) = alpha
-  // offsets of other lanes may be huge (a far mean): keep 0 x inf out
-  dx = contrib ? dx : 0.0f;
-  dy = contrib ? dy : 0.0f;
   const float dpx = dp * dx, dpy = dp * dy;
   g[0] = dpx;
   g[1] = dpy;
@@ -354,29 +376,34 @@ __global__ __launch_bounds__(64) void blend_backward_kernel(
   for (int bend = max_last; bend > 0; bend -= batch) {
     const int bstart = max(0, bend - batch);
     const int bn = bend - bstart;
-    for (int f = lane; f < bn; f += 64) {
-      uint32_t *s = slots + f * kSlotWords;
-      const int64_t local = (int64_t)vals[rg.x + bstart + f] - rbase;
+    // lane f stages fragment f (batch <= 64); bit f of tri_bits marks a triangle
+    bool is_tri = false;
+    if (lane < bn) {
+      uint32_t *s = slots + lane * kSlotWords;
+      const int64_t local = (int64_t)vals[rg.x + bstart + lane] - rbase;
       if (local < N) {
         const uint32_t rec = (uint32_t)((int64_t)v * N + local);
         stage_gauss(s, grec[rec], rec);
       } else {
         stage_tri(s, trec[(int64_t)v * T + (local - N)], P0x, P0y);
+        is_tri = true;
       }
     }
+    const uint64_t tri_bits = __ballot(is_tri);
     __syncthreads();
     for (int f = bn - 1; f >= 0; --f) {
       const uint32_t *s = slots + f * kSlotWords;
       const int pos = bstart + f;
       if (!__any(pos < my_last)) continue;
-      if ((s[31] & 1u) == 0u) {
+      if (((tri_bits >> f) & 1u) == 0u) {
+        const GFrag fr = load_gfrag(s);
         float g[9];
         bool c = false;
 #pragma unroll
         for (int p = 0; p < PPT; ++p) {
           const float pcy = (float)(ty * TH + ly0 + p * RSTEP) + 0.5f;
           float h[9];
-          c |= gauss_bwd(s, pos, pcx, pcy, q[p], h);
+          c |= gauss_bwd(fr, pos, pcx, pcy, q[p], h);
 #pragma unroll
           for (int k = 0; k < 9; ++k) g[k] = p == 0 ? h[k] : g[k] + h[k];
         }
@@ -671,8 +698,8 @@ namespace {
 
 template <int TW, int TH, int SPLIT>
 hipError_t launch_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int32_t *nc, const float *Te) {
-  // the backward's own LDS batch of staged fragments, at most 64 (8 KB per
-  // one-wave workgroup, so LDS does not limit the waves per CU)
+  // the backward's own LDS batch of staged fragments, at most 64 (one per
+  // lane; 8 KB per one-wave workgroup, so LDS does not limit the waves per CU)
   const int batch = std::min(c->frag_batch, 64);
   const size_t lds = (size_t)batch * kSlotWords * sizeof(uint32_t);
   const uint32_t nt = (uint32_t)c->n_tiles;
