@@ -44,7 +44,8 @@ def cam_centres(rng, n):
     return np.stack([OB.camera_center(c.R, c.t) for c in cams]).astype(np.float32)
 
 
-def compare(P, cams, V, F, face_g, bary_g, dist_g):
+def compare(P, cams, V, F, face_g, bary_g, dist_g, EDGE=EDGE, TOL_D=TOL_D, TOL_B=TOL_B,
+            TOL_X=TOL_X):
     """Per target: exact agreement where the oracle's nearest crossing is
     clear, validity elsewhere.  Returns (clear, ambiguous) counts."""
     cand = OB.candidates(P, cams.astype(np.float64), V.astype(np.float64), F)
@@ -127,6 +128,36 @@ def test_binding_matches_oracle_two_layer_proxy(gpu, K, N):
     note(f"raycast K={K}: {clear} clear, {amb} ambiguous")
     assert amb <= 0.02 * (clear + amb)
     assert (face_g == -1).any() and (face_g >= 1280).any()
+    r.close()
+
+
+def test_binding_with_far_cameras(gpu):
+    """Camera centres 100 to 1000 proxy radii away in random (off-axis)
+    directions: every box that holds a crossing must survive the FP32 slab
+    tests, so the nearest crossings are found as from near cameras.  FP32
+    crossings from that far carry errors of order |o| x 2^-24 (about 1e-4 at
+    1000), so the comparison tolerances scale with the distance."""
+    import torch
+    from paper_2601_19233_amd.render import Rasterizer
+    rng = np.random.default_rng(23)
+    V, F = two_spheres()
+    means, s, q = gaussians(rng, V, F, 300)
+    cams = np.stack([OB.camera_center(c.R, c.t) for c in
+                     scenes.orbit_cameras(rng, 4, [(64, 64)] * 4, dist_range=(100.0, 1000.0))])
+    cams = cams.astype(np.float32)
+    note(f"raycast far cameras |o| = {np.linalg.norm(cams, axis=1).round(1).tolist()}")
+    r = Rasterizer("cuda:0", k_bind=8)
+    r.set_proxy(V, F)
+    out = r.bind_raycast(means, s, q, 8, cams)
+    torch.cuda.synchronize()
+    P = OB.target_points(means, s, q, 8).reshape(-1, 3)
+    face_g = out["face"].cpu().numpy().reshape(-1)
+    clear, amb = compare(P, cams, V, F, face_g, out["bary"].cpu().numpy().reshape(-1, 2).astype(np.float64),
+                         out["dist"].cpu().numpy().reshape(-1).astype(np.float64),
+                         EDGE=5e-3, TOL_D=1e-3, TOL_B=3e-3, TOL_X=1e-3)
+    note(f"raycast far cameras: {clear} clear, {amb} ambiguous")
+    assert amb <= 0.05 * (clear + amb)
+    assert (face_g >= 0).mean() > 0.9
     r.close()
 
 
