@@ -134,8 +134,7 @@ def render_pixels(frame: OR.Frame, pixels, means, scales, quats, opacity, sh, de
         else:
             cov = OR.sample_coverage(frame.t, tid, int(px), int(py)).astype(np.float64)
         tcov[i, cols] = cov
-        tcol[i, cols] = OR.triangle_colour(frame.t, tid, int(px), int(py))
-        tal[i, cols] = frame.t.alpha[tid]
+        tcol[i, cols], tal[i, cols] = OR.triangle_shade(frame.t, tid, int(px), int(py), frame.tex)
 
     mean2d, conic, rgb = project_torch(frame.cam, means, scales, quats, opacity, sh, degree,
                                        xform, mean_offset)
@@ -187,7 +186,7 @@ def render_pixels(frame: OR.Frame, pixels, means, scales, quats, opacity, sh, de
 
 def gradients(cam, pixels, dL_dC, means, scales, quats, opacity, sh, degree, tri_xyz, tri_rgb,
               tri_alpha, bg=(0.0, 0.0, 0.0), mode=OR.MODE_UNIMGS, xform=None,
-              mean_offset=None) -> Dict[str, np.ndarray]:
+              mean_offset=None, tri_uv=None, tex=None) -> Dict[str, np.ndarray]:
     """dL/d(means, scales, quats, opacity, sh) for L = sum_p dL_dC[p] . C[p]
     over the listed pixels.  Inputs are NumPy arrays; xform (N,3,3) and
     mean_offset (N,3) describe a deformed scene (then ``means`` are the rest
@@ -201,10 +200,10 @@ def gradients(cam, pixels, dL_dC, means, scales, quats, opacity, sh, degree, tri
         cov = np.stack([Sp[:, 0, 0], Sp[:, 0, 1], Sp[:, 0, 2], Sp[:, 1, 1], Sp[:, 1, 2], Sp[:, 2, 2]], 1)
         mu = np.asarray(means, np.float64) + np.asarray(mean_offset, np.float64)
         frame = OR.Frame(cam, mu, opacity, sh, degree, tri_xyz, tri_rgb, tri_alpha, cov3d=cov,
-                         bg=bg, mode=mode)
+                         bg=bg, mode=mode, tri_uv=tri_uv, tex=tex)
     else:
         frame = OR.Frame(cam, means, opacity, sh, degree, tri_xyz, tri_rgb, tri_alpha,
-                         scales=scales, quats=quats, bg=bg, mode=mode)
+                         scales=scales, quats=quats, bg=bg, mode=mode, tri_uv=tri_uv, tex=tex)
     P = [t64(means), t64(scales), t64(quats), t64(opacity), t64(sh)]
     A_t = None if xform is None else torch.tensor(np.asarray(xform, np.float64), dtype=DT)
     off_t = None if mean_offset is None else torch.tensor(np.asarray(mean_offset, np.float64), dtype=DT)

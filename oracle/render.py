@@ -27,6 +27,14 @@ tiles), sorts them by (depth key, global id) and blends front to back:
   blending a triangle that leaves T < 1e-4.
 * Background (Eq. 10-11 with an opaque background): C += T C_bg.
 
+A triangle's colour and opacity are evaluated at the pixel centre: the
+per-vertex colour interpolated perspective-correctly, and the triangle's
+opacity attribute.  A textured mesh (the paper's Section 1 assigns an
+opacity attribute to textured meshes) also interpolates per-vertex texture
+coordinates with the same weights and samples an RGBA texture bilinearly:
+colour = vertex colour x texel RGB, opacity = attribute x texel alpha (the
+texel alpha is the per-texel opacity).  Sub-sample coverage is unaffected.
+
 Besides C and T the oracle reports, per pixel, the transmittance in front of
 the last blended unit (a Gaussian, or a whole triangle entity), which the
 backward pass needs when that unit is opaque.
@@ -198,9 +206,10 @@ class TriSetup:
     z: np.ndarray            # (T,3) fp64 view z, same vertex order as X/Y
     rgb: np.ndarray          # (T,3,3) per-vertex colour, same vertex order
     alpha: np.ndarray        # (T,)
+    uv: Optional[np.ndarray] = None    # (T,3,2) texture coordinates, same vertex order
 
 
-def setup_triangles(cam, tri_xyz, tri_rgb, tri_alpha) -> TriSetup:
+def setup_triangles(cam, tri_xyz, tri_rgb, tri_alpha, tri_uv=None) -> TriSetup:
     tri_xyz = np.asarray(tri_xyz, F32)
     T = tri_xyz.shape[0]
     R32, t32, fx32, fy32, cx32, cy32 = _cam32(cam)
@@ -231,8 +240,9 @@ def setup_triangles(cam, tri_xyz, tri_rgb, tri_alpha) -> TriSetup:
     p64 = tri_xyz.astype(np.float64) @ R32.astype(np.float64).T + t32.astype(np.float64)
     z64 = p64[:, :, 2][r, order]
     rgb = np.asarray(tri_rgb, np.float64)[r, order]
+    uv = None if tri_uv is None else np.asarray(tri_uv, F32).astype(np.float64).reshape(T, 3, 2)[r, order]
     return TriSetup(valid=valid, key=key, X=X, Y=Y, area2=area2, z=z64, rgb=rgb,
-                    alpha=np.asarray(tri_alpha, np.float64))
+                    alpha=np.asarray(tri_alpha, np.float64), uv=uv)
 
 
 def _edges(X, Y):
@@ -284,17 +294,59 @@ def centre_coverage(ts: TriSetup, idx, px: int, py: int) -> np.ndarray:
     return np.all((E > 0) | ((E == 0) & owned), axis=1)
 
 
-def triangle_colour(ts: TriSetup, idx, px: int, py: int) -> np.ndarray:
-    """Perspective-correct per-vertex colour at the pixel centre.
-
-    Screen barycentrics b_k = E_k(centre) / area2 from the snapped vertices,
+def _perspective_weights(ts: TriSetup, idx, px: int, py: int) -> np.ndarray:
+    """Perspective-correct barycentric weights at the pixel centre: screen
+    barycentrics b_k = E_k(centre) / area2 from the snapped vertices,
     negative ones clamped to 0 and renormalised, then weighted by 1/z_k."""
     E = edge_values(ts, idx, px * SUBPX + SUBPX // 2, py * SUBPX + SUBPX // 2).astype(np.float64)
     b = np.maximum(E, 0.0) / ts.area2[idx, None].astype(np.float64)
     b /= b.sum(axis=1, keepdims=True)
     w = b / ts.z[idx]
-    lam = w / w.sum(axis=1, keepdims=True)
+    return w / w.sum(axis=1, keepdims=True)
+
+
+def triangle_colour(ts: TriSetup, idx, px: int, py: int) -> np.ndarray:
+    """Perspective-correct per-vertex colour at the pixel centre."""
+    lam = _perspective_weights(ts, idx, px, py)
     return np.einsum("nk,nkc->nc", lam, ts.rgb[idx])
+
+
+def texture_sample(tex: np.ndarray, uv: np.ndarray) -> np.ndarray:
+    """Bilinear RGBA of texture tex (H, W, 4) at texture coordinates uv (n, 2):
+    texel (i, j) -- column i, row j -- is centred at ((i + 1/2)/W, (j + 1/2)/H),
+    addresses clamp to the edge texels, and each interpolation step is
+    a + f (b - a) (so a constant texture returns its value exactly)."""
+    tex = np.asarray(tex, np.float64)
+    H, W = tex.shape[0], tex.shape[1]
+    x = uv[:, 0] * W - 0.5
+    y = uv[:, 1] * H - 0.5
+    x0, y0 = np.floor(x), np.floor(y)
+    fx, fy = (x - x0)[:, None], (y - y0)[:, None]
+    i0 = np.clip(x0, 0, W - 1).astype(np.int64)
+    i1 = np.clip(x0 + 1, 0, W - 1).astype(np.int64)
+    j0 = np.clip(y0, 0, H - 1).astype(np.int64)
+    j1 = np.clip(y0 + 1, 0, H - 1).astype(np.int64)
+    top = tex[j0, i0] + fx * (tex[j0, i1] - tex[j0, i0])
+    bot = tex[j1, i0] + fx * (tex[j1, i1] - tex[j1, i0])
+    return top + fy * (bot - top)
+
+
+def triangle_shade(ts: TriSetup, idx, px: int, py: int, tex=None):
+    """Colour (n, 3) and opacity (n,) of triangles idx at the pixel centre.
+    Untextured: the perspective-correct per-vertex colour and the triangle's
+    opacity attribute.  Textured (the paper's Section 1: an opacity attribute
+    on textured meshes): the texture coordinates are interpolated with the
+    same perspective-correct weights, the texture is sampled bilinearly, the
+    colour is the per-vertex colour times the texel RGB and the opacity the
+    triangle's attribute times the texel alpha."""
+    lam = _perspective_weights(ts, idx, px, py)
+    col = np.einsum("nk,nkc->nc", lam, ts.rgb[idx])
+    alpha = ts.alpha[idx].astype(np.float64)
+    if tex is None or ts.uv is None:
+        return col, alpha
+    uv = np.einsum("nk,nkc->nc", lam, ts.uv[idx])
+    t = texture_sample(tex, uv)
+    return col * t[:, :3], alpha * t[:, 3]
 
 
 # ---------------------------------------------------------------------------
@@ -321,11 +373,12 @@ class Frame:
 
     def __init__(self, cam, means, opacity, sh, sh_degree, tri_xyz, tri_rgb, tri_alpha,
                  scales=None, quats=None, cov3d=None, bg=(0.0, 0.0, 0.0),
-                 mode: int = MODE_UNIMGS):
+                 mode: int = MODE_UNIMGS, tri_uv=None, tex=None):
         self.cam = cam
         self.N = int(np.asarray(means).shape[0])
         self.g = project_gaussians(cam, means, opacity, sh, sh_degree, scales, quats, cov3d)
-        self.t = setup_triangles(cam, tri_xyz, tri_rgb, tri_alpha)
+        self.t = setup_triangles(cam, tri_xyz, tri_rgb, tri_alpha, tri_uv)
+        self.tex = None if tex is None else np.asarray(tex, F32)
         self.bg = np.asarray(bg, np.float64)
         self.mode = mode
         g = self.g
@@ -401,10 +454,11 @@ class Frame:
         order = np.lexsort((ids, keys))
         ids = ids[order]
         tri_cov = {int(t) + N: tcov[i] for i, t in enumerate(tidx)}
-        tri_col = {}
+        tri_col, tri_al = {}, {}
         if tidx.size:
-            cols = triangle_colour(self.t, tidx, px, py)
+            cols, als = triangle_shade(self.t, tidx, px, py, self.tex)
             tri_col = {int(t) + N: cols[i] for i, t in enumerate(tidx)}
+            tri_al = {int(t) + N: float(als[i]) for i, t in enumerate(tidx)}
 
         C = np.zeros(3)
         T = 1.0
@@ -436,8 +490,7 @@ class Frame:
                 if mode != MODE_ONE_ENTITY:
                     in_entity = False
             else:
-                ti = gid - N
-                al = self.t.alpha[ti]
+                al = tri_al[gid]
                 col = tri_col[gid]
                 if mode == MODE_DIRECT:
                     # like a Gaussian, but blended before the stop test (an
@@ -500,13 +553,14 @@ class Frame:
 
 def render(cam, means, opacity, sh, sh_degree, tri_xyz, tri_rgb, tri_alpha, scales=None,
            quats=None, cov3d=None, bg=(0.0, 0.0, 0.0), pixels: Optional[np.ndarray] = None,
-           mode: int = MODE_UNIMGS, margin_rel: float = 1e-4) -> Dict[str, np.ndarray]:
+           mode: int = MODE_UNIMGS, margin_rel: float = 1e-4, tri_uv=None,
+           tex=None) -> Dict[str, np.ndarray]:
     """Render a full view (or the listed pixels, an (n,2) array of (px, py)).
 
     Returns image (3,H,W) or (n,3), T_final, n_blended, last_id, T_entity_in,
     margin (per pixel) and the per-pixel blended order (list of lists)."""
     fr = Frame(cam, means, opacity, sh, sh_degree, tri_xyz, tri_rgb, tri_alpha,
-               scales, quats, cov3d, bg, mode)
+               scales, quats, cov3d, bg, mode, tri_uv=tri_uv, tex=tex)
     full = pixels is None
     if full:
         yy, xx = np.mgrid[0:cam.height, 0:cam.width]
