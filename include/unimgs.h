@@ -200,6 +200,24 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
                          int32_t T, const float *tri_xyz, const float *tri_rgb,
                          const float *tri_alpha);
 
+/* Texture the triangles (the paper's Section 1: textured meshes carrying an
+ * opacity attribute).  tex_rgba [device] (tex_h, tex_w, 4) FP32 RGBA, row j
+ * of texels at v = (j + 1/2)/tex_h, column i at u = (i + 1/2)/tex_w;
+ * tri_uv [device] (T,3,2) texture coordinates (u, v) of each triangle's
+ * vertices.  Both are copied into the context (asynchronously on its
+ * stream: the caller may free them after the stream reaches this call).
+ * Every later umgs_project / umgs_render_batched of T triangles then shades a
+ * triangle at each pixel centre with the perspective-correct interpolation
+ * of its texture coordinates: a bilinear fetch (addresses clamped to the
+ * edge texels), colour = per-vertex colour x texel RGB, opacity =
+ * tri_alpha x texel alpha; sub-sample coverage and depth keys do not change.
+ * tex_rgba NULL removes the texture (untextured shading).  Not while
+ * capturing a graph.  Errors: INVALID_ARG (sizes outside 1..16384, T < 0, a
+ * NULL tri_uv with T > 0), STATE, CAPACITY, HIP; umgs_project then fails
+ * with INVALID_ARG if its triangle count is not T. */
+umgs_status umgs_set_texture(umgs_ctx *ctx, int32_t tex_w, int32_t tex_h, const float *tex_rgba,
+                             int32_t T, const float *tri_uv);
+
 /* Bin (first level of the mixed depth sort of Section 3.2): the projected
  * primitives in (depth key, record id) order, then one (supertile, record)
  * entry for every supertile -- a block of 8 x 8 tiles -- that the

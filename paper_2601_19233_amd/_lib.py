@@ -45,6 +45,7 @@ PROTOTYPES = {
     "umgs_bind_transfer_noalloc": (C.c_int, [P, P, I32, P, P, P, P, P, P, P, P, P, P]),
     "umgs_bind_raycast": (C.c_int, [P, I32, P, P, P, I32, I32, C.POINTER(C.c_float), P, P, P]),
     "umgs_project": (C.c_int, [P, I32, C.POINTER(Camera), I32, P, P, P, P, P, P, I32, P, P, P]),
+    "umgs_set_texture": (C.c_int, [P, I32, I32, P, I32, P]),
     "umgs_bin": (C.c_int, [P]),
     "umgs_sort": (C.c_int, [P]),
     "umgs_blend": (C.c_int, [P, P, P, P, P]),

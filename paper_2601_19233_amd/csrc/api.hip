@@ -178,7 +178,7 @@ void umgs_destroy(umgs_ctx *ctx) {
                     &c->chunk_base, &c->cnt2, &c->chunk_tab, &c->tstart, &c->totals,
                     &c->v0, &c->v1, &c->hist, &c->ranges, &c->g2d,
                     &c->minmax, &c->lb, &c->finfo, &c->tile_order, &c->bwd_order, &c->pair_count,
-                    &c->view_sums};
+                    &c->view_sums, &c->tex, &c->tex_uv};
   for (DevBuf *b : bufs) free_buf(*b);
   for (auto &p : c->prof.pending) {
     (void)hipEventDestroy(p.a);
@@ -357,6 +357,34 @@ umgs_status umgs_bind_transfer_noalloc(umgs_ctx *ctx, const float *V_def, int32_
                    "transfer launch");
 }
 
+umgs_status umgs_set_texture(umgs_ctx *ctx, int32_t tex_w, int32_t tex_h, const float *tex_rgba,
+                             int32_t T, const float *tri_uv) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->capturing) return fail(c, UMGS_ERR_STATE, "umgs_set_texture: not allowed during graph capture");
+  if (!tex_rgba) {
+    c->tex_w = c->tex_h = c->tex_T = 0;
+    return UMGS_OK;
+  }
+  if (tex_w < 1 || tex_h < 1 || tex_w > 16384 || tex_h > 16384 || T < 0 || (T > 0 && !tri_uv))
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_set_texture: %dx%d texture, T=%d, tri_uv=%p", tex_w,
+                tex_h, T, (const void *)tri_uv);
+  const size_t tb = sizeof(float) * 4 * (size_t)tex_w * (size_t)tex_h;
+  const size_t ub = sizeof(float) * 6 * (size_t)std::max(T, 1);
+  umgs_status s;
+  if ((s = ensure(c, c->tex, tb, "texture")) || (s = ensure(c, c->tex_uv, ub, "texture coordinates")))
+    return s;
+  hipError_t e = hipMemcpyAsync(c->tex.p, tex_rgba, tb, hipMemcpyDeviceToDevice, c->stream);
+  if (e == hipSuccess && T > 0)
+    e = hipMemcpyAsync(c->tex_uv.p, tri_uv, sizeof(float) * 6 * (size_t)T, hipMemcpyDeviceToDevice,
+                       c->stream);
+  if (e != hipSuccess) return hip_check(c, e, "umgs_set_texture copy");
+  c->tex_w = tex_w;
+  c->tex_h = tex_h;
+  c->tex_T = T;
+  return UMGS_OK;
+}
+
 static umgs_status build_views(Ctx *c, int32_t V, const umgs_camera *cams,
                                std::vector<ViewParams> &vps, int64_t &tiles, int64_t &pix,
                                int64_t *st_total = nullptr) {
@@ -419,6 +447,10 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
     return fail(c, UMGS_ERR_INVALID_ARG, "umgs_project: NULL triangle array");
   if ((int64_t)V * ((int64_t)N + T) >= (1LL << 31))
     return fail(c, UMGS_ERR_CAPACITY, "umgs_project: V*(N+T) = %lld records", (long long)V * (N + T));
+  if (c->tex_w > 0 && T != c->tex_T)
+    return fail(c, UMGS_ERR_INVALID_ARG,
+                "umgs_project: the texture coordinates cover %d triangles, the frame has %d",
+                c->tex_T, T);
   const umgs_options &o = c->opt;
   std::vector<ViewParams> vps;
   int64_t tiles = 0, pix = 0, sts = 0;
@@ -732,7 +764,7 @@ umgs_status umgs_copy_state(umgs_ctx *ctx, int32_t which, void *dst, int64_t cap
   if (which == UMGS_STATE_SORTED_KEYS) {
     e = launch_expand_keys(c, (uint64_t *)dst);
   } else if (which == UMGS_STATE_TRI_FIXED) {
-    // 2D copy: the first 24 bytes of every 80-byte record
+    // 2D copy: the first 24 bytes of every record
     e = hipMemcpy2DAsync(dst, 24, src, sizeof(TriRec), 24, (size_t)c->V * c->T,
                          hipMemcpyDeviceToDevice, c->stream);
   } else {

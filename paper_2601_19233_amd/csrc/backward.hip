@@ -189,14 +189,13 @@ __device__ __forceinline__ void add_sums9(const uint32_t *s, const float (&t)[3]
 // Triangle fragment of the walk for one pixel (a fixed occluder: it passes
 // gradients through T and receives none).
 __device__ __forceinline__ void tri_bwd(const uint32_t *s, int pos, double rlx, double rly,
-                                        bool direct, PixBwd &q) {
+                                        bool direct, const TexView &tex, PixBwd &q) {
   double e[3];
   float o[4];
   if (!(pos < q.last && tri_eval(s, rlx, rly, direct, e, o) > 0)) return;
-  float cr, cg, cbl;
-  tri_colour(s, e, cr, cg, cbl);
+  float cr, cg, cbl, alpha;
+  tri_shade(s, e, tex, cr, cg, cbl, alpha);
   const float cd = fmaf(cr, q.dC0, fmaf(cg, q.dC1, cbl * q.dC2));
-  const float alpha = __uint_as_float(s[30]);
   if (direct) {
     q.Tr = (pos == q.last - 1) ? q.Tterm : q.Tr / (1.0f - alpha);
     q.Bd = fmaf(alpha, cd - q.Bd, q.Bd);
@@ -314,7 +313,7 @@ __global__ __launch_bounds__(64) void blend_backward_kernel(
     float bg0, float bg1, float bg2, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1,
     const FrameInfo *__restrict__ fi, const GaussRec *__restrict__ grec,
-    const TriRec *__restrict__ trec, const float *__restrict__ dLdimg,
+    const TriRec *__restrict__ trec, const TexView tex, const float *__restrict__ dLdimg,
     const float *__restrict__ Tfin, const int32_t *__restrict__ ncontrib,
     const float *__restrict__ Tent, float *__restrict__ g2d) {
   constexpr int ROWS = TH / SPLIT;                        // rows of a part
@@ -414,7 +413,7 @@ __global__ __launch_bounds__(64) void blend_backward_kernel(
       } else {
 #pragma unroll
         for (int p = 0; p < PPT; ++p)
-          tri_bwd(s, pos, rlx, (double)((ly0 + p * RSTEP) * kSubpx), direct, q[p]);
+          tri_bwd(s, pos, rlx, (double)((ly0 + p * RSTEP) * kSubpx), direct, tex, q[p]);
       }
     }
     __syncthreads();
@@ -722,7 +721,8 @@ hipError_t launch_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int32_t
                      batch, c->bg[0], c->bg[1], c->bg[2], (const uint2 *)c->ranges.p,
                      (const uint32_t *)c->v0.p, (const uint32_t *)c->v1.p,
                      (const FrameInfo *)c->finfo.p, (const GaussRec *)c->grec.p,
-                     (const TriRec *)c->trec.p, dL, Tf, nc, Te, (float *)c->g2d.p);
+                     (const TriRec *)c->trec.p, frame_texture(c), dL, Tf, nc, Te,
+                     (float *)c->g2d.p);
   return hipGetLastError();
 }
 

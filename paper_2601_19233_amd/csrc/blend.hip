@@ -48,7 +48,7 @@ __device__ __forceinline__ void blend_tile(
     uint32_t tile, uint32_t *__restrict__ slots, const ViewParams *__restrict__ views, int V,
     int N, int T, int mode, int batch, float bg0, float bg1, float bg2,
     const uint2 *__restrict__ ranges, const uint32_t *__restrict__ vals,
-    const GaussRec *__restrict__ grec, const TriRec *__restrict__ trec,
+    const GaussRec *__restrict__ grec, const TriRec *__restrict__ trec, const TexView tex,
     float *__restrict__ image, float *__restrict__ Tout, int32_t *__restrict__ ncontrib,
     float *__restrict__ Tent_out, unsigned long long *__restrict__ pairs = nullptr) {
   uint32_t n_gp = 0, n_tp = 0, n_wit = 0;
@@ -196,9 +196,8 @@ __device__ __forceinline__ void blend_tile(
             double e[3];
             float o[4];
             if (tri_eval(s, rlx, rly, direct, e, o) != 0) {
-              float cr, cg, cbl;
-              tri_colour(s, e, cr, cg, cbl);
-              const float alpha = __uint_as_float(s[30]);
+              float cr, cg, cbl, alpha;
+              tri_shade(s, e, tex, cr, cg, cbl, alpha);
               if (direct) {
                 const float w = Tr * alpha;
                 C0 = fmaf(w, cr, C0); C1 = fmaf(w, cg, C1); C2 = fmaf(w, cbl, C2);
@@ -268,6 +267,7 @@ struct BlendArgs {
   const uint32_t *v0, *v1;
   const GaussRec *grec;
   const TriRec *trec;
+  TexView tex;
   FrameInfo *fi;
   const uint32_t *order;
   uint32_t n_tiles;
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(kBlendWa
   extern __shared__ uint32_t slots[];   // batch * kSlotWords
   const uint32_t *vals = a.fi->sorted_in ? a.v1 : a.v0;
   blend_tile<TW, TH>(blockIdx.x, slots, a.views, a.V, a.N, a.T, a.mode, a.batch, a.bg0, a.bg1,
-                     a.bg2, a.ranges, vals, a.grec, a.trec, a.image, a.Tout, a.ncontrib, a.Tent);
+                     a.bg2, a.ranges, vals, a.grec, a.trec, a.tex, a.image, a.Tout, a.ncontrib, a.Tent);
 }
 
 template <int TW, int TH>
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(kBlendWa
   extern __shared__ uint32_t slots[];
   const uint32_t *vals = a.fi->sorted_in ? a.v1 : a.v0;
   blend_tile<TW, TH, true>(blockIdx.x, slots, a.views, a.V, a.N, a.T, a.mode, a.batch, a.bg0,
-                           a.bg1, a.bg2, a.ranges, vals, a.grec, a.trec, a.image, a.Tout,
+                           a.bg1, a.bg2, a.ranges, vals, a.grec, a.trec, a.tex, a.image, a.Tout,
                            a.ncontrib, a.Tent, pairs);
 }
 
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(TW *TH) __attribute__((amdgpu_waves_per_eu(kBlendWa
   const uint32_t *vals = a.fi->sorted_in ? a.v1 : a.v0;
   for (uint32_t it = blockIdx.x; it < a.n_tiles; it += gridDim.x)
     blend_tile<TW, TH>(a.order[it], slots, a.views, a.V, a.N, a.T, a.mode, a.batch, a.bg0, a.bg1,
-                       a.bg2, a.ranges, vals, a.grec, a.trec, a.image, a.Tout, a.ncontrib, a.Tent);
+                       a.bg2, a.ranges, vals, a.grec, a.trec, a.tex, a.image, a.Tout, a.ncontrib, a.Tent);
 }
 
 // ---- longest-first tile order: bucket tiles by floor(log2(list length)) ----
@@ -416,6 +416,7 @@ hipError_t launch_blend(Ctx *c, float *image, float *T_final, int32_t *n_contrib
   a.v1 = (const uint32_t *)c->v1.p;
   a.grec = (const GaussRec *)c->grec.p;
   a.trec = (const TriRec *)c->trec.p;
+  a.tex = frame_texture(c);
   a.fi = (FrameInfo *)c->finfo.p;
   a.order = order;
   a.n_tiles = (uint32_t)c->n_tiles;

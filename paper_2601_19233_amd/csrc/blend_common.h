@@ -8,7 +8,7 @@
 
 namespace umgs {
 
-constexpr int kSlotWords = 32;   // one staged fragment: 128 B of LDS
+constexpr int kSlotWords = 40;   // one staged fragment: 160 B of LDS
 
 // Slot layout (32-bit words)
 //   Gaussian: 0 mx, 1 my, 2 qa, 3 qb, 4 qc (times log2(e)), 5 lo = log2(o),
@@ -16,7 +16,7 @@ constexpr int kSlotWords = 32;   // one staged fragment: 128 B of LDS
 //   triangle: 0-5 E0[3] (FP64 edge functions at the tile's first pixel
 //             centre), 6-11 dmax[3] (FP64, max |offset term| over samples),
 //             12-14 dx[3], 15-17 dy[3] (int32), 18-20 1/z, 21-29 colour/z,
-//             30 alpha, 31 tag = 1 | owned << 8
+//             30 alpha, 31 tag = 1 | owned << 8, 32-37 (u, v)/z
 
 // rotated-grid sample offsets from the pixel centre, 1/256 px
 __device__ __forceinline__ int sample_ox(int j) { return j == 0 ? -32 : j == 1 ? 96 : j == 2 ? -96 : 32; }
@@ -52,6 +52,8 @@ __device__ __forceinline__ void stage_tri(uint32_t *s, const TriRec &tr, int64_t
   for (int k = 0; k < 9; ++k) s[21 + k] = __float_as_uint(tr.ciz[k]);
   s[30] = __float_as_uint(tr.alpha);
   s[31] = 1u | (tr.owned << 8);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s[32 + k] = __float_as_uint(tr.uviz[k]);
 }
 
 // p = log2(o exp(power)) = (qa dx + qb dy) dx + (qc dy dy + lo) with the
@@ -138,10 +140,35 @@ __device__ __forceinline__ int tri_eval(const uint32_t *s, double rlx, double rl
   return n;
 }
 
-// Perspective-correct colour at the pixel centre from the (clamped)
-// barycentric edge functions.
-__device__ __forceinline__ void tri_colour(const uint32_t *s, const double e[3], float &cr,
-                                           float &cg, float &cb) {
+// a + f (b - a), the interpolation step of the bilinear texture fetch (a
+// constant texture returns its value exactly)
+__device__ __forceinline__ float4 lerp4(float4 a, float4 b, float f) {
+  return make_float4(fmaf(f, b.x - a.x, a.x), fmaf(f, b.y - a.y, a.y), fmaf(f, b.z - a.z, a.z),
+                     fmaf(f, b.w - a.w, a.w));
+}
+
+// Bilinear RGBA at texture coordinates (u, v): texel (i, j) is centred at
+// ((i + 1/2)/w, (j + 1/2)/h); addresses clamp to the edge texels (also for
+// non-finite coordinates, so no fetch leaves the texture).
+__device__ __forceinline__ float4 tex_sample(const TexView &tv, float u, float v) {
+  const float x = fmaf(u, (float)tv.w, -0.5f), y = fmaf(v, (float)tv.h, -0.5f);
+  const float x0 = floorf(x), y0 = floorf(y);
+  const float fx = x - x0, fy = y - y0;
+  const float xc = fminf(fmaxf(x0, -1.0f), (float)tv.w), yc = fminf(fmaxf(y0, -1.0f), (float)tv.h);
+  const int i0 = min(max((int)xc, 0), tv.w - 1), i1 = min(max((int)xc + 1, 0), tv.w - 1);
+  const int j0 = min(max((int)yc, 0), tv.h - 1), j1 = min(max((int)yc + 1, 0), tv.h - 1);
+  const float4 *r0 = tv.texels + (int64_t)j0 * tv.w, *r1 = tv.texels + (int64_t)j1 * tv.w;
+  const float4 top = lerp4(r0[i0], r0[i1], fx), bot = lerp4(r1[i0], r1[i1], fx);
+  return lerp4(top, bot, fy);
+}
+
+// Colour and opacity of a triangle at the pixel centre: the per-vertex
+// colour and (with a texture) the texture coordinates interpolated
+// perspective-correctly from the (clamped) barycentric edge functions; a
+// textured triangle's colour is multiplied by the texel RGB and its opacity
+// attribute by the texel alpha.
+__device__ __forceinline__ void tri_shade(const uint32_t *s, const double e[3], const TexView &tv,
+                                          float &cr, float &cg, float &cb, float &alpha) {
   const float b0 = fmaxf((float)e[0], 0.0f), b1 = fmaxf((float)e[1], 0.0f),
               b2 = fmaxf((float)e[2], 0.0f);
   const float iz0 = __uint_as_float(s[18]), iz1 = __uint_as_float(s[19]), iz2 = __uint_as_float(s[20]);
@@ -149,6 +176,18 @@ __device__ __forceinline__ void tri_colour(const uint32_t *s, const double e[3],
   cr = (b0 * __uint_as_float(s[21]) + b1 * __uint_as_float(s[24]) + b2 * __uint_as_float(s[27])) * den;
   cg = (b0 * __uint_as_float(s[22]) + b1 * __uint_as_float(s[25]) + b2 * __uint_as_float(s[28])) * den;
   cb = (b0 * __uint_as_float(s[23]) + b1 * __uint_as_float(s[26]) + b2 * __uint_as_float(s[29])) * den;
+  alpha = __uint_as_float(s[30]);
+  if (tv.texels) {
+    const float u = (b0 * __uint_as_float(s[32]) + b1 * __uint_as_float(s[34]) +
+                     b2 * __uint_as_float(s[36])) * den;
+    const float v = (b0 * __uint_as_float(s[33]) + b1 * __uint_as_float(s[35]) +
+                     b2 * __uint_as_float(s[37])) * den;
+    const float4 t = tex_sample(tv, u, v);
+    cr *= t.x;
+    cg *= t.y;
+    cb *= t.z;
+    alpha *= t.w;
+  }
 }
 
 __device__ __forceinline__ int find_view(const ViewParams *views, int V, uint32_t tile) {

@@ -60,15 +60,24 @@ constexpr float kLog2e = 1.44269504088896341f;
 constexpr float kLn2 = 0.69314718055994531f;
 constexpr float kLog2_255 = 7.99435343685885793f;   // log2(255): alpha >= 1/255 iff p >= -this
 
-// Set-up triangle (80 B): snapped vertices after orientation normalisation,
-// per-vertex 1/z and colour/z for perspective-correct colour, alpha, and the
-// edge ownership bits of the tie rule.
+// Set-up triangle (112 B): snapped vertices after orientation normalisation,
+// per-vertex 1/z, colour/z and texture coordinates/z for perspective-correct
+// interpolation, alpha, and the edge ownership bits of the tie rule.
 struct __align__(16) TriRec {
   int32_t X[3], Y[3];
   float iz[3];
   float ciz[9];
   float alpha;
   uint32_t owned;        // bit k: edge k owns samples exactly on it
+  float uviz[6];         // (u, v) / z per vertex (zeros without a texture)
+  float pad[2];
+};
+
+// The triangles' RGBA texture as the blend kernels read it (no texture:
+// texels == nullptr).
+struct TexView {
+  const float4 *texels;  // (h, w) row-major
+  int32_t w, h;
 };
 
 // Kernel ids for the event-based profiler (same order as UMGS_K_* in unimgs.h).
@@ -181,6 +190,8 @@ struct Ctx {
   DevBuf totals;       // 2 uint64: the frame's duplicates and supertile entries
   DevBuf grec;         // V*N GaussRec
   DevBuf trec;         // V*T TriRec
+  DevBuf tex, tex_uv;  // triangle texture (tex_h, tex_w) float4 and (tex_T, 3, 2) coordinates
+  int32_t tex_w = 0, tex_h = 0, tex_T = 0;
   DevBuf scan_tmp;
   DevBuf sk[2], sv[2]; // st_cap supertile ids (uint16 or uint32) / record ids (ping-pong)
   DevBuf masks[2];     // st_cap uint64: tiles of its supertile an entry reaches (ping-pong)
@@ -251,6 +262,14 @@ uint32_t *bvh_fault_flag(Ctx *c);
 float *bvh_cam_slots(Ctx *c);
 hipError_t launch_blend(Ctx *c, float *image, float *T_final, int32_t *n_contrib,
                         float *T_entity_in, unsigned long long *pairs = nullptr);
+// The context's triangle texture as the blend kernels take it.
+inline TexView frame_texture(const Ctx *c) {
+  TexView t;
+  t.texels = c->tex_w > 0 ? (const float4 *)c->tex.p : nullptr;
+  t.w = c->tex_w;
+  t.h = c->tex_h;
+  return t;
+}
 hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32_t *nc,
                            const float *Te, const float *means, const float *scales,
                            const float *quats, const float *xform, const float *sh,

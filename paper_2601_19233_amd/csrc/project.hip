@@ -282,6 +282,7 @@ __global__ __launch_bounds__(256) void project_gaussians_kernel(const ViewParams
 __device__ uint32_t setup_triangle(const ViewParams *__restrict__ views, int N, int T,
                                    int tile_w, int tile_h, const float *__restrict__ xyz,
                                    const float *__restrict__ rgb, const float *__restrict__ alpha,
+                                   const float *__restrict__ uv,
                                    uint32_t *__restrict__ keys, uint2 *__restrict__ rects,
                                    uint64_t *__restrict__ counts, TriRec *__restrict__ trec,
                                    int j, int v) {
@@ -335,7 +336,10 @@ __device__ uint32_t setup_triangle(const ViewParams *__restrict__ views, int N, 
     rec.ciz[3 * k] = C[3 * s] * izk;
     rec.ciz[3 * k + 1] = C[3 * s + 1] * izk;
     rec.ciz[3 * k + 2] = C[3 * s + 2] * izk;
+    rec.uviz[2 * k] = uv ? uv[6 * (int64_t)j + 2 * s] * izk : 0.0f;
+    rec.uviz[2 * k + 1] = uv ? uv[6 * (int64_t)j + 2 * s + 1] * izk : 0.0f;
   }
+  rec.pad[0] = rec.pad[1] = 0.0f;
   rec.alpha = alpha[j];
   uint32_t owned = 0;
   const int ea[3] = {1, 2, 0}, eb[3] = {2, 0, 1};
@@ -374,6 +378,7 @@ __global__ __launch_bounds__(256) void setup_triangles_kernel(const ViewParams *
                                        int tile_w, int tile_h, const float *__restrict__ xyz,
                                        const float *__restrict__ rgb,
                                        const float *__restrict__ alpha,
+                                       const float *__restrict__ uv,
                                        uint32_t *__restrict__ keys, uint2 *__restrict__ rects,
                                        uint64_t *__restrict__ counts,
                                        TriRec *__restrict__ trec, uint32_t *__restrict__ minmax) {
@@ -381,7 +386,8 @@ __global__ __launch_bounds__(256) void setup_triangles_kernel(const ViewParams *
   const int v = blockIdx.y;
   uint32_t key = kCulled;
   if (j < T)
-    key = setup_triangle(views, N, T, tile_w, tile_h, xyz, rgb, alpha, keys, rects, counts, trec, j, v);
+    key = setup_triangle(views, N, T, tile_w, tile_h, xyz, rgb, alpha, uv, keys, rects, counts,
+                         trec, j, v);
   reduce_key_range(key, minmax);
 }
 
@@ -408,8 +414,10 @@ hipError_t launch_setup_triangles(Ctx *c, const float *tri_xyz, const float *tri
   ScopedTimer t(c, K_TRIANGLES);
   hipLaunchKernelGGL(setup_triangles_kernel, grid, dim3(256), 0, c->stream,
                      c->cur_views, c->N, c->T, c->tile_w, c->tile_h,
-                     tri_xyz, tri_rgb, tri_alpha, (uint32_t *)c->keys.p, (uint2 *)c->rects.p,
-                     (uint64_t *)c->counts.p, (TriRec *)c->trec.p, (uint32_t *)c->minmax.p);
+                     tri_xyz, tri_rgb, tri_alpha,
+                     c->tex_w > 0 ? (const float *)c->tex_uv.p : nullptr, (uint32_t *)c->keys.p,
+                     (uint2 *)c->rects.p, (uint64_t *)c->counts.p, (TriRec *)c->trec.p,
+                     (uint32_t *)c->minmax.p);
   return hipGetLastError();
 }
 

@@ -183,6 +183,28 @@ class Rasterizer:
             out["vertex"] = vert
         return out
 
+    # ---- textured triangles ---------------------------------------------------
+    def set_texture(self, tex=None, tri_uv=None):
+        """RGBA texture (H, W, 4) and per-vertex texture coordinates (T, 3, 2)
+        of the triangles for the following frames (umgs_set_texture); None
+        removes the texture."""
+        if tex is None:
+            self._check(self.lib.umgs_set_texture(self.h, 0, 0, None, 0, None))
+            self._tex = None
+            return
+        d = self.device
+        tex = _f32(tex, d)
+        uv = _f32(tri_uv, d)
+        if tex.dim() != 3 or tex.shape[2] != 4:
+            raise ValueError("the texture must be (H, W, 4) RGBA")
+        T = 0 if uv is None else uv.numel() // 6
+        if uv is not None and uv.numel() != 6 * T:
+            raise ValueError("tri_uv must be (T, 3, 2)")
+        with self._on_stream():
+            self._check(self.lib.umgs_set_texture(self.h, tex.shape[1], tex.shape[0], _ptr(tex), T,
+                                                  _ptr(uv)))
+        self._tex = (tex, uv)       # kept alive until the copies on the stream are done
+
     # ---- forward ------------------------------------------------------------
     def _scene_args(self, means=None, opacity=None, sh=None, scales=None, quats=None, cov3d=None,
                     tri_xyz=None, tri_rgb=None, tri_alpha=None):

@@ -45,7 +45,7 @@ def cam_centres(rng, n):
 
 
 def compare(P, cams, V, F, face_g, bary_g, dist_g, EDGE=EDGE, TOL_D=TOL_D, TOL_B=TOL_B,
-            TOL_X=TOL_X):
+            TOL_X=TOL_X, TOL_DC=1e-5):
     """Per target: exact agreement where the oracle's nearest crossing is
     clear, validity elsewhere.  Returns (clear, ambiguous) counts."""
     cand = OB.candidates(P, cams.astype(np.float64), V.astype(np.float64), F)
@@ -81,12 +81,12 @@ def compare(P, cams, V, F, face_g, bary_g, dist_g, EDGE=EDGE, TOL_D=TOL_D, TOL_B
                 Xo = b_o[i, 0] * a_ + b_o[i, 1] * b_ + (1 - b_o[i].sum()) * c_
                 assert np.linalg.norm(Xg - Xo) <= TOL_X, (i, np.linalg.norm(Xg - Xo))
                 np.testing.assert_allclose(bary_g[i], b_o[i], atol=10 * TOL_B, err_msg=str(i))
-                assert abs(dist_g[i] - bd) <= 1e-5 + 1e-5 * bd, (i, dist_g[i], bd)
+                assert abs(dist_g[i] - bd) <= TOL_DC + 1e-5 * bd, (i, dist_g[i], bd)
             else:
                 # the crossing of one of the tied cameras
                 bu = np.stack([cand["u"][i, ci, fi], cand["v"][i, ci, fi]], -1)
                 assert np.abs(bu - bary_g[i]).max(-1).min() <= TOL_B, i
-                assert abs(dist_g[i] - bd) <= TOL_D + 1e-5, (i, dist_g[i], bd)
+                assert abs(dist_g[i] - bd) <= TOL_D + TOL_DC, (i, dist_g[i], bd)
             clear += 1
             continue
         amb += 1
@@ -96,12 +96,12 @@ def compare(P, cams, V, F, face_g, bary_g, dist_g, EDGE=EDGE, TOL_D=TOL_D, TOL_B
             continue
         assert face_g[i] in set(fi.tolist()), (i, face_g[i], sorted(set(fi.tolist())))
         if np.isfinite(bd):
-            assert abs(dist_g[i] - bd) <= TOL_D + 1e-5, (i, dist_g[i], bd)
+            assert abs(dist_g[i] - bd) <= TOL_D + TOL_DC, (i, dist_g[i], bd)
         u, v = float(bary_g[i, 0]), float(bary_g[i, 1])
         assert u >= -1e-5 and v >= -1e-5 and u + v <= 1 + 1e-5, (i, u, v)
         a, b, c = Vd[F[face_g[i]]]
         X = u * a + v * b + (1 - u - v) * c
-        assert abs(np.linalg.norm(X - P[i]) - dist_g[i]) <= 1e-4, i
+        assert abs(np.linalg.norm(X - P[i]) - dist_g[i]) <= 1e-4 + TOL_DC, i
     return clear, amb
 
 
@@ -154,7 +154,7 @@ def test_binding_with_far_cameras(gpu):
     face_g = out["face"].cpu().numpy().reshape(-1)
     clear, amb = compare(P, cams, V, F, face_g, out["bary"].cpu().numpy().reshape(-1, 2).astype(np.float64),
                          out["dist"].cpu().numpy().reshape(-1).astype(np.float64),
-                         EDGE=5e-3, TOL_D=1e-3, TOL_B=3e-3, TOL_X=1e-3)
+                         EDGE=5e-3, TOL_D=1e-3, TOL_B=3e-3, TOL_X=1e-3, TOL_DC=5e-4)
     note(f"raycast far cameras: {clear} clear, {amb} ambiguous")
     assert amb <= 0.05 * (clear + amb)
     assert (face_g >= 0).mean() > 0.9
