@@ -136,7 +136,9 @@ def test_binding_with_far_cameras(gpu):
     directions: every box that holds a crossing must survive the FP32 slab
     tests, so the nearest crossings are found as from near cameras.  FP32
     crossings from that far carry errors of order |o| x 2^-24 (about 1e-4 at
-    1000), so the comparison tolerances scale with the distance."""
+    1000), and the distance |t - 1| |P - o| a few times that (7e-4 seen at
+    940), so the comparison tolerances scale with the distance; the tie
+    window stays at 1e-3 (about 4% of the targets are then ambiguous)."""
     import torch
     from paper_2601_19233_amd.render import Rasterizer
     rng = np.random.default_rng(23)
@@ -154,7 +156,7 @@ def test_binding_with_far_cameras(gpu):
     face_g = out["face"].cpu().numpy().reshape(-1)
     clear, amb = compare(P, cams, V, F, face_g, out["bary"].cpu().numpy().reshape(-1, 2).astype(np.float64),
                          out["dist"].cpu().numpy().reshape(-1).astype(np.float64),
-                         EDGE=5e-3, TOL_D=1e-3, TOL_B=3e-3, TOL_X=1e-3, TOL_DC=5e-4)
+                         EDGE=5e-3, TOL_D=1e-3, TOL_B=3e-3, TOL_X=1e-3, TOL_DC=1.5e-3)
     note(f"raycast far cameras: {clear} clear, {amb} ambiguous")
     assert amb <= 0.05 * (clear + amb)
     assert (face_g >= 0).mean() > 0.9
