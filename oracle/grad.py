@@ -103,10 +103,15 @@ def project_torch(cam, means, scales, quats, opacity, sh, degree, xform=None, me
 
 
 def render_pixels(frame: OR.Frame, pixels, means, scales, quats, opacity, sh, degree,
-                  xform=None, mean_offset=None, results=None):
+                  xform=None, mean_offset=None, results=None, tri_rgb=None, tri_alpha=None):
     """C (P,3) and T (P,) of the listed pixels as torch functions of the
-    Gaussian parameters, decisions frozen from ``frame`` (an oracle Frame
-    built at the same parameter values)."""
+    Gaussian parameters -- and of the triangles' per-vertex colours tri_rgb
+    (T,3,3) and opacity attributes tri_alpha (T,) when those are given as
+    tensors -- decisions frozen from ``frame`` (an oracle Frame built at the
+    same parameter values).  A triangle's colour at a pixel is
+    sum_k w_k rgb_k (times the texel RGB) with its perspective-correct
+    weights w_k, its opacity alpha (times the texel alpha); coverage is a
+    constant of the geometry."""
     if results is None:
         results = [frame.pixel(int(px), int(py)) for px, py in pixels]
     N = frame.N
@@ -120,10 +125,14 @@ def render_pixels(frame: OR.Frame, pixels, means, scales, quats, opacity, sh, de
     valid = ids >= 0
     isg = valid & (ids < N)
     ist = valid & (ids >= N)
-    # triangle constants: coverage and colour at each (pixel, position)
+    # triangle constants: coverage, interpolation weights of the input
+    # vertices and texel factors at each (pixel, position)
     tcov = np.zeros((P, L, 4))
-    tcol = np.zeros((P, L, 3))
-    tal = np.zeros((P, L))
+    tw = np.zeros((P, L, 3))
+    tvid = np.zeros((P, L, 3), np.int64)
+    tfac = np.ones((P, L, 4))
+    ttid = np.zeros((P, L), np.int64)
+    ts = frame.t
     for i, (px, py) in enumerate(pixels):
         cols = np.flatnonzero(ist[i])
         if cols.size == 0:
@@ -132,9 +141,27 @@ def render_pixels(frame: OR.Frame, pixels, means, scales, quats, opacity, sh, de
         if mode == OR.MODE_DIRECT:
             cov = np.ones((cols.size, 4))
         else:
-            cov = OR.sample_coverage(frame.t, tid, int(px), int(py)).astype(np.float64)
+            cov = OR.sample_coverage(ts, tid, int(px), int(py)).astype(np.float64)
         tcov[i, cols] = cov
-        tcol[i, cols], tal[i, cols] = OR.triangle_shade(frame.t, tid, int(px), int(py), frame.tex)
+        lam = OR._perspective_weights(ts, tid, int(px), int(py))
+        tw[i, cols] = lam
+        tvid[i, cols] = ts.order[tid]
+        ttid[i, cols] = tid
+        if frame.tex is not None and ts.uv is not None:
+            uvs = np.einsum("nk,nkc->nc", lam, ts.uv[tid])
+            tfac[i, cols] = OR.texture_sample(frame.tex, uvs)
+    if tri_rgb is None:
+        tri_rgb = torch.tensor(np.asarray(ts.rgb, np.float64)[np.arange(ts.rgb.shape[0])[:, None],
+                                                              np.argsort(ts.order, 1)], dtype=DT) \
+            if ts.rgb.shape[0] else torch.zeros((0, 3, 3), dtype=DT)
+    if tri_alpha is None:
+        tri_alpha = torch.tensor(ts.alpha, dtype=DT)
+    tt = torch.tensor(ttid)
+    vrgb = tri_rgb[tt[..., None], torch.tensor(tvid)] if tri_rgb.shape[0] else \
+        torch.zeros((P, L, 3, 3), dtype=DT)                          # (P,L,3 vertices,3)
+    fac = torch.tensor(tfac, dtype=DT)
+    tcol_t = (torch.tensor(tw, dtype=DT)[..., None] * vrgb).sum(2) * fac[..., :3]
+    tal_t = (tri_alpha[tt] if tri_alpha.shape[0] else torch.zeros((P, L), dtype=DT)) * fac[..., 3]
 
     mean2d, conic, rgb = project_torch(frame.cam, means, scales, quats, opacity, sh, degree,
                                        xform, mean_offset)
@@ -149,8 +176,6 @@ def render_pixels(frame: OR.Frame, pixels, means, scales, quats, opacity, sh, de
     isg_t = torch.tensor(isg)
     ist_t = torch.tensor(ist)
     tcov_t = torch.tensor(tcov, dtype=DT)
-    tcol_t = torch.tensor(tcol, dtype=DT)
-    tal_t = torch.tensor(tal, dtype=DT)
 
     C = torch.zeros((P, 3), dtype=DT)
     T = torch.ones(P, dtype=DT)
@@ -187,10 +212,11 @@ def render_pixels(frame: OR.Frame, pixels, means, scales, quats, opacity, sh, de
 def gradients(cam, pixels, dL_dC, means, scales, quats, opacity, sh, degree, tri_xyz, tri_rgb,
               tri_alpha, bg=(0.0, 0.0, 0.0), mode=OR.MODE_UNIMGS, xform=None,
               mean_offset=None, tri_uv=None, tex=None) -> Dict[str, np.ndarray]:
-    """dL/d(means, scales, quats, opacity, sh) for L = sum_p dL_dC[p] . C[p]
-    over the listed pixels.  Inputs are NumPy arrays; xform (N,3,3) and
-    mean_offset (N,3) describe a deformed scene (then ``means`` are the rest
-    means and the frame is built from means + mean_offset and A Sigma A^T)."""
+    """dL/d(means, scales, quats, opacity, sh) and dL/d(tri_rgb, tri_alpha)
+    for L = sum_p dL_dC[p] . C[p] over the listed pixels.  Inputs are NumPy
+    arrays; xform (N,3,3) and mean_offset (N,3) describe a deformed scene
+    (then ``means`` are the rest means and the frame is built from means +
+    mean_offset and A Sigma A^T)."""
     def t64(a):
         return torch.tensor(np.asarray(a, np.float64), dtype=DT, requires_grad=True)
     if xform is not None:
@@ -204,11 +230,12 @@ def gradients(cam, pixels, dL_dC, means, scales, quats, opacity, sh, degree, tri
     else:
         frame = OR.Frame(cam, means, opacity, sh, degree, tri_xyz, tri_rgb, tri_alpha,
                          scales=scales, quats=quats, bg=bg, mode=mode, tri_uv=tri_uv, tex=tex)
-    P = [t64(means), t64(scales), t64(quats), t64(opacity), t64(sh)]
+    P = [t64(means), t64(scales), t64(quats), t64(opacity), t64(sh), t64(tri_rgb), t64(tri_alpha)]
     A_t = None if xform is None else torch.tensor(np.asarray(xform, np.float64), dtype=DT)
     off_t = None if mean_offset is None else torch.tensor(np.asarray(mean_offset, np.float64), dtype=DT)
-    C, T = render_pixels(frame, pixels, *P, degree, A_t, off_t)
+    C, T = render_pixels(frame, pixels, *P[:5], degree, A_t, off_t, tri_rgb=P[5], tri_alpha=P[6])
     L = (C * torch.tensor(np.asarray(dL_dC, np.float64), dtype=DT)).sum()
     L.backward()
-    names = ["means", "scales", "quats", "opacity", "sh"]
-    return {n: p.grad.numpy() for n, p in zip(names, P)} | {"C": C.detach().numpy(), "T": T.detach().numpy()}
+    names = ["means", "scales", "quats", "opacity", "sh", "tri_rgb", "tri_alpha"]
+    return ({n: (p.grad.numpy() if p.grad is not None else np.zeros(p.shape)) for n, p in zip(names, P)}
+            | {"C": C.detach().numpy(), "T": T.detach().numpy()})

@@ -207,6 +207,7 @@ class TriSetup:
     rgb: np.ndarray          # (T,3,3) per-vertex colour, same vertex order
     alpha: np.ndarray        # (T,)
     uv: Optional[np.ndarray] = None    # (T,3,2) texture coordinates, same vertex order
+    order: Optional[np.ndarray] = None # (T,3) input vertex index of each set-up vertex
 
 
 def setup_triangles(cam, tri_xyz, tri_rgb, tri_alpha, tri_uv=None) -> TriSetup:
@@ -242,7 +243,7 @@ def setup_triangles(cam, tri_xyz, tri_rgb, tri_alpha, tri_uv=None) -> TriSetup:
     rgb = np.asarray(tri_rgb, np.float64)[r, order]
     uv = None if tri_uv is None else np.asarray(tri_uv, F32).astype(np.float64).reshape(T, 3, 2)[r, order]
     return TriSetup(valid=valid, key=key, X=X, Y=Y, area2=area2, z=z64, rgb=rgb,
-                    alpha=np.asarray(tri_alpha, np.float64), uv=uv)
+                    alpha=np.asarray(tri_alpha, np.float64), uv=uv, order=order)
 
 
 def _edges(X, Y):

@@ -187,3 +187,100 @@ def test_gradients_at_800px_sh3_match_stored_finite_differences():
         scale = np.abs(f_[ok]).max()
         bad = ok & (err > 1e-4 * np.abs(f_) + 1e-8 * scale)
         assert not bad.any(), (name, int(bad.sum()), float(np.nanmax(err)), float(scale))
+
+
+def check_fd_triangles(cam, params, deg, xyz, rgb, al, mode, tids, uv=None, tex=None, rtol=2e-5):
+    """Central differences of the forward oracle against the gradient
+    oracle's dL/d(per-vertex colour) and dL/d(opacity attribute) of the
+    listed triangles."""
+    means, scales, quats, opac, sh = params
+    px = all_pixels(cam)
+    w = np.random.default_rng(8).normal(size=(len(px), 3))
+
+    def run(rgb_, al_):
+        fr = OR.Frame(cam, means, opac, sh, deg, xyz, rgb_, al_, scales=scales, quats=quats,
+                      bg=(0.1, 0.2, 0.3), mode=mode, tri_uv=uv, tex=tex)
+        C = np.stack([fr.pixel(x, y).C for x, y in px])
+        return float((C * w).sum()), signature(fr, px)
+
+    g = OG.gradients(cam, px, w, means, scales, quats, opac, sh, deg, xyz, rgb, al,
+                     bg=(0.1, 0.2, 0.3), mode=mode, tri_uv=uv, tex=tex)
+    _, sig0 = run(rgb, al)
+    gmax = max(np.abs(g["tri_rgb"]).max(), np.abs(g["tri_alpha"]).max())
+    rgb64, al64 = rgb.astype(np.float64), al.astype(np.float64)
+    checked = skipped = nonzero = 0
+    for t in tids:
+        cases = [("tri_rgb", (t, k, ch)) for k in range(3) for ch in range(3)] + [("tri_alpha", (t,))]
+        for name, idx in cases:
+            vals, sigs = [], []
+            for s in (+1, -1):
+                r2, a2 = rgb64.copy(), al64.copy()
+                arr = r2 if name == "tri_rgb" else a2
+                arr[idx] += s * 1e-6
+                L, sig = run(r2, a2)
+                vals.append(L)
+                sigs.append(sig)
+            if sigs[0] != sig0 or sigs[1] != sig0:
+                skipped += 1
+                continue
+            fd = (vals[0] - vals[1]) / 2e-6
+            an = g[name][idx]
+            assert abs(fd - an) <= rtol * max(abs(fd), abs(an)) + 1e-7 * gmax, (name, idx, fd, an)
+            checked += 1
+            nonzero += abs(an) > 1e-6 * gmax
+    return checked, skipped, nonzero
+
+
+def visible_triangles(cam, params, deg, xyz, rgb, al, mode, uv=None, tex=None):
+    means, scales, quats, opac, sh = params
+    fr = OR.Frame(cam, means, opac, sh, deg, xyz, rgb, al, scales=scales, quats=quats,
+                  bg=(0.1, 0.2, 0.3), mode=mode, tri_uv=uv, tex=tex)
+    n = means.shape[0]
+    seen = {}
+    for x, y in all_pixels(cam):
+        for gid in fr.pixel(x, y).order:
+            if gid >= n:
+                seen[gid - n] = seen.get(gid - n, 0) + 1
+    return sorted(seen, key=lambda t: -seen[t])
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_triangle_gradients_match_finite_differences(mode):
+    """Per-vertex colours and opacity attributes of the visible triangles
+    (the semi-transparent quad's two halves and the opaque sphere's faces,
+    where entities of several triangles and partial coverage occur)."""
+    cam, means, scales, quats, opac, sh, xyz, rgb, al = mixed_scene(2)
+    params = [means, scales, quats, opac, sh]
+    tids = visible_triangles(cam, params, 0, xyz, rgb, al, mode)
+    assert len(tids) >= 4
+    tids = list(dict.fromkeys(tids[:4] + tids[-2:]))    # the most and the least covered
+    checked, skipped, nonzero = check_fd_triangles(cam, params, 0, xyz, rgb, al, mode, tids)
+    assert checked >= 35 and skipped <= checked // 4 and nonzero >= 30
+
+
+def test_triangle_gradients_opaque_and_stacked():
+    """Opaque triangles (opacity exactly 1, where a sub-sample's transmittance
+    drops to zero) behind and in front of semi-transparent ones: the
+    gradients of the triangles behind an opaque sample vanish there, those of
+    the opaque one still see the colour behind its uncovered samples."""
+    cam, means, scales, quats, opac, sh, xyz, rgb, al = mixed_scene(6)
+    al = al.copy()
+    al[:2] = 1.0                               # the quad opaque too
+    al[2::3] = 0.6                             # a third of the sphere's faces translucent
+    params = [means, scales, quats, opac, sh]
+    tids = visible_triangles(cam, params, 0, xyz, rgb, al, 0)
+    checked, skipped, nonzero = check_fd_triangles(cam, params, 0, xyz, rgb, al, 0, tids[:6])
+    assert checked >= 50 and nonzero >= 30
+
+
+def test_textured_triangle_gradients_match_finite_differences():
+    """Colour times texel RGB and opacity times texel alpha (Section 1): the
+    texture is a constant of the gradients."""
+    cam, means, scales, quats, opac, sh, xyz, rgb, al = mixed_scene(7)
+    rng = np.random.default_rng(9)
+    tex = rng.uniform(0.1, 1.0, size=(5, 7, 4))
+    uv = rng.uniform(-0.1, 1.1, size=(xyz.shape[0], 3, 2)).astype(F32)
+    params = [means, scales, quats, opac, sh]
+    tids = visible_triangles(cam, params, 0, xyz, rgb, al, 0, uv, tex)
+    checked, skipped, nonzero = check_fd_triangles(cam, params, 0, xyz, rgb, al, 0, tids[:6], uv, tex)
+    assert checked >= 50 and nonzero >= 40
