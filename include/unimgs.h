@@ -288,7 +288,7 @@ umgs_status umgs_render_batched(umgs_ctx *ctx, int32_t V, const umgs_camera *cam
  * dL_dopacity (N,), dL_dsh (N,(deg+1)^2,3); written when accumulate is 0,
  * added to their contents otherwise (to sum over groups of views rendered
  * by separate frames).
- * Triangles receive no gradients.  Float atomics make the summation order,
+ * Triangle gradients come from umgs_backward_triangles.  Float atomics make the summation order,
  * hence the last bits, run-dependent.  Errors: STATE without a blended
  * frame; UNSUPPORTED for UMGS_MODE_ONE_ENTITY and UMGS_MODE_LITERAL_T;
  * INVALID_ARG for NULL arrays. */
@@ -297,6 +297,25 @@ umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_
                           const float *scales, const float *quats, const float *xform,
                           const float *sh, float *dL_dmeans, float *dL_dscales, float *dL_dquats,
                           float *dL_dopacity, float *dL_dsh, int32_t accumulate);
+
+/* Gradients of L with respect to the triangles of the last blended frame:
+ * their per-vertex colours and opacity attributes, through the sub-sample
+ * entity blend of Eq. 7-9 (UMGS_MODE_UNIMGS) or the per-triangle blend of
+ * UMGS_MODE_DIRECT, with coverage held fixed (a step function of the
+ * geometry, whose derivative is zero almost everywhere).  The per-pixel
+ * inputs are those of umgs_backward.  A textured triangle's colour is
+ * rgb x texel RGB and its opacity alpha x texel alpha; the texels are
+ * constants here (no texture gradient).
+ * Outputs [device]: dL_dtri_rgb (T,3,3) in the vertex order of tri_rgb,
+ * dL_dtri_alpha (T,); summed over the frame's views; written when
+ * accumulate is 0, added to their contents otherwise.  Independent of
+ * umgs_backward (either may run first, or alone).  Float atomics make the
+ * last bits run-dependent.  Errors: STATE without a blended frame;
+ * UNSUPPORTED for UMGS_MODE_ONE_ENTITY and UMGS_MODE_LITERAL_T;
+ * INVALID_ARG for NULL arrays. */
+umgs_status umgs_backward_triangles(umgs_ctx *ctx, const float *dL_dimage, const float *T_final,
+                                    const int32_t *n_contrib, const float *T_entity_in,
+                                    float *dL_dtri_rgb, float *dL_dtri_alpha, int32_t accumulate);
 
 /* ---- graphs: capture one step, replay it ----------------------------------- */
 
@@ -382,7 +401,8 @@ enum { UMGS_K_VERTEX_FRAMES = 0, UMGS_K_TRANSFER = 1, UMGS_K_PROJECT = 2, UMGS_K
        UMGS_K_SCAN = 4, UMGS_K_EMIT = 5, UMGS_K_SORT_UPSWEEP = 6, UMGS_K_SORT_SCAN = 7,
        UMGS_K_SORT_DOWNSWEEP = 8, UMGS_K_RANGES = 9, UMGS_K_BLEND = 10, UMGS_K_BLEND_BWD = 11,
        UMGS_K_PROJECT_BWD = 12, UMGS_K_DEPTH_SORT = 13, UMGS_K_TILE_COUNT = 14,
-       UMGS_K_TILE_SCATTER = 15, UMGS_K_ST_MASK = 16, UMGS_K_COUNT = 17 };
+       UMGS_K_TILE_SCATTER = 15, UMGS_K_ST_MASK = 16, UMGS_K_BLEND_BWD_TRI = 17,
+       UMGS_K_COUNT = 18 };
 umgs_status umgs_set_profiling(umgs_ctx *ctx, int32_t enable);
 umgs_status umgs_profile_read(umgs_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms);
 

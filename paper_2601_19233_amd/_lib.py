@@ -62,6 +62,7 @@ PROTOTYPES = {
     "umgs_view_dups": (C.c_int, [P, C.POINTER(I64)]),
     "umgs_copy_state": (C.c_int, [P, I32, P, I64]),
     "umgs_backward": (C.c_int, [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, I32]),
+    "umgs_backward_triangles": (C.c_int, [P, P, P, P, P, P, P, I32]),
     "umgs_set_profiling": (C.c_int, [P, I32]),
     "umgs_profile_read": (C.c_int, [P, I32, C.POINTER(I64), C.POINTER(C.c_double)]),
 }
@@ -69,7 +70,7 @@ PROTOTYPES = {
 KERNEL_NAMES = ["vertex_frames", "transfer", "project_gaussians", "setup_triangles", "count_scan",
                 "emit_keys", "sort_upsweep", "sort_scan", "sort_downsweep", "tile_ranges", "blend",
                 "blend_backward", "project_backward", "depth_sort", "tile_count", "tile_scatter",
-                "st_mask"]
+                "st_mask", "blend_backward_tri"]
 
 _lib = None
 

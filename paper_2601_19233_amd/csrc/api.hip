@@ -689,6 +689,24 @@ umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_
                    "backward launch");
 }
 
+umgs_status umgs_backward_triangles(umgs_ctx *ctx, const float *dL_dimage, const float *T_final,
+                                    const int32_t *n_contrib, const float *T_entity_in,
+                                    float *dL_dtri_rgb, float *dL_dtri_alpha, int32_t accumulate) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->stage < 4)
+    return fail(c, UMGS_ERR_STATE, "umgs_backward_triangles: no blended frame on this context");
+  if (c->mode != UMGS_MODE_UNIMGS && c->mode != UMGS_MODE_DIRECT)
+    return fail(c, UMGS_ERR_UNSUPPORTED, "umgs_backward_triangles: mode %d has no backward", c->mode);
+  if (!dL_dimage || !T_final || !n_contrib || !T_entity_in)
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_backward_triangles: NULL per-pixel array");
+  if (c->T > 0 && (!dL_dtri_rgb || !dL_dtri_alpha))
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_backward_triangles: NULL triangle array");
+  return hip_check(c, launch_backward_triangles(c, dL_dimage, T_final, n_contrib, T_entity_in,
+                                                dL_dtri_rgb, dL_dtri_alpha, accumulate != 0),
+                   "triangle backward launch");
+}
+
 // Reads the device frame info into the host copies (synchronizes).
 static umgs_status read_frame_info(Ctx *c, FrameInfo *out) {
   memset(out, 0, sizeof *out);

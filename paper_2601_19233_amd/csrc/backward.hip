@@ -695,17 +695,13 @@ hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v);
 
 namespace {
 
-template <int TW, int TH, int SPLIT>
-hipError_t launch_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int32_t *nc, const float *Te) {
-  // the backward's own LDS batch of staged fragments, at most 64 (one per
-  // lane; 8 KB per one-wave workgroup, so LDS does not limit the waves per CU)
-  const int batch = std::min(c->frag_batch, 64);
-  const size_t lds = (size_t)batch * kSlotWords * sizeof(uint32_t);
+template <int TW, int TH>
+hipError_t launch_walk_order_tw(Ctx *c, const int32_t *nc, const uint32_t **order_out) {
   const uint32_t nt = (uint32_t)c->n_tiles;
   uint32_t *cnt = (uint32_t *)c->bwd_order.p;
   uint32_t *key = cnt + kBwdBuckets;
   uint32_t *order = key + nt;
-  ScopedTimer t(c, K_BLEND_BWD);
+  *order_out = order;
   hipError_t e = launch_fill_u32(c, cnt, kBwdBuckets, 0u);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((walk_key_kernel<TW, TH>), dim3(nt), dim3(64), 0, c->stream, c->cur_views,
@@ -715,7 +711,20 @@ hipError_t launch_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int32_t
   hipLaunchKernelGGL(walk_scan_kernel, dim3(1), dim3(64), 0, c->stream, cnt);
   hipLaunchKernelGGL(walk_scatter_kernel, dim3(ceil_div(nt, 256)), dim3(256), 0, c->stream, key,
                      nt, cnt, order);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+template <int TW, int TH, int SPLIT>
+hipError_t launch_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int32_t *nc, const float *Te) {
+  // the backward's own LDS batch of staged fragments, at most 64 (one per
+  // lane; 10 KB per one-wave workgroup, so LDS does not limit the waves per CU)
+  const int batch = std::min(c->frag_batch, 64);
+  const size_t lds = (size_t)batch * kSlotWords * sizeof(uint32_t);
+  const uint32_t nt = (uint32_t)c->n_tiles;
+  ScopedTimer t(c, K_BLEND_BWD);
+  const uint32_t *order = nullptr;
+  hipError_t e = launch_walk_order_tw<TW, TH>(c, nc, &order);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((blend_backward_kernel<TW, TH, SPLIT>), dim3(nt * SPLIT),
                      dim3(64), lds, c->stream, order, c->cur_views, c->V, c->N, c->T, c->mode,
                      batch, c->bg[0], c->bg[1], c->bg[2], (const uint2 *)c->ranges.p,
@@ -729,6 +738,12 @@ hipError_t launch_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int32_t
 }  // namespace
 
 hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v);
+
+hipError_t launch_walk_order(Ctx *c, const int32_t *nc, const uint32_t **order) {
+  if (c->tile_w == 16 && c->tile_h == 16) return launch_walk_order_tw<16, 16>(c, nc, order);
+  if (c->tile_w == 8 && c->tile_h == 8) return launch_walk_order_tw<8, 8>(c, nc, order);
+  return launch_walk_order_tw<32, 8>(c, nc, order);
+}
 
 hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32_t *nc,
                            const float *Te, const float *means, const float *scales,

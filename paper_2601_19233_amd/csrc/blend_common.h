@@ -94,22 +94,20 @@ __device__ __forceinline__ bool gauss_terms(const uint32_t *s, float pcx, float 
   return inside && alpha >= kAlphaMin;
 }
 
-// Triangle: edge functions at the pixel centre (exact) and sub-sample
-// coverage.  Returns the number of covered samples (0: not a fragment of
-// this pixel).  In direct mode only the pixel centre is tested and o[] is 1.
-__device__ __forceinline__ int tri_eval(const uint32_t *s, double rlx, double rly, bool direct,
-                                        double e[3], float o[4]) {
-  const double *dv = (const double *)s;
-  const uint32_t owned = s[31] >> 8;
+// Sub-sample coverage from the exact edge values e[k] at the pixel centre,
+// the edge steps dxk/dyk, the bound dmax[k] of the sample offset terms and
+// the edge ownership bits.  Returns the number of covered samples (0: not a
+// fragment of this pixel).  In direct mode only the pixel centre is tested
+// and o[] is 1.
+__device__ __forceinline__ int tri_cover(const double e[3], const double dxk[3], const double dyk[3],
+                                         const double dmax[3], uint32_t owned, bool direct,
+                                         float o[4]) {
   bool any = true, full = true;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const double dxk = (double)(int32_t)s[12 + k];
-    const double dyk = (double)(int32_t)s[15 + k];
-    e[k] = fma(dxk, rly, fma(-dyk, rlx, dv[k]));
     const double own = (double)((owned >> k) & 1u);
-    any = any && (e[k] + dv[3 + k] + own > 0.0);
-    full = full && (e[k] - dv[3 + k] > 0.0);
+    any = any && (e[k] + dmax[k] + own > 0.0);
+    full = full && (e[k] - dmax[k] > 0.0);
   }
   if (!any) return 0;
   if (direct) {
@@ -129,15 +127,48 @@ __device__ __forceinline__ int tri_eval(const uint32_t *s, double rlx, double rl
     bool c = true;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double dxk = (double)(int32_t)s[12 + k];
-      const double dyk = (double)(int32_t)s[15 + k];
-      const double ej = fma(dxk, (double)sample_oy(j), fma(-dyk, (double)sample_ox(j), e[k]));
+      const double ej = fma(dxk[k], (double)sample_oy(j), fma(-dyk[k], (double)sample_ox(j), e[k]));
       c = c && (ej + (double)((owned >> k) & 1u) > 0.0);
     }
     o[j] = c ? 1.0f : 0.0f;
     n += c;
   }
   return n;
+}
+
+// Triangle staged in an LDS slot: edge functions at the pixel (offset rlx,
+// rly from the tile's first pixel centre, 1/256 px) and sub-sample coverage.
+__device__ __forceinline__ int tri_eval(const uint32_t *s, double rlx, double rly, bool direct,
+                                        double e[3], float o[4]) {
+  const double *dv = (const double *)s;
+  double dxk[3], dyk[3], dmax[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    dxk[k] = (double)(int32_t)s[12 + k];
+    dyk[k] = (double)(int32_t)s[15 + k];
+    e[k] = fma(dxk[k], rly, fma(-dyk[k], rlx, dv[k]));
+    dmax[k] = dv[3 + k];
+  }
+  return tri_cover(e, dxk, dyk, dmax, s[31] >> 8, direct, o);
+}
+
+// The same from the triangle's record at the pixel centre (Px, Py) in
+// 1/256 px: the edge functions are the same integers (exact in FP64 in both
+// forms), so coverage and shading are bit-identical to tri_eval's.
+__device__ __forceinline__ int tri_eval_rec(const TriRec &tr, int64_t Px, int64_t Py, bool direct,
+                                            double e[3], float o[4]) {
+  const int ea[3] = {1, 2, 0}, eb[3] = {2, 0, 1};
+  double dxk[3], dyk[3], dmax[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int64_t dx = (int64_t)tr.X[eb[k]] - tr.X[ea[k]];
+    const int64_t dy = (int64_t)tr.Y[eb[k]] - tr.Y[ea[k]];
+    e[k] = (double)(dx * (Py - tr.Y[ea[k]]) - dy * (Px - tr.X[ea[k]]));
+    dxk[k] = (double)dx;
+    dyk[k] = (double)dy;
+    dmax[k] = 96.0 * (double)((dx < 0 ? -dx : dx) + (dy < 0 ? -dy : dy));
+  }
+  return tri_cover(e, dxk, dyk, dmax, tr.owned, direct, o);
 }
 
 // a + f (b - a), the interpolation step of the bilinear texture fetch (a
@@ -162,32 +193,59 @@ __device__ __forceinline__ float4 tex_sample(const TexView &tv, float u, float v
   return lerp4(top, bot, fy);
 }
 
+// A triangle's shading words, read from its LDS slot or from its record
+// (slot word numbering: 18-20 1/z, 21-29 colour/z, 30 alpha, 32-37 (u, v)/z).
+struct SlotWords {
+  const uint32_t *s;
+  __device__ __forceinline__ float operator()(int i) const { return __uint_as_float(s[i]); }
+};
+struct RecWords {
+  const TriRec *r;
+  __device__ __forceinline__ float operator()(int i) const {
+    return i < 21 ? r->iz[i - 18] : i < 30 ? r->ciz[i - 21] : i == 30 ? r->alpha : r->uviz[i - 32];
+  }
+};
+
 // Colour and opacity of a triangle at the pixel centre: the per-vertex
 // colour and (with a texture) the texture coordinates interpolated
 // perspective-correctly from the (clamped) barycentric edge functions; a
 // textured triangle's colour is multiplied by the texel RGB and its opacity
-// attribute by the texel alpha.
-__device__ __forceinline__ void tri_shade(const uint32_t *s, const double e[3], const TexView &tv,
-                                          float &cr, float &cg, float &cb, float &alpha) {
+// attribute by the texel alpha.  Optionally also returns the interpolation
+// weights w[k] of the vertices (colour = sum_k w_k rgb_k, times the texel)
+// and the texel (1 without a texture).
+template <class Words>
+__device__ __forceinline__ void tri_shade_w(const Words &at, const double e[3], const TexView &tv,
+                                            float &cr, float &cg, float &cb, float &alpha,
+                                            float *w = nullptr, float4 *texel = nullptr) {
   const float b0 = fmaxf((float)e[0], 0.0f), b1 = fmaxf((float)e[1], 0.0f),
               b2 = fmaxf((float)e[2], 0.0f);
-  const float iz0 = __uint_as_float(s[18]), iz1 = __uint_as_float(s[19]), iz2 = __uint_as_float(s[20]);
+  const float iz0 = at(18), iz1 = at(19), iz2 = at(20);
   const float den = 1.0f / (b0 * iz0 + b1 * iz1 + b2 * iz2);
-  cr = (b0 * __uint_as_float(s[21]) + b1 * __uint_as_float(s[24]) + b2 * __uint_as_float(s[27])) * den;
-  cg = (b0 * __uint_as_float(s[22]) + b1 * __uint_as_float(s[25]) + b2 * __uint_as_float(s[28])) * den;
-  cb = (b0 * __uint_as_float(s[23]) + b1 * __uint_as_float(s[26]) + b2 * __uint_as_float(s[29])) * den;
-  alpha = __uint_as_float(s[30]);
+  cr = (b0 * at(21) + b1 * at(24) + b2 * at(27)) * den;
+  cg = (b0 * at(22) + b1 * at(25) + b2 * at(28)) * den;
+  cb = (b0 * at(23) + b1 * at(26) + b2 * at(29)) * den;
+  alpha = at(30);
+  if (w) {
+    w[0] = b0 * iz0 * den;
+    w[1] = b1 * iz1 * den;
+    w[2] = b2 * iz2 * den;
+  }
+  if (texel) *texel = make_float4(1.0f, 1.0f, 1.0f, 1.0f);
   if (tv.texels) {
-    const float u = (b0 * __uint_as_float(s[32]) + b1 * __uint_as_float(s[34]) +
-                     b2 * __uint_as_float(s[36])) * den;
-    const float v = (b0 * __uint_as_float(s[33]) + b1 * __uint_as_float(s[35]) +
-                     b2 * __uint_as_float(s[37])) * den;
+    const float u = (b0 * at(32) + b1 * at(34) + b2 * at(36)) * den;
+    const float v = (b0 * at(33) + b1 * at(35) + b2 * at(37)) * den;
     const float4 t = tex_sample(tv, u, v);
     cr *= t.x;
     cg *= t.y;
     cb *= t.z;
     alpha *= t.w;
+    if (texel) *texel = t;
   }
+}
+
+__device__ __forceinline__ void tri_shade(const uint32_t *s, const double e[3], const TexView &tv,
+                                          float &cr, float &cg, float &cb, float &alpha) {
+  tri_shade_w(SlotWords{s}, e, tv, cr, cg, cb, alpha);
 }
 
 __device__ __forceinline__ int find_view(const ViewParams *views, int V, uint32_t tile) {

@@ -70,7 +70,8 @@ struct __align__(16) TriRec {
   float alpha;
   uint32_t owned;        // bit k: edge k owns samples exactly on it
   float uviz[6];         // (u, v) / z per vertex (zeros without a texture)
-  float pad[2];
+  uint32_t swapped;      // 1: record vertices 1, 2 are input vertices 2, 1
+  float pad;
 };
 
 // The triangles' RGBA texture as the blend kernels read it (no texture:
@@ -84,7 +85,7 @@ struct TexView {
 enum KernelId {
   K_VERTEX_FRAMES = 0, K_TRANSFER, K_PROJECT, K_TRIANGLES, K_SCAN, K_EMIT, K_SORT_UPSWEEP,
   K_SORT_SCAN, K_SORT_DOWNSWEEP, K_RANGES, K_BLEND, K_BLEND_BWD, K_PROJECT_BWD, K_DEPTH_SORT,
-  K_TILE_COUNT, K_TILE_SCATTER, K_ST_MASK, K_COUNT
+  K_TILE_COUNT, K_TILE_SCATTER, K_ST_MASK, K_BLEND_BWD_TRI, K_COUNT
 };
 
 struct Prof {
@@ -270,6 +271,12 @@ inline TexView frame_texture(const Ctx *c) {
   t.h = c->tex_h;
   return t;
 }
+// Heaviest-first tile order of the backward walks (bwd_order); returns the
+// order array through *order.
+hipError_t launch_walk_order(Ctx *c, const int32_t *nc, const uint32_t **order);
+hipError_t launch_backward_triangles(Ctx *c, const float *dL, const float *Tf, const int32_t *nc,
+                                     const float *Te, float *d_rgb, float *d_alpha,
+                                     bool accumulate);
 hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32_t *nc,
                            const float *Te, const float *means, const float *scales,
                            const float *quats, const float *xform, const float *sh,

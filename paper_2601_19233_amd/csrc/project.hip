@@ -339,7 +339,8 @@ __device__ uint32_t setup_triangle(const ViewParams *__restrict__ views, int N, 
     rec.uviz[2 * k] = uv ? uv[6 * (int64_t)j + 2 * s] * izk : 0.0f;
     rec.uviz[2 * k + 1] = uv ? uv[6 * (int64_t)j + 2 * s + 1] * izk : 0.0f;
   }
-  rec.pad[0] = rec.pad[1] = 0.0f;
+  rec.swapped = area2 < 0 ? 1u : 0u;
+  rec.pad = 0.0f;
   rec.alpha = alpha[j];
   uint32_t owned = 0;
   const int ea[3] = {1, 2, 0}, eb[3] = {2, 0, 1};

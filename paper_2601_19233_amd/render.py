@@ -304,6 +304,25 @@ class Rasterizer:
                 1 if accumulate else 0))
         return out
 
+    def backward_triangles(self, dL_dimage: torch.Tensor, fwd: Dict[str, torch.Tensor],
+                           out: Optional[Dict] = None, accumulate: bool = False
+                           ) -> Dict[str, torch.Tensor]:
+        """Gradients of the last blended frame with respect to the triangles'
+        per-vertex colours (T,3,3) and opacity attributes (T,)
+        (umgs_backward_triangles); ``fwd`` is the dict returned by blend()."""
+        d = self.device
+        dL = _f32(dL_dimage, d)
+        T = self.T
+        if out is None:
+            out = dict(tri_rgb=torch.empty((T, 3, 3), device=d), tri_alpha=torch.empty((T,), device=d))
+        if dL.numel() != fwd["image"].numel():
+            raise ValueError("dL_dimage must have the image's shape")
+        with self._on_stream():
+            self._check(self.lib.umgs_backward_triangles(
+                self.h, _ptr(dL), _ptr(fwd["T_final"]), _ptr(fwd["n_contrib"]), _ptr(fwd["T_entity_in"]),
+                _ptr(out["tri_rgb"]), _ptr(out["tri_alpha"]), 1 if accumulate else 0))
+        return out
+
     def render_batched(self, cams: Sequence, view_offsets: Optional[Sequence[int]] = None,
                        out: Optional[Dict] = None, **scene) -> Dict[str, torch.Tensor]:
         """umgs_render_batched: project, bin, sort and blend V views in one
