@@ -57,6 +57,15 @@ OPS_PER_TRI_PAIR = 60
 # the four sub-samples' colour and transmittance, 9 each).
 OPS_PER_GAUSS_PAIR_BWD = 51
 OPS_PER_TRI_PAIR_BWD = 96
+# ... and per pair of the triangle backward's walk (from each pixel's last
+# blended fragment down to its tile's first triangle): a Gaussian costs 23
+# (alpha 14, T in front 3, the colour behind 6), a triangle 126 (its walk
+# step as in the backward, 96, and its gradient: the four sub-samples'
+# visibility and colour terms 16, the 10 products added to the tile's
+# accumulators 14); the closing re-walk of each entity is extra work, not
+# counted.
+OPS_PER_GAUSS_PAIR_TRI_BWD = 23
+OPS_PER_TRI_PAIR_TRI_BWD = 126
 
 
 def log(msg):
@@ -220,7 +229,7 @@ def algorithmic_bytes(r, scene, n_dup, n_rec, views=1):
     return out, n1
 
 
-def kernel_rooflines(prof, algo_bytes, traffic=None, pairs=None, bpairs=None):
+def kernel_rooflines(prof, algo_bytes, traffic=None, pairs=None, bpairs=None, tpairs=None):
     """Roofline entry per timed kernel: algorithmic work per launch over the
     launch's average duration (the library's HIP events on its stream)."""
     traffic = traffic or {}
@@ -244,6 +253,13 @@ def kernel_rooflines(prof, algo_bytes, traffic=None, pairs=None, bpairs=None):
         if k == "blend_backward" and bpairs is not None:
             g, t = bpairs["gauss"], bpairs["tri"]
             ops = OPS_PER_GAUSS_PAIR_BWD * g + OPS_PER_TRI_PAIR_BWD * t
+            ach = ops / (per_launch[k] * 1e-3) / 1e9
+            return {"kernel": k, "bound": "alu", "achieved": round(ach, 1), "peak": VALU_PEAK_GOPS,
+                    "unit": "Gop/s", "frac": round(ach / VALU_PEAK_GOPS, 4), "traffic": traffic.get(k),
+                    "ms_per_launch": round(per_launch[k], 4), "gauss_pairs": g, "tri_pairs": t}
+        if k == "blend_backward_tri" and tpairs is not None:
+            g, t = tpairs["gauss"], tpairs["tri"]
+            ops = OPS_PER_GAUSS_PAIR_TRI_BWD * g + OPS_PER_TRI_PAIR_TRI_BWD * t
             ach = ops / (per_launch[k] * 1e-3) / 1e9
             return {"kernel": k, "bound": "alu", "achieved": round(ach, 1), "peak": VALU_PEAK_GOPS,
                     "unit": "Gop/s", "frac": round(ach / VALU_PEAK_GOPS, 4), "traffic": traffic.get(k),
@@ -668,6 +684,30 @@ def main():
                "stages_ms": {k: round(v[1] / args.steps, 4) for k, v in prof_fb.items()},
                "roofline": rl_fb.get("blend_backward")}
     log(f"fwd+bwd {ms_fb:.3f} ms/step")
+
+    # ---- triangle colour and opacity gradients of the same frame ------------
+    o = fwd_state["out"]
+    tg = r.backward_triangles(dL, o)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        r.backward_triangles(dL, o, out=tg)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_tri = e0.elapsed_time(e1) / args.steps
+    r.set_profiling(True)
+    for _ in range(args.steps):
+        r.backward_triangles(dL, o, out=tg)
+    prof_tri = r.profile()
+    r.set_profiling(False)
+    tpairs = r.backward_pairs(o["n_contrib"], triangles=True)
+    log(f"triangle backward {ms_tri:.3f} ms, work {tpairs}")
+    fwd_bwd["triangles"] = {
+        "ms_per_call": round(ms_tri, 4),
+        "path": "umgs_backward_triangles on the same frame: dL/d(per-vertex colour, opacity)",
+        "stages_ms": {k: round(v[1] / args.steps, 4) for k, v in prof_tri.items()},
+        "roofline": kernel_rooflines(prof_tri, {}, traffic, tpairs=tpairs).get("blend_backward_tri")}
+    del tg
 
     # ---- the same frame captured in one HIP graph ---------------------------
     # (sizes stay on the device after one eager frame and a reservation, so

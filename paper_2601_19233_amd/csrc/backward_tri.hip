@@ -20,7 +20,8 @@
 // entity closes, the pixel walks the span again from the back, keeping s^j
 // exactly, and takes each triangle's t^j_{i-1} as the product over the
 // span's triangles in front of it.  That costs O(n^2) triangle evaluations
-// per entity, and entities hold one or two triangles at most pixels.
+// per entity of n triangles; most entities hold one triangle, whose terms
+// the first walk keeps (t = 1, s^j = B) and emits at the close directly.
 // Direct mode (triangles blended like Gaussians) needs no entity:
 // dL/dc = T a g, dL/da = T (c . g - B).
 //
@@ -46,6 +47,13 @@ struct TriPix {
   float p0, p1, p2, p3;
   int fpos, bpos;   // list positions of the open entity's front and back triangles
   float Bback;      // B . g behind the open entity
+  int n_ent;        // its triangles so far
+  // the gradient terms of its back triangle as if it were alone (t = 1,
+  // s^j = B), without the factor T_in: what an entity of one triangle (most
+  // of them) emits at its close, with no second walk
+  uint32_t c_rank, c_t;
+  float c_da, c_vis, c_w0, c_w1, c_w2;
+  float4 c_texel;
 };
 
 struct TriCtx {
@@ -61,20 +69,29 @@ struct TriCtx {
   float *d_rgb, *d_alpha;
 };
 
+// Rank of list position pos among the tile's triangle fragments if it has
+// an LDS accumulator, else kNoRank.
+constexpr uint32_t kNoRank = 0xFFFFFFFFu;
+
+__device__ __forceinline__ uint32_t tri_rank(const uint32_t *tpos, int ntab, int pos) {
+  int lo = 0, hi = ntab;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if ((int)tpos[mid] < pos) lo = mid + 1; else hi = mid;
+  }
+  return (lo < ntab && (int)tpos[lo] == pos) ? (uint32_t)lo : kNoRank;
+}
+
 // Adds one (pixel, triangle) term: dL/d(effective opacity) da and the
 // colour gradient vis g (vis = T_in a mean_j o^j t^j), spread over the
-// vertices with the interpolation weights w and the texel.
-__device__ __forceinline__ void emit(const TriCtx &x, int pos, int64_t t, float da, float vis,
+// vertices with the interpolation weights w and the texel; rank is the
+// triangle's accumulator (kNoRank: global memory).
+__device__ __forceinline__ void emit(const TriCtx &x, uint32_t rank, int64_t t, float da, float vis,
                                      const float w[3], float4 texel, const TriPix &q) {
   const float da_attr = da * texel.w;
   const float gc[3] = {vis * texel.x * q.dC0, vis * texel.y * q.dC1, vis * texel.z * q.dC2};
-  int lo = 0, hi = x.ntab;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if ((int)x.tpos[mid] < pos) lo = mid + 1; else hi = mid;
-  }
-  if (lo < x.ntab && (int)x.tpos[lo] == pos) {
-    float *a = x.acc + kTriAcc * lo;
+  if (rank != kNoRank) {
+    float *a = x.acc + kTriAcc * rank;
     atomicAdd(a, da_attr);
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -100,7 +117,7 @@ __device__ __forceinline__ int64_t tri_at(const TriCtx &x, int pos) {
 
 // The gradients of the entity [q.fpos, q.bpos] of this pixel, entered with
 // transmittance T_in.
-__device__ void close_entity(const TriCtx &x, const TriPix &q, float T_in) {
+__device__ void rewalk_entity(const TriCtx &x, const TriPix &q, float T_in) {
   float s0 = q.Bback, s1 = q.Bback, s2 = q.Bback, s3 = q.Bback;
   for (int pi = q.bpos; pi >= q.fpos; --pi) {
     const int64_t ti = tri_at(x, pi);
@@ -130,11 +147,20 @@ __device__ void close_entity(const TriCtx &x, const TriPix &q, float T_in) {
     const float v0 = o[0] * t0, v1 = o[1] * t1, v2 = o[2] * t2, v3 = o[3] * t3;
     const float da = T_in * 0.25f * ((v0 * (cd - s0) + v1 * (cd - s1)) + (v2 * (cd - s2) + v3 * (cd - s3)));
     const float vis = T_in * a * 0.25f * ((v0 + v1) + (v2 + v3));
-    emit(x, pi, ti, da, vis, w, texel, q);
+    emit(x, tri_rank(x.tpos, x.ntab, pi), ti, da, vis, w, texel, q);
     s0 = fmaf(o[0] * a, cd - s0, s0);
     s1 = fmaf(o[1] * a, cd - s1, s1);
     s2 = fmaf(o[2] * a, cd - s2, s2);
     s3 = fmaf(o[3] * a, cd - s3, s3);
+  }
+}
+
+__device__ __forceinline__ void close_entity(const TriCtx &x, const TriPix &q, float T_in) {
+  if (q.n_ent == 1) {
+    const float w[3] = {q.c_w0, q.c_w1, q.c_w2};
+    emit(x, q.c_rank, q.c_t, T_in * q.c_da, T_in * q.c_vis, w, q.c_texel, q);
+  } else {
+    rewalk_entity(x, q, T_in);
   }
 }
 
@@ -153,7 +179,7 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
   uint32_t *slots = lds;                                   // batch * kSlotWords
   uint32_t *tpos = lds + batch * kSlotWords;               // kTriTab
   float *acc = (float *)(tpos + kTriTab);                  // kTriTab * kTriAcc
-  __shared__ int red[NW];
+  __shared__ int red[NW], red2[NW];
   __shared__ int s_ntri;
   const uint32_t *vals = fi->sorted_in ? v1 : v0;
 
@@ -194,6 +220,11 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
   q.p0 = q.p1 = q.p2 = q.p3 = 1.f;
   q.fpos = q.bpos = 0;
   q.Bback = 0.f;
+  q.n_ent = 0;
+  q.c_rank = kNoRank;
+  q.c_t = 0;
+  q.c_da = q.c_vis = q.c_w0 = q.c_w1 = q.c_w2 = 0.f;
+  q.c_texel = make_float4(1.f, 1.f, 1.f, 1.f);
 
   int m = q.last;
 #pragma unroll
@@ -229,10 +260,50 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
   if (ntri == 0) return;                      // no triangle blended in this tile
   const int ntab = min(ntri, kTriTab);
   for (int i = tid; i < ntab * kTriAcc; i += NT) acc[i] = 0.0f;
-  const int wlo = (int)tpos[0];               // frontmost triangle: the walk ends there
-  __syncthreads();
-
   const TriRec *vrec = trec + (int64_t)v * T;
+
+  // The pixel's frontmost covering triangle among the tabled ones (in
+  // batches staged like the walk's); a pixel that blends no triangle walks
+  // nothing, the others walk from their last blended fragment down to it.
+  int first_cov = q.last;
+  for (int c0 = 0; c0 < ntab; c0 += batch) {
+    const int cn = min(batch, ntab - c0);
+    __syncthreads();
+    if (tid < cn) {
+      const int64_t local = (int64_t)vals[rg.x + tpos[c0 + tid]] - rbase;
+      stage_tri(slots + tid * kSlotWords, vrec[local - N], P0x, P0y);
+    }
+    __syncthreads();
+    for (int f = 0; f < cn && first_cov == q.last; ++f) {
+      const int pos = (int)tpos[c0 + f];
+      if (pos >= q.last) break;
+      double e[3];
+      float o[4];
+      if (tri_eval(slots + f * kSlotWords, rlx, rly, direct, e, o) > 0) first_cov = pos;
+    }
+  }
+  // triangles past the table are at later positions; one may still cover
+  if (first_cov == q.last && ntri > ntab) first_cov = min(q.last, (int)tpos[ntab - 1] + 1);
+  if (first_cov >= q.last) q.last = 0;
+  int w_hi = q.last, w_lo = q.last > 0 ? first_cov : 0x7FFFFFFF;
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) {
+    w_hi = max(w_hi, __shfl_xor(w_hi, o, 64));
+    w_lo = min(w_lo, __shfl_xor(w_lo, o, 64));
+  }
+  __syncthreads();
+  if (lane == 0) {
+    red[wid] = w_hi;
+    red2[wid] = w_lo;
+  }
+  __syncthreads();
+  int t_hi = 0, t_lo = 0x7FFFFFFF;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    t_hi = max(t_hi, red[w]);
+    t_lo = min(t_lo, red2[w]);
+  }
+  __syncthreads();
   TriCtx x;
   x.vals = vals + rg.x;
   x.rbase = rbase;
@@ -247,8 +318,8 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
   x.d_rgb = d_rgb;
   x.d_alpha = d_alpha;
 
-  for (int bend = max_last; bend > wlo; bend -= batch) {
-    const int bstart = max(wlo, bend - batch);
+  for (int bend = t_hi; bend > t_lo; bend -= batch) {
+    const int bstart = max(t_lo, bend - batch);
     const int bn = bend - bstart;
     if (tid < bn) {
       uint32_t *s = slots + tid * kSlotWords;
@@ -258,10 +329,14 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
         stage_gauss(s, grec[rec], rec);
       } else {
         stage_tri(s, vrec[local - N], P0x, P0y);
+        s[38] = tri_rank(tpos, ntab, bstart + tid);
+        s[39] = (uint32_t)(local - N);
       }
     }
     __syncthreads();
-    for (int f = bn - 1; f >= 0; --f) {
+    // this wave's part of the batch
+    const int f_hi = min(bn, w_hi - bstart), f_lo = max(0, w_lo - bstart);
+    for (int f = f_hi - 1; f >= f_lo; --f) {
       const uint32_t *s = slots + f * kSlotWords;
       const int pos = bstart + f;
       if (!(pos < q.last)) continue;
@@ -288,7 +363,7 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
         const float cd = fmaf(cr, q.dC0, fmaf(cg, q.dC1, cb * q.dC2));
         if (direct) {
           const float Tb = (pos == q.last - 1) ? q.Tterm : q.Tr / (1.0f - alpha);
-          emit(x, pos, tri_at(x, pos), Tb * (cd - q.Bd), Tb * alpha, w, texel, q);
+          emit(x, s[38], s[39], Tb * (cd - q.Bd), Tb * alpha, w, texel, q);
           q.Tr = Tb;
           q.Bd = fmaf(alpha, cd - q.Bd, q.Bd);
           continue;
@@ -300,6 +375,18 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
           q.p0 = q.p1 = q.p2 = q.p3 = 1.0f;
           q.bpos = pos;
           q.Bback = q.Bd;
+          q.n_ent = 0;
+        }
+        if (++q.n_ent == 1) {
+          const float n = 0.25f * ((o[0] + o[1]) + (o[2] + o[3]));
+          q.c_rank = s[38];
+          q.c_t = s[39];
+          q.c_da = n * (cd - q.Bd);
+          q.c_vis = n * alpha;
+          q.c_w0 = w[0];
+          q.c_w1 = w[1];
+          q.c_w2 = w[2];
+          q.c_texel = texel;
         }
         q.fpos = pos;
         const float a0 = o[0] * alpha, a1 = o[1] * alpha, a2 = o[2] * alpha, a3 = o[3] * alpha;

@@ -422,11 +422,13 @@ class Rasterizer:
         return dict(gauss=int(pairs[0]), tri=int(pairs[1]), wave_iters=int(pairs[2]),
                     staged=int(pairs[3]))
 
-    def backward_pairs(self, n_contrib: torch.Tensor) -> Dict[str, int]:
+    def backward_pairs(self, n_contrib: torch.Tensor, triangles: bool = False) -> Dict[str, int]:
         """(pixel, fragment) pairs the backward walks on the sorted frame: every
         pixel the positions 1..n_contrib of its tile's list (n_contrib as
         written by the blend, views packed in order), split into Gaussian and
-        triangle fragments."""
+        triangle fragments.  triangles=True: the pairs of the triangle
+        backward, whose walk ends at the tile's first triangle fragment and
+        skips tiles that blend none."""
         ranges = self.copy_state(L.STATE_RANGES).long()
         vals = self.copy_state(L.STATE_SORTED_VALS).long() & 0xFFFFFFFF
         per_view = max(1, self.N + self.T)
@@ -444,9 +446,29 @@ class Rasterizer:
             xs = torch.arange(W, device=nc.device)[None, :]
             tiles = tile0 + (ys // th) * ntx + (xs // tw)
             start = ranges[tiles, 0]
-            nt = pref[start + nc] - pref[start]
+            lo = torch.zeros_like(nc)
+            if triangles:
+                n_t = ntx * nty
+                flat = (tiles - tile0).reshape(-1)
+                mx = torch.zeros(n_t, dtype=torch.int64, device=nc.device)
+                mx = mx.scatter_reduce(0, flat, nc.reshape(-1), reduce="amax")
+                s0 = ranges[tile0:tile0 + n_t, 0]
+                tri_idx = torch.nonzero(is_tri).reshape(-1)
+                big = torch.full_like(s0, 1 << 40)
+                if tri_idx.numel():
+                    k = torch.searchsorted(tri_idx, s0)
+                    fpos = torch.where(k < tri_idx.numel(),
+                                       tri_idx[k.clamp(max=tri_idx.numel() - 1)] - s0, big)
+                else:
+                    fpos = big
+                active = fpos < mx                           # the tile walks at all
+                lo = torch.where(active, fpos, 0)[flat].view(H, W)
+                act = active[flat].view(H, W)
+                lo = torch.where(act, lo, nc)                # inactive: no pairs
+                nc = torch.maximum(nc, lo)
+            nt = pref[start + nc] - pref[start + lo]
             t += int(nt.sum())
-            g += int(nc.sum()) - int(nt.sum())
+            g += int((nc - lo).sum()) - int(nt.sum())
             pix0 += W * H
             tile0 += ntx * nty
         return dict(gauss=g, tri=t)

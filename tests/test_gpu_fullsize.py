@@ -4,7 +4,8 @@ outputs.
 * 1920x1080, 1M deformed Gaussians + 100,128 triangles (the benchmark frame,
   same launch configuration): pinned deformed means and depth keys of every
   primitive bit-exact; 160 sampled pixels within 1e-4 (plus the last blended
-  fragment's id); sampled gradients of the backward against the oracle
+  fragment's id); sampled gradients of the backward and of the triangle
+  backward (pixels drawn where triangles are blended) against the oracle
   gradient restricted to those pixels.
 * 800x800, 300k Gaussians with SH degree 3 + 50,176 triangles: sampled
   pixels; gradients on four 16 x 16 windows against FP64 central finite
@@ -133,9 +134,16 @@ def test_cfg1_full_frame(gpu, cfg1):
     res = PT.compare_pixels(fr, img, Tf, lg, px)
     note(f"cfg1 full frame: {res}")
 
-    # gradients: dL nonzero only at 48 sampled pixels
+    # gradients: dL nonzero only at 48 sampled pixels and up to 64 pixels
+    # that blend triangles (the centres of 120 sampled triangles)
     note("cfg1 full backward (sampled pixels)")
     gp = sample_pixels(cam, 48, 12)
+    tv = np.random.default_rng(15).choice(np.flatnonzero(fr.t.valid), 120, replace=False)
+    cx = (fr.t.X[tv].astype(np.float64).mean(1) / 256).astype(int)
+    cy = (fr.t.Y[tv].astype(np.float64).mean(1) / 256).astype(int)
+    cand = [(int(x), int(y)) for x, y in zip(cx, cy) if 0 <= x < cam.width and 0 <= y < cam.height]
+    gp += [p for p in dict.fromkeys(cand) if any(i >= s.N for i in fr.pixel(*p).order)][:64]
+    assert len(gp) >= 90
     amb = [fr.pixel(x, y).margin <= 1e-4 for x, y in gp]
     rng = np.random.default_rng(13)
     w = rng.normal(size=(len(gp), 3))
@@ -152,6 +160,18 @@ def test_cfg1_full_frame(gpu, cfg1):
     assert touched.size > 50
     for n in ("means", "scales", "quats", "opacity", "sh"):
         gg = g[n].cpu().numpy().astype(np.float64).reshape(ref[n].shape)
+        rr = ref[n]
+        scale = np.abs(rr).max()
+        err = np.abs(gg - rr)
+        bad = err > 1e-3 * np.abs(rr) + 1e-5 * scale
+        assert not bad.any(), (n, int(bad.sum()), float(err.max()), float(scale))
+    # triangle colour and opacity gradients of the same frame and loss
+    tg = r.backward_triangles(dLt, out)
+    hit = np.flatnonzero(np.abs(ref["tri_alpha"]) > 0)
+    note(f"cfg1 triangle backward: {hit.size} triangles touched")
+    assert hit.size > 30
+    for n in ("tri_rgb", "tri_alpha"):
+        gg = tg[n].cpu().numpy().astype(np.float64).reshape(ref[n].shape)
         rr = ref[n]
         scale = np.abs(rr).max()
         err = np.abs(gg - rr)
