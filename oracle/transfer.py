@@ -13,7 +13,8 @@ Per proxy vertex v (rest positions V, deformed V'):
     normal direction of D is defined on flat or nearly flat 1-rings:
         D = (sum c e' e^T + w n' n^T) (sum c e e^T + w n n^T)^-1;
   * polar decomposition D = R S (R the nearest rotation, via SVD);
-  * r_v = log R_v as an axis-angle vector (principal branch).
+  * r_v = log R_v as an axis-angle vector (principal branch, angle in
+    [0, pi]; see log_rot for its evaluation near pi).
 
 Per Gaussian with K bindings (face f_i, barycentric (u, v, w = 1 - u - v) of
 the bound point P_i, i = 1..K; K = 8 bounding-box corners or K = 1 centre):
@@ -105,18 +106,37 @@ def polar(D):
 
 
 def log_rot(Rm):
-    """Principal axis-angle vector of rotation matrices (angle < pi)."""
-    tr = np.trace(Rm, axis1=1, axis2=2)
-    c = np.clip((tr - 1.0) / 2.0, -1.0, 1.0)
-    th = np.arccos(c)
+    """Principal axis-angle vector r = theta a of rotation matrices (theta in
+    [0, pi]).  With vee = (R32 - R23, R13 - R31, R21 - R12) = 2 sin(theta) a
+    and cos(theta) = (tr R - 1) / 2, theta = atan2(|vee| / 2, cos theta)
+    (accurate at both ends, unlike arccos near pi).  Up to pi/2,
+    r = theta / (2 sin theta) vee (its series near 0); beyond, where sin theta
+    no longer carries the axis accurately, the axis comes from the symmetric
+    part (R + R^T) / 2 - cos(theta) I = (1 - cos theta) a a^T: its column with
+    the largest diagonal entry, normalised and signed to agree with vee
+    (at theta = pi exactly, where -a is as good as a, that column's own
+    sign)."""
+    Rm = np.asarray(Rm, np.float64)
+    n = Rm.shape[0]
+    c = (np.trace(Rm, axis1=1, axis2=2) - 1.0) / 2.0
     vee = np.stack([Rm[:, 2, 1] - Rm[:, 1, 2], Rm[:, 0, 2] - Rm[:, 2, 0],
                     Rm[:, 1, 0] - Rm[:, 0, 1]], -1)
+    sn = 0.5 * np.linalg.norm(vee, axis=1)
+    th = np.arctan2(sn, c)
     small = th < 1e-4
     # th / (2 sin th) with its series 1/2 (1 + th^2/6) near 0
-    f = np.where(small, 0.5 * (1.0 + th * th / 6.0), th / (2.0 * np.sin(np.where(small, 1.0, th))))
-    if np.any(th > 0.9 * math.pi):
-        raise ValueError("per-vertex rotation beyond 0.9 pi: principal log is ill-conditioned")
-    return f[:, None] * vee
+    f = np.where(small, 0.5 * (1.0 + th * th / 6.0), th / (2.0 * np.where(small, 1.0, sn)))
+    r = f[:, None] * vee
+    big = c < 0.0
+    if np.any(big):
+        B = 0.5 * (Rm[big] + np.transpose(Rm[big], (0, 2, 1))) - c[big, None, None] * np.eye(3)
+        k = np.argmax(np.diagonal(B, axis1=1, axis2=2), axis=1)
+        col = B[np.arange(B.shape[0]), :, k]
+        a = col / np.sqrt(B[np.arange(B.shape[0]), k, k] * (1.0 - c[big]))[:, None]
+        sg = np.sign((a * vee[big]).sum(1))
+        sg[sg == 0] = 1.0
+        r[big] = (th[big] * sg)[:, None] * a
+    return r
 
 
 def exp_rot(r):

@@ -177,6 +177,26 @@ def test_log_exp_match_scipy():
     np.testing.assert_allclose(q, np.c_[qs[:, 3], qs[:, :3]] * np.sign(qs[:, 3:4]) * np.sign(q[:, :1]), atol=1e-13)
 
 
+def test_log_near_pi_matches_scipy():
+    """Angles from pi/2 to pi - 1e-9 (and pi itself): the log returns the
+    rotation vector (scipy's independent conversion) to 1e-9; at pi, where
+    +a and -a name the same rotation, exp(log R) = R."""
+    rng = np.random.default_rng(16)
+    a = rng.normal(size=(200, 3))
+    a /= np.linalg.norm(a, axis=1, keepdims=True)
+    th = np.concatenate([rng.uniform(0.5 * np.pi, np.pi - 1e-3, 150),
+                         np.pi - 10.0 ** -rng.uniform(3, 9, 50)])
+    r = a * th[:, None]
+    Rm = Rotation.from_rotvec(r).as_matrix()
+    got = TR.log_rot(Rm)
+    np.testing.assert_allclose(got, Rotation.from_matrix(Rm).as_rotvec(), atol=1e-9)
+    np.testing.assert_allclose(got, r, atol=2e-8)
+    Rpi = Rotation.from_rotvec(a[:20] * np.pi).as_matrix()
+    lp = TR.log_rot(Rpi)
+    np.testing.assert_allclose(np.linalg.norm(lp, axis=1), np.pi, atol=1e-12)
+    np.testing.assert_allclose(TR.exp_rot(lp), Rpi, atol=1e-12)
+
+
 def test_cot_weights_regular_fan():
     """Six equilateral triangles around a vertex: every interior angle is 60
     degrees, so each spoke's weight is (cot 60 + cot 60)/2 = 1/sqrt 3."""
