@@ -285,9 +285,11 @@ umgs_status umgs_render_batched(umgs_ctx *ctx, int32_t V, const umgs_camera *cam
  * gradient of the rest mean equals that of the deformed mean).
  * Outputs [device]: dL_dmeans (N,3), dL_dscales (N,3) w.r.t. linear scales,
  * dL_dquats (N,4) w.r.t. the raw quaternion before normalisation,
- * dL_dopacity (N,), dL_dsh (N,(deg+1)^2,3); written when accumulate is 0,
- * added to their contents otherwise (to sum over groups of views rendered
- * by separate frames).
+ * dL_dopacity (N,), dL_dsh (N,(deg+1)^2,3); dL_dxform (N,9) w.r.t. A when
+ * both xform and dL_dxform are non-NULL (what umgs_backward_transfer takes
+ * on to the proxy vertices; ignored otherwise); written when accumulate is
+ * 0, added to their contents otherwise (to sum over groups of views
+ * rendered by separate frames).
  * Triangle gradients come from umgs_backward_triangles.  Float atomics make the summation order,
  * hence the last bits, run-dependent.  Errors: STATE without a blended
  * frame; UNSUPPORTED for UMGS_MODE_ONE_ENTITY and UMGS_MODE_LITERAL_T;
@@ -296,7 +298,26 @@ umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_
                           const int32_t *n_contrib, const float *T_entity_in, const float *means,
                           const float *scales, const float *quats, const float *xform,
                           const float *sh, float *dL_dmeans, float *dL_dscales, float *dL_dquats,
-                          float *dL_dopacity, float *dL_dsh, int32_t accumulate);
+                          float *dL_dopacity, float *dL_dsh, float *dL_dxform, int32_t accumulate);
+
+/* Gradient with respect to the deformed proxy vertices V_def [device]
+ * (nV,3) of a loss given its gradients with respect to the transfer's
+ * outputs (Section 3.3.2): dL_dmeans (N,3) w.r.t. the deformed means mu'
+ * and dL_dxform (N,9) w.r.t. A = R'S' (as umgs_backward writes them for a
+ * frame whose Gaussians came from umgs_bind_transfer with this V_def and
+ * these bindings; either may be NULL, meaning zero).  Eq. 12-13 and the
+ * per-vertex transform (the 1-ring least squares D, the polar D = RS, the
+ * principal log of R) are differentiated exactly, the per-vertex part in
+ * FP64; the bindings are the same arrays as umgs_bind_transfer's (corners
+ * outside [0, nF) unbound and without gradient).  Output dL_dV_def (nV,3)
+ * [device], written when accumulate is 0, added to otherwise.  Float
+ * atomics make the last bits run-dependent.  Not capturable (it may grow a
+ * buffer).  Errors: STATE without a proxy or while capturing; INVALID_ARG
+ * for N < 0 or NULL arrays; CAPACITY. */
+umgs_status umgs_backward_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
+                                   const int32_t *bind_face, const float *bind_bary,
+                                   const float *dL_dmeans, const float *dL_dxform,
+                                   float *dL_dV_def, int32_t accumulate);
 
 /* Gradients of L with respect to the triangles of the last blended frame:
  * their per-vertex colours and opacity attributes, through the sub-sample
@@ -402,7 +423,7 @@ enum { UMGS_K_VERTEX_FRAMES = 0, UMGS_K_TRANSFER = 1, UMGS_K_PROJECT = 2, UMGS_K
        UMGS_K_SORT_DOWNSWEEP = 8, UMGS_K_RANGES = 9, UMGS_K_BLEND = 10, UMGS_K_BLEND_BWD = 11,
        UMGS_K_PROJECT_BWD = 12, UMGS_K_DEPTH_SORT = 13, UMGS_K_TILE_COUNT = 14,
        UMGS_K_TILE_SCATTER = 15, UMGS_K_ST_MASK = 16, UMGS_K_BLEND_BWD_TRI = 17,
-       UMGS_K_COUNT = 18 };
+       UMGS_K_TRANSFER_BWD = 18, UMGS_K_COUNT = 19 };
 umgs_status umgs_set_profiling(umgs_ctx *ctx, int32_t enable);
 umgs_status umgs_profile_read(umgs_ctx *ctx, int32_t kernel, int64_t *launches, double *total_ms);
 

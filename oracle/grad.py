@@ -213,7 +213,8 @@ def gradients(cam, pixels, dL_dC, means, scales, quats, opacity, sh, degree, tri
               tri_alpha, bg=(0.0, 0.0, 0.0), mode=OR.MODE_UNIMGS, xform=None,
               mean_offset=None, tri_uv=None, tex=None) -> Dict[str, np.ndarray]:
     """dL/d(means, scales, quats, opacity, sh) and dL/d(tri_rgb, tri_alpha)
-    for L = sum_p dL_dC[p] . C[p] over the listed pixels.  Inputs are NumPy
+    (and dL/dA as "xform" for a deformed scene) for L = sum_p dL_dC[p] . C[p]
+    over the listed pixels.  Inputs are NumPy
     arrays; xform (N,3,3) and mean_offset (N,3) describe a deformed scene
     (then ``means`` are the rest means and the frame is built from means +
     mean_offset and A Sigma A^T)."""
@@ -231,11 +232,15 @@ def gradients(cam, pixels, dL_dC, means, scales, quats, opacity, sh, degree, tri
         frame = OR.Frame(cam, means, opacity, sh, degree, tri_xyz, tri_rgb, tri_alpha,
                          scales=scales, quats=quats, bg=bg, mode=mode, tri_uv=tri_uv, tex=tex)
     P = [t64(means), t64(scales), t64(quats), t64(opacity), t64(sh), t64(tri_rgb), t64(tri_alpha)]
-    A_t = None if xform is None else torch.tensor(np.asarray(xform, np.float64), dtype=DT)
+    A_t = None if xform is None else torch.tensor(np.asarray(xform, np.float64), dtype=DT,
+                                                  requires_grad=True)
     off_t = None if mean_offset is None else torch.tensor(np.asarray(mean_offset, np.float64), dtype=DT)
     C, T = render_pixels(frame, pixels, *P[:5], degree, A_t, off_t, tri_rgb=P[5], tri_alpha=P[6])
     L = (C * torch.tensor(np.asarray(dL_dC, np.float64), dtype=DT)).sum()
     L.backward()
     names = ["means", "scales", "quats", "opacity", "sh", "tri_rgb", "tri_alpha"]
-    return ({n: (p.grad.numpy() if p.grad is not None else np.zeros(p.shape)) for n, p in zip(names, P)}
-            | {"C": C.detach().numpy(), "T": T.detach().numpy()})
+    out = ({n: (p.grad.numpy() if p.grad is not None else np.zeros(p.shape)) for n, p in zip(names, P)}
+           | {"C": C.detach().numpy(), "T": T.detach().numpy()})
+    if A_t is not None:
+        out["xform"] = A_t.grad.numpy() if A_t.grad is not None else np.zeros(A_t.shape)
+    return out

@@ -61,7 +61,8 @@ PROTOTYPES = {
     "umgs_update_views": (C.c_int, [P, I32, C.POINTER(Camera), C.POINTER(Camera)]),
     "umgs_view_dups": (C.c_int, [P, C.POINTER(I64)]),
     "umgs_copy_state": (C.c_int, [P, I32, P, I64]),
-    "umgs_backward": (C.c_int, [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, I32]),
+    "umgs_backward": (C.c_int, [P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, P, I32]),
+    "umgs_backward_transfer": (C.c_int, [P, P, I32, P, P, P, P, P, I32]),
     "umgs_backward_triangles": (C.c_int, [P, P, P, P, P, P, P, I32]),
     "umgs_set_profiling": (C.c_int, [P, I32]),
     "umgs_profile_read": (C.c_int, [P, I32, C.POINTER(I64), C.POINTER(C.c_double)]),
@@ -70,7 +71,7 @@ PROTOTYPES = {
 KERNEL_NAMES = ["vertex_frames", "transfer", "project_gaussians", "setup_triangles", "count_scan",
                 "emit_keys", "sort_upsweep", "sort_scan", "sort_downsweep", "tile_ranges", "blend",
                 "blend_backward", "project_backward", "depth_sort", "tile_count", "tile_scatter",
-                "st_mask", "blend_backward_tri"]
+                "st_mask", "blend_backward_tri", "transfer_backward"]
 
 _lib = None
 

@@ -178,7 +178,7 @@ void umgs_destroy(umgs_ctx *ctx) {
                     &c->chunk_base, &c->cnt2, &c->chunk_tab, &c->tstart, &c->totals,
                     &c->v0, &c->v1, &c->hist, &c->ranges, &c->g2d,
                     &c->minmax, &c->lb, &c->finfo, &c->tile_order, &c->bwd_order, &c->pair_count,
-                    &c->view_sums, &c->tex, &c->tex_uv};
+                    &c->view_sums, &c->tex, &c->tex_uv, &c->gvert};
   for (DevBuf *b : bufs) free_buf(*b);
   for (auto &p : c->prof.pending) {
     (void)hipEventDestroy(p.a);
@@ -669,7 +669,7 @@ umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_
                           const int32_t *n_contrib, const float *T_entity_in, const float *means,
                           const float *scales, const float *quats, const float *xform,
                           const float *sh, float *dL_dmeans, float *dL_dscales, float *dL_dquats,
-                          float *dL_dopacity, float *dL_dsh, int32_t accumulate) {
+                          float *dL_dopacity, float *dL_dsh, float *dL_dxform, int32_t accumulate) {
   if (!ctx) return UMGS_ERR_INVALID_ARG;
   Ctx *c = &ctx->c;
   if (c->stage < 4) return fail(c, UMGS_ERR_STATE, "umgs_backward: no blended frame on this context");
@@ -685,8 +685,30 @@ umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_
   if (s != UMGS_OK) return s;
   return hip_check(c, launch_backward(c, dL_dimage, T_final, n_contrib, T_entity_in, means, scales,
                                       quats, xform, sh, dL_dmeans, dL_dscales, dL_dquats,
-                                      dL_dopacity, dL_dsh, accumulate != 0),
+                                      dL_dopacity, dL_dsh, dL_dxform, accumulate != 0),
                    "backward launch");
+}
+
+umgs_status umgs_backward_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
+                                   const int32_t *bind_face, const float *bind_bary,
+                                   const float *dL_dmeans, const float *dL_dxform,
+                                   float *dL_dV_def, int32_t accumulate) {
+  if (!ctx) return UMGS_ERR_INVALID_ARG;
+  Ctx *c = &ctx->c;
+  if (c->nV == 0)
+    return fail(c, UMGS_ERR_STATE, "umgs_backward_transfer: no proxy (call umgs_set_proxy)");
+  if (N < 0) return fail(c, UMGS_ERR_INVALID_ARG, "umgs_backward_transfer: N=%d", N);
+  if (!V_def || !dL_dV_def)
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_backward_transfer: NULL V_def or dL_dV_def");
+  if (N > 0 && (!bind_face || !bind_bary))
+    return fail(c, UMGS_ERR_INVALID_ARG, "umgs_backward_transfer: NULL binding array");
+  if (c->capturing)
+    return fail(c, UMGS_ERR_STATE, "umgs_backward_transfer: the stream is being captured");
+  umgs_status s = ensure(c, c->gvert, sizeof(float) * 12 * (size_t)c->nV, "vertex gradients");
+  if (s != UMGS_OK) return s;
+  return hip_check(c, launch_transfer_backward(c, V_def, N, bind_face, bind_bary, dL_dmeans,
+                                               dL_dxform, dL_dV_def, accumulate != 0),
+                   "transfer backward launch");
 }
 
 umgs_status umgs_backward_triangles(umgs_ctx *ctx, const float *dL_dimage, const float *T_final,

@@ -476,7 +476,8 @@ __global__ __launch_bounds__(128) void project_backward_kernel(
                                         const float *__restrict__ g2d,
                                         float *__restrict__ d_means, float *__restrict__ d_scales,
                                         float *__restrict__ d_quats, float *__restrict__ d_opac,
-                                        float *__restrict__ d_sh, int accumulate) {
+                                        float *__restrict__ d_sh, float *__restrict__ d_xform,
+                                        int accumulate) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= N) return;
   constexpr int nc = (DEG + 1) * (DEG + 1);
@@ -635,8 +636,27 @@ __global__ __launch_bounds__(128) void project_backward_kernel(
     dmu[2] += (gdz - ddz * dd) * idl;
   }
 
+  // write, or add to what an earlier call (another view group) wrote
+  auto put = [accumulate](float *p, float v) { *p = accumulate ? *p + v : v; };
   // Sigma' -> Sigma
   float dS[9];
+  if (xform && d_xform) {
+    // Sigma' = A Sigma A^T: dL/dA = (dSp + dSp^T) A Sigma
+    float AS[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) AS[3 * r + c] = A[3 * r] * Sg[c] + A[3 * r + 1] * Sg[3 + c] + A[3 * r + 2] * Sg[6 + c];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) acc += (dSp[3 * r + k] + dSp[3 * k + r]) * AS[3 * k + c];
+        put(&d_xform[9 * (int64_t)i + 3 * r + c], acc);
+      }
+  }
   if (xform) {
     float AtG[9];   // A^T dSp
 #pragma unroll
@@ -663,8 +683,6 @@ __global__ __launch_bounds__(128) void project_backward_kernel(
       dM[3 * r + c] = acc;
     }
   float gR[9];
-  // write, or add to what an earlier call (another view group) wrote
-  auto put = [accumulate](float *p, float v) { *p = accumulate ? *p + v : v; };
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     put(&d_scales[3 * (int64_t)i + c], dM[c] * Rq[c] + dM[3 + c] * Rq[3 + c] + dM[6 + c] * Rq[6 + c]);
@@ -749,7 +767,7 @@ hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32
                            const float *Te, const float *means, const float *scales,
                            const float *quats, const float *xform, const float *sh,
                            float *d_means, float *d_scales, float *d_quats, float *d_opac,
-                           float *d_sh, bool accumulate) {
+                           float *d_sh, float *d_xform, bool accumulate) {
   hipError_t e = launch_fill_u32(c, (uint32_t *)c->g2d.p, 9 * (int64_t)c->V * c->N, 0u);
   if (e != hipSuccess) return e;
   if (c->n_tiles > 0) {
@@ -767,22 +785,22 @@ hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32
     case 0:
       hipLaunchKernelGGL(project_backward_kernel<0>, grid, block, 0, c->stream, c->cur_views, c->V,
                          c->N, means, scales, quats, xform, sh, g2d, d_means, d_scales, d_quats,
-                         d_opac, d_sh, acc);
+                         d_opac, d_sh, d_xform, acc);
       break;
     case 1:
       hipLaunchKernelGGL(project_backward_kernel<1>, grid, block, 0, c->stream, c->cur_views, c->V,
                          c->N, means, scales, quats, xform, sh, g2d, d_means, d_scales, d_quats,
-                         d_opac, d_sh, acc);
+                         d_opac, d_sh, d_xform, acc);
       break;
     case 2:
       hipLaunchKernelGGL(project_backward_kernel<2>, grid, block, 0, c->stream, c->cur_views, c->V,
                          c->N, means, scales, quats, xform, sh, g2d, d_means, d_scales, d_quats,
-                         d_opac, d_sh, acc);
+                         d_opac, d_sh, d_xform, acc);
       break;
     default:
       hipLaunchKernelGGL(project_backward_kernel<3>, grid, block, 0, c->stream, c->cur_views, c->V,
                          c->N, means, scales, quats, xform, sh, g2d, d_means, d_scales, d_quats,
-                         d_opac, d_sh, acc);
+                         d_opac, d_sh, d_xform, acc);
       break;
   }
   return hipGetLastError();

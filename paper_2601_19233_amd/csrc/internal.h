@@ -85,7 +85,7 @@ struct TexView {
 enum KernelId {
   K_VERTEX_FRAMES = 0, K_TRANSFER, K_PROJECT, K_TRIANGLES, K_SCAN, K_EMIT, K_SORT_UPSWEEP,
   K_SORT_SCAN, K_SORT_DOWNSWEEP, K_RANGES, K_BLEND, K_BLEND_BWD, K_PROJECT_BWD, K_DEPTH_SORT,
-  K_TILE_COUNT, K_TILE_SCATTER, K_ST_MASK, K_BLEND_BWD_TRI, K_COUNT
+  K_TILE_COUNT, K_TILE_SCATTER, K_ST_MASK, K_BLEND_BWD_TRI, K_TRANSFER_BWD, K_COUNT
 };
 
 struct Prof {
@@ -137,6 +137,7 @@ struct Ctx {
   int32_t nV = 0, nF = 0;
   DevBuf V_rest, faces, vf_ptr, vf_idx, vtab;
   DevBuf ftab;   // per face: its three vertex rows (9 float4, 144 B)
+  DevBuf gvert;  // per vertex: gradient of (Delta, r, S) in the transfer backward (12 floats)
   // BVH of the rest proxy for the binding association (rebuilt per call)
   DevBuf bvh_code[2], bvh_id[2];  // nF uint32: Morton codes / face ids (ping-pong sort)
   DevBuf bvh_tri;                 // nF x 3 float4: leaf triangles in Morton order
@@ -281,7 +282,7 @@ hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32
                            const float *Te, const float *means, const float *scales,
                            const float *quats, const float *xform, const float *sh,
                            float *d_means, float *d_scales, float *d_quats, float *d_opac,
-                           float *d_sh, bool accumulate);
+                           float *d_sh, float *d_xform, bool accumulate);
 // Allocation-free transfer: its scratch is a static device array of
 // kNoAllocScratchBytes per GPU, whose address noalloc_scratch_init looks up
 // once per device (with that device current) and noalloc_scratch returns.
@@ -295,6 +296,10 @@ hipError_t launch_transfer_noalloc(Ctx *c, void *scratch_base, const float *V_de
                                    const float *means, const float *quats, const float *scales,
                                    float *means_out, float *quats_out, float *cov3d_out,
                                    float *xform_out, float *vertex_out);
+hipError_t launch_transfer_backward(Ctx *c, const float *V_def, int32_t N,
+                                    const int32_t *bind_face, const float *bind_bary,
+                                    const float *dL_dmeans, const float *dL_dxform,
+                                    float *dL_dV_def, bool accumulate);
 hipError_t launch_transfer(Ctx *c, const float *V_def, int32_t N, const int32_t *bind_face,
                            const float *bind_bary, const float *means, const float *quats,
                            const float *scales, float *means_out, float *quats_out,

@@ -8,7 +8,8 @@
 //   their mesh, w the mean cotangent weight;
 //   polar D = R S with R = [u1 u2 u1 x u2][v1 v2 v3]^T from the eigenvectors
 //   of D^T D (a proper rotation; the nearest one to D);
-//   r_v = log R (axis-angle), written with S as a 12-float row.
+//   r_v = log R (axis-angle, angle in [0, pi], robust near pi), written with
+//   S as a 12-float row.
 // face_rows_kernel: each face's three vertex rows side by side (144 B), so a
 //   bound point reads one row that spans exactly two 128-B cache lines
 //   (rows start at multiples of 16 B) instead of a face lookup followed by
@@ -138,14 +139,46 @@ __device__ void jacobi3(double A[9], double V[9]) {
   }
 }
 
-__global__ void vertex_frames_kernel(int nV, const float *__restrict__ Vr,
-                                     const float *__restrict__ Vd,
-                                     const int32_t *__restrict__ faces,
-                                     const int32_t *__restrict__ vf_ptr,
-                                     const int32_t *__restrict__ vf_idx,
-                                     float *__restrict__ vtab) {
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nV) return;
+// Principal rotation log r = theta a (theta in [0, pi]) of a rotation R
+// (row-major).  w = (R21 - R12, R02 - R20, R10 - R01) = 2 sin(theta) a and
+// cos(theta) = (tr R - 1)/2 give theta = atan2(|w|/2, cos theta), accurate
+// at both ends.  Up to pi/2, r = theta / (2 sin theta) w; beyond, the axis is
+// taken from the symmetric part (R + R^T)/2 - cos(theta) I = (1 - cos theta)
+// a a^T (its column with the largest diagonal, normalised) and signed to
+// agree with w, whose direction no longer carries it accurately.
+__device__ void rot_log(const double R[9], double r[3]) {
+  const double w[3] = {R[7] - R[5], R[2] - R[6], R[3] - R[1]};
+  const double ct = 0.5 * (R[0] + R[4] + R[8] - 1.0);
+  const double sn = 0.5 * norm3(w);
+  const double th = atan2(sn, ct);
+  if (ct >= 0.0) {
+    const double f = th < 1e-4 ? 0.5 * (1.0 + th * th / 6.0) : th / (2.0 * sn);
+    for (int i = 0; i < 3; ++i) r[i] = f * w[i];
+    return;
+  }
+  double B[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) B[3 * i + j] = 0.5 * (R[3 * i + j] + R[3 * j + i]) - (i == j ? ct : 0.0);
+  int k = 0;
+  if (B[4] > B[3 * k + k]) k = 1;
+  if (B[8] > B[3 * k + k]) k = 2;
+  const double nrm = sqrt(B[3 * k + k] * (1.0 - ct));
+  double a[3] = {B[k] / nrm, B[3 + k] / nrm, B[6 + k] / nrm};
+  const double sg = (a[0] * w[0] + a[1] * w[1] + a[2] * w[2]) < 0.0 ? -1.0 : 1.0;
+  for (int i = 0; i < 3; ++i) r[i] = sg * th * a[i];
+}
+
+// The per-vertex transform of vertex v and the intermediate values its
+// derivative needs, in FP64.
+struct VFrame {
+  double Qi[9], D[9], R[9], S[9], r[3];
+  double nrm[3], nrmd[3];   // rest and deformed 1-ring normal sums
+  double sn, w, nf, lsd;    // rest normal scale, mean cot weight, faces, deformed edge length sum
+};
+
+__device__ void vertex_frame(int v, const float *__restrict__ Vr, const float *__restrict__ Vd,
+                             const int32_t *__restrict__ faces, const int32_t *__restrict__ vf_ptr,
+                             const int32_t *__restrict__ vf_idx, VFrame &F) {
   double P[9] = {0}, Q[9] = {0};
   double nrm[3] = {0, 0, 0}, nrmd[3] = {0, 0, 0};
   double wsum = 0.0, ls = 0.0, lsd = 0.0;
@@ -189,11 +222,11 @@ __global__ void vertex_frames_kernel(int nV, const float *__restrict__ Vr,
       P[3 * i + j] += w * (nrmd[i] * snd) * (nrm[j] * sn);
       Q[3 * i + j] += w * (nrm[i] * sn) * (nrm[j] * sn);
     }
-  double Qi[9], D[9];
-  inv3(Q, Qi);
+  inv3(Q, F.Qi);
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j)
-      D[3 * i + j] = P[3 * i] * Qi[j] + P[3 * i + 1] * Qi[3 + j] + P[3 * i + 2] * Qi[6 + j];
+      F.D[3 * i + j] = P[3 * i] * F.Qi[j] + P[3 * i + 1] * F.Qi[3 + j] + P[3 * i + 2] * F.Qi[6 + j];
+  const double *D = F.D;
 
   // polar decomposition through the eigenvectors of D^T D
   double M[9], E[9];
@@ -222,24 +255,41 @@ __global__ void vertex_frames_kernel(int nV, const float *__restrict__ Vr,
   const double n2 = norm3(u2);
   for (int i = 0; i < 3; ++i) u2[i] /= n2;
   cross3(u1, u2, u3);
-  double R[9];
   for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) R[3 * i + j] = u1[i] * v1[j] + u2[i] * v2[j] + u3[i] * v3[j];
-  double S[9];
+    for (int j = 0; j < 3; ++j) F.R[3 * i + j] = u1[i] * v1[j] + u2[i] * v2[j] + u3[i] * v3[j];
+  const double *R = F.R;
   for (int i = 0; i < 3; ++i)
     for (int j = 0; j < 3; ++j)
-      S[3 * i + j] = R[i] * D[j] + R[3 + i] * D[3 + j] + R[6 + i] * D[6 + j];
-  // principal rotation log
-  const double ct = fmin(1.0, fmax(-1.0, 0.5 * (R[0] + R[4] + R[8] - 1.0)));
-  const double th = acos(ct);
-  const double fth = th < 1e-4 ? 0.5 * (1.0 + th * th / 6.0) : th / (2.0 * sin(th));
+      F.S[3 * i + j] = R[i] * D[j] + R[3 + i] * D[3 + j] + R[6 + i] * D[6 + j];
+  rot_log(R, F.r);
+  for (int i = 0; i < 3; ++i) {
+    F.nrm[i] = nrm[i];
+    F.nrmd[i] = nrmd[i];
+  }
+  F.sn = sn;
+  F.w = w;
+  F.nf = nf;
+  F.lsd = lsd;
+}
+
+__global__ __launch_bounds__(128) void vertex_frames_kernel(int nV, const float *__restrict__ Vr,
+                                     const float *__restrict__ Vd,
+                                     const int32_t *__restrict__ faces,
+                                     const int32_t *__restrict__ vf_ptr,
+                                     const int32_t *__restrict__ vf_idx,
+                                     float *__restrict__ vtab) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nV) return;
+  VFrame F;
+  vertex_frame(v, Vr, Vd, faces, vf_ptr, vf_idx, F);
+  const double *S = F.S;
   float *out = vtab + 12 * (int64_t)v;
   out[0] = Vd[3 * v] - Vr[3 * v];
   out[1] = Vd[3 * v + 1] - Vr[3 * v + 1];
   out[2] = Vd[3 * v + 2] - Vr[3 * v + 2];
-  out[3] = (float)(fth * (R[7] - R[5]));
-  out[4] = (float)(fth * (R[2] - R[6]));
-  out[5] = (float)(fth * (R[3] - R[1]));
+  out[3] = (float)F.r[0];
+  out[4] = (float)F.r[1];
+  out[5] = (float)F.r[2];
   out[6] = (float)S[0];
   out[7] = (float)(0.5 * (S[1] + S[3]));
   out[8] = (float)(0.5 * (S[2] + S[6]));
@@ -520,6 +570,224 @@ __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) vo
                     quats_out, cov3d_out, xform_out);
 }
 
+
+// ---- backward: the gradient with respect to the deformed proxy ------------
+//
+// transfer_bwd_kernel (one thread per Gaussian, FP32): from dL/dmu' and
+// dL/dA of a Gaussian with k_b bound corners, Eq. 13 gives
+//   dL/dS' = R'^T dL/dA,  dL/dR' = dL/dA S'^T,
+//   dL/d rbar = J_r(rbar)^T vee(R'^T dL/dR' - dL/dR'^T R')   (R' = exp(rbar)),
+// and Eq. 12 hands each bound corner's face vertex j the share b_j / k_b
+// of (dL/dmu', dL/d rbar, sym dL/dS'): 12 float atomics per (corner, vertex)
+// into a per-vertex table.
+// vertex_bwd_kernel (one thread per vertex, FP64): with r = log R,
+// D = R S (polar), D = P Q^-1, the vertex's (dL/dDelta, dL/dr, G = dL/dS)
+// become
+//   h = J_r(r)^-T dL/dr,   m = (tr(S) I - S)^-1 (h + vee(S G - G S)),
+//   dL/dD = R ([m]_x + G),  dL/dP = dL/dD Q^-T,
+// (the differential of the polar factor: R^T dR = [w]_x with
+// (tr(S) I - S) w = vee(R^T dD - dD^T R), dS = R^T dD - [w]_x S), then
+// P's 1-ring edge terms and its normal pair pass dL/dP to the deformed
+// edges f = V'_a - V'_v (through the cross products and edge lengths of the
+// deformed normal), i.e. to V' of the vertex and its neighbours.
+
+__device__ __forceinline__ void skew_times(const double m[3], const double x[3], double y[3]) {
+  cross3(m, x, y);   // [m]_x x
+}
+
+template <int K>
+__global__ __launch_bounds__(128) void transfer_bwd_kernel(
+    int N, int nF, const int32_t *__restrict__ faces, const float *__restrict__ ftab,
+    const int32_t *__restrict__ bind_face, const float *__restrict__ bind_bary,
+    const float *__restrict__ dmu, const float *__restrict__ dA, float *__restrict__ gvert) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  int kb = 0;
+  float rs[3] = {0.f, 0.f, 0.f}, Ss[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = bind_face[K * (int64_t)i + k];
+    if ((unsigned)f >= (unsigned)nF) continue;
+    ++kb;
+    const float u = bind_bary[2 * (K * (int64_t)i + k)], v = bind_bary[2 * (K * (int64_t)i + k) + 1];
+    const float bw[3] = {u, v, (1.0f - u) - v};
+    const float *row = ftab + 36 * (int64_t)f;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) rs[c] += bw[j] * row[12 * j + 3 + c];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) Ss[c] += bw[j] * row[12 * j + 6 + c];
+    }
+  }
+  if (kb == 0) return;                 // rest pose: no dependence on the proxy
+  const float invk = 1.0f / (float)kb;
+  const float r0 = rs[0] * invk, r1 = rs[1] * invk, r2 = rs[2] * invk;
+  const float th2 = r0 * r0 + r1 * r1 + r2 * r2, th = sqrtf(th2);
+  float sa, hb, cb;   // sin(th)/th, (1 - cos th)/th^2, (th - sin th)/th^3
+  if (th < 1e-2f) {
+    sa = 1.0f - th2 * (1.0f / 6.0f);
+    hb = 0.5f - th2 * (1.0f / 24.0f);
+    cb = 1.0f / 6.0f - th2 * (1.0f / 120.0f);
+  } else {
+    const float sn = sinf(th), h = sinf(0.5f * th);
+    sa = sn / th;
+    const float q = h / (0.5f * th);
+    hb = 0.5f * q * q;
+    cb = (1.0f - sa) / th2;
+  }
+  const float Rp[9] = {1.f - hb * (r1 * r1 + r2 * r2), -sa * r2 + hb * r0 * r1, sa * r1 + hb * r0 * r2,
+                       sa * r2 + hb * r0 * r1, 1.f - hb * (r0 * r0 + r2 * r2), -sa * r0 + hb * r1 * r2,
+                       -sa * r1 + hb * r0 * r2, sa * r0 + hb * r1 * r2, 1.f - hb * (r0 * r0 + r1 * r1)};
+  const float Sm[9] = {Ss[0] * invk, Ss[1] * invk, Ss[2] * invk, Ss[1] * invk, Ss[3] * invk,
+                       Ss[4] * invk, Ss[2] * invk, Ss[4] * invk, Ss[5] * invk};
+  float GA[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) GA[k] = dA ? dA[9 * (int64_t)i + k] : 0.0f;
+  float GS[9], GR[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      GS[3 * a + b] = Rp[a] * GA[b] + Rp[3 + a] * GA[3 + b] + Rp[6 + a] * GA[6 + b];           // R'^T GA
+      GR[3 * a + b] = GA[3 * a] * Sm[b] + GA[3 * a + 1] * Sm[3 + b] + GA[3 * a + 2] * Sm[6 + b];  // GA S'^T
+    }
+  float X[9];   // R'^T GR
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) X[3 * a + b] = Rp[a] * GR[b] + Rp[3 + a] * GR[3 + b] + Rp[6 + a] * GR[6 + b];
+  const float y[3] = {X[7] - X[5], X[2] - X[6], X[3] - X[1]};
+  // J_r(r)^T y = y + hb r x y + cb r x (r x y)
+  const float rxy[3] = {r1 * y[2] - r2 * y[1], r2 * y[0] - r0 * y[2], r0 * y[1] - r1 * y[0]};
+  const float rxrxy[3] = {r1 * rxy[2] - r2 * rxy[1], r2 * rxy[0] - r0 * rxy[2], r0 * rxy[1] - r1 * rxy[0]};
+  float g[12];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    g[c] = (dmu ? dmu[3 * (int64_t)i + c] : 0.0f) * invk;
+    g[3 + c] = (y[c] + hb * rxy[c] + cb * rxrxy[c]) * invk;
+  }
+  g[6] = GS[0] * invk;
+  g[7] = 0.5f * (GS[1] + GS[3]) * invk;
+  g[8] = 0.5f * (GS[2] + GS[6]) * invk;
+  g[9] = GS[4] * invk;
+  g[10] = 0.5f * (GS[5] + GS[7]) * invk;
+  g[11] = GS[8] * invk;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int f = bind_face[K * (int64_t)i + k];
+    if ((unsigned)f >= (unsigned)nF) continue;
+    const float u = bind_bary[2 * (K * (int64_t)i + k)], v = bind_bary[2 * (K * (int64_t)i + k) + 1];
+    const float bw[3] = {u, v, (1.0f - u) - v};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      float *dst = gvert + 12 * (int64_t)faces[3 * f + j];
+#pragma unroll
+      for (int c = 0; c < 12; ++c) unsafeAtomicAdd(dst + c, bw[j] * g[c]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(128) void vertex_bwd_kernel(
+    int nV, const float *__restrict__ Vr, const float *__restrict__ Vd,
+    const int32_t *__restrict__ faces, const int32_t *__restrict__ vf_ptr,
+    const int32_t *__restrict__ vf_idx, const float *__restrict__ gvert, float *__restrict__ dV) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nV) return;
+  double g[12];
+  bool any = false;
+  for (int c = 0; c < 12; ++c) {
+    g[c] = gvert[12 * (int64_t)v + c];
+    any = any || g[c] != 0.0;
+  }
+  if (!any) return;
+  VFrame F;
+  vertex_frame(v, Vr, Vd, faces, vf_ptr, vf_idx, F);
+  const double *R = F.R, *S = F.S, *r = F.r;
+  // h = J_r(r)^-T g_r = g_r - r x g_r / 2 + beta r x (r x g_r)
+  const double th2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2], th = sqrt(th2);
+  const double beta = th < 1e-4 ? 1.0 / 12.0 + th2 / 720.0
+                                : (1.0 - 0.5 * th * cos(0.5 * th) / sin(0.5 * th)) / th2;
+  const double gr[3] = {g[3], g[4], g[5]};
+  double rxg[3], rxrxg[3];
+  cross3(r, gr, rxg);
+  cross3(r, rxg, rxrxg);
+  double k3[3];
+  for (int c = 0; c < 3; ++c) k3[c] = gr[c] - 0.5 * rxg[c] + beta * rxrxg[c];
+  const double G[9] = {g[6], g[7], g[8], g[7], g[9], g[10], g[8], g[10], g[11]};
+  double SG[9];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      SG[3 * a + b] = S[3 * a] * G[b] + S[3 * a + 1] * G[3 + b] + S[3 * a + 2] * G[6 + b];
+  // vee(S G - G S) = vee(SG - SG^T) (S, G symmetric)
+  k3[0] += SG[7] - SG[5];
+  k3[1] += SG[2] - SG[6];
+  k3[2] += SG[3] - SG[1];
+  const double trS = S[0] + S[4] + S[8];
+  double Y[9], Yi[9];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) Y[3 * a + b] = (a == b ? trS : 0.0) - 0.5 * (S[3 * a + b] + S[3 * b + a]);
+  inv3(Y, Yi);
+  double m[3];
+  for (int a = 0; a < 3; ++a) m[a] = Yi[3 * a] * k3[0] + Yi[3 * a + 1] * k3[1] + Yi[3 * a + 2] * k3[2];
+  const double Mx[9] = {G[0], G[1] - m[2], G[2] + m[1], G[3] + m[2], G[4], G[5] - m[0],
+                        G[6] - m[1], G[7] + m[0], G[8]};   // [m]_x + G
+  double GD[9], GP[9];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b)
+      GD[3 * a + b] = R[3 * a] * Mx[b] + R[3 * a + 1] * Mx[3 + b] + R[3 * a + 2] * Mx[6 + b];
+  for (int a = 0; a < 3; ++a)      // dL/dP = dL/dD Q^-T
+    for (int b = 0; b < 3; ++b)
+      GP[3 * a + b] = GD[3 * a] * F.Qi[3 * b] + GD[3 * a + 1] * F.Qi[3 * b + 1] + GD[3 * a + 2] * F.Qi[3 * b + 2];
+  // the normal pair w n' n^T, n = nrm sn, n' = u l' / |u| (u = nrmd, l' the mean deformed edge length)
+  double nrest[3], dnp[3];
+  for (int c = 0; c < 3; ++c) nrest[c] = F.nrm[c] * F.sn;
+  for (int a = 0; a < 3; ++a)
+    dnp[a] = F.w * (GP[3 * a] * nrest[0] + GP[3 * a + 1] * nrest[1] + GP[3 * a + 2] * nrest[2]);
+  const double nu = norm3(F.nrmd), lp = F.lsd / (2.0 * F.nf);
+  double uh[3];
+  for (int c = 0; c < 3; ++c) uh[c] = F.nrmd[c] / nu;
+  const double dl = dot3(uh, dnp);
+  double du[3];
+  for (int c = 0; c < 3; ++c) du[c] = lp / nu * (dnp[c] - uh[c] * dl);
+  const double dlsd = dl / (2.0 * F.nf);
+
+  double acc[3] = {g[0], g[1], g[2]};   // Delta_v = V'_v - V_v
+  const double pv[3] = {Vr[3 * v], Vr[3 * v + 1], Vr[3 * v + 2]};
+  const double qv[3] = {Vd[3 * v], Vd[3 * v + 1], Vd[3 * v + 2]};
+  for (int k = vf_ptr[v]; k < vf_ptr[v + 1]; ++k) {
+    const int f = vf_idx[k];
+    const int a0 = faces[3 * f], a1 = faces[3 * f + 1], a2 = faces[3 * f + 2];
+    const int ia = (a0 == v) ? a1 : (a1 == v) ? a2 : a0;
+    const int ib = (a0 == v) ? a2 : (a1 == v) ? a0 : a1;
+    const double pa[3] = {Vr[3 * ia], Vr[3 * ia + 1], Vr[3 * ia + 2]};
+    const double pb[3] = {Vr[3 * ib], Vr[3 * ib + 1], Vr[3 * ib + 2]};
+    const double cb = cot_at(pb, pv, pa), ca = cot_at(pa, pv, pb);
+    double ea[3], eb[3], fa[3], fb[3];
+    for (int c = 0; c < 3; ++c) {
+      ea[c] = pa[c] - pv[c]; eb[c] = pb[c] - pv[c];
+      fa[c] = Vd[3 * ia + c] - qv[c]; fb[c] = Vd[3 * ib + c] - qv[c];
+    }
+    double t1[3], t2[3];
+    cross3(fb, du, t1);   // from u = sum fa x fb
+    cross3(du, fa, t2);
+    const double la = norm3(fa), lb = norm3(fb);
+    double gfa[3], gfb[3];
+    for (int a = 0; a < 3; ++a) {
+      gfa[a] = 0.5 * cb * (GP[3 * a] * ea[0] + GP[3 * a + 1] * ea[1] + GP[3 * a + 2] * ea[2]) + t1[a] +
+               dlsd * fa[a] / la;
+      gfb[a] = 0.5 * ca * (GP[3 * a] * eb[0] + GP[3 * a + 1] * eb[1] + GP[3 * a + 2] * eb[2]) + t2[a] +
+               dlsd * fb[a] / lb;
+    }
+    for (int c = 0; c < 3; ++c) {
+      unsafeAtomicAdd(dV + 3 * (int64_t)ia + c, (float)gfa[c]);
+      unsafeAtomicAdd(dV + 3 * (int64_t)ib + c, (float)gfb[c]);
+      acc[c] -= gfa[c] + gfb[c];
+    }
+  }
+  for (int c = 0; c < 3; ++c) unsafeAtomicAdd(dV + 3 * (int64_t)v + c, (float)acc[c]);
+}
+
 }  // namespace
 
 // The transfer's launches with the per-vertex table at vtab and the face rows
@@ -554,6 +822,40 @@ static hipError_t transfer_launches(Ctx *c, const float *V_def, int32_t N,
     hipLaunchKernelGGL(transfer_kernel<1>, grid, block, 0, c->stream, N, c->nF, (const float4 *)ftab,
                        bind_face, bind_bary, means, quats, scales, means_out, quats_out, cov3d_out,
                        xform_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_transfer_backward(Ctx *c, const float *V_def, int32_t N,
+                                    const int32_t *bind_face, const float *bind_bary,
+                                    const float *dL_dmeans, const float *dL_dxform,
+                                    float *dL_dV_def, bool accumulate) {
+  float *vtab = (float *)c->vtab.p;
+  float *gv = (float *)c->gvert.p;
+  hipError_t e = hipSuccess;
+  if (!accumulate) e = launch_fill_u32(c, (uint32_t *)dL_dV_def, 3 * (int64_t)c->nV, 0u);
+  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t *)gv, 12 * (int64_t)c->nV, 0u);
+  if (e != hipSuccess) return e;
+  ScopedTimer t(c, K_TRANSFER_BWD);
+  hipLaunchKernelGGL(vertex_frames_kernel, dim3(ceil_div(c->nV, 128)), dim3(128), 0, c->stream,
+                     c->nV, (const float *)c->V_rest.p, V_def, (const int32_t *)c->faces.p,
+                     (const int32_t *)c->vf_ptr.p, (const int32_t *)c->vf_idx.p, vtab);
+  hipLaunchKernelGGL(face_rows_kernel, dim3((unsigned)ceil_div(9 * ((int64_t)c->nF + 1), 256)),
+                     dim3(256), 0, c->stream, c->nF, (const int32_t *)c->faces.p,
+                     (const float4 *)vtab, (float4 *)c->ftab.p);
+  if (N > 0) {
+    const dim3 grid(ceil_div(N, 128)), block(128);
+    if (c->opt.k_bind == 8)
+      hipLaunchKernelGGL(transfer_bwd_kernel<8>, grid, block, 0, c->stream, N, c->nF,
+                         (const int32_t *)c->faces.p, (const float *)c->ftab.p, bind_face, bind_bary,
+                         dL_dmeans, dL_dxform, gv);
+    else
+      hipLaunchKernelGGL(transfer_bwd_kernel<1>, grid, block, 0, c->stream, N, c->nF,
+                         (const int32_t *)c->faces.p, (const float *)c->ftab.p, bind_face, bind_bary,
+                         dL_dmeans, dL_dxform, gv);
+  }
+  hipLaunchKernelGGL(vertex_bwd_kernel, dim3(ceil_div(c->nV, 128)), dim3(128), 0, c->stream, c->nV,
+                     (const float *)c->V_rest.p, V_def, (const int32_t *)c->faces.p,
+                     (const int32_t *)c->vf_ptr.p, (const int32_t *)c->vf_idx.p, gv, dL_dV_def);
   return hipGetLastError();
 }
 

@@ -294,6 +294,8 @@ class Rasterizer:
             out = dict(means=torch.empty((N, 3), device=d), scales=torch.empty((N, 3), device=d),
                        quats=torch.empty((N, 4), device=d), opacity=torch.empty((N,), device=d),
                        sh=torch.empty((N, nc), device=d))
+            if xform is not None:
+                out["xform"] = torch.empty((N, 9), device=d)
         if dL.numel() != fwd["image"].numel():
             raise ValueError("dL_dimage must have the image's shape")
         with self._on_stream():
@@ -301,6 +303,29 @@ class Rasterizer:
                 self.h, _ptr(dL), _ptr(fwd["T_final"]), _ptr(fwd["n_contrib"]), _ptr(fwd["T_entity_in"]),
                 _ptr(means), _ptr(scales), _ptr(quats), _ptr(xform), _ptr(sh), _ptr(out["means"]),
                 _ptr(out["scales"]), _ptr(out["quats"]), _ptr(out["opacity"]), _ptr(out["sh"]),
+                _ptr(out.get("xform")), 1 if accumulate else 0))
+        return out
+
+    def backward_transfer(self, V_def, bind_face, bind_bary, dL_dmeans=None, dL_dxform=None,
+                          out: Optional[torch.Tensor] = None, accumulate: bool = False) -> torch.Tensor:
+        """dL/dV_def (nV,3) of the deformed proxy from the gradients with
+        respect to the transferred means and A (umgs_backward_transfer):
+        ``dL_dmeans`` and ``dL_dxform`` as backward() returns them as
+        "means" and "xform" for a frame whose Gaussians came from
+        bind_transfer(V_def, bind_face, bind_bary, ...)."""
+        d = self.device
+        V_def = _f32(V_def, d)
+        face = _i32(bind_face, d)
+        bary = _f32(bind_bary, d)
+        N = int(face.shape[0])
+        dm = None if dL_dmeans is None else _f32(dL_dmeans, d)
+        dx = None if dL_dxform is None else _f32(dL_dxform, d)
+        nV = int(V_def.numel() // 3)
+        if out is None:
+            out = torch.empty((nV, 3), device=d)
+        with self._on_stream():
+            self._check(self.lib.umgs_backward_transfer(
+                self.h, _ptr(V_def), N, _ptr(face), _ptr(bary), _ptr(dm), _ptr(dx), _ptr(out),
                 1 if accumulate else 0))
         return out
 
@@ -555,29 +580,37 @@ def scene_inputs(scene, cov3d=None, means=None) -> Dict:
 
 
 class _RenderFunction(torch.autograd.Function):
-    """Differentiable render of Gaussians (+ fixed triangles) through the C ABI."""
+    """Differentiable render through the C ABI: Gaussians, the deformed
+    proxy's vertices, and the triangles' per-vertex colours and opacities."""
 
     @staticmethod
-    def forward(ctx, means, scales, quats, opacity, sh, rast, cams, tris, deform):
+    def forward(ctx, means, scales, quats, opacity, sh, V_def, tri_rgb, tri_alpha, rast, cams,
+                tri_xyz, binding):
         with torch.no_grad():
-            if deform is not None:
-                dt = rast.bind_transfer(deform["V_def"], deform["bind_face"], deform["bind_bary"],
+            if binding is not None:
+                dt = rast.bind_transfer(V_def, binding["bind_face"], binding["bind_bary"],
                                         means, quats, scales)
                 pm, cov, xform = dt["means"], dt["cov3d"], dt["xform"]
             else:
                 pm, cov, xform = means, None, None
             rast.project(cams, means=pm, cov3d=cov, scales=None if cov is not None else scales,
                          quats=None if cov is not None else quats, opacity=opacity,
-                         sh=sh.reshape(sh.shape[0], -1), **tris)
+                         sh=sh.reshape(sh.shape[0], -1), tri_xyz=tri_xyz, tri_rgb=tri_rgb,
+                         tri_alpha=tri_alpha)
             rast.bin()
             rast.sort()
             out = rast.blend(want_state=True)
         ctx.rast = rast
         ctx.frame_id = rast.frame_id
         ctx.fwd = out
+        empty = torch.empty(0, device=means.device)
         ctx.save_for_backward(pm.detach(), scales.detach(), quats.detach(), sh.detach(),
-                              xform if xform is not None else torch.empty(0, device=means.device))
+                              xform if xform is not None else empty)
         ctx.has_xform = xform is not None
+        ctx.binding = binding
+        ctx.V_def = V_def.detach() if isinstance(V_def, torch.Tensor) else V_def
+        ctx.tri_shapes = (tuple(tri_rgb.shape) if isinstance(tri_rgb, torch.Tensor) else None,
+                          tuple(tri_alpha.shape) if isinstance(tri_alpha, torch.Tensor) else None)
         ctx.sh_shape = sh.shape
         return out["image"]
 
@@ -588,19 +621,36 @@ class _RenderFunction(torch.autograd.Function):
             raise RuntimeError("the rasterizer has projected another frame since this forward; "
                                "run backward before the next forward on the same Rasterizer")
         pm, scales, quats, sh, xform = ctx.saved_tensors
-        g = rast.backward(dL_dimage.contiguous(), ctx.fwd, pm, scales, quats,
-                          sh.reshape(sh.shape[0], -1), xform if ctx.has_xform else None)
+        dL = dL_dimage.contiguous()
+        g = rast.backward(dL, ctx.fwd, pm, scales, quats, sh.reshape(sh.shape[0], -1),
+                          xform if ctx.has_xform else None)
+        dV = d_rgb = d_alpha = None
+        if ctx.has_xform and ctx.needs_input_grad[5]:
+            dV = rast.backward_transfer(ctx.V_def, ctx.binding["bind_face"], ctx.binding["bind_bary"],
+                                        g["means"], g["xform"]).reshape(ctx.V_def.shape)
+        if ctx.needs_input_grad[6] or ctx.needs_input_grad[7]:
+            tg = rast.backward_triangles(dL, ctx.fwd)
+            if ctx.needs_input_grad[6]:
+                d_rgb = tg["tri_rgb"].reshape(ctx.tri_shapes[0])
+            if ctx.needs_input_grad[7]:
+                d_alpha = tg["tri_alpha"].reshape(ctx.tri_shapes[1])
         return (g["means"], g["scales"], g["quats"], g["opacity"], g["sh"].reshape(ctx.sh_shape),
-                None, None, None, None)
+                dV, d_rgb, d_alpha, None, None, None, None)
 
 
 def render_differentiable(rast: Rasterizer, cams, means, scales, quats, opacity, sh, tri_xyz=None,
                           tri_rgb=None, tri_alpha=None, deform: Optional[Dict] = None) -> torch.Tensor:
     """Packed image (3,H,W per view) as a differentiable function of the
     Gaussians' means, linear scales, raw quaternions, opacities and SH
-    coefficients.  ``deform`` = dict(V_def, bind_face, bind_bary) moves the
-    Gaussians with the proxy set by ``rast.set_proxy`` first (gradients are
-    then with respect to the rest parameters).  The backward must run before
-    the next forward on the same Rasterizer."""
-    tris = dict(tri_xyz=tri_xyz, tri_rgb=tri_rgb, tri_alpha=tri_alpha)
-    return _RenderFunction.apply(means, scales, quats, opacity, sh, rast, list(cams), tris, deform)
+    coefficients, and of the triangles' per-vertex colours and opacities
+    when those are tensors that require gradients.  ``deform`` =
+    dict(V_def, bind_face, bind_bary) moves the Gaussians with the proxy set
+    by ``rast.set_proxy`` first (gradients are then with respect to the rest
+    parameters, and to V_def when it requires them).  The backward must run
+    before the next forward on the same Rasterizer."""
+    V_def, binding = None, None
+    if deform is not None:
+        V_def = deform["V_def"]
+        binding = dict(bind_face=deform["bind_face"], bind_bary=deform["bind_bary"])
+    return _RenderFunction.apply(means, scales, quats, opacity, sh, V_def, tri_rgb, tri_alpha, rast,
+                                 list(cams), tri_xyz, binding)

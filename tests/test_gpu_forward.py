@@ -432,3 +432,30 @@ def test_many_views_past_one_workgroup_chunk_plan(torch_dev):
     for v in (0, 17, 39):
         r1, o1 = run(s, cams=[cams[v]])
         assert np.array_equal(to_np(imgs[v]), to_np(o1["image"]).reshape(3, 1080, 1920)), v
+
+
+@pytest.mark.parametrize("theta", [0.6, 0.9, 0.97, 0.999])
+def test_rigid_rotation_near_pi_transfer_parity(torch_dev, theta):
+    """The proxy rotated rigidly by theta * pi about an oblique axis (and
+    moved): every vertex's rotation is that one, so R' must be it too.  Past
+    pi/2 both sides take the rotation's axis from its symmetric part (the
+    antisymmetric part, 2 sin(theta) a, no longer carries it accurately)."""
+    from scipy.spatial.transform import Rotation
+    from paper_2601_19233_amd.render import Rasterizer
+    rng = np.random.default_rng(8)
+    V, F = scenes.icosphere(6, 1.0)
+    V, F = V.astype(np.float32), F.astype(np.int32)
+    n = 500
+    mu = scenes._sample_on_mesh(rng, V.astype(np.float64), F, n, 0.02).astype(np.float32)
+    sc, q, _, _ = scenes._gaussian_stats(rng, n, 0)
+    sc, q = sc.astype(np.float32), q.astype(np.float32)
+    bf, bb = scenes.make_binding(mu, sc, q, V, F, 8)
+    axis = np.array([0.3, -0.8, 0.52])
+    Rg = Rotation.from_rotvec(axis / np.linalg.norm(axis) * theta * np.pi).as_matrix()
+    Vd = (V.astype(np.float64) @ Rg.T + np.array([0.2, -0.1, 0.3])).astype(np.float32)
+    note(f"rigid rotation {theta} pi N={n}")
+    r = Rasterizer("cuda:0", k_bind=8)
+    r.set_proxy(V, F)
+    dt, ot = check_transfer(r, V, F, Vd, bf, bb, mu, q, sc)
+    np.testing.assert_allclose(ot["A"], np.broadcast_to(Rg, ot["A"].shape), atol=1e-6)
+    r.close()

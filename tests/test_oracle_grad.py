@@ -150,6 +150,41 @@ def test_gradients_deformed_match_finite_differences():
     assert checked >= 20
 
 
+def test_gradient_wrt_the_transfer_map_matches_finite_differences():
+    """dL/dA of a deformed scene (Sigma' = A Sigma A^T), the input of the
+    transfer backward: central differences of the forward oracle over all
+    nine entries of A for three Gaussians."""
+    cam, means, scales, quats, opac, sh, xyz, rgb, al = mixed_scene(4)
+    rng = np.random.default_rng(5)
+    n = means.shape[0]
+    A = np.eye(3)[None] + rng.normal(0, 0.15, size=(n, 3, 3))
+    off = rng.normal(0, 0.03, size=(n, 3))
+    px = all_pixels(cam)
+    w = np.random.default_rng(7).normal(size=(len(px), 3))
+    params = [means, scales, quats, opac, sh]
+    g = OG.gradients(cam, px, w, means, scales, quats, opac, sh, 0, xyz, rgb, al,
+                     bg=(0.1, 0.2, 0.3), xform=A, mean_offset=off)["xform"]
+    _, sig0 = loss(cam, px, w, *params, 0, xyz, rgb, al, 0, A, off)
+    gmax = np.abs(g).max()
+    checked = 0
+    for gi in (0, 3, 5):
+        for idx in np.ndindex(3, 3):
+            vals, ok = [], True
+            for sgn in (1, -1):
+                A2 = A.copy()
+                A2[(gi,) + idx] += sgn * 1e-6
+                L, sig = loss(cam, px, w, *params, 0, xyz, rgb, al, 0, A2, off)
+                ok &= sig == sig0
+                vals.append(L)
+            if not ok:
+                continue
+            fd = (vals[0] - vals[1]) / 2e-6
+            an = g[(gi,) + idx]
+            assert abs(fd - an) <= 2e-5 * max(abs(fd), abs(an)) + 1e-7 * gmax, (gi, idx, fd, an)
+            checked += 1
+    assert checked >= 20 and gmax > 0
+
+
 @pytest.mark.slow
 def test_gradients_at_800px_sh3_match_stored_finite_differences():
     """The 800x800 SH-3 workload (300,000 Gaussians, 50,176 triangles), loss
