@@ -702,6 +702,42 @@ def main():
     r.set_profiling(False)
     tpairs = r.backward_pairs(o["n_contrib"], triangles=True)
     log(f"triangle backward {ms_tri:.3f} ms, work {tpairs}")
+    # ---- proxy-vertex gradients of the same loss ----------------------------
+    gl = step_fb()
+    gV = r.backward_transfer(V_def, bface, bbary, gl["means"], gl["xform"])
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        r.backward_transfer(V_def, bface, bbary, gl["means"], gl["xform"], out=gV)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_px = e0.elapsed_time(e1) / args.steps
+    r.set_profiling(True)
+    for _ in range(args.steps):
+        r.backward_transfer(V_def, bface, bbary, gl["means"], gl["xform"], out=gV)
+    prof_px = r.profile()
+    r.set_profiling(False)
+    log(f"proxy backward {ms_px:.3f} ms")
+    # algorithmic bytes of one call: per Gaussian its K bindings (12 B each),
+    # dL/dmu' and dL/dA read (48 B), its gradient row and corner keys and ids
+    # written (48 + 8 K B); per corner its key, id and barycentrics read
+    # (16 B) and its Gaussian's row gathered (48 B); per face row 144 B read
+    # (the gather rounds) and 144 B of sums; per vertex its frame inputs
+    K = scene.bind_face.shape[1]
+    nF = int(scene.proxy.faces.shape[0])
+    px_bytes = scene.N * (12 * K + 48 + 48 + 8 * K) + scene.N * K * (16 + 48) + nF * 288
+    px_ms = prof_px["transfer_backward"][1] / prof_px["transfer_backward"][0]
+    px_ach = px_bytes / (px_ms * 1e-3) / 1e9
+    fwd_bwd["proxy"] = {
+        "ms_per_call": round(ms_px, 4),
+        "path": "umgs_backward_transfer: dL/dV' of the deformed proxy from dL/dmu' and dL/dA",
+        "stages_ms": {k: round(v[1] / args.steps, 4) for k, v in prof_px.items()},
+        "nV": int(scene.proxy.V_rest.shape[0]), "gaussians": scene.N,
+        "roofline": {"kernel": "transfer_backward (all of its launches)", "bound": "hbm",
+                     "achieved": round(px_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(px_ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "ms_per_launch": round(px_ms, 4), "bytes": int(px_bytes)}}
+    del gl, gV
     fwd_bwd["triangles"] = {
         "ms_per_call": round(ms_tri, 4),
         "path": "umgs_backward_triangles on the same frame: dL/d(per-vertex colour, opacity)",

@@ -178,7 +178,8 @@ void umgs_destroy(umgs_ctx *ctx) {
                     &c->chunk_base, &c->cnt2, &c->chunk_tab, &c->tstart, &c->totals,
                     &c->v0, &c->v1, &c->hist, &c->ranges, &c->g2d,
                     &c->minmax, &c->lb, &c->finfo, &c->tile_order, &c->bwd_order, &c->pair_count,
-                    &c->view_sums, &c->tex, &c->tex_uv, &c->gvert};
+                    &c->view_sums, &c->tex, &c->tex_uv, &c->tb_g, &c->tb_key[0], &c->tb_key[1],
+                    &c->tb_val[0], &c->tb_val[1], &c->tb_face};
   for (DevBuf *b : bufs) free_buf(*b);
   for (auto &p : c->prof.pending) {
     (void)hipEventDestroy(p.a);
@@ -704,8 +705,21 @@ umgs_status umgs_backward_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
     return fail(c, UMGS_ERR_INVALID_ARG, "umgs_backward_transfer: NULL binding array");
   if (c->capturing)
     return fail(c, UMGS_ERR_STATE, "umgs_backward_transfer: the stream is being captured");
-  umgs_status s = ensure(c, c->gvert, sizeof(float) * 12 * (size_t)c->nV, "vertex gradients");
-  if (s != UMGS_OK) return s;
+  const int64_t M = std::max<int64_t>((int64_t)N * c->opt.k_bind, 1);
+  if (M >= (1LL << 31))
+    return fail(c, UMGS_ERR_CAPACITY, "umgs_backward_transfer: N*K = %lld corners", (long long)M);
+  const int64_t hb = (int64_t)radix_hist_bytes((uint64_t)M);
+  umgs_status s;
+  if ((s = ensure(c, c->tb_face, sizeof(float) * 36 * (size_t)c->nF, "per-face gradient sums")) ||
+      (s = ensure(c, c->tb_g, sizeof(float) * 12 * (size_t)std::max<int32_t>(N, 1), "Gaussian gradient rows")) ||
+      (s = ensure(c, c->tb_key[0], sizeof(uint32_t) * (size_t)M, "corner keys")) ||
+      (s = ensure(c, c->tb_key[1], sizeof(uint32_t) * (size_t)M, "corner keys")) ||
+      (s = ensure(c, c->tb_val[0], sizeof(uint32_t) * (size_t)M, "corner ids")) ||
+      (s = ensure(c, c->tb_val[1], sizeof(uint32_t) * (size_t)M, "corner ids")) ||
+      (s = ensure(c, c->hist, (size_t)hb, "radix histograms")) ||
+      (s = ensure(c, c->scan_tmp, scan_tmp_bytes(std::max<int64_t>({M + 1, 1 << 20, hb / 4})),
+                  "scan scratch")))
+    return s;
   return hip_check(c, launch_transfer_backward(c, V_def, N, bind_face, bind_bary, dL_dmeans,
                                                dL_dxform, dL_dV_def, accumulate != 0),
                    "transfer backward launch");

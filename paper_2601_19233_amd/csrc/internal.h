@@ -137,7 +137,9 @@ struct Ctx {
   int32_t nV = 0, nF = 0;
   DevBuf V_rest, faces, vf_ptr, vf_idx, vtab;
   DevBuf ftab;   // per face: its three vertex rows (9 float4, 144 B)
-  DevBuf gvert;  // per vertex: gradient of (Delta, r, S) in the transfer backward (12 floats)
+  // transfer backward: per-Gaussian gradient rows (12 floats), corner sort
+  // keys and ids (ping-pong), per-face sums (36 floats)
+  DevBuf tb_g, tb_key[2], tb_val[2], tb_face;
   // BVH of the rest proxy for the binding association (rebuilt per call)
   DevBuf bvh_code[2], bvh_id[2];  // nF uint32: Morton codes / face ids (ping-pong sort)
   DevBuf bvh_tri;                 // nF x 3 float4: leaf triangles in Morton order

@@ -466,13 +466,89 @@ __device__ __forceinline__ float inv_bound(int kb) {
   return r;
 }
 
-template <int K>
+// Backward finish of Gaussian i (BWD instantiation of the transfer kernel):
+// from the corner sums rs, Ss and dL/dmu', dL/dA, the row
+// g = (dL/dmu', dL/d rbar, sym dL/dS') / k_b its corners pass on (zero
+// without a bound corner), through Eq. 13:
+//   dL/dS' = R'^T dL/dA,  dL/dR' = dL/dA S'^T,
+//   dL/d rbar = J_r(rbar)^T vee(R'^T dL/dR' - dL/dR'^T R')   (R' = exp(rbar)).
+__device__ __forceinline__ void finish_backward(int i, const float rs[3], const float Ss[6],
+                                                float invk, bool any_bound,
+                                                const float *__restrict__ dmu,
+                                                const float *__restrict__ dA,
+                                                float *__restrict__ gG) {
+  float *go = gG + 12 * (int64_t)i;
+  if (!any_bound) {                    // rest pose: no dependence on the proxy
+#pragma unroll
+    for (int q = 0; q < 12; ++q) go[q] = 0.0f;
+    return;
+  }
+  const float r0 = rs[0] * invk, r1 = rs[1] * invk, r2 = rs[2] * invk;
+  const float th2 = r0 * r0 + r1 * r1 + r2 * r2, th = sqrtf(th2);
+  float sa, hb, cb;   // sin(th)/th, (1 - cos th)/th^2, (th - sin th)/th^3
+  if (th < 1e-2f) {
+    sa = 1.0f - th2 * (1.0f / 6.0f);
+    hb = 0.5f - th2 * (1.0f / 24.0f);
+    cb = 1.0f / 6.0f - th2 * (1.0f / 120.0f);
+  } else {
+    const float sn = sinf(th), h = sinf(0.5f * th);
+    sa = sn / th;
+    const float q = h / (0.5f * th);
+    hb = 0.5f * q * q;
+    cb = (1.0f - sa) / th2;
+  }
+  const float Rp[9] = {1.f - hb * (r1 * r1 + r2 * r2), -sa * r2 + hb * r0 * r1, sa * r1 + hb * r0 * r2,
+                       sa * r2 + hb * r0 * r1, 1.f - hb * (r0 * r0 + r2 * r2), -sa * r0 + hb * r1 * r2,
+                       -sa * r1 + hb * r0 * r2, sa * r0 + hb * r1 * r2, 1.f - hb * (r0 * r0 + r1 * r1)};
+  const float Sm[9] = {Ss[0] * invk, Ss[1] * invk, Ss[2] * invk, Ss[1] * invk, Ss[3] * invk,
+                       Ss[4] * invk, Ss[2] * invk, Ss[4] * invk, Ss[5] * invk};
+  float GA[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) GA[k] = dA ? nt_load(dA + 9 * (int64_t)i + k) : 0.0f;
+  float GS[9], GR[9];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      GS[3 * a + b] = Rp[a] * GA[b] + Rp[3 + a] * GA[3 + b] + Rp[6 + a] * GA[6 + b];           // R'^T GA
+      GR[3 * a + b] = GA[3 * a] * Sm[b] + GA[3 * a + 1] * Sm[3 + b] + GA[3 * a + 2] * Sm[6 + b];  // GA S'^T
+    }
+  float X[9];   // R'^T GR
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) X[3 * a + b] = Rp[a] * GR[b] + Rp[3 + a] * GR[3 + b] + Rp[6 + a] * GR[6 + b];
+  const float y[3] = {X[7] - X[5], X[2] - X[6], X[3] - X[1]};
+  // J_r(r)^T y = y + hb r x y + cb r x (r x y)
+  const float rxy[3] = {r1 * y[2] - r2 * y[1], r2 * y[0] - r0 * y[2], r0 * y[1] - r1 * y[0]};
+  const float rxrxy[3] = {r1 * rxy[2] - r2 * rxy[1], r2 * rxy[0] - r0 * rxy[2], r0 * rxy[1] - r1 * rxy[0]};
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    go[q] = (dmu ? nt_load(dmu + 3 * (int64_t)i + q) : 0.0f) * invk;
+    go[3 + q] = (y[q] + hb * rxy[q] + cb * rxrxy[q]) * invk;
+  }
+  go[6] = GS[0] * invk;
+  go[7] = 0.5f * (GS[1] + GS[3]) * invk;
+  go[8] = 0.5f * (GS[2] + GS[6]) * invk;
+  go[9] = GS[4] * invk;
+  go[10] = 0.5f * (GS[5] + GS[7]) * invk;
+  go[11] = GS[8] * invk;
+}
+
+// Arguments of the backward instantiation (unused by the forward one).
+struct TransferBwdArgs {
+  const float *dmu, *dA;     // dL/dmu' (N,3), dL/dA (N,9); NULL: zero
+  float *gG;                 // (N,12) rows g
+  uint32_t *keys, *vals;     // per corner: its face (nF: unbound) and its index
+};
+
+template <int K, bool BWD = false>
 __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) void transfer_kernel(
     int N, int nF, const float4 *__restrict__ ftab, const int32_t *__restrict__ bind_face,
     const float *__restrict__ bind_bary, const float *__restrict__ means,
     const float *__restrict__ quats, const float *__restrict__ scales,
     float *__restrict__ means_out, float *__restrict__ quats_out, float *__restrict__ cov3d_out,
-    float *__restrict__ xform_out) {
+    float *__restrict__ xform_out, TransferBwdArgs bw = {}) {
   __shared__ f4v rows[kTrRows * 9];
   __shared__ int n_bound[kTrRows];
   const f4v *__restrict__ ftab4 = reinterpret_cast<const f4v *>(ftab);
@@ -522,6 +598,16 @@ __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) vo
     for (int k = 0; k < K; ++k) kb += (unsigned)face[k] < (unsigned)nF ? 1 : 0;
     n_bound[lane] = kb;
   }
+  if constexpr (BWD) {
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        const int64_t c = K * (int64_t)i + k;
+        bw.keys[c] = (unsigned)face[k] < (unsigned)nF ? (uint32_t)face[k] : (uint32_t)nF;
+        bw.vals[c] = (uint32_t)c;
+      }
+    }
+  }
   float3 ds = make_float3(0.f, 0.f, 0.f);
   float rs[3] = {0.f, 0.f, 0.f}, Ss[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   f4v buf[9];
@@ -565,21 +651,25 @@ __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) vo
   }
   round(false);
   const int kb = n_bound[lane];
-  if (valid)
-    finish_gaussian(i, ds, rs, Ss, inv_bound(kb), kb > 0, means, quats, scales, means_out,
-                    quats_out, cov3d_out, xform_out);
+  if constexpr (BWD) {
+    if (valid) finish_backward(i, rs, Ss, inv_bound(kb), kb > 0, bw.dmu, bw.dA, bw.gG);
+  } else {
+    if (valid)
+      finish_gaussian(i, ds, rs, Ss, inv_bound(kb), kb > 0, means, quats, scales, means_out,
+                      quats_out, cov3d_out, xform_out);
+  }
 }
 
 
 // ---- backward: the gradient with respect to the deformed proxy ------------
 //
-// transfer_bwd_kernel (one thread per Gaussian, FP32): from dL/dmu' and
-// dL/dA of a Gaussian with k_b bound corners, Eq. 13 gives
-//   dL/dS' = R'^T dL/dA,  dL/dR' = dL/dA S'^T,
-//   dL/d rbar = J_r(rbar)^T vee(R'^T dL/dR' - dL/dR'^T R')   (R' = exp(rbar)),
-// and Eq. 12 hands each bound corner's face vertex j the share b_j / k_b
-// of (dL/dmu', dL/d rbar, sym dL/dS'): 12 float atomics per (corner, vertex)
-// into a per-vertex table.
+// The transfer kernel's backward instantiation (one lane per Gaussian, the
+// same gather rounds) forms each Gaussian's row g = (dL/dmu', dL/d rbar,
+// sym dL/dS') / k_b (finish_backward) and one sort key per corner (its
+// face; nF when unbound); Eq. 12 hands the corner's face vertex j the share
+// b_j g.  The corners are sorted by face (the frame's radix sort) and
+// transfer_bwd_faces_kernel sums the shares of each run of one face within
+// a wave, adding 36 floats per run to a per-face table.
 // vertex_bwd_kernel (one thread per vertex, FP64): with r = log R,
 // D = R S (polar), D = P Q^-1, the vertex's (dL/dDelta, dL/dr, G = dL/dS)
 // become
@@ -591,99 +681,49 @@ __global__ __launch_bounds__(kTrRows) __attribute__((amdgpu_waves_per_eu(4))) vo
 // edges f = V'_a - V'_v (through the cross products and edge lengths of the
 // deformed normal), i.e. to V' of the vertex and its neighbours.
 
-__device__ __forceinline__ void skew_times(const double m[3], const double x[3], double y[3]) {
-  cross3(m, x, y);   // [m]_x x
-}
-
-template <int K>
-__global__ __launch_bounds__(128) void transfer_bwd_kernel(
-    int N, int nF, const int32_t *__restrict__ faces, const float *__restrict__ ftab,
-    const int32_t *__restrict__ bind_face, const float *__restrict__ bind_bary,
-    const float *__restrict__ dmu, const float *__restrict__ dA, float *__restrict__ gvert) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= N) return;
-  int kb = 0;
-  float rs[3] = {0.f, 0.f, 0.f}, Ss[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+// Per-face sums of the sorted corners: one lane per corner computes its
+// face's three vertex shares (u g, v g, w g) (36 floats) into LDS; the
+// wave's runs of equal faces (ballot of the lanes where the face changes)
+// are then summed column by column by lanes 0..35 and added to the face's
+// row of the table with one float atomic per column and run.
+__global__ __launch_bounds__(64) void transfer_bwd_faces_kernel(
+    int64_t M, int K, int nF, const uint32_t *__restrict__ skeys, const uint32_t *__restrict__ svals,
+    const float *__restrict__ gG, const float *__restrict__ bind_bary, float *__restrict__ ff) {
+  __shared__ float part[64 * 37];      // row stride 37: the column sums hit distinct banks
+  const int lane = threadIdx.x;
+  const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+  uint32_t f = (uint32_t)nF;
+  if (j < M) f = skeys[j];
+  const bool live = f < (uint32_t)nF;
+  float *row = part + 37 * lane;
+  if (live) {
+    const uint32_t c = svals[j];
+    const float u = bind_bary[2 * (int64_t)c], v = bind_bary[2 * (int64_t)c + 1];
+    const float w = (1.0f - u) - v;
+    const float *g = gG + 12 * (int64_t)(c / (uint32_t)K);
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = bind_face[K * (int64_t)i + k];
-    if ((unsigned)f >= (unsigned)nF) continue;
-    ++kb;
-    const float u = bind_bary[2 * (K * (int64_t)i + k)], v = bind_bary[2 * (K * (int64_t)i + k) + 1];
-    const float bw[3] = {u, v, (1.0f - u) - v};
-    const float *row = ftab + 36 * (int64_t)f;
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) rs[c] += bw[j] * row[12 * j + 3 + c];
-#pragma unroll
-      for (int c = 0; c < 6; ++c) Ss[c] += bw[j] * row[12 * j + 6 + c];
+    for (int q = 0; q < 12; ++q) {
+      const float gq = g[q];
+      row[q] = u * gq;
+      row[12 + q] = v * gq;
+      row[24 + q] = w * gq;
     }
   }
-  if (kb == 0) return;                 // rest pose: no dependence on the proxy
-  const float invk = 1.0f / (float)kb;
-  const float r0 = rs[0] * invk, r1 = rs[1] * invk, r2 = rs[2] * invk;
-  const float th2 = r0 * r0 + r1 * r1 + r2 * r2, th = sqrtf(th2);
-  float sa, hb, cb;   // sin(th)/th, (1 - cos th)/th^2, (th - sin th)/th^3
-  if (th < 1e-2f) {
-    sa = 1.0f - th2 * (1.0f / 6.0f);
-    hb = 0.5f - th2 * (1.0f / 24.0f);
-    cb = 1.0f / 6.0f - th2 * (1.0f / 120.0f);
-  } else {
-    const float sn = sinf(th), h = sinf(0.5f * th);
-    sa = sn / th;
-    const float q = h / (0.5f * th);
-    hb = 0.5f * q * q;
-    cb = (1.0f - sa) / th2;
-  }
-  const float Rp[9] = {1.f - hb * (r1 * r1 + r2 * r2), -sa * r2 + hb * r0 * r1, sa * r1 + hb * r0 * r2,
-                       sa * r2 + hb * r0 * r1, 1.f - hb * (r0 * r0 + r2 * r2), -sa * r0 + hb * r1 * r2,
-                       -sa * r1 + hb * r0 * r2, sa * r0 + hb * r1 * r2, 1.f - hb * (r0 * r0 + r1 * r1)};
-  const float Sm[9] = {Ss[0] * invk, Ss[1] * invk, Ss[2] * invk, Ss[1] * invk, Ss[3] * invk,
-                       Ss[4] * invk, Ss[2] * invk, Ss[4] * invk, Ss[5] * invk};
-  float GA[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) GA[k] = dA ? dA[9 * (int64_t)i + k] : 0.0f;
-  float GS[9], GR[9];
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) {
-      GS[3 * a + b] = Rp[a] * GA[b] + Rp[3 + a] * GA[3 + b] + Rp[6 + a] * GA[6 + b];           // R'^T GA
-      GR[3 * a + b] = GA[3 * a] * Sm[b] + GA[3 * a + 1] * Sm[3 + b] + GA[3 * a + 2] * Sm[6 + b];  // GA S'^T
-    }
-  float X[9];   // R'^T GR
-#pragma unroll
-  for (int a = 0; a < 3; ++a)
-#pragma unroll
-    for (int b = 0; b < 3; ++b) X[3 * a + b] = Rp[a] * GR[b] + Rp[3 + a] * GR[3 + b] + Rp[6 + a] * GR[6 + b];
-  const float y[3] = {X[7] - X[5], X[2] - X[6], X[3] - X[1]};
-  // J_r(r)^T y = y + hb r x y + cb r x (r x y)
-  const float rxy[3] = {r1 * y[2] - r2 * y[1], r2 * y[0] - r0 * y[2], r0 * y[1] - r1 * y[0]};
-  const float rxrxy[3] = {r1 * rxy[2] - r2 * rxy[1], r2 * rxy[0] - r0 * rxy[2], r0 * rxy[1] - r1 * rxy[0]};
-  float g[12];
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    g[c] = (dmu ? dmu[3 * (int64_t)i + c] : 0.0f) * invk;
-    g[3 + c] = (y[c] + hb * rxy[c] + cb * rxrxy[c]) * invk;
-  }
-  g[6] = GS[0] * invk;
-  g[7] = 0.5f * (GS[1] + GS[3]) * invk;
-  g[8] = 0.5f * (GS[2] + GS[6]) * invk;
-  g[9] = GS[4] * invk;
-  g[10] = 0.5f * (GS[5] + GS[7]) * invk;
-  g[11] = GS[8] * invk;
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int f = bind_face[K * (int64_t)i + k];
-    if ((unsigned)f >= (unsigned)nF) continue;
-    const float u = bind_bary[2 * (K * (int64_t)i + k)], v = bind_bary[2 * (K * (int64_t)i + k) + 1];
-    const float bw[3] = {u, v, (1.0f - u) - v};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      float *dst = gvert + 12 * (int64_t)faces[3 * f + j];
-#pragma unroll
-      for (int c = 0; c < 12; ++c) unsafeAtomicAdd(dst + c, bw[j] * g[c]);
+  const uint32_t prev = __shfl_up(f, 1, 64);
+  const uint64_t heads = __ballot(live && (lane == 0 || prev != f));
+  const uint64_t lives = __ballot(live);
+  __syncthreads();
+  uint64_t h = heads;
+  while (h) {
+    const int a = __builtin_ctzll(h);
+    h &= h - 1;
+    // the run ends at the next head or at the last live lane
+    const int b = h ? __builtin_ctzll(h) : 64 - __builtin_clzll(lives);
+    const uint32_t fa = __shfl(f, a, 64);
+    if (lane < 36) {
+      float sum = 0.0f;
+      for (int l = a; l < b; ++l) sum += part[37 * l + lane];
+      if (sum != 0.0f) unsafeAtomicAdd(ff + 36 * (int64_t)fa + lane, sum);
     }
   }
 }
@@ -691,15 +731,19 @@ __global__ __launch_bounds__(128) void transfer_bwd_kernel(
 __global__ __launch_bounds__(128) void vertex_bwd_kernel(
     int nV, const float *__restrict__ Vr, const float *__restrict__ Vd,
     const int32_t *__restrict__ faces, const int32_t *__restrict__ vf_ptr,
-    const int32_t *__restrict__ vf_idx, const float *__restrict__ gvert, float *__restrict__ dV) {
+    const int32_t *__restrict__ vf_idx, const float *__restrict__ ff, float *__restrict__ dV) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= nV) return;
-  double g[12];
-  bool any = false;
-  for (int c = 0; c < 12; ++c) {
-    g[c] = gvert[12 * (int64_t)v + c];
-    any = any || g[c] != 0.0;
+  // the vertex's (dL/dDelta, dL/dr, dL/dS): its slot of each incident face's sums
+  double g[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k = vf_ptr[v]; k < vf_ptr[v + 1]; ++k) {
+    const int f = vf_idx[k];
+    const int j = faces[3 * f] == v ? 0 : faces[3 * f + 1] == v ? 1 : 2;
+    const float *src = ff + 36 * (int64_t)f + 12 * j;
+    for (int c = 0; c < 12; ++c) g[c] += src[c];
   }
+  bool any = false;
+  for (int c = 0; c < 12; ++c) any = any || g[c] != 0.0;
   if (!any) return;
   VFrame F;
   vertex_frame(v, Vr, Vd, faces, vf_ptr, vf_idx, F);
@@ -830,10 +874,12 @@ hipError_t launch_transfer_backward(Ctx *c, const float *V_def, int32_t N,
                                     const float *dL_dmeans, const float *dL_dxform,
                                     float *dL_dV_def, bool accumulate) {
   float *vtab = (float *)c->vtab.p;
-  float *gv = (float *)c->gvert.p;
+  float *ff = (float *)c->tb_face.p;
+  const int K = c->opt.k_bind;
+  const int64_t M = (int64_t)N * K;
   hipError_t e = hipSuccess;
   if (!accumulate) e = launch_fill_u32(c, (uint32_t *)dL_dV_def, 3 * (int64_t)c->nV, 0u);
-  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t *)gv, 12 * (int64_t)c->nV, 0u);
+  if (e == hipSuccess) e = launch_fill_u32(c, (uint32_t *)ff, 36 * (int64_t)c->nF, 0u);
   if (e != hipSuccess) return e;
   ScopedTimer t(c, K_TRANSFER_BWD);
   hipLaunchKernelGGL(vertex_frames_kernel, dim3(ceil_div(c->nV, 128)), dim3(128), 0, c->stream,
@@ -843,19 +889,34 @@ hipError_t launch_transfer_backward(Ctx *c, const float *V_def, int32_t N,
                      dim3(256), 0, c->stream, c->nF, (const int32_t *)c->faces.p,
                      (const float4 *)vtab, (float4 *)c->ftab.p);
   if (N > 0) {
-    const dim3 grid(ceil_div(N, 128)), block(128);
-    if (c->opt.k_bind == 8)
-      hipLaunchKernelGGL(transfer_bwd_kernel<8>, grid, block, 0, c->stream, N, c->nF,
-                         (const int32_t *)c->faces.p, (const float *)c->ftab.p, bind_face, bind_bary,
-                         dL_dmeans, dL_dxform, gv);
+    uint32_t *keys[2] = {(uint32_t *)c->tb_key[0].p, (uint32_t *)c->tb_key[1].p};
+    uint32_t *vals[2] = {(uint32_t *)c->tb_val[0].p, (uint32_t *)c->tb_val[1].p};
+    float *gG = (float *)c->tb_g.p;
+    const dim3 grid(ceil_div(N, kTrRows)), block(kTrRows);
+    const TransferBwdArgs ba = {dL_dmeans, dL_dxform, gG, keys[0], vals[0]};
+    if (K == 8)
+      hipLaunchKernelGGL((transfer_kernel<8, true>), grid, block, 0, c->stream, N, c->nF,
+                         (const float4 *)c->ftab.p, bind_face, bind_bary, nullptr, nullptr, nullptr,
+                         nullptr, nullptr, nullptr, nullptr, ba);
     else
-      hipLaunchKernelGGL(transfer_bwd_kernel<1>, grid, block, 0, c->stream, N, c->nF,
-                         (const int32_t *)c->faces.p, (const float *)c->ftab.p, bind_face, bind_bary,
-                         dL_dmeans, dL_dxform, gv);
+      hipLaunchKernelGGL((transfer_kernel<1, true>), grid, block, 0, c->stream, N, c->nF,
+                         (const float4 *)c->ftab.p, bind_face, bind_bary, nullptr, nullptr, nullptr,
+                         nullptr, nullptr, nullptr, nullptr, ba);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    int bits = 1;
+    while ((1ll << bits) <= (int64_t)c->nF) ++bits;   // keys 0..nF
+    if ((e = launch_radix_sort_u32(c, keys, vals, (uint64_t)M, nullptr, nullptr, bits, -1, -1, -1)) !=
+        hipSuccess)
+      return e;
+    const int res = radix_passes(bits) & 1;
+    hipLaunchKernelGGL(transfer_bwd_faces_kernel, dim3((unsigned)ceil_div(M, 64)),
+                       dim3(64), 0, c->stream, M, K, c->nF, (const uint32_t *)keys[res],
+                       (const uint32_t *)vals[res], (const float *)gG, bind_bary, ff);
   }
   hipLaunchKernelGGL(vertex_bwd_kernel, dim3(ceil_div(c->nV, 128)), dim3(128), 0, c->stream, c->nV,
                      (const float *)c->V_rest.p, V_def, (const int32_t *)c->faces.p,
-                     (const int32_t *)c->vf_ptr.p, (const int32_t *)c->vf_idx.p, gv, dL_dV_def);
+                     (const int32_t *)c->vf_ptr.p, (const int32_t *)c->vf_idx.p, (const float *)ff,
+                     dL_dV_def);
   return hipGetLastError();
 }
 
