@@ -413,3 +413,39 @@ def test_cfg1_binding_association_sampled(gpu, cfg1):
     note(f"binding sampled: {clear} clear, {amb} ambiguous")
     assert amb <= 0.02 * (clear + amb)
     r.close()
+
+
+def test_cfg1_proxy_gradient_sampled(gpu, cfg1):
+    """The transfer backward at the benchmark's size (1M Gaussians, K = 8,
+    the 20,480-face proxy) with dL/dmu' and dL/dA nonzero for 3,000 sampled
+    Gaussians: dL/dV' against the transfer gradient oracle on those
+    Gaussians (the others contribute nothing)."""
+    import torch
+    from oracle import transfer_grad as TG
+    from paper_2601_19233_amd.render import Rasterizer
+    s = cfg1
+    rng = np.random.default_rng(31)
+    pick = np.sort(rng.choice(s.N, 3000, replace=False))
+    gm = np.zeros((s.N, 3), np.float32)
+    gA = np.zeros((s.N, 9), np.float32)
+    gm[pick] = rng.normal(size=(pick.size, 3))
+    gA[pick] = rng.normal(size=(pick.size, 9))
+    note(f"cfg1 proxy gradient: N={s.N}, {pick.size} Gaussians with a gradient")
+    ref = TG.proxy_gradient(s.proxy.V_rest, s.proxy.faces, s.proxy.V_def, s.means[pick],
+                            s.bind_face[pick], s.bind_bary[pick], gm[pick].astype(np.float64),
+                            gA[pick].reshape(-1, 3, 3).astype(np.float64))
+    d = dev_tensors(s)
+    r = Rasterizer("cuda:0", tile=(16, 16), frag_batch=128)
+    r.set_proxy(s.proxy.V_rest, s.proxy.faces)
+    df = d["deform"]
+    f = lambda a: torch.from_numpy(a).cuda()
+    g = r.backward_transfer(df["V_def"], df["bind_face"], df["bind_bary"], f(gm), f(gA))
+    torch.cuda.synchronize()
+    gg = g.cpu().numpy().astype(np.float64)
+    hit = np.abs(ref).sum(1) > 0
+    assert hit.sum() > 1000
+    scale = np.abs(ref).max()
+    err = np.abs(gg - ref)
+    bad = err > 1e-3 * np.abs(ref) + 1e-5 * scale
+    assert not bad.any(), (int(bad.sum()), float(err.max()), float(scale))
+    r.close()
