@@ -496,7 +496,7 @@ umgs_status umgs_project(umgs_ctx *ctx, int32_t V, const umgs_camera *cams, int3
       (s = ensure(c, c->lb, sizeof(LbState), "scan state")) ||
       (s = ensure(c, c->finfo, sizeof(FrameInfo), "frame info")) ||
       (s = ensure(c, c->tile_order, sizeof(uint32_t) * (64 + tiles), "tile order")) ||
-      (s = ensure(c, c->bwd_order, sizeof(uint32_t) * (128 + 2 * tiles), "backward tile order")))
+      (s = ensure(c, c->bwd_order, sizeof(uint32_t) * (128 + 3 * tiles), "backward tile order")))
     return s;
   const bool fresh_info = c->finfo.cap && c->views.empty();
   const bool fresh_lb = !c->lb_zeroed;

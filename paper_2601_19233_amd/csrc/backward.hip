@@ -236,13 +236,19 @@ __device__ __forceinline__ int walk_bucket(uint32_t k) {
 }
 
 // key[tile] = the largest last-blended position of its pixels (clamped to
-// its list, as the walk clamps it); one wave per tile.
+// its list, as the walk clamps it), or 0 where mask (if given) is 0; one
+// wave per tile.
 template <int TW, int TH>
 __global__ __launch_bounds__(64) void walk_key_kernel(const ViewParams *__restrict__ views, int V,
                                                      const uint2 *__restrict__ ranges,
                                                      const int32_t *__restrict__ ncontrib,
+                                                     const uint32_t *__restrict__ mask,
                                                      uint32_t *__restrict__ key) {
   const uint32_t tile = blockIdx.x;
+  if (mask && mask[tile] == 0u) {
+    if (threadIdx.x == 0) key[tile] = 0u;
+    return;
+  }
   const int v = find_view(views, V, tile);
   const ViewParams &vp = views[v];
   const uint32_t lt = tile - vp.tile_base;
@@ -714,7 +720,8 @@ hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v);
 namespace {
 
 template <int TW, int TH>
-hipError_t launch_walk_order_tw(Ctx *c, const int32_t *nc, const uint32_t **order_out) {
+hipError_t launch_walk_order_tw(Ctx *c, const int32_t *nc, const uint32_t **order_out,
+                                const uint32_t *mask = nullptr) {
   const uint32_t nt = (uint32_t)c->n_tiles;
   uint32_t *cnt = (uint32_t *)c->bwd_order.p;
   uint32_t *key = cnt + kBwdBuckets;
@@ -723,7 +730,7 @@ hipError_t launch_walk_order_tw(Ctx *c, const int32_t *nc, const uint32_t **orde
   hipError_t e = launch_fill_u32(c, cnt, kBwdBuckets, 0u);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((walk_key_kernel<TW, TH>), dim3(nt), dim3(64), 0, c->stream, c->cur_views,
-                     c->V, (const uint2 *)c->ranges.p, nc, key);
+                     c->V, (const uint2 *)c->ranges.p, nc, mask, key);
   hipLaunchKernelGGL(walk_count_kernel, dim3(ceil_div(nt, 256)), dim3(256), 0, c->stream, key, nt,
                      cnt);
   hipLaunchKernelGGL(walk_scan_kernel, dim3(1), dim3(64), 0, c->stream, cnt);
@@ -757,10 +764,11 @@ hipError_t launch_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int32_t
 
 hipError_t launch_fill_u32(Ctx *c, uint32_t *p, int64_t n, uint32_t v);
 
-hipError_t launch_walk_order(Ctx *c, const int32_t *nc, const uint32_t **order) {
-  if (c->tile_w == 16 && c->tile_h == 16) return launch_walk_order_tw<16, 16>(c, nc, order);
-  if (c->tile_w == 8 && c->tile_h == 8) return launch_walk_order_tw<8, 8>(c, nc, order);
-  return launch_walk_order_tw<32, 8>(c, nc, order);
+hipError_t launch_walk_order(Ctx *c, const int32_t *nc, const uint32_t **order,
+                             const uint32_t *mask) {
+  if (c->tile_w == 16 && c->tile_h == 16) return launch_walk_order_tw<16, 16>(c, nc, order, mask);
+  if (c->tile_w == 8 && c->tile_h == 8) return launch_walk_order_tw<8, 8>(c, nc, order, mask);
+  return launch_walk_order_tw<32, 8>(c, nc, order, mask);
 }
 
 hipError_t launch_backward(Ctx *c, const float *dL, const float *Tf, const int32_t *nc,

@@ -29,7 +29,7 @@
 // fragments get LDS accumulators (the first kTriTab of them by list
 // position); a pixel adds its terms there and the workgroup adds each
 // triangle's totals to global memory once.
-#include "blend_common.h"
+#include "tri_grad.h"
 
 #include <algorithm>
 
@@ -38,135 +38,35 @@ namespace umgs {
 namespace {
 
 constexpr int kTriTab = 512;    // triangle fragments of a tile with LDS accumulators
-constexpr int kTriAcc = 10;     // opacity, then 3 vertices x RGB
 
 struct TriPix {
   float Tr, Tterm, dC0, dC1, dC2, Bd, ent;
   int last;
   float sd0, sd1, sd2, sd3;
   float p0, p1, p2, p3;
-  int fpos, bpos;   // list positions of the open entity's front and back triangles
-  float Bback;      // B . g behind the open entity
-  int n_ent;        // its triangles so far
-  // the gradient terms of its back triangle as if it were alone (t = 1,
-  // s^j = B), without the factor T_in: what an entity of one triangle (most
-  // of them) emits at its close, with no second walk
-  uint32_t c_rank, c_t;
-  float c_da, c_vis, c_w0, c_w1, c_w2;
-  float4 c_texel;
+  PixEnt e;
 };
 
-struct TriCtx {
-  const uint32_t *vals;       // the tile's list (global)
-  int64_t rbase;              // view * (N + T)
-  int N;
-  const TriRec *trec;         // this view's records
-  TexView tex;
-  int64_t Px, Py;             // pixel centre, 1/256 px
-  const uint32_t *tpos;       // LDS: ascending list positions of the tile's triangles
-  float *acc;                 // LDS: their accumulators
-  int ntab;                   // entries in tpos / acc
-  float *d_rgb, *d_alpha;
-};
-
-// Rank of list position pos among the tile's triangle fragments if it has
-// an LDS accumulator, else kNoRank.
-constexpr uint32_t kNoRank = 0xFFFFFFFFu;
-
-__device__ __forceinline__ uint32_t tri_rank(const uint32_t *tpos, int ntab, int pos) {
-  int lo = 0, hi = ntab;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if ((int)tpos[mid] < pos) lo = mid + 1; else hi = mid;
-  }
-  return (lo < ntab && (int)tpos[lo] == pos) ? (uint32_t)lo : kNoRank;
-}
-
-// Adds one (pixel, triangle) term: dL/d(effective opacity) da and the
-// colour gradient vis g (vis = T_in a mean_j o^j t^j), spread over the
-// vertices with the interpolation weights w and the texel; rank is the
-// triangle's accumulator (kNoRank: global memory).
-__device__ __forceinline__ void emit(const TriCtx &x, uint32_t rank, int64_t t, float da, float vis,
-                                     const float w[3], float4 texel, const TriPix &q) {
-  const float da_attr = da * texel.w;
-  const float gc[3] = {vis * texel.x * q.dC0, vis * texel.y * q.dC1, vis * texel.z * q.dC2};
-  if (rank != kNoRank) {
-    float *a = x.acc + kTriAcc * rank;
-    atomicAdd(a, da_attr);
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int ch = 0; ch < 3; ++ch) atomicAdd(a + 1 + 3 * k + ch, w[k] * gc[ch]);
-    return;
-  }
-  const uint32_t sw = x.trec[t].swapped;
-  unsafeAtomicAdd(x.d_alpha + t, da_attr);
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const int vin = (sw && k) ? 3 - k : k;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) unsafeAtomicAdd(x.d_rgb + 9 * t + 3 * vin + ch, w[k] * gc[ch]);
-  }
-}
-
-// Triangle index (within the view) of list position pos, or -1 for a Gaussian.
-__device__ __forceinline__ int64_t tri_at(const TriCtx &x, int pos) {
-  const int64_t local = (int64_t)x.vals[pos] - x.rbase;
-  return local < x.N ? -1 : local - x.N;
-}
-
-// The gradients of the entity [q.fpos, q.bpos] of this pixel, entered with
-// transmittance T_in.
-__device__ void rewalk_entity(const TriCtx &x, const TriPix &q, float T_in) {
-  float s0 = q.Bback, s1 = q.Bback, s2 = q.Bback, s3 = q.Bback;
-  for (int pi = q.bpos; pi >= q.fpos; --pi) {
-    const int64_t ti = tri_at(x, pi);
-    if (ti < 0) continue;
-    const TriRec &ri = x.trec[ti];
-    double e[3];
-    float o[4];
-    if (tri_eval_rec(ri, x.Px, x.Py, false, e, o) == 0) continue;
-    float cr, cg, cb, a, w[3];
-    float4 texel;
-    tri_shade_w(RecWords{&ri}, e, x.tex, cr, cg, cb, a, w, &texel);
-    // t^j in front of triangle i within the entity
-    float t0 = 1.0f, t1 = 1.0f, t2 = 1.0f, t3 = 1.0f;
-    for (int pk = q.fpos; pk < pi; ++pk) {
-      const int64_t tk = tri_at(x, pk);
-      if (tk < 0) continue;
-      const TriRec &rk = x.trec[tk];
-      double ek[3];
-      float ok[4];
-      if (tri_eval_rec(rk, x.Px, x.Py, false, ek, ok) == 0) continue;
-      float kr, kg, kb, ak;
-      tri_shade_w(RecWords{&rk}, ek, x.tex, kr, kg, kb, ak);
-      t0 *= 1.0f - ok[0] * ak; t1 *= 1.0f - ok[1] * ak;
-      t2 *= 1.0f - ok[2] * ak; t3 *= 1.0f - ok[3] * ak;
-    }
-    const float cd = fmaf(cr, q.dC0, fmaf(cg, q.dC1, cb * q.dC2));
-    const float v0 = o[0] * t0, v1 = o[1] * t1, v2 = o[2] * t2, v3 = o[3] * t3;
-    const float da = T_in * 0.25f * ((v0 * (cd - s0) + v1 * (cd - s1)) + (v2 * (cd - s2) + v3 * (cd - s3)));
-    const float vis = T_in * a * 0.25f * ((v0 + v1) + (v2 + v3));
-    emit(x, tri_rank(x.tpos, x.ntab, pi), ti, da, vis, w, texel, q);
-    s0 = fmaf(o[0] * a, cd - s0, s0);
-    s1 = fmaf(o[1] * a, cd - s1, s1);
-    s2 = fmaf(o[2] * a, cd - s2, s2);
-    s3 = fmaf(o[3] * a, cd - s3, s3);
-  }
-}
-
-__device__ __forceinline__ void close_entity(const TriCtx &x, const TriPix &q, float T_in) {
-  if (q.n_ent == 1) {
-    const float w[3] = {q.c_w0, q.c_w1, q.c_w2};
-    emit(x, q.c_rank, q.c_t, T_in * q.c_da, T_in * q.c_vis, w, q.c_texel, q);
-  } else {
-    rewalk_entity(x, q, T_in);
-  }
+// mask[tile] = 1 for every tile a triangle's tile rectangle reaches (a
+// superset of the tiles whose lists hold a triangle; plain stores of the
+// same value).
+__global__ void tri_tile_mask_kernel(const ViewParams *__restrict__ views, int V, int N, int T,
+                                     const uint2 *__restrict__ rects, uint32_t *__restrict__ mask) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)V * T) return;
+  const int v = (int)(idx / T);
+  const int64_t j = idx - (int64_t)v * T;
+  const uint2 r = rects[(int64_t)v * (N + T) + N + j];
+  const ViewParams &vp = views[v];
+  const uint32_t tx0 = r.x & 0xFFFFu, ty0 = r.x >> 16, tx1 = r.y & 0xFFFFu, ty1 = r.y >> 16;
+  for (uint32_t ty = ty0; ty < ty1; ++ty)
+    for (uint32_t tx = tx0; tx < tx1; ++tx) mask[vp.tile_base + ty * (uint32_t)vp.ntx + tx] = 1u;
 }
 
 template <int TW, int TH>
 __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
-    const uint32_t *__restrict__ order, const ViewParams *__restrict__ views, int V, int N, int T,
+    const uint32_t *__restrict__ order, const uint32_t *__restrict__ key,
+    const ViewParams *__restrict__ views, int V, int N, int T,
     int mode, int batch, float bg0, float bg1, float bg2, const uint2 *__restrict__ ranges,
     const uint32_t *__restrict__ v0, const uint32_t *__restrict__ v1,
     const FrameInfo *__restrict__ fi, const GaussRec *__restrict__ grec,
@@ -184,6 +84,7 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
   const uint32_t *vals = fi->sorted_in ? v1 : v0;
 
   const uint32_t tile = order[blockIdx.x];
+  if (key[tile] == 0u) return;       // no triangle reaches the tile (or nothing blended)
   const int v = find_view(views, V, tile);
   const ViewParams &vp = views[v];
   const uint32_t lt = tile - vp.tile_base;
@@ -218,13 +119,7 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
   q.ent = __builtin_inff();
   q.sd0 = q.sd1 = q.sd2 = q.sd3 = 0.f;
   q.p0 = q.p1 = q.p2 = q.p3 = 1.f;
-  q.fpos = q.bpos = 0;
-  q.Bback = 0.f;
-  q.n_ent = 0;
-  q.c_rank = kNoRank;
-  q.c_t = 0;
-  q.c_da = q.c_vis = q.c_w0 = q.c_w1 = q.c_w2 = 0.f;
-  q.c_texel = make_float4(1.f, 1.f, 1.f, 1.f);
+  ent_reset(q.e);
 
   int m = q.last;
 #pragma unroll
@@ -271,15 +166,31 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
     __syncthreads();
     if (tid < cn) {
       const int64_t local = (int64_t)vals[rg.x + tpos[c0 + tid]] - rbase;
-      stage_tri(slots + tid * kSlotWords, vrec[local - N], P0x, P0y);
+      const TriRec &tr = vrec[local - N];
+      uint32_t *s = slots + tid * kSlotWords;
+      stage_tri(s, tr, P0x, P0y);
+      // the tile's pixels whose samples can fall inside the triangle's box
+      // (samples lie 32..224 / 256 px into their pixel)
+      const int minX = min(tr.X[0], min(tr.X[1], tr.X[2])), maxX = max(tr.X[0], max(tr.X[1], tr.X[2]));
+      const int minY = min(tr.Y[0], min(tr.Y[1], tr.Y[2])), maxY = max(tr.Y[0], max(tr.Y[1], tr.Y[2]));
+      const int x0 = min(max(((minX + 31) >> 8) - tx * TW, 0), TW);
+      const int x1 = min(max(((maxX - 32) >> 8) + 1 - tx * TW, 0), TW);
+      const int y0 = min(max(((minY + 31) >> 8) - ty * TH, 0), TH);
+      const int y1 = min(max(((maxY - 32) >> 8) + 1 - ty * TH, 0), TH);
+      s[38] = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | ((uint32_t)y1 << 24);
     }
     __syncthreads();
     for (int f = 0; f < cn && first_cov == q.last; ++f) {
       const int pos = (int)tpos[c0 + f];
       if (pos >= q.last) break;
+      const uint32_t *s = slots + f * kSlotWords;
+      const uint32_t bx = s[38];
+      if (lx < (int)(bx & 0xFFu) || ly < (int)((bx >> 8) & 0xFFu) || lx >= (int)((bx >> 16) & 0xFFu) ||
+          ly >= (int)(bx >> 24))
+        continue;
       double e[3];
       float o[4];
-      if (tri_eval(slots + f * kSlotWords, rlx, rly, direct, e, o) > 0) first_cov = pos;
+      if (tri_eval(s, rlx, rly, direct, e, o) > 0) first_cov = pos;
     }
   }
   // triangles past the table are at later positions; one may still cover
@@ -345,7 +256,7 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
         if (!gauss_terms(s, pcx, pcy, alpha, a_un, dx, dy)) continue;
         // a blended Gaussian in front of an open entity closes it
         if (q.ent != __builtin_inff()) {
-          close_entity(x, q, q.Tr);
+          ent_close(x, q.e, q.dC0, q.dC1, q.dC2, q.Tr);
           q.ent = __builtin_inff();
         }
         const float Tb = (pos == q.last - 1) ? q.Tterm : q.Tr * __builtin_amdgcn_rcpf(1.0f - alpha);
@@ -363,32 +274,20 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
         const float cd = fmaf(cr, q.dC0, fmaf(cg, q.dC1, cb * q.dC2));
         if (direct) {
           const float Tb = (pos == q.last - 1) ? q.Tterm : q.Tr / (1.0f - alpha);
-          emit(x, s[38], s[39], Tb * (cd - q.Bd), Tb * alpha, w, texel, q);
+          emit_tri(x, s[38], s[39], Tb * (cd - q.Bd), Tb * alpha, w, texel, q.dC0, q.dC1, q.dC2);
           q.Tr = Tb;
           q.Bd = fmaf(alpha, cd - q.Bd, q.Bd);
           continue;
         }
-        if (q.ent == __builtin_inff()) {
+        const bool open = q.ent != __builtin_inff();
+        if (!open) {
           // the walk enters an entity at its last triangle
           q.ent = (pos == q.last - 1) ? -1.0f : q.Tr;
           q.sd0 = q.sd1 = q.sd2 = q.sd3 = q.Bd;
           q.p0 = q.p1 = q.p2 = q.p3 = 1.0f;
-          q.bpos = pos;
-          q.Bback = q.Bd;
-          q.n_ent = 0;
         }
-        if (++q.n_ent == 1) {
-          const float n = 0.25f * ((o[0] + o[1]) + (o[2] + o[3]));
-          q.c_rank = s[38];
-          q.c_t = s[39];
-          q.c_da = n * (cd - q.Bd);
-          q.c_vis = n * alpha;
-          q.c_w0 = w[0];
-          q.c_w1 = w[1];
-          q.c_w2 = w[2];
-          q.c_texel = texel;
-        }
-        q.fpos = pos;
+        ent_add(q.e, open, pos, s[38], s[39], q.Bd, cd, alpha,
+                0.25f * ((o[0] + o[1]) + (o[2] + o[3])), w, texel);
         const float a0 = o[0] * alpha, a1 = o[1] * alpha, a2 = o[2] * alpha, a3 = o[3] * alpha;
         q.sd0 = fmaf(a0, cd - q.sd0, q.sd0);
         q.sd1 = fmaf(a1, cd - q.sd1, q.sd1);
@@ -402,7 +301,7 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
     __syncthreads();
   }
   // past the tile's frontmost triangle: what is still open closes here
-  if (q.ent != __builtin_inff()) close_entity(x, q, q.Tr);
+  if (q.ent != __builtin_inff()) ent_close(x, q.e, q.dC0, q.dC1, q.dC2, q.Tr);
   __syncthreads();
 
   for (int i = tid; i < ntab; i += NT) {
@@ -429,11 +328,18 @@ hipError_t launch_tri_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int
   constexpr int NT = TW * TH;
   const int batch = std::min(c->frag_batch, NT);
   const size_t lds = ((size_t)batch * kSlotWords + kTriTab + (size_t)kTriTab * kTriAcc) * 4;
-  const uint32_t *order = nullptr;
-  hipError_t e = launch_walk_order(c, nc, &order);
+  const uint32_t nt = (uint32_t)c->n_tiles;
+  uint32_t *key = (uint32_t *)c->bwd_order.p + 128;
+  uint32_t *mask = key + 2 * (size_t)nt;
+  hipError_t e = launch_fill_u32(c, mask, nt, 0u);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((tri_backward_kernel<TW, TH>), dim3((uint32_t)c->n_tiles), dim3(NT), lds,
-                     c->stream, order, c->cur_views, c->V, c->N, c->T, c->mode, batch, c->bg[0],
+  const int64_t nvt = (int64_t)c->V * c->T;
+  hipLaunchKernelGGL(tri_tile_mask_kernel, dim3((unsigned)ceil_div(nvt, 256)), dim3(256), 0,
+                     c->stream, c->cur_views, c->V, c->N, c->T, (const uint2 *)c->rects.p, mask);
+  const uint32_t *order = nullptr;
+  if ((e = launch_walk_order(c, nc, &order, mask)) != hipSuccess) return e;
+  hipLaunchKernelGGL((tri_backward_kernel<TW, TH>), dim3(nt), dim3(NT), lds,
+                     c->stream, order, (const uint32_t *)key, c->cur_views, c->V, c->N, c->T, c->mode, batch, c->bg[0],
                      c->bg[1], c->bg[2], (const uint2 *)c->ranges.p, (const uint32_t *)c->v0.p,
                      (const uint32_t *)c->v1.p, (const FrameInfo *)c->finfo.p,
                      (const GaussRec *)c->grec.p, (const TriRec *)c->trec.p, frame_texture(c), dL,

@@ -171,7 +171,7 @@ struct Ctx {
   bool minmax_ready = false;   // reset once; the bin stage resets as it folds
   DevBuf finfo;        // FrameInfo (device)
   DevBuf tile_order;   // 64 bucket counters + n_tiles tile ids (persistent blend)
-  DevBuf bwd_order;    // 128 bucket counters + n_tiles keys + n_tiles tile ids (backward)
+  DevBuf bwd_order;    // 128 bucket counters + n_tiles keys + n_tiles tile ids + n_tiles mask words (backward)
   DevBuf pair_count;   // 4 uint64: blend work counters (measurement)
   DevBuf view_sums;    // V uint64: duplicates per view
   hipGraph_t graph = nullptr;
@@ -274,9 +274,12 @@ inline TexView frame_texture(const Ctx *c) {
   t.h = c->tex_h;
   return t;
 }
-// Heaviest-first tile order of the backward walks (bwd_order); returns the
-// order array through *order.
-hipError_t launch_walk_order(Ctx *c, const int32_t *nc, const uint32_t **order);
+// Heaviest-first tile order of the backward walks (bwd_order: 128 bucket
+// counters, n_tiles keys, n_tiles tile ids, n_tiles mask words); returns the
+// order array through *order.  Tiles whose mask word is 0 (mask given) get
+// key 0 and go last.
+hipError_t launch_walk_order(Ctx *c, const int32_t *nc, const uint32_t **order,
+                             const uint32_t *mask = nullptr);
 hipError_t launch_backward_triangles(Ctx *c, const float *dL, const float *Tf, const int32_t *nc,
                                      const float *Te, float *d_rgb, float *d_alpha,
                                      bool accumulate);
