@@ -311,9 +311,10 @@ umgs_status umgs_backward(umgs_ctx *ctx, const float *dL_dimage, const float *T_
  * FP64; the bindings are the same arrays as umgs_bind_transfer's (corners
  * outside [0, nF) unbound and without gradient).  Output dL_dV_def (nV,3)
  * [device], written when accumulate is 0, added to otherwise.  Float
- * atomics make the last bits run-dependent.  Not capturable (it may grow a
- * buffer).  Errors: STATE without a proxy or while capturing; INVALID_ARG
- * for N < 0 or NULL arrays; CAPACITY. */
+ * atomics make the last bits run-dependent.  Capturable once an eager call
+ * with the same N has sized its buffers.  Errors: STATE without a proxy;
+ * INVALID_ARG for N < 0 or NULL arrays; CAPACITY (also when capturing a
+ * call that would need larger buffers). */
 umgs_status umgs_backward_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
                                    const int32_t *bind_face, const float *bind_bary,
                                    const float *dL_dmeans, const float *dL_dxform,

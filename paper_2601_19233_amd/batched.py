@@ -26,7 +26,8 @@ class BatchedStep:
     def __init__(self, rast: Rasterizer, cams: Sequence, scene: Dict[str, torch.Tensor],
                  deform: Optional[Dict[str, torch.Tensor]] = None, backward: bool = False,
                  headroom: float = 1.25, group_budget: int = 3_000_000_000,
-                 group_tiles: int = 1 << 22, loss_grad: Optional[Callable] = None):
+                 group_tiles: int = 1 << 22, loss_grad: Optional[Callable] = None,
+                 triangle_grads: bool = False, proxy_grads: bool = False):
         """scene: device tensors means, opacity, sh (N, nc*3), scales, quats and
         optionally tri_xyz, tri_rgb, tri_alpha.  deform: V_def, bind_face,
         bind_bary (the proxy must already be set on ``rast``).  ``rast`` must
@@ -39,14 +40,22 @@ class BatchedStep:
         after each group's blend with that group's image slice, the slice of
         the dL buffer to fill and the group's pixel range [p0, p1), on the
         rasterizer's stream; it is captured with the rest, so it must launch
-        device work only (no allocation, no synchronisation)."""
+        device work only (no allocation, no synchronisation).
+        ``triangle_grads`` adds the triangles' colour and opacity gradients
+        (``tgrads``: tri_rgb, tri_alpha, summed over the groups),
+        ``proxy_grads`` (with ``deform``) the deformed proxy's vertex
+        gradient (``vgrad``, (nV, 3)), both inside the captured step."""
         if rast.stream.cuda_stream == 0:
             raise ValueError("BatchedStep needs a Rasterizer created with own_stream=True")
         self.r = rast
         self.cams = list(cams)
         self.scene = scene
         self.deform = deform
-        self.do_backward = backward
+        self.do_backward = backward or triangle_grads or proxy_grads
+        self.triangle_grads = triangle_grads
+        self.proxy_grads = proxy_grads and deform is not None
+        self.tgrads = None
+        self.vgrad = None
         self.loss_grad = loss_grad
         self.headroom = headroom
         self.group_budget = int(group_budget)
@@ -135,6 +144,13 @@ class BatchedStep:
                         self.loss_grad(part["image"], self.dL[3 * p0:3 * p1], p0, p1)
                 self.grads = r.backward(self.dL[3 * p0:3 * p1], part, pm, s["scales"], s["quats"],
                                         s["sh"], xf, out=self.grads, accumulate=gi > 0)
+                if self.triangle_grads:
+                    self.tgrads = r.backward_triangles(self.dL[3 * p0:3 * p1], part, out=self.tgrads,
+                                                       accumulate=gi > 0)
+        if self.proxy_grads:
+            d = self.deform
+            self.vgrad = r.backward_transfer(d["V_def"], d["bind_face"], d["bind_bary"],
+                                             self.grads["means"], self.grads["xform"], out=self.vgrad)
         return self.out
 
     def prepare(self):

@@ -703,8 +703,6 @@ umgs_status umgs_backward_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
     return fail(c, UMGS_ERR_INVALID_ARG, "umgs_backward_transfer: NULL V_def or dL_dV_def");
   if (N > 0 && (!bind_face || !bind_bary))
     return fail(c, UMGS_ERR_INVALID_ARG, "umgs_backward_transfer: NULL binding array");
-  if (c->capturing)
-    return fail(c, UMGS_ERR_STATE, "umgs_backward_transfer: the stream is being captured");
   const int64_t M = std::max<int64_t>((int64_t)N * c->opt.k_bind, 1);
   if (M >= (1LL << 31))
     return fail(c, UMGS_ERR_CAPACITY, "umgs_backward_transfer: N*K = %lld corners", (long long)M);
