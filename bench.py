@@ -398,6 +398,29 @@ def batched_leg(s, cams, name, args):
         log(f"batched {name} {key}: {ms:.2f} ms per {V}-view step")
         del step, rb
         torch.cuda.empty_cache()
+    # the whole training step: also the triangles' colour and opacity
+    # gradients and the deformed proxy's vertex gradient, in the same graph
+    rb = Rasterizer("cuda:0", sh_degree=s.sh_degree, k_bind=k_bind, tile=best["tile"],
+                    frag_batch=best["frag_batch"], schedule=best["schedule"], own_stream=True)
+    rb.set_proxy(s.proxy.V_rest, s.proxy.faces)
+
+    def l2_grad_all(img, dl, p0, p1):
+        torch.sub(img, target[3 * p0:3 * p1], out=dl)
+        dl.mul_(2.0)
+
+    step = BatchedStep(rb, cams, sc, deform=deform, backward=True, loss_grad=l2_grad_all,
+                       triangle_grads=True, proxy_grads=True)
+    step.prepare()
+    ms = timed(step, steps)
+    if rb.overflowed():
+        raise RuntimeError("batched step overflowed its reserved key capacity")
+    res["fwd_bwd_all_views_s"] = round(V / (ms * 1e-3), 2)
+    res["fwd_bwd_all_ms_per_step"] = round(ms, 3)
+    res["fwd_bwd_all_path"] = ("forward + backward with the Gaussians', the triangles' (colour, "
+                               "opacity) and the proxy vertices' gradients, one graph")
+    log(f"batched {name} fwd_bwd_all: {ms:.2f} ms per {V}-view step")
+    del step, rb
+    torch.cuda.empty_cache()
     res["fwd_bwd_vs_plain_fwd"] = round(res["fwd_bwd_views_s"] / res["plain_fwd_views_s"], 3)
     return res
 
