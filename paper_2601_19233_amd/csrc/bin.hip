@@ -672,24 +672,48 @@ struct L2Args {
   uint32_t cap;                // record ids out holds
 };
 
-// Lane j's result: how many lanes of the wave have bit j of m set.
-__device__ __forceinline__ uint32_t wave_bit_counts(uint64_t m) {
-  const uint32_t mw[2] = {(uint32_t)m, (uint32_t)(m >> 32)};
-  int mine = 0;
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-#pragma unroll
-    for (int jj = 0; jj < 32; ++jj) {
-      // ballot of bit j, its count (scalar) written straight into lane j
-      const uint64_t b = __builtin_amdgcn_ballot_w64(__builtin_amdgcn_ubfe(mw[h], jj, 1) != 0u);
-      const int n = (int)__popcll(b);
-      asm volatile("v_writelane_b32 %0, %1, %2" : "+v"(mine) : "s"(n), "i"(32 * h + jj));
-    }
+// The wave's 64 x 64 bit matrix (row i = lane i's m) transposed: lane j's
+// result has bit i set iff lane i's m has bit j set.  Six stages swap the
+// off-diagonal blocks of 32, 16, ..., 1 bits between lanes i and i ^ s; in
+// the 32-bit stages the lower lane of a pair keeps the bit positions of
+// mask_s (positions whose bit s is clear) and takes the rest from the upper
+// lane's word rotated left by s, the upper lane keeps the other positions
+// and takes the lower lane's word rotated right by s (one alignbit and one
+// bitfield insert per word and stage).
+__device__ __forceinline__ uint64_t wave_transpose64(uint64_t m) {
+  const int lane = (int)__lane_id();
+  uint32_t lo = (uint32_t)m, hi = (uint32_t)(m >> 32);
+  {
+    const bool low = lane < 32;
+    const uint32_t r = (uint32_t)__shfl_xor((int)(low ? hi : lo), 32, 64);
+    hi = low ? r : hi;
+    lo = low ? lo : r;
   }
-  return (uint32_t)mine;
+  constexpr uint32_t kMask[5] = {0x0000FFFFu, 0x00FF00FFu, 0x0F0F0F0Fu, 0x33333333u, 0x55555555u};
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const int s = 16 >> k;
+    const bool low = (lane & s) == 0;
+    const uint32_t keep = low ? kMask[k] : ~kMask[k];
+    const uint32_t rot = low ? 32u - (uint32_t)s : (uint32_t)s;   // rotate right by this
+    const uint32_t plo = (uint32_t)__shfl_xor((int)lo, s, 64);
+    const uint32_t phi = (uint32_t)__shfl_xor((int)hi, s, 64);
+    lo = (keep & lo) | (~keep & __builtin_amdgcn_alignbit(plo, plo, rot));
+    hi = (keep & hi) | (~keep & __builtin_amdgcn_alignbit(phi, phi, rot));
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Lane j's result: how many lanes of the wave have bit j of m set (every
+// lane of the wave must be active).
+__device__ __forceinline__ uint32_t wave_bit_counts(uint64_t m) {
+  return (uint32_t)__popcll(wave_transpose64(m));
 }
 
 // A chunk's per-tile counts (bit counts of its entries' masks).
+constexpr int kL2Rounds = kChunk / kL2Threads;   // rounds of a chunk: 4 per wave
+static_assert(kChunk % kL2Threads == 0, "a chunk is whole rounds of the workgroup");
+
 __global__ __launch_bounds__(kL2Threads) void tile_count_kernel(L2Args a) {
   // consecutive chunks (mostly of one supertile) on one XCD
   const uint32_t c = xcd_block(blockIdx.x, gridDim.x);
@@ -697,12 +721,17 @@ __global__ __launch_bounds__(kL2Threads) void tile_count_kernel(L2Args a) {
   __shared__ uint32_t wc[kL2Waves][64];
   const ChunkRec ck = a.chunks[c];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  uint32_t acc = 0;
   const uint32_t e1 = ck.e0 + (ck.nk & 0x7FFu);
-  for (uint32_t e0 = ck.e0; e0 < e1; e0 += kL2Threads) {
-    const uint32_t e = e0 + tid;
-    acc += wave_bit_counts(e < e1 ? a.masks[e] : 0ull);
+  // every round's masks in flight at once
+  uint64_t m[kL2Rounds];
+#pragma unroll
+  for (int k = 0; k < kL2Rounds; ++k) {
+    const uint32_t e = ck.e0 + (uint32_t)(k * kL2Threads + tid);
+    m[k] = e < e1 ? a.masks[e] : 0ull;
   }
+  uint32_t acc = 0;
+#pragma unroll
+  for (int k = 0; k < kL2Rounds; ++k) acc += wave_bit_counts(m[k]);
   wc[w][lane] = acc;
   __syncthreads();
   if (tid < 64) {
@@ -714,8 +743,9 @@ __global__ __launch_bounds__(kL2Threads) void tile_count_kernel(L2Args a) {
 }
 
 // Per (supertile, tile j): the tile's total over the supertile's chunks, at
-// its global tile id (every tile of every view is one (supertile, j) pair).
-// Loads only, so they are all in flight together.
+// its global tile id (every tile of every view is one (supertile, j) pair),
+// and each chunk's count replaced by the sum over the supertile's earlier
+// chunks (the chunk's first position inside the tile's part of the lists).
 __global__ void tile_prefix_kernel(L2Args a) {
   const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g == 0) a.tstart[a.n_tiles] = 0;
@@ -724,8 +754,22 @@ __global__ void tile_prefix_kernel(L2Args a) {
   if (s >= a.n_st) return;
   const uint32_t c0 = a.chunk_base[s], c1 = a.chunk_base[s + 1];
   uint32_t run = 0;
-#pragma unroll 8
-  for (uint32_t c = c0; c < c1; ++c) run += a.cnt[(uint64_t)c * 64 + j];
+  uint32_t c = c0;
+  for (; c + 8 <= c1; c += 8) {
+    uint32_t x[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = a.cnt[(uint64_t)(c + i) * 64 + j];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      a.cnt[(uint64_t)(c + i) * 64 + j] = run;
+      run += x[i];
+    }
+  }
+  for (; c < c1; ++c) {
+    const uint32_t x = a.cnt[(uint64_t)c * 64 + j];
+    a.cnt[(uint64_t)c * 64 + j] = run;
+    run += x;
+  }
   const int v = view_of_st(a.views, a.V, (uint32_t)s);
   const ViewParams &vp = a.views[v];
   const uint32_t sl = (uint32_t)s - vp.st_base;
@@ -770,10 +814,14 @@ __device__ __forceinline__ void scatter_round(uint64_t m, uint32_t r, uint32_t o
       const uint64_t b = __builtin_amdgcn_ballot_w64(bit);
       if (b == 0) continue;
       const int j = 32 * h + jj;
+      // the tile's next position (scalar) and the lane's rank among the
+      // lanes with the bit: a scalar base and a 32-bit lane offset
       const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)off, j);
-      const uint32_t pos = o + __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32),
-                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-      if (bit && (!CHECKED || pos < cap)) out[pos] = r;
+      const uint32_t rank =
+          __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+      __builtin_assume(rank < 64u);
+      uint32_t *__restrict__ dst = out + o;
+      if (bit && (!CHECKED || o + rank < cap)) dst[rank] = r;
     }
   }
 }
@@ -784,43 +832,51 @@ __global__ __launch_bounds__(kL2Threads) void tile_scatter_kernel(L2Args a) {
   // every list fits (the usual case): no per-position capacity test
   const bool fits = a.tstart[a.n_tiles] <= a.cap;
   __shared__ uint32_t base[64];
-  __shared__ uint32_t wc[kL2Waves][64];
+  __shared__ uint32_t wc[kL2Rounds * kL2Waves][64];
   const ChunkRec ck = a.chunks[c];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t e1 = ck.e0 + (ck.nk & 0x7FFu);
+  // every round's entries in flight at once
+  uint64_t m[kL2Rounds];
+  uint32_t r[kL2Rounds];
+#pragma unroll
+  for (int k = 0; k < kL2Rounds; ++k) {
+    const uint32_t e = ck.e0 + (uint32_t)(k * kL2Threads + tid);
+    const bool valid = e < e1;
+    m[k] = valid ? a.masks[e] : 0ull;
+    r[k] = valid ? a.rec[e] : 0u;
+  }
   if (tid < 64) {
+    // the tile's first position + the supertile's earlier chunks' counts
     const ViewParams &vp = a.views[ck.v];
     const int tx = (int)(ck.cxy & 0xFFFF) + (tid & (kST - 1));
     const int ty = (int)(ck.cxy >> 16) + (tid >> kSTLog);
     uint32_t b = 0;
-    if (tx < vp.ntx && ty < vp.nty) {
-      b = a.tstart[vp.tile_base + (uint32_t)ty * vp.ntx + tx];
-      const uint32_t k = ck.nk >> 11;   // earlier chunks of the supertile: c - k .. c - 1
-#pragma unroll 8
-      for (uint32_t i = 0; i < k; ++i) b += a.cnt[(uint64_t)(c - k + i) * 64 + tid];
-    }
+    if (tx < vp.ntx && ty < vp.nty)
+      b = a.tstart[vp.tile_base + (uint32_t)ty * vp.ntx + tx] + a.cnt[(uint64_t)c * 64 + tid];
     base[tid] = b;
   }
-  const uint32_t cap = a.cap;
-  const uint32_t e1 = ck.e0 + (ck.nk & 0x7FFu);
-  for (uint32_t e0 = ck.e0; e0 < e1; e0 += kL2Threads) {
-    const uint32_t e = e0 + tid;
-    const bool valid = e < e1;
-    const uint64_t m = valid ? a.masks[e] : 0ull;
-    const uint32_t r = valid ? a.rec[e] : 0u;
-    wc[w][lane] = wave_bit_counts(m);
-    __syncthreads();   // counts of every wave; base of the previous round
-    uint32_t off = base[lane], tot = 0;
+  // wave-round q = k * waves + w holds entries [e0 + 64 q, e0 + 64 q + 64)
 #pragma unroll
-    for (int k = 0; k < kL2Waves; ++k) {
-      off += k < w ? wc[k][lane] : 0u;
-      tot += wc[k][lane];
-    }
-    __syncthreads();   // every wave has read base and wc (the next round rewrites wc)
-    if (w == 0) base[lane] += tot;
+  for (int k = 0; k < kL2Rounds; ++k) wc[k * kL2Waves + w][lane] = wave_bit_counts(m[k]);
+  __syncthreads();
+  // lane j: tile j's first position for each of this wave's rounds (the
+  // counts of every earlier wave-round added)
+  uint32_t off[kL2Rounds];
+  uint32_t run = base[lane];
+#pragma unroll
+  for (int q = 0; q < kL2Rounds * kL2Waves; ++q) {
+    if ((q % kL2Waves) == w) off[q / kL2Waves] = run;
+    run += wc[q][lane];
+  }
+  const uint32_t cap = a.cap;
+#pragma unroll
+  for (int k = 0; k < kL2Rounds; ++k) {
+    if (ck.e0 + (uint32_t)(k * kL2Threads + w * 64) >= e1) break;   // no entries left for this wave
     if (fits)
-      scatter_round<false>(m, r, off, cap, a.out);
+      scatter_round<false>(m[k], r[k], off[k], cap, a.out);
     else
-      scatter_round<true>(m, r, off, cap, a.out);
+      scatter_round<true>(m[k], r[k], off[k], cap, a.out);
   }
 }
 
