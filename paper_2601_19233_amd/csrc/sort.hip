@@ -7,8 +7,10 @@
 // ordered by (depth key, record id).
 //
 // Each pass is reduce-then-scan: an upsweep writes per-block digit counts in
-// digit-major order, an exclusive scan turns them into global offsets, and a
-// downsweep ranks every key stably inside its block (wave ballots build the
+// digit-major order, one workgroup per digit scans its row over the blocks
+// and stores the digit's total (every row at once, no look-back; the
+// downsweep adds the scan of the 256 totals itself), and a downsweep ranks
+// every key stably inside its block (wave ballots build the
 // equal-digit lane masks, per-wave running counts order the rounds), stages
 // the block's keys in LDS in digit order and writes each digit's run with
 // consecutive lanes on consecutive addresses.  A block covers 256 R keys:
@@ -106,12 +108,53 @@ __global__ __launch_bounds__(kThreads) void rs_upsweep(const K *__restrict__ key
   hist[(uint64_t)tid * a.nblocks + blk] = s;
 }
 
+// Exclusive scan of each digit's block counts (row d of the digit-major
+// counts, in place), one workgroup per digit, and the digit's total into
+// totals[d].  Each thread owns kDigitItems consecutive blocks; a pass with
+// more blocks than one workgroup covers takes the generic scan instead.
+constexpr int kDigitItems = 16;
+
+__global__ __launch_bounds__(kThreads) void rs_digit_scan(uint32_t *__restrict__ hist, uint32_t nb,
+                                                          uint32_t *__restrict__ totals) {
+  __shared__ uint32_t wsum[kWaves];
+  uint32_t *row = hist + (uint64_t)blockIdx.x * nb;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const uint32_t i0 = (uint32_t)tid * kDigitItems;
+  uint32_t v[kDigitItems];
+  uint32_t s = 0;
+#pragma unroll
+  for (int k = 0; k < kDigitItems; ++k) {
+    v[k] = i0 + k < nb ? row[i0 + k] : 0u;
+    s += v[k];
+  }
+  uint32_t x = s;   // inclusive scan over the wave, then over the waves
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  uint32_t run = x - s, tot = 0;
+#pragma unroll
+  for (int k = 0; k < kWaves; ++k) {
+    run += k < w ? wsum[k] : 0u;
+    tot += wsum[k];
+  }
+#pragma unroll
+  for (int k = 0; k < kDigitItems; ++k) {
+    if (i0 + k < nb) row[i0 + k] = run;
+    run += v[k];
+  }
+  if (tid == 0) totals[blockIdx.x] = tot;
+}
+
 // With P64, a 64-bit payload per element (pin/pout) moves with its key.
 template <typename K, bool P64, int R>
 __global__ __launch_bounds__(kThreads) void rs_downsweep(
     const K *__restrict__ kin, const uint32_t *__restrict__ vin, const uint64_t *__restrict__ pin,
     K *__restrict__ kout, uint32_t *__restrict__ vout, uint64_t *__restrict__ pout, PassArgs a,
-    const uint32_t *__restrict__ offs) {
+    const uint32_t *__restrict__ offs, const uint32_t *__restrict__ totals) {
   constexpr int kRounds = R;
   constexpr int kTile = kThreads * R;
   const uint32_t n = pass_count(a);
@@ -135,6 +178,7 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
   __shared__ uint32_t lstart[kBins];
   __shared__ uint32_t gbase[kBins];
   __shared__ uint32_t wscan[kWaves];
+  __shared__ uint32_t wscan_g[kWaves];
 
   for (int k = tid; k < kWaves * kBins; k += kThreads) (&wcnt[0][0])[k] = 0;
   __syncthreads();
@@ -166,24 +210,36 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
   }
   __syncthreads();
 
-  // per digit: counts over waves, exclusive prefix over waves, block scan over digits
+  // per digit: counts over waves, exclusive prefix over waves, block scan
+  // over digits; with per-digit scanned counts, the digit's first position
+  // is the scan of the digits' totals (same for every block)
   {
     const int d = tid;
     const uint32_t c0 = wcnt[0][d], c1 = wcnt[1][d], c2 = wcnt[2][d], c3 = wcnt[3][d];
     const uint32_t tot = c0 + c1 + c2 + c3;
-    uint32_t x = tot;
+    const uint32_t gt = totals ? totals[d] : 0u;
+    uint32_t x = tot, xg = gt;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(x, o, 64);
-      if (lane >= o) x += y;
+      const uint32_t y = __shfl_up(x, o, 64), yg = __shfl_up(xg, o, 64);
+      if (lane >= o) {
+        x += y;
+        xg += yg;
+      }
     }
-    if (lane == 63) wscan[w] = x;
+    if (lane == 63) {
+      wscan[w] = x;
+      wscan_g[w] = xg;
+    }
     __syncthreads();
-    uint32_t pre = 0;
-    for (int k = 0; k < w; ++k) pre += wscan[k];
+    uint32_t pre = 0, pre_g = 0;
+    for (int k = 0; k < w; ++k) {
+      pre += wscan[k];
+      pre_g += wscan_g[k];
+    }
     const uint32_t ls = pre + x - tot;
     lstart[d] = ls;
-    gbase[d] = tot ? offs[(uint64_t)d * a.nblocks + blk] : 0u;
+    gbase[d] = tot ? offs[(uint64_t)d * a.nblocks + blk] + (pre_g + xg - gt) : 0u;
     wcnt[0][d] = ls;
     wcnt[1][d] = ls + c0;
     wcnt[2][d] = ls + c0 + c1;
@@ -217,10 +273,12 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
 
 }  // namespace
 
+// Digit-major block counts (blocks of the smallest size) and the 256 digit
+// totals behind them.
 size_t radix_hist_bytes(uint64_t n) {
   constexpr uint64_t kSmallest = kThreads * kMinRounds;
   const uint64_t nb = (n + kSmallest - 1) / kSmallest;
-  return (size_t)(nb * kBins + 16) * sizeof(uint32_t);
+  return (size_t)(nb * kBins + kBins + 16) * sizeof(uint32_t);
 }
 
 namespace {
@@ -248,9 +306,17 @@ hipError_t launch_pass(Ctx *c, K *keys[2], uint32_t *vals[2], uint64_t *pay[2], 
     e = hipGetLastError();
   }
   if (e != hipSuccess) return e;
+  // per-digit scans when one workgroup covers a digit's blocks, else one
+  // scan over all counts (global offsets; no totals)
+  uint32_t *totals = nb <= (uint32_t)(kThreads * kDigitItems) ? hist + (uint64_t)nb * kBins : nullptr;
   {
     ScopedTimer t(c, kid_scan);
-    e = launch_exclusive_scan_u32(c, hist, (int64_t)nb * kBins, (uint32_t *)c->scan_tmp.p);
+    if (totals) {
+      hipLaunchKernelGGL(rs_digit_scan, dim3(kBins), dim3(kThreads), 0, c->stream, hist, nb, totals);
+      e = hipGetLastError();
+    } else {
+      e = launch_exclusive_scan_u32(c, hist, (int64_t)nb * kBins, (uint32_t *)c->scan_tmp.p);
+    }
   }
   if (e != hipSuccess) return e;
   ScopedTimer t(c, kid_down);
@@ -258,12 +324,12 @@ hipError_t launch_pass(Ctx *c, K *keys[2], uint32_t *vals[2], uint64_t *pay[2], 
     hipLaunchKernelGGL((rs_downsweep<K, true, R>), dim3(nb), dim3(kThreads), 0, c->stream,
                        (const K *)keys[src], (const uint32_t *)vals[src],
                        (const uint64_t *)pay[src], keys[dst], vals[dst], pay[dst], a,
-                       (const uint32_t *)hist);
+                       (const uint32_t *)hist, (const uint32_t *)totals);
   else
     hipLaunchKernelGGL((rs_downsweep<K, false, R>), dim3(nb), dim3(kThreads), 0, c->stream,
                        (const K *)keys[src], (const uint32_t *)vals[src],
                        (const uint64_t *)nullptr, keys[dst], vals[dst], (uint64_t *)nullptr, a,
-                       (const uint32_t *)hist);
+                       (const uint32_t *)hist, (const uint32_t *)totals);
   return hipGetLastError();
 }
 
