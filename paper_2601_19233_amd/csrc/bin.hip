@@ -593,10 +593,12 @@ __global__ void chunk_table_kernel(const ViewParams *__restrict__ views, int V,
   }
 }
 
-// The three steps above in one workgroup, for frames of at most kScanTile - 1
-// supertiles: chunk counts, their exclusive scan (left in chunk_base and in
-// LDS, the total in the frame info), then the chunk table with one thread
-// per chunk (its supertile found by binary search in the scanned counts).
+// The three steps above in one launch, for frames of at most kScanTile - 1
+// supertiles: every workgroup takes the chunk counts and their exclusive
+// scan (in LDS; workgroup 0 also leaves it in chunk_base and the total in
+// the frame info), then builds the table entries of its own chunks, one
+// thread per chunk (its supertile found by binary search in the scanned
+// counts), so no thread waits on more than one chain of loads.
 __global__ __launch_bounds__(kScanThreads) void chunk_plan_kernel(
     const ViewParams *__restrict__ views, int V, const uint2 *__restrict__ rng, int64_t n_st,
     uint32_t *__restrict__ chunk_base, FrameInfo *__restrict__ fi, ChunkRec *__restrict__ tab) {
@@ -622,18 +624,18 @@ __global__ __launch_bounds__(kScanThreads) void chunk_plan_kernel(
   for (int k = 0; k < kScanItems; ++k) {
     const int64_t s = s0 + k;
     if (s <= n_st) {
-      chunk_base[s] = run;
+      if (blockIdx.x == 0) chunk_base[s] = run;
       cb[s] = run;
     }
     run += cnt[k];
   }
   if (threadIdx.x == 0) {
-    fi->n_chunks = total;
+    if (blockIdx.x == 0) fi->n_chunks = total;
     s_total = total;
   }
   __syncthreads();
   const uint32_t nc = s_total;
-  for (uint32_t c = threadIdx.x; c < nc; c += kScanThreads) {
+  for (uint32_t c = blockIdx.x * kScanThreads + threadIdx.x; c < nc; c += gridDim.x * kScanThreads) {
     // last supertile s with cb[s] <= c (cb is non-decreasing, cb[0] = 0)
     uint32_t lo = 0, hi = (uint32_t)n_st;   // cb[lo] <= c < cb[hi]
     while (hi - lo > 1) {
@@ -1093,7 +1095,9 @@ hipError_t launch_st_bin(Ctx *c) {
                        c->stream, (const uint32_t *)c->sk[out].p, (const FrameInfo *)fi, rng);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (c->n_st + 1 <= kScanTile) {
-    hipLaunchKernelGGL(chunk_plan_kernel, dim3(1), dim3(kScanThreads), 0, c->stream, c->cur_views,
+    // the grid covers the most chunks the frame can have
+    const unsigned nwg = (unsigned)ceil_div((int64_t)max_chunks(c->st_launch, c->n_st), kScanThreads);
+    hipLaunchKernelGGL(chunk_plan_kernel, dim3(nwg), dim3(kScanThreads), 0, c->stream, c->cur_views,
                        c->V, (const uint2 *)rng, c->n_st, cb, fi, (ChunkRec *)c->chunk_tab.p);
     return hipGetLastError();
   }
