@@ -38,6 +38,21 @@ namespace umgs {
 namespace {
 
 constexpr int kTriTab = 512;    // triangle fragments of a tile with LDS accumulators
+constexpr int kGUnroll = 8;     // Gaussians of a run evaluated together in the walk
+
+// Highest set bit at or below slot f and at or above slot lo of the batch's
+// triangle mask (lo - 1 if none).
+__device__ __forceinline__ int prev_set_slot(const uint64_t *m, int f, int lo) {
+  while (f >= lo) {
+    const uint64_t w = m[f >> 6] & (~0ull >> (63 - (f & 63)));
+    if (w) {
+      const int b = (f & ~63) + 63 - (int)__builtin_clzll(w);
+      return b >= lo ? b : lo - 1;
+    }
+    f = (f & ~63) - 1;
+  }
+  return lo - 1;
+}
 
 struct TriPix {
   float Tr, Tterm, dC0, dC1, dC2, Bd, ent;
@@ -78,9 +93,11 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
   extern __shared__ uint32_t lds[];
   uint32_t *slots = lds;                                   // batch * kSlotWords
   uint32_t *tpos = lds + batch * kSlotWords;               // kTriTab
-  float *acc = (float *)(tpos + kTriTab);                  // kTriTab * kTriAcc
+  uint32_t *ttab = tpos + kTriTab;                         // kTriTab
+  float *acc = (float *)(ttab + kTriTab);                  // kTriTab * kTriAcc
   __shared__ int red[NW], red2[NW];
   __shared__ int s_ntri;
+  __shared__ uint64_t tmask[NW];      // triangle slots of the staged batch (batch <= NT)
   const uint32_t *vals = fi->sorted_in ? v1 : v0;
 
   const uint32_t tile = order[blockIdx.x];
@@ -135,14 +152,18 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
   // the tile's triangle fragments among positions [0, max_last), in order
   for (int base = 0; base < max_last; base += NT) {
     const int pos = base + tid;
-    const bool is_tri = pos < max_last && (int64_t)vals[rg.x + pos] - rbase >= N;
+    const int64_t local = pos < max_last ? (int64_t)vals[rg.x + pos] - rbase : 0;
+    const bool is_tri = pos < max_last && local >= N;
     const uint64_t bits = __ballot(is_tri);
     if (lane == 0) red[wid] = __popcll(bits);
     __syncthreads();
     int off = s_ntri;
     for (int w = 0; w < wid; ++w) off += red[w];
     off += __popcll(bits & ((1ull << lane) - 1ull));
-    if (is_tri && off < kTriTab) tpos[off] = (uint32_t)pos;
+    if (is_tri && off < kTriTab) {
+      tpos[off] = (uint32_t)pos;
+      ttab[off] = (uint32_t)(local - N);
+    }
     __syncthreads();
     if (tid == 0) {
       int tot = 0;
@@ -224,6 +245,7 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
   x.Px = P0x + (int64_t)(lx * kSubpx);
   x.Py = P0y + (int64_t)(ly * kSubpx);
   x.tpos = tpos;
+  x.ttab = ttab;
   x.acc = acc;
   x.ntab = ntab;
   x.d_rgb = d_rgb;
@@ -232,6 +254,7 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
   for (int bend = t_hi; bend > t_lo; bend -= batch) {
     const int bstart = max(t_lo, bend - batch);
     const int bn = bend - bstart;
+    bool is_tri = false;
     if (tid < bn) {
       uint32_t *s = slots + tid * kSlotWords;
       const int64_t local = (int64_t)vals[rg.x + bstart + tid] - rbase;
@@ -242,61 +265,101 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
         stage_tri(s, vrec[local - N], P0x, P0y);
         s[38] = tri_rank(tpos, ntab, bstart + tid);
         s[39] = (uint32_t)(local - N);
+        is_tri = true;
       }
     }
+    const uint64_t tbits = __ballot(is_tri);
+    if (lane == 0) tmask[wid] = tbits;
     __syncthreads();
-    // this wave's part of the batch
+    // this wave's part of the batch, back to front: runs of Gaussians
+    // between the triangles
     const int f_hi = min(bn, w_hi - bstart), f_lo = max(0, w_lo - bstart);
-    for (int f = f_hi - 1; f >= f_lo; --f) {
-      const uint32_t *s = slots + f * kSlotWords;
-      const int pos = bstart + f;
-      if (!(pos < q.last)) continue;
-      if ((s[31] & 1u) == 0u) {
-        float alpha, a_un, dx, dy;
-        if (!gauss_terms(s, pcx, pcy, alpha, a_un, dx, dy)) continue;
-        // a blended Gaussian in front of an open entity closes it
-        if (q.ent != __builtin_inff()) {
-          ent_close(x, q.e, q.dC0, q.dC1, q.dC2, q.Tr);
+    int f = f_hi - 1;
+    while (f >= f_lo) {
+      const int ft = prev_set_slot(tmask, f, f_lo);
+      if (ft < f) {
+        // Gaussians (ft, f]: per-lane selects only (a fragment that is not
+        // blended, or lies past the pixel's last, gets alpha 0, which leaves
+        // T and B . g unchanged).  A blended Gaussian closes an open entity
+        // in front of it with T as it stood at the start of the run (the
+        // Gaussians before the first blended one change nothing), so the
+        // close waits for the run's end.
+        const float Tr0 = q.Tr;
+        bool blended = false;
+        for (; f - (kGUnroll - 1) > ft; f -= kGUnroll) {
+          float al[kGUnroll], cd[kGUnroll];
+#pragma unroll
+          for (int k = 0; k < kGUnroll; ++k) {
+            const uint32_t *s = slots + (f - k) * kSlotWords;
+            float a;
+            const bool ok = gauss_alpha(s, pcx, pcy, a) && bstart + f - k < q.last;
+            blended = blended || ok;
+            al[k] = ok ? a : 0.0f;
+            cd[k] = fmaf(__uint_as_float(s[6]), q.dC0,
+                         fmaf(__uint_as_float(s[7]), q.dC1, __uint_as_float(s[8]) * q.dC2));
+          }
+#pragma unroll
+          for (int k = 0; k < kGUnroll; ++k) {
+            const float Tb = (bstart + f - k == q.last - 1) ? q.Tterm
+                                                            : q.Tr * __builtin_amdgcn_rcpf(1.0f - al[k]);
+            q.Bd = fmaf(al[k], cd[k] - q.Bd, q.Bd);
+            q.Tr = Tb;
+          }
+        }
+        for (; f > ft; --f) {
+          const uint32_t *s = slots + f * kSlotWords;
+          float a;
+          const bool ok = gauss_alpha(s, pcx, pcy, a) && bstart + f < q.last;
+          blended = blended || ok;
+          const float al = ok ? a : 0.0f;
+          const float cd = fmaf(__uint_as_float(s[6]), q.dC0,
+                                fmaf(__uint_as_float(s[7]), q.dC1, __uint_as_float(s[8]) * q.dC2));
+          const float Tb = (bstart + f == q.last - 1) ? q.Tterm : q.Tr * __builtin_amdgcn_rcpf(1.0f - al);
+          q.Bd = fmaf(al, cd - q.Bd, q.Bd);
+          q.Tr = Tb;
+        }
+        if (blended && q.ent != __builtin_inff()) {
+          ent_close(x, q.e, q.dC0, q.dC1, q.dC2, Tr0);
           q.ent = __builtin_inff();
         }
-        const float Tb = (pos == q.last - 1) ? q.Tterm : q.Tr * __builtin_amdgcn_rcpf(1.0f - alpha);
-        const float cd = fmaf(__uint_as_float(s[6]), q.dC0,
-                              fmaf(__uint_as_float(s[7]), q.dC1, __uint_as_float(s[8]) * q.dC2));
-        q.Bd = fmaf(alpha, cd - q.Bd, q.Bd);
-        q.Tr = Tb;
-      } else {
-        double e[3];
-        float o[4];
-        if (tri_eval(s, rlx, rly, direct, e, o) == 0) continue;
-        float cr, cg, cb, alpha, w[3];
-        float4 texel;
-        tri_shade_w(SlotWords{s}, e, tex, cr, cg, cb, alpha, w, &texel);
-        const float cd = fmaf(cr, q.dC0, fmaf(cg, q.dC1, cb * q.dC2));
-        if (direct) {
-          const float Tb = (pos == q.last - 1) ? q.Tterm : q.Tr / (1.0f - alpha);
-          emit_tri(x, s[38], s[39], Tb * (cd - q.Bd), Tb * alpha, w, texel, q.dC0, q.dC1, q.dC2);
-          q.Tr = Tb;
-          q.Bd = fmaf(alpha, cd - q.Bd, q.Bd);
-          continue;
-        }
-        const bool open = q.ent != __builtin_inff();
-        if (!open) {
-          // the walk enters an entity at its last triangle
-          q.ent = (pos == q.last - 1) ? -1.0f : q.Tr;
-          q.sd0 = q.sd1 = q.sd2 = q.sd3 = q.Bd;
-          q.p0 = q.p1 = q.p2 = q.p3 = 1.0f;
-        }
-        ent_add(q.e, open, pos, s[38], s[39], q.Bd, cd, alpha,
-                0.25f * ((o[0] + o[1]) + (o[2] + o[3])), w, texel);
-        const float a0 = o[0] * alpha, a1 = o[1] * alpha, a2 = o[2] * alpha, a3 = o[3] * alpha;
-        q.sd0 = fmaf(a0, cd - q.sd0, q.sd0);
-        q.sd1 = fmaf(a1, cd - q.sd1, q.sd1);
-        q.sd2 = fmaf(a2, cd - q.sd2, q.sd2);
-        q.sd3 = fmaf(a3, cd - q.sd3, q.sd3);
-        q.p0 *= 1.0f - a0; q.p1 *= 1.0f - a1; q.p2 *= 1.0f - a2; q.p3 *= 1.0f - a3;
-        q.Bd = 0.25f * ((q.sd0 + q.sd1) + (q.sd2 + q.sd3));
-        q.Tr = q.ent < 0.0f ? q.Tterm : q.ent / (0.25f * ((q.p0 + q.p1) + (q.p2 + q.p3)));
       }
+      if (f < f_lo) break;
+      // the triangle at slot f
+      const uint32_t *s = slots + f * kSlotWords;
+      const int pos = bstart + f;
+      --f;
+      if (!(pos < q.last)) continue;
+      double e[3];
+      float o[4];
+      if (tri_eval(s, rlx, rly, direct, e, o) == 0) continue;
+      float cr, cg, cb, alpha, w[3];
+      float4 texel;
+      tri_shade_w(SlotWords{s}, e, tex, cr, cg, cb, alpha, w, &texel);
+      const float cd = fmaf(cr, q.dC0, fmaf(cg, q.dC1, cb * q.dC2));
+      if (direct) {
+        const float Tb = (pos == q.last - 1) ? q.Tterm : q.Tr / (1.0f - alpha);
+        emit_tri(x, s[38], s[39], Tb * (cd - q.Bd), Tb * alpha, w, texel, q.dC0, q.dC1, q.dC2);
+        q.Tr = Tb;
+        q.Bd = fmaf(alpha, cd - q.Bd, q.Bd);
+        continue;
+      }
+      const bool open = q.ent != __builtin_inff();
+      if (!open) {
+        // the walk enters an entity at its last triangle
+        q.ent = (pos == q.last - 1) ? -1.0f : q.Tr;
+        q.sd0 = q.sd1 = q.sd2 = q.sd3 = q.Bd;
+        q.p0 = q.p1 = q.p2 = q.p3 = 1.0f;
+      }
+      ent_add(q.e, open, pos, s[38], s[39], q.Bd, cd, alpha,
+              0.25f * ((o[0] + o[1]) + (o[2] + o[3])), w, texel);
+      const float a0 = o[0] * alpha, a1 = o[1] * alpha, a2 = o[2] * alpha, a3 = o[3] * alpha;
+      q.sd0 = fmaf(a0, cd - q.sd0, q.sd0);
+      q.sd1 = fmaf(a1, cd - q.sd1, q.sd1);
+      q.sd2 = fmaf(a2, cd - q.sd2, q.sd2);
+      q.sd3 = fmaf(a3, cd - q.sd3, q.sd3);
+      q.p0 *= 1.0f - a0; q.p1 *= 1.0f - a1; q.p2 *= 1.0f - a2; q.p3 *= 1.0f - a3;
+      q.Bd = 0.25f * ((q.sd0 + q.sd1) + (q.sd2 + q.sd3));
+      q.Tr = q.ent < 0.0f ? q.Tterm : q.ent / (0.25f * ((q.p0 + q.p1) + (q.p2 + q.p3)));
     }
     __syncthreads();
   }
@@ -327,7 +390,7 @@ hipError_t launch_tri_bwd_tw(Ctx *c, const float *dL, const float *Tf, const int
                              const float *Te, float *d_rgb, float *d_alpha) {
   constexpr int NT = TW * TH;
   const int batch = std::min(c->frag_batch, NT);
-  const size_t lds = ((size_t)batch * kSlotWords + kTriTab + (size_t)kTriTab * kTriAcc) * 4;
+  const size_t lds = ((size_t)batch * kSlotWords + 2 * kTriTab + (size_t)kTriTab * kTriAcc) * 4;
   const uint32_t nt = (uint32_t)c->n_tiles;
   uint32_t *key = (uint32_t *)c->bwd_order.p + 128;
   uint32_t *mask = key + 2 * (size_t)nt;

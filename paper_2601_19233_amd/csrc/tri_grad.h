@@ -33,6 +33,9 @@ struct TriCtx {
   // (the span's back triangle has rank rank_b and each triangle fragment
   // in front of it one more)
   const uint32_t *tpos;
+  // with tpos: the triangle index (within the view) of each rank, in LDS,
+  // so that a re-walk visits the span's triangles without the list
+  const uint32_t *ttab;
   float *acc;                 // LDS accumulators
   int ntab;                   // accumulators
   float *d_rgb, *d_alpha;
@@ -98,6 +101,43 @@ __device__ __forceinline__ int64_t tri_at(const TriCtx &x, int pos) {
 __device__ void rewalk_entity(const TriCtx &x, const EntSpan &sp, float g0, float g1, float g2,
                               float T_in) {
   float s0 = sp.Bback, s1 = sp.Bback, s2 = sp.Bback, s3 = sp.Bback;
+  if (x.ttab && sp.rank_b < (uint32_t)x.ntab) {
+    // the span's triangles are the tabled ranks [rank of fpos, rank_b] (every
+    // triangle in front of a tabled one is tabled): the same walk over them
+    // alone, with no list reads and no Gaussians to skip
+    const int rf = (int)tri_rank(x.tpos, x.ntab, sp.fpos);
+    for (int ri = (int)sp.rank_b; ri >= rf; --ri) {
+      const int64_t ti = x.ttab[ri];
+      const TriRec &r = x.trec[ti];
+      double e[3];
+      float o[4];
+      if (tri_eval_rec(r, x.Px, x.Py, false, e, o) == 0) continue;
+      float cr, cg, cb, a, w[3];
+      float4 texel;
+      tri_shade_w(RecWords{&r}, e, x.tex, cr, cg, cb, a, w, &texel);
+      float t0 = 1.0f, t1 = 1.0f, t2 = 1.0f, t3 = 1.0f;
+      for (int rk = rf; rk < ri; ++rk) {
+        const TriRec &rr = x.trec[x.ttab[rk]];
+        double ek[3];
+        float ok[4];
+        if (tri_eval_rec(rr, x.Px, x.Py, false, ek, ok) == 0) continue;
+        float kr, kg, kb, ak;
+        tri_shade_w(RecWords{&rr}, ek, x.tex, kr, kg, kb, ak);
+        t0 *= 1.0f - ok[0] * ak; t1 *= 1.0f - ok[1] * ak;
+        t2 *= 1.0f - ok[2] * ak; t3 *= 1.0f - ok[3] * ak;
+      }
+      const float cd = fmaf(cr, g0, fmaf(cg, g1, cb * g2));
+      const float v0 = o[0] * t0, v1 = o[1] * t1, v2 = o[2] * t2, v3 = o[3] * t3;
+      const float da = T_in * 0.25f * ((v0 * (cd - s0) + v1 * (cd - s1)) + (v2 * (cd - s2) + v3 * (cd - s3)));
+      const float vis = T_in * a * 0.25f * ((v0 + v1) + (v2 + v3));
+      emit_tri(x, (uint32_t)ri, ti, da, vis, w, texel, g0, g1, g2);
+      s0 = fmaf(o[0] * a, cd - s0, s0);
+      s1 = fmaf(o[1] * a, cd - s1, s1);
+      s2 = fmaf(o[2] * a, cd - s2, s2);
+      s3 = fmaf(o[3] * a, cd - s3, s3);
+    }
+    return;
+  }
   uint32_t rank = sp.rank_b;
   for (int pi = sp.bpos; pi >= sp.fpos; --pi) {
     const int64_t ti = tri_at(x, pi);
