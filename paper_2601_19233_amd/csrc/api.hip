@@ -187,6 +187,7 @@ void umgs_destroy(umgs_ctx *ctx) {
   }
   for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
   if (c->host_pinned.p) (void)hipHostFree(c->host_pinned.p);
+  if (c->ev_totals) (void)hipEventDestroy(c->ev_totals);
   delete ctx;
 }
 
@@ -577,6 +578,9 @@ static umgs_status ensure_lists(Ctx *c, uint64_t n, uint64_t st) {
                                                     c->n_tiles + 1, n_st + 1})),
                   "scan scratch")))
     return s;
+  c->list_key = n;
+  c->list_st = st;
+  c->list_nst = n_st;
   return UMGS_OK;
 }
 
@@ -598,10 +602,28 @@ umgs_status umgs_bin(umgs_ctx *ctx) {
         return hip_check(c, e, "pinned scratch");
       c->host_pinned.cap = 256;
     }
+    if (!c->ev_totals &&
+        (e = hipEventCreateWithFlags(&c->ev_totals, hipEventDisableTiming)) != hipSuccess)
+      return hip_check(c, e, "readback event");
     uint64_t *h = (uint64_t *)c->host_pinned.p;
     if ((e = hipMemcpyAsync(h, c->totals.p, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost,
                             c->stream)) != hipSuccess ||
-        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+        (e = hipEventRecord(c->ev_totals, c->stream)) != hipSuccess)
+      return hip_check(c, e, "duplicate count readback");
+    // While the counts travel, the first level goes ahead into the buffers
+    // of earlier frames (grids over their capacity, counts read on the
+    // device, as in a reserved frame); the host then waits for the counts
+    // only, not for that work.  A frame that does not fit is binned again
+    // once the buffers have grown.
+    const bool spec = c->list_key > 0 && c->list_st > 0 &&
+                      std::max(c->n_st, c->n_st_max) <= c->list_nst;
+    if (spec) {
+      c->key_cap = c->list_key;
+      c->st_cap = c->list_st;
+      c->st_launch = c->list_st;
+      if ((e = launch_st_bin(c)) != hipSuccess) return hip_check(c, e, "supertile binning launch");
+    }
+    if ((e = hipEventSynchronize(c->ev_totals)) != hipSuccess)
       return hip_check(c, e, "duplicate count readback");
     const uint64_t nd = h[0], n1 = h[1];
     if (nd >= 0xFFFF0000ull)
@@ -609,13 +631,28 @@ umgs_status umgs_bin(umgs_ctx *ctx) {
     if (n1 >= 0xFFFF0000ull)
       return fail(c, UMGS_ERR_CAPACITY, "umgs_bin: %llu supertile entries exceed 2^32",
                   (unsigned long long)n1);
+    c->n_dup = nd;
+    if (nd) c->st_ratio = (double)n1 / (double)nd;
+    if (spec && nd <= c->list_key && n1 <= c->list_st) {
+      c->stage = 2;
+      return UMGS_OK;
+    }
+    // the work that went ahead (if any) must end before buffers move
+    if (spec && (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+      return hip_check(c, e, "supertile binning");
     umgs_status s = ensure_lists(c, nd, n1);
     if (s != UMGS_OK) return s;
     c->key_cap = std::max<uint64_t>(nd, 1);
     c->st_cap = std::max<uint64_t>(n1, 1);
-    c->n_dup = nd;
     c->st_launch = n1;
-    if (nd) c->st_ratio = (double)n1 / (double)nd;
+    if (spec) {
+      // what it left: the sticky overflow flag it raised, the supertile
+      // ranges it wrote
+      if ((e = launch_fill_u32(c, (uint32_t *)c->finfo.p + offsetof(FrameInfo, overflow) / 4, 1, 0u)) !=
+              hipSuccess ||
+          (e = launch_fill_u32(c, (uint32_t *)c->st_rng.p, 2 * c->n_st, 0u)) != hipSuccess)
+        return hip_check(c, e, "supertile binning reset");
+    }
   }
   if ((e = launch_st_bin(c)) != hipSuccess) return hip_check(c, e, "supertile binning launch");
   c->stage = 2;

@@ -163,6 +163,12 @@ struct Ctx {
   int st_sorted = 0;          // which of sk/sv holds the sorted entries
   uint64_t st_launch = 0;     // entries the first-level grids cover (n1, or the capacity)
   uint64_t st_cap = 0;        // entries the first-level buffers hold
+  // sizes of the last list-buffer growth (duplicates, entries, supertiles):
+  // the buffers hold at least these, so a later eager frame can bin into
+  // them before its own counts reach the host
+  uint64_t list_key = 0, list_st = 0;
+  int64_t list_nst = 0;
+  hipEvent_t ev_totals = nullptr;   // the frame totals' readback has landed
   double st_ratio = 0.0;      // entries / duplicates of the last eager frame
   const int64_t *view_offsets = nullptr;   // caller's per-view pixel offsets (render_batched)
   DevBuf lb;           // LbState of the single-launch scan (zero between scans)
