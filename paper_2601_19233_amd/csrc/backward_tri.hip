@@ -13,15 +13,17 @@
 //   dL/dc_i = T_in a_i mean_j (o_i^j t^j_{i-1}) g,
 //   dL/da_i = T_in mean_j o_i^j t^j_{i-1} (c_i . g - s^j_i).
 // Every gradient needs a product from the front of the entity and a sum
-// from its back.  Recovering either by division fails for opaque samples
-// (a_i o_i^j = 1 makes the product zero), so the kernel takes neither by
-// division: the walk from the back (as in the Gaussian backward) finds each
-// entity's span of list positions, the colour behind it and T_in; when the
-// entity closes, the pixel walks the span again from the back, keeping s^j
-// exactly, and takes each triangle's t^j_{i-1} as the product over the
-// span's triangles in front of it.  That costs O(n^2) triangle evaluations
-// per entity of n triangles; most entities hold one triangle, whose terms
-// the first walk keeps (t = 1, s^j = B) and emits at the close directly.
+// from its back.  A plain division fails for opaque samples (a_i o_i^j = 1
+// makes the product zero): the walk from the back (as in the Gaussian
+// backward) finds each entity's span of list positions, the colour behind
+// it and T_in; when the entity closes, the pixel walks the span again from
+// the back, keeping s^j exactly.  Each triangle's t^j_{i-1} is then either
+// the product over the span's triangles in front of it (O(n^2) triangle
+// evaluations per entity of n triangles) or, when every nonzero factor is
+// at least 1/16, read off two linear passes that count the exactly zero
+// factors and divide only nonzero products.  Most entities hold one
+// triangle, whose terms the first walk keeps (t = 1, s^j = B) and emits at
+// the close directly.
 // Direct mode (triangles blended like Gaussians) needs no entity:
 // dL/dc = T a g, dL/da = T (c . g - B).
 //

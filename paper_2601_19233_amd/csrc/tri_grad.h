@@ -93,6 +93,73 @@ __device__ __forceinline__ int64_t tri_at(const TriCtx &x, int pos) {
   return local < x.N ? -1 : local - x.N;
 }
 
+// Smallest nonzero factor and product floor for rewalk_linear: a factor of
+// at least 1/16 carries a relative error of at most 15 ulp and no product
+// underflows, so each quotient is good to about 32 n ulp for n triangles.
+constexpr float kDivFactorMin = 1.0f / 16.0f;
+constexpr float kDivProductMin = 1e-30f;
+
+// The re-walk of an entity whose span is the tabled ranks [rf, rank_b] in
+// two linear passes, when that is exact enough: the first counts, per
+// sample, the factors 1 - o^j a that are exactly zero (opaque coverage) and
+// multiplies the others; the second walks from the back keeping the same
+// count and product over the suffix, so that the front product of triangle
+// i is zero if a zero factor lies in front of it, else the entity's nonzero
+// product over the suffix's.  Returns false (nothing emitted) when a
+// nonzero factor is below kDivFactorMin or a product below kDivProductMin.
+__device__ bool rewalk_linear(const TriCtx &x, const EntSpan &sp, int rf, float g0, float g1,
+                              float g2, float T_in) {
+  float P0 = 1.0f, P1 = 1.0f, P2 = 1.0f, P3 = 1.0f;
+  int z0 = 0, z1 = 0, z2 = 0, z3 = 0;
+  bool ok = true;
+  for (int ri = (int)sp.rank_b; ri >= rf; --ri) {
+    const TriRec &r = x.trec[x.ttab[ri]];
+    double e[3];
+    float o[4];
+    if (tri_eval_rec(r, x.Px, x.Py, false, e, o) == 0) continue;
+    float cr, cg, cb, a;
+    tri_shade_w(RecWords{&r}, e, x.tex, cr, cg, cb, a);
+    const float f[4] = {1.0f - o[0] * a, 1.0f - o[1] * a, 1.0f - o[2] * a, 1.0f - o[3] * a};
+    ok = ok && (f[0] == 0.0f || f[0] >= kDivFactorMin) && (f[1] == 0.0f || f[1] >= kDivFactorMin) &&
+         (f[2] == 0.0f || f[2] >= kDivFactorMin) && (f[3] == 0.0f || f[3] >= kDivFactorMin);
+    if (f[0] == 0.0f) ++z0; else P0 *= f[0];
+    if (f[1] == 0.0f) ++z1; else P1 *= f[1];
+    if (f[2] == 0.0f) ++z2; else P2 *= f[2];
+    if (f[3] == 0.0f) ++z3; else P3 *= f[3];
+  }
+  if (!ok || fminf(fminf(P0, P1), fminf(P2, P3)) < kDivProductMin) return false;
+  float s0 = sp.Bback, s1 = sp.Bback, s2 = sp.Bback, s3 = sp.Bback;
+  float S0 = 1.0f, S1 = 1.0f, S2 = 1.0f, S3 = 1.0f;
+  for (int ri = (int)sp.rank_b; ri >= rf; --ri) {
+    const int64_t ti = x.ttab[ri];
+    const TriRec &r = x.trec[ti];
+    double e[3];
+    float o[4];
+    if (tri_eval_rec(r, x.Px, x.Py, false, e, o) == 0) continue;
+    float cr, cg, cb, a, w[3];
+    float4 texel;
+    tri_shade_w(RecWords{&r}, e, x.tex, cr, cg, cb, a, w, &texel);
+    const float f0 = 1.0f - o[0] * a, f1 = 1.0f - o[1] * a, f2 = 1.0f - o[2] * a, f3 = 1.0f - o[3] * a;
+    if (f0 == 0.0f) --z0; else S0 *= f0;
+    if (f1 == 0.0f) --z1; else S1 *= f1;
+    if (f2 == 0.0f) --z2; else S2 *= f2;
+    if (f3 == 0.0f) --z3; else S3 *= f3;
+    // z: zero factors in front of this triangle
+    const float t0 = z0 > 0 ? 0.0f : P0 / S0, t1 = z1 > 0 ? 0.0f : P1 / S1;
+    const float t2 = z2 > 0 ? 0.0f : P2 / S2, t3 = z3 > 0 ? 0.0f : P3 / S3;
+    const float cd = fmaf(cr, g0, fmaf(cg, g1, cb * g2));
+    const float v0 = o[0] * t0, v1 = o[1] * t1, v2 = o[2] * t2, v3 = o[3] * t3;
+    const float da = T_in * 0.25f * ((v0 * (cd - s0) + v1 * (cd - s1)) + (v2 * (cd - s2) + v3 * (cd - s3)));
+    const float vis = T_in * a * 0.25f * ((v0 + v1) + (v2 + v3));
+    emit_tri(x, (uint32_t)ri, ti, da, vis, w, texel, g0, g1, g2);
+    s0 = fmaf(o[0] * a, cd - s0, s0);
+    s1 = fmaf(o[1] * a, cd - s1, s1);
+    s2 = fmaf(o[2] * a, cd - s2, s2);
+    s3 = fmaf(o[3] * a, cd - s3, s3);
+  }
+  return true;
+}
+
 // The gradients of an entity of two or more triangles, entered with
 // transmittance T_in: its span walked again from the back, keeping s^j
 // exactly; each triangle's t^j_{i-1} the product over the span's covering
@@ -103,9 +170,10 @@ __device__ void rewalk_entity(const TriCtx &x, const EntSpan &sp, float g0, floa
   float s0 = sp.Bback, s1 = sp.Bback, s2 = sp.Bback, s3 = sp.Bback;
   if (x.ttab && sp.rank_b < (uint32_t)x.ntab) {
     // the span's triangles are the tabled ranks [rank of fpos, rank_b] (every
-    // triangle in front of a tabled one is tabled): the same walk over them
-    // alone, with no list reads and no Gaussians to skip
+    // triangle in front of a tabled one is tabled): walks over them alone,
+    // with no list reads and no Gaussians to skip
     const int rf = (int)tri_rank(x.tpos, x.ntab, sp.fpos);
+    if ((int)sp.rank_b - rf >= 2 && rewalk_linear(x, sp, rf, g0, g1, g2, T_in)) return;
     for (int ri = (int)sp.rank_b; ri >= rf; --ri) {
       const int64_t ti = x.ttab[ri];
       const TriRec &r = x.trec[ti];
