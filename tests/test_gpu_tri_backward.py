@@ -95,16 +95,18 @@ def test_triangle_gradients_match_oracle(gpu, mode, seed, tile):
     check(g, ref)
 
 
-def test_opaque_and_stacked_triangles(gpu):
+@pytest.mark.parametrize("hi", [1.0, 0.97])
+def test_opaque_and_stacked_triangles(gpu, hi):
     """Opaque triangles (a sub-sample's transmittance drops to exactly zero)
-    in front of and behind translucent ones: no division recovers these
-    products, the re-walk of each entity must."""
+    in front of and behind translucent ones: the linear re-walk counts the
+    zero factors.  With alpha 0.97 instead, factors of 0.03 send those
+    entities to the quadratic re-walk."""
     cam, sc = f32_scene(6)
     al = sc[8].copy()
-    al[:2] = 1.0
+    al[:2] = hi
     al[2::3] = 0.6
     sc[8] = al
-    note("triangle backward opaque/stacked")
+    note(f"triangle backward opaque/stacked hi={hi}")
     dL = masked_loss(cam, sc, 31)
     ref = oracle_tri_grads(cam, sc, dL)
     g = gpu_tri_grads([cam], sc, [dL])
