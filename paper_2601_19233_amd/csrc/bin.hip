@@ -718,7 +718,7 @@ static_assert(kChunk % kL2Threads == 0, "a chunk is whole rounds of the workgrou
 
 __global__ __launch_bounds__(kL2Threads) void tile_count_kernel(L2Args a) {
   // consecutive chunks (mostly of one supertile) on one XCD
-  const uint32_t c = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t c = xcd_block_n(blockIdx.x, a.fi->n_chunks);
   if (c >= a.fi->n_chunks) return;
   __shared__ uint32_t wc[kL2Waves][64];
   const ChunkRec ck = a.chunks[c];
@@ -829,7 +829,7 @@ __device__ __forceinline__ void scatter_round(uint64_t m, uint32_t r, uint32_t o
 }
 
 __global__ __launch_bounds__(kL2Threads) void tile_scatter_kernel(L2Args a) {
-  const uint32_t c = xcd_block(blockIdx.x, gridDim.x);
+  const uint32_t c = xcd_block_n(blockIdx.x, a.fi->n_chunks);
   if (c >= a.fi->n_chunks) return;
   // every list fits (the usual case): no per-position capacity test
   const bool fits = a.tstart[a.n_tiles] <= a.cap;

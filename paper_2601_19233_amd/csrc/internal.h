@@ -327,6 +327,17 @@ __device__ __forceinline__ uint32_t xcd_block(uint32_t bid, uint32_t nb) {
   return xcd * per + min(xcd, rem) + k;
 }
 
+// The same for a grid of at least nb workgroups of which only the first nb
+// logical blocks have work (a grid sized for a capacity, the count known on
+// the device): those nb are spread over all 8 XCDs, each a contiguous range,
+// and every other workgroup gets 0xFFFFFFFF.  A bijection onto [0, nb)
+// whatever the grid size >= nb.
+__device__ __forceinline__ uint32_t xcd_block_n(uint32_t bid, uint32_t nb) {
+  const uint32_t xcd = bid & 7u, k = bid >> 3;
+  const uint32_t per = nb >> 3, rem = nb & 7u;
+  return k < per + (xcd < rem ? 1u : 0u) ? xcd * per + min(xcd, rem) + k : 0xFFFFFFFFu;
+}
+
 // Wave-wide minimum / maximum of a uint32 (wave64).
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v) {
   for (int o = 32; o >= 1; o >>= 1) v = min(v, (uint32_t)__shfl_xor((int)v, o, 64));

@@ -45,7 +45,22 @@ struct PassArgs {
   int shift;
   uint32_t mask;             // digit mask (2^bits - 1)
   uint32_t nblocks;
+  // nonzero: only the blocks that hold elements run (spread over the XCDs
+  // by their count on the device) and write counts, which the per-digit
+  // scans read; zero: every block writes its column (the generic scan reads
+  // them all)
+  uint32_t spread;
 };
+
+// Logical block of this workgroup, or a value >= nblocks when it has none.
+template <int R>
+__device__ __forceinline__ uint32_t pass_block(const PassArgs &a, uint32_t n) {
+  if (!a.spread) return xcd_block(blockIdx.x, a.nblocks);
+  constexpr uint32_t kTile = kThreads * R;
+  const uint32_t nb = min(a.nblocks, (n + kTile - 1) / kTile);
+  const uint32_t b = xcd_block_n(blockIdx.x, nb);
+  return b < nb ? b : 0xFFFFFFFFu;
+}
 
 __device__ __forceinline__ uint32_t pass_count(const PassArgs &a) {
   return a.n_dev ? min(*a.n_dev, a.n_host) : a.n_host;
@@ -79,8 +94,9 @@ __global__ __launch_bounds__(kThreads) void rs_upsweep(const K *__restrict__ key
   __shared__ uint32_t h[kWaves][kBins];
   const int tid = threadIdx.x, w = tid >> 6;
   for (int k = tid; k < kWaves * kBins; k += kThreads) (&h[0][0])[k] = 0;
+  const uint32_t blk = pass_block<R>(a, n);
+  if (blk >= a.nblocks) return;
   __syncthreads();
-  const uint32_t blk = xcd_block(blockIdx.x, a.nblocks);
   const uint32_t i0 = blk * kTile + tid * R;
   constexpr int kBytes = R * (int)sizeof(K);   // 8 .. 64, a multiple of 8
   if (i0 + R <= n) {
@@ -114,10 +130,13 @@ __global__ __launch_bounds__(kThreads) void rs_upsweep(const K *__restrict__ key
 // more blocks than one workgroup covers takes the generic scan instead.
 constexpr int kDigitItems = 16;
 
-__global__ __launch_bounds__(kThreads) void rs_digit_scan(uint32_t *__restrict__ hist, uint32_t nb,
-                                                          uint32_t *__restrict__ totals) {
+__global__ __launch_bounds__(kThreads) void rs_digit_scan(uint32_t *__restrict__ hist, uint32_t stride,
+                                                          uint32_t *__restrict__ totals, PassArgs a,
+                                                          uint32_t tile) {
   __shared__ uint32_t wsum[kWaves];
-  uint32_t *row = hist + (uint64_t)blockIdx.x * nb;
+  // the blocks that hold elements (the only ones that wrote counts)
+  const uint32_t nb = min(stride, (pass_count(a) + tile - 1) / tile);
+  uint32_t *row = hist + (uint64_t)blockIdx.x * stride;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const uint32_t i0 = (uint32_t)tid * kDigitItems;
   uint32_t v[kDigitItems];
@@ -158,7 +177,8 @@ __global__ __launch_bounds__(kThreads) void rs_downsweep(
   constexpr int kRounds = R;
   constexpr int kTile = kThreads * R;
   const uint32_t n = pass_count(a);
-  const uint32_t blk = xcd_block(blockIdx.x, a.nblocks);
+  const uint32_t blk = pass_block<R>(a, n);
+  if (blk >= a.nblocks) return;
   const uint32_t base = blk * kTile;
   if (base >= n) return;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -295,9 +315,10 @@ int choose_rounds(uint64_t n, bool payload) {
 
 template <typename K, int R>
 hipError_t launch_pass(Ctx *c, K *keys[2], uint32_t *vals[2], uint64_t *pay[2], int src,
-                       const PassArgs &a, uint32_t *hist, int kid_up, int kid_scan, int kid_down) {
+                       PassArgs a, uint32_t *hist, int kid_up, int kid_scan, int kid_down) {
   const int dst = src ^ 1;
   const uint32_t nb = a.nblocks;
+  a.spread = nb <= (uint32_t)(kThreads * kDigitItems) ? 1u : 0u;
   hipError_t e;
   {
     ScopedTimer t(c, kid_up);
@@ -312,7 +333,8 @@ hipError_t launch_pass(Ctx *c, K *keys[2], uint32_t *vals[2], uint64_t *pay[2], 
   {
     ScopedTimer t(c, kid_scan);
     if (totals) {
-      hipLaunchKernelGGL(rs_digit_scan, dim3(kBins), dim3(kThreads), 0, c->stream, hist, nb, totals);
+      hipLaunchKernelGGL(rs_digit_scan, dim3(kBins), dim3(kThreads), 0, c->stream, hist, nb, totals, a,
+                         (uint32_t)(kThreads * R));
       e = hipGetLastError();
     } else {
       e = launch_exclusive_scan_u32(c, hist, (int64_t)nb * kBins, (uint32_t *)c->scan_tmp.p);
