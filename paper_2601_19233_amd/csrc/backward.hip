@@ -390,7 +390,9 @@ __global__ __launch_bounds__(64) void blend_backward_kernel(
         const uint32_t rec = (uint32_t)((int64_t)v * N + local);
         stage_gauss(s, grec[rec], rec);
       } else {
-        stage_tri(s, trec[(int64_t)v * T + (local - N)], P0x, P0y);
+        const TriRec &tr = trec[(int64_t)v * T + (local - N)];
+        stage_tri(s, tr, P0x, P0y);
+        s[38] = tri_tile_box(tr, tx * TW, ty * TH, TW, TH);
         is_tri = true;
       }
     }
@@ -419,7 +421,9 @@ __global__ __launch_bounds__(64) void blend_backward_kernel(
       } else {
 #pragma unroll
         for (int p = 0; p < PPT; ++p)
-          tri_bwd(s, pos, rlx, (double)((ly0 + p * RSTEP) * kSubpx), direct, tex, q[p]);
+          // only pixels in the triangle's box can have a covered sample
+          if (in_tile_box(s[38], lx, ly0 + p * RSTEP))
+            tri_bwd(s, pos, rlx, (double)((ly0 + p * RSTEP) * kSubpx), direct, tex, q[p]);
       }
     }
     __syncthreads();

@@ -192,25 +192,14 @@ __global__ __launch_bounds__(TW *TH) void tri_backward_kernel(
       const TriRec &tr = vrec[local - N];
       uint32_t *s = slots + tid * kSlotWords;
       stage_tri(s, tr, P0x, P0y);
-      // the tile's pixels whose samples can fall inside the triangle's box
-      // (samples lie 32..224 / 256 px into their pixel)
-      const int minX = min(tr.X[0], min(tr.X[1], tr.X[2])), maxX = max(tr.X[0], max(tr.X[1], tr.X[2]));
-      const int minY = min(tr.Y[0], min(tr.Y[1], tr.Y[2])), maxY = max(tr.Y[0], max(tr.Y[1], tr.Y[2]));
-      const int x0 = min(max(((minX + 31) >> 8) - tx * TW, 0), TW);
-      const int x1 = min(max(((maxX - 32) >> 8) + 1 - tx * TW, 0), TW);
-      const int y0 = min(max(((minY + 31) >> 8) - ty * TH, 0), TH);
-      const int y1 = min(max(((maxY - 32) >> 8) + 1 - ty * TH, 0), TH);
-      s[38] = (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | ((uint32_t)y1 << 24);
+      s[38] = tri_tile_box(tr, tx * TW, ty * TH, TW, TH);
     }
     __syncthreads();
     for (int f = 0; f < cn && first_cov == q.last; ++f) {
       const int pos = (int)tpos[c0 + f];
       if (pos >= q.last) break;
       const uint32_t *s = slots + f * kSlotWords;
-      const uint32_t bx = s[38];
-      if (lx < (int)(bx & 0xFFu) || ly < (int)((bx >> 8) & 0xFFu) || lx >= (int)((bx >> 16) & 0xFFu) ||
-          ly >= (int)(bx >> 24))
-        continue;
+      if (!in_tile_box(s[38], lx, ly)) continue;
       double e[3];
       float o[4];
       if (tri_eval(s, rlx, rly, direct, e, o) > 0) first_cov = pos;

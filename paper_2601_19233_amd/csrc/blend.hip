@@ -96,7 +96,9 @@ __device__ __forceinline__ void blend_tile(
           const uint32_t rec = (uint32_t)((int64_t)v * N + local);
           stage_gauss(s, grec[rec], rec);
         } else {
-          stage_tri(s, trec[(int64_t)v * T + (local - N)], P0x, P0y);
+          const TriRec &tr = trec[(int64_t)v * T + (local - N)];
+          stage_tri(s, tr, P0x, P0y);
+          s[38] = tri_tile_box(tr, tx * TW, ty * TH, TW, TH);
           is_tri = true;
         }
       }
@@ -195,7 +197,7 @@ __device__ __forceinline__ void blend_tile(
             const int32_t pos = (int32_t)(bstart - rg.x + f + 1);
             double e[3];
             float o[4];
-            if (tri_eval(s, rlx, rly, direct, e, o) != 0) {
+            if (in_tile_box(s[38], lx, ly) && tri_eval(s, rlx, rly, direct, e, o) != 0) {
               float cr, cg, cbl, alpha;
               tri_shade(s, e, tex, cr, cg, cbl, alpha);
               if (direct) {

@@ -34,6 +34,26 @@ __device__ __forceinline__ void stage_gauss(uint32_t *s, const GaussRec &g, uint
   s[31] = 0u;
 }
 
+// The pixels of a tile whose sub-samples can fall inside the triangle's
+// bounding box (samples, and the direct mode's pixel centre, lie 32..224 /
+// 256 px into their pixel), tile-relative [x0, x1) x [y0, y1) clamped to the
+// tile, packed x0 | y0 << 8 | x1 << 16 | y1 << 24.  No pixel outside it has
+// a covered sample.
+__device__ __forceinline__ uint32_t tri_tile_box(const TriRec &tr, int px0, int py0, int TW, int TH) {
+  const int minX = min(tr.X[0], min(tr.X[1], tr.X[2])), maxX = max(tr.X[0], max(tr.X[1], tr.X[2]));
+  const int minY = min(tr.Y[0], min(tr.Y[1], tr.Y[2])), maxY = max(tr.Y[0], max(tr.Y[1], tr.Y[2]));
+  const int x0 = min(max(((minX + 31) >> 8) - px0, 0), TW);
+  const int x1 = min(max(((maxX - 32) >> 8) + 1 - px0, 0), TW);
+  const int y0 = min(max(((minY + 31) >> 8) - py0, 0), TH);
+  const int y1 = min(max(((maxY - 32) >> 8) + 1 - py0, 0), TH);
+  return (uint32_t)x0 | ((uint32_t)y0 << 8) | ((uint32_t)x1 << 16) | ((uint32_t)y1 << 24);
+}
+
+__device__ __forceinline__ bool in_tile_box(uint32_t bx, int lx, int ly) {
+  return lx >= (int)(bx & 0xFFu) && ly >= (int)((bx >> 8) & 0xFFu) && lx < (int)((bx >> 16) & 0xFFu) &&
+         ly < (int)(bx >> 24);
+}
+
 __device__ __forceinline__ void stage_tri(uint32_t *s, const TriRec &tr, int64_t P0x, int64_t P0y) {
   const int ea[3] = {1, 2, 0}, eb[3] = {2, 0, 1};
   double *dv = (double *)s;
