@@ -68,7 +68,12 @@ __device__ __forceinline__ void blend_tile(
   const double rlx = (double)(lx * kSubpx), rly = (double)(ly * kSubpx);
   const bool direct = mode == UMGS_MODE_DIRECT;
 
-  const uint2 rg = ranges[tile];
+  // The tile's range, the batch and the walk's slot indices are the same on
+  // every lane: read into scalar registers, the list positions that
+  // n_contrib records and the loop control cost no vector instructions.
+  uint2 rg = ranges[tile];
+  rg.x = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.x);
+  rg.y = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.y);
   const int64_t rbase = (int64_t)v * (N + T);
 
   float C0 = 0.f, C1 = 0.f, C2 = 0.f;
@@ -111,11 +116,15 @@ __device__ __forceinline__ void blend_tile(
     for (uint32_t w = 0; w * 64 < bn; ++w) any_bits |= tmask[w];
     const bool any_tri = any_bits != 0;
 
-    // ---- blend the batch: runs of Gaussians between the triangles
-    if (!done) {
+    // ---- blend the batch: runs of Gaussians between the triangles (the
+    // whole wave walks while one of its pixels is live; a done pixel starts
+    // every run with T = 0, where each fragment is a stop and adds nothing,
+    // and skips the triangles)
+    if (!__all(done)) {
       uint32_t f = 0;
       while (f < bn) {
-        const uint32_t fe = any_tri ? next_set_slot(tmask, f, bn) : bn;
+        const uint32_t fe = (uint32_t)__builtin_amdgcn_readfirstlane(
+            (int)(any_tri ? next_set_slot(tmask, f, bn) : bn));
         if (fe > f) {
           // Gaussians [f, fe): alpha of kUnroll fragments evaluated together
           // (they do not depend on the pixel's state), then blended in list
@@ -143,6 +152,10 @@ __device__ __forceinline__ void blend_tile(
               cg[k] = __uint_as_float(s[7]);
               cb[k] = __uint_as_float(s[8]);
             }
+            // last blended slot of the group, 1-based (0: none): a select of
+            // a constant per fragment; the list position is added once per
+            // group
+            int32_t lastk = 0;
 #pragma unroll
             for (int k = 0; k < kUnroll; ++k) {
               if (COUNT) n_gp += Tl < kTStop ? 0u : 1u;
@@ -155,10 +168,11 @@ __device__ __forceinline__ void blend_tile(
               C1 = fmaf(wc, cg[k], C1);
               C2 = fmaf(wc, cb[k], C2);
               Tent = blend ? Tl : Tent;
-              last = blend ? (int32_t)(bstart - rg.x + f + k + 1) : last;
+              lastk = blend ? k + 1 : lastk;
               Tf = stop ? Tf : test_T;
               Tl = test_T;
             }
+            last = lastk != 0 ? (int32_t)(bstart - rg.x + f) + lastk : last;
           }
           // the rest of the run one at a time, same arithmetic
           for (; f < fe; ++f) {
