@@ -89,7 +89,9 @@ __device__ __forceinline__ bool gauss_bwd(const GFrag &fr, int pos, float pcx, f
   const float pw = gauss_logalpha(fr.a.z, fr.a.w, fr.b.x, fr.b.y, dx, dy);
   const bool inside = pw <= fr.b.y;
   const float a_un = __builtin_amdgcn_exp2f(inside ? pw : fr.b.y);
-  const float alpha = fminf(kAlphaMax, a_un);
+  // min(0.99, a) as a select on the compare the clamp's gradient also takes
+  // (the same value as fminf for every a, NaN included)
+  const float alpha = a_un < kAlphaMax ? a_un : kAlphaMax;
   const bool hit = inside && alpha >= kAlphaMin;
   const bool contrib = pos < q.last && hit;
   q.ent = contrib ? __builtin_inff() : q.ent;     // a blended Gaussian closes an entity

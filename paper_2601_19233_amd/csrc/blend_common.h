@@ -110,7 +110,7 @@ __device__ __forceinline__ bool gauss_terms(const uint32_t *s, float pcx, float 
   const float p = gauss_logalpha(a.z, a.w, b.x, b.y, dx, dy);
   const bool inside = p <= b.y;
   a_un = __builtin_amdgcn_exp2f(inside ? p : b.y);
-  alpha = fminf(kAlphaMax, a_un);
+  alpha = a_un < kAlphaMax ? a_un : kAlphaMax;   // min(0.99, a), as a select
   return inside && alpha >= kAlphaMin;
 }
 
