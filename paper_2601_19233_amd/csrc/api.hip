@@ -746,7 +746,7 @@ umgs_status umgs_backward_transfer(umgs_ctx *ctx, const float *V_def, int32_t N,
   const int64_t hb = (int64_t)radix_hist_bytes((uint64_t)M);
   umgs_status s;
   if ((s = ensure(c, c->tb_face, sizeof(float) * 36 * (size_t)c->nF, "per-face gradient sums")) ||
-      (s = ensure(c, c->tb_g, sizeof(float) * 12 * (size_t)std::max<int32_t>(N, 1), "Gaussian gradient rows")) ||
+      (s = ensure(c, c->tb_g, sizeof(float) * kGRow * (size_t)std::max<int32_t>(N, 1), "Gaussian gradient rows")) ||
       (s = ensure(c, c->tb_key[0], sizeof(uint32_t) * (size_t)M, "corner keys")) ||
       (s = ensure(c, c->tb_key[1], sizeof(uint32_t) * (size_t)M, "corner keys")) ||
       (s = ensure(c, c->tb_val[0], sizeof(uint32_t) * (size_t)M, "corner ids")) ||

@@ -29,6 +29,10 @@ constexpr int kMinMaxSlots = 4096;     // slot pairs of the frame's depth-key ra
 constexpr int kSTLog = 3;
 constexpr int kST = 1 << kSTLog;
 
+// Floats per row of the proxy backward's per-Gaussian gradient table: the
+// row's 12 terms padded to 64 B, one aligned memory sector per gather.
+constexpr int kGRow = 16;
+
 // Per-view parameters in device memory.
 struct ViewParams {
   float R[9];
@@ -139,7 +143,7 @@ struct Ctx {
   DevBuf ftab;   // per face: its three vertex rows (9 float4, 144 B)
   // transfer backward: per-Gaussian gradient rows (12 floats), corner sort
   // keys and ids (ping-pong), per-face sums (36 floats)
-  DevBuf tb_g, tb_key[2], tb_val[2], tb_face;
+  DevBuf tb_g, tb_key[2], tb_val[2], tb_face;   // tb_g: N rows of kGRow floats
   // BVH of the rest proxy for the binding association (rebuilt per call)
   DevBuf bvh_code[2], bvh_id[2];  // nF uint32: Morton codes / face ids (ping-pong sort)
   DevBuf bvh_tri;                 // nF x 3 float4: leaf triangles in Morton order

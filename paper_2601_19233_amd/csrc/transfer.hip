@@ -477,10 +477,14 @@ __device__ __forceinline__ void finish_backward(int i, const float rs[3], const 
                                                 const float *__restrict__ dmu,
                                                 const float *__restrict__ dA,
                                                 float *__restrict__ gG) {
-  float *go = gG + 12 * (int64_t)i;
+  // rows of kGRow floats (64 B, aligned): the per-face pass gathers each
+  // in one memory sector
+  float4 *go4 = reinterpret_cast<float4 *>(gG + kGRow * (int64_t)i);
   if (!any_bound) {                    // rest pose: no dependence on the proxy
-#pragma unroll
-    for (int q = 0; q < 12; ++q) go[q] = 0.0f;
+    const float4 z = make_float4(0.f, 0.f, 0.f, 0.f);
+    go4[0] = z;
+    go4[1] = z;
+    go4[2] = z;
     return;
   }
   const float r0 = rs[0] * invk, r1 = rs[1] * invk, r2 = rs[2] * invk;
@@ -522,6 +526,7 @@ __device__ __forceinline__ void finish_backward(int i, const float rs[3], const 
   // J_r(r)^T y = y + hb r x y + cb r x (r x y)
   const float rxy[3] = {r1 * y[2] - r2 * y[1], r2 * y[0] - r0 * y[2], r0 * y[1] - r1 * y[0]};
   const float rxrxy[3] = {r1 * rxy[2] - r2 * rxy[1], r2 * rxy[0] - r0 * rxy[2], r0 * rxy[1] - r1 * rxy[0]};
+  float go[12];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     go[q] = (dmu ? nt_load(dmu + 3 * (int64_t)i + q) : 0.0f) * invk;
@@ -533,12 +538,15 @@ __device__ __forceinline__ void finish_backward(int i, const float rs[3], const 
   go[9] = GS[4] * invk;
   go[10] = 0.5f * (GS[5] + GS[7]) * invk;
   go[11] = GS[8] * invk;
+  go4[0] = make_float4(go[0], go[1], go[2], go[3]);
+  go4[1] = make_float4(go[4], go[5], go[6], go[7]);
+  go4[2] = make_float4(go[8], go[9], go[10], go[11]);
 }
 
 // Arguments of the backward instantiation (unused by the forward one).
 struct TransferBwdArgs {
   const float *dmu, *dA;     // dL/dmu' (N,3), dL/dA (N,9); NULL: zero
-  float *gG;                 // (N,12) rows g
+  float *gG;                 // (N, kGRow) rows: g's 12 terms, padded to 64 B
   uint32_t *keys, *vals;     // per corner: its face (nF: unbound) and its index
 };
 
@@ -700,7 +708,9 @@ __global__ __launch_bounds__(64) void transfer_bwd_faces_kernel(
     const uint32_t c = svals[j];
     const float u = bind_bary[2 * (int64_t)c], v = bind_bary[2 * (int64_t)c + 1];
     const float w = (1.0f - u) - v;
-    const float *g = gG + 12 * (int64_t)(c / (uint32_t)K);
+    const float4 *g4 = reinterpret_cast<const float4 *>(gG + kGRow * (int64_t)(c / (uint32_t)K));
+    const float4 ga = g4[0], gb = g4[1], gc = g4[2];
+    const float g[12] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w, gc.x, gc.y, gc.z, gc.w};
 #pragma unroll
     for (int q = 0; q < 12; ++q) {
       const float gq = g[q];
