@@ -68,9 +68,8 @@ __device__ __forceinline__ void blend_tile(
   const double rlx = (double)(lx * kSubpx), rly = (double)(ly * kSubpx);
   const bool direct = mode == UMGS_MODE_DIRECT;
 
-  // The tile's range, the batch and the walk's slot indices are the same on
-  // every lane: read into scalar registers, the list positions that
-  // n_contrib records and the loop control cost no vector instructions.
+  // The tile's range (and below, each run's end) is the same on every lane;
+  // taken with readfirstlane, it stays in scalar registers.
   uint2 rg = ranges[tile];
   rg.x = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.x);
   rg.y = (uint32_t)__builtin_amdgcn_readfirstlane((int)rg.y);
